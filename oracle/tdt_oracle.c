@@ -1,0 +1,246 @@
+/*
+ * tdt_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, obviously correct CPU reference for what the GPU path
+ * computes: X = T^{-1} F for the Toeplitz tridiagonal matrix
+ *     T = tridiag{t_-1, t_0, t_1}          (paper, eq. (1); t_1 on the
+ *                                            super-diagonal, t_-1 below)
+ * and the adjoint of that map.  Only tests/, __graft_entry__.smoke() and the
+ * cpu_baseline leg of bench.py may load this library; the product never does.
+ * It shares no code, header or constant with the HIP path.
+ *
+ * Why the definition is the oracle: the dichotomy method is a direct solver.
+ * Sec. 2.2 states that, once the end components of every sub-vector are known,
+ * the remaining systems are solved "by any sequential version of the Thomas
+ * algorithm", and the abstract and Sec. 4 claim accuracy comparable with the
+ * sequential Thomas method.  In exact arithmetic the method reaches exactly
+ * T^{-1} F, so the oracle is plain Gaussian elimination without pivoting on
+ * the tridiagonal matrix (the Thomas algorithm), written out below:
+ *
+ *   forward:  u_1 = t0,            c'_1 = t1 / u_1,   d'_1 = f_1 / u_1
+ *             u_i = t0 - t-1 c'_{i-1},  c'_i = t1 / u_i,
+ *             d'_i = (f_i - t-1 d'_{i-1}) / u_i                 (i = 2..N)
+ *   backward: x_N = d'_N,   x_i = d'_i - c'_i x_{i+1}           (i = N-1..1)
+ *
+ * A zero pivot u_i is reported as singular (status 1).
+ *
+ * Built with  gcc -O2 -ffp-contract=off -fopenmp  so that every product and
+ * sum is rounded as written.  The long double variant (x87 extended, unit
+ * roundoff 2^-64, forward error ~ cond(T) 2^-64) serves as "truth" for the
+ * ill-conditioned systems, where the double result itself errs by
+ * ~ cond(T) 2^-53.
+ *
+ * Adjoint (the differentiation extension): for L = <W, X> with X = T^{-1} F,
+ *   gF = T^{-T} gX,  i.e. the same Thomas recurrence on T^T = tridiag{t1,t0,t-1}
+ *   dL/dt0  = - sum_i   gF_i x_i
+ *   dL/dt1  = - sum_i   gF_i x_{i+1}      (entries T_{i,i+1})
+ *   dL/dt-1 = - sum_i   gF_{i+1} x_i      (entries T_{i+1,i})
+ * which follows from dX = -T^{-1} dT X.  The transposed solve is the paper's
+ * remark in Sec. 2.3 that (A^T)^{-1} = (A^{-1})^T.  Sums are accumulated in
+ * long double over all entries and right-hand sides.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ---- one system, one right-hand side, double ---------------------------- */
+static int thomas_f64(double tm1, double t0, double t1, int64_t n,
+                      const double *f, double *x, double *cp /* scratch n */)
+{
+    double u = t0;
+    if (u == 0.0) return 1;
+    cp[0] = t1 / u;
+    x[0] = f[0] / u;                       /* x holds d' until back-substitution */
+    for (int64_t i = 1; i < n; ++i) {
+        u = t0 - tm1 * cp[i - 1];
+        if (u == 0.0) return 1;
+        cp[i] = t1 / u;
+        x[i] = (f[i] - tm1 * x[i - 1]) / u;
+    }
+    for (int64_t i = n - 2; i >= 0; --i)
+        x[i] = x[i] - cp[i] * x[i + 1];
+    return 0;
+}
+
+/* ---- one system, one right-hand side, long double ------------------------ */
+static int thomas_ld(long double tm1, long double t0, long double t1, int64_t n,
+                     const long double *f, long double *x, long double *cp)
+{
+    long double u = t0;
+    if (u == 0.0L) return 1;
+    cp[0] = t1 / u;
+    x[0] = f[0] / u;
+    for (int64_t i = 1; i < n; ++i) {
+        u = t0 - tm1 * cp[i - 1];
+        if (u == 0.0L) return 1;
+        cp[i] = t1 / u;
+        x[i] = (f[i] - tm1 * x[i - 1]) / u;
+    }
+    for (int64_t i = n - 2; i >= 0; --i)
+        x[i] = x[i] - cp[i] * x[i + 1];
+    return 0;
+}
+
+/* Long double variant: the same recurrence with every operation in x87
+ * extended precision, rounded to double at the end.  work: 3*n long doubles. */
+static int thomas_ld_to_f64(double tm1, double t0, double t1, int64_t n,
+                            const double *f, double *xout, long double *work)
+{
+    long double *fl = work, *x = work + n, *cp = work + 2 * n;
+    for (int64_t i = 0; i < n; ++i) fl[i] = (long double)f[i];
+    int st = thomas_ld(tm1, t0, t1, n, fl, x, cp);
+    if (st) return st;
+    for (int64_t i = 0; i < n; ++i) xout[i] = (double)x[i];
+    return 0;
+}
+
+static int set_threads(int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+    return omp_get_max_threads();
+#else
+    (void)nthreads;
+    return 1;
+#endif
+}
+
+/* F, X: [M][N] row-major (one right-hand side per row).  precision: 0 = double,
+ * 1 = long double.  Returns 0, 1 if some
+ * pivot is zero, 2 on allocation failure.  nthreads <= 0 keeps the default. */
+int oracle_solve(double tm1, double t0, double t1, int64_t N, int64_t M,
+                 const double *F, double *X, int precision, int nthreads)
+{
+    if (N < 1 || M < 1 || !F || !X) return 3;
+    set_threads(nthreads);
+    int status = 0;
+#pragma omp parallel
+    {
+        double *cp = (double *)malloc((size_t)N * sizeof(double));
+        long double *wl = precision == 1
+            ? (long double *)malloc((size_t)(3 * N) * sizeof(long double)) : NULL;
+        int local = (cp && (precision != 1 || wl)) ? 0 : 2;
+#pragma omp for schedule(static)
+        for (int64_t m = 0; m < M; ++m) {
+            if (local == 2) continue;
+            int st = precision == 1
+                ? thomas_ld_to_f64(tm1, t0, t1, N, F + m * N, X + m * N, wl)
+                : thomas_f64(tm1, t0, t1, N, F + m * N, X + m * N, cp);
+            if (st > local) local = st;
+        }
+#pragma omp critical
+        { if (local > status) status = local; }
+        free(cp); free(wl);
+    }
+    return status;
+}
+
+/* S systems packed back to back: system s occupies [offsets[s], offsets[s+1])
+ * of F and X and has its own (tm1[s], t0[s], t1[s]).  Systems are handed out
+ * largest first with dynamic scheduling. */
+int oracle_solve_varlen(int64_t S, const int64_t *offsets, const double *tm1,
+                        const double *t0, const double *t1, const double *F,
+                        double *X, int precision, int nthreads)
+{
+    if (S < 1 || !offsets || !F || !X) return 3;
+    int64_t nmax = 0;
+    for (int64_t s = 0; s < S; ++s) {
+        int64_t n = offsets[s + 1] - offsets[s];
+        if (n < 1) return 3;
+        if (n > nmax) nmax = n;
+    }
+    /* order by length, descending (simple insertion of indices) */
+    int64_t *order = (int64_t *)malloc((size_t)S * sizeof(int64_t));
+    if (!order) return 2;
+    for (int64_t s = 0; s < S; ++s) order[s] = s;
+    for (int64_t i = 1; i < S; ++i) {
+        int64_t k = order[i], nk = offsets[k + 1] - offsets[k], j = i - 1;
+        while (j >= 0 && offsets[order[j] + 1] - offsets[order[j]] < nk) {
+            order[j + 1] = order[j]; --j;
+        }
+        order[j + 1] = k;
+    }
+    set_threads(nthreads);
+    int status = 0;
+#pragma omp parallel
+    {
+        double *cp = (double *)malloc((size_t)nmax * sizeof(double));
+        long double *wl = precision == 1
+            ? (long double *)malloc((size_t)(3 * nmax) * sizeof(long double)) : NULL;
+        int local = (cp && (precision != 1 || wl)) ? 0 : 2;
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t i = 0; i < S; ++i) {
+            if (local == 2) continue;
+            int64_t s = order[i], o = offsets[s], n = offsets[s + 1] - o;
+            int st = precision == 1
+                ? thomas_ld_to_f64(tm1[s], t0[s], t1[s], n, F + o, X + o, wl)
+                : thomas_f64(tm1[s], t0[s], t1[s], n, F + o, X + o, cp);
+            if (st > local) local = st;
+        }
+#pragma omp critical
+        { if (local > status) status = local; }
+        free(cp); free(wl);
+    }
+    free(order);
+    return status;
+}
+
+/* Adjoint of X = T^{-1} F for M right-hand sides sharing one T.
+ * gX, X: [M][N] in; gF: [M][N] out; gt[3] = (dL/dt-1, dL/dt0, dL/dt1) summed
+ * over all right-hand sides. */
+int oracle_adjoint(double tm1, double t0, double t1, int64_t N, int64_t M,
+                   const double *gX, const double *X, double *gF, double *gt,
+                   int nthreads)
+{
+    if (N < 1 || M < 1 || !gX || !X || !gF || !gt) return 3;
+    /* gF = T^{-T} gX: Thomas on the transpose, i.e. t1 and t-1 exchanged */
+    int st = oracle_solve(t1, t0, tm1, N, M, gX, gF, 0, nthreads);
+    if (st) return st;
+    long double s_m1 = 0.0L, s_0 = 0.0L, s_p1 = 0.0L;
+    for (int64_t m = 0; m < M; ++m) {
+        const double *g = gF + m * N, *x = X + m * N;
+        for (int64_t i = 0; i < N; ++i) {
+            s_0 += (long double)g[i] * x[i];
+            if (i + 1 < N) {
+                s_p1 += (long double)g[i] * x[i + 1];
+                s_m1 += (long double)g[i + 1] * x[i];
+            }
+        }
+    }
+    gt[0] = (double)(-s_m1);
+    gt[1] = (double)(-s_0);
+    gt[2] = (double)(-s_p1);
+    return 0;
+}
+
+/* Varlen adjoint: one (dL/dt-1, dL/dt0, dL/dt1) triple per system, gt: [S][3]. */
+int oracle_adjoint_varlen(int64_t S, const int64_t *offsets, const double *tm1,
+                          const double *t0, const double *t1, const double *gX,
+                          const double *X, double *gF, double *gt, int nthreads)
+{
+    if (S < 1 || !offsets || !gX || !X || !gF || !gt) return 3;
+    int st = oracle_solve_varlen(S, offsets, t1, t0, tm1, gX, gF, 0, nthreads);
+    if (st) return st;
+    for (int64_t s = 0; s < S; ++s) {
+        int64_t o = offsets[s], n = offsets[s + 1] - o;
+        const double *g = gF + o, *x = X + o;
+        long double s_m1 = 0.0L, s_0 = 0.0L, s_p1 = 0.0L;
+        for (int64_t i = 0; i < n; ++i) {
+            s_0 += (long double)g[i] * x[i];
+            if (i + 1 < n) {
+                s_p1 += (long double)g[i] * x[i + 1];
+                s_m1 += (long double)g[i + 1] * x[i];
+            }
+        }
+        gt[3 * s + 0] = (double)(-s_m1);
+        gt[3 * s + 1] = (double)(-s_0);
+        gt[3 * s + 2] = (double)(-s_p1);
+    }
+    return 0;
+}
+
+/* Threads the OpenMP runtime would use after set_threads(nthreads). */
+int oracle_threads(int nthreads) { return set_threads(nthreads); }
