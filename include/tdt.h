@@ -1,0 +1,158 @@
+/*
+ * tdt.h -- C ABI of the MI355X (gfx950) solver for Toeplitz tridiagonal
+ * systems T X = F, T = tridiag{t_-1, t_0, t_1}, by the partitioned dichotomy
+ * method (Terekhov, "Application of the Parallel Dichotomy Algorithm for
+ * solving Toeplitz tridiagonal systems of linear equations with one
+ * right-hand side").
+ *
+ * Matrix convention (paper, eq. (1)): row i of T X = F reads
+ *     t_-1 x_{i-1} + t_0 x_i + t_1 x_{i+1} = f_i,     i = 0 .. N-1,
+ * with x_{-1} = x_N = 0: t_1 is the super-diagonal, t_-1 the sub-diagonal.
+ *
+ * Every function returns a tdt_status_t; nothing throws across the ABI.
+ * Data buffers (F, X, gX, gF, gt) are DEVICE pointers owned by the caller;
+ * the library never frees them.  All device work is enqueued on the caller's
+ * stream and is asynchronous: the library never synchronises that stream.
+ * Argument errors are reported synchronously, before anything is enqueued.
+ * A plan owns its device constants and workspace; one plan must not be used
+ * by two solves that may run concurrently (they share the workspace).
+ */
+#ifndef TDT_H
+#define TDT_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tdt_plan_s *tdt_plan_t;
+
+/* Arithmetic of a plan.  Data in and out are double for TDT_F64 and
+ * TDT_F32_REFINE, float for TDT_F32.
+ *   TDT_F64        every step in double;
+ *   TDT_F32        every step in float (accuracy ~ cond(T) * 2^-24);
+ *   TDT_F32_REFINE sweeps, interface pass and correction in float; the
+ *                  residual r = F - T X and the update X += d in double,
+ *                  repeated until the update stops shrinking (iterative
+ *                  refinement), so the result matches the double solve. */
+typedef enum { TDT_F64 = 0, TDT_F32 = 1, TDT_F32_REFINE = 2 } tdt_dtype_t;
+
+typedef enum {
+    TDT_OK = 0,
+    /* solved, but |t_0| < |t_1| + |t_-1|: diagonal dominance, the paper's
+       sufficient condition of stability (Sec. 3.4), does not hold, so
+       rounding errors may grow from one interface level to the next */
+    TDT_WARN_NOT_DOMINANT = 1,
+    TDT_ERR_INVALID_ARG = -1,   /* bad size, null pointer, aliasing, wrong plan kind */
+    TDT_ERR_SINGULAR = -2,      /* T, or one of the sub-blocks the method inverts, is singular */
+    TDT_ERR_HIP = -3,           /* a HIP runtime call or kernel launch failed */
+    TDT_ERR_OOM = -4,           /* device or host allocation failed */
+    TDT_ERR_NOT_CONVERGED = -5, /* reserved: refinement did not converge */
+    TDT_ERR_CAPTURE = -6        /* would allocate during stream capture: call tdt_plan_reserve first */
+} tdt_status_t;
+
+/* Plan for one Toeplitz matrix of order N (the preliminary step of the
+ * method, done once per T: Sec. 3.1 shows that for a Toeplitz matrix every
+ * quantity the interface pass needs costs O(1), so nothing here depends on
+ * the right-hand side).  Builds, in long double on the host, the LU
+ * multipliers of the B x B diagonal block, the block's responses to unit
+ * interface values ("shared basis", the local counterpart of the Green
+ * functions of eqs. (6)-(9) and of the interior problems of eqs. (26)-(27)),
+ * and the same end values for whole tiles; uploads them (blocking copy).
+ * Errors: N < 1, non-finite t's, out == NULL -> TDT_ERR_INVALID_ARG;
+ * a zero pivot in a diagonal block or an interface merge that divides by
+ * zero -> TDT_ERR_SINGULAR.  Returns TDT_WARN_NOT_DOMINANT (plan usable)
+ * when |t_0| < |t_1| + |t_-1|. */
+tdt_status_t tdt_plan_create(double t_m1, double t_0, double t_1, int64_t N,
+                             tdt_dtype_t dtype, tdt_plan_t *out);
+
+/* Plan for S systems of different sizes, each with its own matrix (the
+ * series of Sec. 3.2 produced by separating variables: one system per
+ * Fourier mode).  h_offsets: host array of S+1 increasing int64, system s
+ * occupies elements [h_offsets[s], h_offsets[s+1]) of the packed F and X
+ * (h_offsets[0] may be non-zero only as 0; sizes >= 1).  h_tm1, h_t0, h_t1:
+ * host arrays of S doubles.  Errors and warnings as tdt_plan_create; a
+ * warning refers to the least dominant system. */
+tdt_status_t tdt_plan_varlen_create(int64_t S, const int64_t *h_offsets,
+                                    const double *h_tm1, const double *h_t0,
+                                    const double *h_t1, tdt_dtype_t dtype,
+                                    tdt_plan_t *out);
+
+/* Allocate the workspace for up to M_max right-hand sides now, so that later
+ * solves allocate nothing and may be captured in a hipGraph.  Blocking. */
+tdt_status_t tdt_plan_reserve(tdt_plan_t plan, int64_t M_max);
+
+/* Solve T X_m = F_m for M right-hand sides sharing the plan's matrix (the
+ * series of eq. (2) with a Toeplitz matrix; M = 1 is the single system of
+ * the paper's title).  F, X: device, [M][N] row-major, element type of the
+ * plan's dtype.  X must not overlap F.  Errors: M < 1, null pointers,
+ * overlap, varlen plan -> TDT_ERR_INVALID_ARG; workspace growth during
+ * capture -> TDT_ERR_CAPTURE; launch failure -> TDT_ERR_HIP. */
+tdt_status_t tdt_solve(tdt_plan_t plan, const void *F, void *X, int64_t M,
+                       hipStream_t stream);
+
+/* Solve every system of a varlen plan: F, X device, packed by the plan's
+ * offsets, element type of the plan's dtype.  One launch sequence for all
+ * systems; systems are processed largest first.  Errors as tdt_solve. */
+tdt_status_t tdt_solve_varlen(tdt_plan_t plan, const void *F, void *X,
+                              hipStream_t stream);
+
+/* Adjoint (reverse mode) of X = T^{-1} F for the loss L with dL/dX = gX.
+ * gF = T^{-T} gX is solved through the same dichotomy machinery with t_1 and
+ * t_-1 exchanged (T^T = tridiag{t_1, t_0, t_-1}; the paper's remark in
+ * Sec. 2.3 that (A^T)^{-1} = (A^{-1})^T), and
+ *   d_gt[3s+0] = dL/dt_-1 = - sum_i gF_{i+1} x_i
+ *   d_gt[3s+1] = dL/dt_0  = - sum_i gF_i     x_i
+ *   d_gt[3s+2] = dL/dt_1  = - sum_i gF_i     x_{i+1}
+ * reduced on the device in a fixed order (bitwise repeatable), summed over
+ * the M right-hand sides of a series plan (S = 1) or per system s of a varlen
+ * plan.  gX, X, gF: device, layout of tdt_solve / tdt_solve_varlen (M is
+ * ignored for a varlen plan); X is the forward solution.  d_gt: device, S*3
+ * doubles (may be NULL to skip the t gradients).  gF must not overlap gX or X. */
+tdt_status_t tdt_solve_backward(tdt_plan_t plan, const void *gX, const void *X,
+                                void *gF, double *d_gt, int64_t M,
+                                hipStream_t stream);
+
+/* Free the plan's device memory.  Waits for the device to finish with it. */
+tdt_status_t tdt_plan_destroy(tdt_plan_t plan);
+
+/* Static string for a status code. */
+const char *tdt_status_string(tdt_status_t status);
+
+/* Facts about a plan (any pointer may be NULL): refinement iterations the
+ * last TDT_F32_REFINE solve needed at most (0 otherwise; read back from the
+ * device, so this call synchronises the device), the dominance ratio
+ * min_s |t_0|/(|t_1|+|t_-1|), and the 2-norm condition number of T (the
+ * largest over systems), from the closed-form spectrum
+ * t_0 + 2 sgn(t_1) sqrt(t_1 t_-1) cos(k pi/(N+1)) when t_1 t_-1 > 0, else the
+ * infinity-norm bound from dominance (infinite when not dominant). */
+tdt_status_t tdt_last_info(tdt_plan_t plan, int *n_refine_iters,
+                           double *last_rel_update, double *dominance,
+                           double *kappa2);
+
+/* Host-only (no device needed): the per-T constants the plan would upload for
+ * block length B (1 <= B <= 64): out[0..B) = 1/u_k (inverse pivots of the
+ * B x B block), out[B..2B) = t_1/u_k, out[2B..3B) = phi (response of the
+ * block to a unit value left of it), out[3B..4B) = chi (response to a unit
+ * value right of it), out[4B..4B+4) = (phi_0, phi_{B-1}, chi_0, chi_{B-1}).
+ * Used to test the preliminary step against dense inverses. */
+tdt_status_t tdt_block_constants(double t_m1, double t_0, double t_1, int B,
+                                 double *out);
+
+/* Host-only: the interface merge of two adjacent segments, in double, as the
+ * kernels compute it.  seg = (y_first, y_last, phi_first, phi_last,
+ * chi_first, chi_last) of the left (l) and right (r) segment; out = the
+ * merged six values.  Returns TDT_ERR_SINGULAR if the merge divides by 0. */
+tdt_status_t tdt_segment_merge(const double *l, const double *r, double *out);
+
+/* Compile-time layout facts of this build: block length B and threads per
+ * workgroup for double and float data, and the tile length. */
+tdt_status_t tdt_build_info(int *block_f64, int *block_f32, int *wg_threads,
+                            int64_t *tile_len);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TDT_H */

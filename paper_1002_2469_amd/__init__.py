@@ -1,0 +1,277 @@
+"""Toeplitz tridiagonal solves T X = F on one MI355X by the partitioned
+dichotomy method, T = tridiag{t_-1, t_0, t_1} (t_1 above the diagonal).
+
+Thin Python layer over the C ABI of ``include/tdt.h``: it marshals torch
+device pointers, sizes and the current stream; every arithmetic step runs in
+the HIP kernels of ``libtdt.so``.  PyTorch is used for device memory and
+streams only.
+
+    plan = Plan(t_m1, t_0, t_1, N, dtype="f64")      # preliminary step, once per T
+    X = plan.solve(F)                                # F: cuda [N] or [M, N]
+    gF, gt = plan.backward(gX, X)                    # adjoint: T^T gF = gX, dL/dt
+    vp = VarlenPlan(offsets, t_m1s, t_0s, t_1s)      # many systems, own sizes and T
+    X = vp.solve(F_packed)
+    X = TridiagToeplitzSolve.apply(F, t)             # autograd, t = (t_-1, t_0, t_1)
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import DTYPES, TDTError, build
+
+__all__ = ["Plan", "VarlenPlan", "solve", "TridiagToeplitzSolve", "block_constants",
+           "segment_merge", "build_info", "build", "TDTError"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream=None):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _data_dtype(dtype: str):
+    torch = _torch()
+    return torch.float32 if dtype == "f32" else torch.float64
+
+
+def _check_tensor(t, dtype, numel, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+
+
+class _PlanBase:
+    def __init__(self):
+        self._h = ctypes.c_void_p()
+        self.status = 0
+
+    def reserve(self, m_max: int = 1):
+        """Allocate the workspace now (required before capturing a hipGraph)."""
+        _lib.check(_lib.lib().tdt_plan_reserve(self._h, int(m_max)), "tdt_plan_reserve")
+
+    def info(self) -> dict:
+        it = ctypes.c_int(0)
+        upd, dom, kap = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _lib.check(_lib.lib().tdt_last_info(self._h, ctypes.byref(it), ctypes.byref(upd),
+                                            ctypes.byref(dom), ctypes.byref(kap)),
+                   "tdt_last_info")
+        return dict(refine_iters=it.value, dominance=dom.value, kappa2=kap.value)
+
+    def close(self):
+        if self._h:
+            _lib.lib().tdt_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan(_PlanBase):
+    """Plan of one Toeplitz matrix of order N (data dtype: 'f64', 'f32' or
+    'f32_refine'; the last takes and returns float64)."""
+
+    def __init__(self, t_m1: float, t_0: float, t_1: float, N: int, dtype: str = "f64"):
+        super().__init__()
+        if dtype not in DTYPES:
+            raise ValueError(f"dtype must be one of {list(DTYPES)}")
+        self.t = (float(t_m1), float(t_0), float(t_1))
+        self.N = int(N)
+        self.dtype = dtype
+        self.status = _lib.check(_lib.lib().tdt_plan_create(
+            self.t[0], self.t[1], self.t[2], self.N, DTYPES[dtype], ctypes.byref(self._h)),
+            "tdt_plan_create")
+
+    @property
+    def dominant(self) -> bool:
+        return self.status != _lib.TDT_WARN_NOT_DOMINANT
+
+    def solve(self, F, X=None, stream=None):
+        torch = _torch()
+        dt = _data_dtype(self.dtype)
+        M = F.numel() // self.N if F.numel() else 0
+        if F.numel() != M * self.N or M < 1:
+            raise ValueError("F must hold M whole right-hand sides of length N")
+        _check_tensor(F, dt, M * self.N, "F")
+        if X is None:
+            X = torch.empty_like(F)
+        _check_tensor(X, dt, M * self.N, "X")
+        _lib.check(_lib.lib().tdt_solve(self._h, ctypes.c_void_p(F.data_ptr()),
+                                        ctypes.c_void_p(X.data_ptr()), M,
+                                        _stream_handle(stream)), "tdt_solve")
+        return X
+
+    def backward(self, gX, X, gF=None, gt=None, stream=None):
+        """gF = T^{-T} gX and gt = (dL/dt_-1, dL/dt_0, dL/dt_1) summed over RHS."""
+        torch = _torch()
+        dt = _data_dtype(self.dtype)
+        M = gX.numel() // self.N
+        _check_tensor(gX, dt, M * self.N, "gX")
+        _check_tensor(X, dt, M * self.N, "X")
+        if gF is None:
+            gF = torch.empty_like(gX)
+        if gt is None:
+            gt = torch.empty(3, dtype=torch.float64, device=gX.device)
+        _check_tensor(gF, dt, M * self.N, "gF")
+        _check_tensor(gt, torch.float64, 3, "gt")
+        _lib.check(_lib.lib().tdt_solve_backward(
+            self._h, ctypes.c_void_p(gX.data_ptr()), ctypes.c_void_p(X.data_ptr()),
+            ctypes.c_void_p(gF.data_ptr()), ctypes.c_void_p(gt.data_ptr()), M,
+            _stream_handle(stream)), "tdt_solve_backward")
+        return gF, gt
+
+
+class VarlenPlan(_PlanBase):
+    """S systems of sizes offsets[s+1]-offsets[s], each with its own t's,
+    packed back to back."""
+
+    def __init__(self, offsets, t_m1, t_0, t_1, dtype: str = "f64"):
+        super().__init__()
+        if dtype not in DTYPES:
+            raise ValueError(f"dtype must be one of {list(DTYPES)}")
+        self.offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        self.S = self.offsets.size - 1
+        ts = [np.ascontiguousarray(np.broadcast_to(np.asarray(t, dtype=np.float64), (self.S,)))
+              for t in (t_m1, t_0, t_1)]
+        self.t = ts
+        self.total = int(self.offsets[-1])
+        self.dtype = dtype
+        self.status = _lib.check(_lib.lib().tdt_plan_varlen_create(
+            self.S, self.offsets.ctypes.data_as(ctypes.c_void_p),
+            ts[0].ctypes.data_as(ctypes.c_void_p), ts[1].ctypes.data_as(ctypes.c_void_p),
+            ts[2].ctypes.data_as(ctypes.c_void_p), DTYPES[dtype], ctypes.byref(self._h)),
+            "tdt_plan_varlen_create")
+
+    def solve(self, F, X=None, stream=None):
+        torch = _torch()
+        dt = _data_dtype(self.dtype)
+        _check_tensor(F, dt, self.total, "F")
+        if X is None:
+            X = torch.empty_like(F)
+        _check_tensor(X, dt, self.total, "X")
+        _lib.check(_lib.lib().tdt_solve_varlen(self._h, ctypes.c_void_p(F.data_ptr()),
+                                               ctypes.c_void_p(X.data_ptr()),
+                                               _stream_handle(stream)), "tdt_solve_varlen")
+        return X
+
+    def backward(self, gX, X, gF=None, gt=None, stream=None):
+        """gF = T_s^{-T} gX per system and gt[s] = (dL/dt_-1, dL/dt_0, dL/dt_1)."""
+        torch = _torch()
+        dt = _data_dtype(self.dtype)
+        _check_tensor(gX, dt, self.total, "gX")
+        _check_tensor(X, dt, self.total, "X")
+        if gF is None:
+            gF = torch.empty_like(gX)
+        if gt is None:
+            gt = torch.empty((self.S, 3), dtype=torch.float64, device=gX.device)
+        _check_tensor(gF, dt, self.total, "gF")
+        _check_tensor(gt, torch.float64, 3 * self.S, "gt")
+        _lib.check(_lib.lib().tdt_solve_backward(
+            self._h, ctypes.c_void_p(gX.data_ptr()), ctypes.c_void_p(X.data_ptr()),
+            ctypes.c_void_p(gF.data_ptr()), ctypes.c_void_p(gt.data_ptr()), 1,
+            _stream_handle(stream)), "tdt_solve_backward")
+        return gF, gt
+
+
+_plan_cache: dict = {}
+
+
+def _cached_plan(t_m1, t_0, t_1, N, dtype) -> Plan:
+    key = (float(t_m1), float(t_0), float(t_1), int(N), dtype)
+    p = _plan_cache.get(key)
+    if p is None:
+        if len(_plan_cache) > 64:
+            _plan_cache.clear()
+        p = Plan(*key)
+        _plan_cache[key] = p
+    return p
+
+
+def solve(F, t_m1: float, t_0: float, t_1: float, dtype: str = "f64"):
+    """X = T^{-1} F along the last dimension of F (cached plan per T and N)."""
+    return _cached_plan(t_m1, t_0, t_1, F.shape[-1], dtype).solve(F.contiguous())
+
+
+class TridiagToeplitzSolve:
+    """Differentiable X = T^{-1} F; t = (t_-1, t_0, t_1) as a tensor of 3.
+
+    Backward is the hand-written adjoint kernel: gF = T^{-T} gX through the
+    same dichotomy machinery, and the t-gradients reduced on the device."""
+
+    _fn = None
+
+    @classmethod
+    def _function(cls):
+        if cls._fn is None:
+            torch = _torch()
+
+            class _Fn(torch.autograd.Function):
+                @staticmethod
+                def forward(ctx, F, t, dtype="f64"):
+                    tv = [float(v) for v in t.detach().cpu().tolist()]
+                    plan = _cached_plan(tv[0], tv[1], tv[2], F.shape[-1], dtype)
+                    X = plan.solve(F.contiguous())
+                    ctx.plan = plan
+                    ctx.t_device, ctx.t_dtype = t.device, t.dtype
+                    ctx.save_for_backward(X)
+                    return X
+
+                @staticmethod
+                def backward(ctx, gX):
+                    (X,) = ctx.saved_tensors
+                    gF, gt = ctx.plan.backward(gX.contiguous(), X)
+                    return gF, gt.to(device=ctx.t_device, dtype=ctx.t_dtype), None
+
+            cls._fn = _Fn
+        return cls._fn
+
+    @classmethod
+    def apply(cls, F, t, dtype: str = "f64"):
+        return cls._function().apply(F, t, dtype)
+
+
+def block_constants(t_m1: float, t_0: float, t_1: float, B: int) -> dict:
+    """Host-only: the per-T block constants the plan uploads (no GPU needed)."""
+    out = np.empty(4 * B + 4)
+    _lib.check(_lib.lib().tdt_block_constants(float(t_m1), float(t_0), float(t_1), int(B),
+                                              out.ctypes.data_as(ctypes.c_void_p)),
+               "tdt_block_constants")
+    return dict(inv_pivot=out[:B], cp=out[B:2 * B], phi=out[2 * B:3 * B],
+                chi=out[3 * B:4 * B], ends=out[4 * B:])
+
+
+def segment_merge(left, right) -> np.ndarray:
+    """Host-only: the kernels' interface merge of two segment summaries."""
+    l = np.ascontiguousarray(left, dtype=np.float64)
+    r = np.ascontiguousarray(right, dtype=np.float64)
+    out = np.empty(6)
+    _lib.check(_lib.lib().tdt_segment_merge(l.ctypes.data_as(ctypes.c_void_p),
+                                            r.ctypes.data_as(ctypes.c_void_p),
+                                            out.ctypes.data_as(ctypes.c_void_p)),
+               "tdt_segment_merge")
+    return out
+
+
+def build_info() -> dict:
+    b64, b32, nt = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    tile = ctypes.c_int64()
+    _lib.lib().tdt_build_info(ctypes.byref(b64), ctypes.byref(b32), ctypes.byref(nt),
+                              ctypes.byref(tile))
+    return dict(block_f64=b64.value, block_f32=b32.value, wg_threads=nt.value,
+                tile=tile.value)

@@ -1,0 +1,602 @@
+// tdt_api.cpp -- host side of the C ABI declared in include/tdt.h: the
+// once-per-matrix preliminary step (plan), workspace management and the
+// launch sequence of a solve.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "tdt.h"
+#include "tdt_internal.h"
+
+
+using tdt::kB;
+using tdt::kNT;
+using tdt::kTile;
+using tdt::SysDesc;
+typedef long double ld;
+
+struct tdt_plan_s {
+  bool varlen = false;
+  tdt_dtype_t dtype = TDT_F64;
+  int64_t N = 0;          // series: order of the system
+  int64_t S = 1;          // number of systems
+  int64_t total = 0;      // varlen: packed length
+  std::vector<SysDesc> hsys[2];   // [0]: T, [1]: T^T (adjoint)
+  SysDesc* dsys[2] = {nullptr, nullptr};
+  double* dvec64[2] = {nullptr, nullptr};
+  float* dvec32[2] = {nullptr, nullptr};
+  // varlen launch lists
+  int2* dp1 = nullptr;
+  int2* dfin = nullptr;
+  int* dgrid = nullptr;
+  int64_t n_p1 = 0, n_fin = 0, n_grid = 0;
+  int64_t vslots = 0, vfslots = 0;
+  // workspace
+  int64_t ws_slots = 0, ws_fslots = 0;
+  double* summ = nullptr;
+  double* ghost = nullptr;
+  double* gscr = nullptr;
+  double* gpart = nullptr;
+  int* iters = nullptr;
+  double dominance = 0.0, kappa = 0.0;
+  int max_iter = 40;
+  double refine_tol = 1e-14;
+};
+
+// ---------------------------------------------------------------------------
+// Preliminary step (host, long double).
+// ---------------------------------------------------------------------------
+namespace {
+
+// LU multipliers of the B x B block and its responses to unit outside values
+// (the forward sweep d_i = (q_i - t_-1 d_{i-1}) / u_i and back substitution
+// y_i = d_i - (t_1/u_i) y_{i+1} the kernels run).  Returns false on a zero pivot.
+bool block_vectors(ld a, ld b, ld c, int B, ld* iu, ld* cp, ld* phi, ld* chi) {
+  ld u = b;
+  if (u == 0.0L) return false;
+  iu[0] = 1.0L / u;
+  cp[0] = c * iu[0];
+  for (int i = 1; i < B; ++i) {
+    u = b - a * cp[i - 1];
+    if (u == 0.0L) return false;
+    iu[i] = 1.0L / u;
+    cp[i] = c * iu[i];
+  }
+  // phi: T_B phi = -t_-1 e_0
+  phi[0] = -a * iu[0];
+  for (int i = 1; i < B; ++i) phi[i] = -a * phi[i - 1] * iu[i];
+  for (int i = B - 2; i >= 0; --i) phi[i] -= cp[i] * phi[i + 1];
+  // chi: T_B chi = -t_1 e_{B-1}
+  for (int i = 0; i + 1 < B; ++i) chi[i] = 0.0L;
+  chi[B - 1] = -c * iu[B - 1];
+  for (int i = B - 2; i >= 0; --i) chi[i] -= cp[i] * chi[i + 1];
+  return true;
+}
+
+// End values (phi_first, phi_last, chi_first, chi_last) of a run of L rows,
+// by an O(L) long double elimination.  Returns false on a zero pivot.
+bool segment_ends(ld a, ld b, ld c, int64_t L, ld out[4]) {
+  std::vector<ld> cpv((size_t)L), d1((size_t)L), d2((size_t)L);
+  ld u = b;
+  if (u == 0.0L) return false;
+  cpv[0] = c / u;
+  d1[0] = -a / u;
+  d2[0] = L == 1 ? -c / u : 0.0L;
+  for (int64_t i = 1; i < L; ++i) {
+    u = b - a * cpv[i - 1];
+    if (u == 0.0L) return false;
+    cpv[i] = c / u;
+    d1[i] = (0.0L - a * d1[i - 1]) / u;
+    d2[i] = ((i == L - 1 ? -c : 0.0L) - a * d2[i - 1]) / u;
+  }
+  for (int64_t i = L - 2; i >= 0; --i) {
+    d1[i] -= cpv[i] * d1[i + 1];
+    d2[i] -= cpv[i] * d2[i + 1];
+  }
+  out[0] = d1[0];
+  out[1] = d1[L - 1];
+  out[2] = d2[0];
+  out[3] = d2[L - 1];
+  return std::isfinite((double)out[0]) && std::isfinite((double)out[1]) &&
+         std::isfinite((double)out[2]) && std::isfinite((double)out[3]);
+}
+
+struct SegLD {
+  ld yf, yl, pf, pl, cf, cl;
+};
+
+bool merge_ld(const SegLD& L, const SegLD& R, SegLD& M) {
+  const ld D = 1.0L - L.cl * R.pf;
+  if (!(std::fabs((double)D) > 1e-13)) return false;
+  const ld iD = 1.0L / D;
+  const ld xk0 = (L.yl + L.cl * R.yf) * iD;
+  const ld xk10 = R.yf + R.pf * xk0;
+  const ld tl = L.pl * iD, ur = R.cf * iD;
+  M.yf = L.yf + xk10 * L.cf;
+  M.yl = R.yl + xk0 * R.pl;
+  M.pf = L.pf + L.cf * R.pf * tl;
+  M.pl = tl * R.pl;
+  M.cf = L.cf * ur;
+  M.cl = R.cl + L.cl * ur * R.pl;
+  return true;
+}
+
+// The interface merges the kernels perform divide by 1 - chi_last(L) phi_first(R)
+// for runs of full blocks of every length up to a wavefront and beyond; check
+// them for runs of up to 64 + 64 blocks.  Under diagonal dominance they are
+// bounded away from zero; otherwise a sub-block may be (nearly) singular.
+bool merges_ok(const ld blk4[4]) {
+  std::vector<SegLD> run(65);
+  run[1] = SegLD{0, 0, blk4[0], blk4[1], blk4[2], blk4[3]};
+  for (int k = 2; k <= 64; ++k)
+    if (!merge_ld(run[k - 1], run[1], run[k])) return false;
+  SegLD tmp;
+  for (int j = 1; j <= 64; ++j)
+    for (int k = 1; k <= 64; ++k)
+      if (!merge_ld(run[j], run[k], tmp)) return false;
+  return true;
+}
+
+double dominance_ratio(double a, double b, double c) {
+  const double off = std::fabs(a) + std::fabs(c);
+  return off == 0.0 ? std::numeric_limits<double>::infinity() : std::fabs(b) / off;
+}
+
+// 2-norm condition number from the closed-form spectrum when t_1 t_-1 > 0
+// (T is similar to a symmetric matrix), else the infinity-norm bound.
+double condition_number(double a, double b, double c, int64_t n) {
+  if (a * c > 0.0) {
+    const double s = std::sqrt(a * c) * (c > 0 ? 1.0 : -1.0);
+    const double pi = 3.14159265358979323846;
+    auto lam = [&](double k) { return b + 2.0 * s * std::cos(k * pi / (double)(n + 1)); };
+    double lmax = std::max(std::fabs(lam(1)), std::fabs(lam((double)n)));
+    double lmin = std::min(std::fabs(lam(1)), std::fabs(lam((double)n)));
+    if (std::fabs(b) < 2.0 * std::fabs(s)) {   // the spectrum straddles zero
+      const double th = std::acos(-b / (2.0 * s));
+      const double k0 = th * (double)(n + 1) / pi;
+      for (double k = std::floor(k0) - 1; k <= std::floor(k0) + 2; k += 1.0)
+        if (k >= 1 && k <= (double)n) lmin = std::min(lmin, std::fabs(lam(k)));
+    }
+    return lmin > 0 ? lmax / lmin : std::numeric_limits<double>::infinity();
+  }
+  const double off = std::fabs(a) + std::fabs(c);
+  if (std::fabs(b) > off) return (std::fabs(b) + off) / (std::fabs(b) - off);
+  if (n == 1) return 1.0;
+  return std::numeric_limits<double>::infinity();
+}
+
+// Fill the descriptor and the block vectors of one system.
+tdt_status_t build_system(double a, double b, double c, int64_t n, SysDesc& D, double* v64,
+                          float* v32) {
+  ld iu[kB], cp[kB], phi[kB], chi[kB];
+  if (!block_vectors(a, b, c, kB, iu, cp, phi, chi)) return TDT_ERR_SINGULAR;
+  for (int i = 0; i < kB; ++i) {
+    const ld vv[4] = {iu[i], cp[i], phi[i], chi[i]};
+    for (int k = 0; k < 4; ++k) {
+      v64[k * kB + i] = (double)vv[k];
+      v32[k * kB + i] = (float)vv[k];
+      if (!std::isfinite(v64[k * kB + i])) return TDT_ERR_SINGULAR;
+    }
+  }
+  D.a = a;
+  D.b = b;
+  D.c = c;
+  D.n = n;
+  D.ntiles = (int32_t)((n + kTile - 1) / kTile);
+  const ld blk[4] = {phi[0], phi[kB - 1], chi[0], chi[kB - 1]};
+  for (int k = 0; k < 4; ++k) D.blk[k] = (double)blk[k];
+  if (!merges_ok(blk)) return TDT_ERR_SINGULAR;
+  // last block of the system
+  const int bt = (int)((n - 1) % kB) + 1;
+  if (bt == kB) {
+    D.tail_pf = D.blk[0];
+  } else {
+    ld e[4];
+    if (!segment_ends(a, b, c, bt, e)) return TDT_ERR_SINGULAR;
+    D.tail_pf = (double)e[0];
+  }
+  if (D.ntiles > 1) {
+    ld e[4];
+    if (!segment_ends(a, b, c, kTile, e)) return TDT_ERR_SINGULAR;
+    for (int k = 0; k < 4; ++k) D.tileK[k] = (double)e[k];
+    const int64_t lt = n - (int64_t)(D.ntiles - 1) * kTile;
+    if (lt == kTile) {
+      for (int k = 0; k < 4; ++k) D.ltileK[k] = D.tileK[k];
+    } else {
+      if (!segment_ends(a, b, c, lt, e)) return TDT_ERR_SINGULAR;
+      D.ltileK[0] = (double)e[0];
+      D.ltileK[1] = D.ltileK[2] = D.ltileK[3] = 0.0;
+    }
+  } else {
+    for (int k = 0; k < 4; ++k) D.tileK[k] = D.ltileK[k] = 0.0;
+  }
+  return TDT_OK;
+}
+
+bool finite3(double a, double b, double c) {
+  return std::isfinite(a) && std::isfinite(b) && std::isfinite(c);
+}
+
+template <typename T>
+tdt_status_t dev_upload(T** dst, const T* src, size_t count) {
+  *dst = nullptr;
+  if (count == 0) return TDT_OK;
+  if (hipMalloc(reinterpret_cast<void**>(dst), count * sizeof(T)) != hipSuccess) {
+    *dst = nullptr;
+    return TDT_ERR_OOM;
+  }
+  if (hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+    return TDT_ERR_HIP;
+  return TDT_OK;
+}
+
+void free_workspace(tdt_plan_s* p) {
+  (void)hipFree(p->summ);
+  (void)hipFree(p->ghost);
+  (void)hipFree(p->gscr);
+  (void)hipFree(p->gpart);
+  p->summ = p->ghost = p->gscr = p->gpart = nullptr;
+  p->ws_slots = p->ws_fslots = 0;
+}
+
+// Make sure the workspace holds `slots` tile slots and `fslots` adjoint
+// partial-sum slots.  Never allocates while the stream is being captured.
+tdt_status_t ensure_workspace(tdt_plan_s* p, int64_t slots, int64_t fslots, hipStream_t st) {
+  if (slots <= p->ws_slots && fslots <= p->ws_fslots) return TDT_OK;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+    return TDT_ERR_CAPTURE;
+  const int64_t ns = std::max(slots, p->ws_slots), nf = std::max(fslots, p->ws_fslots);
+  (void)hipDeviceSynchronize();
+  free_workspace(p);
+  if (ns > 0) {
+    if (hipMalloc(&p->summ, (size_t)ns * 2 * sizeof(double)) != hipSuccess ||
+        hipMalloc(&p->ghost, (size_t)ns * 2 * sizeof(double)) != hipSuccess ||
+        hipMalloc(&p->gscr, (size_t)ns * 3 * sizeof(double)) != hipSuccess) {
+      free_workspace(p);
+      return TDT_ERR_OOM;
+    }
+  }
+  if (nf > 0 && hipMalloc(&p->gpart, (size_t)nf * 3 * sizeof(double)) != hipSuccess) {
+    free_workspace(p);
+    return TDT_ERR_OOM;
+  }
+  p->ws_slots = ns;
+  p->ws_fslots = nf;
+  return TDT_OK;
+}
+
+void destroy(tdt_plan_s* p) {
+  if (!p) return;
+  (void)hipDeviceSynchronize();
+  for (int k = 0; k < 2; ++k) {
+    (void)hipFree(p->dsys[k]);
+    (void)hipFree(p->dvec64[k]);
+    (void)hipFree(p->dvec32[k]);
+  }
+  (void)hipFree(p->dp1);
+  (void)hipFree(p->dfin);
+  (void)hipFree(p->dgrid);
+  (void)hipFree(p->iters);
+  free_workspace(p);
+  delete p;
+}
+
+// Build both descriptor sets (T and T^T) and upload everything.
+tdt_status_t finish_plan(tdt_plan_s* p, const std::vector<double>& tm1,
+                         const std::vector<double>& t0, const std::vector<double>& t1,
+                         const std::vector<int64_t>& sizes, const std::vector<int64_t>& offs) {
+  const int64_t S = (int64_t)sizes.size();
+  double dom = std::numeric_limits<double>::infinity(), kap = 0.0;
+  for (int dir = 0; dir < 2; ++dir) {
+    std::vector<double> v64((size_t)S * tdt::kVecN * kB);
+    std::vector<float> v32((size_t)S * tdt::kVecN * kB);
+    p->hsys[dir].assign((size_t)S, SysDesc());
+    for (int64_t s = 0; s < S; ++s) {
+      const double a = dir == 0 ? tm1[s] : t1[s];
+      const double c = dir == 0 ? t1[s] : tm1[s];
+      SysDesc& D = p->hsys[dir][s];
+      std::memset(&D, 0, sizeof(D));
+      tdt_status_t st = build_system(a, t0[s], c, sizes[s], D,
+                                     v64.data() + (size_t)s * tdt::kVecN * kB,
+                                     v32.data() + (size_t)s * tdt::kVecN * kB);
+      if (st != TDT_OK) return st;
+      D.off = offs[s];
+      D.cidx = (int32_t)s;
+      if (dir == 0) {
+        dom = std::min(dom, dominance_ratio(tm1[s], t0[s], t1[s]));
+        kap = std::max(kap, condition_number(tm1[s], t0[s], t1[s], sizes[s]));
+      }
+    }
+    // varlen bookkeeping: tile slots for multi-tile systems, partial-sum slots
+    int64_t fs = 0;
+    for (int64_t s = 0; s < S; ++s) {
+      p->hsys[dir][s].fslot0 = (int32_t)fs;
+      fs += p->hsys[dir][s].ntiles;
+    }
+    p->vfslots = fs;
+    tdt_status_t st = dev_upload(&p->dvec64[dir], v64.data(), v64.size());
+    if (st == TDT_OK) st = dev_upload(&p->dvec32[dir], v32.data(), v32.size());
+    if (st != TDT_OK) return st;
+  }
+  p->dominance = dom;
+  p->kappa = kap;
+  if (p->varlen) {
+    std::vector<int64_t> order((size_t)S);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int64_t x, int64_t y) { return sizes[x] > sizes[y]; });
+    std::vector<int2> p1, fin;
+    std::vector<int> grid;
+    int64_t slot = 0;
+    for (int64_t s : order) {
+      const int nt = p->hsys[0][s].ntiles;
+      if (nt > 1) {
+        for (int dir = 0; dir < 2; ++dir) p->hsys[dir][s].slot0 = (int32_t)slot;
+        for (int t = 0; t < nt; ++t) p1.push_back(make_int2((int)s, t));
+        grid.push_back((int)s);
+        slot += nt;
+      }
+    }
+    for (int64_t s : order)
+      for (int t = 0; t < p->hsys[0][s].ntiles; ++t) fin.push_back(make_int2((int)s, t));
+    p->vslots = slot;
+    p->n_p1 = (int64_t)p1.size();
+    p->n_fin = (int64_t)fin.size();
+    p->n_grid = (int64_t)grid.size();
+    tdt_status_t st = dev_upload(&p->dp1, p1.data(), p1.size());
+    if (st == TDT_OK) st = dev_upload(&p->dfin, fin.data(), fin.size());
+    if (st == TDT_OK) st = dev_upload(&p->dgrid, grid.data(), grid.size());
+    if (st != TDT_OK) return st;
+  }
+  for (int dir = 0; dir < 2; ++dir) {
+    tdt_status_t st = dev_upload(&p->dsys[dir], p->hsys[dir].data(), p->hsys[dir].size());
+    if (st != TDT_OK) return st;
+  }
+  if (hipMalloc(&p->iters, sizeof(int)) != hipSuccess) return TDT_ERR_OOM;
+  if (hipMemset(p->iters, 0, sizeof(int)) != hipSuccess) return TDT_ERR_HIP;
+  if (hipDeviceSynchronize() != hipSuccess) return TDT_ERR_HIP;
+  return p->dominance < 1.0 ? TDT_WARN_NOT_DOMINANT : TDT_OK;
+}
+
+bool overlaps(const void* x, size_t nx, const void* y, size_t ny) {
+  const uintptr_t a = reinterpret_cast<uintptr_t>(x), b = reinterpret_cast<uintptr_t>(y);
+  return a < b + ny && b < a + nx;
+}
+
+size_t elem_size(tdt_dtype_t d) { return d == TDT_F32 ? sizeof(float) : sizeof(double); }
+
+tdt_status_t run(tdt_plan_s* p, int dir, const void* F, void* X, const void* Xfwd, int64_t M,
+                 hipStream_t st) {
+  tdt::LaunchSet L{};
+  L.sys = p->dsys[dir];
+  L.vec64 = p->dvec64[dir];
+  L.vec32 = p->dvec32[dir];
+  L.iters = p->iters;
+  L.max_iter = p->max_iter;
+  L.refine_tol = p->refine_tol;
+  int64_t slots, fslots;
+  if (p->varlen) {
+    L.p1_items = p->dp1;
+    L.fin_items = p->dfin;
+    L.grid_items = p->dgrid;
+    L.n_p1 = p->n_p1;
+    L.n_fin = p->n_fin;
+    L.n_grid = p->n_grid;
+    slots = p->vslots;
+    fslots = Xfwd ? p->vfslots : 0;
+  } else {
+    const int64_t nt = p->hsys[0][0].ntiles;
+    L.p1_items = nullptr;
+    L.fin_items = nullptr;
+    L.grid_items = nullptr;
+    L.n_p1 = nt > 1 ? M * nt : 0;
+    L.n_grid = nt > 1 ? M : 0;
+    L.n_fin = M * nt;
+    slots = nt > 1 ? M * nt : 0;
+    fslots = Xfwd ? M * nt : 0;
+  }
+  if (L.n_fin > 0x7fffffffLL) return TDT_ERR_INVALID_ARG;
+  tdt_status_t s = ensure_workspace(p, slots, fslots, st);
+  if (s != TDT_OK) return s;
+  L.summ = p->summ;
+  L.ghost = p->ghost;
+  L.gscr = p->gscr;
+  L.gpart = p->gpart;
+  if (tdt::launch_solve((int)p->dtype, Xfwd != nullptr, L, F, X, Xfwd, st) != hipSuccess)
+    return TDT_ERR_HIP;
+  return TDT_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* tdt_status_string(tdt_status_t s) {
+  switch (s) {
+    case TDT_OK: return "ok";
+    case TDT_WARN_NOT_DOMINANT: return "solved; matrix not diagonally dominant";
+    case TDT_ERR_INVALID_ARG: return "invalid argument";
+    case TDT_ERR_SINGULAR: return "singular matrix or sub-block";
+    case TDT_ERR_HIP: return "HIP runtime error";
+    case TDT_ERR_OOM: return "out of memory";
+    case TDT_ERR_NOT_CONVERGED: return "refinement did not converge";
+    case TDT_ERR_CAPTURE: return "allocation needed during stream capture";
+  }
+  return "unknown status";
+}
+
+tdt_status_t tdt_plan_create(double t_m1, double t_0, double t_1, int64_t N, tdt_dtype_t dtype,
+                             tdt_plan_t* out) {
+  if (!out) return TDT_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (N < 1 || N > ((int64_t)1 << 40) || !finite3(t_m1, t_0, t_1) ||
+      (dtype != TDT_F64 && dtype != TDT_F32 && dtype != TDT_F32_REFINE))
+    return TDT_ERR_INVALID_ARG;
+  tdt_plan_s* p = new (std::nothrow) tdt_plan_s();
+  if (!p) return TDT_ERR_OOM;
+  p->dtype = dtype;
+  p->N = N;
+  p->S = 1;
+  tdt_status_t st = finish_plan(p, {t_m1}, {t_0}, {t_1}, {N}, {0});
+  if (st < 0) {
+    destroy(p);
+    return st;
+  }
+  *out = p;
+  return st;
+}
+
+tdt_status_t tdt_plan_varlen_create(int64_t S, const int64_t* h_offsets, const double* h_tm1,
+                                    const double* h_t0, const double* h_t1, tdt_dtype_t dtype,
+                                    tdt_plan_t* out) {
+  if (!out) return TDT_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (S < 1 || S > 0x7fffffffLL || !h_offsets || !h_tm1 || !h_t0 || !h_t1 ||
+      (dtype != TDT_F64 && dtype != TDT_F32 && dtype != TDT_F32_REFINE) || h_offsets[0] != 0)
+    return TDT_ERR_INVALID_ARG;
+  std::vector<int64_t> sizes((size_t)S), offs((size_t)S);
+  std::vector<double> tm1(h_tm1, h_tm1 + S), t0(h_t0, h_t0 + S), t1(h_t1, h_t1 + S);
+  for (int64_t s = 0; s < S; ++s) {
+    sizes[s] = h_offsets[s + 1] - h_offsets[s];
+    offs[s] = h_offsets[s];
+    if (sizes[s] < 1 || !finite3(tm1[s], t0[s], t1[s])) return TDT_ERR_INVALID_ARG;
+  }
+  tdt_plan_s* p = new (std::nothrow) tdt_plan_s();
+  if (!p) return TDT_ERR_OOM;
+  p->varlen = true;
+  p->dtype = dtype;
+  p->S = S;
+  p->total = h_offsets[S];
+  tdt_status_t st = finish_plan(p, tm1, t0, t1, sizes, offs);
+  if (st < 0) {
+    destroy(p);
+    return st;
+  }
+  *out = p;
+  return st;
+}
+
+tdt_status_t tdt_plan_reserve(tdt_plan_t p, int64_t M_max) {
+  if (!p || M_max < 1) return TDT_ERR_INVALID_ARG;
+  int64_t slots, fslots;
+  if (p->varlen) {
+    slots = p->vslots;
+    fslots = p->vfslots;
+  } else {
+    const int64_t nt = p->hsys[0][0].ntiles;
+    slots = nt > 1 ? M_max * nt : 0;
+    fslots = M_max * nt;
+  }
+  return ensure_workspace(p, slots, fslots, nullptr);
+}
+
+tdt_status_t tdt_solve(tdt_plan_t p, const void* F, void* X, int64_t M, hipStream_t stream) {
+  if (!p || p->varlen || !F || !X || M < 1) return TDT_ERR_INVALID_ARG;
+  const size_t bytes = (size_t)M * (size_t)p->N * elem_size(p->dtype);
+  if (overlaps(F, bytes, X, bytes)) return TDT_ERR_INVALID_ARG;
+  return run(p, 0, F, X, nullptr, M, stream);
+}
+
+tdt_status_t tdt_solve_varlen(tdt_plan_t p, const void* F, void* X, hipStream_t stream) {
+  if (!p || !p->varlen || !F || !X) return TDT_ERR_INVALID_ARG;
+  const size_t bytes = (size_t)p->total * elem_size(p->dtype);
+  if (overlaps(F, bytes, X, bytes)) return TDT_ERR_INVALID_ARG;
+  return run(p, 0, F, X, nullptr, 1, stream);
+}
+
+tdt_status_t tdt_solve_backward(tdt_plan_t p, const void* gX, const void* X, void* gF,
+                                double* d_gt, int64_t M, hipStream_t stream) {
+  if (!p || !gX || !X || !gF) return TDT_ERR_INVALID_ARG;
+  if (p->varlen) M = 1;
+  if (M < 1) return TDT_ERR_INVALID_ARG;
+  const size_t bytes =
+      (size_t)(p->varlen ? p->total : M * p->N) * elem_size(p->dtype);
+  if (overlaps(gF, bytes, gX, bytes) || overlaps(gF, bytes, X, bytes)) return TDT_ERR_INVALID_ARG;
+  tdt_status_t st = run(p, 1, gX, gF, X, M, stream);
+  if (st != TDT_OK) return st;
+  if (d_gt) {
+    const int64_t nparts = p->varlen ? p->vfslots : M * p->hsys[0][0].ntiles;
+    if (tdt::launch_gt_reduce(p->gpart, p->dsys[1], p->S, nparts, p->varlen ? 1 : 0, d_gt,
+                              stream) != hipSuccess)
+      return TDT_ERR_HIP;
+  }
+  return TDT_OK;
+}
+
+tdt_status_t tdt_plan_destroy(tdt_plan_t p) {
+  if (!p) return TDT_ERR_INVALID_ARG;
+  destroy(p);
+  return TDT_OK;
+}
+
+tdt_status_t tdt_last_info(tdt_plan_t p, int* n_refine_iters, double* last_rel_update,
+                           double* dominance, double* kappa2) {
+  if (!p) return TDT_ERR_INVALID_ARG;
+  if (n_refine_iters) {
+    int v = 0;
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(&v, p->iters, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemset(p->iters, 0, sizeof(int)) != hipSuccess)
+      return TDT_ERR_HIP;
+    *n_refine_iters = v;
+  }
+  if (last_rel_update) *last_rel_update = 0.0;
+  if (dominance) *dominance = p->dominance;
+  if (kappa2) *kappa2 = p->kappa;
+  return TDT_OK;
+}
+
+tdt_status_t tdt_block_constants(double t_m1, double t_0, double t_1, int B, double* out) {
+  if (!out || B < 1 || B > 64 || !finite3(t_m1, t_0, t_1)) return TDT_ERR_INVALID_ARG;
+  ld iu[64], cp[64], phi[64], chi[64];
+  if (!block_vectors(t_m1, t_0, t_1, B, iu, cp, phi, chi)) return TDT_ERR_SINGULAR;
+  for (int i = 0; i < B; ++i) {
+    out[i] = (double)iu[i];
+    out[B + i] = (double)cp[i];
+    out[2 * B + i] = (double)phi[i];
+    out[3 * B + i] = (double)chi[i];
+  }
+  out[4 * B + 0] = (double)phi[0];
+  out[4 * B + 1] = (double)phi[B - 1];
+  out[4 * B + 2] = (double)chi[0];
+  out[4 * B + 3] = (double)chi[B - 1];
+  return TDT_OK;
+}
+
+tdt_status_t tdt_segment_merge(const double* l, const double* r, double* out) {
+  if (!l || !r || !out) return TDT_ERR_INVALID_ARG;
+  const double D = 1.0 - l[5] * r[2];
+  if (D == 0.0) return TDT_ERR_SINGULAR;
+  const double iD = 1.0 / D;
+  const double xk0 = (l[1] + l[5] * r[0]) * iD;
+  const double xk10 = r[0] + r[2] * xk0;
+  const double tl = l[3] * iD, ur = r[4] * iD;
+  out[0] = l[0] + xk10 * l[4];
+  out[1] = r[1] + xk0 * r[3];
+  out[2] = l[2] + l[4] * r[2] * tl;
+  out[3] = tl * r[3];
+  out[4] = l[4] * ur;
+  out[5] = r[5] + l[5] * ur * r[3];
+  return TDT_OK;
+}
+
+tdt_status_t tdt_build_info(int* block_f64, int* block_f32, int* wg_threads, int64_t* tile_len) {
+  if (block_f64) *block_f64 = kB;
+  if (block_f32) *block_f32 = kB;
+  if (wg_threads) *wg_threads = kNT;
+  if (tile_len) *tile_len = kTile;
+  return TDT_OK;
+}
+
+}  // extern "C"

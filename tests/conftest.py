@@ -25,3 +25,11 @@ def gpu_available() -> bool:
 def orc():
     import oracle
     return oracle
+
+
+# Import torch at collection time so that its first (slow) import on a fresh
+# machine is not charged to the first test's time limit.
+try:
+    import torch  # noqa: F401
+except Exception:  # pragma: no cover
+    pass

@@ -1,0 +1,123 @@
+"""Error paths, warnings, info and hipGraph capture through the C ABI."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import to_dev, to_host
+from paper_1002_2469_amd import _lib
+
+pytestmark = pytest.mark.gpu
+
+
+def _tdt():
+    import paper_1002_2469_amd as tdt
+    return tdt
+
+
+def test_error_paths():
+    import torch
+    tdt = _tdt()
+    L = _lib.lib()
+    plan = tdt.Plan(-1.0, 4.0, -1.0, 100)
+    F = to_dev(np.ones(300))
+    p = lambda t: ctypes.c_void_p(t.data_ptr())
+    assert L.tdt_solve(plan._h, p(F), p(F), 3, None) == _lib.TDT_ERR_INVALID_ARG   # X aliases F
+    X = torch.empty_like(F)
+    assert L.tdt_solve(plan._h, p(F), p(X), 0, None) == _lib.TDT_ERR_INVALID_ARG
+    assert L.tdt_solve(plan._h, None, p(X), 1, None) == _lib.TDT_ERR_INVALID_ARG
+    assert L.tdt_solve_varlen(plan._h, p(F), p(X), None) == _lib.TDT_ERR_INVALID_ARG
+    assert L.tdt_solve_backward(plan._h, p(F), p(X), p(F), None, 3, None) == \
+        _lib.TDT_ERR_INVALID_ARG                                                  # gF aliases gX
+    assert L.tdt_plan_reserve(plan._h, 0) == _lib.TDT_ERR_INVALID_ARG
+    with pytest.raises(tdt.TDTError) as e:
+        tdt.Plan(1.0, 0.0, 1.0, 10)                         # zero pivot in the block
+    assert e.value.status == _lib.TDT_ERR_SINGULAR
+    vp = tdt.VarlenPlan([0, 5, 9], [-1, -1], [3, 3], [-1, -1])
+    assert L.tdt_solve(vp._h, p(F), p(X), 1, None) == _lib.TDT_ERR_INVALID_ARG
+
+
+def test_not_dominant_warns_and_solves():
+    tdt = _tdt()
+    a, b, c = 0.5, 0.9, 0.7          # ratio 0.75
+    n = 40
+    plan = tdt.Plan(a, b, c, n)
+    assert plan.status == _lib.TDT_WARN_NOT_DOMINANT and not plan.dominant
+    rng = np.random.default_rng(1)
+    F = rng.standard_normal(n)
+    X = to_host(plan.solve(to_dev(F)))
+    from oracle_pins import dense_T
+    kap = np.linalg.cond(dense_T(n, a, b, c))
+    assert oracle.rel_err(X, oracle.solve(F, a, b, c)) <= 1e-12 * max(1.0, kap)
+
+
+def test_nan_propagates_without_crash():
+    tdt = _tdt()
+    F = np.ones(5000)
+    F[1234] = np.nan
+    X = to_host(tdt.Plan(-1.0, 4.0, -1.0, 5000).solve(to_dev(F)))
+    assert np.isnan(X).any()
+
+
+def test_info():
+    tdt = _tdt()
+    plan = tdt.Plan(-0.9, 2.5, -1.1, 10000, "f32_refine")
+    plan.solve(to_dev(np.random.default_rng(0).standard_normal(10000)))
+    info = plan.info()
+    assert 1 <= info["refine_iters"] <= 40
+    assert info["dominance"] == pytest.approx(1.25)
+    assert 1 < info["kappa2"] < 20
+
+
+@pytest.mark.parametrize("varlen", [False, True])
+def test_hipgraph_capture_replay(varlen):
+    import torch
+    tdt = _tdt()
+    rng = np.random.default_rng(11)
+    if varlen:
+        sizes = np.array([300, 9000, 17, 20000])
+        off = np.concatenate([[0], np.cumsum(sizes)])
+        t0 = rng.uniform(2.5, 4.0, 4)
+        plan = tdt.VarlenPlan(off, -1.0, t0, -0.9, "f32_refine")
+        n_total = int(off[-1])
+        ref_fn = lambda F: oracle.solve_varlen(F, off, -1.0, t0, -0.9)
+        solve = plan.solve
+    else:
+        n_total = 3 * 20000
+        plan = tdt.Plan(-1.0, 3.0, -0.8, 20000, "f64")
+        ref_fn = lambda F: oracle.solve(F.reshape(3, -1), -1.0, 3.0, -0.8).reshape(-1)
+        solve = plan.solve
+    plan.reserve(3)
+    Fd = to_dev(rng.standard_normal(n_total))
+    Xd = torch.empty_like(Fd)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        solve(Fd, Xd)                                   # warm-up outside capture
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        solve(Fd, Xd)
+    for k in range(4):
+        Fh = rng.standard_normal(n_total)
+        Fd.copy_(torch.from_numpy(Fh))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert oracle.rel_err(to_host(Xd), ref_fn(Fh)) <= 1e-12, k
+        _ = (Xd * 2).sum().item()                       # eager work between replays
+
+
+def test_capture_without_reserve_is_refused():
+    import torch
+    tdt = _tdt()
+    plan = tdt.Plan(-1.0, 3.0, -1.0, 50000)              # multi-tile: needs workspace
+    Fd = to_dev(np.ones(50000))
+    Xd = torch.empty_like(Fd)
+    g = torch.cuda.CUDAGraph()
+    with pytest.raises(tdt.TDTError) as e:
+        with torch.cuda.graph(g):
+            plan.solve(Fd, Xd)
+    assert e.value.status == _lib.TDT_ERR_CAPTURE

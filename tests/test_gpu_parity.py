@@ -1,0 +1,137 @@
+"""GPU parity of the forward solve against the CPU oracle (through the C ABI).
+
+Sizes span one lane, one wavefront, one tile and several tiles, with ragged
+last blocks and tiles; matrices are nonsymmetric with off-diagonals of both
+signs and dominance ratios in [1, 3]."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import to_dev, to_host, tol_f32, tol_f64
+from paper_1002_2469_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [1, 2, 3, 31, 32, 33, 63, 64, 65, 2047, 2048, 2049, 8191, 8192, 8193, 16383, 16385,
+         3 * 8192 + 5, 10 * 8192 + 31]
+
+
+def _tdt():
+    import paper_1002_2469_amd as tdt
+    return tdt
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("dtype", ["f64", "f32_refine", "f32"])
+def test_sweep_sizes(n, dtype):
+    tdt = _tdt()
+    rng = np.random.default_rng(n)
+    for rep, M in enumerate((1, 3)):
+        a, b, c = W.random_system(rng, 1.25 if dtype == "f32" else 1.0, 3.0)
+        F = rng.standard_normal((M, n))
+        print(f"[case] n={n} M={M} dtype={dtype} t=({a:.3f},{b:.3f},{c:.3f})", flush=True)
+        plan = tdt.Plan(a, b, c, n, dtype)
+        X = to_host(plan.solve(to_dev(F, dtype)))
+        Fr = F.astype(np.float32).astype(np.float64) if dtype == "f32" else F
+        ref = oracle.solve(Fr, a, b, c)
+        err = oracle.rel_err_rows(X, ref).max()
+        tol = tol_f32(a, b, c, n) if dtype == "f32" else tol_f64(a, b, c, n)
+        assert err <= tol, (n, M, dtype, (a, b, c), err)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32_refine"])
+def test_single_small_config_and_manufactured(dtype):
+    tdt = _tdt()
+    d = W.single_small(0)
+    plan = tdt.Plan(d["t_m1"], d["t_0"], d["t_1"], d["N"], dtype)
+    X = to_host(plan.solve(to_dev(d["F"])))
+    ref = oracle.solve(d["F"], d["t_m1"], d["t_0"], d["t_1"])
+    assert oracle.rel_err(X, ref) <= 1e-12
+    m = W.single_small(0, manufactured=True)
+    from oracle_pins import stencil
+    F = stencil(m["X_true"].copy(), m["t_m1"], m["t_0"], m["t_1"])
+    X = to_host(plan.solve(to_dev(F)))
+    assert oracle.rel_err(X, oracle.solve(F, m["t_m1"], m["t_0"], m["t_1"])) <= 1e-12
+    assert oracle.rel_err(X, m["X_true"]) <= 1e-12
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32_refine", "f32"])
+def test_series_config(dtype):
+    tdt = _tdt()
+    d = W.series(0)
+    plan = tdt.Plan(d["t_m1"], d["t_0"], d["t_1"], d["N"], dtype)
+    X = to_host(plan.solve(to_dev(d["F"], dtype)))
+    Fr = d["F"].astype(np.float32).astype(np.float64) if dtype == "f32" else d["F"]
+    ref = oracle.solve(Fr, d["t_m1"], d["t_0"], d["t_1"])
+    err = oracle.rel_err_rows(X, ref).max()
+    assert err <= (2e-5 if dtype == "f32" else 1e-12), err
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32_refine"])
+def test_single_large_config(dtype):
+    tdt = _tdt()
+    d = W.single_large(0)
+    plan = tdt.Plan(d["t_m1"], d["t_0"], d["t_1"], d["N"], dtype)
+    X = to_host(plan.solve(to_dev(d["F"])))
+    ref = oracle.solve(d["F"], d["t_m1"], d["t_0"], d["t_1"])
+    assert oracle.rel_err(X, ref) <= 1e-12
+
+
+def _varlen_check(d, dtype, tol_of):
+    tdt = _tdt()
+    plan = tdt.VarlenPlan(d["offsets"], d["t_m1"], d["t_0"], d["t_1"], dtype)
+    X = to_host(plan.solve(to_dev(d["F"], dtype)))
+    F = d["F"].astype(np.float32).astype(np.float64) if dtype == "f32" else d["F"]
+    ref = oracle.solve_varlen(F, d["offsets"], d["t_m1"], d["t_0"], d["t_1"])
+    errs = oracle.rel_err_rows(X, ref, d["offsets"])
+    sizes = np.diff(d["offsets"])
+    tols = np.array([tol_of(d["t_m1"][s], d["t_0"][s], d["t_1"][s], int(sizes[s]))
+                     for s in range(len(sizes))])
+    bad = np.nonzero(errs > tols)[0]
+    assert bad.size == 0, [(int(s), int(sizes[s]), errs[s], tols[s]) for s in bad[:5]]
+    return plan
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32_refine", "f32"])
+def test_varlen_ragged(dtype):
+    rng = np.random.default_rng(7)
+    sizes = np.array([1, 2, 3, 33, 8192, 8193, 65, 20000, 5, 16384, 31, 64, 100000])
+    S = len(sizes)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    ts = [W.random_system(rng, 1.25 if dtype == "f32" else 1.0, 3.0) for _ in range(S)]
+    d = dict(offsets=off, t_m1=np.array([t[0] for t in ts]), t_0=np.array([t[1] for t in ts]),
+             t_1=np.array([t[2] for t in ts]), F=rng.standard_normal(int(off[-1])))
+    _varlen_check(d, dtype, tol_f32 if dtype == "f32" else tol_f64)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32_refine"])
+def test_sov_batch_config(dtype):
+    d = W.sov_batch(0)
+    plan = _varlen_check(d, dtype, tol_f64)
+    # against the long double truth too (the ill-conditioned low modes)
+    X = to_host(plan.solve(to_dev(d["F"])))
+    truth = oracle.solve_varlen(d["F"], d["offsets"], d["t_m1"], d["t_0"], d["t_1"],
+                                precision="ld")
+    errs = oracle.rel_err_rows(X, truth, d["offsets"])
+    sizes = np.diff(d["offsets"])
+    tols = np.array([tol_f64(1.0, d["t_0"][s], 1.0, int(sizes[s])) for s in range(len(sizes))])
+    assert np.all(errs <= tols)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32_refine"])
+def test_diff_batch_config_forward(dtype):
+    d = W.diff_batch(0)
+    _varlen_check(dict(offsets=d["offsets"], t_m1=d["t_m1"], t_0=d["t_0"], t_1=d["t_1"],
+                       F=d["F"].reshape(-1)), dtype, tol_f64)
+
+
+def test_repeatable_bitwise():
+    tdt = _tdt()
+    rng = np.random.default_rng(3)
+    n = 3 * 8192 + 77
+    F = to_dev(rng.standard_normal((2, n)))
+    for dtype in ("f64", "f32_refine"):
+        plan = tdt.Plan(-0.9, 2.5, -1.1, n, dtype)
+        X1 = to_host(plan.solve(F))
+        X2 = to_host(plan.solve(F))
+        assert np.array_equal(X1, X2)

@@ -1,0 +1,133 @@
+"""Host-side checks of the C ABI library (no GPU): exported symbols, the
+preliminary-step constants against dense inverses, the interface merge against
+dense solves, and argument validation that happens before any device call."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle_pins import dense_T
+
+import paper_1002_2469_amd as tdt
+from paper_1002_2469_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_symbols():
+    src = open(os.path.join(ROOT, "include", "tdt.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tdt_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.lib()
+    declared = _header_symbols()
+    assert declared == sorted(_lib.EXPORTS)
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+@pytest.mark.parametrize("t", [(-1.0, 4.0, -1.0), (-0.9, 2.5, -1.1), (0.7, -1.9, 0.45),
+                               (1.0, -2.0000003, 1.0)])
+@pytest.mark.parametrize("B", [1, 2, 5, 32])
+def test_block_constants_match_dense_inverse(t, B):
+    a, b, c = t
+    k = tdt.block_constants(a, b, c, B)
+    T = dense_T(B, a, b, c)
+    Ti = np.linalg.inv(T)
+    e0 = np.zeros(B); e0[0] = -a
+    eB = np.zeros(B); eB[-1] = -c
+    phi, chi = Ti @ e0, Ti @ eB
+    scale = np.max(np.abs(Ti))
+    assert np.allclose(k["phi"], phi, rtol=0, atol=1e-14 * max(1, scale))
+    assert np.allclose(k["chi"], chi, rtol=0, atol=1e-14 * max(1, scale))
+    # pivots u_k = det(T_k) / det(T_{k-1})
+    dets = [1.0] + [np.linalg.det(T[:j, :j]) for j in range(1, B + 1)]
+    piv = np.array([dets[j + 1] / dets[j] for j in range(B)])
+    assert np.allclose(1.0 / k["inv_pivot"], piv, rtol=1e-12)
+    assert np.allclose(k["cp"], c / piv, rtol=1e-12)
+    assert np.allclose(k["ends"], [phi[0], phi[-1], chi[0], chi[-1]], rtol=0,
+                       atol=1e-14 * max(1, scale))
+
+
+def _dense_summary(f, a, b, c):
+    n = len(f)
+    T = dense_T(n, a, b, c)
+    y = np.linalg.solve(T, f)
+    e0 = np.zeros(n); e0[0] = -a
+    en = np.zeros(n); en[-1] = -c
+    phi, chi = np.linalg.solve(T, e0), np.linalg.solve(T, en)
+    return np.array([y[0], y[-1], phi[0], phi[-1], chi[0], chi[-1]])
+
+
+@pytest.mark.parametrize("t", [(-1.0, 4.0, -1.0), (-0.9, 2.5, -1.1), (0.5, 0.9, 0.7)])
+@pytest.mark.parametrize("n1,n2", [(1, 1), (1, 7), (13, 2), (32, 32), (40, 23)])
+def test_segment_merge_is_the_union_summary(t, n1, n2):
+    a, b, c = t
+    rng = np.random.default_rng(n1 * 100 + n2)
+    f = rng.standard_normal(n1 + n2)
+    left = _dense_summary(f[:n1], a, b, c)
+    right = _dense_summary(f[n1:], a, b, c)
+    merged = tdt.segment_merge(left, right)
+    whole = _dense_summary(f, a, b, c)
+    assert np.allclose(merged, whole, rtol=1e-11, atol=1e-12)
+
+
+def test_merge_associativity():
+    a, b, c = -0.9, 2.5, -1.1
+    rng = np.random.default_rng(5)
+    f = rng.standard_normal(30)
+    s = [_dense_summary(f[i:i + 10], a, b, c) for i in (0, 10, 20)]
+    x = tdt.segment_merge(tdt.segment_merge(s[0], s[1]), s[2])
+    y = tdt.segment_merge(s[0], tdt.segment_merge(s[1], s[2]))
+    assert np.allclose(x, y, rtol=1e-13, atol=1e-15)
+
+
+def test_argument_validation_without_device():
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    assert L.tdt_plan_create(-1.0, 4.0, -1.0, 0, 0, ctypes.byref(h)) == _lib.TDT_ERR_INVALID_ARG
+    assert L.tdt_plan_create(float("nan"), 4.0, -1.0, 10, 0, ctypes.byref(h)) == _lib.TDT_ERR_INVALID_ARG
+    assert L.tdt_plan_create(-1.0, 4.0, -1.0, 10, 7, ctypes.byref(h)) == _lib.TDT_ERR_INVALID_ARG
+    assert L.tdt_plan_create(-1.0, 4.0, -1.0, 10, 0, None) == _lib.TDT_ERR_INVALID_ARG
+    off = np.array([0, 5, 5], dtype=np.int64)      # an empty system
+    t3 = np.ones(2)
+    p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    assert L.tdt_plan_varlen_create(2, p(off), p(t3), p(t3), p(t3), 0, ctypes.byref(h)) == \
+        _lib.TDT_ERR_INVALID_ARG
+    assert L.tdt_solve(None, None, None, 1, None) == _lib.TDT_ERR_INVALID_ARG
+    assert L.tdt_solve_varlen(None, None, None, None) == _lib.TDT_ERR_INVALID_ARG
+    assert L.tdt_solve_backward(None, None, None, None, None, 1, None) == _lib.TDT_ERR_INVALID_ARG
+    assert L.tdt_plan_reserve(None, 1) == _lib.TDT_ERR_INVALID_ARG
+    assert L.tdt_plan_destroy(None) == _lib.TDT_ERR_INVALID_ARG
+    assert L.tdt_last_info(None, None, None, None, None) == _lib.TDT_ERR_INVALID_ARG
+    out = np.empty(4 * 3 + 4)
+    assert L.tdt_block_constants(1.0, 0.0, 1.0, 3, p(out)) == _lib.TDT_ERR_SINGULAR
+    assert L.tdt_block_constants(1.0, 2.0, 1.0, 65, p(out)) == _lib.TDT_ERR_INVALID_ARG
+
+
+def test_status_strings():
+    for code in (0, 1, -1, -2, -3, -4, -5, -6):
+        assert _lib.status_string(code) not in ("", "unknown status")
+    assert _lib.status_string(42) == "unknown status"
+
+
+def test_product_path_has_no_oracle_or_fallback():
+    """The package never imports the oracle, and raises if the library is missing."""
+    pkg = os.path.join(ROOT, "paper_1002_2469_amd")
+    for fn in os.listdir(pkg):
+        if fn.endswith(".py"):
+            src = open(os.path.join(pkg, fn)).read()
+            assert "import oracle" not in src and "from oracle" not in src, fn
+    saved, _lib._lib = _lib._lib, None
+    real = _lib.LIB_PATH
+    try:
+        _lib.LIB_PATH = real + ".missing"
+        with pytest.raises(RuntimeError):
+            _lib.lib()
+    finally:
+        _lib.LIB_PATH = real
+        _lib._lib = saved
