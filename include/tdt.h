@@ -147,6 +147,16 @@ tdt_status_t tdt_block_constants(double t_m1, double t_0, double t_1, int B,
  * merged six values.  Returns TDT_ERR_SINGULAR if the merge divides by 0. */
 tdt_status_t tdt_segment_merge(const double *l, const double *r, double *out);
 
+/* Measurement support.  While enabled (enable != 0), every solve of the plan
+ * that is not being captured records HIP events on its stream around its
+ * three kernel groups: the first pass over tiles (tile summaries), the
+ * interface pass across tiles, and the final pass (solve and store).
+ * tdt_plan_profile_read synchronises the device, returns in ms3[0..2] the
+ * summed milliseconds of the three groups over the recorded solves and in
+ * *nsolves their number, and clears the record.  Disabling clears it too. */
+tdt_status_t tdt_plan_profile(tdt_plan_t plan, int enable);
+tdt_status_t tdt_plan_profile_read(tdt_plan_t plan, double *ms3, int64_t *nsolves);
+
 /* Compile-time layout facts of this build: block length B and threads per
  * workgroup for double and float data, and the tile length. */
 tdt_status_t tdt_build_info(int *block_f64, int *block_f32, int *wg_threads,

@@ -71,6 +71,18 @@ class _PlanBase:
                    "tdt_last_info")
         return dict(refine_iters=it.value, dominance=dom.value, kappa2=kap.value)
 
+    def profile(self, enable: bool = True):
+        """Record HIP events around the kernels of every later solve."""
+        _lib.check(_lib.lib().tdt_plan_profile(self._h, int(bool(enable))), "tdt_plan_profile")
+
+    def profile_read(self) -> dict:
+        """Summed ms of (first pass, interface pass, final pass) since the last read."""
+        ms = np.zeros(3)
+        n = ctypes.c_int64(0)
+        _lib.check(_lib.lib().tdt_plan_profile_read(self._h, ms.ctypes.data_as(ctypes.c_void_p),
+                                                    ctypes.byref(n)), "tdt_plan_profile_read")
+        return dict(first_pass_ms=ms[0], interface_ms=ms[1], final_ms=ms[2], solves=n.value)
+
     def close(self):
         if self._h:
             _lib.lib().tdt_plan_destroy(self._h)

@@ -33,7 +33,8 @@ DTYPES = {"f64": 0, "f32": 1, "f32_refine": 2}
 EXPORTS = [
     "tdt_plan_create", "tdt_plan_varlen_create", "tdt_plan_reserve", "tdt_solve",
     "tdt_solve_varlen", "tdt_solve_backward", "tdt_plan_destroy", "tdt_status_string",
-    "tdt_last_info", "tdt_block_constants", "tdt_segment_merge", "tdt_build_info",
+    "tdt_last_info", "tdt_block_constants", "tdt_segment_merge", "tdt_plan_profile",
+    "tdt_plan_profile_read", "tdt_build_info",
 ]
 
 
@@ -82,6 +83,8 @@ def lib():
                           ctypes.POINTER(d)],
         "tdt_block_constants": [d, d, d, i32, p],
         "tdt_segment_merge": [p, p, p],
+        "tdt_plan_profile": [p, i32],
+        "tdt_plan_profile_read": [p, p, ctypes.POINTER(i64)],
         "tdt_build_info": [ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
                            ctypes.POINTER(i64)],
     }

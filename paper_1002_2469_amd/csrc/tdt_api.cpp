@@ -32,6 +32,8 @@ struct tdt_plan_s {
   SysDesc* dsys[2] = {nullptr, nullptr};
   double* dvec64[2] = {nullptr, nullptr};
   float* dvec32[2] = {nullptr, nullptr};
+  double* dtab64[2] = {nullptr, nullptr};
+  float* dtab32[2] = {nullptr, nullptr};
   // varlen launch lists
   int2* dp1 = nullptr;
   int2* dfin = nullptr;
@@ -47,7 +49,10 @@ struct tdt_plan_s {
   int* iters = nullptr;
   double dominance = 0.0, kappa = 0.0;
   int max_iter = 40;
-  double refine_tol = 1e-14;
+  double refine_tol = 1e-13;
+  // measurement
+  bool profile = false;
+  std::vector<hipEvent_t> prof_ev;   // 4 per recorded solve
 };
 
 // ---------------------------------------------------------------------------
@@ -174,7 +179,7 @@ double condition_number(double a, double b, double c, int64_t n) {
 
 // Fill the descriptor and the block vectors of one system.
 tdt_status_t build_system(double a, double b, double c, int64_t n, SysDesc& D, double* v64,
-                          float* v32) {
+                          float* v32, double* t64, float* t32) {
   ld iu[kB], cp[kB], phi[kB], chi[kB];
   if (!block_vectors(a, b, c, kB, iu, cp, phi, chi)) return TDT_ERR_SINGULAR;
   for (int i = 0; i < kB; ++i) {
@@ -193,6 +198,22 @@ tdt_status_t build_system(double a, double b, double c, int64_t n, SysDesc& D, d
   const ld blk[4] = {phi[0], phi[kB - 1], chi[0], chi[kB - 1]};
   for (int k = 0; k < 4; ++k) D.blk[k] = (double)blk[k];
   if (!merges_ok(blk)) return TDT_ERR_SINGULAR;
+  // per-position table of the left-to-right interface elimination over the
+  // kNT blocks of a tile: beta_{m-1} and 1/(1 - phi_first beta_{m-1})
+  {
+    ld beta = 0.0L;
+    for (int m = 0; m < kNT; ++m) {
+      const ld D = 1.0L - blk[0] * beta;
+      if (!(std::fabs((double)D) > 1e-13)) return TDT_ERR_SINGULAR;
+      const ld iD = 1.0L / D;
+      t64[tdt::kTabBeta * kNT + m] = (double)beta;
+      t64[tdt::kTabInvD * kNT + m] = (double)iD;
+      t32[tdt::kTabBeta * kNT + m] = (float)beta;
+      t32[tdt::kTabInvD * kNT + m] = (float)iD;
+      beta = blk[3] + blk[1] * beta * blk[2] * iD;
+      if (!std::isfinite((double)beta)) return TDT_ERR_SINGULAR;
+    }
+  }
   // last block of the system
   const int bt = (int)((n - 1) % kB) + 1;
   if (bt == kB) {
@@ -201,6 +222,9 @@ tdt_status_t build_system(double a, double b, double c, int64_t n, SysDesc& D, d
     ld e[4];
     if (!segment_ends(a, b, c, bt, e)) return TDT_ERR_SINGULAR;
     D.tail_pf = (double)e[0];
+    for (int m = 0; m < kNT; ++m)   // the last block may sit at any position
+      if (!(std::fabs(1.0 - D.tail_pf * t64[tdt::kTabBeta * kNT + m]) > 1e-13))
+        return TDT_ERR_SINGULAR;
   }
   if (D.ntiles > 1) {
     ld e[4];
@@ -249,6 +273,10 @@ void free_workspace(tdt_plan_s* p) {
 // Make sure the workspace holds `slots` tile slots and `fslots` adjoint
 // partial-sum slots.  Never allocates while the stream is being captured.
 tdt_status_t ensure_workspace(tdt_plan_s* p, int64_t slots, int64_t fslots, hipStream_t st) {
+  // the kernels read the values just outside a tile unconditionally (slot 0
+  // for a one-tile system), so every array holds at least one slot
+  slots = std::max<int64_t>(slots, 1);
+  fslots = std::max<int64_t>(fslots, 1);
   if (slots <= p->ws_slots && fslots <= p->ws_fslots) return TDT_OK;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
@@ -256,30 +284,37 @@ tdt_status_t ensure_workspace(tdt_plan_s* p, int64_t slots, int64_t fslots, hipS
   const int64_t ns = std::max(slots, p->ws_slots), nf = std::max(fslots, p->ws_fslots);
   (void)hipDeviceSynchronize();
   free_workspace(p);
-  if (ns > 0) {
-    if (hipMalloc(&p->summ, (size_t)ns * 2 * sizeof(double)) != hipSuccess ||
-        hipMalloc(&p->ghost, (size_t)ns * 2 * sizeof(double)) != hipSuccess ||
-        hipMalloc(&p->gscr, (size_t)ns * 3 * sizeof(double)) != hipSuccess) {
-      free_workspace(p);
-      return TDT_ERR_OOM;
-    }
-  }
-  if (nf > 0 && hipMalloc(&p->gpart, (size_t)nf * 3 * sizeof(double)) != hipSuccess) {
+  if (hipMalloc(&p->summ, (size_t)ns * 2 * sizeof(double)) != hipSuccess ||
+      hipMalloc(&p->ghost, (size_t)ns * 2 * sizeof(double)) != hipSuccess ||
+      hipMalloc(&p->gscr, (size_t)ns * 3 * sizeof(double)) != hipSuccess ||
+      hipMalloc(&p->gpart, (size_t)nf * 3 * sizeof(double)) != hipSuccess) {
     free_workspace(p);
     return TDT_ERR_OOM;
+  }
+  if (hipMemset(p->ghost, 0, (size_t)ns * 2 * sizeof(double)) != hipSuccess) {
+    free_workspace(p);
+    return TDT_ERR_HIP;
   }
   p->ws_slots = ns;
   p->ws_fslots = nf;
   return TDT_OK;
 }
 
+void clear_profile(tdt_plan_s* p) {
+  for (hipEvent_t e : p->prof_ev) (void)hipEventDestroy(e);
+  p->prof_ev.clear();
+}
+
 void destroy(tdt_plan_s* p) {
   if (!p) return;
   (void)hipDeviceSynchronize();
+  clear_profile(p);
   for (int k = 0; k < 2; ++k) {
     (void)hipFree(p->dsys[k]);
     (void)hipFree(p->dvec64[k]);
     (void)hipFree(p->dvec32[k]);
+    (void)hipFree(p->dtab64[k]);
+    (void)hipFree(p->dtab32[k]);
   }
   (void)hipFree(p->dp1);
   (void)hipFree(p->dfin);
@@ -298,6 +333,8 @@ tdt_status_t finish_plan(tdt_plan_s* p, const std::vector<double>& tm1,
   for (int dir = 0; dir < 2; ++dir) {
     std::vector<double> v64((size_t)S * tdt::kVecN * kB);
     std::vector<float> v32((size_t)S * tdt::kVecN * kB);
+    std::vector<double> t64((size_t)S * tdt::kTabN * kNT);
+    std::vector<float> t32((size_t)S * tdt::kTabN * kNT);
     p->hsys[dir].assign((size_t)S, SysDesc());
     for (int64_t s = 0; s < S; ++s) {
       const double a = dir == 0 ? tm1[s] : t1[s];
@@ -306,7 +343,9 @@ tdt_status_t finish_plan(tdt_plan_s* p, const std::vector<double>& tm1,
       std::memset(&D, 0, sizeof(D));
       tdt_status_t st = build_system(a, t0[s], c, sizes[s], D,
                                      v64.data() + (size_t)s * tdt::kVecN * kB,
-                                     v32.data() + (size_t)s * tdt::kVecN * kB);
+                                     v32.data() + (size_t)s * tdt::kVecN * kB,
+                                     t64.data() + (size_t)s * tdt::kTabN * kNT,
+                                     t32.data() + (size_t)s * tdt::kTabN * kNT);
       if (st != TDT_OK) return st;
       D.off = offs[s];
       D.cidx = (int32_t)s;
@@ -324,6 +363,8 @@ tdt_status_t finish_plan(tdt_plan_s* p, const std::vector<double>& tm1,
     p->vfslots = fs;
     tdt_status_t st = dev_upload(&p->dvec64[dir], v64.data(), v64.size());
     if (st == TDT_OK) st = dev_upload(&p->dvec32[dir], v32.data(), v32.size());
+    if (st == TDT_OK) st = dev_upload(&p->dtab64[dir], t64.data(), t64.size());
+    if (st == TDT_OK) st = dev_upload(&p->dtab32[dir], t32.data(), t32.size());
     if (st != TDT_OK) return st;
   }
   p->dominance = dom;
@@ -360,6 +401,10 @@ tdt_status_t finish_plan(tdt_plan_s* p, const std::vector<double>& tm1,
     tdt_status_t st = dev_upload(&p->dsys[dir], p->hsys[dir].data(), p->hsys[dir].size());
     if (st != TDT_OK) return st;
   }
+  {
+    const tdt_status_t ws = ensure_workspace(p, 1, 1, nullptr);
+    if (ws != TDT_OK) return ws;
+  }
   if (hipMalloc(&p->iters, sizeof(int)) != hipSuccess) return TDT_ERR_OOM;
   if (hipMemset(p->iters, 0, sizeof(int)) != hipSuccess) return TDT_ERR_HIP;
   if (hipDeviceSynchronize() != hipSuccess) return TDT_ERR_HIP;
@@ -379,6 +424,8 @@ tdt_status_t run(tdt_plan_s* p, int dir, const void* F, void* X, const void* Xfw
   L.sys = p->dsys[dir];
   L.vec64 = p->dvec64[dir];
   L.vec32 = p->dvec32[dir];
+  L.tab64 = p->dtab64[dir];
+  L.tab32 = p->dtab32[dir];
   L.iters = p->iters;
   L.max_iter = p->max_iter;
   L.refine_tol = p->refine_tol;
@@ -406,10 +453,22 @@ tdt_status_t run(tdt_plan_s* p, int dir, const void* F, void* X, const void* Xfw
   if (L.n_fin > 0x7fffffffLL) return TDT_ERR_INVALID_ARG;
   tdt_status_t s = ensure_workspace(p, slots, fslots, st);
   if (s != TDT_OK) return s;
+  if (!p->summ || !p->ghost || !p->gscr || !p->gpart) return TDT_ERR_OOM;
   L.summ = p->summ;
   L.ghost = p->ghost;
   L.gscr = p->gscr;
   L.gpart = p->gpart;
+  L.ev = nullptr;
+  if (p->profile) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
+      const size_t k = p->prof_ev.size();
+      p->prof_ev.resize(k + 4);
+      for (size_t j = 0; j < 4; ++j)
+        if (hipEventCreate(&p->prof_ev[k + j]) != hipSuccess) return TDT_ERR_HIP;
+      L.ev = p->prof_ev.data() + k;
+    }
+  }
   if (tdt::launch_solve((int)p->dtype, Xfwd != nullptr, L, F, X, Xfwd, st) != hipSuccess)
     return TDT_ERR_HIP;
   return TDT_OK;
@@ -588,6 +647,35 @@ tdt_status_t tdt_segment_merge(const double* l, const double* r, double* out) {
   out[3] = tl * r[3];
   out[4] = l[4] * ur;
   out[5] = r[5] + l[5] * ur * r[3];
+  return TDT_OK;
+}
+
+tdt_status_t tdt_plan_profile(tdt_plan_t p, int enable) {
+  if (!p) return TDT_ERR_INVALID_ARG;
+  if (!enable) {
+    (void)hipDeviceSynchronize();
+    clear_profile(p);
+  }
+  p->profile = enable != 0;
+  return TDT_OK;
+}
+
+tdt_status_t tdt_plan_profile_read(tdt_plan_t p, double* ms3, int64_t* nsolves) {
+  if (!p || !ms3) return TDT_ERR_INVALID_ARG;
+  if (hipDeviceSynchronize() != hipSuccess) return TDT_ERR_HIP;
+  ms3[0] = ms3[1] = ms3[2] = 0.0;
+  const size_t ns = p->prof_ev.size() / 4;
+  for (size_t k = 0; k < ns; ++k) {
+    for (int j = 0; j < 3; ++j) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, p->prof_ev[4 * k + j], p->prof_ev[4 * k + j + 1]) !=
+          hipSuccess)
+        return TDT_ERR_HIP;
+      ms3[j] += (double)ms;
+    }
+  }
+  if (nsolves) *nsolves = (int64_t)ns;
+  clear_profile(p);
   return TDT_OK;
 }
 

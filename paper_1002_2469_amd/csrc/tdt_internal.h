@@ -32,6 +32,11 @@ struct SysDesc {
                          // else (phi_first of its real length, 0, 0, 0)
 };
 
+// Per-system table over the kNT block positions of a tile: beta_{m-1} (the
+// coefficient that carries the next block's first unknown into block m-1's
+// last one, from the left-to-right elimination) and 1/(1 - phi_first beta_{m-1}).
+enum { kTabBeta = 0, kTabInvD = 1, kTabN = 2 };
+
 // Per-system block vectors, kB each, in this order.
 enum { kVecIU = 0, kVecCP = 1, kVecPHI = 2, kVecCHI = 3, kVecN = 4 };
 
@@ -40,6 +45,8 @@ struct LaunchSet {
   const SysDesc* sys;
   const double* vec64;
   const float* vec32;
+  const double* tab64;     // per-position table [ncidx][2][kNT]
+  const float* tab32;
   const int2* p1_items;    // varlen: (system, tile) of the first pass; null for a series
   const int2* fin_items;   // varlen: (system, tile) of the final pass
   const int* grid_items;   // varlen: systems with more than one tile
@@ -51,6 +58,8 @@ struct LaunchSet {
   int* iters;
   int max_iter;
   double refine_tol;
+  hipEvent_t* ev;          // measurement: 4 events (before pass 1, after pass 1,
+                           // after the interface pass, after the final pass) or null
 };
 
 // dtype: 0 double, 1 float, 2 float sweeps with double refinement.

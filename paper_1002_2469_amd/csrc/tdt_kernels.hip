@@ -44,6 +44,52 @@ struct Seg {
   T yf, yl, pf, pl, cf, cl;
 };
 
+// Read-only per-plan data (block vectors, system descriptors, work lists) is
+// read through the constant address space: with a wave-uniform address the
+// compiler then uses scalar loads into SGPRs, which the sweeps take as
+// operands, instead of vector loads into VGPRs.
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T*;
+template <typename T>
+__device__ __forceinline__ cptr<T> as_const(const T* p) {
+  return (cptr<T>)(uintptr_t)p;
+}
+
+// Hides a value from the optimiser (an empty asm that "modifies" a register)
+// so that per-element offsets derived from it are recomputed next to each
+// access instead of being hoisted out of the tile loop and kept live.
+__device__ __forceinline__ int opaque(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
+// Raw buffer accesses: a wave-uniform resource (base, size in bytes) held in
+// SGPRs plus one per-lane byte offset.  The hardware range check returns 0
+// for reads at or past `bytes` (and for "negative" offsets, which wrap to
+// huge unsigned ones) and drops such writes, which is how partial tiles and
+// the rows just outside a system are handled.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                           0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, int off) {
+  if constexpr (sizeof(T) == 8)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <typename T>
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, int off, T v) {
+  if constexpr (sizeof(T) == 8) {
+    using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, off, 0, 0);
+  } else {
+    using V = decltype(__builtin_amdgcn_raw_buffer_load_b32(r, 0, 0, 0));
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(V, v), r, off, 0, 0);
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ Seg<T> seg_zero() {
   return Seg<T>{T(0), T(0), T(0), T(0), T(0), T(0)};
@@ -158,24 +204,47 @@ __device__ __forceinline__ void lane_ghosts(const Seg<T>& pre, const Seg<T>& suf
 // Per-system constants in compute precision.
 template <typename Tc>
 struct Consts {
-  const Tc* __restrict__ iu;
-  const Tc* __restrict__ cp;
-  const Tc* __restrict__ phi;
-  const Tc* __restrict__ chi;
+  cptr<Tc> iu;
+  cptr<Tc> cp;
+  cptr<Tc> phi;
+  cptr<Tc> chi;
   Tc a;
-  Tc bpf, bpl, bcf, bcl;
-  Tc tail_pf;
+  Tc pf, pl, cf;          // phi_first, phi_last, chi_first of a full block
+  Tc tail_pf;             // phi_first of the system's last block
 };
 
 // Solve the tile's local problem for this lane's block q (in: right-hand
-// side, out: solution) given the values just outside the tile.  len: real
-// rows of the lane's block (kB full, 1..kB-1 last block, 0 past the end).
-// If tile_seg is non-null the tile summary is returned there and the
-// correction is skipped.  One workgroup barrier inside.
+// side, out: solution) given the values XLt, XRt just outside the tile.
+// len: real rows of the lane's block (kB full, 1..kB-1 last block of the
+// system, 0 past its end).  bp, iDf: this lane's entries of the per-position
+// table (beta_{m-1} and 1/(1 - phi_first beta_{m-1}) for a full block m).
+//
+// Interface pass.  With u_m, v_m the first and last unknown of block m and
+// y its local solution, (*) at those two rows reads
+//     u_m = y_f + phi_f v_{m-1} + chi_f u_{m+1},
+//     v_m = y_l + phi_l v_{m-1} + chi_l u_{m+1}.
+// Eliminating left to right gives v_m = alpha_m + beta_m u_{m+1} with
+//     alpha_m = A_m alpha_{m-1} + g_m,  A_m = phi_l iD_m,
+//     g_m = y_l + A_m beta_{m-1} y_f,   iD_m = 1/(1 - phi_f beta_{m-1}),
+// where beta_m = chi_l + phi_l chi_f beta_{m-1} iD_m depends on T only (the
+// table), and then right to left
+//     u_m = C_m u_{m+1} + h_m,  C_m = chi_f iD_m,  h_m = (y_f + phi_f alpha_{m-1}) iD_m.
+// alpha_m is a sum over blocks j <= m of each block's own contribution g_j
+// carried by products of A's, u_m a sum over blocks j >= m of the h_j
+// carried by products of C's: the two sums of eq. (11) (contributions from
+// the left and from the right, weighted by the exterior responses Z of
+// eq. (7)), evaluated as affine scans.  Associativity (Sec. 2.5) lets the
+// scans run as Kogge-Stone steps inside a wavefront and as one LDS level
+// across wavefronts instead of the recursive halving of Sec. 2.4.
+// If yfo/ylo are non-null the tile summary (first and last unknown of the
+// tile with zero outside values) is written by the owning threads and the
+// correction is skipped.  Two workgroup barriers inside.
 template <typename Tc>
 __device__ __forceinline__ void tile_solve(Tc (&q)[kB], int len, Tc XLt, Tc XRt,
-                                           const Consts<Tc>& K, Tc (*wsum)[6],
-                                           Seg<Tc>* tile_seg) {
+                                           const Consts<Tc>& K, Tc bp, Tc iDf,
+                                           Tc (*fw)[2], Tc (*bw)[2], double* yfo,
+                                           double* ylo) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const bool tail = len > 0 && len < kB;
   const bool wave_tail = __ballot(tail) != 0;
   // local Thomas sweep with the shared multipliers (T_B^{-1} q)
@@ -193,22 +262,66 @@ __device__ __forceinline__ void tile_solve(Tc (&q)[kB], int len, Tc XLt, Tc XRt,
 #pragma unroll
   for (int i = kB - 2; i >= 0; --i) q[i] -= K.cp[i] * q[i + 1];
 
-  Seg<Tc> own = seg_zero<Tc>();
-  if (len == kB) {
-    own = Seg<Tc>{q[0], q[kB - 1], K.bpf, K.bpl, K.bcf, K.bcl};
-  } else if (len > 0) {
-    own = Seg<Tc>{q[0], Tc(0), K.tail_pf, Tc(0), Tc(0), Tc(0)};
+  // this block's coefficients
+  Tc pf = K.pf, pl = K.pl, cf = K.cf, iD = iDf, yf = q[0], yl = q[kB - 1];
+  if (len < kB) {
+    pl = Tc(0);
+    cf = Tc(0);
+    yl = Tc(0);
+    if (len > 0) {
+      pf = K.tail_pf;
+      iD = Tc(1) / (Tc(1) - pf * bp);
+    } else {
+      pf = Tc(0);
+      iD = Tc(1);
+      yf = Tc(0);
+    }
   }
-  Seg<Tc> pre, suf;
-  wave_scan(own, pre, suf);
-  Tc XLw, XRw;
-  const Seg<Tc> ts = wg_level(pre, wsum, XLt, XRt, XLw, XRw);
-  if (tile_seg) {
-    *tile_seg = ts;
+  // left-to-right sums
+  Tc A = pl * iD;
+  Tc g = yl + A * bp * yf;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const Tc Alo = __shfl_up(A, d, 64);
+    const Tc glo = __shfl_up(g, d, 64);
+    if (lane >= d) {
+      g = A * glo + g;
+      A = A * Alo;
+    }
+  }
+  if (lane == 63) { fw[w][0] = A; fw[w][1] = g; }
+  __syncthreads();
+  Tc cin = XLt;
+  for (int k = 0; k < w; ++k) cin = fw[k][0] * cin + fw[k][1];
+  const Tc alpha = A * cin + g;
+  Tc alpha_prev = __shfl_up(alpha, 1, 64);
+  if (lane == 0) alpha_prev = cin;
+  // right-to-left sums
+  Tc C = cf * iD;
+  Tc h = (yf + pf * alpha_prev) * iD;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const Tc Chi = __shfl_down(C, d, 64);
+    const Tc hhi = __shfl_down(h, d, 64);
+    if (lane + d < 64) {
+      h = C * hhi + h;
+      C = C * Chi;
+    }
+  }
+  if (lane == 0) { bw[w][0] = C; bw[w][1] = h; }
+  __syncthreads();
+  Tc ein = XRt;
+  for (int k = kNW - 1; k > w; --k) ein = bw[k][0] * ein + bw[k][1];
+  const Tc u = C * ein + h;
+  if (yfo) {
+    if (threadIdx.x == 0) *yfo = (double)u;
+    if (threadIdx.x == kNT - 1) *ylo = (double)alpha;
     return;
   }
-  Tc xl, xr;
-  lane_ghosts(pre, suf, XLw, XRw, xl, xr);
+  Tc u_next = __shfl_down(u, 1, 64);
+  if (lane == 63) u_next = ein;
+  const Tc xl = alpha_prev + bp * u;   // last unknown of the previous block
+  const Tc xr = u_next;                // first unknown of the next block
   if (len == kB) {
 #pragma unroll
     for (int i = 0; i < kB; ++i) q[i] += xl * K.phi[i] + xr * K.chi[i];
@@ -239,7 +352,11 @@ struct TileArgs {
   const SysDesc* __restrict__ sys;
   const double* __restrict__ vec64;   // [ncidx][kVecN][kB]
   const float* __restrict__ vec32;
-  const int2* __restrict__ items;     // varlen: (system, tile) per workgroup; null for a series
+  const double* __restrict__ tab64;   // [ncidx][2][kNT] per-position table
+  const float* __restrict__ tab32;
+  const int2* __restrict__ items;     // varlen: (system, tile) per item; null for a series
+  int64_t nitems;
+  int reverse;                        // process items last to first
   double* __restrict__ summ;          // [slot][2] tile summaries (y_first, y_last)
   const double* __restrict__ ghost;   // [slot][2] values just outside each tile
   const Tio* __restrict__ Xfwd;       // adjoint: forward solution
@@ -248,6 +365,16 @@ struct TileArgs {
   int max_iter;
   double refine_tol;
 };
+
+// Copy of a system descriptor read with scalar loads (wave-uniform index).
+__device__ __forceinline__ SysDesc load_sys(const SysDesc* sys, int s) {
+  SysDesc D;
+  const cptr<uint64_t> src = as_const(reinterpret_cast<const uint64_t*>(sys + s));
+  uint64_t* dst = reinterpret_cast<uint64_t*>(&D);
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(SysDesc) / 8); ++k) dst[k] = src[k];
+  return D;
+}
 
 struct ItemInfo {
   int s, t;
@@ -258,17 +385,17 @@ __device__ __forceinline__ ItemInfo decode_item(const int2* items, const SysDesc
                                                 int64_t it) {
   ItemInfo r;
   if (items) {
-    const int2 v = items[it];
-    r.s = v.x; r.t = v.y; r.m = 0;
+    const cptr<int> iv = as_const(reinterpret_cast<const int*>(items)) + 2 * it;
+    r.s = iv[0]; r.t = iv[1]; r.m = 0;
   } else {
-    const int nt = sys[0].ntiles;
+    const int nt = *as_const(&sys[0].ntiles);
     r.s = 0; r.m = it / nt; r.t = (int)(it - r.m * nt);
   }
   return r;
 }
 
 template <typename Tc>
-__device__ __forceinline__ Consts<Tc> load_consts(const SysDesc& S, const double* vec64,
+__device__ __forceinline__ Consts<Tc> make_consts(const SysDesc& S, const double* vec64,
                                                   const float* vec32) {
   Consts<Tc> K;
   const Tc* v;
@@ -276,12 +403,13 @@ __device__ __forceinline__ Consts<Tc> load_consts(const SysDesc& S, const double
     v = reinterpret_cast<const Tc*>(vec64) + (int64_t)S.cidx * kVecN * kB;
   else
     v = reinterpret_cast<const Tc*>(vec32) + (int64_t)S.cidx * kVecN * kB;
-  K.iu = v + kVecIU * kB;
-  K.cp = v + kVecCP * kB;
-  K.phi = v + kVecPHI * kB;
-  K.chi = v + kVecCHI * kB;
+  const cptr<Tc> c = as_const(v);
+  K.iu = c + kVecIU * kB;
+  K.cp = c + kVecCP * kB;
+  K.phi = c + kVecPHI * kB;
+  K.chi = c + kVecCHI * kB;
   K.a = (Tc)S.a;
-  K.bpf = (Tc)S.blk[0]; K.bpl = (Tc)S.blk[1]; K.bcf = (Tc)S.blk[2]; K.bcl = (Tc)S.blk[3];
+  K.pf = (Tc)S.blk[0]; K.pl = (Tc)S.blk[1]; K.cf = (Tc)S.blk[2];
   K.tail_pf = (Tc)S.tail_pf;
   return K;
 }
@@ -302,7 +430,69 @@ __device__ __forceinline__ void wg_max2(double& u, double& v, double (*red)[4]) 
   for (int k = 1; k < kNW; ++k) { u = fmax(u, red[k][0]); v = fmax(v, red[k][1]); }
 }
 
-// One workgroup per tile.
+struct TileGeom {
+  ItemInfo I;
+  int64_t base;   // element offset of the tile's first row
+  int64_t t0;     // row of the tile's first element within its system
+  int tl;         // rows in the tile
+};
+
+__device__ __forceinline__ TileGeom tile_geom(const int2* items, const SysDesc* sys,
+                                              int64_t it) {
+  TileGeom G;
+  G.I = decode_item(items, sys, it);
+  const SysDesc S = load_sys(sys, G.I.s);
+  G.t0 = (int64_t)G.I.t * kTile;
+  G.base = S.off + G.I.m * S.n + G.t0;
+  G.tl = (int)(S.n - G.t0 < kTile ? S.n - G.t0 : kTile);
+  return G;
+}
+
+// Everything a workgroup needs from global memory for one tile, fetched one
+// tile ahead: the tile's rows (coalesced, element j*kNT + tid), this lane's
+// table entries, one block-vector entry per thread (tid < kVecN*kB), and the
+// values just outside the tile.  Every load is unconditional (rows past the
+// tile read as 0 through the buffer range check) so that all of them are in
+// flight together and nothing waits for them before the next tile starts.
+template <typename Tio, typename Tc>
+struct Prefetch {
+  Tio v[kB];
+  Tc bp, iD;
+  double XL, XR;
+};
+
+template <typename Tio, typename Tc, bool SUMMARY>
+__device__ __forceinline__ void prefetch(const TileArgs<Tio>& A, int64_t item,
+                                         Prefetch<Tio, Tc>& P) {
+  const int tid = threadIdx.x;
+  const TileGeom G = tile_geom(A.items, A.sys, item);
+  const SysDesc S = load_sys(A.sys, G.I.s);
+  const __amdgpu_buffer_rsrc_t src = make_rsrc(A.F + G.base, (int64_t)G.tl * sizeof(Tio));
+  const int vb = opaque(tid * (int)sizeof(Tio));
+#pragma unroll
+  for (int j = 0; j < kB; ++j) P.v[j] = buf_load<Tio>(src, vb + j * kNT * (int)sizeof(Tio));
+  if constexpr (sizeof(Tc) == 8) {
+    const double* tb = A.tab64 + (int64_t)S.cidx * kTabN * kNT;
+    P.bp = tb[kTabBeta * kNT + tid];
+    P.iD = tb[kTabInvD * kNT + tid];
+  } else {
+    const float* tb = A.tab32 + (int64_t)S.cidx * kTabN * kNT;
+    P.bp = tb[kTabBeta * kNT + tid];
+    P.iD = tb[kTabInvD * kNT + tid];
+  }
+  if (!SUMMARY) {
+    const int64_t slot = A.items ? (int64_t)S.slot0 + G.I.t : G.I.m * S.ntiles + G.I.t;
+    const int64_t gs = S.ntiles > 1 ? slot : 0;   // the ghost array always has slot 0
+    const double xl = A.ghost[2 * gs], xr = A.ghost[2 * gs + 1];
+    P.XL = S.ntiles > 1 ? xl : 0.0;
+    P.XR = S.ntiles > 1 ? xr : 0.0;
+  } else {
+    P.XL = P.XR = 0.0;
+  }
+}
+
+// Persistent workgroups over tiles; each workgroup prefetches its next tile
+// into registers while it solves the current one.
 //   SUMMARY = true : first pass over a tile of a multi-tile system: writes the
 //                    tile's (y_first, y_last) of its zero-boundary problem.
 //   SUMMARY = false: solves the tile given the values just outside it (zero
@@ -312,156 +502,164 @@ __device__ __forceinline__ void wg_max2(double& u, double& v, double (*red)[4]) 
 //   BWD            : also accumulates the t-gradient partial sums against the
 //                    forward solution Xfwd (the tile solves T^T gF = gX).
 template <typename Tio, typename Tc, bool REFINE, bool SUMMARY, bool BWD>
-__global__ __launch_bounds__(kNT) void k_tile(TileArgs<Tio> A) {
+__global__ __launch_bounds__(kNT, 2) void k_tile(TileArgs<Tio> A) {
   constexpr int RP = kB + 16 / (int)sizeof(Tio);   // padded LDS row pitch
   __shared__ __align__(16) Tio lds[kNT * RP];
-  __shared__ Tc wsum[kNW][6];
+  __shared__ Tc fw[kNW][2], bw[kNW][2];
   __shared__ double red[kNW][4];
+  __shared__ double edge[kNW][2];
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const ItemInfo I = decode_item(A.items, A.sys, blockIdx.x);
-  const SysDesc& S = A.sys[I.s];
-  const int64_t n = S.n;
-  const int64_t t0 = (int64_t)I.t * kTile;
-  const int64_t base = S.off + I.m * n + t0;
-  const int tl = (int)(n - t0 < kTile ? n - t0 : kTile);
-  const int64_t slot = A.items ? (int64_t)S.slot0 + I.t : I.m * S.ntiles + I.t;
-  double XLt = 0.0, XRt = 0.0;
-  if (!SUMMARY && S.ntiles > 1) {
-    XLt = A.ghost[2 * slot];
-    XRt = A.ghost[2 * slot + 1];
-  }
+  // element j*kNT + tid of a tile lives in row j*(kNT/kB) + tid/kB, column tid%kB
+  const int lbase = (tid / kB) * RP + (tid % kB);
+  constexpr int lstride = (kNT / kB) * RP;
+  auto item_of = [&](int64_t k) { return A.reverse ? A.nitems - 1 - k : k; };
+  int64_t k = blockIdx.x;
+  Prefetch<Tio, Tc> P;
+  if (k < A.nitems) prefetch<Tio, Tc, SUMMARY>(A, item_of(k), P);
 
-  // coalesced load, transposed through LDS into one row of kB per lane
-#pragma unroll 8
-  for (int j = 0; j < kB; ++j) {
-    const int e = j * kNT + tid;
-    const Tio v = e < tl ? A.F[base + e] : Tio(0);
-    lds[(e / kB) * RP + (e % kB)] = v;
-  }
-  __syncthreads();
+  while (k < A.nitems) {
+    const int64_t item = item_of(k);
+    const TileGeom G = tile_geom(A.items, A.sys, item);
+    const SysDesc S = load_sys(A.sys, G.I.s);
+    const int64_t slot = A.items ? (int64_t)S.slot0 + G.I.t : G.I.m * S.ntiles + G.I.t;
+    const double XLt = P.XL, XRt = P.XR;
+    const Tc bp = P.bp, iDf = P.iD;
+    const Consts<Tc> K = make_consts<Tc>(S, A.vec64, A.vec32);
+    const int tl = G.tl;
+    const int len = tl - tid * kB >= kB ? kB : (tl - tid * kB > 0 ? tl - tid * kB : 0);
 
-  const Consts<Tc> K = load_consts<Tc>(S, A.vec64, A.vec32);
-  const int len = tl - tid * kB >= kB ? kB : (tl - tid * kB > 0 ? tl - tid * kB : 0);
-  Tio* myrow = lds + tid * RP;
-
-  if constexpr (!REFINE) {
-    Tc q[kB];
+    __syncthreads();   // the previous tile is done with LDS
+    {
+      Tio* lw = lds + opaque(lbase);
 #pragma unroll
-    for (int i = 0; i < kB; ++i) q[i] = (Tc)myrow[i];
-    if constexpr (SUMMARY) {
-      Seg<Tc> ts;
-      tile_solve(q, len, Tc(0), Tc(0), K, wsum, &ts);
-      if (tid == 0) {
-        A.summ[2 * slot] = (double)ts.yf;
-        A.summ[2 * slot + 1] = (double)ts.yl;
-      }
-      return;
-    } else {
-      tile_solve(q, len, (Tc)XLt, (Tc)XRt, K, wsum, (Seg<Tc>*)nullptr);
-#pragma unroll
-      for (int i = 0; i < kB; ++i) myrow[i] = (Tio)q[i];
+      for (int j = 0; j < kB; ++j) lw[j * lstride] = P.v[j];
     }
-  } else {
-    // iterative refinement: x = 0; repeat r = f - T x (double, with the
-    // tile's outside values), d = solve_float(r) with zero outside values,
-    // x += d (double)
-    __shared__ double edge[kNW][2];
-    const double a = S.a, b = S.b, c = S.c;
-    double x[kB];
-#pragma unroll
-    for (int i = 0; i < kB; ++i) x[i] = 0.0;
-    double dprev = 0.0;
-    int it = 0;
-    for (;;) {
-      // neighbours of this lane's block
-      if (lane == 0) edge[w][0] = x[0];
-      if (lane == 63) edge[w][1] = x[kB - 1];
-      __syncthreads();
-      double xm = __shfl_up(x[kB - 1], 1, 64);
-      double xp = __shfl_down(x[0], 1, 64);
-      if (lane == 0) xm = w == 0 ? XLt : edge[w - 1][1];
-      if (lane == 63) xp = w == kNW - 1 ? XRt : edge[w + 1][0];
+    const int64_t kn = k + gridDim.x;
+    if (kn < A.nitems) prefetch<Tio, Tc, SUMMARY>(A, item_of(kn), P);
+    __syncthreads();
+    Tio* myrow = lds + tid * RP;
+
+    if constexpr (!REFINE) {
       Tc q[kB];
 #pragma unroll
-      for (int i = 0; i < kB; ++i) {
-        const double left = i == 0 ? xm : x[i - 1];
-        const double right = i + 1 < kB ? x[i + 1] : xp;
-        const double r = (double)myrow[i] - (b * x[i] + a * left + c * right);
-        q[i] = i < len ? (Tc)r : Tc(0);
-      }
-      tile_solve(q, len, Tc(0), Tc(0), K, wsum, (Seg<Tc>*)nullptr);
-      double dmax = 0.0, xmax = 0.0;
+      for (int i = 0; i < kB; ++i) q[i] = (Tc)myrow[i];
+      if constexpr (SUMMARY) {
+        tile_solve(q, len, Tc(0), Tc(0), K, bp, iDf, fw, bw, A.summ + 2 * slot,
+                   A.summ + 2 * slot + 1);
+      } else {
+        tile_solve(q, len, (Tc)XLt, (Tc)XRt, K, bp, iDf, fw, bw, (double*)nullptr,
+                   (double*)nullptr);
 #pragma unroll
-      for (int i = 0; i < kB; ++i) {
-        x[i] += (double)q[i];
-        dmax = fmax(dmax, fabs((double)q[i]));
-        xmax = fmax(xmax, fabs(x[i]));
+        for (int i = 0; i < kB; ++i) myrow[i] = (Tio)q[i];
       }
-      wg_max2(dmax, xmax, red);
-      ++it;
-      // stop when the next update is predicted below tol (contraction
-      // estimate dmax/dprev), when updates stop shrinking, or at the cap
-      bool stop = it >= A.max_iter || dmax == 0.0;
-      if (it >= 2) {
-        const double rho = dmax / dprev;
-        stop = stop || dmax * rho <= A.refine_tol * xmax || rho > 0.9;
-      }
-      dprev = dmax;
-      if (stop) break;
-    }
-    if (tid == 0 && A.iters) atomicMax(A.iters, it);
-    if constexpr (SUMMARY) {
-      if (tid == 0) A.summ[2 * slot] = x[0];
-      __syncthreads();
-      if (tid == kNT - 1) A.summ[2 * slot + 1] = tl == kTile ? x[kB - 1] : 0.0;
-      return;
     } else {
-      __syncthreads();   // every lane is done reading f from LDS
+      // iterative refinement: x = 0; repeat r = f - T x (double, with the
+      // tile's outside values), d = solve_float(r) with zero outside values,
+      // x += d (double)
+      const double a = S.a, b = S.b, c = S.c;
+      double x[kB];
 #pragma unroll
-      for (int i = 0; i < kB; ++i) myrow[i] = (Tio)x[i];
+      for (int i = 0; i < kB; ++i) x[i] = 0.0;
+      double dprev = 0.0;
+      int it = 0;
+      for (;;) {
+        if (lane == 0) edge[w][0] = x[0];
+        if (lane == 63) edge[w][1] = x[kB - 1];
+        __syncthreads();
+        double xm = __shfl_up(x[kB - 1], 1, 64);
+        double xp = __shfl_down(x[0], 1, 64);
+        if (lane == 0) xm = w == 0 ? XLt : edge[w > 0 ? w - 1 : 0][1];
+        if (lane == 63) xp = w == kNW - 1 ? XRt : edge[w + 1 < kNW ? w + 1 : kNW - 1][0];
+        Tc q[kB];
+#pragma unroll
+        for (int i = 0; i < kB; ++i) {
+          const double left = i == 0 ? xm : x[i - 1];
+          const double right = i + 1 < kB ? x[i + 1] : xp;
+          const double r = (double)myrow[i] - (b * x[i] + a * left + c * right);
+          q[i] = i < len ? (Tc)r : Tc(0);
+        }
+        tile_solve(q, len, Tc(0), Tc(0), K, bp, iDf, fw, bw, (double*)nullptr,
+                   (double*)nullptr);
+        double dmax = 0.0, xmax = 0.0;
+#pragma unroll
+        for (int i = 0; i < kB; ++i) {
+          x[i] += (double)q[i];
+          dmax = fmax(dmax, fabs((double)q[i]));
+          xmax = fmax(xmax, fabs(x[i]));
+        }
+        wg_max2(dmax, xmax, red);
+        ++it;
+        // stop when the next update is predicted below tol (contraction
+        // estimate dmax/dprev), when updates stop shrinking, or at the cap
+        bool stop = it >= A.max_iter || dmax == 0.0;
+        if (it >= 2) {
+          const double rho = dmax / dprev;
+          stop = stop || dmax * rho <= A.refine_tol * xmax || rho > 0.9;
+        }
+        dprev = dmax;
+        if (stop) break;
+      }
+      if (tid == 0 && A.iters) atomicMax(A.iters, it);
+      if constexpr (SUMMARY) {
+        if (tid == 0) A.summ[2 * slot] = x[0];
+        if (tid == kNT - 1) A.summ[2 * slot + 1] = tl == kTile ? x[kB - 1] : 0.0;
+      } else {
+        __syncthreads();   // every lane is done reading f from LDS
+#pragma unroll
+        for (int i = 0; i < kB; ++i) myrow[i] = (Tio)x[i];
+      }
     }
-  }
 
-  if constexpr (!SUMMARY) {
-    __syncthreads();
-    double s0 = 0.0, s1 = 0.0, sm1 = 0.0;
-#pragma unroll 8
-    for (int j = 0; j < kB; ++j) {
-      const int e = j * kNT + tid;
-      if (e < tl) {
-        const Tio g = lds[(e / kB) * RP + (e % kB)];
-        A.X[base + e] = g;
+    if constexpr (!SUMMARY) {
+      __syncthreads();
+      double s0 = 0.0, s1 = 0.0, sm1 = 0.0;
+      const __amdgpu_buffer_rsrc_t dst = make_rsrc(A.X + G.base, (int64_t)tl * sizeof(Tio));
+      // adjoint: the forward solution over this tile and one row on each side
+      // that lies inside the system (rows outside read as 0)
+      const int lo = G.t0 > 0 ? 1 : 0, hi = G.t0 + tl < S.n ? 1 : 0;
+      const __amdgpu_buffer_rsrc_t xf =
+          make_rsrc(BWD ? A.Xfwd + G.base - lo : A.X + G.base,
+                    BWD ? (int64_t)(lo + tl + hi) * sizeof(Tio) : 0);
+      const Tio* lr = lds + opaque(lbase);
+      const int vs = opaque(tid * (int)sizeof(Tio));
+#pragma unroll
+      for (int j = 0; j < kB; ++j) {
+        const int e = j * kNT + tid;
+        const Tio gval = lr[j * lstride];
+        buf_store<Tio>(dst, vs + j * kNT * (int)sizeof(Tio), gval);
         if constexpr (BWD) {
-          const int64_t gi = t0 + e;   // row in the system
-          const double xe = (double)A.Xfwd[base + e];
-          const double xn = gi + 1 < n ? (double)A.Xfwd[base + e + 1] : 0.0;
-          const double xq = gi > 0 ? (double)A.Xfwd[base + e - 1] : 0.0;
-          s0 += (double)g * xe;
-          s1 += (double)g * xn;
-          sm1 += (double)g * xq;
+          const int xo = vs + (j * kNT + lo) * (int)sizeof(Tio);
+          const double xe = (double)buf_load<Tio>(xf, xo);
+          const double xn = (double)buf_load<Tio>(xf, xo + (int)sizeof(Tio));
+          const double xq = (double)buf_load<Tio>(xf, xo - (int)sizeof(Tio));
+          const double gv = e < tl ? (double)gval : 0.0;
+          s0 += gv * xe;
+          s1 += gv * xn;
+          sm1 += gv * xq;
+        }
+      }
+      if constexpr (BWD) {
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+          s0 += __shfl_xor(s0, d, 64);
+          s1 += __shfl_xor(s1, d, 64);
+          sm1 += __shfl_xor(sm1, d, 64);
+        }
+        __syncthreads();
+        if (lane == 0) { red[w][0] = sm1; red[w][1] = s0; red[w][2] = s1; }
+        __syncthreads();
+        if (tid == 0) {
+          double u = 0.0, v = 0.0, z = 0.0;
+          for (int q = 0; q < kNW; ++q) { u += red[q][0]; v += red[q][1]; z += red[q][2]; }
+          const int64_t fs = A.items ? (int64_t)S.fslot0 + G.I.t : G.I.m * S.ntiles + G.I.t;
+          A.gpart[3 * fs + 0] = -u;
+          A.gpart[3 * fs + 1] = -v;
+          A.gpart[3 * fs + 2] = -z;
         }
       }
     }
-    if constexpr (BWD) {
-#pragma unroll
-      for (int d = 32; d >= 1; d >>= 1) {
-        s0 += __shfl_xor(s0, d, 64);
-        s1 += __shfl_xor(s1, d, 64);
-        sm1 += __shfl_xor(sm1, d, 64);
-      }
-      __syncthreads();
-      if (lane == 0) { red[w][0] = sm1; red[w][1] = s0; red[w][2] = s1; }
-      __syncthreads();
-      if (tid == 0) {
-        double u = 0.0, v = 0.0, z = 0.0;
-        for (int k = 0; k < kNW; ++k) { u += red[k][0]; v += red[k][1]; z += red[k][2]; }
-        const int64_t fs = A.items ? (int64_t)S.fslot0 + I.t : I.m * S.ntiles + I.t;
-        A.gpart[3 * fs + 0] = -u;
-        A.gpart[3 * fs + 1] = -v;
-        A.gpart[3 * fs + 2] = -z;
-      }
-    }
+    k = kn;
   }
 }
 
@@ -579,6 +777,38 @@ __global__ __launch_bounds__(kNT) void k_gt_reduce(const double* __restrict__ gp
 namespace tdt {
 
 
+// Resident workgroups per CU of a kernel (queried once per variant).
+template <typename KernelT>
+static int resident_per_cu(KernelT kern) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, kNT, 0) != hipSuccess || nb < 1)
+    nb = 1;
+  return nb;
+}
+
+static int num_cus() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus < 1)
+      cus = 1;
+  }
+  return cus;
+}
+
+template <typename Tio, typename Tc, bool REFINE, bool SUMMARY, bool BWD>
+static void launch_tile(TileArgs<Tio>& A, int64_t nitems, int reverse, hipStream_t st) {
+  auto kern = k_tile<Tio, Tc, REFINE, SUMMARY, BWD>;
+  static int per_cu = resident_per_cu(kern);
+  const int64_t cap = (int64_t)per_cu * num_cus();
+  A.nitems = nitems;
+  A.reverse = reverse;
+  const unsigned grid = (unsigned)(nitems < cap ? nitems : cap);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kNT), 0, st, A);
+}
+
 template <typename Tio, typename Tc, bool REFINE, bool BWD>
 static hipError_t run_solve(const LaunchSet& L, const void* F, void* X, const void* Xfwd,
                             hipStream_t st) {
@@ -588,6 +818,8 @@ static hipError_t run_solve(const LaunchSet& L, const void* F, void* X, const vo
   A.sys = L.sys;
   A.vec64 = L.vec64;
   A.vec32 = L.vec32;
+  A.tab64 = L.tab64;
+  A.tab32 = L.tab32;
   A.summ = L.summ;
   A.ghost = L.ghost;
   A.Xfwd = static_cast<const Tio*>(Xfwd);
@@ -595,16 +827,24 @@ static hipError_t run_solve(const LaunchSet& L, const void* F, void* X, const vo
   A.iters = L.iters;
   A.max_iter = L.max_iter;
   A.refine_tol = L.refine_tol;
+  if (L.ev) (void)hipEventRecord(L.ev[0], st);
   if (L.n_p1 > 0) {
     A.items = L.p1_items;
-    hipLaunchKernelGGL((k_tile<Tio, Tc, REFINE, true, false>), dim3((unsigned)L.n_p1),
-                       dim3(kNT), 0, st, A);
+    launch_tile<Tio, Tc, REFINE, true, false>(A, L.n_p1, 0, st);
+    if (L.ev) (void)hipEventRecord(L.ev[1], st);
     GridArgs G{L.sys, L.grid_items, L.summ, L.ghost, L.gscr};
     hipLaunchKernelGGL(k_grid, dim3((unsigned)L.n_grid), dim3(kNT), 0, st, G);
+    if (L.ev) (void)hipEventRecord(L.ev[2], st);
+  } else if (L.ev) {
+    (void)hipEventRecord(L.ev[1], st);
+    (void)hipEventRecord(L.ev[2], st);
   }
   A.items = L.fin_items;
-  hipLaunchKernelGGL((k_tile<Tio, Tc, REFINE, false, BWD>), dim3((unsigned)L.n_fin), dim3(kNT),
-                     0, st, A);
+  // a series of multi-tile systems runs its final pass last-tile-first, so
+  // that the tiles the first pass read last are re-read while still cached
+  launch_tile<Tio, Tc, REFINE, false, BWD>(A, L.n_fin, (L.n_p1 > 0 && !L.fin_items) ? 1 : 0,
+                                           st);
+  if (L.ev) (void)hipEventRecord(L.ev[3], st);
   return hipGetLastError();
 }
 
