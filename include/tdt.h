@@ -141,6 +141,14 @@ tdt_status_t tdt_last_info(tdt_plan_t plan, int *n_refine_iters,
 tdt_status_t tdt_block_constants(double t_m1, double t_0, double t_1, int B,
                                  double *out);
 
+/* Host-only: the first and last row of T_L^{-1}, the L x L Toeplitz matrix
+ * (the Green's function rows of eq. (6) of the paper for a run of L rows
+ * taken as the whole system), in long double rounded to double: first[j] =
+ * (T_L^{-1})_{0,j}, last[j] = (T_L^{-1})_{L-1,j}, j < L.  The first pass of a
+ * series plan uses them for its tiles (L = the tile length). */
+tdt_status_t tdt_green_rows(double t_m1, double t_0, double t_1, int64_t L,
+                            double *first, double *last);
+
 /* Host-only: the interface merge of two adjacent segments, in double, as the
  * kernels compute it.  seg = (y_first, y_last, phi_first, phi_last,
  * chi_first, chi_last) of the left (l) and right (r) segment; out = the

@@ -23,7 +23,7 @@ from . import _lib
 from ._lib import DTYPES, TDTError, build
 
 __all__ = ["Plan", "VarlenPlan", "solve", "TridiagToeplitzSolve", "block_constants",
-           "segment_merge", "build_info", "build", "TDTError"]
+           "green_rows", "segment_merge", "build_info", "build", "TDTError"]
 
 
 def _torch():
@@ -266,6 +266,16 @@ def block_constants(t_m1: float, t_0: float, t_1: float, B: int) -> dict:
                "tdt_block_constants")
     return dict(inv_pivot=out[:B], cp=out[B:2 * B], phi=out[2 * B:3 * B],
                 chi=out[3 * B:4 * B], ends=out[4 * B:])
+
+
+def green_rows(t_m1: float, t_0: float, t_1: float, L: int):
+    """Host-only: first and last row of the inverse of the L x L Toeplitz matrix."""
+    first, last = np.empty(int(L)), np.empty(int(L))
+    _lib.check(_lib.lib().tdt_green_rows(float(t_m1), float(t_0), float(t_1), int(L),
+                                         first.ctypes.data_as(ctypes.c_void_p),
+                                         last.ctypes.data_as(ctypes.c_void_p)),
+               "tdt_green_rows")
+    return first, last
 
 
 def segment_merge(left, right) -> np.ndarray:

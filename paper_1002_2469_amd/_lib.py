@@ -14,6 +14,10 @@ import subprocess
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _ROOT = os.path.dirname(_HERE)
 LIB_PATH = os.path.join(_HERE, "libtdt.so")
+# An alternative build of the same sources may be loaded instead (tuning
+# experiments); the tests and the bench use the in-tree library.
+if os.environ.get("TDT_LIB_PATH"):
+    LIB_PATH = os.environ["TDT_LIB_PATH"]
 SOURCES = [os.path.join(_HERE, "csrc", "tdt_kernels.hip"), os.path.join(_HERE, "csrc", "tdt_api.cpp")]
 HEADER = os.path.join(_ROOT, "include", "tdt.h")
 
@@ -33,7 +37,7 @@ DTYPES = {"f64": 0, "f32": 1, "f32_refine": 2}
 EXPORTS = [
     "tdt_plan_create", "tdt_plan_varlen_create", "tdt_plan_reserve", "tdt_solve",
     "tdt_solve_varlen", "tdt_solve_backward", "tdt_plan_destroy", "tdt_status_string",
-    "tdt_last_info", "tdt_block_constants", "tdt_segment_merge", "tdt_plan_profile",
+    "tdt_last_info", "tdt_block_constants", "tdt_green_rows", "tdt_segment_merge", "tdt_plan_profile",
     "tdt_plan_profile_read", "tdt_build_info",
 ]
 
@@ -83,6 +87,7 @@ def lib():
                           ctypes.POINTER(d)],
         "tdt_block_constants": [d, d, d, i32, p],
         "tdt_segment_merge": [p, p, p],
+        "tdt_green_rows": [d, d, d, i64, p, p],
         "tdt_plan_profile": [p, i32],
         "tdt_plan_profile_read": [p, p, ctypes.POINTER(i64)],
         "tdt_build_info": [ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),

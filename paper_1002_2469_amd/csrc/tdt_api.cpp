@@ -34,6 +34,7 @@ struct tdt_plan_s {
   float* dvec32[2] = {nullptr, nullptr};
   double* dtab64[2] = {nullptr, nullptr};
   float* dtab32[2] = {nullptr, nullptr};
+  double* dgreen[2] = {nullptr, nullptr};   // series with several tiles: [2][kTile]
   // varlen launch lists
   int2* dp1 = nullptr;
   int2* dfin = nullptr;
@@ -43,6 +44,7 @@ struct tdt_plan_s {
   // workspace
   int64_t ws_slots = 0, ws_fslots = 0;
   double* summ = nullptr;
+  double* bpart = nullptr;
   double* ghost = nullptr;
   double* gscr = nullptr;
   double* gpart = nullptr;
@@ -111,6 +113,34 @@ bool segment_ends(ld a, ld b, ld c, int64_t L, ld out[4]) {
   out[3] = d2[L - 1];
   return std::isfinite((double)out[0]) && std::isfinite((double)out[1]) &&
          std::isfinite((double)out[2]) && std::isfinite((double)out[3]);
+}
+
+// First and last row of T_L^{-1} (T = tridiag{a, b, c} of order L): the rows
+// r solve T^T r = e_0 and T^T r = e_{L-1}, T^T = tridiag{c, b, a}.
+bool green_rows(ld a, ld b, ld c, int64_t L, double* first, double* last) {
+  std::vector<ld> cpv((size_t)L), r1((size_t)L), r2((size_t)L);
+  ld u = b;
+  if (u == 0.0L) return false;
+  cpv[0] = a / u;                 // super-diagonal of T^T is a
+  r1[0] = 1.0L / u;
+  r2[0] = L == 1 ? 1.0L / u : 0.0L;
+  for (int64_t i = 1; i < L; ++i) {
+    u = b - c * cpv[i - 1];       // sub-diagonal of T^T is c
+    if (u == 0.0L) return false;
+    cpv[i] = a / u;
+    r1[i] = (0.0L - c * r1[i - 1]) / u;
+    r2[i] = ((i == L - 1 ? 1.0L : 0.0L) - c * r2[i - 1]) / u;
+  }
+  for (int64_t i = L - 2; i >= 0; --i) {
+    r1[i] -= cpv[i] * r1[i + 1];
+    r2[i] -= cpv[i] * r2[i + 1];
+  }
+  for (int64_t i = 0; i < L; ++i) {
+    first[i] = (double)r1[i];
+    last[i] = (double)r2[i];
+    if (!std::isfinite(first[i]) || !std::isfinite(last[i])) return false;
+  }
+  return true;
 }
 
 struct SegLD {
@@ -183,8 +213,13 @@ tdt_status_t build_system(double a, double b, double c, int64_t n, SysDesc& D, d
   ld iu[kB], cp[kB], phi[kB], chi[kB];
   if (!block_vectors(a, b, c, kB, iu, cp, phi, chi)) return TDT_ERR_SINGULAR;
   for (int i = 0; i < kB; ++i) {
-    const ld vv[4] = {iu[i], cp[i], phi[i], chi[i]};
-    for (int k = 0; k < 4; ++k) {
+    ld vv[tdt::kVecN];
+    vv[tdt::kVecIU] = iu[i];
+    vv[tdt::kVecCP] = cp[i];
+    vv[tdt::kVecPHI] = phi[i];
+    vv[tdt::kVecCHI] = chi[i];
+    vv[tdt::kVecAIU] = (ld)a * iu[i];
+    for (int k = 0; k < tdt::kVecN; ++k) {
       v64[k * kB + i] = (double)vv[k];
       v32[k * kB + i] = (float)vv[k];
       if (!std::isfinite(v64[k * kB + i])) return TDT_ERR_SINGULAR;
@@ -263,10 +298,11 @@ tdt_status_t dev_upload(T** dst, const T* src, size_t count) {
 
 void free_workspace(tdt_plan_s* p) {
   (void)hipFree(p->summ);
+  (void)hipFree(p->bpart);
   (void)hipFree(p->ghost);
   (void)hipFree(p->gscr);
   (void)hipFree(p->gpart);
-  p->summ = p->ghost = p->gscr = p->gpart = nullptr;
+  p->summ = p->bpart = p->ghost = p->gscr = p->gpart = nullptr;
   p->ws_slots = p->ws_fslots = 0;
 }
 
@@ -285,6 +321,7 @@ tdt_status_t ensure_workspace(tdt_plan_s* p, int64_t slots, int64_t fslots, hipS
   (void)hipDeviceSynchronize();
   free_workspace(p);
   if (hipMalloc(&p->summ, (size_t)ns * 2 * sizeof(double)) != hipSuccess ||
+      hipMalloc(&p->bpart, (size_t)ns * 2 * tdt::kNW * sizeof(double)) != hipSuccess ||
       hipMalloc(&p->ghost, (size_t)ns * 2 * sizeof(double)) != hipSuccess ||
       hipMalloc(&p->gscr, (size_t)ns * 3 * sizeof(double)) != hipSuccess ||
       hipMalloc(&p->gpart, (size_t)nf * 3 * sizeof(double)) != hipSuccess) {
@@ -315,6 +352,7 @@ void destroy(tdt_plan_s* p) {
     (void)hipFree(p->dvec32[k]);
     (void)hipFree(p->dtab64[k]);
     (void)hipFree(p->dtab32[k]);
+    (void)hipFree(p->dgreen[k]);
   }
   (void)hipFree(p->dp1);
   (void)hipFree(p->dfin);
@@ -361,6 +399,13 @@ tdt_status_t finish_plan(tdt_plan_s* p, const std::vector<double>& tm1,
       fs += p->hsys[dir][s].ntiles;
     }
     p->vfslots = fs;
+    if (!p->varlen && p->hsys[dir][0].ntiles > 1) {
+      std::vector<double> g(2 * (size_t)kTile);
+      const double a = dir == 0 ? tm1[0] : t1[0], c = dir == 0 ? t1[0] : tm1[0];
+      if (!green_rows(a, t0[0], c, kTile, g.data(), g.data() + kTile)) return TDT_ERR_SINGULAR;
+      tdt_status_t sg = dev_upload(&p->dgreen[dir], g.data(), g.size());
+      if (sg != TDT_OK) return sg;
+    }
     tdt_status_t st = dev_upload(&p->dvec64[dir], v64.data(), v64.size());
     if (st == TDT_OK) st = dev_upload(&p->dvec32[dir], v32.data(), v32.size());
     if (st == TDT_OK) st = dev_upload(&p->dtab64[dir], t64.data(), t64.size());
@@ -429,8 +474,13 @@ tdt_status_t run(tdt_plan_s* p, int dir, const void* F, void* X, const void* Xfw
   L.iters = p->iters;
   L.max_iter = p->max_iter;
   L.refine_tol = p->refine_tol;
+  L.max_ntiles = 1;
+  for (const SysDesc& D : p->hsys[0]) L.max_ntiles = std::max(L.max_ntiles, (int)D.ntiles);
   int64_t slots, fslots;
   if (p->varlen) {
+    L.green = nullptr;
+    L.n_beta = L.n_last = 0;
+    L.nfull = 0;
     L.p1_items = p->dp1;
     L.fin_items = p->dfin;
     L.grid_items = p->dgrid;
@@ -444,6 +494,10 @@ tdt_status_t run(tdt_plan_s* p, int dir, const void* F, void* X, const void* Xfw
     L.p1_items = nullptr;
     L.fin_items = nullptr;
     L.grid_items = nullptr;
+    L.green = p->dgreen[dir];
+    L.nfull = (int)(p->N % kTile == 0 ? nt : nt - 1);
+    L.n_beta = nt > 1 ? M * L.nfull : 0;
+    L.n_last = (nt > 1 && p->N % kTile != 0) ? M : 0;
     L.n_p1 = nt > 1 ? M * nt : 0;
     L.n_grid = nt > 1 ? M : 0;
     L.n_fin = M * nt;
@@ -453,8 +507,9 @@ tdt_status_t run(tdt_plan_s* p, int dir, const void* F, void* X, const void* Xfw
   if (L.n_fin > 0x7fffffffLL) return TDT_ERR_INVALID_ARG;
   tdt_status_t s = ensure_workspace(p, slots, fslots, st);
   if (s != TDT_OK) return s;
-  if (!p->summ || !p->ghost || !p->gscr || !p->gpart) return TDT_ERR_OOM;
+  if (!p->summ || !p->bpart || !p->ghost || !p->gscr || !p->gpart) return TDT_ERR_OOM;
   L.summ = p->summ;
+  L.bpart = p->bpart;
   L.ghost = p->ghost;
   L.gscr = p->gscr;
   L.gpart = p->gpart;
@@ -631,6 +686,13 @@ tdt_status_t tdt_block_constants(double t_m1, double t_0, double t_1, int B, dou
   out[4 * B + 2] = (double)chi[0];
   out[4 * B + 3] = (double)chi[B - 1];
   return TDT_OK;
+}
+
+tdt_status_t tdt_green_rows(double t_m1, double t_0, double t_1, int64_t L, double* first,
+                            double* last) {
+  if (!first || !last || L < 1 || L > ((int64_t)1 << 26) || !finite3(t_m1, t_0, t_1))
+    return TDT_ERR_INVALID_ARG;
+  return green_rows(t_m1, t_0, t_1, L, first, last) ? TDT_OK : TDT_ERR_SINGULAR;
 }
 
 tdt_status_t tdt_segment_merge(const double* l, const double* r, double* out) {

@@ -8,10 +8,11 @@ namespace tdt {
 // Block of contiguous unknowns owned by one lane (the paper's sub-vector U_m
 // of Sec. 2.1 held by one processing element), threads per workgroup, and the
 // tile: the unknowns one workgroup holds on chip at once.
-constexpr int kB = 32;
-constexpr int kNT = 256;
+constexpr int kB = 16;
+constexpr int kNT = 512;
 constexpr int kNW = kNT / 64;          // wavefronts per workgroup
 constexpr int kTile = kB * kNT;        // 8192 unknowns per tile
+constexpr int kMinWavesPerSimd = 4;    // occupancy the tile kernels are compiled for
 
 // One Toeplitz system as the kernels see it.  All constants are double; the
 // float kernels round them on load.  Segment end values use the order
@@ -38,7 +39,9 @@ struct SysDesc {
 enum { kTabBeta = 0, kTabInvD = 1, kTabN = 2 };
 
 // Per-system block vectors, kB each, in this order.
-enum { kVecIU = 0, kVecCP = 1, kVecPHI = 2, kVecCHI = 3, kVecN = 4 };
+//   IU: 1/u_i (inverse pivots), AIU: t_-1/u_i, CP: t_1/u_i, PHI, CHI: the
+//   block's responses to unit values just left / right of it.
+enum { kVecIU = 0, kVecCP = 1, kVecPHI = 2, kVecCHI = 3, kVecAIU = 4, kVecN = 5 };
 
 // Everything one solve launch sequence needs (device pointers).
 struct LaunchSet {
@@ -51,7 +54,16 @@ struct LaunchSet {
   const int2* fin_items;   // varlen: (system, tile) of the final pass
   const int* grid_items;   // varlen: systems with more than one tile
   int64_t n_p1, n_fin, n_grid;
+  // series plans with more than one tile: the first pass is a dot product of
+  // every full tile with the tile's Green rows (n_beta items), plus the
+  // sweep-based pass over the partial last tile of each right-hand side
+  // (n_last items); varlen plans use the sweep-based pass over p1_items
+  const double* green;     // [2][kTile] or null
+  int64_t n_beta, n_last;
+  int nfull;
+  int max_ntiles;          // most tiles of any system (selects the interface kernel)
   double* summ;
+  double* bpart;           // [slot][kNW][2] partial sums of the streaming first pass
   double* ghost;
   double* gscr;
   double* gpart;

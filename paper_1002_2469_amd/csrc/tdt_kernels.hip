@@ -1,9 +1,9 @@
 // tdt_kernels.hip -- gfx950 kernels of the partitioned dichotomy solve.
 //
 // Formulation (Sec. 2.2-2.3 of the paper, restated for one GPU).  The system
-// is cut into blocks of kB consecutive unknowns, one block per lane; 256
-// lanes (4 wavefronts) form a workgroup tile of 8192 unknowns; a long system
-// is a sequence of tiles.  Every block of a Toeplitz matrix is the same
+// is cut into blocks of kB consecutive unknowns, one block per lane; kNT
+// lanes form a workgroup tile of kTile unknowns; a long system is a sequence
+// of tiles.  Every block of a Toeplitz matrix is the same
 // kB x kB matrix T_B, so its LU multipliers and its responses to unit values
 // just outside it (phi: left, chi: right) are computed once per T on the host
 // (the economical preliminary step of Sec. 3.1) and read here as
@@ -68,9 +68,16 @@ __device__ __forceinline__ int opaque(int v) {
 // for reads at or past `bytes` (and for "negative" offsets, which wrap to
 // huge unsigned ones) and drops such writes, which is how partial tiles and
 // the rows just outside a system are handled.
+// The base and size are wave-uniform by construction; readfirstlane states it
+// to the compiler, which otherwise may not prove it and would wrap every
+// access in a loop over distinct descriptors.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, int64_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
-                                           0x00020000);
+  const uint64_t a = reinterpret_cast<uintptr_t>(base);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  const int nb = __builtin_amdgcn_readfirstlane((int)bytes);
+  void* ub = reinterpret_cast<void*>((uintptr_t)(((uint64_t)hi << 32) | lo));
+  return __builtin_amdgcn_make_buffer_rsrc(ub, (short)0, nb, 0x00020000);
 }
 template <typename T>
 __device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, int off) {
@@ -201,10 +208,106 @@ __device__ __forceinline__ void lane_ghosts(const Seg<T>& pre, const Seg<T>& suf
   xr = lane == 63 ? XRw : nx;
 }
 
+// Cross-lane moves inside a wavefront.  DPP row shifts move a value by d lanes
+// within each row of 16 lanes (lanes whose source falls outside the row keep
+// `old`); readlane copies one lane's value to all lanes.
+template <int CTRL>
+__device__ __forceinline__ float dpp(float old, float src) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old),
+                                                               __builtin_bit_cast(int, src),
+                                                               CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double old, double src) {
+  const uint64_t o = __builtin_bit_cast(uint64_t, old), v = __builtin_bit_cast(uint64_t, src);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)o, (int)(uint32_t)v,
+                                                            CTRL, 0xf, 0xf, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(o >> 32),
+                                                            (int)(uint32_t)(v >> 32), CTRL, 0xf,
+                                                            0xf, false);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ float readlane(float v, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+__device__ __forceinline__ double readlane(double v, int l) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+// Maximum over the 64 lanes (all lanes receive it).
+__device__ __forceinline__ double wave_max(double v) {
+  v = fmax(v, dpp<0x111>(v, v));
+  v = fmax(v, dpp<0x112>(v, v));
+  v = fmax(v, dpp<0x114>(v, v));
+  v = fmax(v, dpp<0x118>(v, v));
+  return fmax(fmax(readlane(v, 15), readlane(v, 31)), fmax(readlane(v, 47), readlane(v, 63)));
+}
+
+constexpr int kDppRowShr = 0x110;   // + d: row_shr:d
+constexpr int kDppRowShl = 0x100;   // + d: row_shl:d
+
+// Inclusive left-to-right scan over the 64 lanes of affine maps x -> A x + g
+// (composition: the map of lane l applied after those of lanes < l): four
+// in-row DPP steps, then the four row totals (readlane) carried across rows.
+template <typename T>
+__device__ __forceinline__ void wave_scan_affine_fwd(T& A, T& g) {
+#define TDT_FWD_STEP(D)                                    \
+  {                                                        \
+    const T As = dpp<kDppRowShr + D>(T(1), A);             \
+    const T gs = dpp<kDppRowShr + D>(T(0), g);             \
+    g = A * gs + g;                                        \
+    A = A * As;                                            \
+  }
+  TDT_FWD_STEP(1) TDT_FWD_STEP(2) TDT_FWD_STEP(4) TDT_FWD_STEP(8)
+#undef TDT_FWD_STEP
+  const int row = (threadIdx.x & 63) >> 4;
+  const T A0 = readlane(A, 15), g0 = readlane(g, 15);
+  const T A1 = readlane(A, 31), g1 = readlane(g, 31);
+  const T A2 = readlane(A, 47), g2 = readlane(g, 47);
+  // carry into row r: rows 0..r-1 composed
+  const T cA1 = A0, cg1 = g0;
+  const T cA2 = A1 * cA1, cg2 = A1 * cg1 + g1;
+  const T cA3 = A2 * cA2, cg3 = A2 * cg2 + g2;
+  const T cA = row == 0 ? T(1) : (row == 1 ? cA1 : (row == 2 ? cA2 : cA3));
+  const T cg = row == 0 ? T(0) : (row == 1 ? cg1 : (row == 2 ? cg2 : cg3));
+  g = A * cg + g;
+  A = A * cA;
+}
+
+// Inclusive right-to-left scan of affine maps u -> C u + h (the map of lane l
+// applied after those of lanes > l).
+template <typename T>
+__device__ __forceinline__ void wave_scan_affine_bwd(T& C, T& h) {
+#define TDT_BWD_STEP(D)                                    \
+  {                                                        \
+    const T Cs = dpp<kDppRowShl + D>(T(1), C);             \
+    const T hs = dpp<kDppRowShl + D>(T(0), h);             \
+    h = C * hs + h;                                        \
+    C = C * Cs;                                            \
+  }
+  TDT_BWD_STEP(1) TDT_BWD_STEP(2) TDT_BWD_STEP(4) TDT_BWD_STEP(8)
+#undef TDT_BWD_STEP
+  const int row = (threadIdx.x & 63) >> 4;
+  const T C1 = readlane(C, 16), h1 = readlane(h, 16);
+  const T C2 = readlane(C, 32), h2 = readlane(h, 32);
+  const T C3 = readlane(C, 48), h3 = readlane(h, 48);
+  // carry into row r from the right: rows r+1..3 composed
+  const T eC2 = C3, eh2 = h3;
+  const T eC1 = C2 * eC2, eh1 = C2 * eh2 + h2;
+  const T eC0 = C1 * eC1, eh0 = C1 * eh1 + h1;
+  const T eC = row == 3 ? T(1) : (row == 2 ? eC2 : (row == 1 ? eC1 : eC0));
+  const T eh = row == 3 ? T(0) : (row == 2 ? eh2 : (row == 1 ? eh1 : eh0));
+  h = C * eh + h;
+  C = C * eC;
+}
+
 // Per-system constants in compute precision.
 template <typename Tc>
 struct Consts {
   cptr<Tc> iu;
+  cptr<Tc> aiu;
   cptr<Tc> cp;
   cptr<Tc> phi;
   cptr<Tc> chi;
@@ -247,15 +350,17 @@ __device__ __forceinline__ void tile_solve(Tc (&q)[kB], int len, Tc XLt, Tc XRt,
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const bool tail = len > 0 && len < kB;
   const bool wave_tail = __ballot(tail) != 0;
-  // local Thomas sweep with the shared multipliers (T_B^{-1} q)
-  q[0] *= K.iu[0];
+  // local Thomas sweep with the shared multipliers (T_B^{-1} q); the forward
+  // step d_i = q_i/u_i - (t_-1/u_i) d_{i-1} keeps one dependent FMA per row
+#pragma unroll
+  for (int i = 0; i < kB; ++i) q[i] *= K.iu[i];
   if (!wave_tail) {
 #pragma unroll
-    for (int i = 1; i < kB; ++i) q[i] = (q[i] - K.a * q[i - 1]) * K.iu[i];
+    for (int i = 1; i < kB; ++i) q[i] -= K.aiu[i] * q[i - 1];
   } else {
 #pragma unroll
     for (int i = 1; i < kB; ++i) {
-      const Tc d = (q[i] - K.a * q[i - 1]) * K.iu[i];
+      const Tc d = q[i] - K.aiu[i] * q[i - 1];
       q[i] = i < len ? d : Tc(0);
     }
   }
@@ -280,15 +385,7 @@ __device__ __forceinline__ void tile_solve(Tc (&q)[kB], int len, Tc XLt, Tc XRt,
   // left-to-right sums
   Tc A = pl * iD;
   Tc g = yl + A * bp * yf;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const Tc Alo = __shfl_up(A, d, 64);
-    const Tc glo = __shfl_up(g, d, 64);
-    if (lane >= d) {
-      g = A * glo + g;
-      A = A * Alo;
-    }
-  }
+  wave_scan_affine_fwd(A, g);
   if (lane == 63) { fw[w][0] = A; fw[w][1] = g; }
   __syncthreads();
   Tc cin = XLt;
@@ -299,15 +396,7 @@ __device__ __forceinline__ void tile_solve(Tc (&q)[kB], int len, Tc XLt, Tc XRt,
   // right-to-left sums
   Tc C = cf * iD;
   Tc h = (yf + pf * alpha_prev) * iD;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const Tc Chi = __shfl_down(C, d, 64);
-    const Tc hhi = __shfl_down(h, d, 64);
-    if (lane + d < 64) {
-      h = C * hhi + h;
-      C = C * Chi;
-    }
-  }
+  wave_scan_affine_bwd(C, h);
   if (lane == 0) { bw[w][0] = C; bw[w][1] = h; }
   __syncthreads();
   Tc ein = XRt;
@@ -335,7 +424,7 @@ __device__ __forceinline__ void tile_solve(Tc (&q)[kB], int len, Tc XLt, Tc XRt,
       const Tc ynext = i + 1 < kB ? q[i + 1] : Tc(0);
       const Tc dp = q[i] + K.cp[i] * ynext + delta;
       q[i] = i < len ? dp : Tc(0);
-      if (i + 1 < kB) delta = -K.a * delta * K.iu[i + 1];
+      if (i + 1 < kB) delta = -K.aiu[i + 1] * delta;
     }
 #pragma unroll
     for (int i = kB - 2; i >= 0; --i) q[i] -= K.cp[i] * q[i + 1];
@@ -357,6 +446,7 @@ struct TileArgs {
   const int2* __restrict__ items;     // varlen: (system, tile) per item; null for a series
   int64_t nitems;
   int reverse;                        // process items last to first
+  int last_only;                      // series: item m is the last tile of right-hand side m
   double* __restrict__ summ;          // [slot][2] tile summaries (y_first, y_last)
   const double* __restrict__ ghost;   // [slot][2] values just outside each tile
   const Tio* __restrict__ Xfwd;       // adjoint: forward solution
@@ -382,9 +472,11 @@ struct ItemInfo {
 };
 
 __device__ __forceinline__ ItemInfo decode_item(const int2* items, const SysDesc* sys,
-                                                int64_t it) {
+                                                int64_t it, int last_only) {
   ItemInfo r;
-  if (items) {
+  if (last_only) {
+    r.s = 0; r.m = it; r.t = *as_const(&sys[0].ntiles) - 1;
+  } else if (items) {
     const cptr<int> iv = as_const(reinterpret_cast<const int*>(items)) + 2 * it;
     r.s = iv[0]; r.t = iv[1]; r.m = 0;
   } else {
@@ -405,6 +497,7 @@ __device__ __forceinline__ Consts<Tc> make_consts(const SysDesc& S, const double
     v = reinterpret_cast<const Tc*>(vec32) + (int64_t)S.cidx * kVecN * kB;
   const cptr<Tc> c = as_const(v);
   K.iu = c + kVecIU * kB;
+  K.aiu = c + kVecAIU * kB;
   K.cp = c + kVecCP * kB;
   K.phi = c + kVecPHI * kB;
   K.chi = c + kVecCHI * kB;
@@ -412,22 +505,6 @@ __device__ __forceinline__ Consts<Tc> make_consts(const SysDesc& S, const double
   K.pf = (Tc)S.blk[0]; K.pl = (Tc)S.blk[1]; K.cf = (Tc)S.blk[2];
   K.tail_pf = (Tc)S.tail_pf;
   return K;
-}
-
-// Workgroup max of two non-negative values (fixed order, all threads get it).
-__device__ __forceinline__ void wg_max2(double& u, double& v, double (*red)[4]) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) {
-    u = fmax(u, __shfl_xor(u, d, 64));
-    v = fmax(v, __shfl_xor(v, d, 64));
-  }
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) { red[w][0] = u; red[w][1] = v; }
-  __syncthreads();
-  u = red[0][0]; v = red[0][1];
-#pragma unroll
-  for (int k = 1; k < kNW; ++k) { u = fmax(u, red[k][0]); v = fmax(v, red[k][1]); }
 }
 
 struct TileGeom {
@@ -438,9 +515,9 @@ struct TileGeom {
 };
 
 __device__ __forceinline__ TileGeom tile_geom(const int2* items, const SysDesc* sys,
-                                              int64_t it) {
+                                              int64_t it, int last_only) {
   TileGeom G;
-  G.I = decode_item(items, sys, it);
+  G.I = decode_item(items, sys, it, last_only);
   const SysDesc S = load_sys(sys, G.I.s);
   G.t0 = (int64_t)G.I.t * kTile;
   G.base = S.off + G.I.m * S.n + G.t0;
@@ -465,7 +542,7 @@ template <typename Tio, typename Tc, bool SUMMARY>
 __device__ __forceinline__ void prefetch(const TileArgs<Tio>& A, int64_t item,
                                          Prefetch<Tio, Tc>& P) {
   const int tid = threadIdx.x;
-  const TileGeom G = tile_geom(A.items, A.sys, item);
+  const TileGeom G = tile_geom(A.items, A.sys, item, A.last_only);
   const SysDesc S = load_sys(A.sys, G.I.s);
   const __amdgpu_buffer_rsrc_t src = make_rsrc(A.F + G.base, (int64_t)G.tl * sizeof(Tio));
   const int vb = opaque(tid * (int)sizeof(Tio));
@@ -501,8 +578,15 @@ __device__ __forceinline__ void prefetch(const TileArgs<Tio>& A, int64_t item,
 //                    in double, repeated until converged.
 //   BWD            : also accumulates the t-gradient partial sums against the
 //                    forward solution Xfwd (the tile solves T^T gF = gX).
+#ifndef TDT_REFINE_WAVES
+#define TDT_REFINE_WAVES kMinWavesPerSimd
+#endif
+#ifndef TDT_REFINE_PREFETCH
+#define TDT_REFINE_PREFETCH 0
+#endif
 template <typename Tio, typename Tc, bool REFINE, bool SUMMARY, bool BWD>
-__global__ __launch_bounds__(kNT, 2) void k_tile(TileArgs<Tio> A) {
+__global__ __launch_bounds__(kNT, REFINE ? TDT_REFINE_WAVES : kMinWavesPerSimd) void k_tile(
+    TileArgs<Tio> A) {
   constexpr int RP = kB + 16 / (int)sizeof(Tio);   // padded LDS row pitch
   __shared__ __align__(16) Tio lds[kNT * RP];
   __shared__ Tc fw[kNW][2], bw[kNW][2];
@@ -514,13 +598,17 @@ __global__ __launch_bounds__(kNT, 2) void k_tile(TileArgs<Tio> A) {
   const int lbase = (tid / kB) * RP + (tid % kB);
   constexpr int lstride = (kNT / kB) * RP;
   auto item_of = [&](int64_t k) { return A.reverse ? A.nitems - 1 - k : k; };
+  // the refinement kernel may load each tile at the top of its iteration
+  // instead of one tile ahead, trading latency hiding for registers
+  constexpr bool PF = !REFINE || TDT_REFINE_PREFETCH;
   int64_t k = blockIdx.x;
   Prefetch<Tio, Tc> P;
-  if (k < A.nitems) prefetch<Tio, Tc, SUMMARY>(A, item_of(k), P);
+  if (PF && k < A.nitems) prefetch<Tio, Tc, SUMMARY>(A, item_of(k), P);
 
   while (k < A.nitems) {
+    if (!PF) prefetch<Tio, Tc, SUMMARY>(A, item_of(k), P);
     const int64_t item = item_of(k);
-    const TileGeom G = tile_geom(A.items, A.sys, item);
+    const TileGeom G = tile_geom(A.items, A.sys, item, A.last_only);
     const SysDesc S = load_sys(A.sys, G.I.s);
     const int64_t slot = A.items ? (int64_t)S.slot0 + G.I.t : G.I.m * S.ntiles + G.I.t;
     const double XLt = P.XL, XRt = P.XR;
@@ -536,7 +624,7 @@ __global__ __launch_bounds__(kNT, 2) void k_tile(TileArgs<Tio> A) {
       for (int j = 0; j < kB; ++j) lw[j * lstride] = P.v[j];
     }
     const int64_t kn = k + gridDim.x;
-    if (kn < A.nitems) prefetch<Tio, Tc, SUMMARY>(A, item_of(kn), P);
+    if (PF && kn < A.nitems) prefetch<Tio, Tc, SUMMARY>(A, item_of(kn), P);
     __syncthreads();
     Tio* myrow = lds + tid * RP;
 
@@ -554,19 +642,54 @@ __global__ __launch_bounds__(kNT, 2) void k_tile(TileArgs<Tio> A) {
         for (int i = 0; i < kB; ++i) myrow[i] = (Tio)q[i];
       }
     } else {
-      // iterative refinement: x = 0; repeat r = f - T x (double, with the
-      // tile's outside values), d = solve_float(r) with zero outside values,
-      // x += d (double)
+      // iterative refinement: x_1 = solve_float(f with the tile's outside
+      // values); then repeat r = f - T x (double), d = solve_float(r) with
+      // zero outside values, x += d (double).  After update k >= 2 the next
+      // update is predicted as |d_k| rho with rho = |d_k| / |d_{k-1}|
+      // (|d_1| = |x_1|, approximated by |x|); stop when that is below
+      // tol |x|, when updates stop shrinking, or at the cap.  One barrier per
+      // update carries both the wavefront edges for the next residual and the
+      // wavefront maxima of the last update.
       const double a = S.a, b = S.b, c = S.c;
       double x[kB];
+      {
+        Tc q[kB];
 #pragma unroll
-      for (int i = 0; i < kB; ++i) x[i] = 0.0;
-      double dprev = 0.0;
-      int it = 0;
+        for (int i = 0; i < kB; ++i) {
+          double r = (double)myrow[i];
+          if (i == 0 && tid == 0) r -= a * XLt;
+          if (i == kB - 1 && tid == kNT - 1) r -= c * XRt;
+          q[i] = i < len ? (Tc)r : Tc(0);
+        }
+        tile_solve(q, len, Tc(0), Tc(0), K, bp, iDf, fw, bw, (double*)nullptr,
+                   (double*)nullptr);
+#pragma unroll
+        for (int i = 0; i < kB; ++i) x[i] = (double)q[i];
+      }
+      int it = 1;
+      double dprev = 0.0, dloc = 0.0;
       for (;;) {
-        if (lane == 0) edge[w][0] = x[0];
+        double dmax = 0.0, xmax = 0.0;
+        if (it >= 2) {
+          double xl = 0.0;
+#pragma unroll
+          for (int i = 0; i < kB; ++i) xl = fmax(xl, fabs(x[i]));
+          dmax = wave_max(dloc);
+          xmax = wave_max(xl);
+        }
+        if (lane == 0) { edge[w][0] = x[0]; red[w][0] = dmax; red[w][1] = xmax; }
         if (lane == 63) edge[w][1] = x[kB - 1];
         __syncthreads();
+        if (it >= 2) {
+          dmax = red[0][0];
+          xmax = red[0][1];
+#pragma unroll
+          for (int q = 1; q < kNW; ++q) { dmax = fmax(dmax, red[q][0]); xmax = fmax(xmax, red[q][1]); }
+          const double rho = it == 2 ? dmax / xmax : dmax / dprev;
+          dprev = dmax;
+          if (dmax == 0.0 || dmax * rho <= A.refine_tol * xmax || rho > 0.9) break;
+        }
+        if (it >= A.max_iter) break;
         double xm = __shfl_up(x[kB - 1], 1, 64);
         double xp = __shfl_down(x[0], 1, 64);
         if (lane == 0) xm = w == 0 ? XLt : edge[w > 0 ? w - 1 : 0][1];
@@ -581,24 +704,13 @@ __global__ __launch_bounds__(kNT, 2) void k_tile(TileArgs<Tio> A) {
         }
         tile_solve(q, len, Tc(0), Tc(0), K, bp, iDf, fw, bw, (double*)nullptr,
                    (double*)nullptr);
-        double dmax = 0.0, xmax = 0.0;
+        dloc = 0.0;
 #pragma unroll
         for (int i = 0; i < kB; ++i) {
           x[i] += (double)q[i];
-          dmax = fmax(dmax, fabs((double)q[i]));
-          xmax = fmax(xmax, fabs(x[i]));
+          dloc = fmax(dloc, fabs((double)q[i]));
         }
-        wg_max2(dmax, xmax, red);
         ++it;
-        // stop when the next update is predicted below tol (contraction
-        // estimate dmax/dprev), when updates stop shrinking, or at the cap
-        bool stop = it >= A.max_iter || dmax == 0.0;
-        if (it >= 2) {
-          const double rho = dmax / dprev;
-          stop = stop || dmax * rho <= A.refine_tol * xmax || rho > 0.9;
-        }
-        dprev = dmax;
-        if (stop) break;
       }
       if (tid == 0 && A.iters) atomicMax(A.iters, it);
       if constexpr (SUMMARY) {
@@ -660,6 +772,114 @@ __global__ __launch_bounds__(kNT, 2) void k_tile(TileArgs<Tio> A) {
       }
     }
     k = kn;
+  }
+}
+
+// First pass of a series plan over its full tiles: the tile summary is the
+// pair of sums of eq. (10),
+//     y_first = sum_j f_j (T_L^{-1})_{0,j},   y_last = sum_j f_j (T_L^{-1})_{L-1,j},
+// i.e. the right-hand side weighted by the first and last row of the inverse
+// of the tile's matrix (the Green's function rows of eq. (6) for a tile taken
+// as the whole system).  Every full tile of one Toeplitz matrix has the same
+// rows, so each lane keeps the entries of its own element positions in
+// registers and the pass is a streaming dot product with no transposition
+// and no sweeps.  Wavefront w of a workgroup always reads slice w (kTile/kNW
+// consecutive rows, 16 bytes per lane per load) of the workgroup's tiles; the
+// kNW partial sums of a tile meet in LDS and are added in a fixed order one
+// tile later, after the next tile's loads are in flight, so the barrier never
+// stalls the stream.  Double arithmetic for every data type.
+constexpr int kBetaNT = 1024;                  // threads per workgroup of this pass
+constexpr int kBetaNW = kBetaNT / 64;
+constexpr int kSlice = kTile / kBetaNW;        // rows per wavefront slice
+constexpr int kBetaPerLane = kSlice / 64;      // rows per lane
+template <typename Tio>
+struct BetaArgs {
+  const Tio* __restrict__ F;
+  const SysDesc* __restrict__ sys;
+  const double* __restrict__ green;   // [2][kTile]: first row, last row
+  int64_t nitems;                     // right-hand sides x full tiles per right-hand side
+  int nfull;                          // full tiles per right-hand side
+  double* __restrict__ summ;          // [slot][2]
+};
+
+template <typename Tio>
+__global__ __launch_bounds__(kBetaNT) void k_beta(BetaArgs<Tio> A) {
+  constexpr int V = 16 / (int)sizeof(Tio);          // elements per 16-byte load
+  constexpr int NL = kBetaPerLane / V;              // loads per lane per slice
+  __shared__ double part[2][kBetaNW][2];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t n = *as_const(&A.sys[0].n);
+  const int nt = *as_const(&A.sys[0].ntiles);
+  // rows of this lane inside its slice: (j*64 + lane)*V + v
+  double g1[kBetaPerLane], gl[kBetaPerLane];
+#pragma unroll
+  for (int j = 0; j < NL; ++j)
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int e = w * kSlice + (j * 64 + lane) * V + v;
+      g1[j * V + v] = A.green[e];
+      gl[j * V + v] = A.green[kTile + e];
+    }
+  auto slot_of = [&](int64_t it) {
+    const int64_t m = it / A.nfull;
+    return m * nt + (it - m * A.nfull);
+  };
+  int par = 0;
+  int64_t prev = -1;
+  for (int64_t it = blockIdx.x; it < A.nitems; it += gridDim.x) {
+    const int64_t m = it / A.nfull;
+    const int t = (int)(it - m * A.nfull);
+    const __amdgpu_buffer_rsrc_t src = make_rsrc(
+        A.F + m * n + (int64_t)t * kTile + w * kSlice, (int64_t)kSlice * sizeof(Tio));
+    const int vb = opaque(lane * 16);
+    using R4 = decltype(__builtin_amdgcn_raw_buffer_load_b128(src, 0, 0, 0));
+    R4 raw[NL];
+#pragma unroll
+    for (int j = 0; j < NL; ++j) raw[j] = __builtin_amdgcn_raw_buffer_load_b128(src, vb + j * 1024, 0, 0);
+    // the previous tile's partials are complete in LDS once every wavefront
+    // has passed this barrier (its loads for this tile are already issued)
+    __syncthreads();
+    if (tid == 0 && prev >= 0) {
+      double u = 0.0, v = 0.0;
+      for (int k = 0; k < kBetaNW; ++k) { u += part[par ^ 1][k][0]; v += part[par ^ 1][k][1]; }
+      const int64_t sl = slot_of(prev);
+      A.summ[2 * sl] = u;
+      A.summ[2 * sl + 1] = v;
+    }
+    double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < NL; ++j) {
+      if constexpr (sizeof(Tio) == 8) {
+        const double2 f2 = __builtin_bit_cast(double2, raw[j]);
+        s1 += f2.x * g1[2 * j] + f2.y * g1[2 * j + 1];
+        s2 += f2.x * gl[2 * j] + f2.y * gl[2 * j + 1];
+      } else {
+        const float4 f4 = __builtin_bit_cast(float4, raw[j]);
+        const float fv[4] = {f4.x, f4.y, f4.z, f4.w};
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          s1 += (double)fv[v] * g1[4 * j + v];
+          s2 += (double)fv[v] * gl[4 * j + v];
+        }
+      }
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+      s1 += __shfl_xor(s1, d, 64);
+      s2 += __shfl_xor(s2, d, 64);
+    }
+    if (lane == 0) { part[par][w][0] = s1; part[par][w][1] = s2; }
+    prev = it;
+    par ^= 1;
+  }
+  __syncthreads();
+  if (tid == 0 && prev >= 0) {
+    double u = 0.0, v = 0.0;
+    for (int k = 0; k < kBetaNW; ++k) { u += part[par ^ 1][k][0]; v += part[par ^ 1][k][1]; }
+    const int64_t sl = slot_of(prev);
+    A.summ[2 * sl] = u;
+    A.summ[2 * sl + 1] = v;
   }
 }
 
@@ -731,6 +951,203 @@ __global__ __launch_bounds__(kNT) void k_grid(GridArgs A) {
   }
 }
 
+// Interface pass across the tiles of one system, affine form (one workgroup
+// of NTG threads per system and right-hand side, runs of up to R tiles per
+// thread).  Tiles play the role blocks play inside a tile: with (yf_t, yl_t)
+// the tile summaries and (Pf, Pl, Cf, Cl) the end values of a full tile (the
+// last tile has its own, padded), the left-to-right elimination coefficient
+//     beta_t = Cl + Pl Cf beta_{t-1} / (1 - Pf beta_{t-1}),  beta_{-1} = 0,
+// is a Moebius map of beta_{t-1}; its values at the start of every run come
+// from a scan of the 2x2 matrices of those maps.  Then, as in a tile,
+//     alpha_t = A_t alpha_{t-1} + g_t   (left to right, alpha_{-1} = 0),
+//     u_t     = C_t u_{t+1} + h_t       (right to left, u_P = 0),
+// and tile t's outside values are alpha_{t-1} + beta_{t-1} u_t and u_{t+1}.
+template <int NTG>
+struct GridShared {
+  double m[NTG / 64][4];   // wave aggregates (Moebius matrix)
+  double f[NTG / 64][2];   // wave aggregates (left-to-right affine map)
+  double b[NTG / 64][2];   // wave aggregates (right-to-left affine map)
+};
+
+// Kogge-Stone exclusive scans over the threads of a workgroup.
+template <int NTG>
+__device__ __forceinline__ void scan_mobius_excl(double (&M)[4], double (*ws)[4]) {
+  // inclusive in-wave prefix of products M_lane * ... * M_0 (applied right to left)
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double P[4] = {M[0], M[1], M[2], M[3]};
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    double Q[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) Q[k] = __shfl_up(P[k], d, 64);
+    if (lane >= d) {   // P = P * Q
+      const double r0 = P[0] * Q[0] + P[1] * Q[2], r1 = P[0] * Q[1] + P[1] * Q[3];
+      const double r2 = P[2] * Q[0] + P[3] * Q[2], r3 = P[2] * Q[1] + P[3] * Q[3];
+      const double sc = 1.0 / fmax(fmax(fabs(r0), fabs(r1)), fmax(fabs(r2), fabs(r3)));
+      P[0] = r0 * sc; P[1] = r1 * sc; P[2] = r2 * sc; P[3] = r3 * sc;
+    }
+  }
+  if (lane == 63) { ws[w][0] = P[0]; ws[w][1] = P[1]; ws[w][2] = P[2]; ws[w][3] = P[3]; }
+  __syncthreads();
+  // carry from earlier waves: C = W_{w-1} * ... * W_0
+  double C[4] = {1.0, 0.0, 0.0, 1.0};
+  for (int k = 0; k < w; ++k) {
+    const double r0 = ws[k][0] * C[0] + ws[k][1] * C[2], r1 = ws[k][0] * C[1] + ws[k][1] * C[3];
+    const double r2 = ws[k][2] * C[0] + ws[k][3] * C[2], r3 = ws[k][2] * C[1] + ws[k][3] * C[3];
+    const double sc = 1.0 / fmax(fmax(fabs(r0), fabs(r1)), fmax(fabs(r2), fabs(r3)));
+    C[0] = r0 * sc; C[1] = r1 * sc; C[2] = r2 * sc; C[3] = r3 * sc;
+  }
+  // exclusive: previous lane's inclusive prefix times the carry
+  double E[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) E[k] = __shfl_up(P[k], 1, 64);
+  if (lane == 0) { E[0] = 1.0; E[1] = 0.0; E[2] = 0.0; E[3] = 1.0; }
+  M[0] = E[0] * C[0] + E[1] * C[2];
+  M[1] = E[0] * C[1] + E[1] * C[3];
+  M[2] = E[2] * C[0] + E[3] * C[2];
+  M[3] = E[2] * C[1] + E[3] * C[3];
+}
+
+// Exclusive left-to-right scan of affine maps x -> A x + g; returns the value
+// entering this thread given x_in for thread 0.
+template <int NTG>
+__device__ __forceinline__ double scan_affine_fwd(double A, double g, double x_in,
+                                                  double (*ws)[2]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const double Alo = __shfl_up(A, d, 64), glo = __shfl_up(g, d, 64);
+    if (lane >= d) { g = A * glo + g; A = A * Alo; }
+  }
+  if (lane == 63) { ws[w][0] = A; ws[w][1] = g; }
+  __syncthreads();
+  double c = x_in;
+  for (int k = 0; k < w; ++k) c = ws[k][0] * c + ws[k][1];
+  const double incl = A * c + g;
+  const double ex = __shfl_up(incl, 1, 64);
+  return lane == 0 ? c : ex;
+}
+
+// Exclusive right-to-left scan of affine maps x -> C x + h; returns the value
+// entering this thread from the right given x_in after the last thread.
+template <int NTG>
+__device__ __forceinline__ double scan_affine_bwd(double C, double h, double x_in,
+                                                  double (*ws)[2]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  constexpr int NW = NTG / 64;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const double Chi = __shfl_down(C, d, 64), hhi = __shfl_down(h, d, 64);
+    if (lane + d < 64) { h = C * hhi + h; C = C * Chi; }
+  }
+  if (lane == 0) { ws[w][0] = C; ws[w][1] = h; }
+  __syncthreads();
+  double e = x_in;
+  for (int k = NW - 1; k > w; --k) e = ws[k][0] * e + ws[k][1];
+  const double incl = C * e + h;
+  const double ex = __shfl_down(incl, 1, 64);
+  return lane == 63 ? e : ex;
+}
+
+template <int NTG, int R>
+__global__ __launch_bounds__(NTG) void k_grid_affine(GridArgs A) {
+  __shared__ GridShared<NTG> sh;
+  const int tid = threadIdx.x;
+  int s = 0;
+  int64_t slot0;
+  if (A.gitems) {
+    s = as_const(A.gitems)[blockIdx.x];
+    slot0 = *as_const(&A.sys[s].slot0);
+  } else {
+    slot0 = (int64_t)blockIdx.x * *as_const(&A.sys[0].ntiles);
+  }
+  const SysDesc S = load_sys(A.sys, s);
+  const int P = S.ntiles;
+  const double* summ = A.summ + 2 * slot0;
+  double* ghost = A.ghost + 2 * slot0;
+  const int ta = tid * R;
+  // this thread's tiles: ta .. ta+R-1 (those >= P are empty).  Full tiles
+  // share (Pf, Pl, Cf, Cl); the last one has its own.
+  double yf[R], yl[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int t = ta + r;
+    const int tc = t < P ? t : 0;
+    const double u = summ[2 * tc], v = summ[2 * tc + 1];
+    yf[r] = t < P ? u : 0.0;
+    yl[r] = t < P ? v : 0.0;
+  }
+  auto kofs = [&](int t, double& pf, double& pl, double& cf, double& cl) {
+    const bool real = t < P, last = t == P - 1;
+    pf = real ? (last ? S.ltileK[0] : S.tileK[0]) : 0.0;
+    pl = real ? (last ? S.ltileK[1] : S.tileK[1]) : 0.0;
+    cf = real ? (last ? S.ltileK[2] : S.tileK[2]) : 0.0;
+    cl = real ? (last ? S.ltileK[3] : S.tileK[3]) : 0.0;
+  };
+  // 1. beta_{t-1} at every tile: Moebius maps composed over the run, scanned
+  double M[4] = {1.0, 0.0, 0.0, 1.0};
+#pragma unroll
+  for (int r = 0; r < R; ++r) {   // M = M_t * M
+    double pf, pl, cf, cl;
+    kofs(ta + r, pf, pl, cf, cl);
+    const double m0 = pl * cf - cl * pf, m1 = cl, m2 = -pf, m3 = 1.0;
+    const double r0 = m0 * M[0] + m1 * M[2], r1 = m0 * M[1] + m1 * M[3];
+    const double r2 = m2 * M[0] + m3 * M[2], r3 = m2 * M[1] + m3 * M[3];
+    const double sc = 1.0 / fmax(fmax(fabs(r0), fabs(r1)), fmax(fabs(r2), fabs(r3)));
+    M[0] = r0 * sc; M[1] = r1 * sc; M[2] = r2 * sc; M[3] = r3 * sc;
+  }
+  scan_mobius_excl<NTG>(M, sh.m);
+  double beta = M[1] / M[3];   // beta_{ta-1}
+  double bp[R], iD[R];
+  double Af = 1.0, gf = 0.0;   // composite left-to-right map of the run
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    double pf, pl, cf, cl;
+    kofs(ta + r, pf, pl, cf, cl);
+    bp[r] = beta;
+    iD[r] = 1.0 / (1.0 - pf * beta);
+    const double At = pl * iD[r];
+    const double gt = yl[r] + At * beta * yf[r];
+    gf = At * gf + gt;
+    Af = At * Af;
+    beta = cl + pl * beta * cf * iD[r];
+  }
+  // 2. alpha (left to right)
+  double alpha = scan_affine_fwd<NTG>(Af, gf, 0.0, sh.f);   // alpha_{ta-1}
+  double ap[R], h[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    double pf, pl, cf, cl;
+    kofs(ta + r, pf, pl, cf, cl);
+    ap[r] = alpha;
+    h[r] = (yf[r] + pf * alpha) * iD[r];
+    alpha = pl * iD[r] * alpha + (yl[r] + pl * iD[r] * bp[r] * yf[r]);
+  }
+  // 3. u (right to left)
+  double Cb = 1.0, hb = 0.0;   // composite right-to-left map of the run
+#pragma unroll
+  for (int r = R - 1; r >= 0; --r) {
+    double pf, pl, cf, cl;
+    kofs(ta + r, pf, pl, cf, cl);
+    const double Cr = cf * iD[r];
+    hb = Cr * hb + h[r];
+    Cb = Cr * Cb;
+  }
+  double u = scan_affine_bwd<NTG>(Cb, hb, 0.0, sh.b);      // u_{ta+R}
+#pragma unroll
+  for (int r = R - 1; r >= 0; --r) {
+    const int t = ta + r;
+    double pf, pl, cf, cl;
+    kofs(t, pf, pl, cf, cl);
+    const double un = u;                 // u_{t+1}
+    u = cf * iD[r] * u + h[r];           // u_t
+    if (t < P) {
+      ghost[2 * t] = ap[r] + bp[r] * u;
+      ghost[2 * t + 1] = un;
+    }
+  }
+}
+
 // Deterministic second stage of the t-gradient sums: series plans sum all
 // partials (one workgroup, fixed tree); varlen plans sum each system's tiles
 // in order (one thread per system).
@@ -779,9 +1196,9 @@ namespace tdt {
 
 // Resident workgroups per CU of a kernel (queried once per variant).
 template <typename KernelT>
-static int resident_per_cu(KernelT kern) {
+static int resident_per_cu(KernelT kern, int threads = kNT) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, kNT, 0) != hipSuccess || nb < 1)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, threads, 0) != hipSuccess || nb < 1)
     nb = 1;
   return nb;
 }
@@ -799,14 +1216,26 @@ static int num_cus() {
 }
 
 template <typename Tio, typename Tc, bool REFINE, bool SUMMARY, bool BWD>
-static void launch_tile(TileArgs<Tio>& A, int64_t nitems, int reverse, hipStream_t st) {
+static void launch_tile(TileArgs<Tio>& A, int64_t nitems, int reverse, int last_only,
+                        hipStream_t st) {
   auto kern = k_tile<Tio, Tc, REFINE, SUMMARY, BWD>;
   static int per_cu = resident_per_cu(kern);
   const int64_t cap = (int64_t)per_cu * num_cus();
   A.nitems = nitems;
   A.reverse = reverse;
+  A.last_only = last_only;
   const unsigned grid = (unsigned)(nitems < cap ? nitems : cap);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(kNT), 0, st, A);
+}
+
+template <typename Tio>
+static void launch_beta(const LaunchSet& L, const Tio* F, hipStream_t st) {
+  auto kern = k_beta<Tio>;
+  static int per_cu = resident_per_cu(kern, kBetaNT);
+  const int64_t cap = (int64_t)per_cu * num_cus();
+  BetaArgs<Tio> B{F, L.sys, L.green, L.n_beta, L.nfull, L.summ};
+  const unsigned grid = (unsigned)(L.n_beta < cap ? L.n_beta : cap);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kBetaNT), 0, st, B);
 }
 
 template <typename Tio, typename Tc, bool REFINE, bool BWD>
@@ -829,11 +1258,27 @@ static hipError_t run_solve(const LaunchSet& L, const void* F, void* X, const vo
   A.refine_tol = L.refine_tol;
   if (L.ev) (void)hipEventRecord(L.ev[0], st);
   if (L.n_p1 > 0) {
-    A.items = L.p1_items;
-    launch_tile<Tio, Tc, REFINE, true, false>(A, L.n_p1, 0, st);
+    if (L.green) {
+      if (L.n_beta > 0) launch_beta<Tio>(L, static_cast<const Tio*>(F), st);
+      if (L.n_last > 0) {
+        A.items = nullptr;
+        launch_tile<Tio, Tc, REFINE, true, false>(A, L.n_last, 0, 1, st);
+      }
+    } else {
+      A.items = L.p1_items;
+      launch_tile<Tio, Tc, REFINE, true, false>(A, L.n_p1, 0, 0, st);
+    }
     if (L.ev) (void)hipEventRecord(L.ev[1], st);
     GridArgs G{L.sys, L.grid_items, L.summ, L.ghost, L.gscr};
-    hipLaunchKernelGGL(k_grid, dim3((unsigned)L.n_grid), dim3(kNT), 0, st, G);
+    const dim3 gg((unsigned)L.n_grid);
+    if (L.max_ntiles <= 256)
+      hipLaunchKernelGGL((k_grid_affine<256, 1>), gg, dim3(256), 0, st, G);
+    else if (L.max_ntiles <= 2048)
+      hipLaunchKernelGGL((k_grid_affine<256, 8>), gg, dim3(256), 0, st, G);
+    else if (L.max_ntiles <= 8192)
+      hipLaunchKernelGGL((k_grid_affine<512, 16>), gg, dim3(512), 0, st, G);
+    else
+      hipLaunchKernelGGL(k_grid, gg, dim3(kNT), 0, st, G);
     if (L.ev) (void)hipEventRecord(L.ev[2], st);
   } else if (L.ev) {
     (void)hipEventRecord(L.ev[1], st);
@@ -843,7 +1288,7 @@ static hipError_t run_solve(const LaunchSet& L, const void* F, void* X, const vo
   // a series of multi-tile systems runs its final pass last-tile-first, so
   // that the tiles the first pass read last are re-read while still cached
   launch_tile<Tio, Tc, REFINE, false, BWD>(A, L.n_fin, (L.n_p1 > 0 && !L.fin_items) ? 1 : 0,
-                                           st);
+                                           0, st);
   if (L.ev) (void)hipEventRecord(L.ev[3], st);
   return hipGetLastError();
 }

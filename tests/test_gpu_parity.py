@@ -135,3 +135,20 @@ def test_repeatable_bitwise():
         X1 = to_host(plan.solve(F))
         X2 = to_host(plan.solve(F))
         assert np.array_equal(X1, X2)
+
+
+@pytest.mark.parametrize("tiles,extra", [(257, 0), (2048, 17), (2049, 3), (8193, 100)])
+@pytest.mark.parametrize("dtype", ["f64", "f32_refine"])
+def test_many_tiles(tiles, extra, dtype):
+    """Every variant of the interface pass across tiles: up to 256 tiles, up to
+    2048, up to 8192 (the single-system workload) and the general one beyond."""
+    tdt = _tdt()
+    n = (tiles - 1) * 8192 + (extra if extra else 8192)   # last tile partial if extra
+    rng = np.random.default_rng(tiles)
+    a, b, c = W.random_system(rng, 1.05, 2.0)
+    F = rng.standard_normal(n)
+    print(f"[case] tiles n={n} dtype={dtype}", flush=True)
+    plan = tdt.Plan(a, b, c, n, dtype)
+    X = to_host(plan.solve(to_dev(F)))
+    ref = oracle.solve(F, a, b, c)
+    assert oracle.rel_err(X, ref) <= tol_f64(a, b, c, n)

@@ -131,3 +131,13 @@ def test_product_path_has_no_oracle_or_fallback():
     finally:
         _lib.LIB_PATH = real
         _lib._lib = saved
+
+
+@pytest.mark.parametrize("t", [(-1.0, 4.0, -1.0), (-0.9, 2.5, -1.1), (0.7, -1.9, 0.45)])
+@pytest.mark.parametrize("L", [1, 2, 7, 64])
+def test_green_rows_match_dense_inverse(t, L):
+    a, b, c = t
+    first, last = tdt.green_rows(a, b, c, L)
+    Ti = np.linalg.inv(dense_T(L, a, b, c))
+    assert np.allclose(first, Ti[0], rtol=1e-13, atol=1e-15)
+    assert np.allclose(last, Ti[-1], rtol=1e-13, atol=1e-15)
