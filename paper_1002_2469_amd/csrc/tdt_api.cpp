@@ -35,6 +35,8 @@ struct tdt_plan_s {
   double* dtab64[2] = {nullptr, nullptr};
   float* dtab32[2] = {nullptr, nullptr};
   double* dgreen[2] = {nullptr, nullptr};   // series with several tiles: [2][kTile]
+  double* dttab[2] = {nullptr, nullptr};    // per tile position table [2][ttab_n]
+  int64_t ttab_n = 0;
   // varlen launch lists
   int2* dp1 = nullptr;
   int2* dfin = nullptr;
@@ -353,6 +355,7 @@ void destroy(tdt_plan_s* p) {
     (void)hipFree(p->dtab64[k]);
     (void)hipFree(p->dtab32[k]);
     (void)hipFree(p->dgreen[k]);
+    (void)hipFree(p->dttab[k]);
   }
   (void)hipFree(p->dp1);
   (void)hipFree(p->dfin);
@@ -414,6 +417,19 @@ tdt_status_t finish_plan(tdt_plan_s* p, const std::vector<double>& tm1,
   }
   p->dominance = dom;
   p->kappa = kap;
+  // interface-pass layout: tiles per thread of the variant the most tiled
+  // system selects (see launch_solve), and the run-interleaved slot counts
+  {
+    int maxp = 1;
+    for (const SysDesc& D : p->hsys[0]) maxp = std::max(maxp, (int)D.ntiles);
+    const int tr = maxp <= 256 ? 1 : (maxp <= 2048 ? 8 : (maxp <= 8192 ? 16 : 1));
+    for (int dir = 0; dir < 2; ++dir)
+      for (SysDesc& D : p->hsys[dir]) {
+        D.tr = tr;
+        D.tq = (D.ntiles + tr - 1) / tr;
+        D.tslots = D.tq * tr;
+      }
+  }
   if (p->varlen) {
     std::vector<int64_t> order((size_t)S);
     std::iota(order.begin(), order.end(), 0);
@@ -428,7 +444,7 @@ tdt_status_t finish_plan(tdt_plan_s* p, const std::vector<double>& tm1,
         for (int dir = 0; dir < 2; ++dir) p->hsys[dir][s].slot0 = (int32_t)slot;
         for (int t = 0; t < nt; ++t) p1.push_back(make_int2((int)s, t));
         grid.push_back((int)s);
-        slot += nt;
+        slot += p->hsys[0][s].tslots;
       }
     }
     for (int64_t s : order)
@@ -440,6 +456,32 @@ tdt_status_t finish_plan(tdt_plan_s* p, const std::vector<double>& tm1,
     tdt_status_t st = dev_upload(&p->dp1, p1.data(), p1.size());
     if (st == TDT_OK) st = dev_upload(&p->dfin, fin.data(), fin.size());
     if (st == TDT_OK) st = dev_upload(&p->dgrid, grid.data(), grid.size());
+    if (st != TDT_OK) return st;
+  }
+  // interface pass across tiles: beta_{t-1} and 1/(1 - Pf_t beta_{t-1}) for
+  // every tile position of every multi-tile system (a series indexes by tile,
+  // a varlen plan by workspace slot), in long double
+  p->ttab_n = p->varlen ? std::max<int64_t>(p->vslots, 1)
+                        : std::max<int64_t>(p->hsys[0][0].tslots, 1);
+  for (int dir = 0; dir < 2; ++dir) {
+    std::vector<double> tt(2 * (size_t)p->ttab_n, 0.0);
+    for (int64_t s = 0; s < S; ++s) {
+      const SysDesc& D = p->hsys[dir][s];
+      if (D.ntiles < 2) continue;
+      const int64_t base = p->varlen ? D.slot0 : 0;
+      ld beta = 0.0L;
+      for (int t = 0; t < D.ntiles; ++t) {
+        const double* K = t + 1 < D.ntiles ? D.tileK : D.ltileK;
+        const ld den = 1.0L - (ld)K[0] * beta;
+        if (!(std::fabs((double)den) > 1e-13)) return TDT_ERR_SINGULAR;
+        const ld iD = 1.0L / den;
+        const int64_t pos = (int64_t)(t % D.tr) * D.tq + t / D.tr;
+        tt[base + pos] = (double)beta;
+        tt[p->ttab_n + base + pos] = (double)iD;
+        beta = (ld)K[3] + (ld)K[1] * beta * (ld)K[2] * iD;
+      }
+    }
+    tdt_status_t st = dev_upload(&p->dttab[dir], tt.data(), tt.size());
     if (st != TDT_OK) return st;
   }
   for (int dir = 0; dir < 2; ++dir) {
@@ -474,6 +516,8 @@ tdt_status_t run(tdt_plan_s* p, int dir, const void* F, void* X, const void* Xfw
   L.iters = p->iters;
   L.max_iter = p->max_iter;
   L.refine_tol = p->refine_tol;
+  L.ttab = p->dttab[dir];
+  L.ttab_n = p->ttab_n;
   L.max_ntiles = 1;
   for (const SysDesc& D : p->hsys[0]) L.max_ntiles = std::max(L.max_ntiles, (int)D.ntiles);
   int64_t slots, fslots;
@@ -501,7 +545,7 @@ tdt_status_t run(tdt_plan_s* p, int dir, const void* F, void* X, const void* Xfw
     L.n_p1 = nt > 1 ? M * nt : 0;
     L.n_grid = nt > 1 ? M : 0;
     L.n_fin = M * nt;
-    slots = nt > 1 ? M * nt : 0;
+    slots = nt > 1 ? M * p->hsys[0][0].tslots : 0;
     fslots = Xfwd ? M * nt : 0;
   }
   if (L.n_fin > 0x7fffffffLL) return TDT_ERR_INVALID_ARG;
@@ -609,7 +653,7 @@ tdt_status_t tdt_plan_reserve(tdt_plan_t p, int64_t M_max) {
     fslots = p->vfslots;
   } else {
     const int64_t nt = p->hsys[0][0].ntiles;
-    slots = nt > 1 ? M_max * nt : 0;
+    slots = nt > 1 ? M_max * p->hsys[0][0].tslots : 0;
     fslots = M_max * nt;
   }
   return ensure_workspace(p, slots, fslots, nullptr);

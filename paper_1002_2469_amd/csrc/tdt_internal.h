@@ -31,7 +31,22 @@ struct SysDesc {
   double tileK[4];       // end values of a full tile (length kTile)
   double ltileK[4];      // last tile, padded form: full-tile values if full,
                          // else (phi_first of its real length, 0, 0, 0)
+  // Workspace slots of a multi-tile system are "run-interleaved" for the
+  // interface pass, whose thread j walks tiles j*tr .. j*tr+tr-1: tile t
+  // lives at slot (t % tr) * tq + t / tr, so that the r-th access of
+  // consecutive threads touches consecutive slots.
+  int32_t tr;            // tiles per thread of the interface pass
+  int32_t tq;            // threads of the interface pass in use, ceil(ntiles / tr)
+  int32_t tslots;        // slots per right-hand side (tq * tr)
+  int32_t pad1;
 };
+
+// Slot of tile t of a system: a varlen plan adds the system's slot0; a
+// series plan uses tslots slots per right-hand side m.
+__host__ __device__ inline int64_t tile_slot(const SysDesc& S, int64_t m, int t, bool varlen) {
+  const int64_t pos = (int64_t)(t % S.tr) * S.tq + t / S.tr;
+  return varlen ? (int64_t)S.slot0 + pos : m * S.tslots + pos;
+}
 
 // Per-system table over the kNT block positions of a tile: beta_{m-1} (the
 // coefficient that carries the next block's first unknown into block m-1's
@@ -62,6 +77,8 @@ struct LaunchSet {
   int64_t n_beta, n_last;
   int nfull;
   int max_ntiles;          // most tiles of any system (selects the interface kernel)
+  const double* ttab;      // per tile position: beta_{t-1}, 1/(1 - Pf beta_{t-1}) ([2][ttab_n])
+  int64_t ttab_n;
   double* summ;
   double* bpart;           // [slot][kNW][2] partial sums of the streaming first pass
   double* ghost;

@@ -558,7 +558,7 @@ __device__ __forceinline__ void prefetch(const TileArgs<Tio>& A, int64_t item,
     P.iD = tb[kTabInvD * kNT + tid];
   }
   if (!SUMMARY) {
-    const int64_t slot = A.items ? (int64_t)S.slot0 + G.I.t : G.I.m * S.ntiles + G.I.t;
+    const int64_t slot = tile_slot(S, G.I.m, G.I.t, A.items != nullptr);
     const int64_t gs = S.ntiles > 1 ? slot : 0;   // the ghost array always has slot 0
     const double xl = A.ghost[2 * gs], xr = A.ghost[2 * gs + 1];
     P.XL = S.ntiles > 1 ? xl : 0.0;
@@ -610,7 +610,7 @@ __global__ __launch_bounds__(kNT, REFINE ? TDT_REFINE_WAVES : kMinWavesPerSimd) 
     const int64_t item = item_of(k);
     const TileGeom G = tile_geom(A.items, A.sys, item, A.last_only);
     const SysDesc S = load_sys(A.sys, G.I.s);
-    const int64_t slot = A.items ? (int64_t)S.slot0 + G.I.t : G.I.m * S.ntiles + G.I.t;
+    const int64_t slot = tile_slot(S, G.I.m, G.I.t, A.items != nullptr);
     const double XLt = P.XL, XRt = P.XR;
     const Tc bp = P.bp, iDf = P.iD;
     const Consts<Tc> K = make_consts<Tc>(S, A.vec64, A.vec32);
@@ -809,8 +809,8 @@ __global__ __launch_bounds__(kBetaNT) void k_beta(BetaArgs<Tio> A) {
   __shared__ double part[2][kBetaNW][2];
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int64_t n = *as_const(&A.sys[0].n);
-  const int nt = *as_const(&A.sys[0].ntiles);
+  const SysDesc S0 = load_sys(A.sys, 0);
+  const int64_t n = S0.n;
   // rows of this lane inside its slice: (j*64 + lane)*V + v
   double g1[kBetaPerLane], gl[kBetaPerLane];
 #pragma unroll
@@ -823,7 +823,7 @@ __global__ __launch_bounds__(kBetaNT) void k_beta(BetaArgs<Tio> A) {
     }
   auto slot_of = [&](int64_t it) {
     const int64_t m = it / A.nfull;
-    return m * nt + (it - m * A.nfull);
+    return tile_slot(S0, m, (int)(it - m * A.nfull), false);
   };
   int par = 0;
   int64_t prev = -1;
@@ -886,6 +886,8 @@ __global__ __launch_bounds__(kBetaNT) void k_beta(BetaArgs<Tio> A) {
 struct GridArgs {
   const SysDesc* __restrict__ sys;
   const int* __restrict__ gitems;     // varlen: system of each workgroup; null for a series
+  const double* __restrict__ ttab;    // [2][tile slot]: beta_{t-1}, 1/(1 - Pf_t beta_{t-1})
+  int64_t ttab_n;                     // entries per row of ttab
   const double* __restrict__ summ;
   double* __restrict__ ghost;
   double* __restrict__ gscr;          // [slot][3] suffix (y_first, phi_first, chi_first)
@@ -905,7 +907,7 @@ __global__ __launch_bounds__(kNT) void k_grid(GridArgs A) {
     s = A.gitems[blockIdx.x];
     slot0 = A.sys[s].slot0;
   } else {
-    slot0 = (int64_t)blockIdx.x * A.sys[0].ntiles;
+    slot0 = (int64_t)blockIdx.x * A.sys[0].tslots;
   }
   const SysDesc& S = A.sys[s];
   const int P = S.ntiles;
@@ -964,61 +966,18 @@ __global__ __launch_bounds__(kNT) void k_grid(GridArgs A) {
 // and tile t's outside values are alpha_{t-1} + beta_{t-1} u_t and u_{t+1}.
 template <int NTG>
 struct GridShared {
-  double m[NTG / 64][4];   // wave aggregates (Moebius matrix)
   double f[NTG / 64][2];   // wave aggregates (left-to-right affine map)
   double b[NTG / 64][2];   // wave aggregates (right-to-left affine map)
 };
 
-// Kogge-Stone exclusive scans over the threads of a workgroup.
-template <int NTG>
-__device__ __forceinline__ void scan_mobius_excl(double (&M)[4], double (*ws)[4]) {
-  // inclusive in-wave prefix of products M_lane * ... * M_0 (applied right to left)
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  double P[4] = {M[0], M[1], M[2], M[3]};
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    double Q[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) Q[k] = __shfl_up(P[k], d, 64);
-    if (lane >= d) {   // P = P * Q
-      const double r0 = P[0] * Q[0] + P[1] * Q[2], r1 = P[0] * Q[1] + P[1] * Q[3];
-      const double r2 = P[2] * Q[0] + P[3] * Q[2], r3 = P[2] * Q[1] + P[3] * Q[3];
-      const double sc = 1.0 / fmax(fmax(fabs(r0), fabs(r1)), fmax(fabs(r2), fabs(r3)));
-      P[0] = r0 * sc; P[1] = r1 * sc; P[2] = r2 * sc; P[3] = r3 * sc;
-    }
-  }
-  if (lane == 63) { ws[w][0] = P[0]; ws[w][1] = P[1]; ws[w][2] = P[2]; ws[w][3] = P[3]; }
-  __syncthreads();
-  // carry from earlier waves: C = W_{w-1} * ... * W_0
-  double C[4] = {1.0, 0.0, 0.0, 1.0};
-  for (int k = 0; k < w; ++k) {
-    const double r0 = ws[k][0] * C[0] + ws[k][1] * C[2], r1 = ws[k][0] * C[1] + ws[k][1] * C[3];
-    const double r2 = ws[k][2] * C[0] + ws[k][3] * C[2], r3 = ws[k][2] * C[1] + ws[k][3] * C[3];
-    const double sc = 1.0 / fmax(fmax(fabs(r0), fabs(r1)), fmax(fabs(r2), fabs(r3)));
-    C[0] = r0 * sc; C[1] = r1 * sc; C[2] = r2 * sc; C[3] = r3 * sc;
-  }
-  // exclusive: previous lane's inclusive prefix times the carry
-  double E[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) E[k] = __shfl_up(P[k], 1, 64);
-  if (lane == 0) { E[0] = 1.0; E[1] = 0.0; E[2] = 0.0; E[3] = 1.0; }
-  M[0] = E[0] * C[0] + E[1] * C[2];
-  M[1] = E[0] * C[1] + E[1] * C[3];
-  M[2] = E[2] * C[0] + E[3] * C[2];
-  M[3] = E[2] * C[1] + E[3] * C[3];
-}
-
-// Exclusive left-to-right scan of affine maps x -> A x + g; returns the value
-// entering this thread given x_in for thread 0.
+// Exclusive left-to-right scan of affine maps x -> A x + g over the threads
+// of a workgroup; returns the value entering this thread given x_in for
+// thread 0.
 template <int NTG>
 __device__ __forceinline__ double scan_affine_fwd(double A, double g, double x_in,
                                                   double (*ws)[2]) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const double Alo = __shfl_up(A, d, 64), glo = __shfl_up(g, d, 64);
-    if (lane >= d) { g = A * glo + g; A = A * Alo; }
-  }
+  wave_scan_affine_fwd(A, g);
   if (lane == 63) { ws[w][0] = A; ws[w][1] = g; }
   __syncthreads();
   double c = x_in;
@@ -1035,11 +994,7 @@ __device__ __forceinline__ double scan_affine_bwd(double C, double h, double x_i
                                                   double (*ws)[2]) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   constexpr int NW = NTG / 64;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const double Chi = __shfl_down(C, d, 64), hhi = __shfl_down(h, d, 64);
-    if (lane + d < 64) { h = C * hhi + h; C = C * Chi; }
-  }
+  wave_scan_affine_bwd(C, h);
   if (lane == 0) { ws[w][0] = C; ws[w][1] = h; }
   __syncthreads();
   double e = x_in;
@@ -1059,21 +1014,24 @@ __global__ __launch_bounds__(NTG) void k_grid_affine(GridArgs A) {
     s = as_const(A.gitems)[blockIdx.x];
     slot0 = *as_const(&A.sys[s].slot0);
   } else {
-    slot0 = (int64_t)blockIdx.x * *as_const(&A.sys[0].ntiles);
+    slot0 = (int64_t)blockIdx.x * *as_const(&A.sys[0].tslots);
   }
   const SysDesc S = load_sys(A.sys, s);
   const int P = S.ntiles;
+  const int tq = S.tq;
   const double* summ = A.summ + 2 * slot0;
   double* ghost = A.ghost + 2 * slot0;
   const int ta = tid * R;
-  // this thread's tiles: ta .. ta+R-1 (those >= P are empty).  Full tiles
-  // share (Pf, Pl, Cf, Cl); the last one has its own.
+  // this thread's tiles: ta .. ta+R-1 (those >= P are empty), tile ta+r at
+  // slot r*tq + tid (run-interleaved).  Full tiles share (Pf, Pl, Cf, Cl);
+  // the last one has its own.
+  auto pos = [&](int r) { return ta + r < P ? r * tq + tid : 0; };
   double yf[R], yl[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int t = ta + r;
-    const int tc = t < P ? t : 0;
-    const double u = summ[2 * tc], v = summ[2 * tc + 1];
+    const int pc = pos(r);
+    const double u = summ[2 * pc], v = summ[2 * pc + 1];
     yf[r] = t < P ? u : 0.0;
     yl[r] = t < P ? v : 0.0;
   }
@@ -1084,33 +1042,27 @@ __global__ __launch_bounds__(NTG) void k_grid_affine(GridArgs A) {
     cf = real ? (last ? S.ltileK[2] : S.tileK[2]) : 0.0;
     cl = real ? (last ? S.ltileK[3] : S.tileK[3]) : 0.0;
   };
-  // 1. beta_{t-1} at every tile: Moebius maps composed over the run, scanned
-  double M[4] = {1.0, 0.0, 0.0, 1.0};
-#pragma unroll
-  for (int r = 0; r < R; ++r) {   // M = M_t * M
-    double pf, pl, cf, cl;
-    kofs(ta + r, pf, pl, cf, cl);
-    const double m0 = pl * cf - cl * pf, m1 = cl, m2 = -pf, m3 = 1.0;
-    const double r0 = m0 * M[0] + m1 * M[2], r1 = m0 * M[1] + m1 * M[3];
-    const double r2 = m2 * M[0] + m3 * M[2], r3 = m2 * M[1] + m3 * M[3];
-    const double sc = 1.0 / fmax(fmax(fabs(r0), fabs(r1)), fmax(fabs(r2), fabs(r3)));
-    M[0] = r0 * sc; M[1] = r1 * sc; M[2] = r2 * sc; M[3] = r3 * sc;
-  }
-  scan_mobius_excl<NTG>(M, sh.m);
-  double beta = M[1] / M[3];   // beta_{ta-1}
+  // 1. beta_{t-1} and 1/(1 - Pf_t beta_{t-1}) at every tile, from the plan's
+  //    table (they depend on T only)
+  const int64_t tb0 = A.gitems ? slot0 : 0;
   double bp[R], iD[R];
   double Af = 1.0, gf = 0.0;   // composite left-to-right map of the run
 #pragma unroll
   for (int r = 0; r < R; ++r) {
+    const int t = ta + r;
+    const int64_t tc = tb0 + pos(r);
+    const double b0 = A.ttab[tc], i0 = A.ttab[A.ttab_n + tc];
+    bp[r] = t < P ? b0 : 0.0;
+    iD[r] = t < P ? i0 : 1.0;
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
     double pf, pl, cf, cl;
     kofs(ta + r, pf, pl, cf, cl);
-    bp[r] = beta;
-    iD[r] = 1.0 / (1.0 - pf * beta);
     const double At = pl * iD[r];
-    const double gt = yl[r] + At * beta * yf[r];
+    const double gt = yl[r] + At * bp[r] * yf[r];
     gf = At * gf + gt;
     Af = At * Af;
-    beta = cl + pl * beta * cf * iD[r];
   }
   // 2. alpha (left to right)
   double alpha = scan_affine_fwd<NTG>(Af, gf, 0.0, sh.f);   // alpha_{ta-1}
@@ -1142,8 +1094,9 @@ __global__ __launch_bounds__(NTG) void k_grid_affine(GridArgs A) {
     const double un = u;                 // u_{t+1}
     u = cf * iD[r] * u + h[r];           // u_t
     if (t < P) {
-      ghost[2 * t] = ap[r] + bp[r] * u;
-      ghost[2 * t + 1] = un;
+      const int pc = pos(r);
+      ghost[2 * pc] = ap[r] + bp[r] * u;
+      ghost[2 * pc + 1] = un;
     }
   }
 }
@@ -1269,7 +1222,7 @@ static hipError_t run_solve(const LaunchSet& L, const void* F, void* X, const vo
       launch_tile<Tio, Tc, REFINE, true, false>(A, L.n_p1, 0, 0, st);
     }
     if (L.ev) (void)hipEventRecord(L.ev[1], st);
-    GridArgs G{L.sys, L.grid_items, L.summ, L.ghost, L.gscr};
+    GridArgs G{L.sys, L.grid_items, L.ttab, L.ttab_n, L.summ, L.ghost, L.gscr};
     const dim3 gg((unsigned)L.n_grid);
     if (L.max_ntiles <= 256)
       hipLaunchKernelGGL((k_grid_affine<256, 1>), gg, dim3(256), 0, st, G);
