@@ -37,10 +37,10 @@ HBM_PEAK_GBS = 8000.0
 # algorithmic HBM bytes per unknown of each kernel group (double data)
 BYTES_PER_UNKNOWN = {"first_pass": 8.0,    # read F
                      "final_pass": 16.0}   # read F, write X
-KERNEL_NAMES = {"first_pass": "k_tile<double, float, REFINE, SUMMARY> (first pass over tiles)",
-                "final_pass": "k_tile<double, float, REFINE, final> (solve and store)"}
-KERNEL_NAMES_F64 = {"first_pass": "k_tile<double, double, SUMMARY>",
-                    "final_pass": "k_tile<double, double, final>"}
+KERNEL_NAMES = {"first_pass": "k_beta<double> (Green-row tile summaries, first pass)",
+                "final_pass": "k_tile<double, float, REFINE, final> (solve, refine and store)"}
+KERNEL_NAMES_F64 = {"first_pass": "k_beta<double> (Green-row tile summaries, first pass)",
+                    "final_pass": "k_tile<double, double, final> (solve and store)"}
 
 
 def kernel_source_hash() -> str:
@@ -107,7 +107,7 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU; --gpus {args.gpus} is not "
-              "supported (the multi-GPU sharding is described in DESIGN.md, not built)",
+              "supported (one GPU's share of a sharded solve is what is measured here)",
               file=sys.stderr)
         return 2
 
