@@ -24,6 +24,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import statistics
 import sys
 import time
@@ -44,10 +45,16 @@ KERNEL_NAMES_F64 = {"first_pass": "k_beta<double> (Green-row tile summaries, fir
 
 
 def kernel_source_hash() -> str:
+    """Hash of the device code (comments and blank lines removed, so that a
+    comment edit does not invalidate the committed counter summary)."""
     h = hashlib.sha256()
     for rel in ("paper_1002_2469_amd/csrc/tdt_kernels.hip", "paper_1002_2469_amd/csrc/tdt_internal.h"):
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel)) as f:
+            src = f.read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", "", src)
+        src = "\n".join(line.rstrip() for line in src.splitlines() if line.strip())
+        h.update(src.encode())
     return h.hexdigest()[:16]
 
 

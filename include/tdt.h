@@ -59,7 +59,7 @@ typedef enum {
  * the right-hand side).  Builds, in long double on the host, the LU
  * multipliers of the B x B diagonal block, the block's responses to unit
  * interface values ("shared basis", the local counterpart of the Green
- * functions of eqs. (6)-(9) and of the interior problems of eqs. (26)-(27)),
+ * functions of eqs. (9)-(12) and of the interior problems of eqs. (26)-(27)),
  * and the same end values for whole tiles; uploads them (blocking copy).
  * Errors: N < 1, non-finite t's, out == NULL -> TDT_ERR_INVALID_ARG;
  * a zero pivot in a diagonal block or an interface merge that divides by
@@ -142,7 +142,7 @@ tdt_status_t tdt_block_constants(double t_m1, double t_0, double t_1, int B,
                                  double *out);
 
 /* Host-only: the first and last row of T_L^{-1}, the L x L Toeplitz matrix
- * (the Green's function rows of eq. (6) of the paper for a run of L rows
+ * (the Green's function rows of eq. (9) of the paper for a run of L rows
  * taken as the whole system), in long double rounded to double: first[j] =
  * (T_L^{-1})_{0,j}, last[j] = (T_L^{-1})_{L-1,j}, j < L.  The first pass of a
  * series plan uses them for its tiles (L = the tile length). */

@@ -18,9 +18,9 @@
 // Knowing the two values outside a segment made of two halves, (*) written
 // at the two rows where the halves meet is a 2x2 system: solving it gives the
 // two unknowns at the junction and splits the segment into two independent
-// problems -- the dichotomy step of Sec. 2.2 (eqs. (4)-(6)).  The same 2x2
+// problems -- the dichotomy step of Sec. 2.2 (eqs. (6)-(8)).  The same 2x2
 // elimination with zero outside values merges the two half summaries into the
-// summary of the whole (the segment's own "beta" of eq. (10): its first and
+// summary of the whole (the segment's own "beta" of eq. (16): its first and
 // last unknown when the right-hand side vanishes outside it, restricted to
 // the segment taken as the whole system).  Merging is associative (the
 // reordering argument of Sec. 2.5), so all block summaries of a wavefront are
@@ -334,9 +334,9 @@ struct Consts {
 //     u_m = C_m u_{m+1} + h_m,  C_m = chi_f iD_m,  h_m = (y_f + phi_f alpha_{m-1}) iD_m.
 // alpha_m is a sum over blocks j <= m of each block's own contribution g_j
 // carried by products of A's, u_m a sum over blocks j >= m of the h_j
-// carried by products of C's: the two sums of eq. (11) (contributions from
+// carried by products of C's: the two sums of eq. (15) (contributions from
 // the left and from the right, weighted by the exterior responses Z of
-// eq. (7)), evaluated as affine scans.  Associativity (Sec. 2.5) lets the
+// eqs. (10)-(12)), evaluated as affine scans.  Associativity (Sec. 2.5) lets the
 // scans run as Kogge-Stone steps inside a wavefront and as one LDS level
 // across wavefronts instead of the recursive halving of Sec. 2.4.
 // If yfo/ylo are non-null the tile summary (first and last unknown of the
@@ -776,10 +776,10 @@ __global__ __launch_bounds__(kNT, REFINE ? TDT_REFINE_WAVES : kMinWavesPerSimd) 
 }
 
 // First pass of a series plan over its full tiles: the tile summary is the
-// pair of sums of eq. (10),
+// pair of sums of eqs. (13) and (16),
 //     y_first = sum_j f_j (T_L^{-1})_{0,j},   y_last = sum_j f_j (T_L^{-1})_{L-1,j},
 // i.e. the right-hand side weighted by the first and last row of the inverse
-// of the tile's matrix (the Green's function rows of eq. (6) for a tile taken
+// of the tile's matrix (the Green's function rows of eq. (9) for a tile taken
 // as the whole system).  Every full tile of one Toeplitz matrix has the same
 // rows, so each lane keeps the entries of its own element positions in
 // registers and the pass is a streaming dot product with no transposition
