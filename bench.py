@@ -1,22 +1,28 @@
 #!/usr/bin/env python3
 """Throughput of the Toeplitz tridiagonal dichotomy solve on one MI355X.
 
-Workload: the paper's single-system case, one Toeplitz tridiagonal system of
-N = 2**26 unknowns, T = tridiag{-0.9, 2.5, -1.1} (dominance ratio 1.25),
-F ~ N(0, 1) from seed 0, resident in HBM before the timed region.  A step is
-one full solve T X = F (first pass over tiles, interface pass, final pass).
-The headline path is float sweeps with double residual refinement
-('f32_refine', data in and out in double); the all-double path ('f64') is
-timed the same way beside it.
+Default workload (`single_large`): the paper's single-system case, one
+Toeplitz tridiagonal system of N = 2**26 unknowns, T = tridiag{-0.9, 2.5, -1.1}
+(dominance ratio 1.25), F ~ N(0, 1) from seed 0, resident in HBM before the
+timed region.  A step is one full solve T X = F (first pass over tiles,
+interface pass, final pass).  The headline path is float sweeps with double
+residual refinement ('f32_refine', data in and out in double); the all-double
+path ('f64') is timed the same way beside it.
+
+Other workloads (`--workload`): `series` (8192 right-hand sides of N = 8192
+sharing T = tridiag{-1, 3, -1}), `sov` (2048 separation-of-variables systems,
+N_k log-uniform in [256, 65536], each with its own t_0; one step is a replay
+of the solve captured in a hipGraph) and `diff` (1024 systems of N = 16384
+with their own T; a step is the forward solve plus the adjoint backward pass).
 
 Prints one JSON line.  `roofline` is for the kernel with the longest average
 duration in the headline path, from HIP events recorded on the solve stream
 around each kernel during the timed steps; its `traffic` comes from the
 committed rocprofv3 counter summary (profiles/) when it was taken on the
-current kernel source, else null.  `cpu_baseline` is the CPU oracle (plain
-Thomas, one thread: the single system is a sequential recurrence) timed on
-this host on the same system; the same oracle output gives the error of both
-GPU results.
+current device code, else null.  `cpu_baseline` is the CPU oracle (plain
+Thomas; one thread for a single system, all host threads for batches) timed
+on this host on the same inputs; the same oracle output gives the error of
+every GPU result.
 """
 from __future__ import annotations
 
@@ -35,13 +41,7 @@ if ROOT not in sys.path:
 
 METRIC = "unknowns/s + HBM GB/s (% peak): FP32+refine vs FP64 solve at rel err ≤1e-12"
 HBM_PEAK_GBS = 8000.0
-# algorithmic HBM bytes per unknown of each kernel group (double data)
-BYTES_PER_UNKNOWN = {"first_pass": 8.0,    # read F
-                     "final_pass": 16.0}   # read F, write X
-KERNEL_NAMES = {"first_pass": "k_beta<double> (Green-row tile summaries, first pass)",
-                "final_pass": "k_tile<double, float, REFINE, final> (solve, refine and store)"}
-KERNEL_NAMES_F64 = {"first_pass": "k_beta<double> (Green-row tile summaries, first pass)",
-                    "final_pass": "k_tile<double, double, final> (solve and store)"}
+WORKLOADS = ("single_large", "series", "sov", "diff")
 
 
 def kernel_source_hash() -> str:
@@ -58,10 +58,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def committed_traffic(kernel_key: str, mode: str):
+def committed_traffic(workload: str, kernel_key: str, mode: str):
     """HBM bytes per launch from the committed counter summary, if it was
-    taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "traffic_single_large.json")
+    taken on the current device code."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
     try:
@@ -74,31 +74,156 @@ def committed_traffic(kernel_key: str, mode: str):
         return None
 
 
+# --------------------------------------------------------------------------
+# workloads: inputs, plans, per-kernel algorithmic bytes
+# --------------------------------------------------------------------------
+
+def load_workload(name: str, args):
+    from paper_1002_2469_amd import workloads as W
+    if name == "single_large":
+        d = W.single_large(seed=0, n=args.n)
+        d.update(kind="series", units=d["N"],
+                 desc=f"single_large: one Toeplitz tridiagonal system, N={d['N']}, "
+                      f"t=(-0.9, 2.5, -1.1), F~N(0,1) seed 0, double in/out")
+    elif name == "series":
+        d = W.series(seed=0)
+        d.update(kind="series", units=d["N"] * d["M"],
+                 desc=f"series: M={d['M']} right-hand sides of N={d['N']} sharing "
+                      f"t=(-1, 3, -1), F~U[-1,1] seed 0, [M][N] double in/out")
+    elif name == "sov":
+        d = W.sov_batch(seed=0)
+        d.update(kind="varlen", units=int(d["offsets"][-1]), graph=True,
+                 desc=f"sov: S={d['S']} separation-of-variables systems, N_k log-uniform "
+                      f"in [256, 65536] (sum {int(d['offsets'][-1])}), t_+-1=1, own t_0, "
+                      f"F~N(0,1) seed 0, packed, solve replayed from a hipGraph")
+    elif name == "diff":
+        d = W.diff_batch(seed=0)
+        d.update(kind="varlen", units=int(d["offsets"][-1]), adjoint=True,
+                 desc=f"diff: S={d['S']} systems of N={d['N']}, own t's, forward solve "
+                      f"plus adjoint backward (gF, dL/dt), F,W~N(0,1) seed 0")
+    else:
+        raise ValueError(name)
+    return d
+
+
+def make_plan(tdt, d, mode):
+    if d["kind"] == "series":
+        return tdt.Plan(d["t_m1"], d["t_0"], d["t_1"], d["N"], mode)
+    return tdt.VarlenPlan(d["offsets"], d["t_m1"], d["t_0"], d["t_1"], mode)
+
+
+def tile_counts(d):
+    """Unknowns that go through the first pass (systems of more than one
+    tile) and through the final pass (all)."""
+    tile = 8192
+    if d["kind"] == "series":
+        multi = d["N"] > tile
+        return (d["N"] * d["M"] if multi else 0), d["N"] * d["M"]
+    sizes = d["offsets"][1:] - d["offsets"][:-1]
+    return int(sizes[sizes > tile].sum()), int(sizes.sum())
+
+
 def run_mode(tdt, d, F, X, mode, steps, warmup, torch):
-    plan = tdt.Plan(d["t_m1"], d["t_0"], d["t_1"], d["N"], mode)
-    plan.reserve(1)
-    for _ in range(warmup):
+    plan = make_plan(tdt, d, mode)
+    plan.reserve(d.get("M", 1))
+    adj = d.get("adjoint", False)
+    gX = gF = gt = None
+    if adj:
+        gX = torch.from_numpy(d["W"].reshape(-1)).to(F.device)
+        gF = torch.empty_like(gX)
+        gt = torch.empty((d["S"], 3), dtype=torch.float64, device=F.device)
+
+    def step():
         plan.solve(F, X)
+        if adj:
+            plan.backward(gX, X, gF, gt)
+
+    for _ in range(warmup):
+        step()
     torch.cuda.synchronize()
+
+    # kernel-group times: eager solves with HIP events around each kernel
     plan.info()                     # clears the refinement counter
-    plan.profile(True)
+    kern = {}
+    for direction in (("fwd", "bwd") if adj else ("fwd",)):
+        plan.profile(True)
+        for _ in range(steps):
+            if direction == "fwd":
+                plan.solve(F, X)
+            else:
+                plan.backward(gX, X, gF, gt)
+        torch.cuda.synchronize()
+        prof = plan.profile_read()
+        plan.profile(False)
+        n = max(prof["solves"], 1)
+        pre = "" if direction == "fwd" else "bwd_"
+        kern[pre + "first_pass"] = prof["first_pass_ms"] / n
+        kern[pre + "interface"] = prof["interface_ms"] / n
+        kern[pre + "final_pass"] = prof["final_ms"] / n
+    info = plan.info()
+
+    # step time: eager, or replays of a captured graph
+    graph = None
+    if d.get("graph"):
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            step()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step()
+        for _ in range(warmup):
+            graph.replay()
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     start.record()
     for _ in range(steps):
-        plan.solve(F, X)
+        if graph is not None:
+            graph.replay()
+        else:
+            step()
     stop.record()
     torch.cuda.synchronize()
     ms = start.elapsed_time(stop) / steps
-    prof = plan.profile_read()
-    plan.profile(False)
-    info = plan.info()
-    n = prof["solves"]
-    kern = {"first_pass": prof["first_pass_ms"] / n, "interface": prof["interface_ms"] / n,
-            "final_pass": prof["final_ms"] / n}
+    out = dict(ms=ms, kernels_ms=kern, refine_iters=info["refine_iters"],
+               X=X.cpu().numpy().reshape(-1))
+    if adj:
+        out["gF"] = gF.cpu().numpy().reshape(-1)
+        out["gt"] = gt.cpu().numpy()
+    del graph
     plan.close()
-    return dict(ms=ms, kernels_ms=kern, refine_iters=info["refine_iters"], X=X.cpu().numpy())
+    return out
+
+
+def cpu_leg(d, budget_s=12.0):
+    """Time the oracle on this host (same inputs) and return its outputs."""
+    import numpy as np
+    import oracle
+    single = d["kind"] == "series" and d["M"] == 1
+    nthreads = 1 if single else 0
+    threads = oracle.threads(1 if single else 0)
+    times, Xo, gFo, gto = [], None, None, None
+    t_budget = time.perf_counter()
+    while len(times) < 25 and (time.perf_counter() - t_budget < budget_s or len(times) < 3):
+        t0 = time.perf_counter()
+        if d["kind"] == "series":
+            Xo = oracle.solve(d["F"], d["t_m1"], d["t_0"], d["t_1"], nthreads=nthreads)
+        else:
+            Xo = oracle.solve_varlen(d["F"].reshape(-1), d["offsets"], d["t_m1"], d["t_0"],
+                                     d["t_1"], nthreads=nthreads)
+        if d.get("adjoint"):
+            gFo, gto = oracle.adjoint_varlen(d["W"].reshape(-1), Xo, d["offsets"], d["t_m1"],
+                                             d["t_0"], d["t_1"], nthreads=nthreads)
+        times.append(time.perf_counter() - t0)
+    med = statistics.median(times)
+    what = "forward solve + adjoint" if d.get("adjoint") else "solve"
+    cpu = {"value": d["units"] / med, "unit": "unknowns/s", "cores": threads, "kind": "oracle",
+           "sample": f"the whole workload ({d['units']} unknowns, {what}), plain Thomas in "
+                     f"double, {threads} thread(s), median of {len(times)} runs of {med:.3f} s"}
+    return cpu, np.asarray(Xo).reshape(-1), gFo, gto
 
 
 def main() -> int:
@@ -106,15 +231,16 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--n", type=int, default=1 << 26, help="system order (default 2**26)")
+    ap.add_argument("--workload", default="single_large", choices=WORKLOADS)
+    ap.add_argument("--n", type=int, default=1 << 26, help="single_large: system order")
     ap.add_argument("--modes", default="f32_refine,f64")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain device copy of F (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on exactly one GPU; --gpus {args.gpus} is not "
-              "supported (one GPU's share of a sharded solve is what is measured here)",
+        print(f"bench.py: runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              "(one GPU's share of a sharded solve is what is measured here)",
               file=sys.stderr)
         return 2
 
@@ -122,17 +248,16 @@ def main() -> int:
     import torch
 
     import paper_1002_2469_amd as tdt
-    from paper_1002_2469_amd import workloads as W
 
-    d = W.single_large(seed=0, n=args.n)
-    F = torch.from_numpy(d["F"]).to("cuda:0")
+    d = load_workload(args.workload, args)
+    F = torch.from_numpy(np.ascontiguousarray(d["F"]).reshape(-1)).to("cuda:0")
     X = torch.empty_like(F)
     torch.cuda.synchronize()
     modes = [m for m in args.modes.split(",") if m]
     res = {}
     for mode in modes:
         res[mode] = run_mode(tdt, d, F, X, mode, args.steps, args.warmup, torch)
-        print(f"[bench] {mode}: {res[mode]['ms']:.4f} ms/step  kernels(ms) "
+        print(f"[bench] {args.workload} {mode}: {res[mode]['ms']:.4f} ms/step  kernels(ms) "
               f"{json.dumps({k: round(v, 5) for k, v in res[mode]['kernels_ms'].items()})}",
               file=sys.stderr, flush=True)
 
@@ -143,44 +268,58 @@ def main() -> int:
         torch.cuda.synchronize()
         del Y
 
-    N = d["N"]
+    U = d["units"]
     head = modes[0]
+    n_first, n_final = tile_counts(d)
+    # algorithmic HBM bytes per launch of each kernel group (double data)
+    per_launch = {"first_pass": 8.0 * n_first, "final_pass": 16.0 * n_final,
+                  "bwd_first_pass": 8.0 * n_first, "bwd_final_pass": 24.0 * n_final}
+    names = {"first_pass": ("k_beta<double> (Green-row tile summaries, first pass)"
+                            if d["kind"] == "series" else
+                            "k_tile<double, *, SUMMARY> (tile summaries, first pass)"),
+             "final_pass": ("k_tile<double, float, REFINE, final> (solve, refine and store)"
+                            if head == "f32_refine" else "k_tile<double, double, final> (solve and store)"),
+             "bwd_first_pass": "k_tile<double, *, SUMMARY> on T^T (adjoint first pass)",
+             "bwd_final_pass": "k_tile<..., BWD> (adjoint solve, store gF, dL/dt partial sums)"}
 
-    # CPU oracle leg: time it on this host and use its output for the errors
     cpu = None
     errs = {}
     if not args.no_cpu:
+        cpu, Xo, gFo, gto = cpu_leg(d)
         import oracle
-        threads = oracle.threads(1)
-        times = []
-        Xo = None
-        t_budget = time.perf_counter()
-        while len(times) < 25 and (time.perf_counter() - t_budget < 12.0 or len(times) < 3):
-            t0 = time.perf_counter()
-            Xo = oracle.solve(d["F"], d["t_m1"], d["t_0"], d["t_1"], nthreads=1)
-            times.append(time.perf_counter() - t0)
-        med = statistics.median(times)
-        cpu = {"value": N / med, "unit": "unknowns/s", "cores": threads, "kind": "oracle",
-               "sample": f"the whole workload (one system, N={N}), plain Thomas in double, "
-                         f"1 thread, median of {len(times)} runs of {med:.3f} s"}
         for mode in modes:
-            errs[mode] = oracle.rel_err(res[mode]["X"], Xo)
+            if d["kind"] == "series":
+                e = float(np.max(oracle.rel_err_rows(res[mode]["X"].reshape(d["M"], d["N"]),
+                                                     Xo.reshape(d["M"], d["N"]))))
+            else:
+                e = float(np.max(oracle.rel_err_rows(res[mode]["X"], Xo, d["offsets"])))
+            errs[mode] = {"X": e}
+            if gFo is not None:
+                errs[mode]["gF"] = float(np.max(oracle.rel_err_rows(res[mode]["gF"], gFo,
+                                                                    d["offsets"])))
+                errs[mode]["gt"] = float(np.max(np.abs(res[mode]["gt"] - gto))
+                                         / np.max(np.abs(gto)))
+
+    def err_of(mode):
+        e = errs.get(mode)
+        if e is None:
+            return None
+        return e["X"] if len(e) == 1 else e
 
     def path_record(mode):
         r = res[mode]
-        return {"value": N / (r["ms"] * 1e-3), "unit": "unknowns/s", "ms_per_step": r["ms"],
-                "step_gbs_at_16B": 16.0 * N / (r["ms"] * 1e-3) / 1e9,
+        return {"value": U / (r["ms"] * 1e-3), "unit": "unknowns/s", "ms_per_step": r["ms"],
                 "kernels_ms": {k: round(v, 6) for k, v in r["kernels_ms"].items()},
-                "rel_err_vs_oracle": errs.get(mode), "refine_iters": r["refine_iters"]}
+                "rel_err_vs_oracle": err_of(mode), "refine_iters": r["refine_iters"]}
 
     hk = res[head]["kernels_ms"]
-    dom = "final_pass" if hk["final_pass"] >= hk["first_pass"] else "first_pass"
-    achieved = BYTES_PER_UNKNOWN[dom] * N / (hk[dom] * 1e-3) / 1e9
-    traffic = committed_traffic(dom, head)
-    names = KERNEL_NAMES if head == "f32_refine" else KERNEL_NAMES_F64
+    dom = max((k for k in per_launch if hk.get(k, 0) > 0 and per_launch[k] > 0),
+              key=lambda k: hk[k])
+    achieved = per_launch[dom] / (hk[dom] * 1e-3) / 1e9
+    traffic = committed_traffic(args.workload, dom, head)
     line = {
         "metric": METRIC,
-        "value": N / (res[head]["ms"] * 1e-3),
+        "value": U / (res[head]["ms"] * 1e-3),
         "unit": "unknowns/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -190,15 +329,13 @@ def main() -> int:
         "scaling": "strong",
         "vs_baseline": None,
         "dtype": "f32 sweeps + f64 residual/update" if head == "f32_refine" else head,
-        "data": "synthetic (seeded normal right-hand side; no dataset involved)",
-        "config": {"workload": f"single_large: one Toeplitz tridiagonal system, N={N}, "
-                               f"t=(-0.9, 2.5, -1.1), F~N(0,1) seed 0, double in/out",
-                   "N": N, "M": 1, "path": head},
-        "rel_err_vs_oracle": errs.get(head),
+        "data": "synthetic (seeded right-hand sides; no dataset involved)",
+        "config": {"workload": d["desc"], "unknowns": U, "path": head},
+        "rel_err_vs_oracle": err_of(head),
         "roofline": {"bound": "hbm", "kernel": names[dom], "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
-                     "bytes_per_unknown": BYTES_PER_UNKNOWN[dom], "avg_ms": hk[dom]},
+                     "algorithmic_bytes_per_launch": per_launch[dom], "avg_ms": hk[dom]},
         "paths": {m: path_record(m) for m in modes},
         "cpu_baseline": cpu,
     }

@@ -447,8 +447,12 @@ tdt_status_t finish_plan(tdt_plan_s* p, const std::vector<double>& tm1,
         slot += p->hsys[0][s].tslots;
       }
     }
+    // final pass: the multi-tile systems' tiles in the reverse of the first
+    // pass's order (the most recently read, still cached, come first), then
+    // the one-tile systems largest first
+    fin.assign(p1.rbegin(), p1.rend());
     for (int64_t s : order)
-      for (int t = 0; t < p->hsys[0][s].ntiles; ++t) fin.push_back(make_int2((int)s, t));
+      if (p->hsys[0][s].ntiles == 1) fin.push_back(make_int2((int)s, 0));
     p->vslots = slot;
     p->n_p1 = (int64_t)p1.size();
     p->n_fin = (int64_t)fin.size();

@@ -35,6 +35,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "tdt_internal.h"
 
 namespace tdt {
@@ -61,6 +63,17 @@ __device__ __forceinline__ cptr<T> as_const(const T* p) {
 __device__ __forceinline__ int opaque(int v) {
   asm volatile("" : "+v"(v));
   return v;
+}
+
+// The same for a pointer to per-plan constants: loads through the returned
+// pointer cannot be merged with, or hoisted above, earlier loads of the same
+// data, so each phase of a solve re-reads (with cheap scalar loads) the
+// constants it uses instead of keeping all of them live in SGPRs.
+template <typename T>
+__device__ __forceinline__ cptr<T> fresh(cptr<T> p) {
+  uint64_t v = (uint64_t)(uintptr_t)p;
+  asm volatile("" : "+s"(v));
+  return (cptr<T>)(uintptr_t)v;
 }
 
 // Raw buffer accesses: a wave-uniform resource (base, size in bytes) held in
@@ -237,6 +250,13 @@ __device__ __forceinline__ double readlane(double v, int l) {
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 // Maximum over the 64 lanes (all lanes receive it).
+__device__ __forceinline__ float wave_max(float v) {
+  v = fmaxf(v, dpp<0x111>(v, v));
+  v = fmaxf(v, dpp<0x112>(v, v));
+  v = fmaxf(v, dpp<0x114>(v, v));
+  v = fmaxf(v, dpp<0x118>(v, v));
+  return fmaxf(fmaxf(readlane(v, 15), readlane(v, 31)), fmaxf(readlane(v, 47), readlane(v, 63)));
+}
 __device__ __forceinline__ double wave_max(double v) {
   v = fmax(v, dpp<0x111>(v, v));
   v = fmax(v, dpp<0x112>(v, v));
@@ -342,30 +362,35 @@ struct Consts {
 // If yfo/ylo are non-null the tile summary (first and last unknown of the
 // tile with zero outside values) is written by the owning threads and the
 // correction is skipped.  Two workgroup barriers inside.
-template <typename Tc>
-__device__ __forceinline__ void tile_solve(Tc (&q)[kB], int len, Tc XLt, Tc XRt,
+// FULL: every block of the tile has kB rows (the caller has checked it for
+// the whole workgroup), which removes the tail handling from the code.
+template <typename Tc, bool FULL>
+__device__ __forceinline__ void tile_solve(Tc (&q)[kB], int len_in, Tc XLt, Tc XRt,
                                            const Consts<Tc>& K, Tc bp, Tc iDf,
                                            Tc (*fw)[2], Tc (*bw)[2], double* yfo,
                                            double* ylo) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int len = FULL ? kB : len_in;
   const bool tail = len > 0 && len < kB;
-  const bool wave_tail = __ballot(tail) != 0;
+  const bool wave_tail = FULL ? false : __ballot(tail) != 0;
   // local Thomas sweep with the shared multipliers (T_B^{-1} q); the forward
   // step d_i = q_i/u_i - (t_-1/u_i) d_{i-1} keeps one dependent FMA per row
+  const cptr<Tc> iu = fresh(K.iu), aiu = fresh(K.aiu);
 #pragma unroll
-  for (int i = 0; i < kB; ++i) q[i] *= K.iu[i];
+  for (int i = 0; i < kB; ++i) q[i] *= iu[i];
   if (!wave_tail) {
 #pragma unroll
-    for (int i = 1; i < kB; ++i) q[i] -= K.aiu[i] * q[i - 1];
+    for (int i = 1; i < kB; ++i) q[i] -= aiu[i] * q[i - 1];
   } else {
 #pragma unroll
     for (int i = 1; i < kB; ++i) {
-      const Tc d = q[i] - K.aiu[i] * q[i - 1];
+      const Tc d = q[i] - aiu[i] * q[i - 1];
       q[i] = i < len ? d : Tc(0);
     }
   }
+  const cptr<Tc> cpb = fresh(K.cp);
 #pragma unroll
-  for (int i = kB - 2; i >= 0; --i) q[i] -= K.cp[i] * q[i + 1];
+  for (int i = kB - 2; i >= 0; --i) q[i] -= cpb[i] * q[i + 1];
 
   // this block's coefficients
   Tc pf = K.pf, pl = K.pl, cf = K.cf, iD = iDf, yf = q[0], yl = q[kB - 1];
@@ -412,8 +437,9 @@ __device__ __forceinline__ void tile_solve(Tc (&q)[kB], int len, Tc XLt, Tc XRt,
   const Tc xl = alpha_prev + bp * u;   // last unknown of the previous block
   const Tc xr = u_next;                // first unknown of the next block
   if (len == kB) {
+    const cptr<Tc> phi = fresh(K.phi), chi = fresh(K.chi);
 #pragma unroll
-    for (int i = 0; i < kB; ++i) q[i] += xl * K.phi[i] + xr * K.chi[i];
+    for (int i = 0; i < kB; ++i) q[i] += xl * phi[i] + xr * chi[i];
   } else if (len > 0) {
     // last block: re-sweep T_Bt x = q_orig - t_-1 xl e_0 in place, recovering
     // the forward-sweep values d_i = y_i + cp_i y_{i+1} from y (xr is 0 here:
@@ -615,7 +641,6 @@ __global__ __launch_bounds__(kNT, REFINE ? TDT_REFINE_WAVES : kMinWavesPerSimd) 
     const Tc bp = P.bp, iDf = P.iD;
     const Consts<Tc> K = make_consts<Tc>(S, A.vec64, A.vec32);
     const int tl = G.tl;
-    const int len = tl - tid * kB >= kB ? kB : (tl - tid * kB > 0 ? tl - tid * kB : 0);
 
     __syncthreads();   // the previous tile is done with LDS
     {
@@ -628,100 +653,114 @@ __global__ __launch_bounds__(kNT, REFINE ? TDT_REFINE_WAVES : kMinWavesPerSimd) 
     __syncthreads();
     Tio* myrow = lds + tid * RP;
 
-    if constexpr (!REFINE) {
-      Tc q[kB];
-#pragma unroll
-      for (int i = 0; i < kB; ++i) q[i] = (Tc)myrow[i];
-      if constexpr (SUMMARY) {
-        tile_solve(q, len, Tc(0), Tc(0), K, bp, iDf, fw, bw, A.summ + 2 * slot,
-                   A.summ + 2 * slot + 1);
-      } else {
-        tile_solve(q, len, (Tc)XLt, (Tc)XRt, K, bp, iDf, fw, bw, (double*)nullptr,
-                   (double*)nullptr);
-#pragma unroll
-        for (int i = 0; i < kB; ++i) myrow[i] = (Tio)q[i];
-      }
-    } else {
-      // iterative refinement: x_1 = solve_float(f with the tile's outside
-      // values); then repeat r = f - T x (double), d = solve_float(r) with
-      // zero outside values, x += d (double).  After update k >= 2 the next
-      // update is predicted as |d_k| rho with rho = |d_k| / |d_{k-1}|
-      // (|d_1| = |x_1|, approximated by |x|); stop when that is below
-      // tol |x|, when updates stop shrinking, or at the cap.  One barrier per
-      // update carries both the wavefront edges for the next residual and the
-      // wavefront maxima of the last update.
-      const double a = S.a, b = S.b, c = S.c;
-      double x[kB];
-      {
+    // The solve proper, compiled twice: for a full tile (every block has kB
+    // rows; a uniform branch selects it) and for the ragged last tile.
+    auto solve_tile = [&](auto full_tag) {
+      constexpr bool FULL = decltype(full_tag)::value;
+      const int len = FULL ? kB
+                           : (tl - tid * kB >= kB ? kB : (tl - tid * kB > 0 ? tl - tid * kB : 0));
+      if constexpr (!REFINE) {
         Tc q[kB];
 #pragma unroll
-        for (int i = 0; i < kB; ++i) {
-          double r = (double)myrow[i];
-          if (i == 0 && tid == 0) r -= a * XLt;
-          if (i == kB - 1 && tid == kNT - 1) r -= c * XRt;
-          q[i] = i < len ? (Tc)r : Tc(0);
-        }
-        tile_solve(q, len, Tc(0), Tc(0), K, bp, iDf, fw, bw, (double*)nullptr,
-                   (double*)nullptr);
+        for (int i = 0; i < kB; ++i) q[i] = (Tc)myrow[i];
+        if constexpr (SUMMARY) {
+          tile_solve<Tc, FULL>(q, len, Tc(0), Tc(0), K, bp, iDf, fw, bw, A.summ + 2 * slot,
+                               A.summ + 2 * slot + 1);
+        } else {
+          tile_solve<Tc, FULL>(q, len, (Tc)XLt, (Tc)XRt, K, bp, iDf, fw, bw, (double*)nullptr,
+                               (double*)nullptr);
 #pragma unroll
-        for (int i = 0; i < kB; ++i) x[i] = (double)q[i];
-      }
-      int it = 1;
-      double dprev = 0.0, dloc = 0.0;
-      for (;;) {
-        double dmax = 0.0, xmax = 0.0;
-        if (it >= 2) {
-          double xl = 0.0;
-#pragma unroll
-          for (int i = 0; i < kB; ++i) xl = fmax(xl, fabs(x[i]));
-          dmax = wave_max(dloc);
-          xmax = wave_max(xl);
+          for (int i = 0; i < kB; ++i) myrow[i] = (Tio)q[i];
         }
-        if (lane == 0) { edge[w][0] = x[0]; red[w][0] = dmax; red[w][1] = xmax; }
-        if (lane == 63) edge[w][1] = x[kB - 1];
-        __syncthreads();
-        if (it >= 2) {
-          dmax = red[0][0];
-          xmax = red[0][1];
-#pragma unroll
-          for (int q = 1; q < kNW; ++q) { dmax = fmax(dmax, red[q][0]); xmax = fmax(xmax, red[q][1]); }
-          const double rho = it == 2 ? dmax / xmax : dmax / dprev;
-          dprev = dmax;
-          if (dmax == 0.0 || dmax * rho <= A.refine_tol * xmax || rho > 0.9) break;
-        }
-        if (it >= A.max_iter) break;
-        double xm = __shfl_up(x[kB - 1], 1, 64);
-        double xp = __shfl_down(x[0], 1, 64);
-        if (lane == 0) xm = w == 0 ? XLt : edge[w > 0 ? w - 1 : 0][1];
-        if (lane == 63) xp = w == kNW - 1 ? XRt : edge[w + 1 < kNW ? w + 1 : kNW - 1][0];
-        Tc q[kB];
-#pragma unroll
-        for (int i = 0; i < kB; ++i) {
-          const double left = i == 0 ? xm : x[i - 1];
-          const double right = i + 1 < kB ? x[i + 1] : xp;
-          const double r = (double)myrow[i] - (b * x[i] + a * left + c * right);
-          q[i] = i < len ? (Tc)r : Tc(0);
-        }
-        tile_solve(q, len, Tc(0), Tc(0), K, bp, iDf, fw, bw, (double*)nullptr,
-                   (double*)nullptr);
-        dloc = 0.0;
-#pragma unroll
-        for (int i = 0; i < kB; ++i) {
-          x[i] += (double)q[i];
-          dloc = fmax(dloc, fabs((double)q[i]));
-        }
-        ++it;
-      }
-      if (tid == 0 && A.iters) atomicMax(A.iters, it);
-      if constexpr (SUMMARY) {
-        if (tid == 0) A.summ[2 * slot] = x[0];
-        if (tid == kNT - 1) A.summ[2 * slot + 1] = tl == kTile ? x[kB - 1] : 0.0;
       } else {
-        __syncthreads();   // every lane is done reading f from LDS
+        // iterative refinement: x_1 = solve_float(f with the tile's outside
+        // values); then repeat r = f - T x (double), d = solve_float(r) with
+        // zero outside values, x += d (double).  After update k >= 2 the next
+        // update is predicted as |d_k| rho with rho = |d_k| / |d_{k-1}|
+        // (|d_1| = |x_1|); stop when that is below tol |x_1|, when updates
+        // stop shrinking, or at the cap.  The maxima only steer the stopping
+        // test, so they are taken in float.  One barrier per update carries
+        // both the wavefront edges for the next residual and the wavefront
+        // maxima of the last update.
+        const double a = S.a, b = S.b, c = S.c;
+        double x[kB];
+        float xloc = 0.0f;
+        {
+          Tc q[kB];
 #pragma unroll
-        for (int i = 0; i < kB; ++i) myrow[i] = (Tio)x[i];
+          for (int i = 0; i < kB; ++i) {
+            double r = (double)myrow[i];
+            if (i == 0 && tid == 0) r -= a * XLt;
+            if (i == kB - 1 && tid == kNT - 1) r -= c * XRt;
+            q[i] = (FULL || i < len) ? (Tc)r : Tc(0);
+          }
+          tile_solve<Tc, FULL>(q, len, Tc(0), Tc(0), K, bp, iDf, fw, bw, (double*)nullptr,
+                               (double*)nullptr);
+#pragma unroll
+          for (int i = 0; i < kB; ++i) {
+            x[i] = (double)q[i];
+            xloc = fmaxf(xloc, fabsf((float)q[i]));
+          }
+        }
+        int it = 1;
+        float dprev = 0.0f, dloc = 0.0f, xmax = 0.0f;
+        for (;;) {
+          float dmax = 0.0f;
+          if (it >= 2) dmax = wave_max(dloc);
+          else xmax = wave_max(xloc);
+          if (lane == 0) { edge[w][0] = x[0]; red[w][0] = it >= 2 ? dmax : xmax; }
+          if (lane == 63) edge[w][1] = x[kB - 1];
+          __syncthreads();
+          if (it >= 2) {
+            dmax = (float)red[0][0];
+#pragma unroll
+            for (int q = 1; q < kNW; ++q) dmax = fmaxf(dmax, (float)red[q][0]);
+            const float rho = it == 2 ? dmax / xmax : dmax / dprev;
+            dprev = dmax;
+            if (dmax == 0.0f || (double)dmax * rho <= A.refine_tol * xmax || rho > 0.9f) break;
+          } else {
+            xmax = (float)red[0][0];
+#pragma unroll
+            for (int q = 1; q < kNW; ++q) xmax = fmaxf(xmax, (float)red[q][0]);
+          }
+          if (it >= A.max_iter) break;
+          double xm = __shfl_up(x[kB - 1], 1, 64);
+          double xp = __shfl_down(x[0], 1, 64);
+          if (lane == 0) xm = w == 0 ? XLt : edge[w > 0 ? w - 1 : 0][1];
+          if (lane == 63) xp = w == kNW - 1 ? XRt : edge[w + 1 < kNW ? w + 1 : kNW - 1][0];
+          Tc q[kB];
+#pragma unroll
+          for (int i = 0; i < kB; ++i) {
+            const double left = i == 0 ? xm : x[i - 1];
+            const double right = i + 1 < kB ? x[i + 1] : xp;
+            const double r = (double)myrow[i] - (b * x[i] + a * left + c * right);
+            q[i] = (FULL || i < len) ? (Tc)r : Tc(0);
+          }
+          tile_solve<Tc, FULL>(q, len, Tc(0), Tc(0), K, bp, iDf, fw, bw, (double*)nullptr,
+                               (double*)nullptr);
+          dloc = 0.0f;
+#pragma unroll
+          for (int i = 0; i < kB; ++i) {
+            x[i] += (double)q[i];
+            dloc = fmaxf(dloc, fabsf((float)q[i]));
+          }
+          ++it;
+          // the next barrier rewrites red[] and edge[]: every wavefront has
+          // read them once it is past the barrier inside tile_solve
+        }
+        if (tid == 0 && A.iters) atomicMax(A.iters, it);
+        if constexpr (SUMMARY) {
+          if (tid == 0) A.summ[2 * slot] = x[0];
+          if (tid == kNT - 1) A.summ[2 * slot + 1] = tl == kTile ? x[kB - 1] : 0.0;
+        } else {
+          __syncthreads();   // every lane is done reading f from LDS
+#pragma unroll
+          for (int i = 0; i < kB; ++i) myrow[i] = (Tio)x[i];
+        }
       }
-    }
+    };
+    if (tl == kTile) solve_tile(std::true_type{});
+    else solve_tile(std::false_type{});
 
     if constexpr (!SUMMARY) {
       __syncthreads();
@@ -1210,16 +1249,20 @@ static hipError_t run_solve(const LaunchSet& L, const void* F, void* X, const vo
   A.max_iter = L.max_iter;
   A.refine_tol = L.refine_tol;
   if (L.ev) (void)hipEventRecord(L.ev[0], st);
+  // Tile summaries of the refinement path are computed in double (one
+  // double sweep costs less than a float solve plus refinement, and the
+  // values outside each tile then come out exact in double).
+  using Ts = typename std::conditional<REFINE, double, Tc>::type;
   if (L.n_p1 > 0) {
     if (L.green) {
       if (L.n_beta > 0) launch_beta<Tio>(L, static_cast<const Tio*>(F), st);
       if (L.n_last > 0) {
         A.items = nullptr;
-        launch_tile<Tio, Tc, REFINE, true, false>(A, L.n_last, 0, 1, st);
+        launch_tile<Tio, Ts, false, true, false>(A, L.n_last, 0, 1, st);
       }
     } else {
       A.items = L.p1_items;
-      launch_tile<Tio, Tc, REFINE, true, false>(A, L.n_p1, 0, 0, st);
+      launch_tile<Tio, Ts, false, true, false>(A, L.n_p1, 0, 0, st);
     }
     if (L.ev) (void)hipEventRecord(L.ev[1], st);
     GridArgs G{L.sys, L.grid_items, L.ttab, L.ttab_n, L.summ, L.ghost, L.gscr};
@@ -1238,8 +1281,9 @@ static hipError_t run_solve(const LaunchSet& L, const void* F, void* X, const vo
     (void)hipEventRecord(L.ev[2], st);
   }
   A.items = L.fin_items;
-  // a series of multi-tile systems runs its final pass last-tile-first, so
-  // that the tiles the first pass read last are re-read while still cached
+  // after a first pass the final pass re-reads the tiles the first pass read
+  // last while they are still cached: a series runs last-tile-first, a varlen
+  // plan's list already starts with the first pass's tiles in reverse
   launch_tile<Tio, Tc, REFINE, false, BWD>(A, L.n_fin, (L.n_p1 > 0 && !L.fin_items) ? 1 : 0,
                                            0, st);
   if (L.ev) (void)hipEventRecord(L.ev[3], st);
