@@ -165,6 +165,51 @@ tdt_status_t tdt_segment_merge(const double *l, const double *r, double *out);
 tdt_status_t tdt_plan_profile(tdt_plan_t plan, int enable);
 tdt_status_t tdt_plan_profile_read(tdt_plan_t plan, double *ms3, int64_t *nsolves);
 
+/* Launch-shape options of a plan.  None of them changes what is computed;
+ * they trade how the work is spread over the device.
+ *   TDT_OPT_WHOLE_MAX_TILES  varlen plans: systems of at most this many tiles
+ *       (8192 rows each) are solved whole by one workgroup each, so that a
+ *       batch of such systems takes a single launch whose second read of
+ *       every tile comes from cache; larger systems go through the
+ *       tile-parallel three-kernel path (first pass, interface pass, final
+ *       pass).  0..16, default 8; 0 sends every multi-tile system through
+ *       the three kernels.
+ *   TDT_OPT_WG_PER_CU        cap on the persistent workgroups per compute
+ *       unit of every kernel; 0 (default) = as many as fit.
+ *   TDT_OPT_MAX_REFINE       TDT_F32_REFINE: most float solves per tile
+ *       (1..100, default 40). */
+typedef enum {
+    TDT_OPT_WHOLE_MAX_TILES = 0,
+    TDT_OPT_WG_PER_CU = 1,
+    TDT_OPT_MAX_REFINE = 2
+} tdt_option_t;
+
+/* Set / read an option.  Errors: unknown option, value out of range, or
+ * TDT_OPT_WHOLE_MAX_TILES on a series plan -> TDT_ERR_INVALID_ARG.  Setting
+ * TDT_OPT_WHOLE_MAX_TILES rebuilds the plan's work lists (blocking) and must
+ * not happen while a solve of the plan may run or is being captured. */
+tdt_status_t tdt_plan_set_option(tdt_plan_t plan, tdt_option_t opt, int64_t value);
+tdt_status_t tdt_plan_get_option(tdt_plan_t plan, tdt_option_t opt, int64_t *value);
+
+/* Autotuner: times the candidate launch shapes (TDT_OPT_WG_PER_CU, and
+ * TDT_OPT_WHOLE_MAX_TILES for varlen plans) on the caller's data with HIP
+ * events on `stream`, and keeps the fastest.  F, X (and M for a series
+ * plan; ignored for varlen) as for tdt_solve / tdt_solve_varlen; X is
+ * overwritten by the trial solves (it ends holding the solution).
+ * Synchronises the stream; refused while it is being captured
+ * (TDT_ERR_CAPTURE).  The choice is cached in a JSON file keyed by device
+ * (architecture, compute units), plan kind, dtype and problem size (sizes
+ * rounded up to powers of two): the file named by the environment variable
+ * TDT_TUNE_CACHE, else $HOME/.cache/tdt/autotune.json.  A cached choice is
+ * applied without timing.  flags: TDT_TUNE_NO_CACHE neither reads nor
+ * writes the file; TDT_TUNE_FORCE times again and replaces the entry.
+ * *best_ms (may be NULL): the chosen shape's time per solve (0 when taken
+ * from the cache). */
+#define TDT_TUNE_NO_CACHE 1
+#define TDT_TUNE_FORCE 2
+tdt_status_t tdt_plan_autotune(tdt_plan_t plan, const void *F, void *X, int64_t M,
+                               hipStream_t stream, int flags, double *best_ms);
+
 /* Compile-time layout facts of this build: block length B and threads per
  * workgroup for double and float data, and the tile length. */
 tdt_status_t tdt_build_info(int *block_f64, int *block_f32, int *wg_threads,

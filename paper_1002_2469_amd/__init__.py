@@ -83,6 +83,29 @@ class _PlanBase:
                                                     ctypes.byref(n)), "tdt_plan_profile_read")
         return dict(first_pass_ms=ms[0], interface_ms=ms[1], final_ms=ms[2], solves=n.value)
 
+    def set_option(self, name: str, value: int):
+        """Launch-shape option (see tdt_option_t): 'whole_max_tiles',
+        'wg_per_cu' or 'max_refine'."""
+        _lib.check(_lib.lib().tdt_plan_set_option(self._h, _lib.OPTIONS[name], int(value)),
+                   "tdt_plan_set_option")
+
+    def get_option(self, name: str) -> int:
+        v = ctypes.c_int64(0)
+        _lib.check(_lib.lib().tdt_plan_get_option(self._h, _lib.OPTIONS[name], ctypes.byref(v)),
+                   "tdt_plan_get_option")
+        return v.value
+
+    def _autotune(self, F, X, M, cache=True, force=False, stream=None) -> dict:
+        flags = (0 if cache else _lib.TUNE_NO_CACHE) | (_lib.TUNE_FORCE if force else 0)
+        ms = ctypes.c_double(0.0)
+        _lib.check(_lib.lib().tdt_plan_autotune(self._h, ctypes.c_void_p(F.data_ptr()),
+                                                ctypes.c_void_p(X.data_ptr()), int(M),
+                                                _stream_handle(stream), flags, ctypes.byref(ms)),
+                   "tdt_plan_autotune")
+        out = {k: self.get_option(k) for k in ("whole_max_tiles", "wg_per_cu")}
+        out["ms"] = ms.value
+        return out
+
     def close(self):
         if self._h:
             _lib.lib().tdt_plan_destroy(self._h)
@@ -128,6 +151,17 @@ class Plan(_PlanBase):
                                         ctypes.c_void_p(X.data_ptr()), M,
                                         _stream_handle(stream)), "tdt_solve")
         return X
+
+    def autotune(self, F, X=None, cache=True, force=False, stream=None) -> dict:
+        """Time the launch shapes on F (X is overwritten with the solution)
+        and keep the fastest; cached per device and problem size."""
+        torch = _torch()
+        M = F.numel() // self.N
+        if X is None:
+            X = torch.empty_like(F)
+        _check_tensor(F, _data_dtype(self.dtype), M * self.N, "F")
+        _check_tensor(X, _data_dtype(self.dtype), M * self.N, "X")
+        return self._autotune(F, X, M, cache, force, stream)
 
     def backward(self, gX, X, gF=None, gt=None, stream=None):
         """gF = T^{-T} gX and gt = (dL/dt_-1, dL/dt_0, dL/dt_1) summed over RHS."""
@@ -181,6 +215,16 @@ class VarlenPlan(_PlanBase):
                                                ctypes.c_void_p(X.data_ptr()),
                                                _stream_handle(stream)), "tdt_solve_varlen")
         return X
+
+    def autotune(self, F, X=None, cache=True, force=False, stream=None) -> dict:
+        """Time the launch shapes (whole-system threshold, workgroups per CU)
+        on F (X is overwritten with the solution) and keep the fastest."""
+        torch = _torch()
+        if X is None:
+            X = torch.empty_like(F)
+        _check_tensor(F, _data_dtype(self.dtype), self.total, "F")
+        _check_tensor(X, _data_dtype(self.dtype), self.total, "X")
+        return self._autotune(F, X, 1, cache, force, stream)
 
     def backward(self, gX, X, gF=None, gt=None, stream=None):
         """gF = T_s^{-T} gX per system and gt[s] = (dL/dt_-1, dL/dt_0, dL/dt_1)."""

@@ -38,8 +38,14 @@ EXPORTS = [
     "tdt_plan_create", "tdt_plan_varlen_create", "tdt_plan_reserve", "tdt_solve",
     "tdt_solve_varlen", "tdt_solve_backward", "tdt_plan_destroy", "tdt_status_string",
     "tdt_last_info", "tdt_block_constants", "tdt_green_rows", "tdt_segment_merge", "tdt_plan_profile",
-    "tdt_plan_profile_read", "tdt_build_info",
+    "tdt_plan_profile_read", "tdt_build_info", "tdt_plan_set_option", "tdt_plan_get_option",
+    "tdt_plan_autotune",
 ]
+
+# tdt_option_t
+OPTIONS = {"whole_max_tiles": 0, "wg_per_cu": 1, "max_refine": 2}
+TUNE_NO_CACHE = 1
+TUNE_FORCE = 2
 
 
 def build_command(out: str = LIB_PATH) -> list:
@@ -92,6 +98,9 @@ def lib():
         "tdt_plan_profile_read": [p, p, ctypes.POINTER(i64)],
         "tdt_build_info": [ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
                            ctypes.POINTER(i64)],
+        "tdt_plan_set_option": [p, i32, i64],
+        "tdt_plan_get_option": [p, i32, ctypes.POINTER(i64)],
+        "tdt_plan_autotune": [p, p, p, i64, p, i32, ctypes.POINTER(d)],
     }
     for name, args in sig.items():
         f = getattr(L, name)

@@ -2,11 +2,15 @@
 // once-per-matrix preliminary step (plan), workspace management and the
 // launch sequence of a solve.
 #include <hip/hip_runtime.h>
+#include <sys/stat.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <string>
 #include <limits>
 #include <new>
 #include <numeric>
@@ -38,10 +42,13 @@ struct tdt_plan_s {
   double* dttab[2] = {nullptr, nullptr};    // per tile position table [2][ttab_n]
   int64_t ttab_n = 0;
   // varlen launch lists
+  std::vector<int64_t> order;   // systems, largest first
+  int sys_max_tiles = tdt::kSysMaxTilesDefault;
   int2* dp1 = nullptr;
   int2* dfin = nullptr;
   int* dgrid = nullptr;
-  int64_t n_p1 = 0, n_fin = 0, n_grid = 0;
+  int* dwhole = nullptr;
+  int64_t n_p1 = 0, n_fin = 0, n_grid = 0, n_whole = 0;
   int64_t vslots = 0, vfslots = 0;
   // workspace
   int64_t ws_slots = 0, ws_fslots = 0;
@@ -54,6 +61,7 @@ struct tdt_plan_s {
   double dominance = 0.0, kappa = 0.0;
   int max_iter = 40;
   double refine_tol = 1e-13;
+  int wg_per_cu = 0;
   // measurement
   bool profile = false;
   std::vector<hipEvent_t> prof_ev;   // 4 per recorded solve
@@ -360,9 +368,53 @@ void destroy(tdt_plan_s* p) {
   (void)hipFree(p->dp1);
   (void)hipFree(p->dfin);
   (void)hipFree(p->dgrid);
+  (void)hipFree(p->dwhole);
   (void)hipFree(p->iters);
   free_workspace(p);
   delete p;
+}
+
+// Work lists of a varlen plan.  Systems of at most sys_max_tiles tiles are
+// solved whole by one workgroup each (largest first); the others go through
+// the three kernels: first pass over their tiles, interface pass, final pass
+// over their tiles in the reverse of the first pass's order (the most
+// recently read, still cached, tiles first).
+tdt_status_t build_varlen_lists(tdt_plan_s* p) {
+  std::vector<int2> p1, fin;
+  std::vector<int> grid, whole;
+  for (int64_t s : p->order) {
+    const int nt = p->hsys[0][s].ntiles;
+    if (nt <= p->sys_max_tiles) {
+      whole.push_back((int)s);
+    } else {
+      for (int t = 0; t < nt; ++t) p1.push_back(make_int2((int)s, t));
+      if (nt > 1) grid.push_back((int)s);
+    }
+  }
+  // one-tile systems outside the whole-system list: no first pass
+  std::vector<int2> single;
+  for (const int2& it : p1)
+    if (p->hsys[0][it.x].ntiles == 1) single.push_back(it);
+  p1.erase(std::remove_if(p1.begin(), p1.end(),
+                          [&](const int2& it) { return p->hsys[0][it.x].ntiles == 1; }),
+           p1.end());
+  fin.assign(p1.rbegin(), p1.rend());
+  fin.insert(fin.end(), single.begin(), single.end());
+  (void)hipFree(p->dp1);
+  (void)hipFree(p->dfin);
+  (void)hipFree(p->dgrid);
+  (void)hipFree(p->dwhole);
+  p->dp1 = p->dfin = nullptr;
+  p->dgrid = p->dwhole = nullptr;
+  p->n_p1 = (int64_t)p1.size();
+  p->n_fin = (int64_t)fin.size();
+  p->n_grid = (int64_t)grid.size();
+  p->n_whole = (int64_t)whole.size();
+  tdt_status_t st = dev_upload(&p->dp1, p1.data(), p1.size());
+  if (st == TDT_OK) st = dev_upload(&p->dfin, fin.data(), fin.size());
+  if (st == TDT_OK) st = dev_upload(&p->dgrid, grid.data(), grid.size());
+  if (st == TDT_OK) st = dev_upload(&p->dwhole, whole.data(), whole.size());
+  return st;
 }
 
 // Build both descriptor sets (T and T^T) and upload everything.
@@ -431,35 +483,20 @@ tdt_status_t finish_plan(tdt_plan_s* p, const std::vector<double>& tm1,
       }
   }
   if (p->varlen) {
-    std::vector<int64_t> order((size_t)S);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(),
+    // workspace slots of the multi-tile systems, largest system first
+    p->order.resize((size_t)S);
+    std::iota(p->order.begin(), p->order.end(), 0);
+    std::stable_sort(p->order.begin(), p->order.end(),
                      [&](int64_t x, int64_t y) { return sizes[x] > sizes[y]; });
-    std::vector<int2> p1, fin;
-    std::vector<int> grid;
     int64_t slot = 0;
-    for (int64_t s : order) {
-      const int nt = p->hsys[0][s].ntiles;
-      if (nt > 1) {
+    for (int64_t s : p->order) {
+      if (p->hsys[0][s].ntiles > 1) {
         for (int dir = 0; dir < 2; ++dir) p->hsys[dir][s].slot0 = (int32_t)slot;
-        for (int t = 0; t < nt; ++t) p1.push_back(make_int2((int)s, t));
-        grid.push_back((int)s);
         slot += p->hsys[0][s].tslots;
       }
     }
-    // final pass: the multi-tile systems' tiles in the reverse of the first
-    // pass's order (the most recently read, still cached, come first), then
-    // the one-tile systems largest first
-    fin.assign(p1.rbegin(), p1.rend());
-    for (int64_t s : order)
-      if (p->hsys[0][s].ntiles == 1) fin.push_back(make_int2((int)s, 0));
     p->vslots = slot;
-    p->n_p1 = (int64_t)p1.size();
-    p->n_fin = (int64_t)fin.size();
-    p->n_grid = (int64_t)grid.size();
-    tdt_status_t st = dev_upload(&p->dp1, p1.data(), p1.size());
-    if (st == TDT_OK) st = dev_upload(&p->dfin, fin.data(), fin.size());
-    if (st == TDT_OK) st = dev_upload(&p->dgrid, grid.data(), grid.size());
+    const tdt_status_t st = build_varlen_lists(p);
     if (st != TDT_OK) return st;
   }
   // interface pass across tiles: beta_{t-1} and 1/(1 - Pf_t beta_{t-1}) for
@@ -520,6 +557,7 @@ tdt_status_t run(tdt_plan_s* p, int dir, const void* F, void* X, const void* Xfw
   L.iters = p->iters;
   L.max_iter = p->max_iter;
   L.refine_tol = p->refine_tol;
+  L.wg_per_cu = p->wg_per_cu;
   L.ttab = p->dttab[dir];
   L.ttab_n = p->ttab_n;
   L.max_ntiles = 1;
@@ -532,9 +570,11 @@ tdt_status_t run(tdt_plan_s* p, int dir, const void* F, void* X, const void* Xfw
     L.p1_items = p->dp1;
     L.fin_items = p->dfin;
     L.grid_items = p->dgrid;
+    L.sys_items = p->dwhole;
     L.n_p1 = p->n_p1;
     L.n_fin = p->n_fin;
     L.n_grid = p->n_grid;
+    L.n_sys = p->n_whole;
     slots = p->vslots;
     fslots = Xfwd ? p->vfslots : 0;
   } else {
@@ -542,6 +582,8 @@ tdt_status_t run(tdt_plan_s* p, int dir, const void* F, void* X, const void* Xfw
     L.p1_items = nullptr;
     L.fin_items = nullptr;
     L.grid_items = nullptr;
+    L.sys_items = nullptr;
+    L.n_sys = 0;
     L.green = p->dgreen[dir];
     L.nfull = (int)(p->N % kTile == 0 ? nt : nt - 1);
     L.n_beta = nt > 1 ? M * L.nfull : 0;
@@ -582,6 +624,123 @@ tdt_status_t run(tdt_plan_s* p, int dir, const void* F, void* X, const void* Xfw
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
+// Autotuner support: choice record, cache key, JSON cache file.
+namespace tune {
+
+struct Choice {
+  int whole_max_tiles;
+  int wg_per_cu;
+  double ms;
+};
+
+int64_t pow2_ceil(int64_t v) {
+  int64_t r = 1;
+  while (r < v) r <<= 1;
+  return r;
+}
+
+std::string key_of(const tdt_plan_s* p, int64_t M) {
+  int dev = 0, cus = 0;
+  hipDeviceProp_t prop;
+  std::memset(&prop, 0, sizeof(prop));
+  (void)hipGetDevice(&dev);
+  (void)hipGetDeviceProperties(&prop, dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  std::string arch(prop.gcnArchName);
+  const size_t colon = arch.find(':');
+  if (colon != std::string::npos) arch.resize(colon);
+  const char* dt = p->dtype == TDT_F64 ? "f64" : (p->dtype == TDT_F32 ? "f32" : "f32_refine");
+  char buf[256];
+  if (p->varlen) {
+    int maxt = 1;
+    for (const SysDesc& D : p->hsys[0]) maxt = std::max(maxt, (int)D.ntiles);
+    std::snprintf(buf, sizeof(buf), "%s|cu%d|varlen|%s|S%lld|U%lld|P%lld", arch.c_str(), cus, dt,
+                  (long long)pow2_ceil(p->S), (long long)pow2_ceil(p->total),
+                  (long long)pow2_ceil(maxt));
+  } else {
+    std::snprintf(buf, sizeof(buf), "%s|cu%d|series|%s|N%lld|M%lld", arch.c_str(), cus, dt,
+                  (long long)pow2_ceil(p->N), (long long)pow2_ceil(M));
+  }
+  return buf;
+}
+
+std::string cache_path() {
+  if (const char* e = std::getenv("TDT_TUNE_CACHE")) return e;
+  const char* home = std::getenv("HOME");
+  return std::string(home ? home : ".") + "/.cache/tdt/autotune.json";
+}
+
+// The file holds one entry per line:
+//   "key": {"whole_max_tiles": W, "wg_per_cu": C, "ms": T},
+// inside {"format": "tdt-autotune-1", "entries": { ... }}.
+std::vector<std::pair<std::string, Choice>> read_all() {
+  std::vector<std::pair<std::string, Choice>> out;
+  FILE* f = std::fopen(cache_path().c_str(), "r");
+  if (!f) return out;
+  char line[1024];
+  while (std::fgets(line, sizeof(line), f)) {
+    const char* q0 = std::strchr(line, '"');
+    if (!q0) continue;
+    const char* q1 = std::strchr(q0 + 1, '"');
+    if (!q1) continue;
+    const char* b = std::strstr(q1, "{\"whole_max_tiles\":");
+    if (!b) continue;
+    Choice c{0, 0, 0.0};
+    if (std::sscanf(b, "{\"whole_max_tiles\": %d, \"wg_per_cu\": %d, \"ms\": %lf", &c.whole_max_tiles,
+                    &c.wg_per_cu, &c.ms) == 3)
+      out.emplace_back(std::string(q0 + 1, q1), c);
+  }
+  std::fclose(f);
+  return out;
+}
+
+bool lookup(const std::string& key, Choice& c) {
+  for (const auto& e : read_all())
+    if (e.first == key) {
+      c = e.second;
+      return true;
+    }
+  return false;
+}
+
+void store(const std::string& key, const Choice& c) {
+  auto all = read_all();
+  bool found = false;
+  for (auto& e : all)
+    if (e.first == key) {
+      e.second = c;
+      found = true;
+    }
+  if (!found) all.emplace_back(key, c);
+  const std::string path = cache_path();
+  const size_t slash = path.rfind('/');
+  if (slash != std::string::npos) {
+    // create the directories on the way (best effort)
+    for (size_t i = 1; i <= slash; ++i)
+      if (path[i] == '/') (void)mkdir(path.substr(0, i).c_str(), 0755);
+  }
+  const std::string tmp = path + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return;
+  std::fprintf(f, "{\"format\": \"tdt-autotune-1\", \"entries\": {\n");
+  for (size_t i = 0; i < all.size(); ++i)
+    std::fprintf(f, "  \"%s\": {\"whole_max_tiles\": %d, \"wg_per_cu\": %d, \"ms\": %.6f}%s\n",
+                 all[i].first.c_str(), all[i].second.whole_max_tiles, all[i].second.wg_per_cu,
+                 all[i].second.ms, i + 1 < all.size() ? "," : "");
+  std::fprintf(f, "}}\n");
+  std::fclose(f);
+  (void)std::rename(tmp.c_str(), path.c_str());
+}
+
+tdt_status_t apply(tdt_plan_s* p, const Choice& c) {
+  tdt_status_t st = tdt_plan_set_option(p, TDT_OPT_WG_PER_CU, c.wg_per_cu);
+  if (st == TDT_OK && p->varlen)
+    st = tdt_plan_set_option(p, TDT_OPT_WHOLE_MAX_TILES, c.whole_max_tiles);
+  return st;
+}
+
+}  // namespace tune
+
 extern "C" {
 
 const char* tdt_status_string(tdt_status_t s) {
@@ -717,6 +876,101 @@ tdt_status_t tdt_last_info(tdt_plan_t p, int* n_refine_iters, double* last_rel_u
   if (dominance) *dominance = p->dominance;
   if (kappa2) *kappa2 = p->kappa;
   return TDT_OK;
+}
+
+tdt_status_t tdt_plan_set_option(tdt_plan_t p, tdt_option_t opt, int64_t value) {
+  if (!p) return TDT_ERR_INVALID_ARG;
+  switch (opt) {
+    case TDT_OPT_WHOLE_MAX_TILES: {
+      if (!p->varlen || value < 0 || value > tdt::kSysMaxTiles) return TDT_ERR_INVALID_ARG;
+      if ((int)value == p->sys_max_tiles) return TDT_OK;
+      if (hipDeviceSynchronize() != hipSuccess) return TDT_ERR_HIP;
+      p->sys_max_tiles = (int)value;
+      return build_varlen_lists(p);
+    }
+    case TDT_OPT_WG_PER_CU:
+      if (value < 0 || value > 64) return TDT_ERR_INVALID_ARG;
+      p->wg_per_cu = (int)value;
+      return TDT_OK;
+    case TDT_OPT_MAX_REFINE:
+      if (value < 1 || value > 100) return TDT_ERR_INVALID_ARG;
+      p->max_iter = (int)value;
+      return TDT_OK;
+  }
+  return TDT_ERR_INVALID_ARG;
+}
+
+tdt_status_t tdt_plan_get_option(tdt_plan_t p, tdt_option_t opt, int64_t* value) {
+  if (!p || !value) return TDT_ERR_INVALID_ARG;
+  switch (opt) {
+    case TDT_OPT_WHOLE_MAX_TILES: *value = p->sys_max_tiles; return TDT_OK;
+    case TDT_OPT_WG_PER_CU: *value = p->wg_per_cu; return TDT_OK;
+    case TDT_OPT_MAX_REFINE: *value = p->max_iter; return TDT_OK;
+  }
+  return TDT_ERR_INVALID_ARG;
+}
+
+tdt_status_t tdt_plan_autotune(tdt_plan_t p, const void* F, void* X, int64_t M,
+                               hipStream_t stream, int flags, double* best_ms) {
+  if (best_ms) *best_ms = 0.0;
+  if (!p || !F || !X) return TDT_ERR_INVALID_ARG;
+  if (p->varlen) M = 1;
+  if (M < 1) return TDT_ERR_INVALID_ARG;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+    return TDT_ERR_CAPTURE;
+  const std::string key = tune::key_of(p, M);
+  const bool use_cache = !(flags & TDT_TUNE_NO_CACHE);
+  if (use_cache && !(flags & TDT_TUNE_FORCE)) {
+    tune::Choice c;
+    if (tune::lookup(key, c)) return tune::apply(p, c);
+  }
+  auto solve = [&]() {
+    return p->varlen ? tdt_solve_varlen(p, F, X, stream) : tdt_solve(p, F, X, M, stream);
+  };
+  std::vector<tune::Choice> cands;
+  const int whole[] = {0, 1, 2, 4, 8, 16};
+  for (int wpc : {0, 1}) {
+    if (p->varlen)
+      for (int w : whole) cands.push_back(tune::Choice{w, wpc, 0.0});
+    else
+      cands.push_back(tune::Choice{p->sys_max_tiles, wpc, 0.0});
+  }
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return TDT_ERR_HIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return TDT_ERR_HIP;
+  }
+  tdt_status_t st = TDT_OK;
+  int best = -1;
+  for (size_t i = 0; i < cands.size() && st >= 0; ++i) {
+    st = tune::apply(p, cands[i]);
+    if (st < 0) break;
+    st = solve();   // warm-up (also grows the workspace outside the timing)
+    if (st < 0) break;
+    float ms = 0.0f, tot = 0.0f;
+    constexpr int kReps = 3;
+    for (int r = 0; r < kReps && st >= 0; ++r) {
+      (void)hipEventRecord(e0, stream);
+      st = solve();
+      (void)hipEventRecord(e1, stream);
+      if (hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+        st = TDT_ERR_HIP;
+      tot += ms;
+    }
+    cands[i].ms = tot / kReps;
+    if (st >= 0 && (best < 0 || cands[i].ms < cands[best].ms)) best = (int)i;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st < 0) return st;
+  st = tune::apply(p, cands[best]);
+  if (st < 0) return st;
+  if (best_ms) *best_ms = cands[best].ms;
+  if (use_cache) tune::store(key, cands[best]);
+  return solve();   // leave X holding the solution under the chosen shape
 }
 
 tdt_status_t tdt_block_constants(double t_m1, double t_0, double t_1, int B, double* out) {

@@ -13,6 +13,11 @@ constexpr int kNT = 512;
 constexpr int kNW = kNT / 64;          // wavefronts per workgroup
 constexpr int kTile = kB * kNT;        // 8192 unknowns per tile
 constexpr int kMinWavesPerSimd = 4;    // occupancy the tile kernels are compiled for
+// varlen plans: systems of at most this many tiles are solved whole by one
+// workgroup each (default; the plan option can lower it, or raise it up to
+// kSysMaxTiles)
+constexpr int kSysMaxTilesDefault = 8;
+constexpr int kSysMaxTiles = 16;
 
 // One Toeplitz system as the kernels see it.  All constants are double; the
 // float kernels round them on load.  Segment end values use the order
@@ -68,7 +73,8 @@ struct LaunchSet {
   const int2* p1_items;    // varlen: (system, tile) of the first pass; null for a series
   const int2* fin_items;   // varlen: (system, tile) of the final pass
   const int* grid_items;   // varlen: systems with more than one tile
-  int64_t n_p1, n_fin, n_grid;
+  const int* sys_items;    // varlen: systems solved whole by one workgroup each
+  int64_t n_p1, n_fin, n_grid, n_sys;
   // series plans with more than one tile: the first pass is a dot product of
   // every full tile with the tile's Green rows (n_beta items), plus the
   // sweep-based pass over the partial last tile of each right-hand side
@@ -87,6 +93,7 @@ struct LaunchSet {
   int* iters;
   int max_iter;
   double refine_tol;
+  int wg_per_cu;           // cap of persistent workgroups per CU (0: as many as fit)
   hipEvent_t* ev;          // measurement: 4 events (before pass 1, after pass 1,
                            // after the interface pass, after the final pass) or null
 };

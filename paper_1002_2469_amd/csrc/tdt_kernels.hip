@@ -594,8 +594,228 @@ __device__ __forceinline__ void prefetch(const TileArgs<Tio>& A, int64_t item,
   }
 }
 
+#ifndef TDT_REFINE_WAVES
+#define TDT_REFINE_WAVES kMinWavesPerSimd
+#endif
+#ifndef TDT_REFINE_PREFETCH
+#define TDT_REFINE_PREFETCH 0
+#endif
+
+// Workgroup-shared scratch of a tile solve.
+template <typename Tio, typename Tc>
+struct TileShared {
+  static constexpr int RP = kB + 16 / (int)sizeof(Tio);   // padded LDS row pitch
+  __align__(16) Tio lds[kNT * RP];
+  Tc fw[kNW][2], bw[kNW][2];
+  double red[kNW][4];
+  double edge[kNW][2];
+};
+
+// Element j*kNT + tid of a tile lives in LDS row j*(kNT/kB) + tid/kB, column
+// tid%kB: after the coalesced loads each lane owns kB consecutive rows.
+template <typename Tio>
+__device__ __forceinline__ int lds_base() {
+  constexpr int RP = kB + 16 / (int)sizeof(Tio);
+  return (threadIdx.x / kB) * RP + (threadIdx.x % kB);
+}
+template <typename Tio>
+constexpr int lds_stride() {
+  return (kNT / kB) * (kB + 16 / (int)sizeof(Tio));
+}
+
+// Rows of the lane's block that exist in a tile of tl rows.
+__device__ __forceinline__ int block_len(int tl) {
+  const int r = tl - (int)threadIdx.x * kB;
+  return r >= kB ? kB : (r > 0 ? r : 0);
+}
+
+// Solves the tile held in LDS in place (each lane's kB rows at myrow), given
+// the values just outside it.  With yfo/ylo non-null (SUMMARY, outside values
+// zero) it writes the tile's first and last unknown instead.  FULL: every
+// block has kB rows.  REFINE: Tio = double data, Tc = float sweeps; residual
+// and update in double, repeated until converged (see below).
+template <typename Tio, typename Tc, bool REFINE, bool SUMMARY, bool FULL>
+__device__ __forceinline__ void solve_in_lds(TileShared<Tio, Tc>& sh, Tio* myrow, int len, int tl,
+                                             double XLt, double XRt, const SysDesc& S,
+                                             const Consts<Tc>& K, Tc bp, Tc iDf,
+                                             double* yfo, double* ylo, int* iters, int max_iter,
+                                             double refine_tol) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if constexpr (!REFINE) {
+    Tc q[kB];
+#pragma unroll
+    for (int i = 0; i < kB; ++i) q[i] = (Tc)myrow[i];
+    if constexpr (SUMMARY) {
+      tile_solve<Tc, FULL>(q, len, Tc(0), Tc(0), K, bp, iDf, sh.fw, sh.bw, yfo, ylo);
+    } else {
+      tile_solve<Tc, FULL>(q, len, (Tc)XLt, (Tc)XRt, K, bp, iDf, sh.fw, sh.bw, (double*)nullptr,
+                           (double*)nullptr);
+#pragma unroll
+      for (int i = 0; i < kB; ++i) myrow[i] = (Tio)q[i];
+    }
+  } else {
+    // iterative refinement: x_1 = solve_float(f with the tile's outside
+    // values); then repeat r = f - T x (double), d = solve_float(r) with
+    // zero outside values, x += d (double).  After update k >= 2 the next
+    // update is predicted as |d_k| rho with rho = |d_k| / |d_{k-1}|
+    // (|d_1| = |x_1|); stop when that is below tol |x_1|, when updates stop
+    // shrinking, or at the cap.  The maxima only steer the stopping test, so
+    // they are taken in float.  One barrier per update carries both the
+    // wavefront edges for the next residual and the wavefront maxima of the
+    // last update.
+    const double a = S.a, b = S.b, c = S.c;
+    double x[kB];
+    float xloc = 0.0f;
+    {
+      Tc q[kB];
+#pragma unroll
+      for (int i = 0; i < kB; ++i) {
+        double r = (double)myrow[i];
+        if (i == 0 && tid == 0) r -= a * XLt;
+        if (i == kB - 1 && tid == kNT - 1) r -= c * XRt;
+        q[i] = (FULL || i < len) ? (Tc)r : Tc(0);
+      }
+      tile_solve<Tc, FULL>(q, len, Tc(0), Tc(0), K, bp, iDf, sh.fw, sh.bw, (double*)nullptr,
+                           (double*)nullptr);
+#pragma unroll
+      for (int i = 0; i < kB; ++i) {
+        x[i] = (double)q[i];
+        xloc = fmaxf(xloc, fabsf((float)q[i]));
+      }
+    }
+    int it = 1;
+    float dprev = 0.0f, dloc = 0.0f, xmax = 0.0f;
+    for (;;) {
+      float dmax = 0.0f;
+      if (it >= 2) dmax = wave_max(dloc);
+      else xmax = wave_max(xloc);
+      if (lane == 0) { sh.edge[w][0] = x[0]; sh.red[w][0] = it >= 2 ? dmax : xmax; }
+      if (lane == 63) sh.edge[w][1] = x[kB - 1];
+      __syncthreads();
+      if (it >= 2) {
+        dmax = (float)sh.red[0][0];
+#pragma unroll
+        for (int q = 1; q < kNW; ++q) dmax = fmaxf(dmax, (float)sh.red[q][0]);
+        const float rho = it == 2 ? dmax / xmax : dmax / dprev;
+        dprev = dmax;
+        if (dmax == 0.0f || (double)dmax * rho <= refine_tol * xmax || rho > 0.9f) break;
+      } else {
+        xmax = (float)sh.red[0][0];
+#pragma unroll
+        for (int q = 1; q < kNW; ++q) xmax = fmaxf(xmax, (float)sh.red[q][0]);
+      }
+      if (it >= max_iter) break;
+      double xm = __shfl_up(x[kB - 1], 1, 64);
+      double xp = __shfl_down(x[0], 1, 64);
+      if (lane == 0) xm = w == 0 ? XLt : sh.edge[w > 0 ? w - 1 : 0][1];
+      if (lane == 63) xp = w == kNW - 1 ? XRt : sh.edge[w + 1 < kNW ? w + 1 : kNW - 1][0];
+      Tc q[kB];
+#pragma unroll
+      for (int i = 0; i < kB; ++i) {
+        const double left = i == 0 ? xm : x[i - 1];
+        const double right = i + 1 < kB ? x[i + 1] : xp;
+        const double r = (double)myrow[i] - (b * x[i] + a * left + c * right);
+        q[i] = (FULL || i < len) ? (Tc)r : Tc(0);
+      }
+      tile_solve<Tc, FULL>(q, len, Tc(0), Tc(0), K, bp, iDf, sh.fw, sh.bw, (double*)nullptr,
+                           (double*)nullptr);
+      dloc = 0.0f;
+#pragma unroll
+      for (int i = 0; i < kB; ++i) {
+        x[i] += (double)q[i];
+        dloc = fmaxf(dloc, fabsf((float)q[i]));
+      }
+      ++it;
+      // the next barrier rewrites red[] and edge[]: every wavefront has read
+      // them once it is past the barriers inside tile_solve
+    }
+    if (tid == 0 && iters) atomicMax(iters, it);
+    if constexpr (SUMMARY) {
+      if (tid == 0) *yfo = x[0];
+      if (tid == kNT - 1) *ylo = tl == kTile ? x[kB - 1] : 0.0;
+    } else {
+      __syncthreads();   // every lane is done reading f from LDS
+#pragma unroll
+      for (int i = 0; i < kB; ++i) myrow[i] = (Tio)x[i];
+    }
+  }
+}
+
+template <typename Tio, typename Tc, bool REFINE, bool SUMMARY>
+__device__ __forceinline__ void solve_tile_lds(TileShared<Tio, Tc>& sh, int tl, double XLt,
+                                               double XRt, const SysDesc& S,
+                                               const Consts<Tc>& K, Tc bp, Tc iDf, double* yfo,
+                                               double* ylo, int* iters, int max_iter,
+                                               double refine_tol) {
+  Tio* myrow = sh.lds + threadIdx.x * TileShared<Tio, Tc>::RP;
+  // a separate full-tile copy of the solve pays where registers are free:
+  // in the refinement kernel, which holds no prefetched tile
+  if (REFINE && tl == kTile)
+    solve_in_lds<Tio, Tc, REFINE, SUMMARY, true>(sh, myrow, kB, tl, XLt, XRt, S, K, bp, iDf, yfo, ylo,
+                                        iters, max_iter, refine_tol);
+  else
+    solve_in_lds<Tio, Tc, REFINE, SUMMARY, false>(sh, myrow, block_len(tl), tl, XLt, XRt, S, K, bp, iDf,
+                                         yfo, ylo, iters, max_iter, refine_tol);
+}
+
+// Stores the solved tile from LDS (coalesced).  BWD: also forms this tile's
+// t-gradient partial sums against the forward solution Xfwd and writes their
+// negatives to gpart[0..2] (one barrier pair inside).
+template <typename Tio, typename Tc, bool BWD>
+__device__ __forceinline__ void store_tile(TileShared<Tio, Tc>& sh, Tio* X, const Tio* Xfwd,
+                                           int64_t base, int64_t t0, int tl, int64_t n,
+                                           double* gpart) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  constexpr int lstride = lds_stride<Tio>();
+  double s0 = 0.0, s1 = 0.0, sm1 = 0.0;
+  const __amdgpu_buffer_rsrc_t dst = make_rsrc(X + base, (int64_t)tl * sizeof(Tio));
+  // adjoint: the forward solution over this tile and one row on each side
+  // that lies inside the system (rows outside read as 0)
+  const int lo = t0 > 0 ? 1 : 0, hi = t0 + tl < n ? 1 : 0;
+  const __amdgpu_buffer_rsrc_t xf =
+      make_rsrc(BWD ? Xfwd + base - lo : X + base, BWD ? (int64_t)(lo + tl + hi) * sizeof(Tio) : 0);
+  const Tio* lr = sh.lds + opaque(lds_base<Tio>());
+  const int vs = opaque(tid * (int)sizeof(Tio));
+#pragma unroll
+  for (int j = 0; j < kB; ++j) {
+    const int e = j * kNT + tid;
+    const Tio gval = lr[j * lstride];
+    buf_store<Tio>(dst, vs + j * kNT * (int)sizeof(Tio), gval);
+    if constexpr (BWD) {
+      const int xo = vs + (j * kNT + lo) * (int)sizeof(Tio);
+      const double xe = (double)buf_load<Tio>(xf, xo);
+      const double xn = (double)buf_load<Tio>(xf, xo + (int)sizeof(Tio));
+      const double xq = (double)buf_load<Tio>(xf, xo - (int)sizeof(Tio));
+      const double gv = e < tl ? (double)gval : 0.0;
+      s0 += gv * xe;
+      s1 += gv * xn;
+      sm1 += gv * xq;
+    }
+  }
+  if constexpr (BWD) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+      s0 += __shfl_xor(s0, d, 64);
+      s1 += __shfl_xor(s1, d, 64);
+      sm1 += __shfl_xor(sm1, d, 64);
+    }
+    __syncthreads();
+    if (lane == 0) { sh.red[w][0] = sm1; sh.red[w][1] = s0; sh.red[w][2] = s1; }
+    __syncthreads();
+    if (tid == 0) {
+      double u = 0.0, v = 0.0, z = 0.0;
+      for (int q = 0; q < kNW; ++q) { u += sh.red[q][0]; v += sh.red[q][1]; z += sh.red[q][2]; }
+      gpart[0] = -u;
+      gpart[1] = -v;
+      gpart[2] = -z;
+    }
+  }
+}
+
 // Persistent workgroups over tiles; each workgroup prefetches its next tile
-// into registers while it solves the current one.
+// into registers while it solves the current one (the refinement kernel
+// loads each tile at the top of its iteration instead, trading latency
+// hiding for registers).
 //   SUMMARY = true : first pass over a tile of a multi-tile system: writes the
 //                    tile's (y_first, y_last) of its zero-boundary problem.
 //   SUMMARY = false: solves the tile given the values just outside it (zero
@@ -604,28 +824,14 @@ __device__ __forceinline__ void prefetch(const TileArgs<Tio>& A, int64_t item,
 //                    in double, repeated until converged.
 //   BWD            : also accumulates the t-gradient partial sums against the
 //                    forward solution Xfwd (the tile solves T^T gF = gX).
-#ifndef TDT_REFINE_WAVES
-#define TDT_REFINE_WAVES kMinWavesPerSimd
-#endif
-#ifndef TDT_REFINE_PREFETCH
-#define TDT_REFINE_PREFETCH 0
-#endif
 template <typename Tio, typename Tc, bool REFINE, bool SUMMARY, bool BWD>
 __global__ __launch_bounds__(kNT, REFINE ? TDT_REFINE_WAVES : kMinWavesPerSimd) void k_tile(
     TileArgs<Tio> A) {
-  constexpr int RP = kB + 16 / (int)sizeof(Tio);   // padded LDS row pitch
-  __shared__ __align__(16) Tio lds[kNT * RP];
-  __shared__ Tc fw[kNW][2], bw[kNW][2];
-  __shared__ double red[kNW][4];
-  __shared__ double edge[kNW][2];
-
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  // element j*kNT + tid of a tile lives in row j*(kNT/kB) + tid/kB, column tid%kB
-  const int lbase = (tid / kB) * RP + (tid % kB);
-  constexpr int lstride = (kNT / kB) * RP;
+  __shared__ TileShared<Tio, Tc> sh;
+  const int tid = threadIdx.x;
+  const int lbase = lds_base<Tio>();
+  constexpr int lstride = lds_stride<Tio>();
   auto item_of = [&](int64_t k) { return A.reverse ? A.nitems - 1 - k : k; };
-  // the refinement kernel may load each tile at the top of its iteration
-  // instead of one tile ahead, trading latency hiding for registers
   constexpr bool PF = !REFINE || TDT_REFINE_PREFETCH;
   int64_t k = blockIdx.x;
   Prefetch<Tio, Tc> P;
@@ -644,173 +850,167 @@ __global__ __launch_bounds__(kNT, REFINE ? TDT_REFINE_WAVES : kMinWavesPerSimd) 
 
     __syncthreads();   // the previous tile is done with LDS
     {
-      Tio* lw = lds + opaque(lbase);
+      Tio* lw = sh.lds + opaque(lbase);
 #pragma unroll
       for (int j = 0; j < kB; ++j) lw[j * lstride] = P.v[j];
     }
     const int64_t kn = k + gridDim.x;
     if (PF && kn < A.nitems) prefetch<Tio, Tc, SUMMARY>(A, item_of(kn), P);
     __syncthreads();
-    Tio* myrow = lds + tid * RP;
 
-    // The solve proper, compiled twice: for a full tile (every block has kB
-    // rows; a uniform branch selects it) and for the ragged last tile.
-    auto solve_tile = [&](auto full_tag) {
-      constexpr bool FULL = decltype(full_tag)::value;
-      const int len = FULL ? kB
-                           : (tl - tid * kB >= kB ? kB : (tl - tid * kB > 0 ? tl - tid * kB : 0));
-      if constexpr (!REFINE) {
-        Tc q[kB];
-#pragma unroll
-        for (int i = 0; i < kB; ++i) q[i] = (Tc)myrow[i];
-        if constexpr (SUMMARY) {
-          tile_solve<Tc, FULL>(q, len, Tc(0), Tc(0), K, bp, iDf, fw, bw, A.summ + 2 * slot,
-                               A.summ + 2 * slot + 1);
-        } else {
-          tile_solve<Tc, FULL>(q, len, (Tc)XLt, (Tc)XRt, K, bp, iDf, fw, bw, (double*)nullptr,
-                               (double*)nullptr);
-#pragma unroll
-          for (int i = 0; i < kB; ++i) myrow[i] = (Tio)q[i];
-        }
-      } else {
-        // iterative refinement: x_1 = solve_float(f with the tile's outside
-        // values); then repeat r = f - T x (double), d = solve_float(r) with
-        // zero outside values, x += d (double).  After update k >= 2 the next
-        // update is predicted as |d_k| rho with rho = |d_k| / |d_{k-1}|
-        // (|d_1| = |x_1|); stop when that is below tol |x_1|, when updates
-        // stop shrinking, or at the cap.  The maxima only steer the stopping
-        // test, so they are taken in float.  One barrier per update carries
-        // both the wavefront edges for the next residual and the wavefront
-        // maxima of the last update.
-        const double a = S.a, b = S.b, c = S.c;
-        double x[kB];
-        float xloc = 0.0f;
-        {
-          Tc q[kB];
-#pragma unroll
-          for (int i = 0; i < kB; ++i) {
-            double r = (double)myrow[i];
-            if (i == 0 && tid == 0) r -= a * XLt;
-            if (i == kB - 1 && tid == kNT - 1) r -= c * XRt;
-            q[i] = (FULL || i < len) ? (Tc)r : Tc(0);
-          }
-          tile_solve<Tc, FULL>(q, len, Tc(0), Tc(0), K, bp, iDf, fw, bw, (double*)nullptr,
-                               (double*)nullptr);
-#pragma unroll
-          for (int i = 0; i < kB; ++i) {
-            x[i] = (double)q[i];
-            xloc = fmaxf(xloc, fabsf((float)q[i]));
-          }
-        }
-        int it = 1;
-        float dprev = 0.0f, dloc = 0.0f, xmax = 0.0f;
-        for (;;) {
-          float dmax = 0.0f;
-          if (it >= 2) dmax = wave_max(dloc);
-          else xmax = wave_max(xloc);
-          if (lane == 0) { edge[w][0] = x[0]; red[w][0] = it >= 2 ? dmax : xmax; }
-          if (lane == 63) edge[w][1] = x[kB - 1];
-          __syncthreads();
-          if (it >= 2) {
-            dmax = (float)red[0][0];
-#pragma unroll
-            for (int q = 1; q < kNW; ++q) dmax = fmaxf(dmax, (float)red[q][0]);
-            const float rho = it == 2 ? dmax / xmax : dmax / dprev;
-            dprev = dmax;
-            if (dmax == 0.0f || (double)dmax * rho <= A.refine_tol * xmax || rho > 0.9f) break;
-          } else {
-            xmax = (float)red[0][0];
-#pragma unroll
-            for (int q = 1; q < kNW; ++q) xmax = fmaxf(xmax, (float)red[q][0]);
-          }
-          if (it >= A.max_iter) break;
-          double xm = __shfl_up(x[kB - 1], 1, 64);
-          double xp = __shfl_down(x[0], 1, 64);
-          if (lane == 0) xm = w == 0 ? XLt : edge[w > 0 ? w - 1 : 0][1];
-          if (lane == 63) xp = w == kNW - 1 ? XRt : edge[w + 1 < kNW ? w + 1 : kNW - 1][0];
-          Tc q[kB];
-#pragma unroll
-          for (int i = 0; i < kB; ++i) {
-            const double left = i == 0 ? xm : x[i - 1];
-            const double right = i + 1 < kB ? x[i + 1] : xp;
-            const double r = (double)myrow[i] - (b * x[i] + a * left + c * right);
-            q[i] = (FULL || i < len) ? (Tc)r : Tc(0);
-          }
-          tile_solve<Tc, FULL>(q, len, Tc(0), Tc(0), K, bp, iDf, fw, bw, (double*)nullptr,
-                               (double*)nullptr);
-          dloc = 0.0f;
-#pragma unroll
-          for (int i = 0; i < kB; ++i) {
-            x[i] += (double)q[i];
-            dloc = fmaxf(dloc, fabsf((float)q[i]));
-          }
-          ++it;
-          // the next barrier rewrites red[] and edge[]: every wavefront has
-          // read them once it is past the barrier inside tile_solve
-        }
-        if (tid == 0 && A.iters) atomicMax(A.iters, it);
-        if constexpr (SUMMARY) {
-          if (tid == 0) A.summ[2 * slot] = x[0];
-          if (tid == kNT - 1) A.summ[2 * slot + 1] = tl == kTile ? x[kB - 1] : 0.0;
-        } else {
-          __syncthreads();   // every lane is done reading f from LDS
-#pragma unroll
-          for (int i = 0; i < kB; ++i) myrow[i] = (Tio)x[i];
-        }
-      }
-    };
-    if (tl == kTile) solve_tile(std::true_type{});
-    else solve_tile(std::false_type{});
-
-    if constexpr (!SUMMARY) {
+    if constexpr (SUMMARY) {
+      solve_tile_lds<Tio, Tc, REFINE, true>(sh, tl, 0.0, 0.0, S, K, bp, iDf, A.summ + 2 * slot,
+                                      A.summ + 2 * slot + 1, A.iters, A.max_iter, A.refine_tol);
+    } else {
+      solve_tile_lds<Tio, Tc, REFINE, false>(sh, tl, XLt, XRt, S, K, bp, iDf, (double*)nullptr,
+                                      (double*)nullptr, A.iters, A.max_iter, A.refine_tol);
       __syncthreads();
-      double s0 = 0.0, s1 = 0.0, sm1 = 0.0;
-      const __amdgpu_buffer_rsrc_t dst = make_rsrc(A.X + G.base, (int64_t)tl * sizeof(Tio));
-      // adjoint: the forward solution over this tile and one row on each side
-      // that lies inside the system (rows outside read as 0)
-      const int lo = G.t0 > 0 ? 1 : 0, hi = G.t0 + tl < S.n ? 1 : 0;
-      const __amdgpu_buffer_rsrc_t xf =
-          make_rsrc(BWD ? A.Xfwd + G.base - lo : A.X + G.base,
-                    BWD ? (int64_t)(lo + tl + hi) * sizeof(Tio) : 0);
-      const Tio* lr = lds + opaque(lbase);
-      const int vs = opaque(tid * (int)sizeof(Tio));
-#pragma unroll
-      for (int j = 0; j < kB; ++j) {
-        const int e = j * kNT + tid;
-        const Tio gval = lr[j * lstride];
-        buf_store<Tio>(dst, vs + j * kNT * (int)sizeof(Tio), gval);
-        if constexpr (BWD) {
-          const int xo = vs + (j * kNT + lo) * (int)sizeof(Tio);
-          const double xe = (double)buf_load<Tio>(xf, xo);
-          const double xn = (double)buf_load<Tio>(xf, xo + (int)sizeof(Tio));
-          const double xq = (double)buf_load<Tio>(xf, xo - (int)sizeof(Tio));
-          const double gv = e < tl ? (double)gval : 0.0;
-          s0 += gv * xe;
-          s1 += gv * xn;
-          sm1 += gv * xq;
-        }
-      }
-      if constexpr (BWD) {
-#pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) {
-          s0 += __shfl_xor(s0, d, 64);
-          s1 += __shfl_xor(s1, d, 64);
-          sm1 += __shfl_xor(sm1, d, 64);
-        }
-        __syncthreads();
-        if (lane == 0) { red[w][0] = sm1; red[w][1] = s0; red[w][2] = s1; }
-        __syncthreads();
-        if (tid == 0) {
-          double u = 0.0, v = 0.0, z = 0.0;
-          for (int q = 0; q < kNW; ++q) { u += red[q][0]; v += red[q][1]; z += red[q][2]; }
-          const int64_t fs = A.items ? (int64_t)S.fslot0 + G.I.t : G.I.m * S.ntiles + G.I.t;
-          A.gpart[3 * fs + 0] = -u;
-          A.gpart[3 * fs + 1] = -v;
-          A.gpart[3 * fs + 2] = -z;
-        }
-      }
+      const int64_t fs = A.items ? (int64_t)S.fslot0 + G.I.t : G.I.m * S.ntiles + G.I.t;
+      store_tile<Tio, Tc, BWD>(sh, A.X, A.Xfwd, G.base, G.t0, tl, S.n, A.gpart + 3 * fs);
     }
     k = kn;
+  }
+}
+
+template <typename Tio>
+struct SysArgs {
+  const Tio* __restrict__ F;
+  Tio* __restrict__ X;
+  const SysDesc* __restrict__ sys;
+  const double* __restrict__ vec64;
+  const float* __restrict__ vec32;
+  const double* __restrict__ tab64;
+  const float* __restrict__ tab32;
+  const int* __restrict__ items;      // systems, in processing order
+  int64_t nitems;
+  const double* __restrict__ ttab;    // [2][tile slot]: beta_{t-1}, 1/(1 - Pf_t beta_{t-1})
+  int64_t ttab_n;
+  const Tio* __restrict__ Xfwd;       // adjoint: forward solution
+  double* __restrict__ gpart;         // adjoint: [final slot][3] partial t-gradients
+  int* __restrict__ iters;
+  int max_iter;
+  double refine_tol;
+};
+
+// Coalesced load of rows [base, base + tl) into the LDS tile (rows past tl
+// read as 0).  The caller brackets it with barriers.
+template <typename Tio, typename Tc>
+__device__ __forceinline__ void load_tile(TileShared<Tio, Tc>& sh, const Tio* F, int64_t base,
+                                          int tl) {
+  const __amdgpu_buffer_rsrc_t src = make_rsrc(F + base, (int64_t)tl * sizeof(Tio));
+  const int vb = opaque((int)threadIdx.x * (int)sizeof(Tio));
+  Tio v[kB];
+#pragma unroll
+  for (int j = 0; j < kB; ++j) v[j] = buf_load<Tio>(src, vb + j * kNT * (int)sizeof(Tio));
+  Tio* lw = sh.lds + opaque(lds_base<Tio>());
+  constexpr int lstride = lds_stride<Tio>();
+#pragma unroll
+  for (int j = 0; j < kB; ++j) lw[j * lstride] = v[j];
+}
+
+template <typename T>
+__device__ __forceinline__ void lane_table(const SysDesc& S, const double* tab64,
+                                           const float* tab32, T& bp, T& iD) {
+  const int tid = threadIdx.x;
+  if constexpr (sizeof(T) == 8) {
+    const double* tb = tab64 + (int64_t)S.cidx * kTabN * kNT;
+    bp = tb[kTabBeta * kNT + tid];
+    iD = tb[kTabInvD * kNT + tid];
+  } else {
+    const float* tb = tab32 + (int64_t)S.cidx * kTabN * kNT;
+    bp = tb[kTabBeta * kNT + tid];
+    iD = tb[kTabInvD * kNT + tid];
+  }
+}
+
+// One workgroup per system of at most kSysMaxTiles tiles (persistent, over a
+// list of systems).  All three steps of the method run inside the workgroup:
+//   1. every tile's summary (its first and last unknown with zero outside
+//      values), tile by tile, kept in LDS;
+//   2. the interface across the tiles: the same left-to-right and
+//      right-to-left affine recurrences as the grid interface pass (the two
+//      sums of eq. (15)), walked by one thread over the few tiles;
+//   3. the tiles solved with their outside values and stored, last tile
+//      first, so that the rows read last in step 1 are re-read from cache.
+// Summaries are computed in double for the refinement path (as in the
+// multi-kernel path), in the data precision otherwise.
+template <typename Tio, typename Tc, bool REFINE, bool BWD>
+__global__ __launch_bounds__(kNT, REFINE ? TDT_REFINE_WAVES : kMinWavesPerSimd) void k_sys(
+    SysArgs<Tio> A) {
+  using Ts = typename std::conditional<REFINE, double, Tc>::type;
+  __shared__ TileShared<Tio, Tc> sh;
+  __shared__ Ts sfw[kNW][2], sbw[kNW][2];
+  __shared__ double tsum[kSysMaxTiles][2];
+  __shared__ double tgh[kSysMaxTiles][2];
+  __shared__ double tap[kSysMaxTiles], th[kSysMaxTiles], tbp[kSysMaxTiles], tiD[kSysMaxTiles];
+  const int tid = threadIdx.x;
+
+  for (int64_t k = blockIdx.x; k < A.nitems; k += gridDim.x) {
+    const int s = as_const(A.items)[k];
+    const SysDesc S = load_sys(A.sys, s);
+    const int nt = S.ntiles;
+    if (nt > kSysMaxTiles) continue;   // never listed here (the host checks it)
+    if (nt > 1) {
+      const Consts<Ts> KS = make_consts<Ts>(S, A.vec64, A.vec32);
+      Ts sbp, siD;
+      lane_table<Ts>(S, A.tab64, A.tab32, sbp, siD);
+      for (int t = 0; t < nt; ++t) {
+        const int64_t t0 = (int64_t)t * kTile;
+        const int tl = (int)(S.n - t0 < kTile ? S.n - t0 : kTile);
+        __syncthreads();   // LDS free
+        load_tile(sh, A.F, S.off + t0, tl);
+        __syncthreads();
+        Ts q[kB];
+        const Tio* myrow = sh.lds + tid * TileShared<Tio, Tc>::RP;
+#pragma unroll
+        for (int i = 0; i < kB; ++i) q[i] = (Ts)myrow[i];
+        tile_solve<Ts, false>(q, block_len(tl), Ts(0), Ts(0), KS, sbp, siD, sfw, sbw,
+                              &tsum[t][0], &tsum[t][1]);
+      }
+      __syncthreads();
+      if (tid == 0) {
+        // beta_{t-1} and 1/(1 - Pf_t beta_{t-1}) from the plan's table
+        // (slot order of the grid interface pass)
+        double alpha = 0.0;
+        for (int t = 0; t < nt; ++t) {
+          const double* Kt = t + 1 < nt ? S.tileK : S.ltileK;
+          const int64_t pos = S.slot0 + (int64_t)(t % S.tr) * S.tq + t / S.tr;
+          const double bt = A.ttab[pos], iD = A.ttab[A.ttab_n + pos];
+          tbp[t] = bt;
+          tiD[t] = iD;
+          tap[t] = alpha;
+          th[t] = (tsum[t][0] + Kt[0] * alpha) * iD;
+          const double At = Kt[1] * iD;
+          alpha = At * alpha + (tsum[t][1] + At * bt * tsum[t][0]);
+        }
+        double u = 0.0;
+        for (int t = nt - 1; t >= 0; --t) {
+          const double* Kt = t + 1 < nt ? S.tileK : S.ltileK;
+          const double un = u;
+          u = Kt[2] * tiD[t] * u + th[t];
+          tgh[t][0] = tap[t] + tbp[t] * u;
+          tgh[t][1] = un;
+        }
+      }
+      __syncthreads();
+    }
+    const Consts<Tc> K = make_consts<Tc>(S, A.vec64, A.vec32);
+    Tc bp, iD;
+    lane_table<Tc>(S, A.tab64, A.tab32, bp, iD);
+    for (int t = nt - 1; t >= 0; --t) {
+      const int64_t t0 = (int64_t)t * kTile;
+      const int tl = (int)(S.n - t0 < kTile ? S.n - t0 : kTile);
+      const double XLt = nt > 1 ? tgh[t][0] : 0.0, XRt = nt > 1 ? tgh[t][1] : 0.0;
+      __syncthreads();   // LDS free
+      load_tile(sh, A.F, S.off + t0, tl);
+      __syncthreads();
+      solve_tile_lds<Tio, Tc, REFINE, false>(sh, tl, XLt, XRt, S, K, bp, iD, (double*)nullptr,
+                                             (double*)nullptr, A.iters, A.max_iter,
+                                             A.refine_tol);
+      __syncthreads();
+      store_tile<Tio, Tc, BWD>(sh, A.X, A.Xfwd, S.off + t0, t0, tl, S.n,
+                               A.gpart + 3 * ((int64_t)S.fslot0 + t));
+    }
   }
 }
 
@@ -1207,12 +1407,19 @@ static int num_cus() {
   return cus;
 }
 
+// Persistent grid: as many workgroups as fit on the device at once, or the
+// plan's cap per CU if lower.
+static int64_t grid_cap(int per_cu, int wg_per_cu) {
+  const int n = wg_per_cu > 0 && wg_per_cu < per_cu ? wg_per_cu : per_cu;
+  return (int64_t)n * num_cus();
+}
+
 template <typename Tio, typename Tc, bool REFINE, bool SUMMARY, bool BWD>
 static void launch_tile(TileArgs<Tio>& A, int64_t nitems, int reverse, int last_only,
-                        hipStream_t st) {
+                        int wg_per_cu, hipStream_t st) {
   auto kern = k_tile<Tio, Tc, REFINE, SUMMARY, BWD>;
   static int per_cu = resident_per_cu(kern);
-  const int64_t cap = (int64_t)per_cu * num_cus();
+  const int64_t cap = grid_cap(per_cu, wg_per_cu);
   A.nitems = nitems;
   A.reverse = reverse;
   A.last_only = last_only;
@@ -1220,11 +1427,22 @@ static void launch_tile(TileArgs<Tio>& A, int64_t nitems, int reverse, int last_
   hipLaunchKernelGGL(kern, dim3(grid), dim3(kNT), 0, st, A);
 }
 
+template <typename Tio, typename Tc, bool REFINE, bool BWD>
+static void launch_sys(const LaunchSet& L, const TileArgs<Tio>& T, hipStream_t st) {
+  auto kern = k_sys<Tio, Tc, REFINE, BWD>;
+  static int per_cu = resident_per_cu(kern);
+  const int64_t cap = grid_cap(per_cu, L.wg_per_cu);
+  SysArgs<Tio> A{T.F, T.X, T.sys, T.vec64, T.vec32, T.tab64, T.tab32, L.sys_items, L.n_sys,
+                 L.ttab, L.ttab_n, T.Xfwd, T.gpart, T.iters, T.max_iter, T.refine_tol};
+  const unsigned grid = (unsigned)(L.n_sys < cap ? L.n_sys : cap);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kNT), 0, st, A);
+}
+
 template <typename Tio>
 static void launch_beta(const LaunchSet& L, const Tio* F, hipStream_t st) {
   auto kern = k_beta<Tio>;
   static int per_cu = resident_per_cu(kern, kBetaNT);
-  const int64_t cap = (int64_t)per_cu * num_cus();
+  const int64_t cap = grid_cap(per_cu, L.wg_per_cu);
   BetaArgs<Tio> B{F, L.sys, L.green, L.n_beta, L.nfull, L.summ};
   const unsigned grid = (unsigned)(L.n_beta < cap ? L.n_beta : cap);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(kBetaNT), 0, st, B);
@@ -1258,11 +1476,11 @@ static hipError_t run_solve(const LaunchSet& L, const void* F, void* X, const vo
       if (L.n_beta > 0) launch_beta<Tio>(L, static_cast<const Tio*>(F), st);
       if (L.n_last > 0) {
         A.items = nullptr;
-        launch_tile<Tio, Ts, false, true, false>(A, L.n_last, 0, 1, st);
+        launch_tile<Tio, Ts, false, true, false>(A, L.n_last, 0, 1, L.wg_per_cu, st);
       }
     } else {
       A.items = L.p1_items;
-      launch_tile<Tio, Ts, false, true, false>(A, L.n_p1, 0, 0, st);
+      launch_tile<Tio, Ts, false, true, false>(A, L.n_p1, 0, 0, L.wg_per_cu, st);
     }
     if (L.ev) (void)hipEventRecord(L.ev[1], st);
     GridArgs G{L.sys, L.grid_items, L.ttab, L.ttab_n, L.summ, L.ghost, L.gscr};
@@ -1280,12 +1498,15 @@ static hipError_t run_solve(const LaunchSet& L, const void* F, void* X, const vo
     (void)hipEventRecord(L.ev[1], st);
     (void)hipEventRecord(L.ev[2], st);
   }
+  // systems solved whole by one workgroup each (varlen plans)
+  if (L.n_sys > 0) launch_sys<Tio, Tc, REFINE, BWD>(L, A, st);
   A.items = L.fin_items;
   // after a first pass the final pass re-reads the tiles the first pass read
   // last while they are still cached: a series runs last-tile-first, a varlen
   // plan's list already starts with the first pass's tiles in reverse
-  launch_tile<Tio, Tc, REFINE, false, BWD>(A, L.n_fin, (L.n_p1 > 0 && !L.fin_items) ? 1 : 0,
-                                           0, st);
+  if (L.n_fin > 0)
+    launch_tile<Tio, Tc, REFINE, false, BWD>(A, L.n_fin, (L.n_p1 > 0 && !L.fin_items) ? 1 : 0,
+                                             0, L.wg_per_cu, st);
   if (L.ev) (void)hipEventRecord(L.ev[3], st);
   return hipGetLastError();
 }

@@ -60,16 +60,42 @@ def test_adjoint_finite_differences():
     assert abs(float(to_host(gF) @ v) - fd_dir) <= 1e-6 * max(1.0, abs(fd_dir))
 
 
+@pytest.mark.parametrize("whole", [0, 8])
 @pytest.mark.parametrize("dtype", ["f64", "f32_refine"])
-def test_adjoint_varlen_diff_batch(dtype):
+def test_adjoint_varlen_diff_batch(dtype, whole):
     tdt = _tdt()
+    print(f"[case] adjoint diff batch dtype={dtype} whole_max_tiles={whole}", flush=True)
     d = W.diff_batch(0, s=256)       # 256 systems of 16384 (two tiles each)
     off = d["offsets"]
     plan = tdt.VarlenPlan(off, d["t_m1"], d["t_0"], d["t_1"], dtype)
+    plan.set_option("whole_max_tiles", whole)
     Xd = plan.solve(to_dev(d["F"].reshape(-1)))
     gF, gt = plan.backward(to_dev(d["W"].reshape(-1)), Xd)
     X = oracle.solve_varlen(d["F"].reshape(-1), off, d["t_m1"], d["t_0"], d["t_1"])
     gFr, gtr = oracle.adjoint_varlen(d["W"].reshape(-1), X, off, d["t_m1"], d["t_0"], d["t_1"])
+    assert oracle.rel_err_rows(to_host(gF), gFr, off).max() <= 1e-12
+    gt = to_host(gt)
+    assert np.max(np.abs(gt - gtr) / np.maximum(1.0, np.abs(gtr))) <= 1e-11
+
+
+@pytest.mark.parametrize("whole", [0, 16])
+def test_adjoint_varlen_ragged(whole):
+    """Adjoint of systems of 1 to 13 tiles with ragged ends, both paths."""
+    tdt = _tdt()
+    print(f"[case] adjoint varlen ragged whole_max_tiles={whole}", flush=True)
+    rng = np.random.default_rng(21)
+    sizes = np.array([1, 3, 8193, 100000, 64, 16385, 2])
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    ts = [W.random_system(rng, 1.1, 3.0) for _ in sizes]
+    tm1, t0, t1 = (np.array([t[k] for t in ts]) for k in range(3))
+    F = rng.standard_normal(int(off[-1]))
+    G = rng.standard_normal(int(off[-1]))
+    plan = tdt.VarlenPlan(off, tm1, t0, t1, "f64")
+    plan.set_option("whole_max_tiles", whole)
+    Xd = plan.solve(to_dev(F))
+    gF, gt = plan.backward(to_dev(G), Xd)
+    X = oracle.solve_varlen(F, off, tm1, t0, t1)
+    gFr, gtr = oracle.adjoint_varlen(G, X, off, tm1, t0, t1)
     assert oracle.rel_err_rows(to_host(gF), gFr, off).max() <= 1e-12
     gt = to_host(gt)
     assert np.max(np.abs(gt - gtr) / np.maximum(1.0, np.abs(gtr))) <= 1e-11

@@ -121,3 +121,56 @@ def test_capture_without_reserve_is_refused():
         with torch.cuda.graph(g):
             plan.solve(Fd, Xd)
     assert e.value.status == _lib.TDT_ERR_CAPTURE
+
+
+def test_options_validation():
+    tdt = _tdt()
+    plan = tdt.Plan(-1.0, 3.0, -1.0, 1000)
+    with pytest.raises(tdt.TDTError):
+        plan.set_option("whole_max_tiles", 4)           # series plan: no such choice
+    off = np.array([0, 100, 20000], dtype=np.int64)
+    vp = tdt.VarlenPlan(off, -1.0, 3.0, -1.0)
+    for name, bad in (("whole_max_tiles", -1), ("whole_max_tiles", 17), ("wg_per_cu", -1),
+                      ("max_refine", 0), ("max_refine", 101)):
+        with pytest.raises(tdt.TDTError) as e:
+            vp.set_option(name, bad)
+        assert e.value.status == _lib.TDT_ERR_INVALID_ARG
+    assert vp.get_option("whole_max_tiles") == 8
+    assert vp.get_option("wg_per_cu") == 0
+    assert vp.get_option("max_refine") == 40
+
+
+def test_autotune_choice_cache_and_result(tmp_path, monkeypatch):
+    """The autotuner times the launch shapes, keeps one, writes its cache
+    file, reuses the entry without timing, and every shape gives the same
+    solution (checked against the oracle)."""
+    import json
+    tdt = _tdt()
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("TDT_TUNE_CACHE", str(cache))
+    rng = np.random.default_rng(5)
+    sizes = np.array([30000, 700, 9000, 17, 20000, 65536])
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    t0 = rng.uniform(2.5, 4.0, len(sizes))
+    F = rng.standard_normal(int(off[-1]))
+    ref = oracle.solve_varlen(F, off, -1.0, t0, -0.9)
+    plan = tdt.VarlenPlan(off, -1.0, t0, -0.9, "f32_refine")
+    Fd = to_dev(F)
+    res = plan.autotune(Fd)
+    assert res["ms"] > 0 and res["whole_max_tiles"] in (0, 1, 2, 4, 8, 16)
+    assert res["wg_per_cu"] in (0, 1)
+    X = to_host(plan.solve(Fd))
+    assert oracle.rel_err_rows(X, ref, off).max() <= 1e-12
+    doc = json.loads(cache.read_text())
+    assert doc["format"] == "tdt-autotune-1" and len(doc["entries"]) == 1
+    (key, entry), = doc["entries"].items()
+    assert "varlen|f32_refine" in key and entry["whole_max_tiles"] == res["whole_max_tiles"]
+    plan2 = tdt.VarlenPlan(off, -1.0, t0, -0.9, "f32_refine")
+    res2 = plan2.autotune(Fd)                     # from the cache: no timing
+    assert res2["ms"] == 0.0 and res2["whole_max_tiles"] == res["whole_max_tiles"]
+    # a series plan gets its own entry
+    sp = tdt.Plan(-1.0, 3.0, -1.0, 20000, "f64")
+    Fs = to_dev(rng.standard_normal((2, 20000)))
+    r3 = sp.autotune(Fs, force=True)
+    assert r3["ms"] > 0
+    assert len(json.loads(cache.read_text())["entries"]) == 2

@@ -77,9 +77,12 @@ def test_single_large_config(dtype):
     assert oracle.rel_err(X, ref) <= 1e-12
 
 
-def _varlen_check(d, dtype, tol_of):
+def _varlen_check(d, dtype, tol_of, whole=None):
     tdt = _tdt()
     plan = tdt.VarlenPlan(d["offsets"], d["t_m1"], d["t_0"], d["t_1"], dtype)
+    if whole is not None:
+        plan.set_option("whole_max_tiles", whole)
+        assert plan.get_option("whole_max_tiles") == whole
     X = to_host(plan.solve(to_dev(d["F"], dtype)))
     F = d["F"].astype(np.float32).astype(np.float64) if dtype == "f32" else d["F"]
     ref = oracle.solve_varlen(F, d["offsets"], d["t_m1"], d["t_0"], d["t_1"])
@@ -92,8 +95,12 @@ def _varlen_check(d, dtype, tol_of):
     return plan
 
 
+@pytest.mark.parametrize("whole", [0, 1, 2, 8, 16])
 @pytest.mark.parametrize("dtype", ["f64", "f32_refine", "f32"])
-def test_varlen_ragged(dtype):
+def test_varlen_ragged(dtype, whole):
+    """Systems of 1 to 13 tiles, solved whole by one workgroup each up to
+    `whole` tiles and by the three-kernel path beyond."""
+    print(f"[case] varlen ragged dtype={dtype} whole_max_tiles={whole}", flush=True)
     rng = np.random.default_rng(7)
     sizes = np.array([1, 2, 3, 33, 8192, 8193, 65, 20000, 5, 16384, 31, 64, 100000])
     S = len(sizes)
@@ -101,13 +108,15 @@ def test_varlen_ragged(dtype):
     ts = [W.random_system(rng, 1.25 if dtype == "f32" else 1.0, 3.0) for _ in range(S)]
     d = dict(offsets=off, t_m1=np.array([t[0] for t in ts]), t_0=np.array([t[1] for t in ts]),
              t_1=np.array([t[2] for t in ts]), F=rng.standard_normal(int(off[-1])))
-    _varlen_check(d, dtype, tol_f32 if dtype == "f32" else tol_f64)
+    _varlen_check(d, dtype, tol_f32 if dtype == "f32" else tol_f64, whole)
 
 
+@pytest.mark.parametrize("whole", [0, 8])
 @pytest.mark.parametrize("dtype", ["f64", "f32_refine"])
-def test_sov_batch_config(dtype):
+def test_sov_batch_config(dtype, whole):
+    print(f"[case] sov batch dtype={dtype} whole_max_tiles={whole}", flush=True)
     d = W.sov_batch(0)
-    plan = _varlen_check(d, dtype, tol_f64)
+    plan = _varlen_check(d, dtype, tol_f64, whole)
     # against the long double truth too (the ill-conditioned low modes)
     X = to_host(plan.solve(to_dev(d["F"])))
     truth = oracle.solve_varlen(d["F"], d["offsets"], d["t_m1"], d["t_0"], d["t_1"],
@@ -118,11 +127,13 @@ def test_sov_batch_config(dtype):
     assert np.all(errs <= tols)
 
 
+@pytest.mark.parametrize("whole", [0, 8])
 @pytest.mark.parametrize("dtype", ["f64", "f32_refine"])
-def test_diff_batch_config_forward(dtype):
+def test_diff_batch_config_forward(dtype, whole):
+    print(f"[case] diff batch forward dtype={dtype} whole_max_tiles={whole}", flush=True)
     d = W.diff_batch(0)
     _varlen_check(dict(offsets=d["offsets"], t_m1=d["t_m1"], t_0=d["t_0"], t_1=d["t_1"],
-                       F=d["F"].reshape(-1)), dtype, tol_f64)
+                       F=d["F"].reshape(-1)), dtype, tol_f64, whole)
 
 
 def test_repeatable_bitwise():
@@ -135,6 +146,18 @@ def test_repeatable_bitwise():
         X1 = to_host(plan.solve(F))
         X2 = to_host(plan.solve(F))
         assert np.array_equal(X1, X2)
+    # varlen, both paths, and a different workgroup count (the persistent
+    # grid must not change any result)
+    sizes = np.array([40000, 9000, 300, 8192, 17])
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    Fv = to_dev(rng.standard_normal(int(off[-1])))
+    for whole in (0, 8):
+        plan = tdt.VarlenPlan(off, -1.0, 3.2, -0.7, "f32_refine")
+        plan.set_option("whole_max_tiles", whole)
+        X1 = to_host(plan.solve(Fv))
+        plan.set_option("wg_per_cu", 1)
+        X2 = to_host(plan.solve(Fv))
+        assert np.array_equal(X1, X2), whole
 
 
 @pytest.mark.parametrize("tiles,extra", [(257, 0), (2048, 17), (2049, 3), (8193, 100)])
