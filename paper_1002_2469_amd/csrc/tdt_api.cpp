@@ -14,6 +14,7 @@
 #include <limits>
 #include <new>
 #include <numeric>
+#include <queue>
 #include <vector>
 
 #include "tdt.h"
@@ -48,7 +49,8 @@ struct tdt_plan_s {
   int2* dfin = nullptr;
   int* dgrid = nullptr;
   int* dwhole = nullptr;
-  int64_t n_p1 = 0, n_fin = 0, n_grid = 0, n_whole = 0;
+  int* dbins = nullptr;
+  int64_t n_p1 = 0, n_fin = 0, n_grid = 0, n_whole = 0, n_bins = 0;
   int64_t vslots = 0, vfslots = 0;
   // workspace
   int64_t ws_slots = 0, ws_fslots = 0;
@@ -369,6 +371,7 @@ void destroy(tdt_plan_s* p) {
   (void)hipFree(p->dfin);
   (void)hipFree(p->dgrid);
   (void)hipFree(p->dwhole);
+  (void)hipFree(p->dbins);
   (void)hipFree(p->iters);
   free_workspace(p);
   delete p;
@@ -381,11 +384,11 @@ void destroy(tdt_plan_s* p) {
 // recently read, still cached, tiles first).
 tdt_status_t build_varlen_lists(tdt_plan_s* p) {
   std::vector<int2> p1, fin;
-  std::vector<int> grid, whole;
+  std::vector<int> grid, whole_sys;
   for (int64_t s : p->order) {
     const int nt = p->hsys[0][s].ntiles;
     if (nt <= p->sys_max_tiles) {
-      whole.push_back((int)s);
+      whole_sys.push_back((int)s);
     } else {
       for (int t = 0; t < nt; ++t) p1.push_back(make_int2((int)s, t));
       if (nt > 1) grid.push_back((int)s);
@@ -400,20 +403,50 @@ tdt_status_t build_varlen_lists(tdt_plan_s* p) {
            p1.end());
   fin.assign(p1.rbegin(), p1.rend());
   fin.insert(fin.end(), single.begin(), single.end());
+  // Whole systems over the resident workgroups, longest processing time
+  // first: each system (largest first) goes to the least loaded list.  A
+  // system of nt tiles costs about 2 nt tile steps (summaries, then the
+  // solve), a one-tile system one.
+  std::vector<int> whole, bins;
+  if (!whole_sys.empty()) {
+    const int64_t G = std::min<int64_t>(
+        (int64_t)whole_sys.size(),
+        std::max(1, tdt::sys_wg_capacity((int)p->dtype, p->wg_per_cu)));
+    std::vector<std::vector<int>> lists((size_t)G);
+    typedef std::pair<int64_t, int64_t> Load;   // (cost so far, list)
+    std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
+    for (int64_t b = 0; b < G; ++b) heap.push(Load(0, b));
+    for (int s : whole_sys) {
+      const int nt = p->hsys[0][s].ntiles;
+      Load l = heap.top();
+      heap.pop();
+      lists[(size_t)l.second].push_back(s);
+      l.first += nt > 1 ? 2 * nt : 1;
+      heap.push(l);
+    }
+    bins.push_back(0);
+    for (const auto& l : lists) {
+      whole.insert(whole.end(), l.begin(), l.end());
+      bins.push_back((int)whole.size());
+    }
+  }
   (void)hipFree(p->dp1);
   (void)hipFree(p->dfin);
   (void)hipFree(p->dgrid);
   (void)hipFree(p->dwhole);
+  (void)hipFree(p->dbins);
   p->dp1 = p->dfin = nullptr;
-  p->dgrid = p->dwhole = nullptr;
+  p->dgrid = p->dwhole = p->dbins = nullptr;
   p->n_p1 = (int64_t)p1.size();
   p->n_fin = (int64_t)fin.size();
   p->n_grid = (int64_t)grid.size();
   p->n_whole = (int64_t)whole.size();
+  p->n_bins = bins.empty() ? 0 : (int64_t)bins.size() - 1;
   tdt_status_t st = dev_upload(&p->dp1, p1.data(), p1.size());
   if (st == TDT_OK) st = dev_upload(&p->dfin, fin.data(), fin.size());
   if (st == TDT_OK) st = dev_upload(&p->dgrid, grid.data(), grid.size());
   if (st == TDT_OK) st = dev_upload(&p->dwhole, whole.data(), whole.size());
+  if (st == TDT_OK) st = dev_upload(&p->dbins, bins.data(), bins.size());
   return st;
 }
 
@@ -571,6 +604,8 @@ tdt_status_t run(tdt_plan_s* p, int dir, const void* F, void* X, const void* Xfw
     L.fin_items = p->dfin;
     L.grid_items = p->dgrid;
     L.sys_items = p->dwhole;
+    L.sys_bins = p->dbins;
+    L.n_bins = p->n_bins;
     L.n_p1 = p->n_p1;
     L.n_fin = p->n_fin;
     L.n_grid = p->n_grid;
@@ -583,6 +618,8 @@ tdt_status_t run(tdt_plan_s* p, int dir, const void* F, void* X, const void* Xfw
     L.fin_items = nullptr;
     L.grid_items = nullptr;
     L.sys_items = nullptr;
+    L.sys_bins = nullptr;
+    L.n_bins = 0;
     L.n_sys = 0;
     L.green = p->dgreen[dir];
     L.nfull = (int)(p->N % kTile == 0 ? nt : nt - 1);
@@ -890,8 +927,11 @@ tdt_status_t tdt_plan_set_option(tdt_plan_t p, tdt_option_t opt, int64_t value) 
     }
     case TDT_OPT_WG_PER_CU:
       if (value < 0 || value > 64) return TDT_ERR_INVALID_ARG;
+      if ((int)value == p->wg_per_cu) return TDT_OK;
       p->wg_per_cu = (int)value;
-      return TDT_OK;
+      if (!p->varlen) return TDT_OK;
+      if (hipDeviceSynchronize() != hipSuccess) return TDT_ERR_HIP;
+      return build_varlen_lists(p);   // the whole-system lists follow the grid
     case TDT_OPT_MAX_REFINE:
       if (value < 1 || value > 100) return TDT_ERR_INVALID_ARG;
       p->max_iter = (int)value;

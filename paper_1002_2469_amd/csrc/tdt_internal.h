@@ -73,7 +73,9 @@ struct LaunchSet {
   const int2* p1_items;    // varlen: (system, tile) of the first pass; null for a series
   const int2* fin_items;   // varlen: (system, tile) of the final pass
   const int* grid_items;   // varlen: systems with more than one tile
-  const int* sys_items;    // varlen: systems solved whole by one workgroup each
+  const int* sys_items;    // varlen: systems solved whole by one workgroup each,
+  const int* sys_bins;     //   grouped by workgroup: bin b = sys_items[sys_bins[b] ..
+  int64_t n_bins;          //   sys_bins[b+1]), one workgroup per bin
   int64_t n_p1, n_fin, n_grid, n_sys;
   // series plans with more than one tile: the first pass is a dot product of
   // every full tile with the tile's Green rows (n_beta items), plus the
@@ -101,6 +103,9 @@ struct LaunchSet {
 // dtype: 0 double, 1 float, 2 float sweeps with double refinement.
 hipError_t launch_solve(int dtype, bool bwd, const LaunchSet& L, const void* F, void* X,
                         const void* Xfwd, hipStream_t st);
+// Workgroups of the whole-system kernel that are resident at once (the
+// plan spreads its systems over this many lists).
+int sys_wg_capacity(int dtype, int wg_per_cu);
 hipError_t launch_gt_reduce(const double* gpart, const SysDesc* sys, int64_t nsys,
                             int64_t nparts, int varlen, double* gt, hipStream_t st);
 

@@ -881,8 +881,8 @@ struct SysArgs {
   const float* __restrict__ vec32;
   const double* __restrict__ tab64;
   const float* __restrict__ tab32;
-  const int* __restrict__ items;      // systems, in processing order
-  int64_t nitems;
+  const int* __restrict__ items;      // systems, grouped by workgroup
+  const int* __restrict__ bins;       // workgroup b takes items[bins[b] .. bins[b+1])
   const double* __restrict__ ttab;    // [2][tile slot]: beta_{t-1}, 1/(1 - Pf_t beta_{t-1})
   int64_t ttab_n;
   const Tio* __restrict__ Xfwd;       // adjoint: forward solution
@@ -923,8 +923,8 @@ __device__ __forceinline__ void lane_table(const SysDesc& S, const double* tab64
   }
 }
 
-// One workgroup per system of at most kSysMaxTiles tiles (persistent, over a
-// list of systems).  All three steps of the method run inside the workgroup:
+// One workgroup per system of at most kSysMaxTiles tiles; each workgroup
+// works through its own list of systems (the host balances the lists).  All three steps of the method run inside the workgroup:
 //   1. every tile's summary (its first and last unknown with zero outside
 //      values), tile by tile, kept in LDS;
 //   2. the interface across the tiles: the same left-to-right and
@@ -944,8 +944,29 @@ __global__ __launch_bounds__(kNT, REFINE ? TDT_REFINE_WAVES : kMinWavesPerSimd) 
   __shared__ double tgh[kSysMaxTiles][2];
   __shared__ double tap[kSysMaxTiles], th[kSysMaxTiles], tbp[kSysMaxTiles], tiD[kSysMaxTiles];
   const int tid = threadIdx.x;
+  constexpr int lstride = lds_stride<Tio>();
+  // The next tile of the system is loaded into registers while the current
+  // one is solved, unless the refinement solve needs those registers.
+  constexpr bool PF = !REFINE;
+  Tio pv[kB];
+  auto issue = [&](int64_t base, int tl) {
+    const __amdgpu_buffer_rsrc_t src = make_rsrc(A.F + base, (int64_t)tl * sizeof(Tio));
+    const int vb = opaque(tid * (int)sizeof(Tio));
+#pragma unroll
+    for (int j = 0; j < kB; ++j) pv[j] = buf_load<Tio>(src, vb + j * kNT * (int)sizeof(Tio));
+  };
+  auto commit = [&]() {
+    Tio* lw = sh.lds + opaque(lds_base<Tio>());
+#pragma unroll
+    for (int j = 0; j < kB; ++j) lw[j * lstride] = pv[j];
+  };
+  auto tile_len = [](const SysDesc& S, int t) {
+    const int64_t t0 = (int64_t)t * kTile;
+    return (int)(S.n - t0 < kTile ? S.n - t0 : kTile);
+  };
 
-  for (int64_t k = blockIdx.x; k < A.nitems; k += gridDim.x) {
+  const int kb = as_const(A.bins)[blockIdx.x], ke = as_const(A.bins)[blockIdx.x + 1];
+  for (int k = kb; k < ke; ++k) {
     const int s = as_const(A.items)[k];
     const SysDesc S = load_sys(A.sys, s);
     const int nt = S.ntiles;
@@ -955,10 +976,11 @@ __global__ __launch_bounds__(kNT, REFINE ? TDT_REFINE_WAVES : kMinWavesPerSimd) 
       Ts sbp, siD;
       lane_table<Ts>(S, A.tab64, A.tab32, sbp, siD);
       for (int t = 0; t < nt; ++t) {
-        const int64_t t0 = (int64_t)t * kTile;
-        const int tl = (int)(S.n - t0 < kTile ? S.n - t0 : kTile);
+        const int tl = tile_len(S, t);
         __syncthreads();   // LDS free
-        load_tile(sh, A.F, S.off + t0, tl);
+        if (!PF || t == 0) load_tile(sh, A.F, S.off + (int64_t)t * kTile, tl);
+        else commit();
+        if (PF && t + 1 < nt) issue(S.off + (int64_t)(t + 1) * kTile, tile_len(S, t + 1));
         __syncthreads();
         Ts q[kB];
         const Tio* myrow = sh.lds + tid * TileShared<Tio, Tc>::RP;
@@ -999,11 +1021,16 @@ __global__ __launch_bounds__(kNT, REFINE ? TDT_REFINE_WAVES : kMinWavesPerSimd) 
     lane_table<Tc>(S, A.tab64, A.tab32, bp, iD);
     for (int t = nt - 1; t >= 0; --t) {
       const int64_t t0 = (int64_t)t * kTile;
-      const int tl = (int)(S.n - t0 < kTile ? S.n - t0 : kTile);
+      const int tl = tile_len(S, t);
       const double XLt = nt > 1 ? tgh[t][0] : 0.0, XRt = nt > 1 ? tgh[t][1] : 0.0;
-      __syncthreads();   // LDS free
-      load_tile(sh, A.F, S.off + t0, tl);
-      __syncthreads();
+      // the last tile of a multi-tile system is still in LDS from its summary
+      if (nt == 1 || t < nt - 1) {
+        __syncthreads();   // LDS free
+        if (PF && t < nt - 1) commit();
+        else load_tile(sh, A.F, S.off + t0, tl);
+        __syncthreads();
+      }
+      if (PF && t > 0) issue(S.off + t0 - kTile, kTile);
       solve_tile_lds<Tio, Tc, REFINE, false>(sh, tl, XLt, XRt, S, K, bp, iD, (double*)nullptr,
                                              (double*)nullptr, A.iters, A.max_iter,
                                              A.refine_tol);
@@ -1429,13 +1456,21 @@ static void launch_tile(TileArgs<Tio>& A, int64_t nitems, int reverse, int last_
 
 template <typename Tio, typename Tc, bool REFINE, bool BWD>
 static void launch_sys(const LaunchSet& L, const TileArgs<Tio>& T, hipStream_t st) {
-  auto kern = k_sys<Tio, Tc, REFINE, BWD>;
-  static int per_cu = resident_per_cu(kern);
-  const int64_t cap = grid_cap(per_cu, L.wg_per_cu);
-  SysArgs<Tio> A{T.F, T.X, T.sys, T.vec64, T.vec32, T.tab64, T.tab32, L.sys_items, L.n_sys,
-                 L.ttab, L.ttab_n, T.Xfwd, T.gpart, T.iters, T.max_iter, T.refine_tol};
-  const unsigned grid = (unsigned)(L.n_sys < cap ? L.n_sys : cap);
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(kNT), 0, st, A);
+  SysArgs<Tio> A{T.F,         T.X,         T.sys,      T.vec64,  T.vec32,   T.tab64,
+                 T.tab32,     L.sys_items, L.sys_bins, L.ttab,   L.ttab_n,  T.Xfwd,
+                 T.gpart,     T.iters,     T.max_iter, T.refine_tol};
+  hipLaunchKernelGGL((k_sys<Tio, Tc, REFINE, BWD>), dim3((unsigned)L.n_bins), dim3(kNT), 0, st,
+                     A);
+}
+
+int sys_wg_capacity(int dtype, int wg_per_cu) {
+  int per_cu;
+  switch (dtype) {
+    case 0: per_cu = resident_per_cu(k_sys<double, double, false, false>); break;
+    case 1: per_cu = resident_per_cu(k_sys<float, float, false, false>); break;
+    default: per_cu = resident_per_cu(k_sys<double, float, true, false>); break;
+  }
+  return (int)grid_cap(per_cu, wg_per_cu);
 }
 
 template <typename Tio>
