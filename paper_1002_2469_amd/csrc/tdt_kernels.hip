@@ -714,7 +714,10 @@ __device__ __forceinline__ void solve_in_lds(TileShared<Tio, Tc>& sh, Tio* myrow
       for (int i = 0; i < kB; ++i) {
         const double left = i == 0 ? xm : x[i - 1];
         const double right = i + 1 < kB ? x[i + 1] : xp;
-        const double r = (double)myrow[i] - (b * x[i] + a * left + c * right);
+        // r = f - (t_0 x_i + t_-1 x_{i-1} + t_1 x_{i+1}), three fused steps
+        double r = fma(-b, x[i], (double)myrow[i]);
+        r = fma(-a, left, r);
+        r = fma(-c, right, r);
         q[i] = (FULL || i < len) ? (Tc)r : Tc(0);
       }
       tile_solve<Tc, FULL>(q, len, Tc(0), Tc(0), K, bp, iDf, sh.fw, sh.bw, (double*)nullptr,
