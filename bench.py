@@ -123,9 +123,12 @@ def tile_counts(d):
     return int(sizes[sizes > tile].sum()), int(sizes.sum())
 
 
-def run_mode(tdt, d, F, X, mode, steps, warmup, torch):
+def run_mode(tdt, d, F, X, mode, steps, warmup, torch, autotune=True):
     plan = make_plan(tdt, d, mode)
     plan.reserve(d.get("M", 1))
+    # the library's autotuner picks the work shape and launch options on
+    # this data (timed afresh, not from a cache file)
+    tuned = plan.autotune(F, X, cache=False) if autotune else None
     adj = d.get("adjoint", False)
     gX = gF = gt = None
     if adj:
@@ -189,7 +192,7 @@ def run_mode(tdt, d, F, X, mode, steps, warmup, torch):
     torch.cuda.synchronize()
     ms = start.elapsed_time(stop) / steps
     out = dict(ms=ms, kernels_ms=kern, refine_iters=info["refine_iters"],
-               X=X.cpu().numpy().reshape(-1))
+               X=X.cpu().numpy().reshape(-1), tuned=tuned)
     if adj:
         out["gF"] = gF.cpu().numpy().reshape(-1)
         out["gt"] = gt.cpu().numpy()
@@ -237,6 +240,8 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain device copy of F (counter calibration)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="time the default work shape instead of the autotuner's choice")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -256,7 +261,8 @@ def main() -> int:
     modes = [m for m in args.modes.split(",") if m]
     res = {}
     for mode in modes:
-        res[mode] = run_mode(tdt, d, F, X, mode, args.steps, args.warmup, torch)
+        res[mode] = run_mode(tdt, d, F, X, mode, args.steps, args.warmup, torch,
+                             autotune=not args.no_autotune)
         print(f"[bench] {args.workload} {mode}: {res[mode]['ms']:.4f} ms/step  kernels(ms) "
               f"{json.dumps({k: round(v, 5) for k, v in res[mode]['kernels_ms'].items()})}",
               file=sys.stderr, flush=True)
@@ -310,7 +316,8 @@ def main() -> int:
         r = res[mode]
         return {"value": U / (r["ms"] * 1e-3), "unit": "unknowns/s", "ms_per_step": r["ms"],
                 "kernels_ms": {k: round(v, 6) for k, v in r["kernels_ms"].items()},
-                "rel_err_vs_oracle": err_of(mode), "refine_iters": r["refine_iters"]}
+                "rel_err_vs_oracle": err_of(mode), "refine_iters": r["refine_iters"],
+                "tuned": r["tuned"]}
 
     hk = res[head]["kernels_ms"]
     dom = max((k for k in per_launch if hk.get(k, 0) > 0 and per_launch[k] > 0),

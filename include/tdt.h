@@ -49,7 +49,7 @@ typedef enum {
     TDT_ERR_SINGULAR = -2,      /* T, or one of the sub-blocks the method inverts, is singular */
     TDT_ERR_HIP = -3,           /* a HIP runtime call or kernel launch failed */
     TDT_ERR_OOM = -4,           /* device or host allocation failed */
-    TDT_ERR_NOT_CONVERGED = -5, /* reserved: refinement did not converge */
+    TDT_ERR_NOT_CONVERGED = -5, /* refinement did not converge (tdt_last_info) */
     TDT_ERR_CAPTURE = -6        /* would allocate during stream capture: call tdt_plan_reserve first */
 } tdt_status_t;
 
@@ -121,13 +121,23 @@ tdt_status_t tdt_plan_destroy(tdt_plan_t plan);
 /* Static string for a status code. */
 const char *tdt_status_string(tdt_status_t status);
 
-/* Facts about a plan (any pointer may be NULL): refinement iterations the
- * last TDT_F32_REFINE solve needed at most (0 otherwise; read back from the
- * device, so this call synchronises the device), the dominance ratio
- * min_s |t_0|/(|t_1|+|t_-1|), and the 2-norm condition number of T (the
- * largest over systems), from the closed-form spectrum
- * t_0 + 2 sgn(t_1) sqrt(t_1 t_-1) cos(k pi/(N+1)) when t_1 t_-1 > 0, else the
- * infinity-norm bound from dominance (infinite when not dominant). */
+/* Facts about a plan (any pointer may be NULL).  For TDT_F32_REFINE solves
+ * since the previous call that asked for them (read back from the device, so
+ * asking synchronises the device; the record is then cleared):
+ * *n_refine_iters = the most float solves any tile needed (0 when no such
+ * solve ran), *last_rel_update = the largest estimated remaining relative
+ * error of a tile: the size of the update the iteration would make next,
+ * |d_k| rho / |x| with rho = |d_k| / |d_{k-1}| the observed contraction, or
+ * |d_k| / |x| when updates stopped shrinking (1 when a tile ran no update).
+ * Always: the dominance
+ * ratio min_s |t_0|/(|t_1|+|t_-1|), and the 2-norm condition number of T
+ * (the largest over systems), from the closed-form spectrum
+ * t_0 + 2 sgn(t_1) sqrt(t_1 t_-1) cos(k pi/(N+1)) when t_1 t_-1 > 0, else
+ * the infinity-norm bound from dominance (infinite when not dominant).
+ * Returns TDT_ERR_NOT_CONVERGED (outputs still filled) when that estimate
+ * is above 1e-7, i.e. refinement stopped (at TDT_OPT_MAX_REFINE, or because
+ * its updates stopped shrinking) without getting past float resolution: X
+ * then holds the last iterate. */
 tdt_status_t tdt_last_info(tdt_plan_t plan, int *n_refine_iters,
                            double *last_rel_update, double *dominance,
                            double *kappa2);
@@ -177,23 +187,31 @@ tdt_status_t tdt_plan_profile_read(tdt_plan_t plan, double *ms3, int64_t *nsolve
  *   TDT_OPT_WG_PER_CU        cap on the persistent workgroups per compute
  *       unit of every kernel; 0 (default) = as many as fit.
  *   TDT_OPT_MAX_REFINE       TDT_F32_REFINE: most float solves per tile
- *       (1..100, default 40). */
+ *       (1..100, default 40).
+ *   TDT_OPT_SHAPE            work shape of the tile kernels: 0 = blocks of
+ *       16 rows per lane and 512 lanes per workgroup (tiles of 8192 rows,
+ *       default), 1 = 8 rows x 512 lanes (tiles of 4096), 2 = 16 rows x 256
+ *       lanes (tiles of 4096).  Setting it rebuilds the plan's tables for the
+ *       new block length (blocking; results change only by rounding). */
 typedef enum {
     TDT_OPT_WHOLE_MAX_TILES = 0,
     TDT_OPT_WG_PER_CU = 1,
-    TDT_OPT_MAX_REFINE = 2
+    TDT_OPT_MAX_REFINE = 2,
+    TDT_OPT_SHAPE = 3
 } tdt_option_t;
 
 /* Set / read an option.  Errors: unknown option, value out of range, or
  * TDT_OPT_WHOLE_MAX_TILES on a series plan -> TDT_ERR_INVALID_ARG.  Setting
- * TDT_OPT_WHOLE_MAX_TILES rebuilds the plan's work lists (blocking) and must
- * not happen while a solve of the plan may run or is being captured. */
+ * TDT_OPT_WHOLE_MAX_TILES, TDT_OPT_WG_PER_CU (varlen) or TDT_OPT_SHAPE
+ * rebuilds the plan's work lists or tables (blocking; a reservation made
+ * with tdt_plan_reserve is renewed) and must not happen while a solve of the
+ * plan may run or is being captured. */
 tdt_status_t tdt_plan_set_option(tdt_plan_t plan, tdt_option_t opt, int64_t value);
 tdt_status_t tdt_plan_get_option(tdt_plan_t plan, tdt_option_t opt, int64_t *value);
 
-/* Autotuner: times the candidate launch shapes (TDT_OPT_WG_PER_CU, and
- * TDT_OPT_WHOLE_MAX_TILES for varlen plans) on the caller's data with HIP
- * events on `stream`, and keeps the fastest.  F, X (and M for a series
+/* Autotuner: times the candidate work and launch shapes (TDT_OPT_SHAPE,
+ * TDT_OPT_WG_PER_CU, and TDT_OPT_WHOLE_MAX_TILES for varlen plans) on the
+ * caller's data with HIP events on `stream`, and keeps the fastest.  F, X (and M for a series
  * plan; ignored for varlen) as for tdt_solve / tdt_solve_varlen; X is
  * overwritten by the trial solves (it ends holding the solution).
  * Synchronises the stream; refused while it is being captured

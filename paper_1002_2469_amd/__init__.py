@@ -22,7 +22,7 @@ import numpy as np
 from . import _lib
 from ._lib import DTYPES, TDTError, build
 
-__all__ = ["Plan", "VarlenPlan", "solve", "TridiagToeplitzSolve", "block_constants",
+__all__ = ["Plan", "VarlenPlan", "solve", "solve_varlen", "TridiagToeplitzSolve", "block_constants",
            "green_rows", "segment_merge", "build_info", "build", "TDTError"]
 
 
@@ -64,12 +64,17 @@ class _PlanBase:
         _lib.check(_lib.lib().tdt_plan_reserve(self._h, int(m_max)), "tdt_plan_reserve")
 
     def info(self) -> dict:
+        """Refinement record since the last call (synchronises), dominance
+        ratio and condition number; converged is False when a refinement
+        stopped above float resolution."""
         it = ctypes.c_int(0)
         upd, dom, kap = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
-        _lib.check(_lib.lib().tdt_last_info(self._h, ctypes.byref(it), ctypes.byref(upd),
-                                            ctypes.byref(dom), ctypes.byref(kap)),
-                   "tdt_last_info")
-        return dict(refine_iters=it.value, dominance=dom.value, kappa2=kap.value)
+        st = _lib.lib().tdt_last_info(self._h, ctypes.byref(it), ctypes.byref(upd),
+                                      ctypes.byref(dom), ctypes.byref(kap))
+        if st != _lib.TDT_ERR_NOT_CONVERGED:
+            _lib.check(st, "tdt_last_info")
+        return dict(refine_iters=it.value, last_rel_update=upd.value, dominance=dom.value,
+                    kappa2=kap.value, converged=st != _lib.TDT_ERR_NOT_CONVERGED)
 
     def profile(self, enable: bool = True):
         """Record HIP events around the kernels of every later solve."""
@@ -84,8 +89,8 @@ class _PlanBase:
         return dict(first_pass_ms=ms[0], interface_ms=ms[1], final_ms=ms[2], solves=n.value)
 
     def set_option(self, name: str, value: int):
-        """Launch-shape option (see tdt_option_t): 'whole_max_tiles',
-        'wg_per_cu' or 'max_refine'."""
+        """Option of tdt_option_t: 'whole_max_tiles', 'wg_per_cu',
+        'max_refine' or 'shape' (index into _lib.SHAPES)."""
         _lib.check(_lib.lib().tdt_plan_set_option(self._h, _lib.OPTIONS[name], int(value)),
                    "tdt_plan_set_option")
 
@@ -102,7 +107,7 @@ class _PlanBase:
                                                 ctypes.c_void_p(X.data_ptr()), int(M),
                                                 _stream_handle(stream), flags, ctypes.byref(ms)),
                    "tdt_plan_autotune")
-        out = {k: self.get_option(k) for k in ("whole_max_tiles", "wg_per_cu")}
+        out = {k: self.get_option(k) for k in ("shape", "whole_max_tiles", "wg_per_cu")}
         out["ms"] = ms.value
         return out
 
@@ -262,6 +267,17 @@ def _cached_plan(t_m1, t_0, t_1, N, dtype) -> Plan:
 def solve(F, t_m1: float, t_0: float, t_1: float, dtype: str = "f64"):
     """X = T^{-1} F along the last dimension of F (cached plan per T and N)."""
     return _cached_plan(t_m1, t_0, t_1, F.shape[-1], dtype).solve(F.contiguous())
+
+
+def solve_varlen(F, offsets, t_m1, t_0, t_1, dtype: str = "f64"):
+    """X_s = T_s^{-1} F_s for packed systems s (F[offsets[s]:offsets[s+1]]),
+    each with its own t's (scalars broadcast).  Builds a plan per call: keep a
+    VarlenPlan to solve the same systems again."""
+    plan = VarlenPlan(offsets, t_m1, t_0, t_1, dtype)
+    try:
+        return plan.solve(F.contiguous())
+    finally:
+        plan.close()
 
 
 class TridiagToeplitzSolve:

@@ -43,7 +43,9 @@ EXPORTS = [
 ]
 
 # tdt_option_t
-OPTIONS = {"whole_max_tiles": 0, "wg_per_cu": 1, "max_refine": 2}
+OPTIONS = {"whole_max_tiles": 0, "wg_per_cu": 1, "max_refine": 2, "shape": 3}
+# work shapes of TDT_OPT_SHAPE: (rows per lane, lanes per workgroup)
+SHAPES = [(16, 512), (8, 512), (16, 256)]
 TUNE_NO_CACHE = 1
 TUNE_FORCE = 2
 

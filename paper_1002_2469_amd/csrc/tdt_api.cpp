@@ -21,13 +21,22 @@
 #include "tdt_internal.h"
 
 
-using tdt::kB;
-using tdt::kNT;
-using tdt::kTile;
 using tdt::SysDesc;
 typedef long double ld;
 
+// tdt_last_info reports TDT_ERR_NOT_CONVERGED above this estimated remaining
+// relative error of a refinement.
+constexpr float kNotConvergedRel = 1e-7f;
+
 struct tdt_plan_s {
+  // work shape (index into tdt::kShapes): B rows per lane, NT lanes, tiles of L rows
+  int shape = 0;
+  int B = tdt::kShapes[0].B, NT = tdt::kShapes[0].NT;
+  int64_t L = (int64_t)tdt::kShapes[0].B * tdt::kShapes[0].NT;
+  // the creation arguments (a change of shape rebuilds the plan from them)
+  std::vector<double> in_tm1, in_t0, in_t1;
+  std::vector<int64_t> in_sizes, in_offs;
+  int64_t reserved_M = 0;
   bool varlen = false;
   tdt_dtype_t dtype = TDT_F64;
   int64_t N = 0;          // series: order of the system
@@ -39,7 +48,7 @@ struct tdt_plan_s {
   float* dvec32[2] = {nullptr, nullptr};
   double* dtab64[2] = {nullptr, nullptr};
   float* dtab32[2] = {nullptr, nullptr};
-  double* dgreen[2] = {nullptr, nullptr};   // series with several tiles: [2][kTile]
+  double* dgreen[2] = {nullptr, nullptr};   // series with several tiles: [2][L]
   double* dttab[2] = {nullptr, nullptr};    // per tile position table [2][ttab_n]
   int64_t ttab_n = 0;
   // varlen launch lists
@@ -55,7 +64,6 @@ struct tdt_plan_s {
   // workspace
   int64_t ws_slots = 0, ws_fslots = 0;
   double* summ = nullptr;
-  double* bpart = nullptr;
   double* ghost = nullptr;
   double* gscr = nullptr;
   double* gpart = nullptr;
@@ -220,9 +228,10 @@ double condition_number(double a, double b, double c, int64_t n) {
 }
 
 // Fill the descriptor and the block vectors of one system.
-tdt_status_t build_system(double a, double b, double c, int64_t n, SysDesc& D, double* v64,
-                          float* v32, double* t64, float* t32) {
-  ld iu[kB], cp[kB], phi[kB], chi[kB];
+tdt_status_t build_system(double a, double b, double c, int64_t n, int kB, int kNT, SysDesc& D,
+                          double* v64, float* v32, double* t64, float* t32) {
+  const int64_t kTile = (int64_t)kB * kNT;
+  ld iu[tdt::kMaxB], cp[tdt::kMaxB], phi[tdt::kMaxB], chi[tdt::kMaxB];
   if (!block_vectors(a, b, c, kB, iu, cp, phi, chi)) return TDT_ERR_SINGULAR;
   for (int i = 0; i < kB; ++i) {
     ld vv[tdt::kVecN];
@@ -246,7 +255,7 @@ tdt_status_t build_system(double a, double b, double c, int64_t n, SysDesc& D, d
   for (int k = 0; k < 4; ++k) D.blk[k] = (double)blk[k];
   if (!merges_ok(blk)) return TDT_ERR_SINGULAR;
   // per-position table of the left-to-right interface elimination over the
-  // kNT blocks of a tile: beta_{m-1} and 1/(1 - phi_first beta_{m-1})
+  // NT blocks of a tile: beta_{m-1} and 1/(1 - phi_first beta_{m-1})
   {
     ld beta = 0.0L;
     for (int m = 0; m < kNT; ++m) {
@@ -310,11 +319,10 @@ tdt_status_t dev_upload(T** dst, const T* src, size_t count) {
 
 void free_workspace(tdt_plan_s* p) {
   (void)hipFree(p->summ);
-  (void)hipFree(p->bpart);
   (void)hipFree(p->ghost);
   (void)hipFree(p->gscr);
   (void)hipFree(p->gpart);
-  p->summ = p->bpart = p->ghost = p->gscr = p->gpart = nullptr;
+  p->summ = p->ghost = p->gscr = p->gpart = nullptr;
   p->ws_slots = p->ws_fslots = 0;
 }
 
@@ -333,7 +341,6 @@ tdt_status_t ensure_workspace(tdt_plan_s* p, int64_t slots, int64_t fslots, hipS
   (void)hipDeviceSynchronize();
   free_workspace(p);
   if (hipMalloc(&p->summ, (size_t)ns * 2 * sizeof(double)) != hipSuccess ||
-      hipMalloc(&p->bpart, (size_t)ns * 2 * tdt::kNW * sizeof(double)) != hipSuccess ||
       hipMalloc(&p->ghost, (size_t)ns * 2 * sizeof(double)) != hipSuccess ||
       hipMalloc(&p->gscr, (size_t)ns * 3 * sizeof(double)) != hipSuccess ||
       hipMalloc(&p->gpart, (size_t)nf * 3 * sizeof(double)) != hipSuccess) {
@@ -411,7 +418,7 @@ tdt_status_t build_varlen_lists(tdt_plan_s* p) {
   if (!whole_sys.empty()) {
     const int64_t G = std::min<int64_t>(
         (int64_t)whole_sys.size(),
-        std::max(1, tdt::sys_wg_capacity((int)p->dtype, p->wg_per_cu)));
+        std::max(1, tdt::sys_wg_capacity(p->shape, (int)p->dtype, p->wg_per_cu)));
     std::vector<std::vector<int>> lists((size_t)G);
     typedef std::pair<int64_t, int64_t> Load;   // (cost so far, list)
     std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
@@ -457,6 +464,8 @@ tdt_status_t finish_plan(tdt_plan_s* p, const std::vector<double>& tm1,
   const int64_t S = (int64_t)sizes.size();
   double dom = std::numeric_limits<double>::infinity(), kap = 0.0;
   for (int dir = 0; dir < 2; ++dir) {
+    const int kB = p->B, kNT = p->NT;
+    const int64_t kTile = p->L;
     std::vector<double> v64((size_t)S * tdt::kVecN * kB);
     std::vector<float> v32((size_t)S * tdt::kVecN * kB);
     std::vector<double> t64((size_t)S * tdt::kTabN * kNT);
@@ -467,7 +476,7 @@ tdt_status_t finish_plan(tdt_plan_s* p, const std::vector<double>& tm1,
       const double c = dir == 0 ? t1[s] : tm1[s];
       SysDesc& D = p->hsys[dir][s];
       std::memset(&D, 0, sizeof(D));
-      tdt_status_t st = build_system(a, t0[s], c, sizes[s], D,
+      tdt_status_t st = build_system(a, t0[s], c, sizes[s], kB, kNT, D,
                                      v64.data() + (size_t)s * tdt::kVecN * kB,
                                      v32.data() + (size_t)s * tdt::kVecN * kB,
                                      t64.data() + (size_t)s * tdt::kTabN * kNT,
@@ -507,7 +516,9 @@ tdt_status_t finish_plan(tdt_plan_s* p, const std::vector<double>& tm1,
   {
     int maxp = 1;
     for (const SysDesc& D : p->hsys[0]) maxp = std::max(maxp, (int)D.ntiles);
-    const int tr = maxp <= 256 ? 1 : (maxp <= 2048 ? 8 : (maxp <= 8192 ? 16 : 1));
+    // (the same thresholds as launch_grid: <256,1>, <256,8>, <512,16>,
+    // <1024,16>, then the segment-merge kernel)
+    const int tr = maxp <= 256 ? 1 : (maxp <= 2048 ? 8 : (maxp <= 16384 ? 16 : 1));
     for (int dir = 0; dir < 2; ++dir)
       for (SysDesc& D : p->hsys[dir]) {
         D.tr = tr;
@@ -566,10 +577,46 @@ tdt_status_t finish_plan(tdt_plan_s* p, const std::vector<double>& tm1,
     const tdt_status_t ws = ensure_workspace(p, 1, 1, nullptr);
     if (ws != TDT_OK) return ws;
   }
-  if (hipMalloc(&p->iters, sizeof(int)) != hipSuccess) return TDT_ERR_OOM;
-  if (hipMemset(p->iters, 0, sizeof(int)) != hipSuccess) return TDT_ERR_HIP;
+  if (hipMalloc(&p->iters, 2 * sizeof(int)) != hipSuccess) return TDT_ERR_OOM;
+  if (hipMemset(p->iters, 0, 2 * sizeof(int)) != hipSuccess) return TDT_ERR_HIP;
   if (hipDeviceSynchronize() != hipSuccess) return TDT_ERR_HIP;
   return p->dominance < 1.0 ? TDT_WARN_NOT_DOMINANT : TDT_OK;
+}
+
+// Rebuild the plan for another work shape from its creation arguments,
+// keeping its options and reservation.  On failure the plan is unchanged.
+tdt_status_t rebuild_plan(tdt_plan_s* p, int shape) {
+  if (hipDeviceSynchronize() != hipSuccess) return TDT_ERR_HIP;
+  tdt_plan_s* q = new (std::nothrow) tdt_plan_s();
+  if (!q) return TDT_ERR_OOM;
+  q->shape = shape;
+  q->B = tdt::kShapes[shape].B;
+  q->NT = tdt::kShapes[shape].NT;
+  q->L = (int64_t)q->B * q->NT;
+  q->in_tm1 = p->in_tm1;
+  q->in_t0 = p->in_t0;
+  q->in_t1 = p->in_t1;
+  q->in_sizes = p->in_sizes;
+  q->in_offs = p->in_offs;
+  q->varlen = p->varlen;
+  q->dtype = p->dtype;
+  q->N = p->N;
+  q->S = p->S;
+  q->total = p->total;
+  q->sys_max_tiles = p->sys_max_tiles;
+  q->max_iter = p->max_iter;
+  q->refine_tol = p->refine_tol;
+  q->wg_per_cu = p->wg_per_cu;
+  tdt_status_t st = finish_plan(q, q->in_tm1, q->in_t0, q->in_t1, q->in_sizes, q->in_offs);
+  if (st >= 0 && p->reserved_M > 0) st = tdt_plan_reserve(q, p->reserved_M);
+  if (st < 0) {
+    destroy(q);
+    return st;
+  }
+  q->profile = p->profile;
+  std::swap(*p, *q);
+  destroy(q);   // the old buffers
+  return TDT_OK;
 }
 
 bool overlaps(const void* x, size_t nx, const void* y, size_t ny) {
@@ -591,6 +638,7 @@ tdt_status_t run(tdt_plan_s* p, int dir, const void* F, void* X, const void* Xfw
   L.max_iter = p->max_iter;
   L.refine_tol = p->refine_tol;
   L.wg_per_cu = p->wg_per_cu;
+  L.shape = p->shape;
   L.ttab = p->dttab[dir];
   L.ttab_n = p->ttab_n;
   L.max_ntiles = 1;
@@ -622,9 +670,9 @@ tdt_status_t run(tdt_plan_s* p, int dir, const void* F, void* X, const void* Xfw
     L.n_bins = 0;
     L.n_sys = 0;
     L.green = p->dgreen[dir];
-    L.nfull = (int)(p->N % kTile == 0 ? nt : nt - 1);
+    L.nfull = (int)(p->N % p->L == 0 ? nt : nt - 1);
     L.n_beta = nt > 1 ? M * L.nfull : 0;
-    L.n_last = (nt > 1 && p->N % kTile != 0) ? M : 0;
+    L.n_last = (nt > 1 && p->N % p->L != 0) ? M : 0;
     L.n_p1 = nt > 1 ? M * nt : 0;
     L.n_grid = nt > 1 ? M : 0;
     L.n_fin = M * nt;
@@ -634,9 +682,8 @@ tdt_status_t run(tdt_plan_s* p, int dir, const void* F, void* X, const void* Xfw
   if (L.n_fin > 0x7fffffffLL) return TDT_ERR_INVALID_ARG;
   tdt_status_t s = ensure_workspace(p, slots, fslots, st);
   if (s != TDT_OK) return s;
-  if (!p->summ || !p->bpart || !p->ghost || !p->gscr || !p->gpart) return TDT_ERR_OOM;
+  if (!p->summ || !p->ghost || !p->gscr || !p->gpart) return TDT_ERR_OOM;
   L.summ = p->summ;
-  L.bpart = p->bpart;
   L.ghost = p->ghost;
   L.gscr = p->gscr;
   L.gpart = p->gpart;
@@ -665,6 +712,7 @@ tdt_status_t run(tdt_plan_s* p, int dir, const void* F, void* X, const void* Xfw
 namespace tune {
 
 struct Choice {
+  int shape;
   int whole_max_tiles;
   int wg_per_cu;
   double ms;
@@ -708,7 +756,7 @@ std::string cache_path() {
 }
 
 // The file holds one entry per line:
-//   "key": {"whole_max_tiles": W, "wg_per_cu": C, "ms": T},
+//   "key": {"shape": S, "whole_max_tiles": W, "wg_per_cu": C, "ms": T},
 // inside {"format": "tdt-autotune-1", "entries": { ... }}.
 std::vector<std::pair<std::string, Choice>> read_all() {
   std::vector<std::pair<std::string, Choice>> out;
@@ -720,11 +768,12 @@ std::vector<std::pair<std::string, Choice>> read_all() {
     if (!q0) continue;
     const char* q1 = std::strchr(q0 + 1, '"');
     if (!q1) continue;
-    const char* b = std::strstr(q1, "{\"whole_max_tiles\":");
+    const char* b = std::strstr(q1, "{\"shape\":");
     if (!b) continue;
-    Choice c{0, 0, 0.0};
-    if (std::sscanf(b, "{\"whole_max_tiles\": %d, \"wg_per_cu\": %d, \"ms\": %lf", &c.whole_max_tiles,
-                    &c.wg_per_cu, &c.ms) == 3)
+    Choice c{0, 0, 0, 0.0};
+    if (std::sscanf(b, "{\"shape\": %d, \"whole_max_tiles\": %d, \"wg_per_cu\": %d, \"ms\": %lf",
+                    &c.shape, &c.whole_max_tiles, &c.wg_per_cu, &c.ms) == 4 &&
+        c.shape >= 0 && c.shape < tdt::kNumShapes)
       out.emplace_back(std::string(q0 + 1, q1), c);
   }
   std::fclose(f);
@@ -761,16 +810,19 @@ void store(const std::string& key, const Choice& c) {
   if (!f) return;
   std::fprintf(f, "{\"format\": \"tdt-autotune-1\", \"entries\": {\n");
   for (size_t i = 0; i < all.size(); ++i)
-    std::fprintf(f, "  \"%s\": {\"whole_max_tiles\": %d, \"wg_per_cu\": %d, \"ms\": %.6f}%s\n",
-                 all[i].first.c_str(), all[i].second.whole_max_tiles, all[i].second.wg_per_cu,
-                 all[i].second.ms, i + 1 < all.size() ? "," : "");
+    std::fprintf(f,
+                 "  \"%s\": {\"shape\": %d, \"whole_max_tiles\": %d, \"wg_per_cu\": %d, "
+                 "\"ms\": %.6f}%s\n",
+                 all[i].first.c_str(), all[i].second.shape, all[i].second.whole_max_tiles,
+                 all[i].second.wg_per_cu, all[i].second.ms, i + 1 < all.size() ? "," : "");
   std::fprintf(f, "}}\n");
   std::fclose(f);
   (void)std::rename(tmp.c_str(), path.c_str());
 }
 
 tdt_status_t apply(tdt_plan_s* p, const Choice& c) {
-  tdt_status_t st = tdt_plan_set_option(p, TDT_OPT_WG_PER_CU, c.wg_per_cu);
+  tdt_status_t st = tdt_plan_set_option(p, TDT_OPT_SHAPE, c.shape);
+  if (st == TDT_OK) st = tdt_plan_set_option(p, TDT_OPT_WG_PER_CU, c.wg_per_cu);
   if (st == TDT_OK && p->varlen)
     st = tdt_plan_set_option(p, TDT_OPT_WHOLE_MAX_TILES, c.whole_max_tiles);
   return st;
@@ -806,7 +858,12 @@ tdt_status_t tdt_plan_create(double t_m1, double t_0, double t_1, int64_t N, tdt
   p->dtype = dtype;
   p->N = N;
   p->S = 1;
-  tdt_status_t st = finish_plan(p, {t_m1}, {t_0}, {t_1}, {N}, {0});
+  p->in_tm1 = {t_m1};
+  p->in_t0 = {t_0};
+  p->in_t1 = {t_1};
+  p->in_sizes = {N};
+  p->in_offs = {0};
+  tdt_status_t st = finish_plan(p, p->in_tm1, p->in_t0, p->in_t1, p->in_sizes, p->in_offs);
   if (st < 0) {
     destroy(p);
     return st;
@@ -836,6 +893,11 @@ tdt_status_t tdt_plan_varlen_create(int64_t S, const int64_t* h_offsets, const d
   p->dtype = dtype;
   p->S = S;
   p->total = h_offsets[S];
+  p->in_tm1 = tm1;
+  p->in_t0 = t0;
+  p->in_t1 = t1;
+  p->in_sizes = sizes;
+  p->in_offs = offs;
   tdt_status_t st = finish_plan(p, tm1, t0, t1, sizes, offs);
   if (st < 0) {
     destroy(p);
@@ -847,6 +909,7 @@ tdt_status_t tdt_plan_varlen_create(int64_t S, const int64_t* h_offsets, const d
 
 tdt_status_t tdt_plan_reserve(tdt_plan_t p, int64_t M_max) {
   if (!p || M_max < 1) return TDT_ERR_INVALID_ARG;
+  p->reserved_M = std::max(p->reserved_M, M_max);
   int64_t slots, fslots;
   if (p->varlen) {
     slots = p->vslots;
@@ -901,17 +964,22 @@ tdt_status_t tdt_plan_destroy(tdt_plan_t p) {
 tdt_status_t tdt_last_info(tdt_plan_t p, int* n_refine_iters, double* last_rel_update,
                            double* dominance, double* kappa2) {
   if (!p) return TDT_ERR_INVALID_ARG;
-  if (n_refine_iters) {
-    int v = 0;
-    if (hipDeviceSynchronize() != hipSuccess ||
-        hipMemcpy(&v, p->iters, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess ||
-        hipMemset(p->iters, 0, sizeof(int)) != hipSuccess)
-      return TDT_ERR_HIP;
-    *n_refine_iters = v;
-  }
-  if (last_rel_update) *last_rel_update = 0.0;
   if (dominance) *dominance = p->dominance;
   if (kappa2) *kappa2 = p->kappa;
+  if (!n_refine_iters && !last_rel_update) return TDT_OK;
+  int v[2] = {0, 0};
+  if (hipDeviceSynchronize() != hipSuccess ||
+      hipMemcpy(v, p->iters, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemset(p->iters, 0, sizeof(v)) != hipSuccess)
+    return TDT_ERR_HIP;
+  float rel;
+  std::memcpy(&rel, &v[1], sizeof(rel));
+  if (n_refine_iters) *n_refine_iters = v[0];
+  if (last_rel_update) *last_rel_update = (double)rel;
+  // refinement stopped (cap, or updates no longer shrinking) while its
+  // remaining error was still above float resolution relative to the solution
+  if (p->dtype == TDT_F32_REFINE && v[0] > 0 && !(rel <= kNotConvergedRel))
+    return TDT_ERR_NOT_CONVERGED;
   return TDT_OK;
 }
 
@@ -936,6 +1004,10 @@ tdt_status_t tdt_plan_set_option(tdt_plan_t p, tdt_option_t opt, int64_t value) 
       if (value < 1 || value > 100) return TDT_ERR_INVALID_ARG;
       p->max_iter = (int)value;
       return TDT_OK;
+    case TDT_OPT_SHAPE:
+      if (value < 0 || value >= tdt::kNumShapes) return TDT_ERR_INVALID_ARG;
+      if ((int)value == p->shape) return TDT_OK;
+      return rebuild_plan(p, (int)value);
   }
   return TDT_ERR_INVALID_ARG;
 }
@@ -946,6 +1018,7 @@ tdt_status_t tdt_plan_get_option(tdt_plan_t p, tdt_option_t opt, int64_t* value)
     case TDT_OPT_WHOLE_MAX_TILES: *value = p->sys_max_tiles; return TDT_OK;
     case TDT_OPT_WG_PER_CU: *value = p->wg_per_cu; return TDT_OK;
     case TDT_OPT_MAX_REFINE: *value = p->max_iter; return TDT_OK;
+    case TDT_OPT_SHAPE: *value = p->shape; return TDT_OK;
   }
   return TDT_ERR_INVALID_ARG;
 }
@@ -970,12 +1043,13 @@ tdt_status_t tdt_plan_autotune(tdt_plan_t p, const void* F, void* X, int64_t M,
   };
   std::vector<tune::Choice> cands;
   const int whole[] = {0, 1, 2, 4, 8, 16};
-  for (int wpc : {0, 1}) {
-    if (p->varlen)
-      for (int w : whole) cands.push_back(tune::Choice{w, wpc, 0.0});
-    else
-      cands.push_back(tune::Choice{p->sys_max_tiles, wpc, 0.0});
-  }
+  for (int sh = 0; sh < tdt::kNumShapes; ++sh)
+    for (int wpc : {0, 1}) {
+      if (p->varlen)
+        for (int w : whole) cands.push_back(tune::Choice{sh, w, wpc, 0.0});
+      else
+        cands.push_back(tune::Choice{sh, p->sys_max_tiles, wpc, 0.0});
+    }
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return TDT_ERR_HIP;
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -1084,10 +1158,10 @@ tdt_status_t tdt_plan_profile_read(tdt_plan_t p, double* ms3, int64_t* nsolves) 
 }
 
 tdt_status_t tdt_build_info(int* block_f64, int* block_f32, int* wg_threads, int64_t* tile_len) {
-  if (block_f64) *block_f64 = kB;
-  if (block_f32) *block_f32 = kB;
-  if (wg_threads) *wg_threads = kNT;
-  if (tile_len) *tile_len = kTile;
+  if (block_f64) *block_f64 = tdt::kShapes[0].B;
+  if (block_f32) *block_f32 = tdt::kShapes[0].B;
+  if (wg_threads) *wg_threads = tdt::kShapes[0].NT;
+  if (tile_len) *tile_len = (int64_t)tdt::kShapes[0].B * tdt::kShapes[0].NT;
   return TDT_OK;
 }
 

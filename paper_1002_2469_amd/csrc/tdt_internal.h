@@ -5,14 +5,19 @@
 
 namespace tdt {
 
-// Block of contiguous unknowns owned by one lane (the paper's sub-vector U_m
-// of Sec. 2.1 held by one processing element), threads per workgroup, and the
-// tile: the unknowns one workgroup holds on chip at once.
-constexpr int kB = 16;
-constexpr int kNT = 512;
-constexpr int kNW = kNT / 64;          // wavefronts per workgroup
-constexpr int kTile = kB * kNT;        // 8192 unknowns per tile
-constexpr int kMinWavesPerSimd = 4;    // occupancy the tile kernels are compiled for
+// Work shape of the tile kernels: B contiguous unknowns per lane (the
+// paper's sub-vector U_m of Sec. 2.1 held by one processing element), NT
+// lanes per workgroup, and the tile of L = B*NT unknowns one workgroup holds
+// on chip at once.  A plan is built for one shape; the shapes below are
+// compiled in and the autotuner may pick any of them.
+struct ShapeInfo {
+  int B, NT, waves;   // waves: occupancy (waves per SIMD) the kernels target
+};
+constexpr ShapeInfo kShapes[] = {{16, 512, 4}, {8, 512, 4}, {16, 256, 4}};
+constexpr int kNumShapes = 3;
+constexpr int kMaxB = 16;
+constexpr int kMaxNT = 512;
+constexpr int kMinWavesPerSimd = 4;    // occupancy of the other kernels
 // varlen plans: systems of at most this many tiles are solved whole by one
 // workgroup each (default; the plan option can lower it, or raise it up to
 // kSysMaxTiles)
@@ -31,9 +36,9 @@ struct SysDesc {
   int32_t slot0;         // first workspace slot of the system (varlen)
   int32_t cidx;          // index of the block-constant vectors of this system
   int32_t fslot0;         // first adjoint partial-sum slot of the system (varlen)
-  double tail_pf;        // phi_first of the last block of the system (length (n-1)%kB+1)
-  double blk[4];         // end values of a full block (length kB)
-  double tileK[4];       // end values of a full tile (length kTile)
+  double tail_pf;        // phi_first of the last block of the system (length (n-1)%B+1)
+  double blk[4];         // end values of a full block (length B)
+  double tileK[4];       // end values of a full tile (length L)
   double ltileK[4];      // last tile, padded form: full-tile values if full,
                          // else (phi_first of its real length, 0, 0, 0)
   // Workspace slots of a multi-tile system are "run-interleaved" for the
@@ -53,12 +58,12 @@ __host__ __device__ inline int64_t tile_slot(const SysDesc& S, int64_t m, int t,
   return varlen ? (int64_t)S.slot0 + pos : m * S.tslots + pos;
 }
 
-// Per-system table over the kNT block positions of a tile: beta_{m-1} (the
+// Per-system table over the NT block positions of a tile: beta_{m-1} (the
 // coefficient that carries the next block's first unknown into block m-1's
 // last one, from the left-to-right elimination) and 1/(1 - phi_first beta_{m-1}).
 enum { kTabBeta = 0, kTabInvD = 1, kTabN = 2 };
 
-// Per-system block vectors, kB each, in this order.
+// Per-system block vectors, B each, in this order.
 //   IU: 1/u_i (inverse pivots), AIU: t_-1/u_i, CP: t_1/u_i, PHI, CHI: the
 //   block's responses to unit values just left / right of it.
 enum { kVecIU = 0, kVecCP = 1, kVecPHI = 2, kVecCHI = 3, kVecAIU = 4, kVecN = 5 };
@@ -68,7 +73,8 @@ struct LaunchSet {
   const SysDesc* sys;
   const double* vec64;
   const float* vec32;
-  const double* tab64;     // per-position table [ncidx][2][kNT]
+  int shape;               // index into kShapes
+  const double* tab64;     // per-position table [ncidx][2][NT]
   const float* tab32;
   const int2* p1_items;    // varlen: (system, tile) of the first pass; null for a series
   const int2* fin_items;   // varlen: (system, tile) of the final pass
@@ -81,14 +87,13 @@ struct LaunchSet {
   // every full tile with the tile's Green rows (n_beta items), plus the
   // sweep-based pass over the partial last tile of each right-hand side
   // (n_last items); varlen plans use the sweep-based pass over p1_items
-  const double* green;     // [2][kTile] or null
+  const double* green;     // [2][L] or null
   int64_t n_beta, n_last;
   int nfull;
   int max_ntiles;          // most tiles of any system (selects the interface kernel)
   const double* ttab;      // per tile position: beta_{t-1}, 1/(1 - Pf beta_{t-1}) ([2][ttab_n])
   int64_t ttab_n;
   double* summ;
-  double* bpart;           // [slot][kNW][2] partial sums of the streaming first pass
   double* ghost;
   double* gscr;
   double* gpart;
@@ -105,7 +110,7 @@ hipError_t launch_solve(int dtype, bool bwd, const LaunchSet& L, const void* F, 
                         const void* Xfwd, hipStream_t st);
 // Workgroups of the whole-system kernel that are resident at once (the
 // plan spreads its systems over this many lists).
-int sys_wg_capacity(int dtype, int wg_per_cu);
+int sys_wg_capacity(int shape, int dtype, int wg_per_cu);
 hipError_t launch_gt_reduce(const double* gpart, const SysDesc* sys, int64_t nsys,
                             int64_t nparts, int varlen, double* gt, hipStream_t st);
 

@@ -41,6 +41,28 @@
 
 namespace tdt {
 
+// Compile-time work shape of the tile kernels: B rows per lane, NT lanes per
+// workgroup (NW wavefronts), tiles of L = B*NT rows, occupancy target WAVES.
+template <int B_, int NT_, int WAVES_>
+struct Shape {
+  static constexpr int B = B_;
+  static constexpr int NT = NT_;
+  static constexpr int NW = NT_ / 64;
+  static constexpr int L = B_ * NT_;
+  static constexpr int WAVES = WAVES_;
+};
+// The names the shape-generic code uses for its shape's sizes.
+#define TDT_SHAPE(SH)                          \
+  [[maybe_unused]] constexpr int kB = SH::B;   \
+  [[maybe_unused]] constexpr int kNT = SH::NT; \
+  [[maybe_unused]] constexpr int kNW = SH::NW; \
+  [[maybe_unused]] constexpr int kTile = SH::L;
+
+// The grid-level kernels (interface fallback, gradient reduction) use a
+// fixed workgroup of their own.
+constexpr int kGridNT = 512;
+constexpr int kGridNW = kGridNT / 64;
+
 template <typename T>
 struct Seg {
   T yf, yl, pf, pl, cf, cl;
@@ -182,27 +204,27 @@ __device__ __forceinline__ Seg<T> wg_level(const Seg<T>& pre, T (*wsum)[6], T XL
     wsum[w][3] = pre.pl; wsum[w][4] = pre.cf; wsum[w][5] = pre.cl;
   }
   __syncthreads();
-  Seg<T> W[kNW];
+  Seg<T> W[kGridNW];
 #pragma unroll
-  for (int k = 0; k < kNW; ++k)
+  for (int k = 0; k < kGridNW; ++k)
     W[k] = Seg<T>{wsum[k][0], wsum[k][1], wsum[k][2], wsum[k][3], wsum[k][4], wsum[k][5]};
-  Seg<T> P[kNW], Q[kNW];   // P[k] = W[0..k], Q[k] = W[k..kNW-1]
+  Seg<T> P[kGridNW], Q[kGridNW];   // P[k] = W[0..k], Q[k] = W[k..kGridNW-1]
   P[0] = W[0];
 #pragma unroll
-  for (int k = 1; k < kNW; ++k) P[k] = seg_merge(P[k - 1], W[k]);
-  Q[kNW - 1] = W[kNW - 1];
+  for (int k = 1; k < kGridNW; ++k) P[k] = seg_merge(P[k - 1], W[k]);
+  Q[kGridNW - 1] = W[kGridNW - 1];
 #pragma unroll
-  for (int k = kNW - 2; k >= 0; --k) Q[k] = seg_merge(W[k], Q[k + 1]);
+  for (int k = kGridNW - 2; k >= 0; --k) Q[k] = seg_merge(W[k], Q[k + 1]);
   XLw = XLt;
   XRw = XRt;
 #pragma unroll
-  for (int k = 0; k + 1 < kNW; ++k) {   // junction between waves k and k+1
+  for (int k = 0; k + 1 < kGridNW; ++k) {   // junction between waves k and k+1
     T xk, xk1;
     junction(P[k].yl, P[k].pl, P[k].cl, Q[k + 1].yf, Q[k + 1].pf, Q[k + 1].cf, XLt, XRt, xk, xk1);
     if (w == k) XRw = xk1;
     if (w == k + 1) XLw = xk;
   }
-  return P[kNW - 1];
+  return P[kGridNW - 1];
 }
 
 // Values just outside this lane's block, from the scans and the wavefront's
@@ -364,11 +386,12 @@ struct Consts {
 // correction is skipped.  Two workgroup barriers inside.
 // FULL: every block of the tile has kB rows (the caller has checked it for
 // the whole workgroup), which removes the tail handling from the code.
-template <typename Tc, bool FULL>
-__device__ __forceinline__ void tile_solve(Tc (&q)[kB], int len_in, Tc XLt, Tc XRt,
+template <class SH, typename Tc, bool FULL>
+__device__ __forceinline__ void tile_solve(Tc (&q)[SH::B], int len_in, Tc XLt, Tc XRt,
                                            const Consts<Tc>& K, Tc bp, Tc iDf,
                                            Tc (*fw)[2], Tc (*bw)[2], double* yfo,
                                            double* ylo) {
+  TDT_SHAPE(SH)
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int len = FULL ? kB : len_in;
   const bool tail = len > 0 && len < kB;
@@ -512,9 +535,10 @@ __device__ __forceinline__ ItemInfo decode_item(const int2* items, const SysDesc
   return r;
 }
 
-template <typename Tc>
+template <class SH, typename Tc>
 __device__ __forceinline__ Consts<Tc> make_consts(const SysDesc& S, const double* vec64,
                                                   const float* vec32) {
+  TDT_SHAPE(SH)
   Consts<Tc> K;
   const Tc* v;
   if constexpr (sizeof(Tc) == 8)
@@ -540,8 +564,10 @@ struct TileGeom {
   int tl;         // rows in the tile
 };
 
+template <class SH>
 __device__ __forceinline__ TileGeom tile_geom(const int2* items, const SysDesc* sys,
                                               int64_t it, int last_only) {
+  TDT_SHAPE(SH)
   TileGeom G;
   G.I = decode_item(items, sys, it, last_only);
   const SysDesc S = load_sys(sys, G.I.s);
@@ -557,18 +583,19 @@ __device__ __forceinline__ TileGeom tile_geom(const int2* items, const SysDesc* 
 // values just outside the tile.  Every load is unconditional (rows past the
 // tile read as 0 through the buffer range check) so that all of them are in
 // flight together and nothing waits for them before the next tile starts.
-template <typename Tio, typename Tc>
+template <class SH, typename Tio, typename Tc>
 struct Prefetch {
-  Tio v[kB];
+  Tio v[SH::B];
   Tc bp, iD;
   double XL, XR;
 };
 
-template <typename Tio, typename Tc, bool SUMMARY>
+template <class SH, typename Tio, typename Tc, bool SUMMARY>
 __device__ __forceinline__ void prefetch(const TileArgs<Tio>& A, int64_t item,
-                                         Prefetch<Tio, Tc>& P) {
+                                         Prefetch<SH, Tio, Tc>& P) {
+  TDT_SHAPE(SH)
   const int tid = threadIdx.x;
-  const TileGeom G = tile_geom(A.items, A.sys, item, A.last_only);
+  const TileGeom G = tile_geom<SH>(A.items, A.sys, item, A.last_only);
   const SysDesc S = load_sys(A.sys, G.I.s);
   const __amdgpu_buffer_rsrc_t src = make_rsrc(A.F + G.base, (int64_t)G.tl * sizeof(Tio));
   const int vb = opaque(tid * (int)sizeof(Tio));
@@ -601,30 +628,43 @@ __device__ __forceinline__ void prefetch(const TileArgs<Tio>& A, int64_t item,
 #define TDT_REFINE_PREFETCH 0
 #endif
 
+// A workgroup's refinement record, published once when it exits: rec[0] =
+// most float solves of any tile, rec[1] = bits of the largest estimated
+// remaining relative error (non-negative floats order like their bits).
+__device__ __forceinline__ void publish_refine_record(int* rec, int it_max, float est_max) {
+  if (threadIdx.x == 0 && rec && it_max > 0) {
+    atomicMax(rec, it_max);
+    atomicMax(rec + 1, __float_as_int(est_max));
+  }
+}
+
 // Workgroup-shared scratch of a tile solve.
-template <typename Tio, typename Tc>
+template <class SH, typename Tio, typename Tc>
 struct TileShared {
-  static constexpr int RP = kB + 16 / (int)sizeof(Tio);   // padded LDS row pitch
-  __align__(16) Tio lds[kNT * RP];
-  Tc fw[kNW][2], bw[kNW][2];
-  double red[kNW][4];
-  double edge[kNW][2];
+  static constexpr int RP = SH::B + 16 / (int)sizeof(Tio);   // padded LDS row pitch
+  __align__(16) Tio lds[SH::NT * RP];
+  Tc fw[SH::NW][2], bw[SH::NW][2];
+  double red[SH::NW][4];
+  double edge[SH::NW][2];
 };
 
 // Element j*kNT + tid of a tile lives in LDS row j*(kNT/kB) + tid/kB, column
 // tid%kB: after the coalesced loads each lane owns kB consecutive rows.
-template <typename Tio>
+template <class SH, typename Tio>
 __device__ __forceinline__ int lds_base() {
+  TDT_SHAPE(SH)
   constexpr int RP = kB + 16 / (int)sizeof(Tio);
   return (threadIdx.x / kB) * RP + (threadIdx.x % kB);
 }
-template <typename Tio>
+template <class SH, typename Tio>
 constexpr int lds_stride() {
-  return (kNT / kB) * (kB + 16 / (int)sizeof(Tio));
+  return (SH::NT / SH::B) * (SH::B + 16 / (int)sizeof(Tio));
 }
 
 // Rows of the lane's block that exist in a tile of tl rows.
+template <class SH>
 __device__ __forceinline__ int block_len(int tl) {
+  TDT_SHAPE(SH)
   const int r = tl - (int)threadIdx.x * kB;
   return r >= kB ? kB : (r > 0 ? r : 0);
 }
@@ -634,21 +674,22 @@ __device__ __forceinline__ int block_len(int tl) {
 // zero) it writes the tile's first and last unknown instead.  FULL: every
 // block has kB rows.  REFINE: Tio = double data, Tc = float sweeps; residual
 // and update in double, repeated until converged (see below).
-template <typename Tio, typename Tc, bool REFINE, bool SUMMARY, bool FULL>
-__device__ __forceinline__ void solve_in_lds(TileShared<Tio, Tc>& sh, Tio* myrow, int len, int tl,
+template <class SH, typename Tio, typename Tc, bool REFINE, bool SUMMARY, bool FULL>
+__device__ __forceinline__ void solve_in_lds(TileShared<SH, Tio, Tc>& sh, Tio* myrow, int len, int tl,
                                              double XLt, double XRt, const SysDesc& S,
                                              const Consts<Tc>& K, Tc bp, Tc iDf,
-                                             double* yfo, double* ylo, int* iters, int max_iter,
-                                             double refine_tol) {
+                                             double* yfo, double* ylo, int& it_max,
+                                             float& est_max, int max_iter, double refine_tol) {
+  TDT_SHAPE(SH)
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   if constexpr (!REFINE) {
     Tc q[kB];
 #pragma unroll
     for (int i = 0; i < kB; ++i) q[i] = (Tc)myrow[i];
     if constexpr (SUMMARY) {
-      tile_solve<Tc, FULL>(q, len, Tc(0), Tc(0), K, bp, iDf, sh.fw, sh.bw, yfo, ylo);
+      tile_solve<SH, Tc, FULL>(q, len, Tc(0), Tc(0), K, bp, iDf, sh.fw, sh.bw, yfo, ylo);
     } else {
-      tile_solve<Tc, FULL>(q, len, (Tc)XLt, (Tc)XRt, K, bp, iDf, sh.fw, sh.bw, (double*)nullptr,
+      tile_solve<SH, Tc, FULL>(q, len, (Tc)XLt, (Tc)XRt, K, bp, iDf, sh.fw, sh.bw, (double*)nullptr,
                            (double*)nullptr);
 #pragma unroll
       for (int i = 0; i < kB; ++i) myrow[i] = (Tio)q[i];
@@ -675,7 +716,7 @@ __device__ __forceinline__ void solve_in_lds(TileShared<Tio, Tc>& sh, Tio* myrow
         if (i == kB - 1 && tid == kNT - 1) r -= c * XRt;
         q[i] = (FULL || i < len) ? (Tc)r : Tc(0);
       }
-      tile_solve<Tc, FULL>(q, len, Tc(0), Tc(0), K, bp, iDf, sh.fw, sh.bw, (double*)nullptr,
+      tile_solve<SH, Tc, FULL>(q, len, Tc(0), Tc(0), K, bp, iDf, sh.fw, sh.bw, (double*)nullptr,
                            (double*)nullptr);
 #pragma unroll
       for (int i = 0; i < kB; ++i) {
@@ -685,6 +726,7 @@ __device__ __forceinline__ void solve_in_lds(TileShared<Tio, Tc>& sh, Tio* myrow
     }
     int it = 1;
     float dprev = 0.0f, dloc = 0.0f, xmax = 0.0f;
+    float est = 1.0f;   // estimated remaining relative error (1: no update ran)
     for (;;) {
       float dmax = 0.0f;
       if (it >= 2) dmax = wave_max(dloc);
@@ -698,6 +740,10 @@ __device__ __forceinline__ void solve_in_lds(TileShared<Tio, Tc>& sh, Tio* myrow
         for (int q = 1; q < kNW; ++q) dmax = fmaxf(dmax, (float)sh.red[q][0]);
         const float rho = it == 2 ? dmax / xmax : dmax / dprev;
         dprev = dmax;
+        // the next update, predicted (or, once updates stop shrinking, the
+        // last one), relative to |x|
+        est = dmax == 0.0f ? 0.0f
+                           : (xmax > 0.0f ? (rho > 0.9f ? dmax : dmax * rho) / xmax : 1.0f);
         if (dmax == 0.0f || (double)dmax * rho <= refine_tol * xmax || rho > 0.9f) break;
       } else {
         xmax = (float)sh.red[0][0];
@@ -720,7 +766,7 @@ __device__ __forceinline__ void solve_in_lds(TileShared<Tio, Tc>& sh, Tio* myrow
         r = fma(-c, right, r);
         q[i] = (FULL || i < len) ? (Tc)r : Tc(0);
       }
-      tile_solve<Tc, FULL>(q, len, Tc(0), Tc(0), K, bp, iDf, sh.fw, sh.bw, (double*)nullptr,
+      tile_solve<SH, Tc, FULL>(q, len, Tc(0), Tc(0), K, bp, iDf, sh.fw, sh.bw, (double*)nullptr,
                            (double*)nullptr);
       dloc = 0.0f;
 #pragma unroll
@@ -732,7 +778,9 @@ __device__ __forceinline__ void solve_in_lds(TileShared<Tio, Tc>& sh, Tio* myrow
       // the next barrier rewrites red[] and edge[]: every wavefront has read
       // them once it is past the barriers inside tile_solve
     }
-    if (tid == 0 && iters) atomicMax(iters, it);
+    // the workgroup's record (kept by every lane; the kernel publishes it once)
+    it_max = it > it_max ? it : it_max;
+    est_max = fmaxf(est_max, est);
     if constexpr (SUMMARY) {
       if (tid == 0) *yfo = x[0];
       if (tid == kNT - 1) *ylo = tl == kTile ? x[kB - 1] : 0.0;
@@ -744,32 +792,34 @@ __device__ __forceinline__ void solve_in_lds(TileShared<Tio, Tc>& sh, Tio* myrow
   }
 }
 
-template <typename Tio, typename Tc, bool REFINE, bool SUMMARY>
-__device__ __forceinline__ void solve_tile_lds(TileShared<Tio, Tc>& sh, int tl, double XLt,
+template <class SH, typename Tio, typename Tc, bool REFINE, bool SUMMARY>
+__device__ __forceinline__ void solve_tile_lds(TileShared<SH, Tio, Tc>& sh, int tl, double XLt,
                                                double XRt, const SysDesc& S,
                                                const Consts<Tc>& K, Tc bp, Tc iDf, double* yfo,
-                                               double* ylo, int* iters, int max_iter,
-                                               double refine_tol) {
-  Tio* myrow = sh.lds + threadIdx.x * TileShared<Tio, Tc>::RP;
+                                               double* ylo, int& it_max, float& est_max,
+                                               int max_iter, double refine_tol) {
+  TDT_SHAPE(SH)
+  Tio* myrow = sh.lds + threadIdx.x * TileShared<SH, Tio, Tc>::RP;
   // a separate full-tile copy of the solve pays where registers are free:
   // in the refinement kernel, which holds no prefetched tile
   if (REFINE && tl == kTile)
-    solve_in_lds<Tio, Tc, REFINE, SUMMARY, true>(sh, myrow, kB, tl, XLt, XRt, S, K, bp, iDf, yfo, ylo,
-                                        iters, max_iter, refine_tol);
+    solve_in_lds<SH, Tio, Tc, REFINE, SUMMARY, true>(sh, myrow, kB, tl, XLt, XRt, S, K, bp, iDf, yfo, ylo,
+                                        it_max, est_max, max_iter, refine_tol);
   else
-    solve_in_lds<Tio, Tc, REFINE, SUMMARY, false>(sh, myrow, block_len(tl), tl, XLt, XRt, S, K, bp, iDf,
-                                         yfo, ylo, iters, max_iter, refine_tol);
+    solve_in_lds<SH, Tio, Tc, REFINE, SUMMARY, false>(sh, myrow, block_len<SH>(tl), tl, XLt, XRt, S, K, bp, iDf,
+                                         yfo, ylo, it_max, est_max, max_iter, refine_tol);
 }
 
 // Stores the solved tile from LDS (coalesced).  BWD: also forms this tile's
 // t-gradient partial sums against the forward solution Xfwd and writes their
 // negatives to gpart[0..2] (one barrier pair inside).
-template <typename Tio, typename Tc, bool BWD>
-__device__ __forceinline__ void store_tile(TileShared<Tio, Tc>& sh, Tio* X, const Tio* Xfwd,
+template <class SH, typename Tio, typename Tc, bool BWD>
+__device__ __forceinline__ void store_tile(TileShared<SH, Tio, Tc>& sh, Tio* X, const Tio* Xfwd,
                                            int64_t base, int64_t t0, int tl, int64_t n,
                                            double* gpart) {
+  TDT_SHAPE(SH)
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  constexpr int lstride = lds_stride<Tio>();
+  constexpr int lstride = lds_stride<SH, Tio>();
   double s0 = 0.0, s1 = 0.0, sm1 = 0.0;
   const __amdgpu_buffer_rsrc_t dst = make_rsrc(X + base, (int64_t)tl * sizeof(Tio));
   // adjoint: the forward solution over this tile and one row on each side
@@ -777,7 +827,7 @@ __device__ __forceinline__ void store_tile(TileShared<Tio, Tc>& sh, Tio* X, cons
   const int lo = t0 > 0 ? 1 : 0, hi = t0 + tl < n ? 1 : 0;
   const __amdgpu_buffer_rsrc_t xf =
       make_rsrc(BWD ? Xfwd + base - lo : X + base, BWD ? (int64_t)(lo + tl + hi) * sizeof(Tio) : 0);
-  const Tio* lr = sh.lds + opaque(lds_base<Tio>());
+  const Tio* lr = sh.lds + opaque(lds_base<SH, Tio>());
   const int vs = opaque(tid * (int)sizeof(Tio));
 #pragma unroll
   for (int j = 0; j < kB; ++j) {
@@ -827,28 +877,31 @@ __device__ __forceinline__ void store_tile(TileShared<Tio, Tc>& sh, Tio* X, cons
 //                    in double, repeated until converged.
 //   BWD            : also accumulates the t-gradient partial sums against the
 //                    forward solution Xfwd (the tile solves T^T gF = gX).
-template <typename Tio, typename Tc, bool REFINE, bool SUMMARY, bool BWD>
-__global__ __launch_bounds__(kNT, REFINE ? TDT_REFINE_WAVES : kMinWavesPerSimd) void k_tile(
+template <class SH, typename Tio, typename Tc, bool REFINE, bool SUMMARY, bool BWD>
+__global__ __launch_bounds__(SH::NT, REFINE ? TDT_REFINE_WAVES : SH::WAVES) void k_tile(
     TileArgs<Tio> A) {
-  __shared__ TileShared<Tio, Tc> sh;
+  TDT_SHAPE(SH)
+  __shared__ TileShared<SH, Tio, Tc> sh;
   const int tid = threadIdx.x;
-  const int lbase = lds_base<Tio>();
-  constexpr int lstride = lds_stride<Tio>();
+  const int lbase = lds_base<SH, Tio>();
+  constexpr int lstride = lds_stride<SH, Tio>();
   auto item_of = [&](int64_t k) { return A.reverse ? A.nitems - 1 - k : k; };
   constexpr bool PF = !REFINE || TDT_REFINE_PREFETCH;
+  int it_max = 0;        // refinement record of this workgroup
+  float est_max = 0.0f;
   int64_t k = blockIdx.x;
-  Prefetch<Tio, Tc> P;
-  if (PF && k < A.nitems) prefetch<Tio, Tc, SUMMARY>(A, item_of(k), P);
+  Prefetch<SH, Tio, Tc> P;
+  if (PF && k < A.nitems) prefetch<SH, Tio, Tc, SUMMARY>(A, item_of(k), P);
 
   while (k < A.nitems) {
-    if (!PF) prefetch<Tio, Tc, SUMMARY>(A, item_of(k), P);
+    if (!PF) prefetch<SH, Tio, Tc, SUMMARY>(A, item_of(k), P);
     const int64_t item = item_of(k);
-    const TileGeom G = tile_geom(A.items, A.sys, item, A.last_only);
+    const TileGeom G = tile_geom<SH>(A.items, A.sys, item, A.last_only);
     const SysDesc S = load_sys(A.sys, G.I.s);
     const int64_t slot = tile_slot(S, G.I.m, G.I.t, A.items != nullptr);
     const double XLt = P.XL, XRt = P.XR;
     const Tc bp = P.bp, iDf = P.iD;
-    const Consts<Tc> K = make_consts<Tc>(S, A.vec64, A.vec32);
+    const Consts<Tc> K = make_consts<SH, Tc>(S, A.vec64, A.vec32);
     const int tl = G.tl;
 
     __syncthreads();   // the previous tile is done with LDS
@@ -858,21 +911,22 @@ __global__ __launch_bounds__(kNT, REFINE ? TDT_REFINE_WAVES : kMinWavesPerSimd) 
       for (int j = 0; j < kB; ++j) lw[j * lstride] = P.v[j];
     }
     const int64_t kn = k + gridDim.x;
-    if (PF && kn < A.nitems) prefetch<Tio, Tc, SUMMARY>(A, item_of(kn), P);
+    if (PF && kn < A.nitems) prefetch<SH, Tio, Tc, SUMMARY>(A, item_of(kn), P);
     __syncthreads();
 
     if constexpr (SUMMARY) {
-      solve_tile_lds<Tio, Tc, REFINE, true>(sh, tl, 0.0, 0.0, S, K, bp, iDf, A.summ + 2 * slot,
-                                      A.summ + 2 * slot + 1, A.iters, A.max_iter, A.refine_tol);
+      solve_tile_lds<SH, Tio, Tc, REFINE, true>(sh, tl, 0.0, 0.0, S, K, bp, iDf, A.summ + 2 * slot,
+                                      A.summ + 2 * slot + 1, it_max, est_max, A.max_iter, A.refine_tol);
     } else {
-      solve_tile_lds<Tio, Tc, REFINE, false>(sh, tl, XLt, XRt, S, K, bp, iDf, (double*)nullptr,
-                                      (double*)nullptr, A.iters, A.max_iter, A.refine_tol);
+      solve_tile_lds<SH, Tio, Tc, REFINE, false>(sh, tl, XLt, XRt, S, K, bp, iDf, (double*)nullptr,
+                                      (double*)nullptr, it_max, est_max, A.max_iter, A.refine_tol);
       __syncthreads();
       const int64_t fs = A.items ? (int64_t)S.fslot0 + G.I.t : G.I.m * S.ntiles + G.I.t;
-      store_tile<Tio, Tc, BWD>(sh, A.X, A.Xfwd, G.base, G.t0, tl, S.n, A.gpart + 3 * fs);
+      store_tile<SH, Tio, Tc, BWD>(sh, A.X, A.Xfwd, G.base, G.t0, tl, S.n, A.gpart + 3 * fs);
     }
     k = kn;
   }
+  publish_refine_record(A.iters, it_max, est_max);
 }
 
 template <typename Tio>
@@ -897,23 +951,25 @@ struct SysArgs {
 
 // Coalesced load of rows [base, base + tl) into the LDS tile (rows past tl
 // read as 0).  The caller brackets it with barriers.
-template <typename Tio, typename Tc>
-__device__ __forceinline__ void load_tile(TileShared<Tio, Tc>& sh, const Tio* F, int64_t base,
+template <class SH, typename Tio, typename Tc>
+__device__ __forceinline__ void load_tile(TileShared<SH, Tio, Tc>& sh, const Tio* F, int64_t base,
                                           int tl) {
+  TDT_SHAPE(SH)
   const __amdgpu_buffer_rsrc_t src = make_rsrc(F + base, (int64_t)tl * sizeof(Tio));
   const int vb = opaque((int)threadIdx.x * (int)sizeof(Tio));
   Tio v[kB];
 #pragma unroll
   for (int j = 0; j < kB; ++j) v[j] = buf_load<Tio>(src, vb + j * kNT * (int)sizeof(Tio));
-  Tio* lw = sh.lds + opaque(lds_base<Tio>());
-  constexpr int lstride = lds_stride<Tio>();
+  Tio* lw = sh.lds + opaque(lds_base<SH, Tio>());
+  constexpr int lstride = lds_stride<SH, Tio>();
 #pragma unroll
   for (int j = 0; j < kB; ++j) lw[j * lstride] = v[j];
 }
 
-template <typename T>
+template <class SH, typename T>
 __device__ __forceinline__ void lane_table(const SysDesc& S, const double* tab64,
                                            const float* tab32, T& bp, T& iD) {
+  TDT_SHAPE(SH)
   const int tid = threadIdx.x;
   if constexpr (sizeof(T) == 8) {
     const double* tb = tab64 + (int64_t)S.cidx * kTabN * kNT;
@@ -937,17 +993,18 @@ __device__ __forceinline__ void lane_table(const SysDesc& S, const double* tab64
 //      first, so that the rows read last in step 1 are re-read from cache.
 // Summaries are computed in double for the refinement path (as in the
 // multi-kernel path), in the data precision otherwise.
-template <typename Tio, typename Tc, bool REFINE, bool BWD>
-__global__ __launch_bounds__(kNT, REFINE ? TDT_REFINE_WAVES : kMinWavesPerSimd) void k_sys(
+template <class SH, typename Tio, typename Tc, bool REFINE, bool BWD>
+__global__ __launch_bounds__(SH::NT, REFINE ? TDT_REFINE_WAVES : SH::WAVES) void k_sys(
     SysArgs<Tio> A) {
+  TDT_SHAPE(SH)
   using Ts = typename std::conditional<REFINE, double, Tc>::type;
-  __shared__ TileShared<Tio, Tc> sh;
+  __shared__ TileShared<SH, Tio, Tc> sh;
   __shared__ Ts sfw[kNW][2], sbw[kNW][2];
   __shared__ double tsum[kSysMaxTiles][2];
   __shared__ double tgh[kSysMaxTiles][2];
   __shared__ double tap[kSysMaxTiles], th[kSysMaxTiles], tbp[kSysMaxTiles], tiD[kSysMaxTiles];
   const int tid = threadIdx.x;
-  constexpr int lstride = lds_stride<Tio>();
+  constexpr int lstride = lds_stride<SH, Tio>();
   // The next tile of the system is loaded into registers while the current
   // one is solved, unless the refinement solve needs those registers.
   constexpr bool PF = !REFINE;
@@ -959,7 +1016,7 @@ __global__ __launch_bounds__(kNT, REFINE ? TDT_REFINE_WAVES : kMinWavesPerSimd) 
     for (int j = 0; j < kB; ++j) pv[j] = buf_load<Tio>(src, vb + j * kNT * (int)sizeof(Tio));
   };
   auto commit = [&]() {
-    Tio* lw = sh.lds + opaque(lds_base<Tio>());
+    Tio* lw = sh.lds + opaque(lds_base<SH, Tio>());
 #pragma unroll
     for (int j = 0; j < kB; ++j) lw[j * lstride] = pv[j];
   };
@@ -968,6 +1025,8 @@ __global__ __launch_bounds__(kNT, REFINE ? TDT_REFINE_WAVES : kMinWavesPerSimd) 
     return (int)(S.n - t0 < kTile ? S.n - t0 : kTile);
   };
 
+  int it_max = 0;        // refinement record of this workgroup
+  float est_max = 0.0f;
   const int kb = as_const(A.bins)[blockIdx.x], ke = as_const(A.bins)[blockIdx.x + 1];
   for (int k = kb; k < ke; ++k) {
     const int s = as_const(A.items)[k];
@@ -975,21 +1034,21 @@ __global__ __launch_bounds__(kNT, REFINE ? TDT_REFINE_WAVES : kMinWavesPerSimd) 
     const int nt = S.ntiles;
     if (nt > kSysMaxTiles) continue;   // never listed here (the host checks it)
     if (nt > 1) {
-      const Consts<Ts> KS = make_consts<Ts>(S, A.vec64, A.vec32);
+      const Consts<Ts> KS = make_consts<SH, Ts>(S, A.vec64, A.vec32);
       Ts sbp, siD;
-      lane_table<Ts>(S, A.tab64, A.tab32, sbp, siD);
+      lane_table<SH, Ts>(S, A.tab64, A.tab32, sbp, siD);
       for (int t = 0; t < nt; ++t) {
         const int tl = tile_len(S, t);
         __syncthreads();   // LDS free
-        if (!PF || t == 0) load_tile(sh, A.F, S.off + (int64_t)t * kTile, tl);
+        if (!PF || t == 0) load_tile<SH>(sh, A.F, S.off + (int64_t)t * kTile, tl);
         else commit();
         if (PF && t + 1 < nt) issue(S.off + (int64_t)(t + 1) * kTile, tile_len(S, t + 1));
         __syncthreads();
         Ts q[kB];
-        const Tio* myrow = sh.lds + tid * TileShared<Tio, Tc>::RP;
+        const Tio* myrow = sh.lds + tid * TileShared<SH, Tio, Tc>::RP;
 #pragma unroll
         for (int i = 0; i < kB; ++i) q[i] = (Ts)myrow[i];
-        tile_solve<Ts, false>(q, block_len(tl), Ts(0), Ts(0), KS, sbp, siD, sfw, sbw,
+        tile_solve<SH, Ts, false>(q, block_len<SH>(tl), Ts(0), Ts(0), KS, sbp, siD, sfw, sbw,
                               &tsum[t][0], &tsum[t][1]);
       }
       __syncthreads();
@@ -1019,9 +1078,9 @@ __global__ __launch_bounds__(kNT, REFINE ? TDT_REFINE_WAVES : kMinWavesPerSimd) 
       }
       __syncthreads();
     }
-    const Consts<Tc> K = make_consts<Tc>(S, A.vec64, A.vec32);
+    const Consts<Tc> K = make_consts<SH, Tc>(S, A.vec64, A.vec32);
     Tc bp, iD;
-    lane_table<Tc>(S, A.tab64, A.tab32, bp, iD);
+    lane_table<SH, Tc>(S, A.tab64, A.tab32, bp, iD);
     for (int t = nt - 1; t >= 0; --t) {
       const int64_t t0 = (int64_t)t * kTile;
       const int tl = tile_len(S, t);
@@ -1030,18 +1089,19 @@ __global__ __launch_bounds__(kNT, REFINE ? TDT_REFINE_WAVES : kMinWavesPerSimd) 
       if (nt == 1 || t < nt - 1) {
         __syncthreads();   // LDS free
         if (PF && t < nt - 1) commit();
-        else load_tile(sh, A.F, S.off + t0, tl);
+        else load_tile<SH>(sh, A.F, S.off + t0, tl);
         __syncthreads();
       }
       if (PF && t > 0) issue(S.off + t0 - kTile, kTile);
-      solve_tile_lds<Tio, Tc, REFINE, false>(sh, tl, XLt, XRt, S, K, bp, iD, (double*)nullptr,
-                                             (double*)nullptr, A.iters, A.max_iter,
-                                             A.refine_tol);
+      solve_tile_lds<SH, Tio, Tc, REFINE, false>(sh, tl, XLt, XRt, S, K, bp, iD, (double*)nullptr,
+                                             (double*)nullptr, it_max, est_max,
+                                             A.max_iter, A.refine_tol);
       __syncthreads();
-      store_tile<Tio, Tc, BWD>(sh, A.X, A.Xfwd, S.off + t0, t0, tl, S.n,
+      store_tile<SH, Tio, Tc, BWD>(sh, A.X, A.Xfwd, S.off + t0, t0, tl, S.n,
                                A.gpart + 3 * ((int64_t)S.fslot0 + t));
     }
   }
+  publish_refine_record(A.iters, it_max, est_max);
 }
 
 // First pass of a series plan over its full tiles: the tile summary is the
@@ -1059,8 +1119,6 @@ __global__ __launch_bounds__(kNT, REFINE ? TDT_REFINE_WAVES : kMinWavesPerSimd) 
 // stalls the stream.  Double arithmetic for every data type.
 constexpr int kBetaNT = 1024;                  // threads per workgroup of this pass
 constexpr int kBetaNW = kBetaNT / 64;
-constexpr int kSlice = kTile / kBetaNW;        // rows per wavefront slice
-constexpr int kBetaPerLane = kSlice / 64;      // rows per lane
 template <typename Tio>
 struct BetaArgs {
   const Tio* __restrict__ F;
@@ -1071,8 +1129,11 @@ struct BetaArgs {
   double* __restrict__ summ;          // [slot][2]
 };
 
-template <typename Tio>
+template <class SH, typename Tio>
 __global__ __launch_bounds__(kBetaNT) void k_beta(BetaArgs<Tio> A) {
+  TDT_SHAPE(SH)
+  constexpr int kSlice = kTile / kBetaNW;           // rows per wavefront slice
+  constexpr int kBetaPerLane = kSlice / 64;         // rows per lane
   constexpr int V = 16 / (int)sizeof(Tio);          // elements per 16-byte load
   constexpr int NL = kBetaPerLane / V;              // loads per lane per slice
   __shared__ double part[2][kBetaNW][2];
@@ -1167,8 +1228,8 @@ struct GridArgs {
 // summaries, the runs are combined by the same wavefront scans and LDS level
 // as inside a tile, and each thread then walks its run left to right to give
 // every tile the values just outside it.
-__global__ __launch_bounds__(kNT) void k_grid(GridArgs A) {
-  __shared__ double wsum[kNW][6];
+__global__ __launch_bounds__(kGridNT) void k_grid(GridArgs A) {
+  __shared__ double wsum[kGridNW][6];
   const int tid = threadIdx.x;
   int s = 0;
   int64_t slot0;
@@ -1183,7 +1244,7 @@ __global__ __launch_bounds__(kNT) void k_grid(GridArgs A) {
   const double* summ = A.summ + 2 * slot0;
   double* ghost = A.ghost + 2 * slot0;
   double* scr = A.gscr + 3 * slot0;
-  const int ch = (P + kNT - 1) / kNT;
+  const int ch = (P + kGridNT - 1) / kGridNT;
   const int ta = tid * ch < P ? tid * ch : P;
   const int tb = ta + ch < P ? ta + ch : P;
 
@@ -1373,12 +1434,12 @@ __global__ __launch_bounds__(NTG) void k_grid_affine(GridArgs A) {
 // Deterministic second stage of the t-gradient sums: series plans sum all
 // partials (one workgroup, fixed tree); varlen plans sum each system's tiles
 // in order (one thread per system).
-__global__ __launch_bounds__(kNT) void k_gt_reduce(const double* __restrict__ gpart,
+__global__ __launch_bounds__(kGridNT) void k_gt_reduce(const double* __restrict__ gpart,
                                                    const SysDesc* __restrict__ sys,
                                                    int64_t nsys, int64_t nparts, int varlen,
                                                    double* __restrict__ gt) {
   if (varlen) {
-    const int64_t s = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    const int64_t s = (int64_t)blockIdx.x * kGridNT + threadIdx.x;
     if (s >= nsys) return;
     const int64_t f0 = sys[s].fslot0;
     double u = 0.0, v = 0.0, z = 0.0;
@@ -1390,14 +1451,14 @@ __global__ __launch_bounds__(kNT) void k_gt_reduce(const double* __restrict__ gp
     gt[3 * s] = u; gt[3 * s + 1] = v; gt[3 * s + 2] = z;
     return;
   }
-  __shared__ double red[kNT][3];
+  __shared__ double red[kGridNT][3];
   double u = 0.0, v = 0.0, z = 0.0;
-  for (int64_t k = threadIdx.x; k < nparts; k += kNT) {
+  for (int64_t k = threadIdx.x; k < nparts; k += kGridNT) {
     u += gpart[3 * k]; v += gpart[3 * k + 1]; z += gpart[3 * k + 2];
   }
   red[threadIdx.x][0] = u; red[threadIdx.x][1] = v; red[threadIdx.x][2] = z;
   __syncthreads();
-  for (int h = kNT / 2; h >= 1; h >>= 1) {
+  for (int h = kGridNT / 2; h >= 1; h >>= 1) {
     if ((int)threadIdx.x < h) {
       red[threadIdx.x][0] += red[threadIdx.x + h][0];
       red[threadIdx.x][1] += red[threadIdx.x + h][1];
@@ -1418,7 +1479,7 @@ namespace tdt {
 
 // Resident workgroups per CU of a kernel (queried once per variant).
 template <typename KernelT>
-static int resident_per_cu(KernelT kern, int threads = kNT) {
+static int resident_per_cu(KernelT kern, int threads) {
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, threads, 0) != hipSuccess || nb < 1)
     nb = 1;
@@ -1444,41 +1505,42 @@ static int64_t grid_cap(int per_cu, int wg_per_cu) {
   return (int64_t)n * num_cus();
 }
 
-template <typename Tio, typename Tc, bool REFINE, bool SUMMARY, bool BWD>
+template <class SH, typename Tio, typename Tc, bool REFINE, bool SUMMARY, bool BWD>
 static void launch_tile(TileArgs<Tio>& A, int64_t nitems, int reverse, int last_only,
                         int wg_per_cu, hipStream_t st) {
-  auto kern = k_tile<Tio, Tc, REFINE, SUMMARY, BWD>;
-  static int per_cu = resident_per_cu(kern);
+  auto kern = k_tile<SH, Tio, Tc, REFINE, SUMMARY, BWD>;
+  static int per_cu = resident_per_cu(kern, SH::NT);
   const int64_t cap = grid_cap(per_cu, wg_per_cu);
   A.nitems = nitems;
   A.reverse = reverse;
   A.last_only = last_only;
   const unsigned grid = (unsigned)(nitems < cap ? nitems : cap);
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(kNT), 0, st, A);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(SH::NT), 0, st, A);
 }
 
-template <typename Tio, typename Tc, bool REFINE, bool BWD>
+template <class SH, typename Tio, typename Tc, bool REFINE, bool BWD>
 static void launch_sys(const LaunchSet& L, const TileArgs<Tio>& T, hipStream_t st) {
   SysArgs<Tio> A{T.F,         T.X,         T.sys,      T.vec64,  T.vec32,   T.tab64,
                  T.tab32,     L.sys_items, L.sys_bins, L.ttab,   L.ttab_n,  T.Xfwd,
                  T.gpart,     T.iters,     T.max_iter, T.refine_tol};
-  hipLaunchKernelGGL((k_sys<Tio, Tc, REFINE, BWD>), dim3((unsigned)L.n_bins), dim3(kNT), 0, st,
-                     A);
+  hipLaunchKernelGGL((k_sys<SH, Tio, Tc, REFINE, BWD>), dim3((unsigned)L.n_bins), dim3(SH::NT),
+                     0, st, A);
 }
 
-int sys_wg_capacity(int dtype, int wg_per_cu) {
+template <class SH>
+static int sys_capacity(int dtype, int wg_per_cu) {
   int per_cu;
   switch (dtype) {
-    case 0: per_cu = resident_per_cu(k_sys<double, double, false, false>); break;
-    case 1: per_cu = resident_per_cu(k_sys<float, float, false, false>); break;
-    default: per_cu = resident_per_cu(k_sys<double, float, true, false>); break;
+    case 0: per_cu = resident_per_cu(k_sys<SH, double, double, false, false>, SH::NT); break;
+    case 1: per_cu = resident_per_cu(k_sys<SH, float, float, false, false>, SH::NT); break;
+    default: per_cu = resident_per_cu(k_sys<SH, double, float, true, false>, SH::NT); break;
   }
   return (int)grid_cap(per_cu, wg_per_cu);
 }
 
-template <typename Tio>
+template <class SH, typename Tio>
 static void launch_beta(const LaunchSet& L, const Tio* F, hipStream_t st) {
-  auto kern = k_beta<Tio>;
+  auto kern = k_beta<SH, Tio>;
   static int per_cu = resident_per_cu(kern, kBetaNT);
   const int64_t cap = grid_cap(per_cu, L.wg_per_cu);
   BetaArgs<Tio> B{F, L.sys, L.green, L.n_beta, L.nfull, L.summ};
@@ -1486,7 +1548,25 @@ static void launch_beta(const LaunchSet& L, const Tio* F, hipStream_t st) {
   hipLaunchKernelGGL(kern, dim3(grid), dim3(kBetaNT), 0, st, B);
 }
 
-template <typename Tio, typename Tc, bool REFINE, bool BWD>
+// Interface pass across tiles: the affine variant sized for the most tiled
+// system (up to 16384 tiles), beyond that the segment-merge kernel.  The
+// plan lays out its workspace slots for the same choice (interface_run).
+static void launch_grid(const LaunchSet& L, hipStream_t st) {
+  GridArgs G{L.sys, L.grid_items, L.ttab, L.ttab_n, L.summ, L.ghost, L.gscr};
+  const dim3 gg((unsigned)L.n_grid);
+  if (L.max_ntiles <= 256)
+    hipLaunchKernelGGL((k_grid_affine<256, 1>), gg, dim3(256), 0, st, G);
+  else if (L.max_ntiles <= 2048)
+    hipLaunchKernelGGL((k_grid_affine<256, 8>), gg, dim3(256), 0, st, G);
+  else if (L.max_ntiles <= 8192)
+    hipLaunchKernelGGL((k_grid_affine<512, 16>), gg, dim3(512), 0, st, G);
+  else if (L.max_ntiles <= 16384)
+    hipLaunchKernelGGL((k_grid_affine<1024, 16>), gg, dim3(1024), 0, st, G);
+  else
+    hipLaunchKernelGGL(k_grid, gg, dim3(kGridNT), 0, st, G);
+}
+
+template <class SH, typename Tio, typename Tc, bool REFINE, bool BWD>
 static hipError_t run_solve(const LaunchSet& L, const void* F, void* X, const void* Xfwd,
                             hipStream_t st) {
   TileArgs<Tio> A;
@@ -1511,64 +1591,78 @@ static hipError_t run_solve(const LaunchSet& L, const void* F, void* X, const vo
   using Ts = typename std::conditional<REFINE, double, Tc>::type;
   if (L.n_p1 > 0) {
     if (L.green) {
-      if (L.n_beta > 0) launch_beta<Tio>(L, static_cast<const Tio*>(F), st);
+      if (L.n_beta > 0) launch_beta<SH, Tio>(L, static_cast<const Tio*>(F), st);
       if (L.n_last > 0) {
         A.items = nullptr;
-        launch_tile<Tio, Ts, false, true, false>(A, L.n_last, 0, 1, L.wg_per_cu, st);
+        launch_tile<SH, Tio, Ts, false, true, false>(A, L.n_last, 0, 1, L.wg_per_cu, st);
       }
     } else {
       A.items = L.p1_items;
-      launch_tile<Tio, Ts, false, true, false>(A, L.n_p1, 0, 0, L.wg_per_cu, st);
+      launch_tile<SH, Tio, Ts, false, true, false>(A, L.n_p1, 0, 0, L.wg_per_cu, st);
     }
     if (L.ev) (void)hipEventRecord(L.ev[1], st);
-    GridArgs G{L.sys, L.grid_items, L.ttab, L.ttab_n, L.summ, L.ghost, L.gscr};
-    const dim3 gg((unsigned)L.n_grid);
-    if (L.max_ntiles <= 256)
-      hipLaunchKernelGGL((k_grid_affine<256, 1>), gg, dim3(256), 0, st, G);
-    else if (L.max_ntiles <= 2048)
-      hipLaunchKernelGGL((k_grid_affine<256, 8>), gg, dim3(256), 0, st, G);
-    else if (L.max_ntiles <= 8192)
-      hipLaunchKernelGGL((k_grid_affine<512, 16>), gg, dim3(512), 0, st, G);
-    else
-      hipLaunchKernelGGL(k_grid, gg, dim3(kNT), 0, st, G);
+    launch_grid(L, st);
     if (L.ev) (void)hipEventRecord(L.ev[2], st);
   } else if (L.ev) {
     (void)hipEventRecord(L.ev[1], st);
     (void)hipEventRecord(L.ev[2], st);
   }
   // systems solved whole by one workgroup each (varlen plans)
-  if (L.n_sys > 0) launch_sys<Tio, Tc, REFINE, BWD>(L, A, st);
+  if (L.n_sys > 0) launch_sys<SH, Tio, Tc, REFINE, BWD>(L, A, st);
   A.items = L.fin_items;
   // after a first pass the final pass re-reads the tiles the first pass read
   // last while they are still cached: a series runs last-tile-first, a varlen
   // plan's list already starts with the first pass's tiles in reverse
   if (L.n_fin > 0)
-    launch_tile<Tio, Tc, REFINE, false, BWD>(A, L.n_fin, (L.n_p1 > 0 && !L.fin_items) ? 1 : 0,
-                                             0, L.wg_per_cu, st);
+    launch_tile<SH, Tio, Tc, REFINE, false, BWD>(
+        A, L.n_fin, (L.n_p1 > 0 && !L.fin_items) ? 1 : 0, 0, L.wg_per_cu, st);
   if (L.ev) (void)hipEventRecord(L.ev[3], st);
   return hipGetLastError();
 }
 
-hipError_t launch_solve(int dtype, bool bwd, const LaunchSet& L, const void* F, void* X,
-                        const void* Xfwd, hipStream_t st) {
+template <class SH>
+static hipError_t launch_shape(int dtype, bool bwd, const LaunchSet& L, const void* F, void* X,
+                               const void* Xfwd, hipStream_t st) {
   switch (dtype) {
     case 0:
-      return bwd ? run_solve<double, double, false, true>(L, F, X, Xfwd, st)
-                 : run_solve<double, double, false, false>(L, F, X, Xfwd, st);
+      return bwd ? run_solve<SH, double, double, false, true>(L, F, X, Xfwd, st)
+                 : run_solve<SH, double, double, false, false>(L, F, X, Xfwd, st);
     case 1:
-      return bwd ? run_solve<float, float, false, true>(L, F, X, Xfwd, st)
-                 : run_solve<float, float, false, false>(L, F, X, Xfwd, st);
+      return bwd ? run_solve<SH, float, float, false, true>(L, F, X, Xfwd, st)
+                 : run_solve<SH, float, float, false, false>(L, F, X, Xfwd, st);
     default:
-      return bwd ? run_solve<double, float, true, true>(L, F, X, Xfwd, st)
-                 : run_solve<double, float, true, false>(L, F, X, Xfwd, st);
+      return bwd ? run_solve<SH, double, float, true, true>(L, F, X, Xfwd, st)
+                 : run_solve<SH, double, float, true, false>(L, F, X, Xfwd, st);
+  }
+}
+
+using Shape0 = Shape<kShapes[0].B, kShapes[0].NT, kShapes[0].waves>;
+using Shape1 = Shape<kShapes[1].B, kShapes[1].NT, kShapes[1].waves>;
+using Shape2 = Shape<kShapes[2].B, kShapes[2].NT, kShapes[2].waves>;
+static_assert(kNumShapes == 3, "one Shape alias per entry of kShapes");
+
+hipError_t launch_solve(int dtype, bool bwd, const LaunchSet& L, const void* F, void* X,
+                        const void* Xfwd, hipStream_t st) {
+  switch (L.shape) {
+    case 1: return launch_shape<Shape1>(dtype, bwd, L, F, X, Xfwd, st);
+    case 2: return launch_shape<Shape2>(dtype, bwd, L, F, X, Xfwd, st);
+    default: return launch_shape<Shape0>(dtype, bwd, L, F, X, Xfwd, st);
+  }
+}
+
+int sys_wg_capacity(int shape, int dtype, int wg_per_cu) {
+  switch (shape) {
+    case 1: return sys_capacity<Shape1>(dtype, wg_per_cu);
+    case 2: return sys_capacity<Shape2>(dtype, wg_per_cu);
+    default: return sys_capacity<Shape0>(dtype, wg_per_cu);
   }
 }
 
 hipError_t launch_gt_reduce(const double* gpart, const SysDesc* sys, int64_t nsys,
                             int64_t nparts, int varlen, double* gt, hipStream_t st) {
-  const unsigned grid = varlen ? (unsigned)((nsys + kNT - 1) / kNT) : 1u;
-  hipLaunchKernelGGL(k_gt_reduce, dim3(grid), dim3(kNT), 0, st, gpart, sys, nsys, nparts, varlen,
-                     gt);
+  const unsigned grid = varlen ? (unsigned)((nsys + kGridNT - 1) / kGridNT) : 1u;
+  hipLaunchKernelGGL(k_gt_reduce, dim3(grid), dim3(kGridNT), 0, st, gpart, sys, nsys, nparts,
+                     varlen, gt);
   return hipGetLastError();
 }
 

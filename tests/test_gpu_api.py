@@ -68,6 +68,38 @@ def test_info():
     assert 1 <= info["refine_iters"] <= 40
     assert info["dominance"] == pytest.approx(1.25)
     assert 1 < info["kappa2"] < 20
+    assert info["converged"] and 0 <= info["last_rel_update"] <= 1e-12
+    assert plan.info()["refine_iters"] == 0            # the record was cleared
+
+
+def test_not_converged_is_reported():
+    """A cap of one float solve leaves no refinement update: the plan reports
+    it through tdt_last_info (the solution is the float one)."""
+    tdt = _tdt()
+    n = 10000
+    F = np.random.default_rng(1).standard_normal(n)
+    plan = tdt.Plan(-0.9, 2.5, -1.1, n, "f32_refine")
+    plan.set_option("max_refine", 1)
+    X = to_host(plan.solve(to_dev(F)))
+    info = plan.info()
+    assert info["refine_iters"] == 1 and not info["converged"]
+    assert info["last_rel_update"] == 1.0
+    assert oracle.rel_err(X, oracle.solve(F, -0.9, 2.5, -1.1)) <= 1e-5
+    plan.set_option("max_refine", 40)
+    X = to_host(plan.solve(to_dev(F)))
+    assert plan.info()["converged"]
+    assert oracle.rel_err(X, oracle.solve(F, -0.9, 2.5, -1.1)) <= 1e-12
+
+
+def test_solve_varlen_function():
+    tdt = _tdt()
+    rng = np.random.default_rng(8)
+    off = np.array([0, 5, 9000, 9001, 30000], dtype=np.int64)
+    t0 = rng.uniform(2.5, 4.0, 4)
+    F = rng.standard_normal(int(off[-1]))
+    X = to_host(tdt.solve_varlen(to_dev(F), off, -1.0, t0, -0.8, "f32_refine"))
+    ref = oracle.solve_varlen(F, off, -1.0, t0, -0.8)
+    assert oracle.rel_err_rows(X, ref, off).max() <= 1e-12
 
 
 @pytest.mark.parametrize("varlen", [False, True])
@@ -131,13 +163,15 @@ def test_options_validation():
     off = np.array([0, 100, 20000], dtype=np.int64)
     vp = tdt.VarlenPlan(off, -1.0, 3.0, -1.0)
     for name, bad in (("whole_max_tiles", -1), ("whole_max_tiles", 17), ("wg_per_cu", -1),
-                      ("max_refine", 0), ("max_refine", 101)):
+                      ("max_refine", 0), ("max_refine", 101), ("shape", -1),
+                      ("shape", len(_lib.SHAPES))):
         with pytest.raises(tdt.TDTError) as e:
             vp.set_option(name, bad)
         assert e.value.status == _lib.TDT_ERR_INVALID_ARG
     assert vp.get_option("whole_max_tiles") == 8
     assert vp.get_option("wg_per_cu") == 0
     assert vp.get_option("max_refine") == 40
+    assert vp.get_option("shape") == 0
 
 
 def test_autotune_choice_cache_and_result(tmp_path, monkeypatch):
@@ -158,16 +192,20 @@ def test_autotune_choice_cache_and_result(tmp_path, monkeypatch):
     Fd = to_dev(F)
     res = plan.autotune(Fd)
     assert res["ms"] > 0 and res["whole_max_tiles"] in (0, 1, 2, 4, 8, 16)
-    assert res["wg_per_cu"] in (0, 1)
+    assert res["wg_per_cu"] in (0, 1) and res["shape"] in range(len(_lib.SHAPES))
     X = to_host(plan.solve(Fd))
     assert oracle.rel_err_rows(X, ref, off).max() <= 1e-12
     doc = json.loads(cache.read_text())
     assert doc["format"] == "tdt-autotune-1" and len(doc["entries"]) == 1
     (key, entry), = doc["entries"].items()
     assert "varlen|f32_refine" in key and entry["whole_max_tiles"] == res["whole_max_tiles"]
+    assert entry["shape"] == res["shape"]
     plan2 = tdt.VarlenPlan(off, -1.0, t0, -0.9, "f32_refine")
     res2 = plan2.autotune(Fd)                     # from the cache: no timing
     assert res2["ms"] == 0.0 and res2["whole_max_tiles"] == res["whole_max_tiles"]
+    assert res2["shape"] == res["shape"]
+    X2 = to_host(plan2.solve(Fd))
+    assert oracle.rel_err_rows(X2, ref, off).max() <= 1e-12
     # a series plan gets its own entry
     sp = tdt.Plan(-1.0, 3.0, -1.0, 20000, "f64")
     Fs = to_dev(rng.standard_normal((2, 20000)))
