@@ -112,10 +112,9 @@ def make_plan(tdt, d, mode):
     return tdt.VarlenPlan(d["offsets"], d["t_m1"], d["t_0"], d["t_1"], mode)
 
 
-def tile_counts(d):
+def tile_counts(d, tile):
     """Unknowns that go through the first pass (systems of more than one
-    tile) and through the final pass (all)."""
-    tile = 8192
+    tile of `tile` rows) and through the final pass (all)."""
     if d["kind"] == "series":
         multi = d["N"] > tile
         return (d["N"] * d["M"] if multi else 0), d["N"] * d["M"]
@@ -276,7 +275,9 @@ def main() -> int:
 
     U = d["units"]
     head = modes[0]
-    n_first, n_final = tile_counts(d)
+    from paper_1002_2469_amd import _lib
+    shape = (res[head]["tuned"] or {}).get("shape", 0)
+    n_first, n_final = tile_counts(d, _lib.SHAPES[shape][0] * _lib.SHAPES[shape][1])
     # algorithmic HBM bytes per launch of each kernel group (double data)
     per_launch = {"first_pass": 8.0 * n_first, "final_pass": 16.0 * n_final,
                   "bwd_first_pass": 8.0 * n_first, "bwd_final_pass": 24.0 * n_final}
