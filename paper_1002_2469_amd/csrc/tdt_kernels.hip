@@ -121,16 +121,23 @@ __device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, int off) {
   else
     return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
 }
-template <typename T>
+// AUX: the instruction's cache-policy bits (0: default; 2: non-temporal).
+template <typename T, int AUX = 0>
 __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, int off, T v) {
   if constexpr (sizeof(T) == 8) {
     using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, off, 0, AUX);
   } else {
     using V = decltype(__builtin_amdgcn_raw_buffer_load_b32(r, 0, 0, 0));
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(V, v), r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(V, v), r, off, 0, AUX);
   }
 }
+// The solution is stored non-temporal: it is not read again by this solve,
+// and lines that do not linger dirty in the caches leave the next read of the
+// right-hand side (the first pass of the next solve) at full speed.
+#ifndef TDT_STORE_AUX
+#define TDT_STORE_AUX 2
+#endif
 
 template <typename T>
 __device__ __forceinline__ Seg<T> seg_zero() {
@@ -833,7 +840,7 @@ __device__ __forceinline__ void store_tile(TileShared<SH, Tio, Tc>& sh, Tio* X, 
   for (int j = 0; j < kB; ++j) {
     const int e = j * kNT + tid;
     const Tio gval = lr[j * lstride];
-    buf_store<Tio>(dst, vs + j * kNT * (int)sizeof(Tio), gval);
+    buf_store<Tio, TDT_STORE_AUX>(dst, vs + j * kNT * (int)sizeof(Tio), gval);
     if constexpr (BWD) {
       const int xo = vs + (j * kNT + lo) * (int)sizeof(Tio);
       const double xe = (double)buf_load<Tio>(xf, xo);
