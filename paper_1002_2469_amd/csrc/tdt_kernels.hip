@@ -1291,16 +1291,18 @@ __global__ __launch_bounds__(kGridNT) void k_grid(GridArgs A) {
 }
 
 // Interface pass across the tiles of one system, affine form (one workgroup
-// of NTG threads per system and right-hand side, runs of up to R tiles per
-// thread).  Tiles play the role blocks play inside a tile: with (yf_t, yl_t)
-// the tile summaries and (Pf, Pl, Cf, Cl) the end values of a full tile (the
-// last tile has its own, padded), the left-to-right elimination coefficient
+// of NTG threads per system and right-hand side, runs of R consecutive tiles
+// per thread).  Tiles play the role blocks play inside a tile: with
+// (yf_t, yl_t) the tile summaries and (Pf, Pl, Cf, Cl) the end values of a
+// full tile (the last tile has its own, padded), the left-to-right
+// elimination coefficient
 //     beta_t = Cl + Pl Cf beta_{t-1} / (1 - Pf beta_{t-1}),  beta_{-1} = 0,
-// is a Moebius map of beta_{t-1}; its values at the start of every run come
-// from a scan of the 2x2 matrices of those maps.  Then, as in a tile,
+// depends on T only and comes, with 1/(1 - Pf beta_{t-1}), from the plan's
+// table.  Then, as in a tile,
 //     alpha_t = A_t alpha_{t-1} + g_t   (left to right, alpha_{-1} = 0),
 //     u_t     = C_t u_{t+1} + h_t       (right to left, u_P = 0),
-// and tile t's outside values are alpha_{t-1} + beta_{t-1} u_t and u_{t+1}.
+// evaluated as two affine scans over the runs, and tile t's outside values
+// are alpha_{t-1} + beta_{t-1} u_t and u_{t+1}.
 template <int NTG>
 struct GridShared {
   double f[NTG / 64][2];   // wave aggregates (left-to-right affine map)
@@ -1341,6 +1343,7 @@ __device__ __forceinline__ double scan_affine_bwd(double C, double h, double x_i
   return lane == 63 ? e : ex;
 }
 
+// Runs are held in registers: every input of the run is loaded up front.
 template <int NTG, int R>
 __global__ __launch_bounds__(NTG) void k_grid_affine(GridArgs A) {
   __shared__ GridShared<NTG> sh;
@@ -1435,6 +1438,97 @@ __global__ __launch_bounds__(NTG) void k_grid_affine(GridArgs A) {
       ghost[2 * pc] = ap[r] + bp[r] * u;
       ghost[2 * pc + 1] = un;
     }
+  }
+}
+
+// The same pass for the widest workgroup (1024 threads, whose register
+// budget cannot hold a run's inputs): each pass re-reads a tile's inputs from
+// L2, and alpha_{t-1} and h_t wait in the tile's ghost slot between passes.
+template <int NTG, int R>
+__global__ __launch_bounds__(NTG) void k_grid_affine_lean(GridArgs A) {
+  __shared__ GridShared<NTG> sh;
+  const int tid = threadIdx.x;
+  int s = 0;
+  int64_t slot0;
+  if (A.gitems) {
+    s = as_const(A.gitems)[blockIdx.x];
+    slot0 = *as_const(&A.sys[s].slot0);
+  } else {
+    slot0 = (int64_t)blockIdx.x * *as_const(&A.sys[0].tslots);
+  }
+  const SysDesc S = load_sys(A.sys, s);
+  const int P = S.ntiles;
+  const int tq = S.tq;
+  const double* summ = A.summ + 2 * slot0;
+  double* ghost = A.ghost + 2 * slot0;
+  const int64_t tb0 = A.gitems ? slot0 : 0;
+  const int ta = tid * R;
+  // This thread's tiles ta .. ta+R-1 (those >= P are empty); tile ta+r sits
+  // at slot r*tq + tid (run-interleaved).  Each pass re-reads a tile's
+  // inputs (L2-resident) instead of holding them in registers: the summary
+  // (yf, yl), beta_{t-1} and 1/(1 - Pf_t beta_{t-1}) from the plan's table
+  // (they depend on T only), and the end values (Pf, Pl, Cf) of a full tile
+  // (the last tile has its own).
+  auto pos = [&](int r) { return ta + r < P ? r * tq + tid : 0; };
+  struct TileIn { double yf, yl, bp, iD, pf, pl, cf; };
+  auto tile_in = [&](int r) {
+    const int t = ta + r;
+    const int pc = pos(r);
+    const bool real = t < P, last = t == P - 1;
+    const double* K = last ? S.ltileK : S.tileK;
+    const double u = summ[2 * pc], v = summ[2 * pc + 1];
+    const double b0 = A.ttab[tb0 + pc], i0 = A.ttab[A.ttab_n + tb0 + pc];
+    TileIn x;
+    x.yf = real ? u : 0.0;
+    x.yl = real ? v : 0.0;
+    x.bp = real ? b0 : 0.0;
+    x.iD = real ? i0 : 1.0;
+    x.pf = real ? K[0] : 0.0;
+    x.pl = real ? K[1] : 0.0;
+    x.cf = real ? K[2] : 0.0;
+    return x;
+  };
+  // 1. composite left-to-right map of the run: alpha_t = A_t alpha_{t-1} + g_t
+  double Af = 1.0, gf = 0.0;
+#pragma unroll 4
+  for (int r = 0; r < R; ++r) {
+    const TileIn x = tile_in(r);
+    const double At = x.pl * x.iD;
+    const double gt = x.yl + At * x.bp * x.yf;
+    gf = At * gf + gt;
+    Af = At * Af;
+  }
+  // 2. alpha entering the run; walk it, keeping alpha_{t-1} and h_t of every
+  //    tile in its ghost slot until step 3, and compose the run's right-to-left
+  //    map u_t = C_t u_{t+1} + h_t front to back (u_ta = Cb u_{ta+R} + hb)
+  double alpha = scan_affine_fwd<NTG>(Af, gf, 0.0, sh.f);   // alpha_{ta-1}
+  double Cb = 1.0, hb = 0.0;
+#pragma unroll 4
+  for (int r = 0; r < R; ++r) {
+    const TileIn x = tile_in(r);
+    const double h = (x.yf + x.pf * alpha) * x.iD;
+    if (ta + r < P) {
+      const int pc = pos(r);
+      ghost[2 * pc] = alpha;
+      ghost[2 * pc + 1] = h;
+    }
+    hb += Cb * h;
+    Cb *= x.cf * x.iD;
+    alpha = x.pl * x.iD * alpha + (x.yl + x.pl * x.iD * x.bp * x.yf);
+  }
+  // 3. u (right to left) and the values just outside every tile:
+  //    alpha_{t-1} + beta_{t-1} u_t and u_{t+1}
+  double u = scan_affine_bwd<NTG>(Cb, hb, 0.0, sh.b);       // u_{ta+R}
+#pragma unroll 4
+  for (int r = R - 1; r >= 0; --r) {
+    if (ta + r >= P) continue;
+    const TileIn x = tile_in(r);
+    const int pc = pos(r);
+    const double ap = ghost[2 * pc], h = ghost[2 * pc + 1];
+    const double un = u;                 // u_{t+1}
+    u = x.cf * x.iD * u + h;             // u_t
+    ghost[2 * pc] = ap + x.bp * u;
+    ghost[2 * pc + 1] = un;
   }
 }
 
@@ -1568,7 +1662,7 @@ static void launch_grid(const LaunchSet& L, hipStream_t st) {
   else if (L.max_ntiles <= 8192)
     hipLaunchKernelGGL((k_grid_affine<512, 16>), gg, dim3(512), 0, st, G);
   else if (L.max_ntiles <= 16384)
-    hipLaunchKernelGGL((k_grid_affine<1024, 16>), gg, dim3(1024), 0, st, G);
+    hipLaunchKernelGGL((k_grid_affine_lean<1024, 16>), gg, dim3(1024), 0, st, G);
   else
     hipLaunchKernelGGL(k_grid, gg, dim3(kGridNT), 0, st, G);
 }
