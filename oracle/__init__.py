@@ -46,10 +46,10 @@ def build(force: bool = True) -> str:
 def _bind(path: str):
     lib = ctypes.CDLL(path)
     d, i64, i32, p = ctypes.c_double, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p
-    lib.oracle_solve.argtypes = [d, d, d, i64, i64, p, p, i32, i32]
-    lib.oracle_solve_varlen.argtypes = [i64, p, p, p, p, p, p, i32, i32]
-    lib.oracle_adjoint.argtypes = [d, d, d, i64, i64, p, p, p, p, i32]
-    lib.oracle_adjoint_varlen.argtypes = [i64, p, p, p, p, p, p, p, p, i32]
+    lib.oracle_solve.argtypes = [d, d, d, d, d, i64, i64, p, p, i32, i32]
+    lib.oracle_solve_varlen.argtypes = [i64, p, p, p, p, p, p, p, p, i32, i32]
+    lib.oracle_adjoint.argtypes = [d, d, d, d, d, i64, i64, p, p, p, p, i32]
+    lib.oracle_adjoint_varlen.argtypes = [i64, p, p, p, p, p, p, p, p, p, p, i32]
     lib.oracle_threads.argtypes = [i32]
     for f in (lib.oracle_solve, lib.oracle_solve_varlen, lib.oracle_adjoint,
               lib.oracle_adjoint_varlen, lib.oracle_threads):
@@ -102,57 +102,71 @@ class Oracle:
         return self.lib.oracle_threads(int(nthreads))
 
     def solve(self, F, t_m1: float, t_0: float, t_1: float, precision: str = "f64",
-              nthreads: int = 0) -> np.ndarray:
-        """X = T^{-1} F.  F is [N] or [M, N] (one right-hand side per row)."""
+              nthreads: int = 0, psi: float = 0.0, chi: float = 0.0) -> np.ndarray:
+        """X = T^{-1} F.  F is [N] or [M, N] (one right-hand side per row).
+        psi, chi: corner terms of the quasi-Toeplitz matrix of eq. (21)."""
         F = _f64(F)
         squeeze = F.ndim == 1
         F2 = F.reshape(1, -1) if squeeze else F
         M, N = F2.shape
         X = np.empty_like(F2)
         prec = {"f64": 0, "ld": 1}[precision]
-        _check(self.lib.oracle_solve(float(t_m1), float(t_0), float(t_1), N, M,
-                                     _ptr(F2), _ptr(X), prec, int(nthreads)))
+        _check(self.lib.oracle_solve(float(t_m1), float(t_0), float(t_1), float(psi),
+                                     float(chi), N, M, _ptr(F2), _ptr(X), prec, int(nthreads)))
         return X.reshape(-1) if squeeze else X
 
     def solve_varlen(self, F, offsets, t_m1, t_0, t_1, precision: str = "f64",
-                     nthreads: int = 0) -> np.ndarray:
-        """Packed systems: system s is F[offsets[s]:offsets[s+1]] with its own t's."""
+                     nthreads: int = 0, psi=None, chi=None) -> np.ndarray:
+        """Packed systems: system s is F[offsets[s]:offsets[s+1]] with its own t's
+        (and corner terms psi[s], chi[s] when given)."""
         F = _f64(F)
         off = np.ascontiguousarray(offsets, dtype=np.int64)
         S = off.size - 1
         tm1, t0, t1 = (_f64(np.broadcast_to(t, (S,))) for t in (t_m1, t_0, t_1))
+        ps = None if psi is None else _f64(np.broadcast_to(psi, (S,)))
+        ch = None if chi is None else _f64(np.broadcast_to(chi, (S,)))
         X = np.empty_like(F)
         prec = {"f64": 0, "ld": 1}[precision]
         _check(self.lib.oracle_solve_varlen(S, _ptr(off), _ptr(tm1), _ptr(t0), _ptr(t1),
+                                            None if ps is None else _ptr(ps),
+                                            None if ch is None else _ptr(ch),
                                             _ptr(F), _ptr(X), prec, int(nthreads)))
         return X
 
-    def adjoint(self, gX, X, t_m1: float, t_0: float, t_1: float, nthreads: int = 0):
-        """Returns (gF, gt) with gt = (dL/dt_-1, dL/dt_0, dL/dt_1) summed over RHS."""
+    def adjoint(self, gX, X, t_m1: float, t_0: float, t_1: float, nthreads: int = 0,
+                psi: float = 0.0, chi: float = 0.0, corners: bool = False):
+        """Returns (gF, gt) with gt = (dL/dt_-1, dL/dt_0, dL/dt_1) summed over RHS,
+        followed by (dL/dpsi, dL/dchi) when ``corners``."""
         gX, X = _f64(gX), _f64(X)
         squeeze = gX.ndim == 1
         g2 = gX.reshape(1, -1) if squeeze else gX
         x2 = X.reshape(1, -1) if squeeze else X
         M, N = g2.shape
         gF = np.empty_like(g2)
-        gt = np.empty(3)
-        _check(self.lib.oracle_adjoint(float(t_m1), float(t_0), float(t_1), N, M,
-                                       _ptr(g2), _ptr(x2), _ptr(gF), _ptr(gt),
-                                       int(nthreads)))
-        return (gF.reshape(-1) if squeeze else gF), gt
+        gt = np.empty(5)
+        _check(self.lib.oracle_adjoint(float(t_m1), float(t_0), float(t_1), float(psi),
+                                       float(chi), N, M, _ptr(g2), _ptr(x2), _ptr(gF),
+                                       _ptr(gt), int(nthreads)))
+        return (gF.reshape(-1) if squeeze else gF), (gt if corners else gt[:3])
 
-    def adjoint_varlen(self, gX, X, offsets, t_m1, t_0, t_1, nthreads: int = 0):
-        """Returns (gF packed, gt [S, 3])."""
+    def adjoint_varlen(self, gX, X, offsets, t_m1, t_0, t_1, nthreads: int = 0,
+                       psi=None, chi=None, corners: bool = False):
+        """Returns (gF packed, gt [S, 3]), or gt [S, 5] with (dL/dpsi, dL/dchi)
+        appended when ``corners``."""
         gX, X = _f64(gX), _f64(X)
         off = np.ascontiguousarray(offsets, dtype=np.int64)
         S = off.size - 1
         tm1, t0, t1 = (_f64(np.broadcast_to(t, (S,))) for t in (t_m1, t_0, t_1))
+        ps = None if psi is None else _f64(np.broadcast_to(psi, (S,)))
+        ch = None if chi is None else _f64(np.broadcast_to(chi, (S,)))
         gF = np.empty_like(gX)
-        gt = np.empty((S, 3))
-        _check(self.lib.oracle_adjoint_varlen(S, _ptr(off), _ptr(tm1), _ptr(t0),
-                                              _ptr(t1), _ptr(gX), _ptr(X), _ptr(gF),
-                                              _ptr(gt), int(nthreads)))
-        return gF, gt
+        gt = np.empty((S, 5))
+        _check(self.lib.oracle_adjoint_varlen(S, _ptr(off), _ptr(tm1), _ptr(t0), _ptr(t1),
+                                              None if ps is None else _ptr(ps),
+                                              None if ch is None else _ptr(ch),
+                                              _ptr(gX), _ptr(X), _ptr(gF), _ptr(gt),
+                                              int(nthreads)))
+        return gF, (gt if corners else gt[:, :3])
 
 
 def load_library(path: str) -> Oracle:

@@ -30,11 +30,17 @@
  * ill-conditioned systems, where the double result itself errs by
  * ~ cond(T) 2^-53.
  *
+ * Quasi-Toeplitz matrices (paper, eq. (21)): the same matrix with t0+psi as
+ * its first and t0+chi as its last diagonal entry (both added to the single
+ * entry when N = 1).  The recurrence above is unchanged but for the pivot of
+ * those rows: u_1 = t0 + psi, and t0 + chi in place of t0 in u_N.
+ *
  * Adjoint (the differentiation extension): for L = <W, X> with X = T^{-1} F,
  *   gF = T^{-T} gX,  i.e. the same Thomas recurrence on T^T = tridiag{t1,t0,t-1}
  *   dL/dt0  = - sum_i   gF_i x_i
  *   dL/dt1  = - sum_i   gF_i x_{i+1}      (entries T_{i,i+1})
  *   dL/dt-1 = - sum_i   gF_{i+1} x_i      (entries T_{i+1,i})
+ *   dL/dpsi = - gF_1 x_1,   dL/dchi = - gF_N x_N   (quasi-Toeplitz)
  * which follows from dX = -T^{-1} dT X.  The transposed solve is the paper's
  * remark in Sec. 2.3 that (A^T)^{-1} = (A^{-1})^T.  Sums are accumulated in
  * long double over all entries and right-hand sides.
@@ -47,15 +53,24 @@
 #endif
 
 /* ---- one system, one right-hand side, double ---------------------------- */
-static int thomas_f64(double tm1, double t0, double t1, int64_t n,
+/* diagonal entry of row i (0-based) of the quasi-Toeplitz matrix */
+static double diag_f64(double t0, double psi, double chi, int64_t i, int64_t n)
+{
+    double d = t0;
+    if (i == 0) d += psi;
+    if (i == n - 1) d += chi;
+    return d;
+}
+
+static int thomas_f64(double tm1, double t0, double t1, double psi, double chi, int64_t n,
                       const double *f, double *x, double *cp /* scratch n */)
 {
-    double u = t0;
+    double u = diag_f64(t0, psi, chi, 0, n);
     if (u == 0.0) return 1;
     cp[0] = t1 / u;
     x[0] = f[0] / u;                       /* x holds d' until back-substitution */
     for (int64_t i = 1; i < n; ++i) {
-        u = t0 - tm1 * cp[i - 1];
+        u = diag_f64(t0, psi, chi, i, n) - tm1 * cp[i - 1];
         if (u == 0.0) return 1;
         cp[i] = t1 / u;
         x[i] = (f[i] - tm1 * x[i - 1]) / u;
@@ -66,15 +81,25 @@ static int thomas_f64(double tm1, double t0, double t1, int64_t n,
 }
 
 /* ---- one system, one right-hand side, long double ------------------------ */
-static int thomas_ld(long double tm1, long double t0, long double t1, int64_t n,
-                     const long double *f, long double *x, long double *cp)
+static long double diag_ld(long double t0, long double psi, long double chi, int64_t i,
+                           int64_t n)
 {
-    long double u = t0;
+    long double d = t0;
+    if (i == 0) d += psi;
+    if (i == n - 1) d += chi;
+    return d;
+}
+
+static int thomas_ld(long double tm1, long double t0, long double t1, long double psi,
+                     long double chi, int64_t n, const long double *f, long double *x,
+                     long double *cp)
+{
+    long double u = diag_ld(t0, psi, chi, 0, n);
     if (u == 0.0L) return 1;
     cp[0] = t1 / u;
     x[0] = f[0] / u;
     for (int64_t i = 1; i < n; ++i) {
-        u = t0 - tm1 * cp[i - 1];
+        u = diag_ld(t0, psi, chi, i, n) - tm1 * cp[i - 1];
         if (u == 0.0L) return 1;
         cp[i] = t1 / u;
         x[i] = (f[i] - tm1 * x[i - 1]) / u;
@@ -86,12 +111,12 @@ static int thomas_ld(long double tm1, long double t0, long double t1, int64_t n,
 
 /* Long double variant: the same recurrence with every operation in x87
  * extended precision, rounded to double at the end.  work: 3*n long doubles. */
-static int thomas_ld_to_f64(double tm1, double t0, double t1, int64_t n,
-                            const double *f, double *xout, long double *work)
+static int thomas_ld_to_f64(double tm1, double t0, double t1, double psi, double chi,
+                            int64_t n, const double *f, double *xout, long double *work)
 {
     long double *fl = work, *x = work + n, *cp = work + 2 * n;
     for (int64_t i = 0; i < n; ++i) fl[i] = (long double)f[i];
-    int st = thomas_ld(tm1, t0, t1, n, fl, x, cp);
+    int st = thomas_ld(tm1, t0, t1, psi, chi, n, fl, x, cp);
     if (st) return st;
     for (int64_t i = 0; i < n; ++i) xout[i] = (double)x[i];
     return 0;
@@ -108,10 +133,11 @@ static int set_threads(int nthreads)
 #endif
 }
 
-/* F, X: [M][N] row-major (one right-hand side per row).  precision: 0 = double,
- * 1 = long double.  Returns 0, 1 if some
- * pivot is zero, 2 on allocation failure.  nthreads <= 0 keeps the default. */
-int oracle_solve(double tm1, double t0, double t1, int64_t N, int64_t M,
+/* F, X: [M][N] row-major (one right-hand side per row).  psi, chi: corner
+ * terms of eq. (21) (0 for a Toeplitz matrix).  precision: 0 = double,
+ * 1 = long double.  Returns 0, 1 if some pivot is zero, 2 on allocation
+ * failure, 3 on bad arguments.  nthreads <= 0 keeps the default. */
+int oracle_solve(double tm1, double t0, double t1, double psi, double chi, int64_t N, int64_t M,
                  const double *F, double *X, int precision, int nthreads)
 {
     if (N < 1 || M < 1 || !F || !X) return 3;
@@ -127,8 +153,8 @@ int oracle_solve(double tm1, double t0, double t1, int64_t N, int64_t M,
         for (int64_t m = 0; m < M; ++m) {
             if (local == 2) continue;
             int st = precision == 1
-                ? thomas_ld_to_f64(tm1, t0, t1, N, F + m * N, X + m * N, wl)
-                : thomas_f64(tm1, t0, t1, N, F + m * N, X + m * N, cp);
+                ? thomas_ld_to_f64(tm1, t0, t1, psi, chi, N, F + m * N, X + m * N, wl)
+                : thomas_f64(tm1, t0, t1, psi, chi, N, F + m * N, X + m * N, cp);
             if (st > local) local = st;
         }
 #pragma omp critical
@@ -139,11 +165,13 @@ int oracle_solve(double tm1, double t0, double t1, int64_t N, int64_t M,
 }
 
 /* S systems packed back to back: system s occupies [offsets[s], offsets[s+1])
- * of F and X and has its own (tm1[s], t0[s], t1[s]).  Systems are handed out
- * largest first with dynamic scheduling. */
+ * of F and X and has its own (tm1[s], t0[s], t1[s]) and corner terms
+ * (psi[s], chi[s]; both arrays may be NULL for Toeplitz systems).  Systems are
+ * handed out largest first with dynamic scheduling. */
 int oracle_solve_varlen(int64_t S, const int64_t *offsets, const double *tm1,
-                        const double *t0, const double *t1, const double *F,
-                        double *X, int precision, int nthreads)
+                        const double *t0, const double *t1, const double *psi,
+                        const double *chi, const double *F, double *X, int precision,
+                        int nthreads)
 {
     if (S < 1 || !offsets || !F || !X) return 3;
     int64_t nmax = 0;
@@ -175,9 +203,10 @@ int oracle_solve_varlen(int64_t S, const int64_t *offsets, const double *tm1,
         for (int64_t i = 0; i < S; ++i) {
             if (local == 2) continue;
             int64_t s = order[i], o = offsets[s], n = offsets[s + 1] - o;
+            const double ps = psi ? psi[s] : 0.0, ch = chi ? chi[s] : 0.0;
             int st = precision == 1
-                ? thomas_ld_to_f64(tm1[s], t0[s], t1[s], n, F + o, X + o, wl)
-                : thomas_f64(tm1[s], t0[s], t1[s], n, F + o, X + o, cp);
+                ? thomas_ld_to_f64(tm1[s], t0[s], t1[s], ps, ch, n, F + o, X + o, wl)
+                : thomas_f64(tm1[s], t0[s], t1[s], ps, ch, n, F + o, X + o, cp);
             if (st > local) local = st;
         }
 #pragma omp critical
@@ -189,17 +218,18 @@ int oracle_solve_varlen(int64_t S, const int64_t *offsets, const double *tm1,
 }
 
 /* Adjoint of X = T^{-1} F for M right-hand sides sharing one T.
- * gX, X: [M][N] in; gF: [M][N] out; gt[3] = (dL/dt-1, dL/dt0, dL/dt1) summed
- * over all right-hand sides. */
-int oracle_adjoint(double tm1, double t0, double t1, int64_t N, int64_t M,
-                   const double *gX, const double *X, double *gF, double *gt,
+ * gX, X: [M][N] in; gF: [M][N] out; gt[5] = (dL/dt-1, dL/dt0, dL/dt1,
+ * dL/dpsi, dL/dchi) summed over all right-hand sides. */
+int oracle_adjoint(double tm1, double t0, double t1, double psi, double chi, int64_t N,
+                   int64_t M, const double *gX, const double *X, double *gF, double *gt,
                    int nthreads)
 {
     if (N < 1 || M < 1 || !gX || !X || !gF || !gt) return 3;
-    /* gF = T^{-T} gX: Thomas on the transpose, i.e. t1 and t-1 exchanged */
-    int st = oracle_solve(t1, t0, tm1, N, M, gX, gF, 0, nthreads);
+    /* gF = T^{-T} gX: Thomas on the transpose, i.e. t1 and t-1 exchanged
+       (the corner terms sit on the diagonal and stay) */
+    int st = oracle_solve(t1, t0, tm1, psi, chi, N, M, gX, gF, 0, nthreads);
     if (st) return st;
-    long double s_m1 = 0.0L, s_0 = 0.0L, s_p1 = 0.0L;
+    long double s_m1 = 0.0L, s_0 = 0.0L, s_p1 = 0.0L, s_ps = 0.0L, s_ch = 0.0L;
     for (int64_t m = 0; m < M; ++m) {
         const double *g = gF + m * N, *x = X + m * N;
         for (int64_t i = 0; i < N; ++i) {
@@ -209,20 +239,26 @@ int oracle_adjoint(double tm1, double t0, double t1, int64_t N, int64_t M,
                 s_m1 += (long double)g[i + 1] * x[i];
             }
         }
+        s_ps += (long double)g[0] * x[0];
+        s_ch += (long double)g[N - 1] * x[N - 1];
     }
     gt[0] = (double)(-s_m1);
     gt[1] = (double)(-s_0);
     gt[2] = (double)(-s_p1);
+    gt[3] = (double)(-s_ps);
+    gt[4] = (double)(-s_ch);
     return 0;
 }
 
-/* Varlen adjoint: one (dL/dt-1, dL/dt0, dL/dt1) triple per system, gt: [S][3]. */
+/* Varlen adjoint: per system (dL/dt-1, dL/dt0, dL/dt1, dL/dpsi, dL/dchi),
+ * gt: [S][5]; psi, chi as in oracle_solve_varlen. */
 int oracle_adjoint_varlen(int64_t S, const int64_t *offsets, const double *tm1,
-                          const double *t0, const double *t1, const double *gX,
-                          const double *X, double *gF, double *gt, int nthreads)
+                          const double *t0, const double *t1, const double *psi,
+                          const double *chi, const double *gX, const double *X, double *gF,
+                          double *gt, int nthreads)
 {
     if (S < 1 || !offsets || !gX || !X || !gF || !gt) return 3;
-    int st = oracle_solve_varlen(S, offsets, t1, t0, tm1, gX, gF, 0, nthreads);
+    int st = oracle_solve_varlen(S, offsets, t1, t0, tm1, psi, chi, gX, gF, 0, nthreads);
     if (st) return st;
     for (int64_t s = 0; s < S; ++s) {
         int64_t o = offsets[s], n = offsets[s + 1] - o;
@@ -235,9 +271,11 @@ int oracle_adjoint_varlen(int64_t S, const int64_t *offsets, const double *tm1,
                 s_m1 += (long double)g[i + 1] * x[i];
             }
         }
-        gt[3 * s + 0] = (double)(-s_m1);
-        gt[3 * s + 1] = (double)(-s_0);
-        gt[3 * s + 2] = (double)(-s_p1);
+        gt[5 * s + 0] = (double)(-s_m1);
+        gt[5 * s + 1] = (double)(-s_0);
+        gt[5 * s + 2] = (double)(-s_p1);
+        gt[5 * s + 3] = (double)(-((long double)g[0] * x[0]));
+        gt[5 * s + 4] = (double)(-((long double)g[n - 1] * x[n - 1]));
     }
     return 0;
 }

@@ -21,7 +21,14 @@ oracle disagrees with what the paper or the mathematics fixes:
                        against the eigen-pair closed form;
   * pin_adjoint        gF against a dense solve with T^T, dL/dt against central
                        finite differences (step 1e-6) and the closed form at
-                       t_{+-1} = 0.
+                       t_{+-1} = 0;
+  * pin_quasi          the quasi-Toeplitz matrices of eq. (21) (t0+psi, t0+chi
+                       in the corners): dense elimination, the closed-form
+                       eigenpairs of the Neumann (psi = chi = -1, cosine
+                       vectors) and half-point Dirichlet (psi = chi = +1, sine
+                       vectors) matrices, N = 1 and 2, manufactured solutions,
+                       varlen, and the adjoint with dL/dpsi, dL/dchi against a
+                       dense transposed solve and central differences.
 """
 from __future__ import annotations
 
@@ -31,11 +38,14 @@ import mpmath
 import numpy as np
 
 
-def dense_T(n, a, b, c):
-    """Dense Toeplitz tridiagonal matrix: a below, b on, c above the diagonal."""
+def dense_T(n, a, b, c, psi=0.0, chi=0.0):
+    """Dense Toeplitz tridiagonal matrix: a below, b on, c above the diagonal;
+    psi and chi added to the first and last diagonal entry (eq. (21))."""
     T = np.diag(np.full(n, float(b)))
     if n > 1:
         T += np.diag(np.full(n - 1, float(c)), 1) + np.diag(np.full(n - 1, float(a)), -1)
+    T[0, 0] += psi
+    T[-1, -1] += chi
     return T
 
 
@@ -291,5 +301,82 @@ def pin_adjoint(orc, seed=8):
         assert _relerr(gFp[sl], ref) < 1e-13
 
 
+def pin_quasi(orc, seed=10):
+    rng = np.random.default_rng(seed)
+    # dense elimination, both corners, including N = 1 (one entry t0+psi+chi)
+    for n in (1, 2, 3, 5, 13, 40):
+        for _ in range(4):
+            a, b, c = _rand_t(rng, 1.2, 3.0)
+            psi, chi = rng.uniform(-0.5, 0.5, 2) * abs(b)
+            F = rng.standard_normal((2, n))
+            X = orc.solve(F, a, b, c, psi=psi, chi=chi)
+            ref = np.linalg.solve(dense_T(n, a, b, c, psi, chi), F.T).T
+            assert _relerr(X, ref) < 1e-13, (n, psi, chi, _relerr(X, ref))
+    # N = 2: the explicit inverse of [[b+psi, c], [a, b+chi]]
+    a, b, c, psi, chi = -0.6, 2.1, 0.8, 0.3, -0.45
+    f = np.array([0.7, -1.3])
+    d = (b + psi) * (b + chi) - a * c
+    x2 = np.array([(b + chi) * f[0] - c * f[1], -a * f[0] + (b + psi) * f[1]]) / d
+    assert _relerr(orc.solve(f, a, b, c, psi=psi, chi=chi), x2) < 1e-15
+    # closed-form eigenpairs (t0 = 2 + eps, t_{+-1} = -1)
+    n, eps = 37, 0.05
+    i = np.arange(n)
+    for psi, trig, ks in ((-1.0, np.cos, range(0, n)), (1.0, np.sin, range(1, n + 1))):
+        for k in ks:
+            v = trig(np.pi * k * (i + 0.5) / n)
+            lam = eps + 4.0 * math.sin(math.pi * k / (2 * n)) ** 2
+            x = orc.solve(v, -1.0, 2.0 + eps, -1.0, psi=psi, chi=psi)
+            assert _relerr(x, v / lam) < 1e-12, (psi, k, _relerr(x, v / lam))
+    # manufactured solution
+    a, b, c, psi, chi = -0.8, 2.6, -1.1, 0.9, -0.7
+    Xs = rng.uniform(-1, 1, (3, 500))
+    F = stencil(Xs.copy(), a, b, c)
+    F[:, 0] += psi * Xs[:, 0]
+    F[:, -1] += chi * Xs[:, -1]
+    assert _relerr(orc.solve(F, a, b, c, psi=psi, chi=chi), Xs) < 1e-13
+    # varlen with per-system corners equals one-by-one solves and dense ones
+    sizes = np.array([3, 17, 1, 40])
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    ts = [_rand_t(rng, 1.2, 3.0) for _ in sizes]
+    tm1, t0, t1 = (np.array([t[k] for t in ts]) for k in range(3))
+    ps = rng.uniform(-0.4, 0.4, len(sizes))
+    ch = rng.uniform(-0.4, 0.4, len(sizes))
+    Fp = rng.standard_normal(int(off[-1]))
+    Xp = orc.solve_varlen(Fp, off, tm1, t0, t1, psi=ps, chi=ch)
+    for s in range(len(sizes)):
+        sl = slice(off[s], off[s + 1])
+        ref = np.linalg.solve(dense_T(sizes[s], tm1[s], t0[s], t1[s], ps[s], ch[s]), Fp[sl])
+        assert _relerr(Xp[sl], ref) < 1e-13, s
+    # adjoint: gF = A^{-T} gX and (dL/dt-1, dL/dt0, dL/dt1, dL/dpsi, dL/dchi)
+    n, m = 30, 2
+    a, b, c, psi, chi = -0.7, 2.3, -0.9, 0.6, -0.4
+    F = rng.standard_normal((m, n))
+    W = rng.standard_normal((m, n))
+    X = orc.solve(F, a, b, c, psi=psi, chi=chi)
+    gF, gt = orc.adjoint(W, X, a, b, c, psi=psi, chi=chi, corners=True)
+    assert gt.shape == (5,)
+    ref_gF = np.linalg.solve(dense_T(n, a, b, c, psi, chi).T, W.T).T
+    assert _relerr(gF, ref_gF) < 1e-13
+    h = 1e-6
+
+    def loss(a_, b_, c_, p_, q_):
+        return float(np.sum(W * np.linalg.solve(dense_T(n, a_, b_, c_, p_, q_), F.T).T))
+
+    base = np.array([a, b, c, psi, chi])
+    fd = []
+    for k in range(5):
+        e = np.zeros(5)
+        e[k] = h
+        fd.append((loss(*(base + e)) - loss(*(base - e))) / (2 * h))
+    fd = np.array(fd)
+    assert np.max(np.abs(gt - fd)) < 1e-6 * max(1.0, np.max(np.abs(fd))), (gt, fd)
+    gFp, gtp = orc.adjoint_varlen(Fp, Xp, off, tm1, t0, t1, psi=ps, chi=ch, corners=True)
+    for s in range(len(sizes)):
+        sl = slice(off[s], off[s + 1])
+        g1, t1s = orc.adjoint(Fp[sl], Xp[sl], tm1[s], t0[s], t1[s], psi=ps[s], chi=ch[s],
+                              corners=True)
+        assert np.allclose(gFp[sl], g1, rtol=1e-15, atol=0) and np.allclose(gtp[s], t1s)
+
+
 ALL_PINS = [pin_dense_ge, pin_eigenpairs, pin_theorem1, pin_chebyshev, pin_manufactured,
-            pin_special, pin_long_double, pin_adjoint]
+            pin_special, pin_long_double, pin_adjoint, pin_quasi]
