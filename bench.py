@@ -12,8 +12,10 @@ path ('f64') is timed the same way beside it.
 Other workloads (`--workload`): `series` (8192 right-hand sides of N = 8192
 sharing T = tridiag{-1, 3, -1}), `sov` (2048 separation-of-variables systems,
 N_k log-uniform in [256, 65536], each with its own t_0; one step is a replay
-of the solve captured in a hipGraph) and `diff` (1024 systems of N = 16384
-with their own T; a step is the forward solve plus the adjoint backward pass).
+of the solve captured in a hipGraph), `sov_neumann` (the same batch with
+Neumann ends: quasi-Toeplitz systems with psi = chi = 1) and `diff` (1024
+systems of N = 16384 with their own T; a step is the forward solve plus the
+adjoint backward pass).
 
 Prints one JSON line.  `roofline` is for the kernel with the longest average
 duration in the headline path, from HIP events recorded on the solve stream
@@ -41,7 +43,7 @@ if ROOT not in sys.path:
 
 METRIC = "unknowns/s + HBM GB/s (% peak): FP32+refine vs FP64 solve at rel err ≤1e-12"
 HBM_PEAK_GBS = 8000.0
-WORKLOADS = ("single_large", "series", "sov", "diff")
+WORKLOADS = ("single_large", "series", "sov", "sov_neumann", "diff")
 
 
 def kernel_source_hash() -> str:
@@ -96,6 +98,13 @@ def load_workload(name: str, args):
                  desc=f"sov: S={d['S']} separation-of-variables systems, N_k log-uniform "
                       f"in [256, 65536] (sum {int(d['offsets'][-1])}), t_+-1=1, own t_0, "
                       f"F~N(0,1) seed 0, packed, solve replayed from a hipGraph")
+    elif name == "sov_neumann":
+        d = W.sov_neumann_batch(seed=0)
+        d.update(kind="varlen", units=int(d["offsets"][-1]), graph=True,
+                 desc=f"sov_neumann: S={d['S']} separation-of-variables systems with Neumann "
+                      f"ends (quasi-Toeplitz, psi=chi=1), N_k log-uniform in [256, 65536] "
+                      f"(sum {int(d['offsets'][-1])}), t_+-1=1, own t_0, F~N(0,1) seed 0, "
+                      f"packed, solve replayed from a hipGraph")
     elif name == "diff":
         d = W.diff_batch(seed=0)
         d.update(kind="varlen", units=int(d["offsets"][-1]), adjoint=True,
@@ -109,7 +118,8 @@ def load_workload(name: str, args):
 def make_plan(tdt, d, mode):
     if d["kind"] == "series":
         return tdt.Plan(d["t_m1"], d["t_0"], d["t_1"], d["N"], mode)
-    return tdt.VarlenPlan(d["offsets"], d["t_m1"], d["t_0"], d["t_1"], mode)
+    return tdt.VarlenPlan(d["offsets"], d["t_m1"], d["t_0"], d["t_1"], mode,
+                          psi=d.get("psi"), chi=d.get("chi"))
 
 
 def tile_counts(d, tile):
@@ -119,7 +129,8 @@ def tile_counts(d, tile):
         multi = d["N"] > tile
         return (d["N"] * d["M"] if multi else 0), d["N"] * d["M"]
     sizes = d["offsets"][1:] - d["offsets"][:-1]
-    return int(sizes[sizes > tile].sum()), int(sizes.sum())
+    inner = sizes - (2 if "psi" in d else 0)     # quasi-Toeplitz: tiles cover the inner rows
+    return int(sizes[inner > tile].sum()), int(sizes.sum())
 
 
 def run_mode(tdt, d, F, X, mode, steps, warmup, torch, autotune=True):
@@ -215,7 +226,8 @@ def cpu_leg(d, budget_s=12.0):
             Xo = oracle.solve(d["F"], d["t_m1"], d["t_0"], d["t_1"], nthreads=nthreads)
         else:
             Xo = oracle.solve_varlen(d["F"].reshape(-1), d["offsets"], d["t_m1"], d["t_0"],
-                                     d["t_1"], nthreads=nthreads)
+                                     d["t_1"], nthreads=nthreads, psi=d.get("psi"),
+                                     chi=d.get("chi"))
         if d.get("adjoint"):
             gFo, gto = oracle.adjoint_varlen(d["W"].reshape(-1), Xo, d["offsets"], d["t_m1"],
                                              d["t_0"], d["t_1"], nthreads=nthreads)

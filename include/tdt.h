@@ -80,6 +80,37 @@ tdt_status_t tdt_plan_varlen_create(int64_t S, const int64_t *h_offsets,
                                     const double *h_t1, tdt_dtype_t dtype,
                                     tdt_plan_t *out);
 
+/* Plan for the quasi-Toeplitz matrix of eq. (21): T with its first diagonal
+ * entry t_0 + psi and its last t_0 + chi (the form a Poisson problem with
+ * Neumann or Robin boundary rows takes, Sec. 3.2), order N >= 3.  The tiles
+ * cover the N - 2 inner rows, which are Toeplitz; the two corner rows join the
+ * interface pass across tiles as one-row segments at its two ends, so the
+ * corner terms cost O(1) per right-hand side.  Solves, the adjoint and every
+ * option work as for tdt_plan_create, with the same layouts (rows 0 .. N-1);
+ * tdt_solve_backward then writes 5 doubles per system to d_gt:
+ *   d_gt[5s+0..2] as for a Toeplitz plan (the corner rows included: row 0
+ *                 has no t_-1 term, row N-1 no t_1 term),
+ *   d_gt[5s+3]  = dL/dpsi = - gF_0 x_0,
+ *   d_gt[5s+4]  = dL/dchi = - gF_{N-1} x_{N-1}.
+ * Errors: N < 3, non-finite arguments -> TDT_ERR_INVALID_ARG; t_0 + psi = 0,
+ * t_0 + chi = 0 or a vanishing interface pivot -> TDT_ERR_SINGULAR.  The
+ * dominance ratio includes the corner rows (|t_0+psi|/|t_1|,
+ * |t_0+chi|/|t_-1|); kappa2 (tdt_last_info) is an upper bound,
+ * sqrt(kappa_1 kappa_inf) with both from strict row and column dominance
+ * (infinite without it). */
+tdt_status_t tdt_plan_quasi_create(double t_m1, double t_0, double t_1, double psi,
+                                   double chi, int64_t N, tdt_dtype_t dtype,
+                                   tdt_plan_t *out);
+
+/* Varlen plan of quasi-Toeplitz systems (eq. (21)), each with its own t's and
+ * corner terms h_psi[s], h_chi[s] (host arrays of S doubles); sizes >= 3.
+ * Layout, errors and the 5 t-gradients per system as above. */
+tdt_status_t tdt_plan_varlen_quasi_create(int64_t S, const int64_t *h_offsets,
+                                          const double *h_tm1, const double *h_t0,
+                                          const double *h_t1, const double *h_psi,
+                                          const double *h_chi, tdt_dtype_t dtype,
+                                          tdt_plan_t *out);
+
 /* Allocate the workspace for up to M_max right-hand sides now, so that later
  * solves allocate nothing and may be captured in a hipGraph.  Blocking. */
 tdt_status_t tdt_plan_reserve(tdt_plan_t plan, int64_t M_max);

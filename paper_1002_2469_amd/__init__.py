@@ -125,18 +125,32 @@ class _PlanBase:
 
 class Plan(_PlanBase):
     """Plan of one Toeplitz matrix of order N (data dtype: 'f64', 'f32' or
-    'f32_refine'; the last takes and returns float64)."""
+    'f32_refine'; the last takes and returns float64).  With psi and chi the
+    matrix is quasi-Toeplitz (eq. (21): t_0 + psi in the first diagonal
+    entry, t_0 + chi in the last; N >= 3) and backward returns 5 t-gradients
+    (dL/dt_-1, dL/dt_0, dL/dt_1, dL/dpsi, dL/dchi)."""
 
-    def __init__(self, t_m1: float, t_0: float, t_1: float, N: int, dtype: str = "f64"):
+    def __init__(self, t_m1: float, t_0: float, t_1: float, N: int, dtype: str = "f64",
+                 psi=None, chi=None):
         super().__init__()
         if dtype not in DTYPES:
             raise ValueError(f"dtype must be one of {list(DTYPES)}")
+        if (psi is None) != (chi is None):
+            raise ValueError("give both psi and chi, or neither")
         self.t = (float(t_m1), float(t_0), float(t_1))
         self.N = int(N)
         self.dtype = dtype
-        self.status = _lib.check(_lib.lib().tdt_plan_create(
-            self.t[0], self.t[1], self.t[2], self.N, DTYPES[dtype], ctypes.byref(self._h)),
-            "tdt_plan_create")
+        self.quasi = psi is not None
+        self.ngt = 5 if self.quasi else 3
+        if self.quasi:
+            self.corners = (float(psi), float(chi))
+            self.status = _lib.check(_lib.lib().tdt_plan_quasi_create(
+                self.t[0], self.t[1], self.t[2], self.corners[0], self.corners[1], self.N,
+                DTYPES[dtype], ctypes.byref(self._h)), "tdt_plan_quasi_create")
+        else:
+            self.status = _lib.check(_lib.lib().tdt_plan_create(
+                self.t[0], self.t[1], self.t[2], self.N, DTYPES[dtype], ctypes.byref(self._h)),
+                "tdt_plan_create")
 
     @property
     def dominant(self) -> bool:
@@ -169,7 +183,8 @@ class Plan(_PlanBase):
         return self._autotune(F, X, M, cache, force, stream)
 
     def backward(self, gX, X, gF=None, gt=None, stream=None):
-        """gF = T^{-T} gX and gt = (dL/dt_-1, dL/dt_0, dL/dt_1) summed over RHS."""
+        """gF = T^{-T} gX and gt = (dL/dt_-1, dL/dt_0, dL/dt_1[, dL/dpsi,
+        dL/dchi]) summed over RHS."""
         torch = _torch()
         dt = _data_dtype(self.dtype)
         M = gX.numel() // self.N
@@ -178,9 +193,9 @@ class Plan(_PlanBase):
         if gF is None:
             gF = torch.empty_like(gX)
         if gt is None:
-            gt = torch.empty(3, dtype=torch.float64, device=gX.device)
+            gt = torch.empty(self.ngt, dtype=torch.float64, device=gX.device)
         _check_tensor(gF, dt, M * self.N, "gF")
-        _check_tensor(gt, torch.float64, 3, "gt")
+        _check_tensor(gt, torch.float64, self.ngt, "gt")
         _lib.check(_lib.lib().tdt_solve_backward(
             self._h, ctypes.c_void_p(gX.data_ptr()), ctypes.c_void_p(X.data_ptr()),
             ctypes.c_void_p(gF.data_ptr()), ctypes.c_void_p(gt.data_ptr()), M,
@@ -190,24 +205,41 @@ class Plan(_PlanBase):
 
 class VarlenPlan(_PlanBase):
     """S systems of sizes offsets[s+1]-offsets[s], each with its own t's,
-    packed back to back."""
+    packed back to back.  With psi and chi (scalars or S values) every system
+    is quasi-Toeplitz (eq. (21), sizes >= 3) and backward returns 5
+    t-gradients per system."""
 
-    def __init__(self, offsets, t_m1, t_0, t_1, dtype: str = "f64"):
+    def __init__(self, offsets, t_m1, t_0, t_1, dtype: str = "f64", psi=None, chi=None):
         super().__init__()
         if dtype not in DTYPES:
             raise ValueError(f"dtype must be one of {list(DTYPES)}")
+        if (psi is None) != (chi is None):
+            raise ValueError("give both psi and chi, or neither")
         self.offsets = np.ascontiguousarray(offsets, dtype=np.int64)
         self.S = self.offsets.size - 1
-        ts = [np.ascontiguousarray(np.broadcast_to(np.asarray(t, dtype=np.float64), (self.S,)))
-              for t in (t_m1, t_0, t_1)]
+
+        def per_system(t):
+            return np.ascontiguousarray(np.broadcast_to(np.asarray(t, dtype=np.float64),
+                                                        (self.S,)))
+
+        ts = [per_system(t) for t in (t_m1, t_0, t_1)]
         self.t = ts
         self.total = int(self.offsets[-1])
         self.dtype = dtype
-        self.status = _lib.check(_lib.lib().tdt_plan_varlen_create(
-            self.S, self.offsets.ctypes.data_as(ctypes.c_void_p),
-            ts[0].ctypes.data_as(ctypes.c_void_p), ts[1].ctypes.data_as(ctypes.c_void_p),
-            ts[2].ctypes.data_as(ctypes.c_void_p), DTYPES[dtype], ctypes.byref(self._h)),
-            "tdt_plan_varlen_create")
+        self.quasi = psi is not None
+        self.ngt = 5 if self.quasi else 3
+        vp = [x.ctypes.data_as(ctypes.c_void_p) for x in ts]
+        if self.quasi:
+            self.corners = [per_system(psi), per_system(chi)]
+            cp = [x.ctypes.data_as(ctypes.c_void_p) for x in self.corners]
+            self.status = _lib.check(_lib.lib().tdt_plan_varlen_quasi_create(
+                self.S, self.offsets.ctypes.data_as(ctypes.c_void_p), vp[0], vp[1], vp[2],
+                cp[0], cp[1], DTYPES[dtype], ctypes.byref(self._h)),
+                "tdt_plan_varlen_quasi_create")
+        else:
+            self.status = _lib.check(_lib.lib().tdt_plan_varlen_create(
+                self.S, self.offsets.ctypes.data_as(ctypes.c_void_p), vp[0], vp[1], vp[2],
+                DTYPES[dtype], ctypes.byref(self._h)), "tdt_plan_varlen_create")
 
     def solve(self, F, X=None, stream=None):
         torch = _torch()
@@ -232,7 +264,8 @@ class VarlenPlan(_PlanBase):
         return self._autotune(F, X, 1, cache, force, stream)
 
     def backward(self, gX, X, gF=None, gt=None, stream=None):
-        """gF = T_s^{-T} gX per system and gt[s] = (dL/dt_-1, dL/dt_0, dL/dt_1)."""
+        """gF = T_s^{-T} gX per system and gt[s] = (dL/dt_-1, dL/dt_0,
+        dL/dt_1[, dL/dpsi, dL/dchi])."""
         torch = _torch()
         dt = _data_dtype(self.dtype)
         _check_tensor(gX, dt, self.total, "gX")
@@ -240,9 +273,9 @@ class VarlenPlan(_PlanBase):
         if gF is None:
             gF = torch.empty_like(gX)
         if gt is None:
-            gt = torch.empty((self.S, 3), dtype=torch.float64, device=gX.device)
+            gt = torch.empty((self.S, self.ngt), dtype=torch.float64, device=gX.device)
         _check_tensor(gF, dt, self.total, "gF")
-        _check_tensor(gt, torch.float64, 3 * self.S, "gt")
+        _check_tensor(gt, torch.float64, self.ngt * self.S, "gt")
         _lib.check(_lib.lib().tdt_solve_backward(
             self._h, ctypes.c_void_p(gX.data_ptr()), ctypes.c_void_p(X.data_ptr()),
             ctypes.c_void_p(gF.data_ptr()), ctypes.c_void_p(gt.data_ptr()), 1,
@@ -253,27 +286,30 @@ class VarlenPlan(_PlanBase):
 _plan_cache: dict = {}
 
 
-def _cached_plan(t_m1, t_0, t_1, N, dtype) -> Plan:
-    key = (float(t_m1), float(t_0), float(t_1), int(N), dtype)
+def _cached_plan(t_m1, t_0, t_1, N, dtype, psi=None, chi=None) -> Plan:
+    corners = None if psi is None else (float(psi), float(chi))
+    key = (float(t_m1), float(t_0), float(t_1), int(N), dtype, corners)
     p = _plan_cache.get(key)
     if p is None:
         if len(_plan_cache) > 64:
             _plan_cache.clear()
-        p = Plan(*key)
+        p = Plan(*key[:5], psi=psi, chi=chi)
         _plan_cache[key] = p
     return p
 
 
-def solve(F, t_m1: float, t_0: float, t_1: float, dtype: str = "f64"):
-    """X = T^{-1} F along the last dimension of F (cached plan per T and N)."""
-    return _cached_plan(t_m1, t_0, t_1, F.shape[-1], dtype).solve(F.contiguous())
+def solve(F, t_m1: float, t_0: float, t_1: float, dtype: str = "f64", psi=None, chi=None):
+    """X = T^{-1} F along the last dimension of F (cached plan per T and N);
+    psi/chi: quasi-Toeplitz corner terms."""
+    return _cached_plan(t_m1, t_0, t_1, F.shape[-1], dtype, psi, chi).solve(F.contiguous())
 
 
-def solve_varlen(F, offsets, t_m1, t_0, t_1, dtype: str = "f64"):
+def solve_varlen(F, offsets, t_m1, t_0, t_1, dtype: str = "f64", psi=None, chi=None):
     """X_s = T_s^{-1} F_s for packed systems s (F[offsets[s]:offsets[s+1]]),
-    each with its own t's (scalars broadcast).  Builds a plan per call: keep a
-    VarlenPlan to solve the same systems again."""
-    plan = VarlenPlan(offsets, t_m1, t_0, t_1, dtype)
+    each with its own t's (scalars broadcast; psi/chi: quasi-Toeplitz corner
+    terms).  Builds a plan per call: keep a VarlenPlan to solve the same
+    systems again."""
+    plan = VarlenPlan(offsets, t_m1, t_0, t_1, dtype, psi=psi, chi=chi)
     try:
         return plan.solve(F.contiguous())
     finally:
@@ -281,7 +317,9 @@ def solve_varlen(F, offsets, t_m1, t_0, t_1, dtype: str = "f64"):
 
 
 class TridiagToeplitzSolve:
-    """Differentiable X = T^{-1} F; t = (t_-1, t_0, t_1) as a tensor of 3.
+    """Differentiable X = T^{-1} F; t = (t_-1, t_0, t_1) as a tensor of 3, or
+    (t_-1, t_0, t_1, psi, chi) as a tensor of 5 for the quasi-Toeplitz
+    matrix of eq. (21).
 
     Backward is the hand-written adjoint kernel: gF = T^{-T} gX through the
     same dichotomy machinery, and the t-gradients reduced on the device."""
@@ -297,7 +335,9 @@ class TridiagToeplitzSolve:
                 @staticmethod
                 def forward(ctx, F, t, dtype="f64"):
                     tv = [float(v) for v in t.detach().cpu().tolist()]
-                    plan = _cached_plan(tv[0], tv[1], tv[2], F.shape[-1], dtype)
+                    if len(tv) not in (3, 5):
+                        raise ValueError("t must hold 3 (Toeplitz) or 5 (quasi-Toeplitz) values")
+                    plan = _cached_plan(*tv[:3], F.shape[-1], dtype, *tv[3:])
                     X = plan.solve(F.contiguous())
                     ctx.plan = plan
                     ctx.t_device, ctx.t_dtype = t.device, t.dtype

@@ -39,7 +39,7 @@ EXPORTS = [
     "tdt_solve_varlen", "tdt_solve_backward", "tdt_plan_destroy", "tdt_status_string",
     "tdt_last_info", "tdt_block_constants", "tdt_green_rows", "tdt_segment_merge", "tdt_plan_profile",
     "tdt_plan_profile_read", "tdt_build_info", "tdt_plan_set_option", "tdt_plan_get_option",
-    "tdt_plan_autotune",
+    "tdt_plan_autotune", "tdt_plan_quasi_create", "tdt_plan_varlen_quasi_create",
 ]
 
 # tdt_option_t
@@ -86,6 +86,8 @@ def lib():
     sig = {
         "tdt_plan_create": [d, d, d, i64, i32, pp],
         "tdt_plan_varlen_create": [i64, p, p, p, p, i32, pp],
+        "tdt_plan_quasi_create": [d, d, d, d, d, i64, i32, pp],
+        "tdt_plan_varlen_quasi_create": [i64, p, p, p, p, p, p, i32, pp],
         "tdt_plan_reserve": [p, i64],
         "tdt_solve": [p, p, p, i64, p],
         "tdt_solve_varlen": [p, p, p, p],

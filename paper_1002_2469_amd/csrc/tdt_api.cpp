@@ -35,11 +35,13 @@ struct tdt_plan_s {
   int64_t L = (int64_t)tdt::kShapes[0].B * tdt::kShapes[0].NT;
   // the creation arguments (a change of shape rebuilds the plan from them)
   std::vector<double> in_tm1, in_t0, in_t1;
+  std::vector<double> in_psi, in_chi;   // quasi-Toeplitz corner terms (quasi plans)
   std::vector<int64_t> in_sizes, in_offs;
+  bool quasi = false;     // every system is quasi-Toeplitz (eq. (21))
   int64_t reserved_M = 0;
   bool varlen = false;
   tdt_dtype_t dtype = TDT_F64;
-  int64_t N = 0;          // series: order of the system
+  int64_t N = 0;          // series: order of the system (with its corner rows)
   int64_t S = 1;          // number of systems
   int64_t total = 0;      // varlen: packed length
   std::vector<SysDesc> hsys[2];   // [0]: T, [1]: T^T (adjoint)
@@ -204,6 +206,34 @@ double dominance_ratio(double a, double b, double c) {
   return off == 0.0 ? std::numeric_limits<double>::infinity() : std::fabs(b) / off;
 }
 
+// Row dominance of a quasi-Toeplitz matrix: the inner rows and the two
+// corner rows (t0+psi next to t_1, t0+chi next to t_-1).
+double quasi_dominance(double a, double b, double c, double psi, double chi) {
+  const double inf = std::numeric_limits<double>::infinity();
+  auto ratio = [&](double d, double off) { return off == 0.0 ? inf : std::fabs(d) / off; };
+  return std::min(dominance_ratio(a, b, c),
+                  std::min(ratio(b + psi, std::fabs(c)), ratio(b + chi, std::fabs(a))));
+}
+
+// Upper bound of the 2-norm condition number of a quasi-Toeplitz matrix of
+// order n >= 3: kappa_2 <= sqrt(kappa_1 kappa_inf), each bounded by the norm
+// times the inverse-norm bound of a strictly dominant matrix (the smallest
+// diagonal excess over its row's, resp. column's, off-diagonal sum);
+// infinite without strict row and column dominance.
+double quasi_condition_bound(double a, double b, double c, double psi, double chi) {
+  const double inf = std::numeric_limits<double>::infinity();
+  const double A = std::fabs(a), C = std::fabs(c), d = std::fabs(b);
+  const double d0 = std::fabs(b + psi), d1 = std::fabs(b + chi);
+  // rows: first (d0, C), inner (d, A + C), last (d1, A); columns: first
+  // (d0, A), inner (d, A + C), last (d1, C)
+  const double rex = std::min(d0 - C, std::min(d - A - C, d1 - A));
+  const double cex = std::min(d0 - A, std::min(d - A - C, d1 - C));
+  if (!(rex > 0.0) || !(cex > 0.0)) return inf;
+  const double rnorm = std::max(d0 + C, std::max(d + A + C, d1 + A));
+  const double cnorm = std::max(d0 + A, std::max(d + A + C, d1 + C));
+  return std::sqrt((rnorm / rex) * (cnorm / cex));
+}
+
 // 2-norm condition number from the closed-form spectrum when t_1 t_-1 > 0
 // (T is similar to a symmetric matrix), else the infinity-norm bound.
 double condition_number(double a, double b, double c, int64_t n) {
@@ -228,8 +258,8 @@ double condition_number(double a, double b, double c, int64_t n) {
 }
 
 // Fill the descriptor and the block vectors of one system.
-tdt_status_t build_system(double a, double b, double c, int64_t n, int kB, int kNT, SysDesc& D,
-                          double* v64, float* v32, double* t64, float* t32) {
+tdt_status_t build_system(double a, double b, double c, int64_t n, bool quasi, int kB, int kNT,
+                          SysDesc& D, double* v64, float* v32, double* t64, float* t32) {
   const int64_t kTile = (int64_t)kB * kNT;
   ld iu[tdt::kMaxB], cp[tdt::kMaxB], phi[tdt::kMaxB], chi[tdt::kMaxB];
   if (!block_vectors(a, b, c, kB, iu, cp, phi, chi)) return TDT_ERR_SINGULAR;
@@ -274,31 +304,58 @@ tdt_status_t build_system(double a, double b, double c, int64_t n, int kB, int k
   const int bt = (int)((n - 1) % kB) + 1;
   if (bt == kB) {
     D.tail_pf = D.blk[0];
+    D.tail_pl = D.blk[1];
+    D.tail_cf = D.blk[2];
   } else {
     ld e[4];
     if (!segment_ends(a, b, c, bt, e)) return TDT_ERR_SINGULAR;
     D.tail_pf = (double)e[0];
+    D.tail_pl = (double)e[1];
+    D.tail_cf = (double)e[2];
     for (int m = 0; m < kNT; ++m)   // the last block may sit at any position
       if (!(std::fabs(1.0 - D.tail_pf * t64[tdt::kTabBeta * kNT + m]) > 1e-13))
         return TDT_ERR_SINGULAR;
   }
-  if (D.ntiles > 1) {
+  // end values of a full tile and of the last tile (its real length), which
+  // the interface pass needs when the system has several tiles or corner rows
+  for (int k = 0; k < 4; ++k) D.tileK[k] = D.ltileK[k] = 0.0;
+  if (D.ntiles > 1 || quasi) {
     ld e[4];
-    if (!segment_ends(a, b, c, kTile, e)) return TDT_ERR_SINGULAR;
-    for (int k = 0; k < 4; ++k) D.tileK[k] = (double)e[k];
     const int64_t lt = n - (int64_t)(D.ntiles - 1) * kTile;
-    if (lt == kTile) {
+    if (D.ntiles > 1) {
+      if (!segment_ends(a, b, c, kTile, e)) return TDT_ERR_SINGULAR;
+      for (int k = 0; k < 4; ++k) D.tileK[k] = (double)e[k];
+    }
+    if (lt == kTile && D.ntiles > 1) {
       for (int k = 0; k < 4; ++k) D.ltileK[k] = D.tileK[k];
     } else {
       if (!segment_ends(a, b, c, lt, e)) return TDT_ERR_SINGULAR;
-      D.ltileK[0] = (double)e[0];
-      D.ltileK[1] = D.ltileK[2] = D.ltileK[3] = 0.0;
+      for (int k = 0; k < 4; ++k) D.ltileK[k] = (double)e[k];
     }
-  } else {
-    for (int k = 0; k < 4; ++k) D.tileK[k] = D.ltileK[k] = 0.0;
   }
   return TDT_OK;
 }
+
+// Corner constants of a quasi-Toeplitz system (first diagonal entry t0+psi,
+// last t0+chi; a, c the sub- and super-diagonal of the matrix being solved):
+// each corner row alone, and its response to the unknown next to it.
+tdt_status_t corner_constants(double a, double b, double c, double psi, double chi, SysDesc& D) {
+  const ld d0 = (ld)b + (ld)psi, d1 = (ld)b + (ld)chi;
+  if (d0 == 0.0L || d1 == 0.0L) return TDT_ERR_SINGULAR;
+  D.quasi = 1;
+  D.qc[0] = (double)(1.0L / d0);
+  D.qc[1] = (double)(-(ld)c / d0);
+  D.qc[2] = (double)(1.0L / d1);
+  D.qc[3] = (double)(-(ld)a / d1);
+  D.qc[4] = D.qc[5] = 0.0;   // set with the interface table
+  for (int k = 0; k < 4; ++k)
+    if (!std::isfinite(D.qc[k])) return TDT_ERR_SINGULAR;
+  return TDT_OK;
+}
+
+// A system goes through the interface pass when it has several tiles or
+// corner rows.
+bool needs_interface(const SysDesc& D) { return D.ntiles > 1 || D.quasi != 0; }
 
 bool finite3(double a, double b, double c) {
   return std::isfinite(a) && std::isfinite(b) && std::isfinite(c);
@@ -343,7 +400,7 @@ tdt_status_t ensure_workspace(tdt_plan_s* p, int64_t slots, int64_t fslots, hipS
   if (hipMalloc(&p->summ, (size_t)ns * 2 * sizeof(double)) != hipSuccess ||
       hipMalloc(&p->ghost, (size_t)ns * 2 * sizeof(double)) != hipSuccess ||
       hipMalloc(&p->gscr, (size_t)ns * 3 * sizeof(double)) != hipSuccess ||
-      hipMalloc(&p->gpart, (size_t)nf * 3 * sizeof(double)) != hipSuccess) {
+      hipMalloc(&p->gpart, (size_t)nf * tdt::kGradN * sizeof(double)) != hipSuccess) {
     free_workspace(p);
     return TDT_ERR_OOM;
   }
@@ -398,16 +455,16 @@ tdt_status_t build_varlen_lists(tdt_plan_s* p) {
       whole_sys.push_back((int)s);
     } else {
       for (int t = 0; t < nt; ++t) p1.push_back(make_int2((int)s, t));
-      if (nt > 1) grid.push_back((int)s);
+      if (needs_interface(p->hsys[0][s])) grid.push_back((int)s);
     }
   }
-  // one-tile systems outside the whole-system list: no first pass
+  // systems outside the whole-system list without an interface pass (one
+  // tile, no corner rows): no first pass
   std::vector<int2> single;
+  auto alone = [&](const int2& it) { return !needs_interface(p->hsys[0][it.x]); };
   for (const int2& it : p1)
-    if (p->hsys[0][it.x].ntiles == 1) single.push_back(it);
-  p1.erase(std::remove_if(p1.begin(), p1.end(),
-                          [&](const int2& it) { return p->hsys[0][it.x].ntiles == 1; }),
-           p1.end());
+    if (alone(it)) single.push_back(it);
+  p1.erase(std::remove_if(p1.begin(), p1.end(), alone), p1.end());
   fin.assign(p1.rbegin(), p1.rend());
   fin.insert(fin.end(), single.begin(), single.end());
   // Whole systems over the resident workgroups, longest processing time
@@ -418,7 +475,8 @@ tdt_status_t build_varlen_lists(tdt_plan_s* p) {
   if (!whole_sys.empty()) {
     const int64_t G = std::min<int64_t>(
         (int64_t)whole_sys.size(),
-        std::max(1, tdt::sys_wg_capacity(p->shape, (int)p->dtype, p->wg_per_cu)));
+        std::max(1, tdt::sys_wg_capacity(p->shape, (int)p->dtype, p->wg_per_cu,
+                                         p->quasi ? 1 : 0)));
     std::vector<std::vector<int>> lists((size_t)G);
     typedef std::pair<int64_t, int64_t> Load;   // (cost so far, list)
     std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
@@ -428,7 +486,7 @@ tdt_status_t build_varlen_lists(tdt_plan_s* p) {
       Load l = heap.top();
       heap.pop();
       lists[(size_t)l.second].push_back(s);
-      l.first += nt > 1 ? 2 * nt : 1;
+      l.first += needs_interface(p->hsys[0][s]) ? 2 * nt : 1;
       heap.push(l);
     }
     bins.push_back(0);
@@ -457,11 +515,14 @@ tdt_status_t build_varlen_lists(tdt_plan_s* p) {
   return st;
 }
 
-// Build both descriptor sets (T and T^T) and upload everything.
+// Build both descriptor sets (T and T^T) and upload everything.  sizes and
+// offs are the systems' orders and first rows; the tiles of a quasi-Toeplitz
+// system cover its N - 2 inner rows.
 tdt_status_t finish_plan(tdt_plan_s* p, const std::vector<double>& tm1,
                          const std::vector<double>& t0, const std::vector<double>& t1,
                          const std::vector<int64_t>& sizes, const std::vector<int64_t>& offs) {
   const int64_t S = (int64_t)sizes.size();
+  const int64_t cut = p->quasi ? 2 : 0;
   double dom = std::numeric_limits<double>::infinity(), kap = 0.0;
   for (int dir = 0; dir < 2; ++dir) {
     const int kB = p->B, kNT = p->NT;
@@ -476,27 +537,39 @@ tdt_status_t finish_plan(tdt_plan_s* p, const std::vector<double>& tm1,
       const double c = dir == 0 ? t1[s] : tm1[s];
       SysDesc& D = p->hsys[dir][s];
       std::memset(&D, 0, sizeof(D));
-      tdt_status_t st = build_system(a, t0[s], c, sizes[s], kB, kNT, D,
+      tdt_status_t st = build_system(a, t0[s], c, sizes[s] - cut, p->quasi, kB, kNT, D,
                                      v64.data() + (size_t)s * tdt::kVecN * kB,
                                      v32.data() + (size_t)s * tdt::kVecN * kB,
                                      t64.data() + (size_t)s * tdt::kTabN * kNT,
                                      t32.data() + (size_t)s * tdt::kTabN * kNT);
       if (st != TDT_OK) return st;
-      D.off = offs[s];
+      if (p->quasi) {
+        st = corner_constants(a, t0[s], c, p->in_psi[s], p->in_chi[s], D);
+        if (st != TDT_OK) return st;
+      }
+      D.off = offs[s] + cut / 2;
+      D.stride = sizes[s];
       D.cidx = (int32_t)s;
       if (dir == 0) {
-        dom = std::min(dom, dominance_ratio(tm1[s], t0[s], t1[s]));
-        kap = std::max(kap, condition_number(tm1[s], t0[s], t1[s], sizes[s]));
+        if (p->quasi) {
+          dom = std::min(dom, quasi_dominance(tm1[s], t0[s], t1[s], p->in_psi[s], p->in_chi[s]));
+          kap = std::max(kap, quasi_condition_bound(tm1[s], t0[s], t1[s], p->in_psi[s],
+                                                    p->in_chi[s]));
+        } else {
+          dom = std::min(dom, dominance_ratio(tm1[s], t0[s], t1[s]));
+          kap = std::max(kap, condition_number(tm1[s], t0[s], t1[s], sizes[s]));
+        }
       }
     }
-    // varlen bookkeeping: tile slots for multi-tile systems, partial-sum slots
+    // varlen bookkeeping: adjoint partial-sum slots, one per tile and one
+    // per corner row
     int64_t fs = 0;
     for (int64_t s = 0; s < S; ++s) {
       p->hsys[dir][s].fslot0 = (int32_t)fs;
-      fs += p->hsys[dir][s].ntiles;
+      fs += p->hsys[dir][s].ntiles + (p->quasi ? 2 : 0);
     }
     p->vfslots = fs;
-    if (!p->varlen && p->hsys[dir][0].ntiles > 1) {
+    if (!p->varlen && needs_interface(p->hsys[dir][0])) {
       std::vector<double> g(2 * (size_t)kTile);
       const double a = dir == 0 ? tm1[0] : t1[0], c = dir == 0 ? t1[0] : tm1[0];
       if (!green_rows(a, t0[0], c, kTile, g.data(), g.data() + kTile)) return TDT_ERR_SINGULAR;
@@ -534,7 +607,7 @@ tdt_status_t finish_plan(tdt_plan_s* p, const std::vector<double>& tm1,
                      [&](int64_t x, int64_t y) { return sizes[x] > sizes[y]; });
     int64_t slot = 0;
     for (int64_t s : p->order) {
-      if (p->hsys[0][s].ntiles > 1) {
+      if (needs_interface(p->hsys[0][s])) {
         for (int dir = 0; dir < 2; ++dir) p->hsys[dir][s].slot0 = (int32_t)slot;
         slot += p->hsys[0][s].tslots;
       }
@@ -544,17 +617,19 @@ tdt_status_t finish_plan(tdt_plan_s* p, const std::vector<double>& tm1,
     if (st != TDT_OK) return st;
   }
   // interface pass across tiles: beta_{t-1} and 1/(1 - Pf_t beta_{t-1}) for
-  // every tile position of every multi-tile system (a series indexes by tile,
-  // a varlen plan by workspace slot), in long double
+  // every tile position of every system with an interface pass (a series
+  // indexes by tile, a varlen plan by workspace slot), in long double.  A
+  // quasi-Toeplitz system starts from its first corner row (beta_{-1} is that
+  // row's response to the unknown right of it) and ends with its last.
   p->ttab_n = p->varlen ? std::max<int64_t>(p->vslots, 1)
                         : std::max<int64_t>(p->hsys[0][0].tslots, 1);
   for (int dir = 0; dir < 2; ++dir) {
     std::vector<double> tt(2 * (size_t)p->ttab_n, 0.0);
     for (int64_t s = 0; s < S; ++s) {
-      const SysDesc& D = p->hsys[dir][s];
-      if (D.ntiles < 2) continue;
+      SysDesc& D = p->hsys[dir][s];
+      if (!needs_interface(D)) continue;
       const int64_t base = p->varlen ? D.slot0 : 0;
-      ld beta = 0.0L;
+      ld beta = D.quasi ? (ld)D.qc[1] : 0.0L;
       for (int t = 0; t < D.ntiles; ++t) {
         const double* K = t + 1 < D.ntiles ? D.tileK : D.ltileK;
         const ld den = 1.0L - (ld)K[0] * beta;
@@ -564,6 +639,12 @@ tdt_status_t finish_plan(tdt_plan_s* p, const std::vector<double>& tm1,
         tt[base + pos] = (double)beta;
         tt[p->ttab_n + base + pos] = (double)iD;
         beta = (ld)K[3] + (ld)K[1] * beta * (ld)K[2] * iD;
+      }
+      if (D.quasi) {
+        const ld den = 1.0L - (ld)D.qc[3] * beta;
+        if (!(std::fabs((double)den) > 1e-13)) return TDT_ERR_SINGULAR;
+        D.qc[4] = (double)beta;
+        D.qc[5] = (double)(1.0L / den);
       }
     }
     tdt_status_t st = dev_upload(&p->dttab[dir], tt.data(), tt.size());
@@ -596,6 +677,9 @@ tdt_status_t rebuild_plan(tdt_plan_s* p, int shape) {
   q->in_tm1 = p->in_tm1;
   q->in_t0 = p->in_t0;
   q->in_t1 = p->in_t1;
+  q->in_psi = p->in_psi;
+  q->in_chi = p->in_chi;
+  q->quasi = p->quasi;
   q->in_sizes = p->in_sizes;
   q->in_offs = p->in_offs;
   q->varlen = p->varlen;
@@ -626,6 +710,12 @@ bool overlaps(const void* x, size_t nx, const void* y, size_t ny) {
 
 size_t elem_size(tdt_dtype_t d) { return d == TDT_F32 ? sizeof(float) : sizeof(double); }
 
+// Adjoint partial-sum slots of a series of M right-hand sides: one per tile,
+// then two per right-hand side for the corner rows of a quasi-Toeplitz plan.
+int64_t series_fslots(const tdt_plan_s* p, int64_t M) {
+  return M * p->hsys[0][0].ntiles + (p->quasi ? 2 * M : 0);
+}
+
 tdt_status_t run(tdt_plan_s* p, int dir, const void* F, void* X, const void* Xfwd, int64_t M,
                  hipStream_t st) {
   tdt::LaunchSet L{};
@@ -639,6 +729,7 @@ tdt_status_t run(tdt_plan_s* p, int dir, const void* F, void* X, const void* Xfw
   L.refine_tol = p->refine_tol;
   L.wg_per_cu = p->wg_per_cu;
   L.shape = p->shape;
+  L.quasi = p->quasi ? 1 : 0;
   L.ttab = p->dttab[dir];
   L.ttab_n = p->ttab_n;
   L.max_ntiles = 1;
@@ -660,8 +751,11 @@ tdt_status_t run(tdt_plan_s* p, int dir, const void* F, void* X, const void* Xfw
     L.n_sys = p->n_whole;
     slots = p->vslots;
     fslots = Xfwd ? p->vfslots : 0;
+    L.corner0 = 0;
   } else {
-    const int64_t nt = p->hsys[0][0].ntiles;
+    const SysDesc& D0 = p->hsys[0][0];
+    const int64_t nt = D0.ntiles;
+    const bool itf = needs_interface(D0);
     L.p1_items = nullptr;
     L.fin_items = nullptr;
     L.grid_items = nullptr;
@@ -670,14 +764,15 @@ tdt_status_t run(tdt_plan_s* p, int dir, const void* F, void* X, const void* Xfw
     L.n_bins = 0;
     L.n_sys = 0;
     L.green = p->dgreen[dir];
-    L.nfull = (int)(p->N % p->L == 0 ? nt : nt - 1);
-    L.n_beta = nt > 1 ? M * L.nfull : 0;
-    L.n_last = (nt > 1 && p->N % p->L != 0) ? M : 0;
-    L.n_p1 = nt > 1 ? M * nt : 0;
-    L.n_grid = nt > 1 ? M : 0;
+    L.nfull = (int)(D0.n % p->L == 0 ? nt : nt - 1);
+    L.n_beta = itf ? M * L.nfull : 0;
+    L.n_last = (itf && D0.n % p->L != 0) ? M : 0;
+    L.n_p1 = itf ? M * nt : 0;
+    L.n_grid = itf ? M : 0;
     L.n_fin = M * nt;
-    slots = nt > 1 ? M * p->hsys[0][0].tslots : 0;
-    fslots = Xfwd ? M * nt : 0;
+    slots = itf ? M * D0.tslots : 0;
+    fslots = Xfwd ? series_fslots(p, M) : 0;
+    L.corner0 = M * nt;
   }
   if (L.n_fin > 0x7fffffffLL) return TDT_ERR_INVALID_ARG;
   tdt_status_t s = ensure_workspace(p, slots, fslots, st);
@@ -735,15 +830,18 @@ std::string key_of(const tdt_plan_s* p, int64_t M) {
   const size_t colon = arch.find(':');
   if (colon != std::string::npos) arch.resize(colon);
   const char* dt = p->dtype == TDT_F64 ? "f64" : (p->dtype == TDT_F32 ? "f32" : "f32_refine");
+  const char* kind = p->quasi ? "q" : "";
   char buf[256];
   if (p->varlen) {
     int maxt = 1;
     for (const SysDesc& D : p->hsys[0]) maxt = std::max(maxt, (int)D.ntiles);
-    std::snprintf(buf, sizeof(buf), "%s|cu%d|varlen|%s|S%lld|U%lld|P%lld", arch.c_str(), cus, dt,
+    std::snprintf(buf, sizeof(buf), "%s|cu%d|varlen%s|%s|S%lld|U%lld|P%lld", arch.c_str(), cus,
+                  kind, dt,
                   (long long)pow2_ceil(p->S), (long long)pow2_ceil(p->total),
                   (long long)pow2_ceil(maxt));
   } else {
-    std::snprintf(buf, sizeof(buf), "%s|cu%d|series|%s|N%lld|M%lld", arch.c_str(), cus, dt,
+    std::snprintf(buf, sizeof(buf), "%s|cu%d|series%s|%s|N%lld|M%lld", arch.c_str(), cus, kind,
+                  dt,
                   (long long)pow2_ceil(p->N), (long long)pow2_ceil(M));
   }
   return buf;
@@ -830,6 +928,89 @@ tdt_status_t apply(tdt_plan_s* p, const Choice& c) {
 
 }  // namespace tune
 
+namespace {
+
+bool valid_dtype(tdt_dtype_t d) { return d == TDT_F64 || d == TDT_F32 || d == TDT_F32_REFINE; }
+
+// One system (or a series sharing it); psi/chi non-null: quasi-Toeplitz.
+tdt_status_t create_series(double t_m1, double t_0, double t_1, const double* psi,
+                           const double* chi, int64_t N, tdt_dtype_t dtype, tdt_plan_t* out) {
+  if (!out) return TDT_ERR_INVALID_ARG;
+  *out = nullptr;
+  const bool quasi = psi != nullptr;
+  if (N < (quasi ? 3 : 1) || N > ((int64_t)1 << 40) || !finite3(t_m1, t_0, t_1) ||
+      !valid_dtype(dtype) || (quasi && !(std::isfinite(*psi) && std::isfinite(*chi))))
+    return TDT_ERR_INVALID_ARG;
+  tdt_plan_s* p = new (std::nothrow) tdt_plan_s();
+  if (!p) return TDT_ERR_OOM;
+  p->dtype = dtype;
+  p->N = N;
+  p->S = 1;
+  p->in_tm1 = {t_m1};
+  p->in_t0 = {t_0};
+  p->in_t1 = {t_1};
+  p->in_sizes = {N};
+  p->in_offs = {0};
+  if (quasi) {
+    p->quasi = true;
+    p->in_psi = {*psi};
+    p->in_chi = {*chi};
+  }
+  tdt_status_t st = finish_plan(p, p->in_tm1, p->in_t0, p->in_t1, p->in_sizes, p->in_offs);
+  if (st < 0) {
+    destroy(p);
+    return st;
+  }
+  *out = p;
+  return st;
+}
+
+// Packed systems of their own sizes; h_psi/h_chi non-null: quasi-Toeplitz.
+tdt_status_t create_varlen(int64_t S, const int64_t* h_offsets, const double* h_tm1,
+                           const double* h_t0, const double* h_t1, const double* h_psi,
+                           const double* h_chi, tdt_dtype_t dtype, tdt_plan_t* out) {
+  if (!out) return TDT_ERR_INVALID_ARG;
+  *out = nullptr;
+  const bool quasi = h_psi != nullptr;
+  if (S < 1 || S > 0x7fffffffLL || !h_offsets || !h_tm1 || !h_t0 || !h_t1 ||
+      !valid_dtype(dtype) || h_offsets[0] != 0)
+    return TDT_ERR_INVALID_ARG;
+  std::vector<int64_t> sizes((size_t)S), offs((size_t)S);
+  std::vector<double> tm1(h_tm1, h_tm1 + S), t0(h_t0, h_t0 + S), t1(h_t1, h_t1 + S);
+  for (int64_t s = 0; s < S; ++s) {
+    sizes[s] = h_offsets[s + 1] - h_offsets[s];
+    offs[s] = h_offsets[s];
+    if (sizes[s] < (quasi ? 3 : 1) || !finite3(tm1[s], t0[s], t1[s]) ||
+        (quasi && !(std::isfinite(h_psi[s]) && std::isfinite(h_chi[s]))))
+      return TDT_ERR_INVALID_ARG;
+  }
+  tdt_plan_s* p = new (std::nothrow) tdt_plan_s();
+  if (!p) return TDT_ERR_OOM;
+  p->varlen = true;
+  p->dtype = dtype;
+  p->S = S;
+  p->total = h_offsets[S];
+  p->in_tm1 = tm1;
+  p->in_t0 = t0;
+  p->in_t1 = t1;
+  p->in_sizes = sizes;
+  p->in_offs = offs;
+  if (quasi) {
+    p->quasi = true;
+    p->in_psi.assign(h_psi, h_psi + S);
+    p->in_chi.assign(h_chi, h_chi + S);
+  }
+  tdt_status_t st = finish_plan(p, tm1, t0, t1, sizes, offs);
+  if (st < 0) {
+    destroy(p);
+    return st;
+  }
+  *out = p;
+  return st;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* tdt_status_string(tdt_status_t s) {
@@ -848,63 +1029,30 @@ const char* tdt_status_string(tdt_status_t s) {
 
 tdt_status_t tdt_plan_create(double t_m1, double t_0, double t_1, int64_t N, tdt_dtype_t dtype,
                              tdt_plan_t* out) {
-  if (!out) return TDT_ERR_INVALID_ARG;
-  *out = nullptr;
-  if (N < 1 || N > ((int64_t)1 << 40) || !finite3(t_m1, t_0, t_1) ||
-      (dtype != TDT_F64 && dtype != TDT_F32 && dtype != TDT_F32_REFINE))
-    return TDT_ERR_INVALID_ARG;
-  tdt_plan_s* p = new (std::nothrow) tdt_plan_s();
-  if (!p) return TDT_ERR_OOM;
-  p->dtype = dtype;
-  p->N = N;
-  p->S = 1;
-  p->in_tm1 = {t_m1};
-  p->in_t0 = {t_0};
-  p->in_t1 = {t_1};
-  p->in_sizes = {N};
-  p->in_offs = {0};
-  tdt_status_t st = finish_plan(p, p->in_tm1, p->in_t0, p->in_t1, p->in_sizes, p->in_offs);
-  if (st < 0) {
-    destroy(p);
-    return st;
-  }
-  *out = p;
-  return st;
+  return create_series(t_m1, t_0, t_1, nullptr, nullptr, N, dtype, out);
+}
+
+tdt_status_t tdt_plan_quasi_create(double t_m1, double t_0, double t_1, double psi, double chi,
+                                   int64_t N, tdt_dtype_t dtype, tdt_plan_t* out) {
+  return create_series(t_m1, t_0, t_1, &psi, &chi, N, dtype, out);
 }
 
 tdt_status_t tdt_plan_varlen_create(int64_t S, const int64_t* h_offsets, const double* h_tm1,
                                     const double* h_t0, const double* h_t1, tdt_dtype_t dtype,
                                     tdt_plan_t* out) {
-  if (!out) return TDT_ERR_INVALID_ARG;
-  *out = nullptr;
-  if (S < 1 || S > 0x7fffffffLL || !h_offsets || !h_tm1 || !h_t0 || !h_t1 ||
-      (dtype != TDT_F64 && dtype != TDT_F32 && dtype != TDT_F32_REFINE) || h_offsets[0] != 0)
+  return create_varlen(S, h_offsets, h_tm1, h_t0, h_t1, nullptr, nullptr, dtype, out);
+}
+
+tdt_status_t tdt_plan_varlen_quasi_create(int64_t S, const int64_t* h_offsets,
+                                          const double* h_tm1, const double* h_t0,
+                                          const double* h_t1, const double* h_psi,
+                                          const double* h_chi, tdt_dtype_t dtype,
+                                          tdt_plan_t* out) {
+  if (!h_psi || !h_chi) {
+    if (out) *out = nullptr;
     return TDT_ERR_INVALID_ARG;
-  std::vector<int64_t> sizes((size_t)S), offs((size_t)S);
-  std::vector<double> tm1(h_tm1, h_tm1 + S), t0(h_t0, h_t0 + S), t1(h_t1, h_t1 + S);
-  for (int64_t s = 0; s < S; ++s) {
-    sizes[s] = h_offsets[s + 1] - h_offsets[s];
-    offs[s] = h_offsets[s];
-    if (sizes[s] < 1 || !finite3(tm1[s], t0[s], t1[s])) return TDT_ERR_INVALID_ARG;
   }
-  tdt_plan_s* p = new (std::nothrow) tdt_plan_s();
-  if (!p) return TDT_ERR_OOM;
-  p->varlen = true;
-  p->dtype = dtype;
-  p->S = S;
-  p->total = h_offsets[S];
-  p->in_tm1 = tm1;
-  p->in_t0 = t0;
-  p->in_t1 = t1;
-  p->in_sizes = sizes;
-  p->in_offs = offs;
-  tdt_status_t st = finish_plan(p, tm1, t0, t1, sizes, offs);
-  if (st < 0) {
-    destroy(p);
-    return st;
-  }
-  *out = p;
-  return st;
+  return create_varlen(S, h_offsets, h_tm1, h_t0, h_t1, h_psi, h_chi, dtype, out);
 }
 
 tdt_status_t tdt_plan_reserve(tdt_plan_t p, int64_t M_max) {
@@ -915,9 +1063,8 @@ tdt_status_t tdt_plan_reserve(tdt_plan_t p, int64_t M_max) {
     slots = p->vslots;
     fslots = p->vfslots;
   } else {
-    const int64_t nt = p->hsys[0][0].ntiles;
-    slots = nt > 1 ? M_max * p->hsys[0][0].tslots : 0;
-    fslots = M_max * nt;
+    slots = needs_interface(p->hsys[0][0]) ? M_max * p->hsys[0][0].tslots : 0;
+    fslots = series_fslots(p, M_max);
   }
   return ensure_workspace(p, slots, fslots, nullptr);
 }
@@ -947,9 +1094,9 @@ tdt_status_t tdt_solve_backward(tdt_plan_t p, const void* gX, const void* X, voi
   tdt_status_t st = run(p, 1, gX, gF, X, M, stream);
   if (st != TDT_OK) return st;
   if (d_gt) {
-    const int64_t nparts = p->varlen ? p->vfslots : M * p->hsys[0][0].ntiles;
-    if (tdt::launch_gt_reduce(p->gpart, p->dsys[1], p->S, nparts, p->varlen ? 1 : 0, d_gt,
-                              stream) != hipSuccess)
+    const int64_t nparts = p->varlen ? p->vfslots : series_fslots(p, M);
+    if (tdt::launch_gt_reduce(p->gpart, p->dsys[1], p->S, nparts, p->varlen ? 1 : 0,
+                              p->quasi ? tdt::kGradN : 3, d_gt, stream) != hipSuccess)
       return TDT_ERR_HIP;
   }
   return TDT_OK;

@@ -39,8 +39,7 @@ struct SysDesc {
   double tail_pf;        // phi_first of the last block of the system (length (n-1)%B+1)
   double blk[4];         // end values of a full block (length B)
   double tileK[4];       // end values of a full tile (length L)
-  double ltileK[4];      // last tile, padded form: full-tile values if full,
-                         // else (phi_first of its real length, 0, 0, 0)
+  double ltileK[4];      // end values of the last tile (its real length)
   // Workspace slots of a multi-tile system are "run-interleaved" for the
   // interface pass, whose thread j walks tiles j*tr .. j*tr+tr-1: tile t
   // lives at slot (t % tr) * tq + t / tr, so that the r-th access of
@@ -48,7 +47,19 @@ struct SysDesc {
   int32_t tr;            // tiles per thread of the interface pass
   int32_t tq;            // threads of the interface pass in use, ceil(ntiles / tr)
   int32_t tslots;        // slots per right-hand side (tq * tr)
-  int32_t pad1;
+  // Quasi-Toeplitz systems (t0+psi and t0+chi in the first and last diagonal
+  // entry): the tiles cover the n = N - 2 inner rows, which start one row
+  // after the system's first row; the two corner rows are one-row segments
+  // at both ends of the interface pass.
+  int32_t quasi;         // 1 for a quasi-Toeplitz system
+  int64_t stride;        // rows between right-hand sides of a series (N)
+  double tail_pl;        // phi_last and chi_first of the system's last block
+  double tail_cf;        //   (tile summaries of quasi-Toeplitz systems)
+  // corner constants: [0] 1/(t0+psi); [1] -t1/(t0+psi), the first corner's
+  // response to a unit value right of it (and its beta); [2] 1/(t0+chi);
+  // [3] -t_-1/(t0+chi), the last corner's response to a unit value left of
+  // it; [4] beta of the last inner tile; [5] 1/(1 - [3] [4])
+  double qc[6];
 };
 
 // Slot of tile t of a system: a varlen plan adds the system's slot0; a
@@ -97,6 +108,8 @@ struct LaunchSet {
   double* ghost;
   double* gscr;
   double* gpart;
+  int64_t corner0;        // series, quasi-Toeplitz: first corner t-gradient slot
+  int quasi;              // the plan's systems are quasi-Toeplitz
   int* iters;
   int max_iter;
   double refine_tol;
@@ -110,8 +123,12 @@ hipError_t launch_solve(int dtype, bool bwd, const LaunchSet& L, const void* F, 
                         const void* Xfwd, hipStream_t st);
 // Workgroups of the whole-system kernel that are resident at once (the
 // plan spreads its systems over this many lists).
-int sys_wg_capacity(int shape, int dtype, int wg_per_cu);
+int sys_wg_capacity(int shape, int dtype, int wg_per_cu, int quasi);
+// Partial t-gradient sums per tile of the adjoint: (t_-1, t_0, t_1, psi, chi).
+constexpr int kGradN = 5;
+// Sums the partials per system (varlen) or over all (series) into gt,
+// ncomp (3, or 5 for quasi-Toeplitz plans) values per system.
 hipError_t launch_gt_reduce(const double* gpart, const SysDesc* sys, int64_t nsys,
-                            int64_t nparts, int varlen, double* gt, hipStream_t st);
+                            int64_t nparts, int varlen, int ncomp, double* gt, hipStream_t st);
 
 }  // namespace tdt

@@ -139,9 +139,12 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, int off, T v
 #define TDT_STORE_AUX 2
 #endif
 
+// The segment of no rows: its "first row" is the value right of it and its
+// "last row" the value left of it, so that merging it on either side of a
+// segment changes nothing and outside values pass through it.
 template <typename T>
-__device__ __forceinline__ Seg<T> seg_zero() {
-  return Seg<T>{T(0), T(0), T(0), T(0), T(0), T(0)};
+__device__ __forceinline__ Seg<T> seg_identity() {
+  return Seg<T>{T(0), T(0), T(0), T(1), T(1), T(0)};
 }
 
 // Summary of L followed by R (the 2x2 elimination at their junction with zero
@@ -200,10 +203,11 @@ __device__ __forceinline__ void wave_scan(const Seg<T>& own, Seg<T>& pre, Seg<T>
 }
 
 // Workgroup level: wavefront summaries go through LDS; every thread derives
-// the values just outside its own wavefront from the tile's outside values.
-// Returns the tile summary.  Contains one barrier (all threads must call).
-template <typename T>
-__device__ __forceinline__ Seg<T> wg_level(const Seg<T>& pre, T (*wsum)[6], T XLt, T XRt,
+// the values just outside its own wavefront from the chain's outside values,
+// which outer(summary of the whole chain, XLt, XRt) supplies.  Returns the
+// chain's summary.  Contains one barrier (all threads must call).
+template <typename T, class Outer>
+__device__ __forceinline__ Seg<T> wg_level(const Seg<T>& pre, T (*wsum)[6], Outer outer,
                                            T& XLw, T& XRw) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (lane == 63) {
@@ -222,6 +226,8 @@ __device__ __forceinline__ Seg<T> wg_level(const Seg<T>& pre, T (*wsum)[6], T XL
   Q[kGridNW - 1] = W[kGridNW - 1];
 #pragma unroll
   for (int k = kGridNW - 2; k >= 0; --k) Q[k] = seg_merge(W[k], Q[k + 1]);
+  T XLt, XRt;
+  outer(P[kGridNW - 1], XLt, XRt);
   XLw = XLt;
   XRw = XRt;
 #pragma unroll
@@ -362,7 +368,7 @@ struct Consts {
   cptr<Tc> chi;
   Tc a;
   Tc pf, pl, cf;          // phi_first, phi_last, chi_first of a full block
-  Tc tail_pf;             // phi_first of the system's last block
+  Tc tail_pf, tail_pl, tail_cf;   // the same of the system's last block
 };
 
 // Solve the tile's local problem for this lane's block q (in: right-hand
@@ -393,7 +399,14 @@ struct Consts {
 // correction is skipped.  Two workgroup barriers inside.
 // FULL: every block of the tile has kB rows (the caller has checked it for
 // the whole workgroup), which removes the tail handling from the code.
-template <class SH, typename Tc, bool FULL>
+// Otherwise the rows past the system's last block (1..kB-1 rows) are 0 and
+// nothing is taken from the right of it (a right outside value of a tile
+// that ends inside a block is folded into its right-hand side by the caller).
+// TAILV (summaries): the last block takes the end values of its own length,
+// and the lanes past the end pass both recurrences through unchanged
+// (A = C = 1, g = h = 0), so that the tile's last unknown is the one of its
+// real last row.
+template <class SH, typename Tc, bool FULL, bool TAILV = false>
 __device__ __forceinline__ void tile_solve(Tc (&q)[SH::B], int len_in, Tc XLt, Tc XRt,
                                            const Consts<Tc>& K, Tc bp, Tc iDf,
                                            Tc (*fw)[2], Tc (*bw)[2], double* yfo,
@@ -424,17 +437,28 @@ __device__ __forceinline__ void tile_solve(Tc (&q)[SH::B], int len_in, Tc XLt, T
 
   // this block's coefficients
   Tc pf = K.pf, pl = K.pl, cf = K.cf, iD = iDf, yf = q[0], yl = q[kB - 1];
-  if (len < kB) {
-    pl = Tc(0);
-    cf = Tc(0);
-    yl = Tc(0);
+  if (!FULL && len < kB) {
     if (len > 0) {
       pf = K.tail_pf;
       iD = Tc(1) / (Tc(1) - pf * bp);
-    } else {
+      if (TAILV) {
+        pl = K.tail_pl;
+        cf = K.tail_cf;
+#pragma unroll
+        for (int i = 0; i + 1 < kB; ++i)
+          if (i == len - 1) yl = q[i];
+      } else {
+        pl = Tc(0);
+        cf = Tc(0);
+        yl = Tc(0);
+      }
+    } else {   // past the end
       pf = Tc(0);
+      pl = TAILV ? Tc(1) : Tc(0);
+      cf = TAILV ? Tc(1) : Tc(0);
       iD = Tc(1);
       yf = Tc(0);
+      yl = Tc(0);
     }
   }
   // left-to-right sums
@@ -457,7 +481,7 @@ __device__ __forceinline__ void tile_solve(Tc (&q)[SH::B], int len_in, Tc XLt, T
   Tc ein = XRt;
   for (int k = kNW - 1; k > w; --k) ein = bw[k][0] * ein + bw[k][1];
   const Tc u = C * ein + h;
-  if (yfo) {
+  if (TAILV || yfo) {
     if (threadIdx.x == 0) *yfo = (double)u;
     if (threadIdx.x == kNT - 1) *ylo = (double)alpha;
     return;
@@ -472,8 +496,8 @@ __device__ __forceinline__ void tile_solve(Tc (&q)[SH::B], int len_in, Tc XLt, T
     for (int i = 0; i < kB; ++i) q[i] += xl * phi[i] + xr * chi[i];
   } else if (len > 0) {
     // last block: re-sweep T_Bt x = q_orig - t_-1 xl e_0 in place, recovering
-    // the forward-sweep values d_i = y_i + cp_i y_{i+1} from y (xr is 0 here:
-    // the next row is past the end of the system)
+    // the forward-sweep values d_i = y_i + cp_i y_{i+1} from y (nothing comes
+    // from the right: see above)
     Tc delta = -K.a * xl * K.iu[0];
 #pragma unroll
     for (int i = 0; i < kB; ++i) {
@@ -560,7 +584,7 @@ __device__ __forceinline__ Consts<Tc> make_consts(const SysDesc& S, const double
   K.chi = c + kVecCHI * kB;
   K.a = (Tc)S.a;
   K.pf = (Tc)S.blk[0]; K.pl = (Tc)S.blk[1]; K.cf = (Tc)S.blk[2];
-  K.tail_pf = (Tc)S.tail_pf;
+  K.tail_pf = (Tc)S.tail_pf; K.tail_pl = (Tc)S.tail_pl; K.tail_cf = (Tc)S.tail_cf;
   return K;
 }
 
@@ -579,7 +603,7 @@ __device__ __forceinline__ TileGeom tile_geom(const int2* items, const SysDesc* 
   G.I = decode_item(items, sys, it, last_only);
   const SysDesc S = load_sys(sys, G.I.s);
   G.t0 = (int64_t)G.I.t * kTile;
-  G.base = S.off + G.I.m * S.n + G.t0;
+  G.base = S.off + G.I.m * S.stride + G.t0;
   G.tl = (int)(S.n - G.t0 < kTile ? S.n - G.t0 : kTile);
   return G;
 }
@@ -597,7 +621,7 @@ struct Prefetch {
   double XL, XR;
 };
 
-template <class SH, typename Tio, typename Tc, bool SUMMARY>
+template <class SH, typename Tio, typename Tc, bool SUMMARY, bool QUASI>
 __device__ __forceinline__ void prefetch(const TileArgs<Tio>& A, int64_t item,
                                          Prefetch<SH, Tio, Tc>& P) {
   TDT_SHAPE(SH)
@@ -618,11 +642,14 @@ __device__ __forceinline__ void prefetch(const TileArgs<Tio>& A, int64_t item,
     P.iD = tb[kTabInvD * kNT + tid];
   }
   if (!SUMMARY) {
+    // a one-tile system has no interface pass (zero outside values) unless
+    // it has corner rows
+    const bool has_ghosts = S.ntiles > 1 || QUASI;
     const int64_t slot = tile_slot(S, G.I.m, G.I.t, A.items != nullptr);
-    const int64_t gs = S.ntiles > 1 ? slot : 0;   // the ghost array always has slot 0
+    const int64_t gs = has_ghosts ? slot : 0;   // the ghost array always has slot 0
     const double xl = A.ghost[2 * gs], xr = A.ghost[2 * gs + 1];
-    P.XL = S.ntiles > 1 ? xl : 0.0;
-    P.XR = S.ntiles > 1 ? xr : 0.0;
+    P.XL = has_ghosts ? xl : 0.0;
+    P.XR = has_ghosts ? xr : 0.0;
   } else {
     P.XL = P.XR = 0.0;
   }
@@ -681,7 +708,8 @@ __device__ __forceinline__ int block_len(int tl) {
 // zero) it writes the tile's first and last unknown instead.  FULL: every
 // block has kB rows.  REFINE: Tio = double data, Tc = float sweeps; residual
 // and update in double, repeated until converged (see below).
-template <class SH, typename Tio, typename Tc, bool REFINE, bool SUMMARY, bool FULL>
+template <class SH, typename Tio, typename Tc, bool REFINE, bool SUMMARY, bool FULL,
+          bool TAILV = false>
 __device__ __forceinline__ void solve_in_lds(TileShared<SH, Tio, Tc>& sh, Tio* myrow, int len, int tl,
                                              double XLt, double XRt, const SysDesc& S,
                                              const Consts<Tc>& K, Tc bp, Tc iDf,
@@ -694,7 +722,7 @@ __device__ __forceinline__ void solve_in_lds(TileShared<SH, Tio, Tc>& sh, Tio* m
 #pragma unroll
     for (int i = 0; i < kB; ++i) q[i] = (Tc)myrow[i];
     if constexpr (SUMMARY) {
-      tile_solve<SH, Tc, FULL>(q, len, Tc(0), Tc(0), K, bp, iDf, sh.fw, sh.bw, yfo, ylo);
+      tile_solve<SH, Tc, FULL, TAILV>(q, len, Tc(0), Tc(0), K, bp, iDf, sh.fw, sh.bw, yfo, ylo);
     } else {
       tile_solve<SH, Tc, FULL>(q, len, (Tc)XLt, (Tc)XRt, K, bp, iDf, sh.fw, sh.bw, (double*)nullptr,
                            (double*)nullptr);
@@ -790,7 +818,13 @@ __device__ __forceinline__ void solve_in_lds(TileShared<SH, Tio, Tc>& sh, Tio* m
     est_max = fmaxf(est_max, est);
     if constexpr (SUMMARY) {
       if (tid == 0) *yfo = x[0];
-      if (tid == kNT - 1) *ylo = tl == kTile ? x[kB - 1] : 0.0;
+      if (tid == (tl - 1) / kB) {
+        double xl = x[kB - 1];
+#pragma unroll
+        for (int i = 0; i + 1 < kB; ++i)
+          if (i == (tl - 1) % kB) xl = x[i];
+        *ylo = xl;
+      }
     } else {
       __syncthreads();   // every lane is done reading f from LDS
 #pragma unroll
@@ -799,7 +833,7 @@ __device__ __forceinline__ void solve_in_lds(TileShared<SH, Tio, Tc>& sh, Tio* m
   }
 }
 
-template <class SH, typename Tio, typename Tc, bool REFINE, bool SUMMARY>
+template <class SH, typename Tio, typename Tc, bool REFINE, bool SUMMARY, bool TAILV = false>
 __device__ __forceinline__ void solve_tile_lds(TileShared<SH, Tio, Tc>& sh, int tl, double XLt,
                                                double XRt, const SysDesc& S,
                                                const Consts<Tc>& K, Tc bp, Tc iDf, double* yfo,
@@ -810,17 +844,20 @@ __device__ __forceinline__ void solve_tile_lds(TileShared<SH, Tio, Tc>& sh, int 
   // a separate full-tile copy of the solve pays where registers are free:
   // in the refinement kernel, which holds no prefetched tile
   if (REFINE && tl == kTile)
-    solve_in_lds<SH, Tio, Tc, REFINE, SUMMARY, true>(sh, myrow, kB, tl, XLt, XRt, S, K, bp, iDf, yfo, ylo,
+    solve_in_lds<SH, Tio, Tc, REFINE, SUMMARY, true, TAILV>(sh, myrow, kB, tl, XLt, XRt, S, K, bp, iDf, yfo, ylo,
                                         it_max, est_max, max_iter, refine_tol);
   else
-    solve_in_lds<SH, Tio, Tc, REFINE, SUMMARY, false>(sh, myrow, block_len<SH>(tl), tl, XLt, XRt, S, K, bp, iDf,
+    solve_in_lds<SH, Tio, Tc, REFINE, SUMMARY, false, TAILV>(sh, myrow, block_len<SH>(tl), tl, XLt, XRt, S, K, bp, iDf,
                                          yfo, ylo, it_max, est_max, max_iter, refine_tol);
 }
 
 // Stores the solved tile from LDS (coalesced).  BWD: also forms this tile's
 // t-gradient partial sums against the forward solution Xfwd and writes their
-// negatives to gpart[0..2] (one barrier pair inside).
-template <class SH, typename Tio, typename Tc, bool BWD>
+// negatives to gpart[0..2] (one barrier pair inside).  QUASI (quasi-Toeplitz
+// plans, whose partials have 5 components): 0 to the corner components
+// gpart[3..4], and the rows next to the corner rows read those rows' forward
+// solution; the corner rows themselves are stored by the interface pass.
+template <class SH, typename Tio, typename Tc, bool BWD, bool QUASI>
 __device__ __forceinline__ void store_tile(TileShared<SH, Tio, Tc>& sh, Tio* X, const Tio* Xfwd,
                                            int64_t base, int64_t t0, int tl, int64_t n,
                                            double* gpart) {
@@ -831,7 +868,7 @@ __device__ __forceinline__ void store_tile(TileShared<SH, Tio, Tc>& sh, Tio* X, 
   const __amdgpu_buffer_rsrc_t dst = make_rsrc(X + base, (int64_t)tl * sizeof(Tio));
   // adjoint: the forward solution over this tile and one row on each side
   // that lies inside the system (rows outside read as 0)
-  const int lo = t0 > 0 ? 1 : 0, hi = t0 + tl < n ? 1 : 0;
+  const int lo = t0 > 0 || QUASI ? 1 : 0, hi = t0 + tl < n || QUASI ? 1 : 0;
   const __amdgpu_buffer_rsrc_t xf =
       make_rsrc(BWD ? Xfwd + base - lo : X + base, BWD ? (int64_t)(lo + tl + hi) * sizeof(Tio) : 0);
   const Tio* lr = sh.lds + opaque(lds_base<SH, Tio>());
@@ -868,6 +905,57 @@ __device__ __forceinline__ void store_tile(TileShared<SH, Tio, Tc>& sh, Tio* X, 
       gpart[0] = -u;
       gpart[1] = -v;
       gpart[2] = -z;
+      if (QUASI) {
+        gpart[3] = 0.0;
+        gpart[4] = 0.0;
+      }
+    }
+  }
+}
+
+// The last tile of a quasi-Toeplitz system, when it ends inside a block: the
+// corner row's value XR right of it is folded into the tile's last
+// right-hand side row (f - t_1 XR), and the tile is then solved with 0 on
+// its right.  One thread changes the LDS copy; the caller's next barrier
+// publishes it.
+template <class SH, typename Tio, typename Tc>
+__device__ __forceinline__ void fold_right(TileShared<SH, Tio, Tc>& sh, int tl, double c,
+                                           double XR) {
+  TDT_SHAPE(SH)
+  const int e = tl - 1;
+  if ((int)threadIdx.x == e % kNT) {
+    Tio* p = sh.lds + lds_base<SH, Tio>() + (e / kNT) * lds_stride<SH, Tio>();
+    *p = (Tio)((double)*p - c * XR);
+  }
+}
+
+// A corner row of a quasi-Toeplitz system once the interface pass has its
+// value v: which = 0 is row 0 (stored at X[base - 1], base = the first inner
+// row), which = 1 row N-1 (at X[base + n]).  With Xfwd (adjoint, v = gF of
+// that row) the row's own t-gradient terms go to the corner slot cg[0..4]:
+// row 0 holds t_0 + psi and t_1, row N-1 holds t_-1 and t_0 + chi.
+template <typename Tio>
+__device__ __forceinline__ void store_corner(Tio* X, const Tio* Xfwd, double* cg, int64_t base,
+                                             int64_t n, int which, double v) {
+  if (which == 0) {
+    X[base - 1] = (Tio)v;
+    if (Xfwd) {
+      const double x0 = (double)Xfwd[base - 1], x1 = (double)Xfwd[base];
+      cg[0] = 0.0;
+      cg[1] = -v * x0;
+      cg[2] = -v * x1;
+      cg[3] = -v * x0;
+      cg[4] = 0.0;
+    }
+  } else {
+    X[base + n] = (Tio)v;
+    if (Xfwd) {
+      const double xn = (double)Xfwd[base + n], xp = (double)Xfwd[base + n - 1];
+      cg[0] = -v * xp;
+      cg[1] = -v * xn;
+      cg[2] = 0.0;
+      cg[3] = 0.0;
+      cg[4] = -v * xn;
     }
   }
 }
@@ -884,7 +972,7 @@ __device__ __forceinline__ void store_tile(TileShared<SH, Tio, Tc>& sh, Tio* X, 
 //                    in double, repeated until converged.
 //   BWD            : also accumulates the t-gradient partial sums against the
 //                    forward solution Xfwd (the tile solves T^T gF = gX).
-template <class SH, typename Tio, typename Tc, bool REFINE, bool SUMMARY, bool BWD>
+template <class SH, typename Tio, typename Tc, bool REFINE, bool SUMMARY, bool BWD, bool QUASI>
 __global__ __launch_bounds__(SH::NT, REFINE ? TDT_REFINE_WAVES : SH::WAVES) void k_tile(
     TileArgs<Tio> A) {
   TDT_SHAPE(SH)
@@ -898,10 +986,10 @@ __global__ __launch_bounds__(SH::NT, REFINE ? TDT_REFINE_WAVES : SH::WAVES) void
   float est_max = 0.0f;
   int64_t k = blockIdx.x;
   Prefetch<SH, Tio, Tc> P;
-  if (PF && k < A.nitems) prefetch<SH, Tio, Tc, SUMMARY>(A, item_of(k), P);
+  if (PF && k < A.nitems) prefetch<SH, Tio, Tc, SUMMARY, QUASI>(A, item_of(k), P);
 
   while (k < A.nitems) {
-    if (!PF) prefetch<SH, Tio, Tc, SUMMARY>(A, item_of(k), P);
+    if (!PF) prefetch<SH, Tio, Tc, SUMMARY, QUASI>(A, item_of(k), P);
     const int64_t item = item_of(k);
     const TileGeom G = tile_geom<SH>(A.items, A.sys, item, A.last_only);
     const SysDesc S = load_sys(A.sys, G.I.s);
@@ -918,18 +1006,25 @@ __global__ __launch_bounds__(SH::NT, REFINE ? TDT_REFINE_WAVES : SH::WAVES) void
       for (int j = 0; j < kB; ++j) lw[j * lstride] = P.v[j];
     }
     const int64_t kn = k + gridDim.x;
-    if (PF && kn < A.nitems) prefetch<SH, Tio, Tc, SUMMARY>(A, item_of(kn), P);
+    if (PF && kn < A.nitems) prefetch<SH, Tio, Tc, SUMMARY, QUASI>(A, item_of(kn), P);
     __syncthreads();
+    const bool fold = QUASI && !SUMMARY && tl < kTile;
+    if (fold) {
+      fold_right<SH>(sh, tl, S.c, XRt);
+      __syncthreads();
+    }
 
     if constexpr (SUMMARY) {
-      solve_tile_lds<SH, Tio, Tc, REFINE, true>(sh, tl, 0.0, 0.0, S, K, bp, iDf, A.summ + 2 * slot,
+      solve_tile_lds<SH, Tio, Tc, REFINE, true, QUASI>(sh, tl, 0.0, 0.0, S, K, bp, iDf, A.summ + 2 * slot,
                                       A.summ + 2 * slot + 1, it_max, est_max, A.max_iter, A.refine_tol);
     } else {
-      solve_tile_lds<SH, Tio, Tc, REFINE, false>(sh, tl, XLt, XRt, S, K, bp, iDf, (double*)nullptr,
-                                      (double*)nullptr, it_max, est_max, A.max_iter, A.refine_tol);
+      solve_tile_lds<SH, Tio, Tc, REFINE, false>(sh, tl, XLt, fold ? 0.0 : XRt, S, K, bp, iDf,
+                                                 (double*)nullptr, (double*)nullptr, it_max,
+                                                 est_max, A.max_iter, A.refine_tol);
       __syncthreads();
       const int64_t fs = A.items ? (int64_t)S.fslot0 + G.I.t : G.I.m * S.ntiles + G.I.t;
-      store_tile<SH, Tio, Tc, BWD>(sh, A.X, A.Xfwd, G.base, G.t0, tl, S.n, A.gpart + 3 * fs);
+      store_tile<SH, Tio, Tc, BWD, QUASI>(sh, A.X, A.Xfwd, G.base, G.t0, tl, S.n,
+                                          A.gpart + (QUASI ? kGradN : 3) * fs);
     }
     k = kn;
   }
@@ -1000,7 +1095,7 @@ __device__ __forceinline__ void lane_table(const SysDesc& S, const double* tab64
 //      first, so that the rows read last in step 1 are re-read from cache.
 // Summaries are computed in double for the refinement path (as in the
 // multi-kernel path), in the data precision otherwise.
-template <class SH, typename Tio, typename Tc, bool REFINE, bool BWD>
+template <class SH, typename Tio, typename Tc, bool REFINE, bool BWD, bool QUASI>
 __global__ __launch_bounds__(SH::NT, REFINE ? TDT_REFINE_WAVES : SH::WAVES) void k_sys(
     SysArgs<Tio> A) {
   TDT_SHAPE(SH)
@@ -1040,7 +1135,7 @@ __global__ __launch_bounds__(SH::NT, REFINE ? TDT_REFINE_WAVES : SH::WAVES) void
     const SysDesc S = load_sys(A.sys, s);
     const int nt = S.ntiles;
     if (nt > kSysMaxTiles) continue;   // never listed here (the host checks it)
-    if (nt > 1) {
+    if (nt > 1 || QUASI) {
       const Consts<Ts> KS = make_consts<SH, Ts>(S, A.vec64, A.vec32);
       Ts sbp, siD;
       lane_table<SH, Ts>(S, A.tab64, A.tab32, sbp, siD);
@@ -1055,14 +1150,16 @@ __global__ __launch_bounds__(SH::NT, REFINE ? TDT_REFINE_WAVES : SH::WAVES) void
         const Tio* myrow = sh.lds + tid * TileShared<SH, Tio, Tc>::RP;
 #pragma unroll
         for (int i = 0; i < kB; ++i) q[i] = (Ts)myrow[i];
-        tile_solve<SH, Ts, false>(q, block_len<SH>(tl), Ts(0), Ts(0), KS, sbp, siD, sfw, sbw,
-                              &tsum[t][0], &tsum[t][1]);
+        tile_solve<SH, Ts, false, QUASI>(q, block_len<SH>(tl), Ts(0), Ts(0), KS, sbp, siD, sfw,
+                                        sbw, &tsum[t][0], &tsum[t][1]);
       }
       __syncthreads();
       if (tid == 0) {
         // beta_{t-1} and 1/(1 - Pf_t beta_{t-1}) from the plan's table
-        // (slot order of the grid interface pass)
-        double alpha = 0.0;
+        // (slot order of the grid interface pass); a quasi-Toeplitz system
+        // starts from its first corner row (alpha = its local solution) and
+        // ends with its last (u = its solution)
+        double alpha = QUASI ? (double)A.F[S.off - 1] * S.qc[0] : 0.0;
         for (int t = 0; t < nt; ++t) {
           const double* Kt = t + 1 < nt ? S.tileK : S.ltileK;
           const int64_t pos = S.slot0 + (int64_t)(t % S.tr) * S.tq + t / S.tr;
@@ -1074,13 +1171,20 @@ __global__ __launch_bounds__(SH::NT, REFINE ? TDT_REFINE_WAVES : SH::WAVES) void
           const double At = Kt[1] * iD;
           alpha = At * alpha + (tsum[t][1] + At * bt * tsum[t][0]);
         }
-        double u = 0.0;
+        double u = QUASI ? ((double)A.F[S.off + S.n] * S.qc[2] + S.qc[3] * alpha) * S.qc[5]
+                           : 0.0;
         for (int t = nt - 1; t >= 0; --t) {
           const double* Kt = t + 1 < nt ? S.tileK : S.ltileK;
           const double un = u;
           u = Kt[2] * tiD[t] * u + th[t];
           tgh[t][0] = tap[t] + tbp[t] * u;
           tgh[t][1] = un;
+        }
+        if (QUASI) {   // the corner rows (slots after the system's tiles)
+          double* cg = A.gpart + kGradN * ((int64_t)S.fslot0 + nt);
+          const Tio* xf = BWD ? A.Xfwd : nullptr;
+          store_corner<Tio>(A.X, xf, cg, S.off, S.n, 0, tgh[0][0]);
+          store_corner<Tio>(A.X, xf, cg + kGradN, S.off, S.n, 1, tgh[nt - 1][1]);
         }
       }
       __syncthreads();
@@ -1091,21 +1195,27 @@ __global__ __launch_bounds__(SH::NT, REFINE ? TDT_REFINE_WAVES : SH::WAVES) void
     for (int t = nt - 1; t >= 0; --t) {
       const int64_t t0 = (int64_t)t * kTile;
       const int tl = tile_len(S, t);
-      const double XLt = nt > 1 ? tgh[t][0] : 0.0, XRt = nt > 1 ? tgh[t][1] : 0.0;
-      // the last tile of a multi-tile system is still in LDS from its summary
-      if (nt == 1 || t < nt - 1) {
+      const double XLt = nt > 1 || QUASI ? tgh[t][0] : 0.0;
+      const double XRt = nt > 1 || QUASI ? tgh[t][1] : 0.0;
+      // the last tile summarised is still in LDS
+      if ((!QUASI && nt == 1) || t < nt - 1) {
         __syncthreads();   // LDS free
         if (PF && t < nt - 1) commit();
         else load_tile<SH>(sh, A.F, S.off + t0, tl);
         __syncthreads();
       }
+      const bool fold = QUASI && tl < kTile;   // only the last tile can be short
+      if (fold) {
+        fold_right<SH>(sh, tl, S.c, XRt);
+        __syncthreads();
+      }
       if (PF && t > 0) issue(S.off + t0 - kTile, kTile);
-      solve_tile_lds<SH, Tio, Tc, REFINE, false>(sh, tl, XLt, XRt, S, K, bp, iD, (double*)nullptr,
-                                             (double*)nullptr, it_max, est_max,
-                                             A.max_iter, A.refine_tol);
+      solve_tile_lds<SH, Tio, Tc, REFINE, false>(sh, tl, XLt, fold ? 0.0 : XRt, S, K, bp, iD,
+                                                 (double*)nullptr, (double*)nullptr, it_max,
+                                                 est_max, A.max_iter, A.refine_tol);
       __syncthreads();
-      store_tile<SH, Tio, Tc, BWD>(sh, A.X, A.Xfwd, S.off + t0, t0, tl, S.n,
-                               A.gpart + 3 * ((int64_t)S.fslot0 + t));
+      store_tile<SH, Tio, Tc, BWD, QUASI>(sh, A.X, A.Xfwd, S.off + t0, t0, tl, S.n,
+                                          A.gpart + (QUASI ? kGradN : 3) * ((int64_t)S.fslot0 + t));
     }
   }
   publish_refine_record(A.iters, it_max, est_max);
@@ -1147,7 +1257,7 @@ __global__ __launch_bounds__(kBetaNT) void k_beta(BetaArgs<Tio> A) {
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const SysDesc S0 = load_sys(A.sys, 0);
-  const int64_t n = S0.n;
+  const int64_t base0 = S0.off, stride = S0.stride;
   // rows of this lane inside its slice: (j*64 + lane)*V + v
   double g1[kBetaPerLane], gl[kBetaPerLane];
 #pragma unroll
@@ -1168,7 +1278,8 @@ __global__ __launch_bounds__(kBetaNT) void k_beta(BetaArgs<Tio> A) {
     const int64_t m = it / A.nfull;
     const int t = (int)(it - m * A.nfull);
     const __amdgpu_buffer_rsrc_t src = make_rsrc(
-        A.F + m * n + (int64_t)t * kTile + w * kSlice, (int64_t)kSlice * sizeof(Tio));
+        A.F + base0 + m * stride + (int64_t)t * kTile + w * kSlice,
+        (int64_t)kSlice * sizeof(Tio));
     const int vb = opaque(lane * 16);
     using R4 = decltype(__builtin_amdgcn_raw_buffer_load_b128(src, 0, 0, 0));
     R4 raw[NL];
@@ -1221,6 +1332,14 @@ __global__ __launch_bounds__(kBetaNT) void k_beta(BetaArgs<Tio> A) {
 }
 
 struct GridArgs {
+  // quasi-Toeplitz systems: the corner rows of the right-hand side are read,
+  // and those of the solution written, here
+  const void* F;
+  void* X;
+  const void* Xfwd;                   // adjoint: forward solution (else null)
+  double* gpart;                      // adjoint: t-gradient slots (corner rows)
+  int64_t corner0;                    // series: first corner slot (2 per right-hand side)
+  int f32;                            // F, X hold floats
   const SysDesc* __restrict__ sys;
   const int* __restrict__ gitems;     // varlen: system of each workgroup; null for a series
   const double* __restrict__ ttab;    // [2][tile slot]: beta_{t-1}, 1/(1 - Pf_t beta_{t-1})
@@ -1230,11 +1349,48 @@ struct GridArgs {
   double* __restrict__ gscr;          // [slot][3] suffix (y_first, phi_first, chi_first)
 };
 
+__device__ __forceinline__ double grid_f(const GridArgs& A, int64_t i) {
+  return A.f32 ? (double)static_cast<const float*>(A.F)[i] : static_cast<const double*>(A.F)[i];
+}
+
+// The two corner rows of a quasi-Toeplitz system in the interface pass: the
+// first one enters the left-to-right recurrence as alpha = its local solution
+// f_0 / (t0 + psi) (its beta is part of the plan's table); the last one
+// closes the right-to-left recurrence with u = (f_{N-1} / (t0 + chi) +
+// Pf alpha_{P-1}) / (1 - Pf beta_{P-1}), Pf = -t_-1 / (t0 + chi), which is
+// the solution in that row.
+template <bool QUASI>
+__device__ __forceinline__ double corner_alpha(const GridArgs& A, const SysDesc& S,
+                                               int64_t base) {
+  return QUASI ? grid_f(A, base - 1) * S.qc[0] : 0.0;
+}
+template <bool QUASI>
+__device__ __forceinline__ double corner_u(const GridArgs& A, const SysDesc& S, int64_t base,
+                                           double alpha_last) {
+  return QUASI ? (grid_f(A, base + S.n) * S.qc[2] + S.qc[3] * alpha_last) * S.qc[5] : 0.0;
+}
+// Stores corner row `which` (0: row 0, 1: row N-1) with value v; a series
+// keeps the corner slots of right-hand side m at corner0 + 2m, a varlen
+// system right after its tiles' slots.
+__device__ __forceinline__ void grid_corner(const GridArgs& A, const SysDesc& S, int64_t base,
+                                            int which, double v) {
+  const int64_t cs =
+      (A.gitems ? (int64_t)S.fslot0 + S.ntiles : A.corner0 + 2 * (int64_t)blockIdx.x) + which;
+  double* cg = A.gpart + kGradN * cs;
+  if (A.f32)
+    store_corner<float>(static_cast<float*>(A.X), static_cast<const float*>(A.Xfwd), cg, base,
+                        S.n, which, v);
+  else
+    store_corner<double>(static_cast<double*>(A.X), static_cast<const double*>(A.Xfwd), cg, base,
+                         S.n, which, v);
+}
+
 // Interface pass across the tiles of one system (one workgroup per system
 // and right-hand side): every thread folds a run of consecutive tile
 // summaries, the runs are combined by the same wavefront scans and LDS level
 // as inside a tile, and each thread then walks its run left to right to give
 // every tile the values just outside it.
+template <bool QUASI>
 __global__ __launch_bounds__(kGridNT) void k_grid(GridArgs A) {
   __shared__ double wsum[kGridNW][6];
   const int tid = threadIdx.x;
@@ -1260,7 +1416,7 @@ __global__ __launch_bounds__(kGridNT) void k_grid(GridArgs A) {
     return Seg<double>{summ[2 * t], summ[2 * t + 1], k[0], k[1], k[2], k[3]};
   };
 
-  Seg<double> acc = seg_zero<double>();
+  Seg<double> acc = seg_identity<double>();   // an empty run
   for (int t = tb - 1; t >= ta; --t) {
     const Seg<double> ts = tile_seg(t);
     acc = t == tb - 1 ? ts : seg_merge(ts, acc);
@@ -1270,14 +1426,34 @@ __global__ __launch_bounds__(kGridNT) void k_grid(GridArgs A) {
   }
   Seg<double> pre, suf;
   wave_scan(acc, pre, suf);
+  // values outside the chain of tiles: 0, or for a quasi-Toeplitz system the
+  // two corner rows, from their equations and the chain's end responses
+  //   x_0     = f_0 qc0     + qc1 (yf + pf x_0 + cf x_N-1),
+  //   x_{N-1} = f_{N-1} qc2 + qc3 (yl + pl x_0 + cl x_N-1)
+  const int64_t base = S.off + (A.gitems ? 0 : (int64_t)blockIdx.x) * S.stride;
+  auto outer = [&](const Seg<double>& W, double& xl0, double& xr0) {
+    if (!QUASI) {
+      xl0 = xr0 = 0.0;
+      return;
+    }
+    const double l = grid_f(A, base - 1) * S.qc[0] + S.qc[1] * W.yf;
+    const double r = grid_f(A, base + S.n) * S.qc[2] + S.qc[3] * W.yl;
+    const double m00 = 1.0 - S.qc[1] * W.pf, m01 = -S.qc[1] * W.cf;
+    const double m10 = -S.qc[3] * W.pl, m11 = 1.0 - S.qc[3] * W.cl;
+    const double idet = 1.0 / (m00 * m11 - m01 * m10);
+    xl0 = (l * m11 - m01 * r) * idet;
+    xr0 = (m00 * r - m10 * l) * idet;
+  };
   double XLw, XRw;
-  wg_level(pre, wsum, 0.0, 0.0, XLw, XRw);
+  wg_level(pre, wsum, outer, XLw, XRw);
   double xl, xr;
   lane_ghosts(pre, suf, XLw, XRw, xl, xr);
+  if (QUASI && ta == 0 && tb > 0) grid_corner(A, S, base, 0, xl);
   for (int t = ta; t < tb; ++t) {
     if (t == tb - 1) {
       ghost[2 * t] = xl;
       ghost[2 * t + 1] = xr;
+      if (QUASI && t == P - 1) grid_corner(A, S, base, 1, xr);
     } else {
       const Seg<double> ts = tile_seg(t);
       double xk, xk1;
@@ -1294,7 +1470,7 @@ __global__ __launch_bounds__(kGridNT) void k_grid(GridArgs A) {
 // of NTG threads per system and right-hand side, runs of R consecutive tiles
 // per thread).  Tiles play the role blocks play inside a tile: with
 // (yf_t, yl_t) the tile summaries and (Pf, Pl, Cf, Cl) the end values of a
-// full tile (the last tile has its own, padded), the left-to-right
+// full tile (the last tile has those of its own length), the left-to-right
 // elimination coefficient
 //     beta_t = Cl + Pl Cf beta_{t-1} / (1 - Pf beta_{t-1}),  beta_{-1} = 0,
 // depends on T only and comes, with 1/(1 - Pf beta_{t-1}), from the plan's
@@ -1307,7 +1483,19 @@ template <int NTG>
 struct GridShared {
   double f[NTG / 64][2];   // wave aggregates (left-to-right affine map)
   double b[NTG / 64][2];   // wave aggregates (right-to-left affine map)
+  double alast;            // alpha of the last tile (quasi-Toeplitz systems)
 };
+
+// alpha of the last tile, from the thread that holds it to all (one
+// barrier, quasi-Toeplitz systems only)
+template <int NTG, bool QUASI>
+__device__ __forceinline__ double share_alpha_last(GridShared<NTG>& sh, bool mine,
+                                                   double alast) {
+  if (!QUASI) return 0.0;
+  if (mine) sh.alast = alast;
+  __syncthreads();
+  return sh.alast;
+}
 
 // Exclusive left-to-right scan of affine maps x -> A x + g over the threads
 // of a workgroup; returns the value entering this thread given x_in for
@@ -1344,7 +1532,7 @@ __device__ __forceinline__ double scan_affine_bwd(double C, double h, double x_i
 }
 
 // Runs are held in registers: every input of the run is loaded up front.
-template <int NTG, int R>
+template <int NTG, int R, bool QUASI>
 __global__ __launch_bounds__(NTG) void k_grid_affine(GridArgs A) {
   __shared__ GridShared<NTG> sh;
   const int tid = threadIdx.x;
@@ -1361,6 +1549,7 @@ __global__ __launch_bounds__(NTG) void k_grid_affine(GridArgs A) {
   const int tq = S.tq;
   const double* summ = A.summ + 2 * slot0;
   double* ghost = A.ghost + 2 * slot0;
+  const int64_t base = S.off + (A.gitems ? 0 : (int64_t)blockIdx.x) * S.stride;
   const int ta = tid * R;
   // this thread's tiles: ta .. ta+R-1 (those >= P are empty), tile ta+r at
   // slot r*tq + tid (run-interleaved).  Full tiles share (Pf, Pl, Cf, Cl);
@@ -1375,11 +1564,13 @@ __global__ __launch_bounds__(NTG) void k_grid_affine(GridArgs A) {
     yf[r] = t < P ? u : 0.0;
     yl[r] = t < P ? v : 0.0;
   }
+  // an empty tile passes both recurrences through (A = C = 1, g = h = 0),
+  // so that the value entering from the right reaches the last tile
   auto kofs = [&](int t, double& pf, double& pl, double& cf, double& cl) {
     const bool real = t < P, last = t == P - 1;
     pf = real ? (last ? S.ltileK[0] : S.tileK[0]) : 0.0;
-    pl = real ? (last ? S.ltileK[1] : S.tileK[1]) : 0.0;
-    cf = real ? (last ? S.ltileK[2] : S.tileK[2]) : 0.0;
+    pl = real ? (last ? S.ltileK[1] : S.tileK[1]) : 1.0;
+    cf = real ? (last ? S.ltileK[2] : S.tileK[2]) : 1.0;
     cl = real ? (last ? S.ltileK[3] : S.tileK[3]) : 0.0;
   };
   // 1. beta_{t-1} and 1/(1 - Pf_t beta_{t-1}) at every tile, from the plan's
@@ -1405,8 +1596,9 @@ __global__ __launch_bounds__(NTG) void k_grid_affine(GridArgs A) {
     Af = At * Af;
   }
   // 2. alpha (left to right)
-  double alpha = scan_affine_fwd<NTG>(Af, gf, 0.0, sh.f);   // alpha_{ta-1}
+  double alpha = scan_affine_fwd<NTG>(Af, gf, corner_alpha<QUASI>(A, S, base), sh.f);   // alpha_{ta-1}
   double ap[R], h[R];
+  double alast = 0.0;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     double pf, pl, cf, cl;
@@ -1414,7 +1606,9 @@ __global__ __launch_bounds__(NTG) void k_grid_affine(GridArgs A) {
     ap[r] = alpha;
     h[r] = (yf[r] + pf * alpha) * iD[r];
     alpha = pl * iD[r] * alpha + (yl[r] + pl * iD[r] * bp[r] * yf[r]);
+    if (ta + r == P - 1) alast = alpha;
   }
+  alast = share_alpha_last<NTG, QUASI>(sh, ta <= P - 1 && P - 1 < ta + R, alast);
   // 3. u (right to left)
   double Cb = 1.0, hb = 0.0;   // composite right-to-left map of the run
 #pragma unroll
@@ -1425,7 +1619,7 @@ __global__ __launch_bounds__(NTG) void k_grid_affine(GridArgs A) {
     hb = Cr * hb + h[r];
     Cb = Cr * Cb;
   }
-  double u = scan_affine_bwd<NTG>(Cb, hb, 0.0, sh.b);      // u_{ta+R}
+  double u = scan_affine_bwd<NTG>(Cb, hb, corner_u<QUASI>(A, S, base, alast), sh.b);   // u_{ta+R}
 #pragma unroll
   for (int r = R - 1; r >= 0; --r) {
     const int t = ta + r;
@@ -1435,8 +1629,11 @@ __global__ __launch_bounds__(NTG) void k_grid_affine(GridArgs A) {
     u = cf * iD[r] * u + h[r];           // u_t
     if (t < P) {
       const int pc = pos(r);
-      ghost[2 * pc] = ap[r] + bp[r] * u;
+      const double xl = ap[r] + bp[r] * u;
+      ghost[2 * pc] = xl;
       ghost[2 * pc + 1] = un;
+      if (QUASI && t == 0) grid_corner(A, S, base, 0, xl);
+      if (QUASI && t == P - 1) grid_corner(A, S, base, 1, un);
     }
   }
 }
@@ -1444,7 +1641,7 @@ __global__ __launch_bounds__(NTG) void k_grid_affine(GridArgs A) {
 // The same pass for the widest workgroup (1024 threads, whose register
 // budget cannot hold a run's inputs): each pass re-reads a tile's inputs from
 // L2, and alpha_{t-1} and h_t wait in the tile's ghost slot between passes.
-template <int NTG, int R>
+template <int NTG, int R, bool QUASI>
 __global__ __launch_bounds__(NTG) void k_grid_affine_lean(GridArgs A) {
   __shared__ GridShared<NTG> sh;
   const int tid = threadIdx.x;
@@ -1462,6 +1659,7 @@ __global__ __launch_bounds__(NTG) void k_grid_affine_lean(GridArgs A) {
   const double* summ = A.summ + 2 * slot0;
   double* ghost = A.ghost + 2 * slot0;
   const int64_t tb0 = A.gitems ? slot0 : 0;
+  const int64_t base = S.off + (A.gitems ? 0 : (int64_t)blockIdx.x) * S.stride;
   const int ta = tid * R;
   // This thread's tiles ta .. ta+R-1 (those >= P are empty); tile ta+r sits
   // at slot r*tq + tid (run-interleaved).  Each pass re-reads a tile's
@@ -1483,9 +1681,10 @@ __global__ __launch_bounds__(NTG) void k_grid_affine_lean(GridArgs A) {
     x.yl = real ? v : 0.0;
     x.bp = real ? b0 : 0.0;
     x.iD = real ? i0 : 1.0;
+    // an empty tile passes both recurrences through (A = C = 1, g = h = 0)
     x.pf = real ? K[0] : 0.0;
-    x.pl = real ? K[1] : 0.0;
-    x.cf = real ? K[2] : 0.0;
+    x.pl = real ? K[1] : 1.0;
+    x.cf = real ? K[2] : 1.0;
     return x;
   };
   // 1. composite left-to-right map of the run: alpha_t = A_t alpha_{t-1} + g_t
@@ -1501,8 +1700,9 @@ __global__ __launch_bounds__(NTG) void k_grid_affine_lean(GridArgs A) {
   // 2. alpha entering the run; walk it, keeping alpha_{t-1} and h_t of every
   //    tile in its ghost slot until step 3, and compose the run's right-to-left
   //    map u_t = C_t u_{t+1} + h_t front to back (u_ta = Cb u_{ta+R} + hb)
-  double alpha = scan_affine_fwd<NTG>(Af, gf, 0.0, sh.f);   // alpha_{ta-1}
+  double alpha = scan_affine_fwd<NTG>(Af, gf, corner_alpha<QUASI>(A, S, base), sh.f);   // alpha_{ta-1}
   double Cb = 1.0, hb = 0.0;
+  double alast = 0.0;
 #pragma unroll 4
   for (int r = 0; r < R; ++r) {
     const TileIn x = tile_in(r);
@@ -1515,10 +1715,12 @@ __global__ __launch_bounds__(NTG) void k_grid_affine_lean(GridArgs A) {
     hb += Cb * h;
     Cb *= x.cf * x.iD;
     alpha = x.pl * x.iD * alpha + (x.yl + x.pl * x.iD * x.bp * x.yf);
+    if (ta + r == P - 1) alast = alpha;
   }
+  alast = share_alpha_last<NTG, QUASI>(sh, ta <= P - 1 && P - 1 < ta + R, alast);
   // 3. u (right to left) and the values just outside every tile:
   //    alpha_{t-1} + beta_{t-1} u_t and u_{t+1}
-  double u = scan_affine_bwd<NTG>(Cb, hb, 0.0, sh.b);       // u_{ta+R}
+  double u = scan_affine_bwd<NTG>(Cb, hb, corner_u<QUASI>(A, S, base, alast), sh.b);   // u_{ta+R}
 #pragma unroll 4
   for (int r = R - 1; r >= 0; --r) {
     if (ta + r >= P) continue;
@@ -1527,47 +1729,47 @@ __global__ __launch_bounds__(NTG) void k_grid_affine_lean(GridArgs A) {
     const double ap = ghost[2 * pc], h = ghost[2 * pc + 1];
     const double un = u;                 // u_{t+1}
     u = x.cf * x.iD * u + h;             // u_t
-    ghost[2 * pc] = ap + x.bp * u;
+    const double xl = ap + x.bp * u;
+    ghost[2 * pc] = xl;
     ghost[2 * pc + 1] = un;
+    if (QUASI && ta + r == 0) grid_corner(A, S, base, 0, xl);
+    if (QUASI && ta + r == P - 1) grid_corner(A, S, base, 1, un);
   }
 }
 
 // Deterministic second stage of the t-gradient sums: series plans sum all
 // partials (one workgroup, fixed tree); varlen plans sum each system's tiles
-// in order (one thread per system).
+// in order (one thread per system).  A partial slot holds ncomp values: 3
+// (t_-1, t_0, t_1), or 5 with (psi, chi) for quasi-Toeplitz plans.
 __global__ __launch_bounds__(kGridNT) void k_gt_reduce(const double* __restrict__ gpart,
                                                    const SysDesc* __restrict__ sys,
                                                    int64_t nsys, int64_t nparts, int varlen,
-                                                   double* __restrict__ gt) {
+                                                   int ncomp, double* __restrict__ gt) {
   if (varlen) {
     const int64_t s = (int64_t)blockIdx.x * kGridNT + threadIdx.x;
     if (s >= nsys) return;
     const int64_t f0 = sys[s].fslot0;
-    double u = 0.0, v = 0.0, z = 0.0;
-    for (int t = 0; t < sys[s].ntiles; ++t) {
-      u += gpart[3 * (f0 + t)];
-      v += gpart[3 * (f0 + t) + 1];
-      z += gpart[3 * (f0 + t) + 2];
-    }
-    gt[3 * s] = u; gt[3 * s + 1] = v; gt[3 * s + 2] = z;
+    // the system's tiles, then its two corner rows (quasi-Toeplitz)
+    const int nf = sys[s].ntiles + (sys[s].quasi ? 2 : 0);
+    double acc[kGradN] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < nf; ++t)
+      for (int c = 0; c < ncomp; ++c) acc[c] += gpart[ncomp * (f0 + t) + c];
+    for (int c = 0; c < ncomp; ++c) gt[ncomp * s + c] = acc[c];
     return;
   }
-  __shared__ double red[kGridNT][3];
-  double u = 0.0, v = 0.0, z = 0.0;
-  for (int64_t k = threadIdx.x; k < nparts; k += kGridNT) {
-    u += gpart[3 * k]; v += gpart[3 * k + 1]; z += gpart[3 * k + 2];
-  }
-  red[threadIdx.x][0] = u; red[threadIdx.x][1] = v; red[threadIdx.x][2] = z;
+  __shared__ double red[kGridNT][kGradN];
+  double acc[kGradN] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t k = threadIdx.x; k < nparts; k += kGridNT)
+    for (int c = 0; c < ncomp; ++c) acc[c] += gpart[ncomp * k + c];
+  for (int c = 0; c < kGradN; ++c) red[threadIdx.x][c] = acc[c];
   __syncthreads();
   for (int h = kGridNT / 2; h >= 1; h >>= 1) {
-    if ((int)threadIdx.x < h) {
-      red[threadIdx.x][0] += red[threadIdx.x + h][0];
-      red[threadIdx.x][1] += red[threadIdx.x + h][1];
-      red[threadIdx.x][2] += red[threadIdx.x + h][2];
-    }
+    if ((int)threadIdx.x < h)
+      for (int c = 0; c < kGradN; ++c) red[threadIdx.x][c] += red[threadIdx.x + h][c];
     __syncthreads();
   }
-  if (threadIdx.x == 0) { gt[0] = red[0][0]; gt[1] = red[0][1]; gt[2] = red[0][2]; }
+  if (threadIdx.x == 0)
+    for (int c = 0; c < ncomp; ++c) gt[c] = red[0][c];
 }
 
 }  // namespace tdt
@@ -1606,10 +1808,10 @@ static int64_t grid_cap(int per_cu, int wg_per_cu) {
   return (int64_t)n * num_cus();
 }
 
-template <class SH, typename Tio, typename Tc, bool REFINE, bool SUMMARY, bool BWD>
+template <class SH, typename Tio, typename Tc, bool REFINE, bool SUMMARY, bool BWD, bool QUASI>
 static void launch_tile(TileArgs<Tio>& A, int64_t nitems, int reverse, int last_only,
                         int wg_per_cu, hipStream_t st) {
-  auto kern = k_tile<SH, Tio, Tc, REFINE, SUMMARY, BWD>;
+  auto kern = k_tile<SH, Tio, Tc, REFINE, SUMMARY, BWD, QUASI>;
   static int per_cu = resident_per_cu(kern, SH::NT);
   const int64_t cap = grid_cap(per_cu, wg_per_cu);
   A.nitems = nitems;
@@ -1619,22 +1821,22 @@ static void launch_tile(TileArgs<Tio>& A, int64_t nitems, int reverse, int last_
   hipLaunchKernelGGL(kern, dim3(grid), dim3(SH::NT), 0, st, A);
 }
 
-template <class SH, typename Tio, typename Tc, bool REFINE, bool BWD>
+template <class SH, typename Tio, typename Tc, bool REFINE, bool BWD, bool QUASI>
 static void launch_sys(const LaunchSet& L, const TileArgs<Tio>& T, hipStream_t st) {
   SysArgs<Tio> A{T.F,         T.X,         T.sys,      T.vec64,  T.vec32,   T.tab64,
                  T.tab32,     L.sys_items, L.sys_bins, L.ttab,   L.ttab_n,  T.Xfwd,
                  T.gpart,     T.iters,     T.max_iter, T.refine_tol};
-  hipLaunchKernelGGL((k_sys<SH, Tio, Tc, REFINE, BWD>), dim3((unsigned)L.n_bins), dim3(SH::NT),
+  hipLaunchKernelGGL((k_sys<SH, Tio, Tc, REFINE, BWD, QUASI>), dim3((unsigned)L.n_bins), dim3(SH::NT),
                      0, st, A);
 }
 
-template <class SH>
+template <class SH, bool QUASI>
 static int sys_capacity(int dtype, int wg_per_cu) {
   int per_cu;
   switch (dtype) {
-    case 0: per_cu = resident_per_cu(k_sys<SH, double, double, false, false>, SH::NT); break;
-    case 1: per_cu = resident_per_cu(k_sys<SH, float, float, false, false>, SH::NT); break;
-    default: per_cu = resident_per_cu(k_sys<SH, double, float, true, false>, SH::NT); break;
+    case 0: per_cu = resident_per_cu(k_sys<SH, double, double, false, false, QUASI>, SH::NT); break;
+    case 1: per_cu = resident_per_cu(k_sys<SH, float, float, false, false, QUASI>, SH::NT); break;
+    default: per_cu = resident_per_cu(k_sys<SH, double, float, true, false, QUASI>, SH::NT); break;
   }
   return (int)grid_cap(per_cu, wg_per_cu);
 }
@@ -1652,22 +1854,25 @@ static void launch_beta(const LaunchSet& L, const Tio* F, hipStream_t st) {
 // Interface pass across tiles: the affine variant sized for the most tiled
 // system (up to 16384 tiles), beyond that the segment-merge kernel.  The
 // plan lays out its workspace slots for the same choice (interface_run).
-static void launch_grid(const LaunchSet& L, hipStream_t st) {
-  GridArgs G{L.sys, L.grid_items, L.ttab, L.ttab_n, L.summ, L.ghost, L.gscr};
+template <bool QUASI>
+static void launch_grid(const LaunchSet& L, const void* F, void* X, const void* Xfwd, int f32,
+                        hipStream_t st) {
+  GridArgs G{F,     X,          Xfwd,   L.gpart,  L.corner0, f32,    L.sys,
+             L.grid_items, L.ttab, L.ttab_n, L.summ,   L.ghost, L.gscr};
   const dim3 gg((unsigned)L.n_grid);
   if (L.max_ntiles <= 256)
-    hipLaunchKernelGGL((k_grid_affine<256, 1>), gg, dim3(256), 0, st, G);
+    hipLaunchKernelGGL((k_grid_affine<256, 1, QUASI>), gg, dim3(256), 0, st, G);
   else if (L.max_ntiles <= 2048)
-    hipLaunchKernelGGL((k_grid_affine<256, 8>), gg, dim3(256), 0, st, G);
+    hipLaunchKernelGGL((k_grid_affine<256, 8, QUASI>), gg, dim3(256), 0, st, G);
   else if (L.max_ntiles <= 8192)
-    hipLaunchKernelGGL((k_grid_affine<512, 16>), gg, dim3(512), 0, st, G);
+    hipLaunchKernelGGL((k_grid_affine<512, 16, QUASI>), gg, dim3(512), 0, st, G);
   else if (L.max_ntiles <= 16384)
-    hipLaunchKernelGGL((k_grid_affine_lean<1024, 16>), gg, dim3(1024), 0, st, G);
+    hipLaunchKernelGGL((k_grid_affine_lean<1024, 16, QUASI>), gg, dim3(1024), 0, st, G);
   else
-    hipLaunchKernelGGL(k_grid, gg, dim3(kGridNT), 0, st, G);
+    hipLaunchKernelGGL((k_grid<QUASI>), gg, dim3(kGridNT), 0, st, G);
 }
 
-template <class SH, typename Tio, typename Tc, bool REFINE, bool BWD>
+template <class SH, typename Tio, typename Tc, bool REFINE, bool BWD, bool QUASI>
 static hipError_t run_solve(const LaunchSet& L, const void* F, void* X, const void* Xfwd,
                             hipStream_t st) {
   TileArgs<Tio> A;
@@ -1695,27 +1900,27 @@ static hipError_t run_solve(const LaunchSet& L, const void* F, void* X, const vo
       if (L.n_beta > 0) launch_beta<SH, Tio>(L, static_cast<const Tio*>(F), st);
       if (L.n_last > 0) {
         A.items = nullptr;
-        launch_tile<SH, Tio, Ts, false, true, false>(A, L.n_last, 0, 1, L.wg_per_cu, st);
+        launch_tile<SH, Tio, Ts, false, true, false, QUASI>(A, L.n_last, 0, 1, L.wg_per_cu, st);
       }
     } else {
       A.items = L.p1_items;
-      launch_tile<SH, Tio, Ts, false, true, false>(A, L.n_p1, 0, 0, L.wg_per_cu, st);
+      launch_tile<SH, Tio, Ts, false, true, false, QUASI>(A, L.n_p1, 0, 0, L.wg_per_cu, st);
     }
     if (L.ev) (void)hipEventRecord(L.ev[1], st);
-    launch_grid(L, st);
+    launch_grid<QUASI>(L, F, X, Xfwd, sizeof(Tio) == 4 ? 1 : 0, st);
     if (L.ev) (void)hipEventRecord(L.ev[2], st);
   } else if (L.ev) {
     (void)hipEventRecord(L.ev[1], st);
     (void)hipEventRecord(L.ev[2], st);
   }
   // systems solved whole by one workgroup each (varlen plans)
-  if (L.n_sys > 0) launch_sys<SH, Tio, Tc, REFINE, BWD>(L, A, st);
+  if (L.n_sys > 0) launch_sys<SH, Tio, Tc, REFINE, BWD, QUASI>(L, A, st);
   A.items = L.fin_items;
   // after a first pass the final pass re-reads the tiles the first pass read
   // last while they are still cached: a series runs last-tile-first, a varlen
   // plan's list already starts with the first pass's tiles in reverse
   if (L.n_fin > 0)
-    launch_tile<SH, Tio, Tc, REFINE, false, BWD>(
+    launch_tile<SH, Tio, Tc, REFINE, false, BWD, QUASI>(
         A, L.n_fin, (L.n_p1 > 0 && !L.fin_items) ? 1 : 0, 0, L.wg_per_cu, st);
   if (L.ev) (void)hipEventRecord(L.ev[3], st);
   return hipGetLastError();
@@ -1724,17 +1929,23 @@ static hipError_t run_solve(const LaunchSet& L, const void* F, void* X, const vo
 template <class SH>
 static hipError_t launch_shape(int dtype, bool bwd, const LaunchSet& L, const void* F, void* X,
                                const void* Xfwd, hipStream_t st) {
-  switch (dtype) {
-    case 0:
-      return bwd ? run_solve<SH, double, double, false, true>(L, F, X, Xfwd, st)
-                 : run_solve<SH, double, double, false, false>(L, F, X, Xfwd, st);
-    case 1:
-      return bwd ? run_solve<SH, float, float, false, true>(L, F, X, Xfwd, st)
-                 : run_solve<SH, float, float, false, false>(L, F, X, Xfwd, st);
-    default:
-      return bwd ? run_solve<SH, double, float, true, true>(L, F, X, Xfwd, st)
-                 : run_solve<SH, double, float, true, false>(L, F, X, Xfwd, st);
-  }
+  // quasi-Toeplitz plans run their own instantiations, so that the corner
+  // handling costs the Toeplitz kernels nothing
+  auto go = [&](auto quasi) -> hipError_t {
+    constexpr bool Q = decltype(quasi)::value;
+    switch (dtype) {
+      case 0:
+        return bwd ? run_solve<SH, double, double, false, true, Q>(L, F, X, Xfwd, st)
+                   : run_solve<SH, double, double, false, false, Q>(L, F, X, Xfwd, st);
+      case 1:
+        return bwd ? run_solve<SH, float, float, false, true, Q>(L, F, X, Xfwd, st)
+                   : run_solve<SH, float, float, false, false, Q>(L, F, X, Xfwd, st);
+      default:
+        return bwd ? run_solve<SH, double, float, true, true, Q>(L, F, X, Xfwd, st)
+                   : run_solve<SH, double, float, true, false, Q>(L, F, X, Xfwd, st);
+    }
+  };
+  return L.quasi ? go(std::true_type()) : go(std::false_type());
 }
 
 using Shape0 = Shape<kShapes[0].B, kShapes[0].NT, kShapes[0].waves>;
@@ -1751,19 +1962,25 @@ hipError_t launch_solve(int dtype, bool bwd, const LaunchSet& L, const void* F, 
   }
 }
 
-int sys_wg_capacity(int shape, int dtype, int wg_per_cu) {
+int sys_wg_capacity(int shape, int dtype, int wg_per_cu, int quasi) {
   switch (shape) {
-    case 1: return sys_capacity<Shape1>(dtype, wg_per_cu);
-    case 2: return sys_capacity<Shape2>(dtype, wg_per_cu);
-    default: return sys_capacity<Shape0>(dtype, wg_per_cu);
+    case 1:
+      return quasi ? sys_capacity<Shape1, true>(dtype, wg_per_cu)
+                   : sys_capacity<Shape1, false>(dtype, wg_per_cu);
+    case 2:
+      return quasi ? sys_capacity<Shape2, true>(dtype, wg_per_cu)
+                   : sys_capacity<Shape2, false>(dtype, wg_per_cu);
+    default:
+      return quasi ? sys_capacity<Shape0, true>(dtype, wg_per_cu)
+                   : sys_capacity<Shape0, false>(dtype, wg_per_cu);
   }
 }
 
 hipError_t launch_gt_reduce(const double* gpart, const SysDesc* sys, int64_t nsys,
-                            int64_t nparts, int varlen, double* gt, hipStream_t st) {
+                            int64_t nparts, int varlen, int ncomp, double* gt, hipStream_t st) {
   const unsigned grid = varlen ? (unsigned)((nsys + kGridNT - 1) / kGridNT) : 1u;
   hipLaunchKernelGGL(k_gt_reduce, dim3(grid), dim3(kGridNT), 0, st, gpart, sys, nsys, nparts,
-                     varlen, gt);
+                     varlen, ncomp, gt);
   return hipGetLastError();
 }
 

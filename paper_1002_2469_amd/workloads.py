@@ -73,6 +73,16 @@ def sov_batch(seed: int = 0, s: int = 2048, n_min: int = 256, n_max: int = 65536
                 t_m1=np.ones(s), t_0=t0, t_1=np.ones(s), F=F)
 
 
+def sov_neumann_batch(seed: int = 0, s: int = 2048, n_min: int = 256,
+                      n_max: int = 65536) -> dict:
+    """The separation-of-variables batch with Neumann ends in the solved
+    direction: the mirrored ghost value adds t_-1 = 1 to the first and t_1 = 1
+    to the last diagonal entry, a quasi-Toeplitz matrix with psi = chi = 1."""
+    d = sov_batch(seed, s, n_min, n_max)
+    d.update(name="sov_neumann_batch", psi=np.ones(s), chi=np.ones(s))
+    return d
+
+
 def diff_batch(seed: int = 0, s: int = 1024, n: int = 16384) -> dict:
     rng = np.random.default_rng(seed)
     t0 = rng.uniform(2.5, 4.0, size=s)

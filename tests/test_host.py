@@ -76,6 +76,20 @@ def test_segment_merge_is_the_union_summary(t, n1, n2):
     assert np.allclose(merged, whole, rtol=1e-11, atol=1e-12)
 
 
+def test_empty_segment_is_the_merge_identity():
+    """The segment of no rows (first row = the value right of it, last row =
+    the value left of it: (0, 0, 0, 1, 1, 0)) leaves any segment unchanged on
+    either side; the interface pass gives it to threads with no tiles, so that
+    outside values pass through them."""
+    rng = np.random.default_rng(11)
+    E = np.array([0.0, 0.0, 0.0, 1.0, 1.0, 0.0])
+    for _ in range(20):
+        s = rng.standard_normal(6) * 0.5
+        assert np.array_equal(tdt.segment_merge(s, E), s)
+        assert np.array_equal(tdt.segment_merge(E, s), s)
+    assert np.array_equal(tdt.segment_merge(E, E), E)
+
+
 def test_merge_associativity():
     a, b, c = -0.9, 2.5, -1.1
     rng = np.random.default_rng(5)
@@ -104,6 +118,19 @@ def test_argument_validation_without_device():
     assert L.tdt_plan_reserve(None, 1) == _lib.TDT_ERR_INVALID_ARG
     assert L.tdt_plan_destroy(None) == _lib.TDT_ERR_INVALID_ARG
     assert L.tdt_last_info(None, None, None, None, None) == _lib.TDT_ERR_INVALID_ARG
+    # quasi-Toeplitz plans: N >= 3, finite corner terms, both corner arrays
+    assert L.tdt_plan_quasi_create(-1.0, 4.0, -1.0, 0.5, 0.5, 2, 0, ctypes.byref(h)) == \
+        _lib.TDT_ERR_INVALID_ARG
+    assert L.tdt_plan_quasi_create(-1.0, 4.0, -1.0, float("inf"), 0.5, 10, 0,
+                                   ctypes.byref(h)) == _lib.TDT_ERR_INVALID_ARG
+    assert L.tdt_plan_quasi_create(-1.0, 4.0, -1.0, 0.5, float("nan"), 10, 0,
+                                   ctypes.byref(h)) == _lib.TDT_ERR_INVALID_ARG
+    offq = np.array([0, 5, 7], dtype=np.int64)     # a system of 2 rows
+    assert L.tdt_plan_varlen_quasi_create(2, p(offq), p(t3), p(t3), p(t3), p(t3), p(t3), 0,
+                                          ctypes.byref(h)) == _lib.TDT_ERR_INVALID_ARG
+    offq = np.array([0, 5, 8], dtype=np.int64)
+    assert L.tdt_plan_varlen_quasi_create(2, p(offq), p(t3), p(t3), p(t3), None, p(t3), 0,
+                                          ctypes.byref(h)) == _lib.TDT_ERR_INVALID_ARG
     out = np.empty(4 * 3 + 4)
     assert L.tdt_block_constants(1.0, 0.0, 1.0, 3, p(out)) == _lib.TDT_ERR_SINGULAR
     assert L.tdt_block_constants(1.0, 2.0, 1.0, 65, p(out)) == _lib.TDT_ERR_INVALID_ARG
