@@ -51,8 +51,11 @@ def _bind(path: str):
     lib.oracle_adjoint.argtypes = [d, d, d, d, d, i64, i64, p, p, p, p, i32]
     lib.oracle_adjoint_varlen.argtypes = [i64, p, p, p, p, p, p, p, p, p, p, i32]
     lib.oracle_threads.argtypes = [i32]
+    lib.oracle_solve_general.argtypes = [p, p, p, i64, i64, p, p, i32, i32]
+    lib.oracle_adjoint_general.argtypes = [p, p, p, i64, i64, p, p, p, p, p, p, i32]
     for f in (lib.oracle_solve, lib.oracle_solve_varlen, lib.oracle_adjoint,
-              lib.oracle_adjoint_varlen, lib.oracle_threads):
+              lib.oracle_adjoint_varlen, lib.oracle_threads, lib.oracle_solve_general,
+              lib.oracle_adjoint_general):
         f.restype = i32
     return lib
 
@@ -169,6 +172,37 @@ class Oracle:
         return gF, (gt if corners else gt[:, :3])
 
 
+    def solve_general(self, F, a, b, c, precision: str = "f64", nthreads: int = 0):
+        """X = A^{-1} F for the general tridiagonal A with rows (a_i, b_i, c_i)
+        (a_0 and c_{N-1} unused).  F is [N] or [M, N]."""
+        F = _f64(F)
+        squeeze = F.ndim == 1
+        F2 = F.reshape(1, -1) if squeeze else F
+        M, N = F2.shape
+        av, bv, cv = (_f64(np.broadcast_to(v, (N,))) for v in (a, b, c))
+        X = np.empty_like(F2)
+        prec = {"f64": 0, "ld": 1}[precision]
+        _check(self.lib.oracle_solve_general(_ptr(av), _ptr(bv), _ptr(cv), N, M, _ptr(F2),
+                                             _ptr(X), prec, int(nthreads)))
+        return X.reshape(-1) if squeeze else X
+
+    def adjoint_general(self, gX, X, a, b, c, nthreads: int = 0):
+        """Returns (gF, (dL/da, dL/db, dL/dc)) for the general matrix, the
+        entry gradients summed over the right-hand sides."""
+        gX, X = _f64(gX), _f64(X)
+        squeeze = gX.ndim == 1
+        g2 = gX.reshape(1, -1) if squeeze else gX
+        x2 = X.reshape(1, -1) if squeeze else X
+        M, N = g2.shape
+        av, bv, cv = (_f64(np.broadcast_to(v, (N,))) for v in (a, b, c))
+        gF = np.empty_like(g2)
+        ga, gb, gc = np.empty(N), np.empty(N), np.empty(N)
+        _check(self.lib.oracle_adjoint_general(_ptr(av), _ptr(bv), _ptr(cv), N, M, _ptr(g2),
+                                               _ptr(x2), _ptr(gF), _ptr(ga), _ptr(gb),
+                                               _ptr(gc), int(nthreads)))
+        return (gF.reshape(-1) if squeeze else gF), (ga, gb, gc)
+
+
 def load_library(path: str) -> Oracle:
     """Bind a separately compiled copy of the oracle source (used by the tests
     that plant a mistake in the oracle to show that the pins catch it)."""
@@ -181,6 +215,8 @@ solve = _default.solve
 solve_varlen = _default.solve_varlen
 adjoint = _default.adjoint
 adjoint_varlen = _default.adjoint_varlen
+solve_general = _default.solve_general
+adjoint_general = _default.adjoint_general
 
 
 def rel_err(x, ref) -> float:

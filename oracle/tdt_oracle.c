@@ -44,6 +44,17 @@
  * which follows from dX = -T^{-1} dT X.  The transposed solve is the paper's
  * remark in Sec. 2.3 that (A^T)^{-1} = (A^{-1})^T.  Sums are accumulated in
  * long double over all entries and right-hand sides.
+ *
+ * General tridiagonal matrices (the series of eq. (2) with a matrix whose
+ * entries vary by row; the preliminary step of Sec. 2.3 is written for any
+ * such A): row i reads a_i x_{i-1} + b_i x_i + c_i x_{i+1} = f_i, with a_1 and
+ * c_N unused.  The recurrence is the one above with each row's own entries:
+ *   u_1 = b_1,  u_i = b_i - a_i c'_{i-1},  c'_i = c_i / u_i,
+ *   d'_i = (f_i - a_i d'_{i-1}) / u_i,  x_i = d'_i - c'_i x_{i+1}.
+ * Its adjoint is the same solve with A^T (sub-diagonal c_{i-1}, super-diagonal
+ * a_{i+1}) and the entry gradients, summed over the right-hand sides,
+ *   dL/da_i = - sum gF_i x_{i-1},  dL/db_i = - sum gF_i x_i,
+ *   dL/dc_i = - sum gF_i x_{i+1}   (0 for the unused a_1 and c_N).
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -276,6 +287,113 @@ int oracle_adjoint_varlen(int64_t S, const int64_t *offsets, const double *tm1,
         gt[5 * s + 2] = (double)(-s_p1);
         gt[5 * s + 3] = (double)(-((long double)g[0] * x[0]));
         gt[5 * s + 4] = (double)(-((long double)g[n - 1] * x[n - 1]));
+    }
+    return 0;
+}
+
+/* ---- general tridiagonal matrix -------------------------------------------- */
+static int thomas_gen_f64(const double *a, const double *b, const double *c, int64_t n,
+                          const double *f, double *x, double *cp)
+{
+    double u = b[0];
+    if (u == 0.0) return 1;
+    cp[0] = c[0] / u;
+    x[0] = f[0] / u;
+    for (int64_t i = 1; i < n; ++i) {
+        u = b[i] - a[i] * cp[i - 1];
+        if (u == 0.0) return 1;
+        cp[i] = c[i] / u;
+        x[i] = (f[i] - a[i] * x[i - 1]) / u;
+    }
+    for (int64_t i = n - 2; i >= 0; --i)
+        x[i] = x[i] - cp[i] * x[i + 1];
+    return 0;
+}
+
+/* the same in long double, rounded to double at the end; work: 2*n */
+static int thomas_gen_ld(const double *a, const double *b, const double *c, int64_t n,
+                         const double *f, double *xout, long double *work)
+{
+    long double *x = work, *cp = work + n;
+    long double u = (long double)b[0];
+    if (u == 0.0L) return 1;
+    cp[0] = (long double)c[0] / u;
+    x[0] = (long double)f[0] / u;
+    for (int64_t i = 1; i < n; ++i) {
+        u = (long double)b[i] - (long double)a[i] * cp[i - 1];
+        if (u == 0.0L) return 1;
+        cp[i] = (long double)c[i] / u;
+        x[i] = ((long double)f[i] - (long double)a[i] * x[i - 1]) / u;
+    }
+    for (int64_t i = n - 2; i >= 0; --i)
+        x[i] = x[i] - cp[i] * x[i + 1];
+    for (int64_t i = 0; i < n; ++i) xout[i] = (double)x[i];
+    return 0;
+}
+
+/* X = A^{-1} F for M right-hand sides ([M][N]) sharing the general matrix
+ * with rows (a_i, b_i, c_i); precision and status as oracle_solve. */
+int oracle_solve_general(const double *a, const double *b, const double *c, int64_t N,
+                         int64_t M, const double *F, double *X, int precision, int nthreads)
+{
+    if (N < 1 || M < 1 || !a || !b || !c || !F || !X || (precision != 0 && precision != 1))
+        return 3;
+    set_threads(nthreads);
+    int status = 0;
+#pragma omp parallel
+    {
+        void *work = precision == 1 ? malloc((size_t)(2 * N) * sizeof(long double))
+                                    : malloc((size_t)N * sizeof(double));
+        int local = work ? 0 : 2;
+#pragma omp for schedule(static)
+        for (int64_t m = 0; m < M; ++m) {
+            if (local == 2) continue;
+            int st = precision == 1
+                ? thomas_gen_ld(a, b, c, N, F + m * N, X + m * N, (long double *)work)
+                : thomas_gen_f64(a, b, c, N, F + m * N, X + m * N, (double *)work);
+            if (st > local) local = st;
+        }
+#pragma omp critical
+        { if (local > status) status = local; }
+        free(work);
+    }
+    return status;
+}
+
+/* Adjoint for the general matrix: gF = A^{-T} gX ([M][N]) and the entry
+ * gradients ga, gb, gc ([N] each) summed over the right-hand sides. */
+int oracle_adjoint_general(const double *a, const double *b, const double *c, int64_t N,
+                           int64_t M, const double *gX, const double *X, double *gF,
+                           double *ga, double *gb, double *gc, int nthreads)
+{
+    if (N < 1 || M < 1 || !a || !b || !c || !gX || !X || !gF || !ga || !gb || !gc) return 3;
+    double *at = malloc((size_t)N * sizeof(double)), *ct = malloc((size_t)N * sizeof(double));
+    if (!at || !ct) {
+        free(at);
+        free(ct);
+        return 2;
+    }
+    /* A^T: row i has c_{i-1} left of the diagonal and a_{i+1} right of it */
+    for (int64_t i = 0; i < N; ++i) {
+        at[i] = i > 0 ? c[i - 1] : 0.0;
+        ct[i] = i + 1 < N ? a[i + 1] : 0.0;
+    }
+    int st = oracle_solve_general(at, b, ct, N, M, gX, gF, 0, nthreads);
+    free(at);
+    free(ct);
+    if (st) return st;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+        long double sa = 0.0L, sb = 0.0L, sc = 0.0L;
+        for (int64_t m = 0; m < M; ++m) {
+            const double *g = gF + m * N, *x = X + m * N;
+            sb += (long double)g[i] * x[i];
+            if (i > 0) sa += (long double)g[i] * x[i - 1];
+            if (i + 1 < N) sc += (long double)g[i] * x[i + 1];
+        }
+        ga[i] = (double)(-sa);
+        gb[i] = (double)(-sb);
+        gc[i] = (double)(-sc);
     }
     return 0;
 }

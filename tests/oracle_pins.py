@@ -378,5 +378,107 @@ def pin_quasi(orc, seed=10):
         assert np.allclose(gFp[sl], g1, rtol=1e-15, atol=0) and np.allclose(gtp[s], t1s)
 
 
+def dense_general(a, b, c):
+    """Dense tridiagonal matrix with rows (a_i, b_i, c_i); a_0, c_{N-1} unused."""
+    n = len(b)
+    A = np.diag(np.asarray(b, dtype=float))
+    if n > 1:
+        A += np.diag(np.asarray(a[1:], dtype=float), -1) + np.diag(np.asarray(c[:-1], dtype=float), 1)
+    return A
+
+
+def random_rows(rng, n, ratio_lo=1.0, ratio_hi=3.0):
+    """Rows whose |b_i| / (|a_i| + |c_i|) lies in [ratio_lo, ratio_hi], entries
+    of both signs."""
+    a = rng.uniform(0.2, 1.0, n) * rng.choice([-1.0, 1.0], n)
+    c = rng.uniform(0.2, 1.0, n) * rng.choice([-1.0, 1.0], n)
+    b = rng.uniform(ratio_lo, ratio_hi, n) * (np.abs(a) + np.abs(c)) * rng.choice([-1.0, 1.0], n)
+    return a, b, c
+
+
+def pin_general(orc, seed=11):
+    """General tridiagonal matrices (per-row entries): dense elimination,
+    N = 1 and 2 in closed form, a manufactured solution, zero off-diagonals,
+    constant rows against the Toeplitz solve, a nearly singular case against
+    mpmath for the long double variant, and the adjoint against the dense
+    transposed solve and central differences of every entry class."""
+    rng = np.random.default_rng(seed)
+    for n in (1, 2, 3, 7, 16, 40, 64):
+        for _ in range(4):
+            a, b, c = random_rows(rng, n)
+            F = rng.standard_normal((3, n))
+            X = orc.solve_general(F, a, b, c)
+            ref = np.linalg.solve(dense_general(a, b, c), F.T).T
+            assert _relerr(X, ref) < 1e-13, (n, _relerr(X, ref))
+    # N = 1, N = 2
+    assert orc.solve_general(np.array([0.7]), [0.3], [-2.0], [0.9])[0] == 0.7 / -2.0
+    a, b, c = [0.0, -0.6], [2.1, 1.7], [0.8, 0.0]
+    f = np.array([0.7, -1.3])
+    d = b[0] * b[1] - c[0] * a[1]
+    x2 = np.array([b[1] * f[0] - c[0] * f[1], -a[1] * f[0] + b[0] * f[1]]) / d
+    assert _relerr(orc.solve_general(f, a, b, c), x2) < 1e-15
+    # manufactured solution
+    a, b, c = random_rows(rng, 500, 1.2, 2.5)
+    Xs = rng.uniform(-1, 1, (2, 500))
+    F = (dense_general(a, b, c) @ Xs.T).T
+    assert _relerr(orc.solve_general(F, a, b, c), Xs) < 1e-13
+    # zero off-diagonals: x = f / b exactly
+    b = rng.uniform(0.5, 2.0, 50) * rng.choice([-1.0, 1.0], 50)
+    F = rng.standard_normal(50)
+    assert np.array_equal(orc.solve_general(F, np.zeros(50), b, np.zeros(50)), F / b)
+    # constant rows: the Toeplitz solve (same recurrence, bit for bit)
+    F = rng.standard_normal((2, 300))
+    assert np.array_equal(orc.solve_general(F, np.full(300, -0.8), np.full(300, 2.6),
+                                            np.full(300, 1.1)),
+                          orc.solve(F, -0.8, 2.6, 1.1))
+    # long double: a nearly singular nonsymmetric matrix against mpmath
+    n = 24
+    a, b, c = random_rows(rng, n, 1.0, 1.5)
+    A = dense_general(a, b, c)
+    lam = np.linalg.eigvals(A)
+    b = b - lam[np.argmin(np.abs(lam))].real + 1e-7     # shift next to an eigenvalue
+    A = dense_general(a, b, c)
+    g = rng.standard_normal(n)
+    with mpmath.workdps(50):
+        ref = np.array([float(v) for v in mpmath.lu_solve(mpmath.matrix(A.tolist()),
+                                                          mpmath.matrix(g.tolist()))])
+    e_ld = _relerr(orc.solve_general(g, a, b, c, precision="ld"), ref)
+    e_64 = _relerr(orc.solve_general(g, a, b, c), ref)
+    assert e_ld < 1e-11 and e_ld < e_64 / 100.0, (e_ld, e_64)
+    # adjoint
+    n, m = 30, 2
+    a, b, c = random_rows(rng, n, 1.2, 2.5)
+    F = rng.standard_normal((m, n))
+    W = rng.standard_normal((m, n))
+    X = orc.solve_general(F, a, b, c)
+    gF, (ga, gb, gc) = orc.adjoint_general(W, X, a, b, c)
+    A = dense_general(a, b, c)
+    assert _relerr(gF, np.linalg.solve(A.T, W.T).T) < 1e-13
+    assert ga[0] == 0.0 and gc[-1] == 0.0
+    h = 1e-6
+
+    def loss(a_, b_, c_):
+        return float(np.sum(W * np.linalg.solve(dense_general(a_, b_, c_), F.T).T))
+
+    for i in (1, 7, n - 1):
+        ap, am = a.copy(), a.copy()
+        ap[i] += h
+        am[i] -= h
+        fd = (loss(ap, b, c) - loss(am, b, c)) / (2 * h)
+        assert abs(fd - ga[i]) <= 1e-6 * max(1.0, abs(fd)), ("a", i, fd, ga[i])
+    for i in (0, 11, n - 1):
+        bp, bm = b.copy(), b.copy()
+        bp[i] += h
+        bm[i] -= h
+        fd = (loss(a, bp, c) - loss(a, bm, c)) / (2 * h)
+        assert abs(fd - gb[i]) <= 1e-6 * max(1.0, abs(fd)), ("b", i, fd, gb[i])
+    for i in (0, 13, n - 2):
+        cp, cm = c.copy(), c.copy()
+        cp[i] += h
+        cm[i] -= h
+        fd = (loss(a, b, cp) - loss(a, b, cm)) / (2 * h)
+        assert abs(fd - gc[i]) <= 1e-6 * max(1.0, abs(fd)), ("c", i, fd, gc[i])
+
+
 ALL_PINS = [pin_dense_ge, pin_eigenpairs, pin_theorem1, pin_chebyshev, pin_manufactured,
-            pin_special, pin_long_double, pin_adjoint, pin_quasi]
+            pin_special, pin_long_double, pin_adjoint, pin_quasi, pin_general]

@@ -48,6 +48,21 @@ MUTANTS = {
     "adjoint_gpsi_index": ("s_ps += (long double)g[0] * x[0];",
                            "s_ps += (long double)g[0] * x[1];"),
     "adjoint_gchi_sign": ("gt[4] = (double)(-s_ch);", "gt[4] = (double)(s_ch);"),
+    # general tridiagonal matrices
+    "gen_forward_sign": ("x[i] = (f[i] - a[i] * x[i - 1]) / u;",
+                         "x[i] = (f[i] + a[i] * x[i - 1]) / u;"),
+    "gen_pivot_row": ("u = b[i] - a[i] * cp[i - 1];", "u = b[i] - a[i - 1] * cp[i - 1];"),
+    "gen_cp_transposed": ("cp[i] = c[i] / u;", "cp[i] = a[i] / u;"),
+    "gen_backsub_dropped": ("x[i] = x[i] - cp[i] * x[i + 1];\n    return 0;\n}\n\n/* the same in long",
+                            "x[i] = x[i];\n    return 0;\n}\n\n/* the same in long"),
+    "gen_ld_pivot_rounded": (
+        "u = (long double)b[i] - (long double)a[i] * cp[i - 1];",
+        "u = (double)((long double)b[i] - (long double)a[i] * cp[i - 1]);"),
+    "gen_adjoint_not_transposed": ("at[i] = i > 0 ? c[i - 1] : 0.0;",
+                                   "at[i] = i > 0 ? a[i] : 0.0;"),
+    "gen_adjoint_ga_index": ("if (i > 0) sa += (long double)g[i] * x[i - 1];",
+                             "if (i > 0) sa += (long double)g[i - 1] * x[i];"),
+    "gen_adjoint_gc_sign": ("gc[i] = (double)(-sc);", "gc[i] = (double)(sc);"),
 }
 
 
