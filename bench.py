@@ -15,7 +15,8 @@ N_k log-uniform in [256, 65536], each with its own t_0; one step is a replay
 of the solve captured in a hipGraph), `sov_neumann` (the same batch with
 Neumann ends: quasi-Toeplitz systems with psi = chi = 1) and `diff` (1024
 systems of N = 16384 with their own T; a step is the forward solve plus the
-adjoint backward pass).
+adjoint backward pass) and `general` (64 right-hand sides of N = 2**20 sharing a
+general tridiagonal matrix with per-row entries; paths f64 and f32).
 
 Prints one JSON line.  `roofline` is for the kernel with the longest average
 duration in the headline path, from HIP events recorded on the solve stream
@@ -43,7 +44,7 @@ if ROOT not in sys.path:
 
 METRIC = "unknowns/s + HBM GB/s (% peak): FP32+refine vs FP64 solve at rel err ≤1e-12"
 HBM_PEAK_GBS = 8000.0
-WORKLOADS = ("single_large", "series", "sov", "sov_neumann", "diff")
+WORKLOADS = ("single_large", "series", "sov", "sov_neumann", "diff", "general")
 
 
 def kernel_source_hash() -> str:
@@ -105,6 +106,12 @@ def load_workload(name: str, args):
                       f"ends (quasi-Toeplitz, psi=chi=1), N_k log-uniform in [256, 65536] "
                       f"(sum {int(d['offsets'][-1])}), t_+-1=1, own t_0, F~N(0,1) seed 0, "
                       f"packed, solve replayed from a hipGraph")
+    elif name == "general":
+        d = W.general_series(seed=0)
+        d.update(kind="general", units=d["N"] * d["M"],
+                 desc=f"general: M={d['M']} right-hand sides of N={d['N']} sharing a general "
+                      f"tridiagonal matrix (variable-coefficient diffusion-reaction rows, "
+                      f"dominance 1.1-1.6), F~N(0,1) seed 0, [M][N] double in/out")
     elif name == "diff":
         d = W.diff_batch(seed=0)
         d.update(kind="varlen", units=int(d["offsets"][-1]), adjoint=True,
@@ -116,6 +123,8 @@ def load_workload(name: str, args):
 
 
 def make_plan(tdt, d, mode):
+    if d["kind"] == "general":
+        return tdt.GeneralPlan(d["a"], d["b"], d["c"], mode)
     if d["kind"] == "series":
         return tdt.Plan(d["t_m1"], d["t_0"], d["t_1"], d["N"], mode)
     return tdt.VarlenPlan(d["offsets"], d["t_m1"], d["t_0"], d["t_1"], mode,
@@ -125,7 +134,7 @@ def make_plan(tdt, d, mode):
 def tile_counts(d, tile):
     """Unknowns that go through the first pass (systems of more than one
     tile of `tile` rows) and through the final pass (all)."""
-    if d["kind"] == "series":
+    if d["kind"] in ("series", "general"):
         multi = d["N"] > tile
         return (d["N"] * d["M"] if multi else 0), d["N"] * d["M"]
     sizes = d["offsets"][1:] - d["offsets"][:-1]
@@ -215,14 +224,16 @@ def cpu_leg(d, budget_s=12.0):
     """Time the oracle on this host (same inputs) and return its outputs."""
     import numpy as np
     import oracle
-    single = d["kind"] == "series" and d["M"] == 1
+    single = d["kind"] in ("series", "general") and d["M"] == 1
     nthreads = 1 if single else 0
     threads = oracle.threads(1 if single else 0)
     times, Xo, gFo, gto = [], None, None, None
     t_budget = time.perf_counter()
     while len(times) < 25 and (time.perf_counter() - t_budget < budget_s or len(times) < 3):
         t0 = time.perf_counter()
-        if d["kind"] == "series":
+        if d["kind"] == "general":
+            Xo = oracle.solve_general(d["F"], d["a"], d["b"], d["c"], nthreads=nthreads)
+        elif d["kind"] == "series":
             Xo = oracle.solve(d["F"], d["t_m1"], d["t_0"], d["t_1"], nthreads=nthreads)
         else:
             Xo = oracle.solve_varlen(d["F"].reshape(-1), d["offsets"], d["t_m1"], d["t_0"],
@@ -247,7 +258,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="single_large", choices=WORKLOADS)
     ap.add_argument("--n", type=int, default=1 << 26, help="single_large: system order")
-    ap.add_argument("--modes", default="f32_refine,f64")
+    ap.add_argument("--modes", default=None,
+                    help="paths to time, first = headline (default f32_refine,f64; "
+                         "f64,f32 for the general workload)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain device copy of F (counter calibration)")
@@ -269,10 +282,14 @@ def main() -> int:
     F = torch.from_numpy(np.ascontiguousarray(d["F"]).reshape(-1)).to("cuda:0")
     X = torch.empty_like(F)
     torch.cuda.synchronize()
+    if args.modes is None:
+        args.modes = "f64,f32" if args.workload == "general" else "f32_refine,f64"
     modes = [m for m in args.modes.split(",") if m]
     res = {}
     for mode in modes:
-        res[mode] = run_mode(tdt, d, F, X, mode, args.steps, args.warmup, torch,
+        Fm = F.float() if mode == "f32" else F      # plain float takes float data
+        Xm = torch.empty_like(Fm) if mode == "f32" else X
+        res[mode] = run_mode(tdt, d, Fm, Xm, mode, args.steps, args.warmup, torch,
                              autotune=not args.no_autotune)
         print(f"[bench] {args.workload} {mode}: {res[mode]['ms']:.4f} ms/step  kernels(ms) "
               f"{json.dumps({k: round(v, 5) for k, v in res[mode]['kernels_ms'].items()})}",
@@ -295,8 +312,12 @@ def main() -> int:
                   "bwd_first_pass": 8.0 * n_first, "bwd_final_pass": 24.0 * n_final}
     names = {"first_pass": ("k_beta<double> (Green-row tile summaries, first pass)"
                             if d["kind"] == "series" else
+                            "k_gtile<double, SUMMARY> (general matrix, tile summaries)"
+                            if d["kind"] == "general" else
                             "k_tile<double, *, SUMMARY> (tile summaries, first pass)"),
-             "final_pass": ("k_tile<double, float, REFINE, final> (solve, refine and store)"
+             "final_pass": ("k_gtile<double, final> (general matrix: solve and store)"
+                            if d["kind"] == "general" else
+                            "k_tile<double, float, REFINE, final> (solve, refine and store)"
                             if head == "f32_refine" else "k_tile<double, double, final> (solve and store)"),
              "bwd_first_pass": "k_tile<double, *, SUMMARY> on T^T (adjoint first pass)",
              "bwd_final_pass": "k_tile<..., BWD> (adjoint solve, store gF, dL/dt partial sums)"}
@@ -307,7 +328,7 @@ def main() -> int:
         cpu, Xo, gFo, gto = cpu_leg(d)
         import oracle
         for mode in modes:
-            if d["kind"] == "series":
+            if d["kind"] in ("series", "general"):
                 e = float(np.max(oracle.rel_err_rows(res[mode]["X"].reshape(d["M"], d["N"]),
                                                      Xo.reshape(d["M"], d["N"]))))
             else:

@@ -111,6 +111,29 @@ tdt_status_t tdt_plan_varlen_quasi_create(int64_t S, const int64_t *h_offsets,
                                           const double *h_chi, tdt_dtype_t dtype,
                                           tdt_plan_t *out);
 
+/* Plan for a general tridiagonal matrix A of order N: row i reads
+ *     a_i x_{i-1} + b_i x_i + c_i x_{i+1} = f_i     (a_0 and c_{N-1} unused),
+ * for series of right-hand sides sharing A (eq. (2) with any A; the
+ * preliminary step of Sec. 2.3 is written for such A, and its O(N) cost is
+ * paid once per A).  h_a, h_b, h_c: host arrays of N doubles, copied.  The
+ * plan computes, in long double, the LU of every B-row block, every block's
+ * responses to unit outside values and the end values of every tile, for A
+ * and for A^T; the device holds 3 values per row and 5 per block in the
+ * compute precision, plus 4 per tile.  dtype: TDT_F64 or TDT_F32
+ * (TDT_F32_REFINE -> TDT_ERR_INVALID_ARG).  Solve with tdt_solve (F, X:
+ * [M][N]).  tdt_solve_backward solves A^T gF = gX and, if d_gt is not NULL,
+ * writes 3*N doubles: d_gt[i] = dL/da_i, d_gt[N+i] = dL/db_i, d_gt[2N+i] =
+ * dL/dc_i, each summed over the M right-hand sides (0 for a_0 and c_{N-1}).
+ * The plan is built for work shape 1 (8 rows x 512 lanes); TDT_OPT_SHAPE
+ * accepts only that.  Errors: N < 1, null arrays, non-finite entries ->
+ * TDT_ERR_INVALID_ARG; a zero block pivot or a vanishing interface pivot ->
+ * TDT_ERR_SINGULAR.  The dominance ratio is min_i |b_i|/(|a_i|+|c_i|);
+ * kappa2 is the bound sqrt(kappa_1 kappa_inf) from strict row and column
+ * dominance (infinite without it). */
+tdt_status_t tdt_plan_general_create(int64_t N, const double *h_a, const double *h_b,
+                                     const double *h_c, tdt_dtype_t dtype,
+                                     tdt_plan_t *out);
+
 /* Allocate the workspace for up to M_max right-hand sides now, so that later
  * solves allocate nothing and may be captured in a hipGraph.  Blocking. */
 tdt_status_t tdt_plan_reserve(tdt_plan_t plan, int64_t M_max);

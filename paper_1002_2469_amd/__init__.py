@@ -283,6 +283,54 @@ class VarlenPlan(_PlanBase):
         return gF, gt
 
 
+class GeneralPlan(_PlanBase):
+    """Plan of a general tridiagonal matrix of order N (row i: a_i x_{i-1} +
+    b_i x_i + c_i x_{i+1} = f_i; a_0 and c_{N-1} unused) for series of
+    right-hand sides sharing it.  dtype: 'f64' or 'f32'."""
+
+    def __init__(self, a, b, c, dtype: str = "f64"):
+        super().__init__()
+        if dtype not in ("f64", "f32"):
+            raise ValueError("dtype must be 'f64' or 'f32' for a general matrix")
+        self.b = np.ascontiguousarray(b, dtype=np.float64)
+        self.N = int(self.b.size)
+        self.a = np.ascontiguousarray(np.broadcast_to(np.asarray(a, dtype=np.float64),
+                                                      (self.N,)))
+        self.c = np.ascontiguousarray(np.broadcast_to(np.asarray(c, dtype=np.float64),
+                                                      (self.N,)))
+        self.dtype = dtype
+        self.status = _lib.check(_lib.lib().tdt_plan_general_create(
+            self.N, self.a.ctypes.data_as(ctypes.c_void_p),
+            self.b.ctypes.data_as(ctypes.c_void_p), self.c.ctypes.data_as(ctypes.c_void_p),
+            DTYPES[dtype], ctypes.byref(self._h)), "tdt_plan_general_create")
+
+    def solve(self, F, X=None, stream=None):
+        return Plan.solve(self, F, X, stream)
+
+    def autotune(self, F, X=None, cache=True, force=False, stream=None) -> dict:
+        return Plan.autotune(self, F, X, cache, force, stream)
+
+    def backward(self, gX, X, gF=None, g=None, stream=None):
+        """gF = A^{-T} gX and g = [3][N]: (dL/da, dL/db, dL/dc) summed over
+        the right-hand sides."""
+        torch = _torch()
+        dt = _data_dtype(self.dtype)
+        M = gX.numel() // self.N
+        _check_tensor(gX, dt, M * self.N, "gX")
+        _check_tensor(X, dt, M * self.N, "X")
+        if gF is None:
+            gF = torch.empty_like(gX)
+        if g is None:
+            g = torch.empty((3, self.N), dtype=torch.float64, device=gX.device)
+        _check_tensor(gF, dt, M * self.N, "gF")
+        _check_tensor(g, torch.float64, 3 * self.N, "g")
+        _lib.check(_lib.lib().tdt_solve_backward(
+            self._h, ctypes.c_void_p(gX.data_ptr()), ctypes.c_void_p(X.data_ptr()),
+            ctypes.c_void_p(gF.data_ptr()), ctypes.c_void_p(g.data_ptr()), M,
+            _stream_handle(stream)), "tdt_solve_backward")
+        return gF, g
+
+
 _plan_cache: dict = {}
 
 

@@ -40,6 +40,7 @@ EXPORTS = [
     "tdt_last_info", "tdt_block_constants", "tdt_green_rows", "tdt_segment_merge", "tdt_plan_profile",
     "tdt_plan_profile_read", "tdt_build_info", "tdt_plan_set_option", "tdt_plan_get_option",
     "tdt_plan_autotune", "tdt_plan_quasi_create", "tdt_plan_varlen_quasi_create",
+    "tdt_plan_general_create",
 ]
 
 # tdt_option_t
@@ -88,6 +89,7 @@ def lib():
         "tdt_plan_varlen_create": [i64, p, p, p, p, i32, pp],
         "tdt_plan_quasi_create": [d, d, d, d, d, i64, i32, pp],
         "tdt_plan_varlen_quasi_create": [i64, p, p, p, p, p, p, i32, pp],
+        "tdt_plan_general_create": [i64, p, p, p, i32, pp],
         "tdt_plan_reserve": [p, i64],
         "tdt_solve": [p, p, p, i64, p],
         "tdt_solve_varlen": [p, p, p, p],

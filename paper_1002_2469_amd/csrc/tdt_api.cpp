@@ -38,6 +38,13 @@ struct tdt_plan_s {
   std::vector<double> in_psi, in_chi;   // quasi-Toeplitz corner terms (quasi plans)
   std::vector<int64_t> in_sizes, in_offs;
   bool quasi = false;     // every system is quasi-Toeplitz (eq. (21))
+  // general (per-row) matrix of a series plan: its rows, and per direction the
+  // per-row LU and per-block constants (compute precision), per-tile end values
+  bool general = false;
+  std::vector<double> in_ga, in_gb, in_gc;
+  void* dgrow[2] = {nullptr, nullptr};
+  void* dgblk[2] = {nullptr, nullptr};
+  double* dgtK[2] = {nullptr, nullptr};
   int64_t reserved_M = 0;
   bool varlen = false;
   tdt_dtype_t dtype = TDT_F64;
@@ -430,6 +437,9 @@ void destroy(tdt_plan_s* p) {
     (void)hipFree(p->dtab32[k]);
     (void)hipFree(p->dgreen[k]);
     (void)hipFree(p->dttab[k]);
+    (void)hipFree(p->dgrow[k]);
+    (void)hipFree(p->dgblk[k]);
+    (void)hipFree(p->dgtK[k]);
   }
   (void)hipFree(p->dp1);
   (void)hipFree(p->dfin);
@@ -703,6 +713,164 @@ tdt_status_t rebuild_plan(tdt_plan_s* p, int shape) {
   return TDT_OK;
 }
 
+// ---------------------------------------------------------------------------
+// General (per-row) matrices.  The system is padded to whole tiles with
+// decoupled rows (b = 1, a = c = 0), so every tile is full.  Everything below
+// is long double, rounded once on upload.
+// ---------------------------------------------------------------------------
+template <typename Tc>
+tdt_status_t build_general_dir(tdt_plan_s* p, int dir, double& dom, double& kap) {
+  const int B = p->B, NT = p->NT;
+  const int64_t L = p->L, N = p->N;
+  const int64_t P = (N + L - 1) / L, Np = P * L;
+  // rows of the matrix being solved: A (dir 0) or A^T (dir 1)
+  std::vector<ld> a((size_t)Np, 0.0L), b((size_t)Np, 1.0L), c((size_t)Np, 0.0L);
+  for (int64_t i = 0; i < N; ++i) {
+    b[i] = p->in_gb[i];
+    if (dir == 0) {
+      a[i] = i > 0 ? p->in_ga[i] : 0.0;
+      c[i] = i + 1 < N ? p->in_gc[i] : 0.0;
+    } else {
+      a[i] = i > 0 ? p->in_gc[i - 1] : 0.0;
+      c[i] = i + 1 < N ? p->in_ga[i + 1] : 0.0;
+    }
+  }
+  if (dir == 0) {
+    // row dominance, and the 2-norm condition bound sqrt(kappa_1 kappa_inf)
+    // from strict row and column dominance (infinite without it)
+    double rmin = std::numeric_limits<double>::infinity();
+    double rex = rmin, cex = rmin, rn = 0.0, cn = 0.0;
+    for (int64_t i = 0; i < N; ++i) {
+      const double ai = std::fabs((double)a[i]), bi = std::fabs((double)b[i]);
+      const double ci = std::fabs((double)c[i]);
+      if (ai + ci > 0.0) rmin = std::min(rmin, bi / (ai + ci));
+      // column i: c_{i-1} above the diagonal, a_{i+1} below
+      const double up = i > 0 ? std::fabs((double)c[i - 1]) : 0.0;
+      const double dn = i + 1 < N ? std::fabs((double)a[i + 1]) : 0.0;
+      rex = std::min(rex, bi - ai - ci);
+      cex = std::min(cex, bi - up - dn);
+      rn = std::max(rn, bi + ai + ci);
+      cn = std::max(cn, bi + up + dn);
+    }
+    dom = rmin;
+    kap = (rex > 0.0 && cex > 0.0) ? std::sqrt((rn / rex) * (cn / cex))
+                                   : std::numeric_limits<double>::infinity();
+  }
+  std::vector<Tc> row((size_t)P * tdt::kGenRowN * L), blk((size_t)P * tdt::kGenBlkN * NT);
+  std::vector<double> tK((size_t)P * 4);
+  std::vector<ld> iu(B), aiu(B), cp(B), ph(B), ch(B);
+  for (int64_t t = 0; t < P; ++t) {
+    ld beta = 0.0L;
+    SegLD tile{0, 0, 0, 0, 0, 0};
+    for (int j = 0; j < NT; ++j) {
+      const int64_t r0 = t * L + (int64_t)j * B;
+      // block-local LU: u_0 = b, u_i = b_i - a_i c_{i-1}/u_{i-1}
+      ld u = b[r0];
+      for (int i = 0; i < B; ++i) {
+        const int64_t r = r0 + i;
+        if (i > 0) u = b[r] - a[r] * cp[i - 1];
+        if (u == 0.0L) return TDT_ERR_SINGULAR;
+        iu[i] = 1.0L / u;
+        aiu[i] = a[r] * iu[i];
+        cp[i] = c[r] * iu[i];
+      }
+      // responses to unit values just left (phi) and right (chi) of the block
+      ph[0] = -aiu[0];
+      for (int i = 1; i < B; ++i) ph[i] = -aiu[i] * ph[i - 1];
+      for (int i = B - 2; i >= 0; --i) ph[i] -= cp[i] * ph[i + 1];
+      for (int i = 0; i + 1 < B; ++i) ch[i] = 0.0L;
+      ch[B - 1] = -cp[B - 1];
+      for (int i = B - 2; i >= 0; --i) ch[i] -= cp[i] * ch[i + 1];
+      const ld pf = ph[0], pl = ph[B - 1], cf = ch[0], cl = ch[B - 1];
+      for (int i = 0; i < B; ++i) {
+        Tc* rw = row.data() + (size_t)t * tdt::kGenRowN * L + (size_t)i * NT + j;
+        rw[(size_t)tdt::kGenIU * L] = (Tc)iu[i];
+        rw[(size_t)tdt::kGenAIU * L] = (Tc)aiu[i];
+        rw[(size_t)tdt::kGenCP * L] = (Tc)cp[i];
+        if (!std::isfinite((double)iu[i]) || !std::isfinite((double)cp[i]))
+          return TDT_ERR_SINGULAR;
+      }
+      // in-tile left-to-right elimination across the blocks
+      const ld den = 1.0L - pf * beta;
+      if (!(std::fabs((double)den) > 1e-13)) return TDT_ERR_SINGULAR;
+      const ld iD = 1.0L / den;
+      Tc* bk = blk.data() + (size_t)t * tdt::kGenBlkN * NT + j;
+      bk[(size_t)tdt::kGenPF * NT] = (Tc)pf;
+      bk[(size_t)tdt::kGenPL * NT] = (Tc)pl;
+      bk[(size_t)tdt::kGenCF * NT] = (Tc)cf;
+      bk[(size_t)tdt::kGenBP * NT] = (Tc)beta;
+      bk[(size_t)tdt::kGenID * NT] = (Tc)iD;
+      beta = cl + pl * beta * cf * iD;
+      if (!std::isfinite((double)beta)) return TDT_ERR_SINGULAR;
+      // the tile's end values: its blocks merged left to right
+      const SegLD s{0, 0, pf, pl, cf, cl};
+      if (j == 0) {
+        tile = s;
+      } else {
+        SegLD mrg;
+        if (!merge_ld(tile, s, mrg)) return TDT_ERR_SINGULAR;
+        tile = mrg;
+      }
+    }
+    tK[4 * t + 0] = (double)tile.pf;
+    tK[4 * t + 1] = (double)tile.pl;
+    tK[4 * t + 2] = (double)tile.cf;
+    tK[4 * t + 3] = (double)tile.cl;
+  }
+  // the system descriptor (the interface pass and the item geometry use it)
+  SysDesc D;
+  std::memset(&D, 0, sizeof(D));
+  D.n = N;
+  D.ntiles = (int32_t)P;
+  D.stride = N;
+  const int maxp = (int)P;
+  D.tr = maxp <= 256 ? 1 : (maxp <= 2048 ? 8 : (maxp <= 16384 ? 16 : 1));
+  D.tq = (D.ntiles + D.tr - 1) / D.tr;
+  D.tslots = D.tq * D.tr;
+  p->hsys[dir].assign(1, D);
+  // interface pass across tiles: beta_{t-1}, 1/(1 - Pf_t beta_{t-1}) per tile
+  p->ttab_n = std::max<int64_t>(D.tslots, 1);
+  std::vector<double> tt(2 * (size_t)p->ttab_n, 0.0);
+  if (P > 1) {
+    ld beta = 0.0L;
+    for (int64_t t = 0; t < P; ++t) {
+      const double* K = tK.data() + 4 * t;
+      const ld den = 1.0L - (ld)K[0] * beta;
+      if (!(std::fabs((double)den) > 1e-13)) return TDT_ERR_SINGULAR;
+      const ld iD = 1.0L / den;
+      const int64_t pos = (t % D.tr) * D.tq + t / D.tr;
+      tt[pos] = (double)beta;
+      tt[p->ttab_n + pos] = (double)iD;
+      beta = (ld)K[3] + (ld)K[1] * beta * (ld)K[2] * iD;
+    }
+  }
+  tdt_status_t st = dev_upload(reinterpret_cast<Tc**>(&p->dgrow[dir]), row.data(), row.size());
+  if (st == TDT_OK) st = dev_upload(reinterpret_cast<Tc**>(&p->dgblk[dir]), blk.data(), blk.size());
+  if (st == TDT_OK) st = dev_upload(&p->dgtK[dir], tK.data(), tK.size());
+  if (st == TDT_OK) st = dev_upload(&p->dttab[dir], tt.data(), tt.size());
+  if (st == TDT_OK) st = dev_upload(&p->dsys[dir], p->hsys[dir].data(), 1);
+  return st;
+}
+
+tdt_status_t finish_general_plan(tdt_plan_s* p) {
+  double dom = 0.0, kap = 0.0;
+  for (int dir = 0; dir < 2; ++dir) {
+    const tdt_status_t st = p->dtype == TDT_F32 ? build_general_dir<float>(p, dir, dom, kap)
+                                                : build_general_dir<double>(p, dir, dom, kap);
+    if (st != TDT_OK) return st;
+  }
+  p->dominance = dom;
+  p->kappa = kap;
+  {
+    const tdt_status_t ws = ensure_workspace(p, 1, 1, nullptr);
+    if (ws != TDT_OK) return ws;
+  }
+  if (hipMalloc(&p->iters, 2 * sizeof(int)) != hipSuccess) return TDT_ERR_OOM;
+  if (hipMemset(p->iters, 0, 2 * sizeof(int)) != hipSuccess) return TDT_ERR_HIP;
+  if (hipDeviceSynchronize() != hipSuccess) return TDT_ERR_HIP;
+  return p->dominance < 1.0 ? TDT_WARN_NOT_DOMINANT : TDT_OK;
+}
+
 bool overlaps(const void* x, size_t nx, const void* y, size_t ny) {
   const uintptr_t a = reinterpret_cast<uintptr_t>(x), b = reinterpret_cast<uintptr_t>(y);
   return a < b + ny && b < a + nx;
@@ -734,8 +902,39 @@ tdt_status_t run(tdt_plan_s* p, int dir, const void* F, void* X, const void* Xfw
   L.ttab_n = p->ttab_n;
   L.max_ntiles = 1;
   for (const SysDesc& D : p->hsys[0]) L.max_ntiles = std::max(L.max_ntiles, (int)D.ntiles);
+  L.general = p->general ? 1 : 0;
+  L.gen_row = p->dgrow[dir];
+  L.gen_blk = p->dgblk[dir];
+  L.gen_tK = p->dgtK[dir];
+  L.gen_M = M;
   int64_t slots, fslots;
-  if (p->varlen) {
+  if (p->general) {
+    const SysDesc& D0 = p->hsys[0][0];
+    const int64_t nt = D0.ntiles;
+    L.green = nullptr;
+    L.p1_items = L.fin_items = nullptr;
+    L.grid_items = L.sys_items = L.sys_bins = nullptr;
+    L.n_bins = L.n_sys = 0;
+    L.n_beta = L.n_last = 0;
+    L.nfull = 0;
+    // right-hand sides per item: up to 8 share one load of a tile's
+    // constants, as long as at least 4 items per compute unit remain
+    int R = (int)std::min<int64_t>(M, 8);
+    int dev = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus < 1)
+      cus = 256;
+    while (R > 1 && nt * ((M + R - 1) / R) < 4 * (int64_t)cus) --R;
+    L.gen_R = R;
+    const int64_t groups = (M + R - 1) / R;
+    L.n_p1 = nt > 1 ? groups * nt : 0;
+    L.n_grid = nt > 1 ? M : 0;
+    L.n_fin = groups * nt;
+    L.corner0 = 0;
+    slots = nt > 1 ? M * D0.tslots : 0;
+    fslots = 0;
+  } else if (p->varlen) {
     L.green = nullptr;
     L.n_beta = L.n_last = 0;
     L.nfull = 0;
@@ -830,7 +1029,7 @@ std::string key_of(const tdt_plan_s* p, int64_t M) {
   const size_t colon = arch.find(':');
   if (colon != std::string::npos) arch.resize(colon);
   const char* dt = p->dtype == TDT_F64 ? "f64" : (p->dtype == TDT_F32 ? "f32" : "f32_refine");
-  const char* kind = p->quasi ? "q" : "";
+  const char* kind = p->quasi ? "q" : (p->general ? "g" : "");
   char buf[256];
   if (p->varlen) {
     int maxt = 1;
@@ -1043,6 +1242,39 @@ tdt_status_t tdt_plan_varlen_create(int64_t S, const int64_t* h_offsets, const d
   return create_varlen(S, h_offsets, h_tm1, h_t0, h_t1, nullptr, nullptr, dtype, out);
 }
 
+tdt_status_t tdt_plan_general_create(int64_t N, const double* h_a, const double* h_b,
+                                     const double* h_c, tdt_dtype_t dtype, tdt_plan_t* out) {
+  if (!out) return TDT_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (N < 1 || N > ((int64_t)1 << 40) || !h_a || !h_b || !h_c ||
+      (dtype != TDT_F64 && dtype != TDT_F32))
+    return TDT_ERR_INVALID_ARG;
+  for (int64_t i = 0; i < N; ++i)
+    if (!std::isfinite(h_b[i]) || (i > 0 && !std::isfinite(h_a[i])) ||
+        (i + 1 < N && !std::isfinite(h_c[i])))
+      return TDT_ERR_INVALID_ARG;
+  tdt_plan_s* p = new (std::nothrow) tdt_plan_s();
+  if (!p) return TDT_ERR_OOM;
+  p->general = true;
+  p->dtype = dtype;
+  p->N = N;
+  p->S = 1;
+  p->shape = tdt::kGeneralShape;
+  p->B = tdt::kShapes[p->shape].B;
+  p->NT = tdt::kShapes[p->shape].NT;
+  p->L = (int64_t)p->B * p->NT;
+  p->in_ga.assign(h_a, h_a + N);
+  p->in_gb.assign(h_b, h_b + N);
+  p->in_gc.assign(h_c, h_c + N);
+  tdt_status_t st = finish_general_plan(p);
+  if (st < 0) {
+    destroy(p);
+    return st;
+  }
+  *out = p;
+  return st;
+}
+
 tdt_status_t tdt_plan_varlen_quasi_create(int64_t S, const int64_t* h_offsets,
                                           const double* h_tm1, const double* h_t0,
                                           const double* h_t1, const double* h_psi,
@@ -1059,7 +1291,10 @@ tdt_status_t tdt_plan_reserve(tdt_plan_t p, int64_t M_max) {
   if (!p || M_max < 1) return TDT_ERR_INVALID_ARG;
   p->reserved_M = std::max(p->reserved_M, M_max);
   int64_t slots, fslots;
-  if (p->varlen) {
+  if (p->general) {
+    slots = p->hsys[0][0].ntiles > 1 ? M_max * p->hsys[0][0].tslots : 0;
+    fslots = 0;
+  } else if (p->varlen) {
     slots = p->vslots;
     fslots = p->vfslots;
   } else {
@@ -1091,6 +1326,15 @@ tdt_status_t tdt_solve_backward(tdt_plan_t p, const void* gX, const void* X, voi
   const size_t bytes =
       (size_t)(p->varlen ? p->total : M * p->N) * elem_size(p->dtype);
   if (overlaps(gF, bytes, gX, bytes) || overlaps(gF, bytes, X, bytes)) return TDT_ERR_INVALID_ARG;
+  if (p->general) {
+    // gF = A^{-T} gX, then the entry gradients from gF and X
+    tdt_status_t st = run(p, 1, gX, gF, nullptr, M, stream);
+    if (st != TDT_OK) return st;
+    if (d_gt && tdt::launch_general_grad(p->dtype == TDT_F32 ? 1 : 0, gF, X, p->N, M, d_gt,
+                                         stream) != hipSuccess)
+      return TDT_ERR_HIP;
+    return TDT_OK;
+  }
   tdt_status_t st = run(p, 1, gX, gF, X, M, stream);
   if (st != TDT_OK) return st;
   if (d_gt) {
@@ -1154,6 +1398,7 @@ tdt_status_t tdt_plan_set_option(tdt_plan_t p, tdt_option_t opt, int64_t value) 
     case TDT_OPT_SHAPE:
       if (value < 0 || value >= tdt::kNumShapes) return TDT_ERR_INVALID_ARG;
       if ((int)value == p->shape) return TDT_OK;
+      if (p->general) return TDT_ERR_INVALID_ARG;   // built for kGeneralShape only
       return rebuild_plan(p, (int)value);
   }
   return TDT_ERR_INVALID_ARG;
@@ -1192,6 +1437,7 @@ tdt_status_t tdt_plan_autotune(tdt_plan_t p, const void* F, void* X, int64_t M,
   const int whole[] = {0, 1, 2, 4, 8, 16};
   for (int sh = 0; sh < tdt::kNumShapes; ++sh)
     for (int wpc : {0, 1}) {
+      if (p->general && sh != tdt::kGeneralShape) continue;
       if (p->varlen)
         for (int w : whole) cands.push_back(tune::Choice{sh, w, wpc, 0.0});
       else

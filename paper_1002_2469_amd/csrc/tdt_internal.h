@@ -79,6 +79,13 @@ enum { kTabBeta = 0, kTabInvD = 1, kTabN = 2 };
 //   block's responses to unit values just left / right of it.
 enum { kVecIU = 0, kVecCP = 1, kVecPHI = 2, kVecCHI = 3, kVecAIU = 4, kVecN = 5 };
 
+// General (per-row) matrices: per row of a block, the block-local LU
+// (1/u_i, a_i/u_i, c_i/u_i), laid out [tile][value][row in block][lane]; per
+// block, its end values, beta_{m-1} and 1/(1 - pf beta_{m-1}) of the in-tile
+// elimination, laid out [tile][value][lane].
+enum { kGenIU = 0, kGenAIU = 1, kGenCP = 2, kGenRowN = 3 };
+enum { kGenPF = 0, kGenPL = 1, kGenCF = 2, kGenBP = 3, kGenID = 4, kGenBlkN = 5 };
+
 // Everything one solve launch sequence needs (device pointers).
 struct LaunchSet {
   const SysDesc* sys;
@@ -110,6 +117,14 @@ struct LaunchSet {
   double* gpart;
   int64_t corner0;        // series, quasi-Toeplitz: first corner t-gradient slot
   int quasi;              // the plan's systems are quasi-Toeplitz
+  // general (per-row) matrix, series plans: per-row LU and per-block constants
+  // in the compute precision, per-tile end values; gen_M right-hand sides
+  int general;
+  const void* gen_row;
+  const void* gen_blk;
+  const double* gen_tK;
+  int64_t gen_M;
+  int gen_R;               // right-hand sides per item (the item counts below are per item)
   int* iters;
   int max_iter;
   double refine_tol;
@@ -130,5 +145,11 @@ constexpr int kGradN = 5;
 // ncomp (3, or 5 for quasi-Toeplitz plans) values per system.
 hipError_t launch_gt_reduce(const double* gpart, const SysDesc* sys, int64_t nsys,
                             int64_t nparts, int varlen, int ncomp, double* gt, hipStream_t st);
+// General matrices: the work shape their kernels are built for (index into
+// kShapes), and the entry gradients [3][n] from the adjoint solution gF and
+// the forward solution X ([M][n], floats if f32).
+constexpr int kGeneralShape = 1;
+hipError_t launch_general_grad(int f32, const void* gF, const void* X, int64_t n, int64_t M,
+                               double* g, hipStream_t st);
 
 }  // namespace tdt

@@ -1340,6 +1340,7 @@ struct GridArgs {
   double* gpart;                      // adjoint: t-gradient slots (corner rows)
   int64_t corner0;                    // series: first corner slot (2 per right-hand side)
   int f32;                            // F, X hold floats
+  const double* tK;                   // general matrices: end values of every tile [tile][4]
   const SysDesc* __restrict__ sys;
   const int* __restrict__ gitems;     // varlen: system of each workgroup; null for a series
   const double* __restrict__ ttab;    // [2][tile slot]: beta_{t-1}, 1/(1 - Pf_t beta_{t-1})
@@ -1390,7 +1391,7 @@ __device__ __forceinline__ void grid_corner(const GridArgs& A, const SysDesc& S,
 // summaries, the runs are combined by the same wavefront scans and LDS level
 // as inside a tile, and each thread then walks its run left to right to give
 // every tile the values just outside it.
-template <bool QUASI>
+template <bool QUASI, bool GEN>
 __global__ __launch_bounds__(kGridNT) void k_grid(GridArgs A) {
   __shared__ double wsum[kGridNW][6];
   const int tid = threadIdx.x;
@@ -1412,7 +1413,7 @@ __global__ __launch_bounds__(kGridNT) void k_grid(GridArgs A) {
   const int tb = ta + ch < P ? ta + ch : P;
 
   auto tile_seg = [&](int t) {
-    const double* k = t + 1 < P ? S.tileK : S.ltileK;
+    const double* k = GEN ? A.tK + 4 * (int64_t)t : (t + 1 < P ? S.tileK : S.ltileK);
     return Seg<double>{summ[2 * t], summ[2 * t + 1], k[0], k[1], k[2], k[3]};
   };
 
@@ -1532,7 +1533,7 @@ __device__ __forceinline__ double scan_affine_bwd(double C, double h, double x_i
 }
 
 // Runs are held in registers: every input of the run is loaded up front.
-template <int NTG, int R, bool QUASI>
+template <int NTG, int R, bool QUASI, bool GEN>
 __global__ __launch_bounds__(NTG) void k_grid_affine(GridArgs A) {
   __shared__ GridShared<NTG> sh;
   const int tid = threadIdx.x;
@@ -1566,12 +1567,14 @@ __global__ __launch_bounds__(NTG) void k_grid_affine(GridArgs A) {
   }
   // an empty tile passes both recurrences through (A = C = 1, g = h = 0),
   // so that the value entering from the right reaches the last tile
+  // (a general matrix has end values per tile)
   auto kofs = [&](int t, double& pf, double& pl, double& cf, double& cl) {
     const bool real = t < P, last = t == P - 1;
-    pf = real ? (last ? S.ltileK[0] : S.tileK[0]) : 0.0;
-    pl = real ? (last ? S.ltileK[1] : S.tileK[1]) : 1.0;
-    cf = real ? (last ? S.ltileK[2] : S.tileK[2]) : 1.0;
-    cl = real ? (last ? S.ltileK[3] : S.tileK[3]) : 0.0;
+    const double* K = GEN ? A.tK + 4 * (int64_t)(real ? t : 0) : (last ? S.ltileK : S.tileK);
+    pf = real ? K[0] : 0.0;
+    pl = real ? K[1] : 1.0;
+    cf = real ? K[2] : 1.0;
+    cl = real ? K[3] : 0.0;
   };
   // 1. beta_{t-1} and 1/(1 - Pf_t beta_{t-1}) at every tile, from the plan's
   //    table (they depend on T only)
@@ -1641,7 +1644,7 @@ __global__ __launch_bounds__(NTG) void k_grid_affine(GridArgs A) {
 // The same pass for the widest workgroup (1024 threads, whose register
 // budget cannot hold a run's inputs): each pass re-reads a tile's inputs from
 // L2, and alpha_{t-1} and h_t wait in the tile's ghost slot between passes.
-template <int NTG, int R, bool QUASI>
+template <int NTG, int R, bool QUASI, bool GEN>
 __global__ __launch_bounds__(NTG) void k_grid_affine_lean(GridArgs A) {
   __shared__ GridShared<NTG> sh;
   const int tid = threadIdx.x;
@@ -1673,7 +1676,7 @@ __global__ __launch_bounds__(NTG) void k_grid_affine_lean(GridArgs A) {
     const int t = ta + r;
     const int pc = pos(r);
     const bool real = t < P, last = t == P - 1;
-    const double* K = last ? S.ltileK : S.tileK;
+    const double* K = GEN ? A.tK + 4 * (int64_t)(real ? t : 0) : (last ? S.ltileK : S.tileK);
     const double u = summ[2 * pc], v = summ[2 * pc + 1];
     const double b0 = A.ttab[tb0 + pc], i0 = A.ttab[A.ttab_n + tb0 + pc];
     TileIn x;
@@ -1772,6 +1775,212 @@ __global__ __launch_bounds__(kGridNT) void k_gt_reduce(const double* __restrict_
     for (int c = 0; c < ncomp; ++c) gt[c] = red[0][c];
 }
 
+
+// ---------------------------------------------------------------------------
+// General tridiagonal matrices: row i reads a_i x_{i-1} + b_i x_i + c_i
+// x_{i+1} = f_i with entries of its own, for a series of right-hand sides
+// sharing the matrix (eq. (2) with any A; the preliminary step of Sec. 2.3
+// is written for such A).  The method is unchanged: B-row blocks per lane,
+// the two affine recurrences of eq. (15) across the blocks of a tile and
+// across tiles; only the constants become per block and per tile.  The plan
+// pads the system to whole tiles with decoupled rows (b = 1, a = c = 0, f =
+// 0), so every tile is full, and lays its per-row and per-block constants
+// out [tile][value][row in block][lane], so that each lane loads its own with
+// loads that are coalesced across the workgroup.  An item is a tile and a
+// group of R right-hand sides: the workgroup loads the tile's constants once
+// and keeps them in registers while it solves the group (the items run
+// tile-major, so neighbouring items find the constants in L2).
+// ---------------------------------------------------------------------------
+
+template <typename Tio, typename Tc>
+struct GenArgs {
+  const Tio* __restrict__ F;
+  Tio* __restrict__ X;
+  const Tc* __restrict__ row;    // [tile][kGenRowN][B][NT]: 1/u, a/u, c/u of the block-local LU
+  const Tc* __restrict__ blk;    // [tile][kGenBlkN][NT]: block end values, beta_{m-1}, 1/(1 - pf beta_{m-1})
+  const SysDesc* __restrict__ sys;
+  int64_t M;                     // right-hand sides
+  int R;                         // right-hand sides per item
+  int64_t G;                     // groups of R right-hand sides per tile, ceil(M / R)
+  int64_t nitems;                // G * tiles
+  int reverse;
+  double* __restrict__ summ;     // [slot][2] tile summaries
+  const double* __restrict__ ghost;
+};
+
+// One tile of a general matrix for one right-hand side, this lane's block in
+// q (in: right-hand side, out: solution, or with yfo/ylo the tile summary).
+// The correction re-sweeps each block with its outside values folded into
+// its first and last right-hand side rows, so that only the LU of the block
+// is needed (no stored basis vectors): with y the block's own solution, the
+// forward-sweep values are d_i = y_i + (c/u)_i y_{i+1}; the left value xl
+// adds -(a/u)_0 xl to d_0, carried down by d_i -= (a/u)_i times the previous
+// change, and the right value xr adds -(c/u)_{B-1} xr to d_{B-1}.
+template <class SH, typename Tc>
+__device__ __forceinline__ void gen_tile_solve(Tc (&q)[SH::B], const Tc (&iu)[SH::B],
+                                               const Tc (&aiu)[SH::B], const Tc (&cp)[SH::B],
+                                               Tc pf, Tc pl, Tc cf, Tc bp, Tc iD, Tc XLt, Tc XRt,
+                                               Tc (*fw)[2], Tc (*bw)[2], double* yfo,
+                                               double* ylo) {
+  TDT_SHAPE(SH)
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  q[0] *= iu[0];
+#pragma unroll
+  for (int i = 1; i < kB; ++i) q[i] = q[i] * iu[i] - aiu[i] * q[i - 1];
+#pragma unroll
+  for (int i = kB - 2; i >= 0; --i) q[i] -= cp[i] * q[i + 1];
+  const Tc yf = q[0], yl = q[kB - 1];
+  // left-to-right and right-to-left sums (eq. (15)), as in the Toeplitz tile
+  Tc A = pl * iD;
+  Tc g = yl + A * bp * yf;
+  wave_scan_affine_fwd(A, g);
+  if (lane == 63) { fw[w][0] = A; fw[w][1] = g; }
+  __syncthreads();
+  Tc cin = XLt;
+  for (int k = 0; k < w; ++k) cin = fw[k][0] * cin + fw[k][1];
+  const Tc alpha = A * cin + g;
+  Tc alpha_prev = __shfl_up(alpha, 1, 64);
+  if (lane == 0) alpha_prev = cin;
+  Tc C = cf * iD;
+  Tc h = (yf + pf * alpha_prev) * iD;
+  wave_scan_affine_bwd(C, h);
+  if (lane == 0) { bw[w][0] = C; bw[w][1] = h; }
+  __syncthreads();
+  Tc ein = XRt;
+  for (int k = kNW - 1; k > w; --k) ein = bw[k][0] * ein + bw[k][1];
+  const Tc u = C * ein + h;
+  if (yfo) {
+    if (threadIdx.x == 0) *yfo = (double)u;
+    if (threadIdx.x == kNT - 1) *ylo = (double)alpha;
+    return;
+  }
+  Tc u_next = __shfl_down(u, 1, 64);
+  if (lane == 63) u_next = ein;
+  const Tc xl = alpha_prev + bp * u;   // last unknown of the previous block
+  const Tc xr = u_next;                // first unknown of the next block
+  Tc delta = -aiu[0] * xl;
+#pragma unroll
+  for (int i = 0; i < kB; ++i) {
+    Tc d = i + 1 < kB ? q[i] + cp[i] * q[i + 1] : q[i];
+    d += delta;
+    if (i == kB - 1) d -= cp[kB - 1] * xr;
+    q[i] = d;
+    if (i + 1 < kB) delta = -aiu[i + 1] * delta;
+  }
+#pragma unroll
+  for (int i = kB - 2; i >= 0; --i) q[i] -= cp[i] * q[i + 1];
+}
+
+// Persistent workgroups over the (tile, group of right-hand sides) items of a
+// general series plan, tile-major; the next right-hand side's rows are
+// prefetched in registers.
+//   SUMMARY = true : first pass, the tile summaries (y_first, y_last);
+//   SUMMARY = false: solve with the values just outside the tile and store.
+template <class SH, typename Tio, typename Tc, bool SUMMARY>
+__global__ __launch_bounds__(SH::NT, SH::WAVES) void k_gtile(GenArgs<Tio, Tc> A) {
+  TDT_SHAPE(SH)
+  __shared__ TileShared<SH, Tio, Tc> sh;
+  const int tid = threadIdx.x;
+  const SysDesc S = load_sys(A.sys, 0);
+  const int nt = S.ntiles;
+  auto item_of = [&](int64_t k) { return A.reverse ? A.nitems - 1 - k : k; };
+  // item it: tile t, right-hand sides g R .. min(g R + R, M) - 1
+  auto tile_of = [&](int64_t it) { return (int)(it / A.G); };
+  auto first_of = [&](int64_t it) { return (it - (int64_t)tile_of(it) * A.G) * A.R; };
+  auto tile_rows = [&](int t) {
+    return (int)(S.n - (int64_t)t * kTile < kTile ? S.n - (int64_t)t * kTile : kTile);
+  };
+  Tio pv[kB];
+  auto issue = [&](int t, int64_t m) {
+    const int64_t base = m * S.stride + (int64_t)t * kTile;
+    const __amdgpu_buffer_rsrc_t src =
+        make_rsrc(A.F + base, (int64_t)tile_rows(t) * sizeof(Tio));
+    const int vb = opaque(tid * (int)sizeof(Tio));
+#pragma unroll
+    for (int j = 0; j < kB; ++j) pv[j] = buf_load<Tio>(src, vb + j * kNT * (int)sizeof(Tio));
+  };
+  int64_t k = blockIdx.x;
+  if (k < A.nitems) issue(tile_of(item_of(k)), first_of(item_of(k)));
+  while (k < A.nitems) {
+    const int64_t it = item_of(k);
+    const int t = tile_of(it), tl = tile_rows(t);
+    const int64_t m0 = first_of(it);
+    const int64_t m1 = m0 + A.R < A.M ? m0 + A.R : A.M;
+    const int64_t kn = k + gridDim.x;
+    // this lane's constants, kept for the item's right-hand sides
+    const Tc* rw = A.row + (int64_t)t * kGenRowN * kTile + tid;
+    Tc iu[kB], aiu[kB], cp[kB];
+#pragma unroll
+    for (int i = 0; i < kB; ++i) {
+      iu[i] = rw[(kGenIU * kB + i) * kNT];
+      aiu[i] = rw[(kGenAIU * kB + i) * kNT];
+      cp[i] = rw[(kGenCP * kB + i) * kNT];
+    }
+    const Tc* bk = A.blk + (int64_t)t * kGenBlkN * kNT + tid;
+    const Tc pf = bk[kGenPF * kNT], pl = bk[kGenPL * kNT], cf = bk[kGenCF * kNT];
+    const Tc bp = bk[kGenBP * kNT], iD = bk[kGenID * kNT];
+    for (int64_t m = m0; m < m1; ++m) {
+      const int64_t slot = tile_slot(S, m, t, false);
+      double XLt = 0.0, XRt = 0.0;
+      if (!SUMMARY && nt > 1) {
+        XLt = A.ghost[2 * slot];
+        XRt = A.ghost[2 * slot + 1];
+      }
+      __syncthreads();   // the previous right-hand side is done with LDS
+      {
+        Tio* lw = sh.lds + opaque(lds_base<SH, Tio>());
+#pragma unroll
+        for (int j = 0; j < kB; ++j) lw[j * lds_stride<SH, Tio>()] = pv[j];
+      }
+      if (m + 1 < m1) issue(t, m + 1);
+      else if (kn < A.nitems) issue(tile_of(item_of(kn)), first_of(item_of(kn)));
+      __syncthreads();
+      Tio* myrow = sh.lds + tid * TileShared<SH, Tio, Tc>::RP;
+      Tc q[kB];
+#pragma unroll
+      for (int i = 0; i < kB; ++i) q[i] = (Tc)myrow[i];
+      if constexpr (SUMMARY) {
+        gen_tile_solve<SH, Tc>(q, iu, aiu, cp, pf, pl, cf, bp, iD, Tc(0), Tc(0), sh.fw, sh.bw,
+                               A.summ + 2 * slot, A.summ + 2 * slot + 1);
+      } else {
+        gen_tile_solve<SH, Tc>(q, iu, aiu, cp, pf, pl, cf, bp, iD, (Tc)XLt, (Tc)XRt, sh.fw,
+                               sh.bw, (double*)nullptr, (double*)nullptr);
+#pragma unroll
+        for (int i = 0; i < kB; ++i) myrow[i] = (Tio)q[i];
+        __syncthreads();
+        store_tile<SH, Tio, Tc, false, false>(sh, A.X, (const Tio*)nullptr,
+                                              m * S.stride + (int64_t)t * kTile,
+                                              (int64_t)t * kTile, tl, S.n, (double*)nullptr);
+      }
+    }
+    k = kn;
+  }
+}
+
+// Entry gradients of a general series plan after its adjoint solve:
+// g[0][i] = dL/da_i = -sum_m gF_{m,i} x_{m,i-1}, g[1][i] = dL/db_i =
+// -sum_m gF_{m,i} x_{m,i}, g[2][i] = dL/dc_i = -sum_m gF_{m,i} x_{m,i+1}
+// (0 for the unused a_0 and c_{n-1}); one thread per row, right-hand sides
+// in order (deterministic).
+template <typename Tio>
+__global__ __launch_bounds__(kGridNT) void k_ggrad(const Tio* __restrict__ gF,
+                                                const Tio* __restrict__ X, int64_t n, int64_t M,
+                                                double* __restrict__ g) {
+  const int64_t i = (int64_t)blockIdx.x * kGridNT + threadIdx.x;
+  if (i >= n) return;
+  double sa = 0.0, sb = 0.0, sc = 0.0;
+  for (int64_t m = 0; m < M; ++m) {
+    const Tio* gp = gF + m * n;
+    const Tio* xp = X + m * n;
+    const double gv = (double)gp[i];
+    sb += gv * (double)xp[i];
+    if (i > 0) sa += gv * (double)xp[i - 1];
+    if (i + 1 < n) sc += gv * (double)xp[i + 1];
+  }
+  g[i] = -sa;
+  g[n + i] = -sb;
+  g[2 * n + i] = -sc;
+}
 }  // namespace tdt
 
 // ---------------------------------------------------------------------------
@@ -1854,22 +2063,22 @@ static void launch_beta(const LaunchSet& L, const Tio* F, hipStream_t st) {
 // Interface pass across tiles: the affine variant sized for the most tiled
 // system (up to 16384 tiles), beyond that the segment-merge kernel.  The
 // plan lays out its workspace slots for the same choice (interface_run).
-template <bool QUASI>
+template <bool QUASI, bool GEN = false>
 static void launch_grid(const LaunchSet& L, const void* F, void* X, const void* Xfwd, int f32,
                         hipStream_t st) {
-  GridArgs G{F,     X,          Xfwd,   L.gpart,  L.corner0, f32,    L.sys,
+  GridArgs G{F,     X,          Xfwd,   L.gpart,  L.corner0, f32,    L.gen_tK, L.sys,
              L.grid_items, L.ttab, L.ttab_n, L.summ,   L.ghost, L.gscr};
   const dim3 gg((unsigned)L.n_grid);
   if (L.max_ntiles <= 256)
-    hipLaunchKernelGGL((k_grid_affine<256, 1, QUASI>), gg, dim3(256), 0, st, G);
+    hipLaunchKernelGGL((k_grid_affine<256, 1, QUASI, GEN>), gg, dim3(256), 0, st, G);
   else if (L.max_ntiles <= 2048)
-    hipLaunchKernelGGL((k_grid_affine<256, 8, QUASI>), gg, dim3(256), 0, st, G);
+    hipLaunchKernelGGL((k_grid_affine<256, 8, QUASI, GEN>), gg, dim3(256), 0, st, G);
   else if (L.max_ntiles <= 8192)
-    hipLaunchKernelGGL((k_grid_affine<512, 16, QUASI>), gg, dim3(512), 0, st, G);
+    hipLaunchKernelGGL((k_grid_affine<512, 16, QUASI, GEN>), gg, dim3(512), 0, st, G);
   else if (L.max_ntiles <= 16384)
-    hipLaunchKernelGGL((k_grid_affine_lean<1024, 16, QUASI>), gg, dim3(1024), 0, st, G);
+    hipLaunchKernelGGL((k_grid_affine_lean<1024, 16, QUASI, GEN>), gg, dim3(1024), 0, st, G);
   else
-    hipLaunchKernelGGL((k_grid<QUASI>), gg, dim3(kGridNT), 0, st, G);
+    hipLaunchKernelGGL((k_grid<QUASI, GEN>), gg, dim3(kGridNT), 0, st, G);
 }
 
 template <class SH, typename Tio, typename Tc, bool REFINE, bool BWD, bool QUASI>
@@ -1953,8 +2162,61 @@ using Shape1 = Shape<kShapes[1].B, kShapes[1].NT, kShapes[1].waves>;
 using Shape2 = Shape<kShapes[2].B, kShapes[2].NT, kShapes[2].waves>;
 static_assert(kNumShapes == 3, "one Shape alias per entry of kShapes");
 
+// General matrices (series plans, work shape kGeneralShape): first pass over
+// the (tile, right-hand side) items, interface pass with per-tile end values,
+// final pass in reverse item order (the most recently read tiles first).
+template <class SH, typename Tio, typename Tc, bool SUMMARY>
+static void launch_gtile(GenArgs<Tio, Tc>& A, int64_t nitems, int reverse, int wg_per_cu,
+                         hipStream_t st) {
+  auto kern = k_gtile<SH, Tio, Tc, SUMMARY>;
+  static int per_cu = resident_per_cu(kern, SH::NT);
+  const int64_t cap = grid_cap(per_cu, wg_per_cu);
+  A.nitems = nitems;
+  A.reverse = reverse;
+  hipLaunchKernelGGL(kern, dim3((unsigned)(nitems < cap ? nitems : cap)), dim3(SH::NT), 0, st,
+                     A);
+}
+
+template <typename Tio, typename Tc>
+static hipError_t run_general(const LaunchSet& L, const void* F, void* X, hipStream_t st) {
+  using SH = Shape<kShapes[kGeneralShape].B, kShapes[kGeneralShape].NT,
+                   kShapes[kGeneralShape].waves>;
+  GenArgs<Tio, Tc> A{static_cast<const Tio*>(F), static_cast<Tio*>(X),
+                     static_cast<const Tc*>(L.gen_row), static_cast<const Tc*>(L.gen_blk),
+                     L.sys, L.gen_M, L.gen_R, (L.gen_M + L.gen_R - 1) / L.gen_R, 0, 0,
+                     L.summ, L.ghost};
+  if (L.ev) (void)hipEventRecord(L.ev[0], st);
+  if (L.n_p1 > 0) {
+    launch_gtile<SH, Tio, Tc, true>(A, L.n_p1, 0, L.wg_per_cu, st);
+    if (L.ev) (void)hipEventRecord(L.ev[1], st);
+    launch_grid<false, true>(L, F, X, nullptr, sizeof(Tio) == 4 ? 1 : 0, st);
+    if (L.ev) (void)hipEventRecord(L.ev[2], st);
+  } else if (L.ev) {
+    (void)hipEventRecord(L.ev[1], st);
+    (void)hipEventRecord(L.ev[2], st);
+  }
+  launch_gtile<SH, Tio, Tc, false>(A, L.n_fin, L.n_p1 > 0 ? 1 : 0, L.wg_per_cu, st);
+  if (L.ev) (void)hipEventRecord(L.ev[3], st);
+  return hipGetLastError();
+}
+
+hipError_t launch_general_grad(int f32, const void* gF, const void* X, int64_t n, int64_t M,
+                               double* g, hipStream_t st) {
+  const unsigned grid = (unsigned)((n + kGridNT - 1) / kGridNT);
+  if (f32)
+    hipLaunchKernelGGL(k_ggrad<float>, dim3(grid), dim3(kGridNT), 0, st,
+                       static_cast<const float*>(gF), static_cast<const float*>(X), n, M, g);
+  else
+    hipLaunchKernelGGL(k_ggrad<double>, dim3(grid), dim3(kGridNT), 0, st,
+                       static_cast<const double*>(gF), static_cast<const double*>(X), n, M, g);
+  return hipGetLastError();
+}
+
 hipError_t launch_solve(int dtype, bool bwd, const LaunchSet& L, const void* F, void* X,
                         const void* Xfwd, hipStream_t st) {
+  if (L.general)
+    return dtype == 1 ? run_general<float, float>(L, F, X, st)
+                      : run_general<double, double>(L, F, X, st);
   switch (L.shape) {
     case 1: return launch_shape<Shape1>(dtype, bwd, L, F, X, Xfwd, st);
     case 2: return launch_shape<Shape2>(dtype, bwd, L, F, X, Xfwd, st);

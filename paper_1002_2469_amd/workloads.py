@@ -83,6 +83,30 @@ def sov_neumann_batch(seed: int = 0, s: int = 2048, n_min: int = 256,
     return d
 
 
+def general_rows(rng: np.random.Generator, n: int, ratio_lo: float = 1.1,
+                 ratio_hi: float = 1.6) -> tuple:
+    """Rows of a variable-coefficient diffusion-reaction operator with a
+    skewed (nonsymmetric) stencil: kappa(x) = exp(0.5 sin(2 pi x) + 0.3 xi),
+    a_i = -kappa_{i-1/2} (1 + e_i), c_i = -kappa_{i+1/2} (1 - e_i) with
+    e_i ~ U[-0.3, 0.3], and b_i = r_i (|a_i| + |c_i|) with the dominance ratio
+    r_i ~ U[ratio_lo, ratio_hi] (the reaction term)."""
+    x = (np.arange(n + 1) + 0.5) / (n + 1)
+    kap = np.exp(0.5 * np.sin(2.0 * math.pi * x) + 0.3 * rng.uniform(-1.0, 1.0, n + 1))
+    e = rng.uniform(-0.3, 0.3, n)
+    a = -kap[:-1] * (1.0 + e)
+    c = -kap[1:] * (1.0 - e)
+    b = rng.uniform(ratio_lo, ratio_hi, n) * (np.abs(a) + np.abs(c))
+    return a, b, c
+
+
+def general_series(seed: int = 0, n: int = 1 << 20, m: int = 64) -> dict:
+    """M right-hand sides [M][N] sharing one general tridiagonal matrix."""
+    rng = np.random.default_rng(seed)
+    a, b, c = general_rows(rng, n)
+    F = rng.standard_normal((m, n))
+    return dict(name="general_series", N=n, M=m, a=a, b=b, c=c, F=F)
+
+
 def diff_batch(seed: int = 0, s: int = 1024, n: int = 16384) -> dict:
     rng = np.random.default_rng(seed)
     t0 = rng.uniform(2.5, 4.0, size=s)
