@@ -45,6 +45,7 @@ struct tdt_plan_s {
   void* dgrow[2] = {nullptr, nullptr};
   void* dgblk[2] = {nullptr, nullptr};
   double* dgtK[2] = {nullptr, nullptr};
+  void* dggreen[2] = {nullptr, nullptr};   // first and last row of each tile's inverse
   int64_t reserved_M = 0;
   bool varlen = false;
   tdt_dtype_t dtype = TDT_F64;
@@ -440,6 +441,7 @@ void destroy(tdt_plan_s* p) {
     (void)hipFree(p->dgrow[k]);
     (void)hipFree(p->dgblk[k]);
     (void)hipFree(p->dgtK[k]);
+    (void)hipFree(p->dggreen[k]);
   }
   (void)hipFree(p->dp1);
   (void)hipFree(p->dfin);
@@ -718,6 +720,36 @@ tdt_status_t rebuild_plan(tdt_plan_s* p, int shape) {
 // decoupled rows (b = 1, a = c = 0), so every tile is full.  Everything below
 // is long double, rounded once on upload.
 // ---------------------------------------------------------------------------
+// First and last row of the inverse of the L-row matrix with rows
+// (a_i, b_i, c_i), i.e. the solutions of T^T r = e_0 and T^T r = e_{L-1}
+// (T^T has c_{i-1} left of its diagonal and a_{i+1} right of it).
+bool green_rows_general(const ld* a, const ld* b, const ld* c, int64_t L, double* first,
+                        double* last) {
+  std::vector<ld> cpv((size_t)L), r1((size_t)L), r2((size_t)L);
+  ld u = b[0];
+  if (u == 0.0L) return false;
+  cpv[0] = L > 1 ? a[1] / u : 0.0L;
+  r1[0] = 1.0L / u;
+  r2[0] = L == 1 ? 1.0L / u : 0.0L;
+  for (int64_t i = 1; i < L; ++i) {
+    u = b[i] - c[i - 1] * cpv[i - 1];
+    if (u == 0.0L) return false;
+    cpv[i] = i + 1 < L ? a[i + 1] / u : 0.0L;
+    r1[i] = (0.0L - c[i - 1] * r1[i - 1]) / u;
+    r2[i] = ((i == L - 1 ? 1.0L : 0.0L) - c[i - 1] * r2[i - 1]) / u;
+  }
+  for (int64_t i = L - 2; i >= 0; --i) {
+    r1[i] -= cpv[i] * r1[i + 1];
+    r2[i] -= cpv[i] * r2[i + 1];
+  }
+  for (int64_t i = 0; i < L; ++i) {
+    first[i] = (double)r1[i];
+    last[i] = (double)r2[i];
+    if (!std::isfinite(first[i]) || !std::isfinite(last[i])) return false;
+  }
+  return true;
+}
+
 template <typename Tc>
 tdt_status_t build_general_dir(tdt_plan_s* p, int dir, double& dom, double& kap) {
   const int B = p->B, NT = p->NT;
@@ -758,6 +790,20 @@ tdt_status_t build_general_dir(tdt_plan_s* p, int dir, double& dom, double& kap)
   }
   std::vector<Tc> row((size_t)P * tdt::kGenRowN * L), blk((size_t)P * tdt::kGenBlkN * NT);
   std::vector<double> tK((size_t)P * 4);
+  // the tiles' Green rows (first pass of a double plan with several tiles)
+  std::vector<Tc> green(P > 1 && sizeof(Tc) == 8 ? (size_t)P * 2 * L : 0);
+  {
+    std::vector<double> g1((size_t)L), g2((size_t)L);
+    for (int64_t t = 0; !green.empty() && t < P; ++t) {
+      if (!green_rows_general(a.data() + t * L, b.data() + t * L, c.data() + t * L, L,
+                              g1.data(), g2.data()))
+        return TDT_ERR_SINGULAR;
+      for (int64_t i = 0; i < L; ++i) {
+        green[(size_t)t * 2 * L + i] = (Tc)g1[i];
+        green[(size_t)t * 2 * L + L + i] = (Tc)g2[i];
+      }
+    }
+  }
   std::vector<ld> iu(B), aiu(B), cp(B), ph(B), ch(B);
   for (int64_t t = 0; t < P; ++t) {
     ld beta = 0.0L;
@@ -847,6 +893,8 @@ tdt_status_t build_general_dir(tdt_plan_s* p, int dir, double& dom, double& kap)
   tdt_status_t st = dev_upload(reinterpret_cast<Tc**>(&p->dgrow[dir]), row.data(), row.size());
   if (st == TDT_OK) st = dev_upload(reinterpret_cast<Tc**>(&p->dgblk[dir]), blk.data(), blk.size());
   if (st == TDT_OK) st = dev_upload(&p->dgtK[dir], tK.data(), tK.size());
+  if (st == TDT_OK)
+    st = dev_upload(reinterpret_cast<Tc**>(&p->dggreen[dir]), green.data(), green.size());
   if (st == TDT_OK) st = dev_upload(&p->dttab[dir], tt.data(), tt.size());
   if (st == TDT_OK) st = dev_upload(&p->dsys[dir], p->hsys[dir].data(), 1);
   return st;
@@ -912,6 +960,7 @@ tdt_status_t run(tdt_plan_s* p, int dir, const void* F, void* X, const void* Xfw
     const SysDesc& D0 = p->hsys[0][0];
     const int64_t nt = D0.ntiles;
     L.green = nullptr;
+    L.gen_green = p->dggreen[dir];
     L.p1_items = L.fin_items = nullptr;
     L.grid_items = L.sys_items = L.sys_bins = nullptr;
     L.n_bins = L.n_sys = 0;

@@ -123,6 +123,7 @@ struct LaunchSet {
   const void* gen_row;
   const void* gen_blk;
   const double* gen_tK;
+  const void* gen_green;   // [tile][2][L] Green rows, data precision
   int64_t gen_M;
   int gen_R;               // right-hand sides per item (the item counts below are per item)
   int* iters;

@@ -1331,6 +1331,135 @@ __global__ __launch_bounds__(kBetaNT) void k_beta(BetaArgs<Tio> A) {
   }
 }
 
+
+// First pass of a general double series plan: the same Green-row dot
+// products as k_beta, with the rows of each tile's own inverse
+// ([tile][2][kTile], from the plan).  An item is a tile and a group of R
+// right-hand sides: the lane loads its entries of the tile's two rows once and
+// streams the group.  (A float plan sweeps its tiles instead: its Green rows
+// would weigh as much as its data and measured slower.)
+template <typename Tio>
+struct GBetaArgs {
+  const Tio* __restrict__ F;
+  const SysDesc* __restrict__ sys;
+  const Tio* __restrict__ green;      // [tile][2][kTile]
+  int64_t M;
+  int R;
+  int64_t G;                          // groups per tile, ceil(M / R)
+  int64_t nitems;                     // G * tiles
+  double* __restrict__ summ;          // [slot][2]
+};
+
+template <class SH, typename Tio>
+__global__ __launch_bounds__(kBetaNT) void k_gbeta(GBetaArgs<Tio> A) {
+  TDT_SHAPE(SH)
+  constexpr int kSlice = kTile / kBetaNW;
+  constexpr int kBetaPerLane = kSlice / 64;
+  constexpr int V = 16 / (int)sizeof(Tio);
+  constexpr int NL = kBetaPerLane / V;
+  constexpr int U = 1;   // right-hand sides per step (more in flight did not pay)
+  __shared__ double part[2][U][kBetaNW][2];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const SysDesc S0 = load_sys(A.sys, 0);
+  const int64_t stride = S0.stride;
+  // partials of the previous step: tile pt, right-hand sides pm .. pm+pc-1
+  auto flush = [&](int pt, int64_t pm, int pc, int pp) {
+    for (int u = 0; u < pc; ++u) {
+      double y1 = 0.0, y2 = 0.0;
+      for (int k = 0; k < kBetaNW; ++k) { y1 += part[pp][u][k][0]; y2 += part[pp][u][k][1]; }
+      const int64_t sl = tile_slot(S0, pm + u, pt, false);
+      A.summ[2 * sl] = y1;
+      A.summ[2 * sl + 1] = y2;
+    }
+  };
+  int par = 0, pt = -1, pc = 0;
+  int64_t pm = -1;
+  for (int64_t k = blockIdx.x; k < A.nitems; k += gridDim.x) {
+    const int t = (int)(k / A.G);
+    const int64_t m0 = (k - (int64_t)t * A.G) * A.R;
+    const int64_t m1 = m0 + A.R < A.M ? m0 + A.R : A.M;
+    const Tio* gr = A.green + (int64_t)t * 2 * kTile;
+    double g1[kBetaPerLane], gl[kBetaPerLane];
+#pragma unroll
+    for (int j = 0; j < NL; ++j)
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const int e = w * kSlice + (j * 64 + lane) * V + v;
+        g1[j * V + v] = (double)gr[e];
+        gl[j * V + v] = (double)gr[kTile + e];
+      }
+    // rows of this wavefront's slice that lie inside the system: all of them
+    // but in the last tile, whose rows past the end read as 0 (loaded one
+    // element at a time there, so that the range check applies to each)
+    const int64_t r0 = (int64_t)t * kTile + w * kSlice;
+    const int64_t avail = S0.n - r0;
+    const int nrows = avail <= 0 ? 0 : (avail < kSlice ? (int)avail : kSlice);
+    for (int64_t m = m0; m < m1; m += U) {
+      const int cnt = m1 - m < U ? (int)(m1 - m) : U;
+      using R4 = decltype(__builtin_amdgcn_raw_buffer_load_b128(
+          make_rsrc(A.F, 0), 0, 0, 0));
+      R4 raw[U][NL];
+      const int vb = opaque(lane * 16);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        // right-hand sides past the group read nothing (empty range)
+        const __amdgpu_buffer_rsrc_t src = make_rsrc(
+            A.F + (m + (u < cnt ? u : 0)) * stride + r0,
+            u < cnt ? (int64_t)nrows * sizeof(Tio) : 0);
+        if (nrows == kSlice) {
+#pragma unroll
+          for (int j = 0; j < NL; ++j)
+            raw[u][j] = __builtin_amdgcn_raw_buffer_load_b128(src, vb + j * 1024, 0, 0);
+        } else {
+#pragma unroll
+          for (int j = 0; j < NL; ++j) {
+            Tio e[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+              e[v] = buf_load<Tio>(src, vb + j * 1024 + v * (int)sizeof(Tio));
+            raw[u][j] = __builtin_bit_cast(R4, e);
+          }
+        }
+      }
+      __syncthreads();   // the previous step's partials are in LDS
+      if (tid == 0 && pt >= 0) flush(pt, pm, pc, par ^ 1);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+        for (int j = 0; j < NL; ++j) {
+          if constexpr (sizeof(Tio) == 8) {
+            const double2 f2 = __builtin_bit_cast(double2, raw[u][j]);
+            s1 += f2.x * g1[2 * j] + f2.y * g1[2 * j + 1];
+            s2 += f2.x * gl[2 * j] + f2.y * gl[2 * j + 1];
+          } else {
+            const float4 f4 = __builtin_bit_cast(float4, raw[u][j]);
+            const float fv[4] = {f4.x, f4.y, f4.z, f4.w};
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              s1 += (double)fv[v] * g1[4 * j + v];
+              s2 += (double)fv[v] * gl[4 * j + v];
+            }
+          }
+        }
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+          s1 += __shfl_xor(s1, d, 64);
+          s2 += __shfl_xor(s2, d, 64);
+        }
+        if (lane == 0) { part[par][u][w][0] = s1; part[par][u][w][1] = s2; }
+      }
+      pt = t;
+      pm = m;
+      pc = cnt;
+      par ^= 1;
+    }
+  }
+  __syncthreads();
+  if (tid == 0 && pt >= 0) flush(pt, pm, pc, par ^ 1);
+}
+
 struct GridArgs {
   // quasi-Toeplitz systems: the corner rows of the right-hand side are read,
   // and those of the solution written, here
@@ -2187,7 +2316,19 @@ static hipError_t run_general(const LaunchSet& L, const void* F, void* X, hipStr
                      L.summ, L.ghost};
   if (L.ev) (void)hipEventRecord(L.ev[0], st);
   if (L.n_p1 > 0) {
-    launch_gtile<SH, Tio, Tc, true>(A, L.n_p1, 0, L.wg_per_cu, st);
+    if constexpr (sizeof(Tio) == 8) {
+      // tile summaries as Green-row dot products (double plans)
+      auto kern = k_gbeta<SH, Tio>;
+      static int per_cu = resident_per_cu(kern, kBetaNT);
+      const int64_t cap = grid_cap(per_cu, L.wg_per_cu);
+      GBetaArgs<Tio> B{static_cast<const Tio*>(F), L.sys, static_cast<const Tio*>(L.gen_green),
+                       L.gen_M, L.gen_R, A.G, L.n_p1, L.summ};
+      hipLaunchKernelGGL(kern, dim3((unsigned)(L.n_p1 < cap ? L.n_p1 : cap)), dim3(kBetaNT), 0,
+                         st, B);
+    } else {
+      // by sweeps (float plans: there the Green rows would be as large as F)
+      launch_gtile<SH, Tio, Tc, true>(A, L.n_p1, 0, L.wg_per_cu, st);
+    }
     if (L.ev) (void)hipEventRecord(L.ev[1], st);
     launch_grid<false, true>(L, F, X, nullptr, sizeof(Tio) == 4 ? 1 : 0, st);
     if (L.ev) (void)hipEventRecord(L.ev[2], st);
