@@ -134,6 +134,32 @@ tdt_status_t tdt_plan_general_create(int64_t N, const double *h_a, const double 
                                      const double *h_c, tdt_dtype_t dtype,
                                      tdt_plan_t *out);
 
+/* 2D Poisson solve by separation of variables (the application of Sec. 3.2
+ * and of the paper's timings): the five-point system
+ *     (2u_ij - u_{i-1,j} - u_{i+1,j}) / hx^2 + (2u_ij - u_{i,j-1} - u_{i,j+1}) / hy^2 = f_ij
+ * on Nx x Ny interior points with u = 0 on the boundary.  A sine transform
+ * along x (a real FFT of each row's odd extension, hipFFT) leaves one
+ * tridiagonal Toeplitz system per mode k along y, t_+-1 = -1,
+ * t_0 = 2 + hy^2 (4/hx^2) sin^2(pi k / (2 (Nx+1))), solved by a varlen plan of
+ * this library (dtype TDT_F64 or TDT_F32_REFINE); the inverse transform
+ * gives U.  The handle owns the line plan, the FFT plan and 3 Nx Ny + 2 Ny
+ * (Nx + 2) doubles of workspace (allocated here, blocking).  Errors: sizes
+ * < 1 or Nx Ny > 2^31, non-positive or non-finite spacings, another dtype ->
+ * TDT_ERR_INVALID_ARG; allocation -> TDT_ERR_OOM; an FFT plan failure ->
+ * TDT_ERR_HIP. */
+typedef struct tdt_poisson_s *tdt_poisson_t;
+tdt_status_t tdt_poisson2d_create(int64_t nx, int64_t ny, double hx, double hy,
+                                  tdt_dtype_t dtype, tdt_poisson_t *out);
+/* U = A^{-1} F; F, U: device, [Ny][Nx] doubles, caller-owned, distinct.
+ * Enqueued on stream (the FFTs too); one handle must not be used by two
+ * solves that may run concurrently (shared workspace). */
+tdt_status_t tdt_poisson2d_solve(tdt_poisson_t p, const double *F, double *U,
+                                 hipStream_t stream);
+/* The handle's line plan (owned by the handle), e.g. to set its options or
+ * autotune it. */
+tdt_status_t tdt_poisson2d_line_plan(tdt_poisson_t p, tdt_plan_t *line);
+tdt_status_t tdt_poisson2d_destroy(tdt_poisson_t p);
+
 /* Allocate the workspace for up to M_max right-hand sides now, so that later
  * solves allocate nothing and may be captured in a hipGraph.  Blocking. */
 tdt_status_t tdt_plan_reserve(tdt_plan_t plan, int64_t M_max);

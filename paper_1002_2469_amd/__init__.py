@@ -331,6 +331,53 @@ class GeneralPlan(_PlanBase):
         return gF, g
 
 
+class Poisson2D:
+    """2D Poisson solve by separation of variables (Sec. 3.2): the five-point
+    system on Nx x Ny interior points with zero boundary values, F and U
+    [Ny][Nx] float64 on the device.  Sine transforms along x (hipFFT), one
+    Toeplitz line system per mode along y (a varlen plan of dtype 'f64' or
+    'f32_refine'), inverse transform."""
+
+    def __init__(self, nx: int, ny: int, hx: float, hy: float, dtype: str = "f64"):
+        if dtype not in ("f64", "f32_refine"):
+            raise ValueError("dtype must be 'f64' or 'f32_refine'")
+        self._h = ctypes.c_void_p()
+        self.nx, self.ny, self.hx, self.hy, self.dtype = int(nx), int(ny), float(hx), float(hy), dtype
+        _lib.check(_lib.lib().tdt_poisson2d_create(self.nx, self.ny, self.hx, self.hy,
+                                                   DTYPES[dtype], ctypes.byref(self._h)),
+                   "tdt_poisson2d_create")
+
+    def solve(self, F, U=None, stream=None):
+        torch = _torch()
+        _check_tensor(F, torch.float64, self.nx * self.ny, "F")
+        if U is None:
+            U = torch.empty_like(F)
+        _check_tensor(U, torch.float64, self.nx * self.ny, "U")
+        _lib.check(_lib.lib().tdt_poisson2d_solve(self._h, ctypes.c_void_p(F.data_ptr()),
+                                                  ctypes.c_void_p(U.data_ptr()),
+                                                  _stream_handle(stream)), "tdt_poisson2d_solve")
+        return U
+
+    def set_line_option(self, name: str, value: int):
+        """A launch option of the line plan (see Plan.set_option)."""
+        line = ctypes.c_void_p()
+        _lib.check(_lib.lib().tdt_poisson2d_line_plan(self._h, ctypes.byref(line)),
+                   "tdt_poisson2d_line_plan")
+        _lib.check(_lib.lib().tdt_plan_set_option(line, _lib.OPTIONS[name], int(value)),
+                   "tdt_plan_set_option")
+
+    def close(self):
+        if self._h:
+            _lib.lib().tdt_poisson2d_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 _plan_cache: dict = {}
 
 

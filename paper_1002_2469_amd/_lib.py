@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libtdt.so")
 # experiments); the tests and the bench use the in-tree library.
 if os.environ.get("TDT_LIB_PATH"):
     LIB_PATH = os.environ["TDT_LIB_PATH"]
-SOURCES = [os.path.join(_HERE, "csrc", "tdt_kernels.hip"), os.path.join(_HERE, "csrc", "tdt_api.cpp")]
+SOURCES = [os.path.join(_HERE, "csrc", "tdt_kernels.hip"), os.path.join(_HERE, "csrc", "tdt_api.cpp"),
+           os.path.join(_HERE, "csrc", "tdt_poisson.hip")]
 HEADER = os.path.join(_ROOT, "include", "tdt.h")
 
 # status codes (include/tdt.h)
@@ -40,7 +41,8 @@ EXPORTS = [
     "tdt_last_info", "tdt_block_constants", "tdt_green_rows", "tdt_segment_merge", "tdt_plan_profile",
     "tdt_plan_profile_read", "tdt_build_info", "tdt_plan_set_option", "tdt_plan_get_option",
     "tdt_plan_autotune", "tdt_plan_quasi_create", "tdt_plan_varlen_quasi_create",
-    "tdt_plan_general_create",
+    "tdt_plan_general_create", "tdt_poisson2d_create", "tdt_poisson2d_solve",
+    "tdt_poisson2d_line_plan", "tdt_poisson2d_destroy",
 ]
 
 # tdt_option_t
@@ -55,7 +57,7 @@ def build_command(out: str = LIB_PATH) -> list:
     return ["hipcc", "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-I", os.path.join(_ROOT, "include"), "-I", os.path.join(_HERE, "csrc"),
-            *SOURCES, "-o", out]
+            *SOURCES, "-o", out, "-L/opt/rocm/lib", "-lhipfft"]
 
 
 def build() -> str:
@@ -90,6 +92,10 @@ def lib():
         "tdt_plan_quasi_create": [d, d, d, d, d, i64, i32, pp],
         "tdt_plan_varlen_quasi_create": [i64, p, p, p, p, p, p, i32, pp],
         "tdt_plan_general_create": [i64, p, p, p, i32, pp],
+        "tdt_poisson2d_create": [i64, i64, d, d, i32, pp],
+        "tdt_poisson2d_solve": [p, p, p, p],
+        "tdt_poisson2d_line_plan": [p, pp],
+        "tdt_poisson2d_destroy": [p],
         "tdt_plan_reserve": [p, i64],
         "tdt_solve": [p, p, p, i64, p],
         "tdt_solve_varlen": [p, p, p, p],

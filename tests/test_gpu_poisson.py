@@ -1,0 +1,104 @@
+"""GPU parity of the 2D Poisson solve by separation of variables (Sec. 3.2)
+against the CPU oracle (explicit sine transforms and Thomas per mode, itself
+pinned to the dense Kronecker-sum solve), through the C ABI; at the
+benchmark size (8192 x 8192) against the closed-form discrete eigenfunctions
+and the five-point residual, which hold at any size.
+
+Inputs: F ~ N(0, 1), spacings drawn in [0.002, 0.2] (unequal hx, hy)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import to_dev, to_host
+from oracle import poisson2d as P2
+
+pytestmark = pytest.mark.gpu
+U64 = 2.0 ** -53
+
+
+def _tdt():
+    import paper_1002_2469_amd as tdt
+    return tdt
+
+
+def kappa(nx, ny, hx, hy):
+    """Condition number of the five-point operator (closed-form spectrum)."""
+    lo = P2.mode_eigenvalues(nx, hx)[0] + P2.mode_eigenvalues(ny, hy)[0]
+    hi = P2.mode_eigenvalues(nx, hx)[-1] + P2.mode_eigenvalues(ny, hy)[-1]
+    return hi / lo
+
+
+def tol(nx, ny, hx, hy):
+    return max(1e-12, 8 * U64 * kappa(nx, ny, hx, hy))
+
+
+GRIDS = [(1, 1), (1, 9), (7, 1), (31, 17), (64, 64), (100, 257), (513, 700), (16, 20000)]
+
+
+@pytest.mark.parametrize("nx,ny", GRIDS)
+@pytest.mark.parametrize("dtype", ["f64", "f32_refine"])
+def test_poisson_grids(nx, ny, dtype):
+    tdt = _tdt()
+    rng = np.random.default_rng(nx * 1000 + ny)
+    hx, hy = rng.uniform(0.002, 0.2), rng.uniform(0.002, 0.2)
+    F = rng.standard_normal((ny, nx))
+    print(f"[case] poisson nx={nx} ny={ny} dtype={dtype}", flush=True)
+    solver = tdt.Poisson2D(nx, ny, hx, hy, dtype)
+    U = to_host(solver.solve(to_dev(F)))
+    ref = P2.solve(F, hx, hy)
+    err = oracle.rel_err(U, ref)
+    assert err <= tol(nx, ny, hx, hy), (nx, ny, dtype, err, tol(nx, ny, hx, hy))
+
+
+@pytest.mark.parametrize("whole", [0, 8])
+def test_poisson_line_paths(whole):
+    """Mode systems of 3 tiles, solved whole by one workgroup each or by the
+    three-kernel path of the line plan."""
+    tdt = _tdt()
+    rng = np.random.default_rng(5)
+    nx, ny, hx, hy = 40, 3 * 8192 + 11, 0.01, 0.003
+    F = rng.standard_normal((ny, nx))
+    print(f"[case] poisson line path whole={whole}", flush=True)
+    solver = tdt.Poisson2D(nx, ny, hx, hy)
+    solver.set_line_option("whole_max_tiles", whole)
+    U = to_host(solver.solve(to_dev(F)))
+    assert oracle.rel_err(U, P2.solve(F, hx, hy)) <= tol(nx, ny, hx, hy)
+
+
+@pytest.mark.parametrize("n,dtype", [(8192, "f64"), (2048, "f32_refine")])
+def test_poisson_benchmark_size(n, dtype):
+    """8192 x 8192 (the benchmark): closed-form eigenfunctions (U = F /
+    lambda_pq) and the five-point residual of a random right-hand side.  The
+    refinement path is checked at 2048 x 2048: at 8192 the lowest modes' line
+    systems have cond ~ 1e7, where float sweeps no longer contract."""
+    tdt = _tdt()
+    h = 1.0 / (n + 1)
+    solver = tdt.Poisson2D(n, n, h, h, dtype)
+    t = tol(n, n, h, h)
+    for p, q in ((1, 1), (3, n // 2), (n, 17)):
+        print(f"[case] poisson {n}^2 dtype={dtype} eigen ({p},{q})", flush=True)
+        F, Uex = P2.eigen_solution(n, n, p, q, h, h)
+        U = to_host(solver.solve(to_dev(F)))
+        assert oracle.rel_err(U, Uex) <= t, (p, q, oracle.rel_err(U, Uex), t)
+    print(f"[case] poisson {n}^2 dtype={dtype} residual", flush=True)
+    F = np.random.default_rng(0).standard_normal((n, n))
+    U = to_host(solver.solve(to_dev(F)))
+    assert oracle.rel_err(P2.laplacian(U, h, h), F) <= t
+
+
+def test_poisson_errors_and_repeatable():
+    tdt = _tdt()
+    from paper_1002_2469_amd import _lib
+    with pytest.raises(_lib.TDTError):
+        tdt.Poisson2D(0, 5, 0.1, 0.1)
+    with pytest.raises(_lib.TDTError):
+        tdt.Poisson2D(5, 5, -0.1, 0.1)
+    with pytest.raises(ValueError):
+        tdt.Poisson2D(5, 5, 0.1, 0.1, "f32")
+    rng = np.random.default_rng(2)
+    F = to_dev(rng.standard_normal((300, 200)))
+    print("[case] poisson repeatable", flush=True)
+    solver = tdt.Poisson2D(200, 300, 0.01, 0.02)
+    assert np.array_equal(to_host(solver.solve(F)), to_host(solver.solve(F)))
