@@ -16,7 +16,10 @@ of the solve captured in a hipGraph), `sov_neumann` (the same batch with
 Neumann ends: quasi-Toeplitz systems with psi = chi = 1) and `diff` (1024
 systems of N = 16384 with their own T; a step is the forward solve plus the
 adjoint backward pass) and `general` (64 right-hand sides of N = 2**20 sharing a
-general tridiagonal matrix with per-row entries; paths f64 and f32).
+general tridiagonal matrix with per-row entries; paths f64 and f32) and
+`poisson2d` (the 2D Poisson problem on 8191 x 8191 interior points, 2^13
+intervals per side, solved end to end by separation of variables: sine
+transforms, 8191 line systems of 8191, inverse transforms; path f64).
 
 Prints one JSON line.  `roofline` is for the kernel with the longest average
 duration in the headline path, from HIP events recorded on the solve stream
@@ -44,7 +47,7 @@ if ROOT not in sys.path:
 
 METRIC = "unknowns/s + HBM GB/s (% peak): FP32+refine vs FP64 solve at rel err ≤1e-12"
 HBM_PEAK_GBS = 8000.0
-WORKLOADS = ("single_large", "series", "sov", "sov_neumann", "diff", "general")
+WORKLOADS = ("single_large", "series", "sov", "sov_neumann", "diff", "general", "poisson2d")
 
 
 def kernel_source_hash() -> str:
@@ -112,6 +115,13 @@ def load_workload(name: str, args):
                  desc=f"general: M={d['M']} right-hand sides of N={d['N']} sharing a general "
                       f"tridiagonal matrix (variable-coefficient diffusion-reaction rows, "
                       f"dominance 1.1-1.6), F~N(0,1) seed 0, [M][N] double in/out")
+    elif name == "poisson2d":
+        d = W.poisson2d(seed=0)
+        d.update(kind="poisson", units=d["nx"] * d["ny"],
+                 desc=f"poisson2d: five-point Poisson problem on {d['nx']}x{d['ny']} interior "
+                      f"points of the unit square, zero boundary, F~N(0,1) seed 0, [Ny][Nx] "
+                      f"double in/out; sine transforms (hipFFT) + one Toeplitz line system per "
+                      f"mode + inverse transforms")
     elif name == "diff":
         d = W.diff_batch(seed=0)
         d.update(kind="varlen", units=int(d["offsets"][-1]), adjoint=True,
@@ -220,6 +230,61 @@ def run_mode(tdt, d, F, X, mode, steps, warmup, torch, autotune=True):
     return out
 
 
+def run_poisson(tdt, d, F, mode, steps, warmup, torch):
+    """A step is one whole 2D solve (transforms and line solves)."""
+    solver = tdt.Poisson2D(d["nx"], d["ny"], d["hx"], d["hy"], mode)
+    U = torch.empty_like(F)
+    for _ in range(warmup):
+        solver.solve(F, U)
+    torch.cuda.synchronize()
+    solver.line_profile(True)
+    for _ in range(steps):
+        solver.solve(F, U)
+    torch.cuda.synchronize()
+    prof = solver.line_profile_read()
+    solver.line_profile(False)
+    n = max(prof["solves"], 1)
+    kern = {"line_first_pass": prof["first_pass_ms"] / n, "line_interface": prof["interface_ms"] / n,
+            "line_final_pass": prof["final_ms"] / n}
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(steps):
+        solver.solve(F, U)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / steps
+    out = dict(ms=ms, kernels_ms=kern, refine_iters=0, X=U.cpu().numpy().reshape(-1), tuned=None)
+    solver.close()
+    return out
+
+
+def cpu_leg_poisson(d, budget_s=12.0, n_sample=2048):
+    """The oracle (explicit sine transforms, Thomas per mode) on a smaller
+    grid of the same problem: at the full size its O(N^3) transforms take
+    minutes."""
+    import numpy as np
+    import oracle
+    from oracle import poisson2d as P2
+    threads = oracle.threads(0)
+    h = 1.0 / (n_sample + 1)
+    F = np.random.default_rng(1).standard_normal((n_sample, n_sample))
+    times = []
+    t_budget = time.perf_counter()
+    while len(times) < 10 and (time.perf_counter() - t_budget < budget_s or len(times) < 2):
+        t0 = time.perf_counter()
+        P2.solve(F, h, h)
+        times.append(time.perf_counter() - t0)
+    med = statistics.median(times)
+    return {"value": n_sample * n_sample / med, "unit": "unknowns/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"the same problem on a {n_sample}x{n_sample} grid (the oracle's explicit "
+                      f"sine transforms cost O(N^3): the full grid would take minutes), "
+                      f"numpy + the C Thomas oracle, {threads} thread(s), median of "
+                      f"{len(times)} runs of {med:.3f} s"}
+
+
 def cpu_leg(d, budget_s=12.0):
     """Time the oracle on this host (same inputs) and return its outputs."""
     import numpy as np
@@ -283,14 +348,18 @@ def main() -> int:
     X = torch.empty_like(F)
     torch.cuda.synchronize()
     if args.modes is None:
-        args.modes = "f64,f32" if args.workload == "general" else "f32_refine,f64"
+        args.modes = {"general": "f64,f32", "poisson2d": "f64"}.get(args.workload,
+                                                                    "f32_refine,f64")
     modes = [m for m in args.modes.split(",") if m]
     res = {}
     for mode in modes:
         Fm = F.float() if mode == "f32" else F      # plain float takes float data
         Xm = torch.empty_like(Fm) if mode == "f32" else X
-        res[mode] = run_mode(tdt, d, Fm, Xm, mode, args.steps, args.warmup, torch,
-                             autotune=not args.no_autotune)
+        if d["kind"] == "poisson":
+            res[mode] = run_poisson(tdt, d, F, mode, args.steps, args.warmup, torch)
+        else:
+            res[mode] = run_mode(tdt, d, Fm, Xm, mode, args.steps, args.warmup, torch,
+                                 autotune=not args.no_autotune)
         print(f"[bench] {args.workload} {mode}: {res[mode]['ms']:.4f} ms/step  kernels(ms) "
               f"{json.dumps({k: round(v, 5) for k, v in res[mode]['kernels_ms'].items()})}",
               file=sys.stderr, flush=True)
@@ -306,10 +375,14 @@ def main() -> int:
     head = modes[0]
     from paper_1002_2469_amd import _lib
     shape = (res[head]["tuned"] or {}).get("shape", 0)
-    n_first, n_final = tile_counts(d, _lib.SHAPES[shape][0] * _lib.SHAPES[shape][1])
+    if d["kind"] == "poisson":
+        n_first, n_final = 0, U
+    else:
+        n_first, n_final = tile_counts(d, _lib.SHAPES[shape][0] * _lib.SHAPES[shape][1])
     # algorithmic HBM bytes per launch of each kernel group (double data)
     per_launch = {"first_pass": 8.0 * n_first, "final_pass": 16.0 * n_final,
-                  "bwd_first_pass": 8.0 * n_first, "bwd_final_pass": 24.0 * n_final}
+                  "bwd_first_pass": 8.0 * n_first, "bwd_final_pass": 24.0 * n_final,
+                  "line_first_pass": 0.0, "line_interface": 0.0, "line_final_pass": 16.0 * n_final}
     names = {"first_pass": ("k_beta<double> (Green-row tile summaries, first pass)"
                             if d["kind"] == "series" else
                             "k_gtile<double, SUMMARY> (general matrix, tile summaries)"
@@ -319,12 +392,21 @@ def main() -> int:
                             if d["kind"] == "general" else
                             "k_tile<double, float, REFINE, final> (solve, refine and store)"
                             if head == "f32_refine" else "k_tile<double, double, final> (solve and store)"),
+             "line_final_pass": "k_sys<double, double> (the mode line systems, solved whole; "
+                                "the sine transforms around it are hipFFT's)",
              "bwd_first_pass": "k_tile<double, *, SUMMARY> on T^T (adjoint first pass)",
              "bwd_final_pass": "k_tile<..., BWD> (adjoint solve, store gF, dL/dt partial sums)"}
 
     cpu = None
     errs = {}
-    if not args.no_cpu:
+    if not args.no_cpu and d["kind"] == "poisson":
+        from oracle import poisson2d as P2
+        cpu = cpu_leg_poisson(d)
+        for mode in modes:
+            Um = res[mode]["X"].reshape(d["ny"], d["nx"])
+            r = P2.laplacian(Um, d["hx"], d["hy"]) - d["F"]
+            errs[mode] = {"residual": float(np.max(np.abs(r)) / np.max(np.abs(d["F"])))}
+    elif not args.no_cpu:
         cpu, Xo, gFo, gto = cpu_leg(d)
         import oracle
         for mode in modes:
@@ -344,7 +426,7 @@ def main() -> int:
         e = errs.get(mode)
         if e is None:
             return None
-        return e["X"] if len(e) == 1 else e
+        return e["X"] if len(e) == 1 and "X" in e else e
 
     def path_record(mode):
         r = res[mode]

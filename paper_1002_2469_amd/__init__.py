@@ -358,12 +358,28 @@ class Poisson2D:
                                                   _stream_handle(stream)), "tdt_poisson2d_solve")
         return U
 
-    def set_line_option(self, name: str, value: int):
-        """A launch option of the line plan (see Plan.set_option)."""
+    def _line(self):
         line = ctypes.c_void_p()
         _lib.check(_lib.lib().tdt_poisson2d_line_plan(self._h, ctypes.byref(line)),
                    "tdt_poisson2d_line_plan")
-        _lib.check(_lib.lib().tdt_plan_set_option(line, _lib.OPTIONS[name], int(value)),
+        return line
+
+    def line_profile(self, enable: bool = True):
+        """Record HIP events around the line plan's kernel groups."""
+        _lib.check(_lib.lib().tdt_plan_profile(self._line(), 1 if enable else 0),
+                   "tdt_plan_profile")
+
+    def line_profile_read(self) -> dict:
+        ms = np.zeros(3)
+        n = ctypes.c_int64(0)
+        _lib.check(_lib.lib().tdt_plan_profile_read(self._line(),
+                                                    ms.ctypes.data_as(ctypes.c_void_p),
+                                                    ctypes.byref(n)), "tdt_plan_profile_read")
+        return dict(first_pass_ms=ms[0], interface_ms=ms[1], final_ms=ms[2], solves=n.value)
+
+    def set_line_option(self, name: str, value: int):
+        """A launch option of the line plan (see Plan.set_option)."""
+        _lib.check(_lib.lib().tdt_plan_set_option(self._line(), _lib.OPTIONS[name], int(value)),
                    "tdt_plan_set_option")
 
     def close(self):

@@ -107,6 +107,16 @@ def general_series(seed: int = 0, n: int = 1 << 20, m: int = 64) -> dict:
     return dict(name="general_series", N=n, M=m, a=a, b=b, c=c, F=F)
 
 
+def poisson2d(seed: int = 0, n: int = 8191) -> dict:
+    """The 2D Poisson problem of the separation-of-variables application on
+    the unit square cut into n + 1 = 2^13 intervals per side (n x n interior
+    points, h = 1 / (n + 1)), F ~ N(0, 1) [Ny][Nx].  A power-of-two interval
+    count keeps the sine transforms' FFT length 2 (n + 1) a power of two."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / (n + 1)
+    return dict(name="poisson2d", nx=n, ny=n, hx=h, hy=h, F=rng.standard_normal((n, n)))
+
+
 def diff_batch(seed: int = 0, s: int = 1024, n: int = 16384) -> dict:
     rng = np.random.default_rng(seed)
     t0 = rng.uniform(2.5, 4.0, size=s)

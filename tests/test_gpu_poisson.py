@@ -1,7 +1,7 @@
 """GPU parity of the 2D Poisson solve by separation of variables (Sec. 3.2)
 against the CPU oracle (explicit sine transforms and Thomas per mode, itself
 pinned to the dense Kronecker-sum solve), through the C ABI; at the
-benchmark size (8192 x 8192) against the closed-form discrete eigenfunctions
+benchmark size (8191 x 8191) against the closed-form discrete eigenfunctions
 and the five-point residual, which hold at any size.
 
 Inputs: F ~ N(0, 1), spacings drawn in [0.002, 0.2] (unequal hx, hy)."""
@@ -67,12 +67,13 @@ def test_poisson_line_paths(whole):
     assert oracle.rel_err(U, P2.solve(F, hx, hy)) <= tol(nx, ny, hx, hy)
 
 
-@pytest.mark.parametrize("n,dtype", [(8192, "f64"), (2048, "f32_refine")])
+@pytest.mark.parametrize("n,dtype", [(8191, "f64"), (2047, "f32_refine")])
 def test_poisson_benchmark_size(n, dtype):
-    """8192 x 8192 (the benchmark): closed-form eigenfunctions (U = F /
-    lambda_pq) and the five-point residual of a random right-hand side.  The
-    refinement path is checked at 2048 x 2048: at 8192 the lowest modes' line
-    systems have cond ~ 1e7, where float sweeps no longer contract."""
+    """8191 x 8191 (the benchmark, 2^13 intervals per side): closed-form
+    eigenfunctions (U = F / lambda_pq) and the five-point residual of a random
+    right-hand side.  The refinement path is checked at 2047 x 2047: at 8191
+    the lowest modes' line systems have cond ~ 1e7, where float sweeps no
+    longer contract."""
     tdt = _tdt()
     h = 1.0 / (n + 1)
     solver = tdt.Poisson2D(n, n, h, h, dtype)
