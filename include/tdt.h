@@ -134,16 +134,50 @@ tdt_status_t tdt_plan_general_create(int64_t N, const double *h_a, const double 
                                      const double *h_c, tdt_dtype_t dtype,
                                      tdt_plan_t *out);
 
+/* Plan for batches of Toeplitz systems laid out along a slow axis (the
+ * lines along y or z of a row-major 2D or 3D array): P classes of matrices
+ * T_k = tridiag{h_tm1[k], h_t0[k], h_t1[k]} of order N (host arrays of P
+ * doubles, copied), 1 <= N <= 1024.  Solved with tdt_solve_strided, which
+ * runs the dichotomy method (Sec. 2.1-2.5) with one workgroup per column of
+ * adjacent systems: every lane holds a 16-row block of one system, the
+ * interface values of eq. (15) are scanned across the blocks inside the
+ * workgroup, and the blocks are corrected in registers.  The plan holds per
+ * class the block LU, the blocks' end values and the interface table of the
+ * column, computed in long double (17 + 2 ceil(N/16) doubles per class).
+ * dtype: TDT_F64 only.  Errors: N outside [1, 1024], P < 1, null arrays,
+ * non-finite entries, another dtype -> TDT_ERR_INVALID_ARG; a zero block
+ * pivot or a vanishing interface pivot -> TDT_ERR_SINGULAR; returns
+ * TDT_WARN_NOT_DOMINANT (plan valid) when some class has
+ * |t_0| < |t_-1| + |t_1|.  tdt_solve, tdt_solve_varlen, tdt_solve_backward,
+ * options and autotuning refuse such a plan (TDT_ERR_INVALID_ARG). */
+tdt_status_t tdt_plan_strided_create(int64_t N, int64_t P, const double *h_tm1,
+                                     const double *h_t0, const double *h_t1,
+                                     tdt_dtype_t dtype, tdt_plan_t *out);
+
+/* Solve system s = 0 .. M-1 (M <= P; system s uses class s) of every batch
+ * b = 0 .. nb-1: unknown i of system s of batch b is F[b*ldb + i*ld + s]
+ * (and X[...] likewise), i = 0 .. N-1.  F, X: device doubles, caller-owned;
+ * X may be F itself (in place) but must not overlap it otherwise.  The
+ * layout must be one of: batches one after another (ld >= M and, for
+ * nb > 1, ldb >= (N-1)*ld + M), or batches interleaved in each row
+ * (ldb >= M, ld >= (nb-1)*ldb + M); other layouts -> TDT_ERR_INVALID_ARG.
+ * No workspace; capturable in a hipGraph.  Under tdt_plan_profile the
+ * kernel time is reported as the third value of tdt_plan_profile_read. */
+tdt_status_t tdt_solve_strided(tdt_plan_t plan, const double *F, double *X, int64_t M,
+                               int64_t ld, int64_t nb, int64_t ldb, hipStream_t stream);
+
 /* 2D Poisson solve by separation of variables (the application of Sec. 3.2
  * and of the paper's timings): the five-point system
  *     (2u_ij - u_{i-1,j} - u_{i+1,j}) / hx^2 + (2u_ij - u_{i,j-1} - u_{i,j+1}) / hy^2 = f_ij
  * on Nx x Ny interior points with u = 0 on the boundary.  A sine transform
- * along x (a real FFT of each row's odd extension, hipFFT) leaves one
- * tridiagonal Toeplitz system per mode k along y, t_+-1 = -1,
+ * along x (a real FFT of length Nx+1 of each folded row, hipFFT, then a
+ * prefix sum for the odd coefficients) leaves one tridiagonal Toeplitz
+ * system per mode k along y, t_+-1 = -1,
  * t_0 = 2 + hy^2 (4/hx^2) sin^2(pi k / (2 (Nx+1))), solved by a varlen plan of
  * this library (dtype TDT_F64 or TDT_F32_REFINE); the inverse transform
- * gives U.  The handle owns the line plan, the FFT plan and 3 Nx Ny + 2 Ny
- * (Nx + 2) doubles of workspace (allocated here, blocking).  Errors: sizes
+ * gives U.  The handle owns the line plan, the FFT plan and
+ * 2 Nx Ny + Ny (Nx + 1) + 2 Ny (floor((Nx+1)/2) + 1) doubles of workspace
+ * (allocated here, blocking).  Errors: sizes
  * < 1 or Nx Ny > 2^31, non-positive or non-finite spacings, another dtype ->
  * TDT_ERR_INVALID_ARG; allocation -> TDT_ERR_OOM; an FFT plan failure ->
  * TDT_ERR_HIP. */

@@ -22,7 +22,7 @@ import numpy as np
 from . import _lib
 from ._lib import DTYPES, TDTError, build
 
-__all__ = ["Plan", "VarlenPlan", "solve", "solve_varlen", "TridiagToeplitzSolve", "block_constants",
+__all__ = ["Plan", "VarlenPlan", "GeneralPlan", "StridedPlan", "Poisson2D", "solve", "solve_varlen", "TridiagToeplitzSolve", "block_constants",
            "green_rows", "segment_merge", "build_info", "build", "TDTError"]
 
 
@@ -329,6 +329,61 @@ class GeneralPlan(_PlanBase):
             ctypes.c_void_p(gF.data_ptr()), ctypes.c_void_p(g.data_ptr()), M,
             _stream_handle(stream)), "tdt_solve_backward")
         return gF, g
+
+
+class StridedPlan(_PlanBase):
+    """Plan of P classes of Toeplitz matrices of order N <= 1024 (class k:
+    tridiag{t_m1[k], t_0[k], t_1[k]}) for systems along a slow axis: unknown
+    i of system s of batch b at element b*ldb + i*ld + s, system s using
+    class s.  float64 only.  Scalars broadcast over the P classes."""
+
+    def __init__(self, N: int, t_m1, t_0, t_1):
+        super().__init__()
+        t0 = np.ascontiguousarray(np.asarray(t_0, dtype=np.float64).reshape(-1))
+        self.N, self.P = int(N), int(t0.size)
+        self.t_0 = t0
+        self.t_m1 = np.ascontiguousarray(np.broadcast_to(np.asarray(t_m1, dtype=np.float64),
+                                                         (self.P,)))
+        self.t_1 = np.ascontiguousarray(np.broadcast_to(np.asarray(t_1, dtype=np.float64),
+                                                        (self.P,)))
+        self.dtype = "f64"
+        self.status = _lib.check(_lib.lib().tdt_plan_strided_create(
+            self.N, self.P, self.t_m1.ctypes.data_as(ctypes.c_void_p),
+            self.t_0.ctypes.data_as(ctypes.c_void_p), self.t_1.ctypes.data_as(ctypes.c_void_p),
+            DTYPES["f64"], ctypes.byref(self._h)), "tdt_plan_strided_create")
+
+    def solve(self, F, X=None, M=None, ld=None, nb=None, ldb=None, stream=None):
+        """F: float64 CUDA tensor.  Without layout arguments F is read as
+        [N][M] (ld = M) or [nb][N][M] (ldb = N*M).  X may be F (in place)."""
+        torch = _torch()
+        if not isinstance(F, torch.Tensor) or not F.is_cuda or F.dtype != torch.float64:
+            raise TypeError("F must be a float64 CUDA (HIP) tensor")
+        if not F.is_contiguous():
+            raise ValueError("F must be contiguous")
+        if M is None:
+            if F.dim() == 2:
+                nb, M, ld, ldb = 1, F.shape[1], F.shape[1], 0
+            elif F.dim() == 3:
+                nb, M, ld, ldb = F.shape[0], F.shape[2], F.shape[2], F.shape[1] * F.shape[2]
+            else:
+                raise ValueError("give the layout (M, ld, nb, ldb) for this shape")
+            if (F.shape[-2] != self.N):
+                raise ValueError(f"F has {F.shape[-2]} rows, the plan {self.N}")
+        nb = 1 if nb is None else int(nb)
+        ld = int(M) if ld is None else int(ld)
+        ldb = 0 if ldb is None else int(ldb)
+        extent = (nb - 1) * ldb + (self.N - 1) * ld + int(M)
+        if F.numel() < extent:
+            raise ValueError(f"F has {F.numel()} elements, the layout reaches {extent}")
+        if X is None:
+            X = torch.empty_like(F)
+        if X.shape != F.shape or X.dtype != F.dtype or not X.is_cuda or not X.is_contiguous():
+            raise ValueError("X must be a contiguous float64 CUDA tensor shaped like F")
+        _lib.check(_lib.lib().tdt_solve_strided(self._h, ctypes.c_void_p(F.data_ptr()),
+                                                ctypes.c_void_p(X.data_ptr()), int(M), ld, nb,
+                                                ldb, _stream_handle(stream)),
+                   "tdt_solve_strided")
+        return X
 
 
 class Poisson2D:

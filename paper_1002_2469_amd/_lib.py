@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libtdt.so")
 if os.environ.get("TDT_LIB_PATH"):
     LIB_PATH = os.environ["TDT_LIB_PATH"]
 SOURCES = [os.path.join(_HERE, "csrc", "tdt_kernels.hip"), os.path.join(_HERE, "csrc", "tdt_api.cpp"),
-           os.path.join(_HERE, "csrc", "tdt_poisson.hip")]
+           os.path.join(_HERE, "csrc", "tdt_poisson.hip"), os.path.join(_HERE, "csrc", "tdt_strided.hip")]
 HEADER = os.path.join(_ROOT, "include", "tdt.h")
 
 # status codes (include/tdt.h)
@@ -42,7 +42,8 @@ EXPORTS = [
     "tdt_plan_profile_read", "tdt_build_info", "tdt_plan_set_option", "tdt_plan_get_option",
     "tdt_plan_autotune", "tdt_plan_quasi_create", "tdt_plan_varlen_quasi_create",
     "tdt_plan_general_create", "tdt_poisson2d_create", "tdt_poisson2d_solve",
-    "tdt_poisson2d_line_plan", "tdt_poisson2d_destroy",
+    "tdt_poisson2d_line_plan", "tdt_poisson2d_destroy", "tdt_plan_strided_create",
+    "tdt_solve_strided",
 ]
 
 # tdt_option_t
@@ -96,6 +97,8 @@ def lib():
         "tdt_poisson2d_solve": [p, p, p, p],
         "tdt_poisson2d_line_plan": [p, pp],
         "tdt_poisson2d_destroy": [p],
+        "tdt_plan_strided_create": [i64, i64, p, p, p, i32, pp],
+        "tdt_solve_strided": [p, p, p, i64, i64, i64, i64, p],
         "tdt_plan_reserve": [p, i64],
         "tdt_solve": [p, p, p, i64, p],
         "tdt_solve_varlen": [p, p, p, p],

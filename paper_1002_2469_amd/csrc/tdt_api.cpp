@@ -47,6 +47,11 @@ struct tdt_plan_s {
   double* dgtK[2] = {nullptr, nullptr};
   void* dggreen[2] = {nullptr, nullptr};   // first and last row of each tile's inverse
   int64_t reserved_M = 0;
+  // strided batch plan (systems along a slow axis): P classes of order N
+  bool strided = false;
+  int64_t sP = 0;
+  int sC = 0;
+  double* dstr = nullptr;   // iu [kStrB][P] | sc [kStrScalarN][P] | pos [2][C][P]
   bool varlen = false;
   tdt_dtype_t dtype = TDT_F64;
   int64_t N = 0;          // series: order of the system (with its corner rows)
@@ -443,6 +448,7 @@ void destroy(tdt_plan_s* p) {
     (void)hipFree(p->dgtK[k]);
     (void)hipFree(p->dggreen[k]);
   }
+  (void)hipFree(p->dstr);
   (void)hipFree(p->dp1);
   (void)hipFree(p->dfin);
   (void)hipFree(p->dgrid);
@@ -1048,6 +1054,61 @@ tdt_status_t run(tdt_plan_s* p, int dir, const void* F, void* X, const void* Xfw
 
 }  // namespace
 
+// Tables of a strided batch (systems along a slow axis, one workgroup per
+// column of adjacent systems): per class the block LU pivots, the end values
+// of a full block and of the last block, and the left-to-right interface
+// table over the C block positions of a column (beta_{c-1} and
+// 1/(1 - phi_first(c) beta_{c-1}), each block with its own end values).
+namespace tdt {
+int strided_tables(int64_t N, int64_t P, const double* tm1, const double* t0, const double* t1,
+                   double* iu, double* sc, double* pos, double* dominance) {
+  if (N < 1 || N > (int64_t)kStrMaxChunks * kStrB || P < 1 || !tm1 || !t0 || !t1)
+    return TDT_ERR_INVALID_ARG;
+  const int C = strided_chunks(N);
+  const int bt = (int)(N - (int64_t)(C - 1) * kStrB);
+  double dom = std::numeric_limits<double>::infinity();
+  ld iuv[kStrB], cp[kStrB], phi[kStrB], chi[kStrB];
+  for (int64_t k = 0; k < P; ++k) {
+    const double a = tm1[k], b = t0[k], c = t1[k];
+    if (!finite3(a, b, c)) return TDT_ERR_INVALID_ARG;
+    dom = std::min(dom, dominance_ratio(a, b, c));
+    if (!block_vectors(a, b, c, kStrB, iuv, cp, phi, chi)) return TDT_ERR_SINGULAR;
+    for (int i = 0; i < kStrB; ++i) {
+      iu[(int64_t)i * P + k] = (double)iuv[i];
+      if (!std::isfinite(iu[(int64_t)i * P + k])) return TDT_ERR_SINGULAR;
+    }
+    const ld full[4] = {phi[0], phi[kStrB - 1], chi[0], chi[kStrB - 1]};
+    ld tail[4];
+    if (bt == kStrB) {
+      for (int e = 0; e < 4; ++e) tail[e] = full[e];
+    } else if (!segment_ends(a, b, c, bt, tail)) {
+      return TDT_ERR_SINGULAR;
+    }
+    sc[kStrTM1 * P + k] = a;
+    sc[kStrT1 * P + k] = c;
+    sc[kStrPF * P + k] = (double)full[0];
+    sc[kStrPL * P + k] = (double)full[1];
+    sc[kStrCF * P + k] = (double)full[2];
+    sc[kStrTPF * P + k] = (double)tail[0];
+    sc[kStrTPL * P + k] = (double)tail[1];
+    sc[kStrTCF * P + k] = (double)tail[2];
+    ld beta = 0.0L;
+    for (int m = 0; m < C; ++m) {
+      const ld* e = m == C - 1 ? tail : full;
+      const ld D = 1.0L - e[0] * beta;
+      if (!(std::fabs((double)D) > 1e-13)) return TDT_ERR_SINGULAR;
+      const ld iD = 1.0L / D;
+      pos[(int64_t)m * P + k] = (double)beta;
+      pos[((int64_t)C + m) * P + k] = (double)iD;
+      beta = e[3] + e[1] * e[2] * beta * iD;
+      if (!std::isfinite((double)beta)) return TDT_ERR_SINGULAR;
+    }
+  }
+  if (dominance) *dominance = dom;
+  return TDT_OK;
+}
+}  // namespace tdt
+
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
@@ -1324,6 +1385,87 @@ tdt_status_t tdt_plan_general_create(int64_t N, const double* h_a, const double*
   return st;
 }
 
+tdt_status_t tdt_plan_strided_create(int64_t N, int64_t P, const double* h_tm1,
+                                     const double* h_t0, const double* h_t1, tdt_dtype_t dtype,
+                                     tdt_plan_t* out) {
+  if (!out) return TDT_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (N < 1 || N > (int64_t)tdt::kStrMaxChunks * tdt::kStrB || P < 1 || P > ((int64_t)1 << 31) ||
+      !h_tm1 || !h_t0 || !h_t1 || dtype != TDT_F64)
+    return TDT_ERR_INVALID_ARG;
+  const int C = tdt::strided_chunks(N);
+  const int64_t nv = (int64_t)(tdt::kStrB + tdt::kStrScalarN + 2 * C) * P;
+  std::vector<double> tab((size_t)nv);
+  double dom = 0.0;
+  double* iu = tab.data();
+  double* sc = iu + (int64_t)tdt::kStrB * P;
+  double* pos = sc + (int64_t)tdt::kStrScalarN * P;
+  const int st = tdt::strided_tables(N, P, h_tm1, h_t0, h_t1, iu, sc, pos, &dom);
+  if (st < 0) return (tdt_status_t)st;
+  tdt_plan_s* p = new (std::nothrow) tdt_plan_s();
+  if (!p) return TDT_ERR_OOM;
+  p->strided = true;
+  p->dtype = dtype;
+  p->N = N;
+  p->S = P;
+  p->sP = P;
+  p->sC = C;
+  p->dominance = dom;
+  p->kappa = 0.0;
+  tdt_status_t s = dev_upload(&p->dstr, tab.data(), tab.size());
+  if (s != TDT_OK) {
+    destroy(p);
+    return s;
+  }
+  *out = p;
+  return dom < 1.0 ? TDT_WARN_NOT_DOMINANT : TDT_OK;
+}
+
+tdt_status_t tdt_solve_strided(tdt_plan_t p, const double* F, double* X, int64_t M, int64_t ld,
+                               int64_t nb, int64_t ldb, hipStream_t stream) {
+  if (!p || !p->strided || !F || !X || M < 1 || M > p->sP || nb < 1 || ld < 1 || ldb < 0)
+    return TDT_ERR_INVALID_ARG;
+  const int64_t N = p->N;
+  // the two layouts whose addresses b*ldb + i*ld + s are all distinct: batches
+  // one after the other, or batches interleaved inside each row
+  const bool outer = ld >= M && (nb == 1 || ldb >= (N - 1) * ld + M);
+  const bool inner = ldb >= M && ld >= (nb - 1) * ldb + M;
+  if (!outer && !inner) return TDT_ERR_INVALID_ARG;
+  const int64_t extent = (nb - 1) * ldb + (N - 1) * ld + M;
+  const size_t bytes = (size_t)extent * sizeof(double);
+  if (F != X && overlaps(F, bytes, X, bytes)) return TDT_ERR_INVALID_ARG;
+  tdt::StridedArgs a{};
+  a.R = F;
+  a.O = X;
+  a.G = nullptr;
+  a.epi = nullptr;
+  a.iu = p->dstr;
+  a.sc = a.iu + (int64_t)tdt::kStrB * p->sP;
+  a.pos = a.sc + (int64_t)tdt::kStrScalarN * p->sP;
+  a.N = N;
+  a.P = p->sP;
+  a.M = M;
+  a.ld = ld;
+  a.nb = nb;
+  a.ldb = ldb;
+  a.C = p->sC;
+  hipEvent_t* ev = nullptr;
+  if (p->profile) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
+      const size_t k = p->prof_ev.size();
+      p->prof_ev.resize(k + 4);
+      for (size_t j = 0; j < 4; ++j)
+        if (hipEventCreate(&p->prof_ev[k + j]) != hipSuccess) return TDT_ERR_HIP;
+      ev = p->prof_ev.data() + k;
+      for (int j = 0; j < 3; ++j) (void)hipEventRecord(ev[j], stream);
+    }
+  }
+  if (tdt::launch_strided(a, stream) != hipSuccess) return TDT_ERR_HIP;
+  if (ev) (void)hipEventRecord(ev[3], stream);
+  return TDT_OK;
+}
+
 tdt_status_t tdt_plan_varlen_quasi_create(int64_t S, const int64_t* h_offsets,
                                           const double* h_tm1, const double* h_t0,
                                           const double* h_t1, const double* h_psi,
@@ -1338,6 +1480,7 @@ tdt_status_t tdt_plan_varlen_quasi_create(int64_t S, const int64_t* h_offsets,
 
 tdt_status_t tdt_plan_reserve(tdt_plan_t p, int64_t M_max) {
   if (!p || M_max < 1) return TDT_ERR_INVALID_ARG;
+  if (p->strided) return TDT_OK;   // no workspace
   p->reserved_M = std::max(p->reserved_M, M_max);
   int64_t slots, fslots;
   if (p->general) {
@@ -1354,14 +1497,14 @@ tdt_status_t tdt_plan_reserve(tdt_plan_t p, int64_t M_max) {
 }
 
 tdt_status_t tdt_solve(tdt_plan_t p, const void* F, void* X, int64_t M, hipStream_t stream) {
-  if (!p || p->varlen || !F || !X || M < 1) return TDT_ERR_INVALID_ARG;
+  if (!p || p->varlen || p->strided || !F || !X || M < 1) return TDT_ERR_INVALID_ARG;
   const size_t bytes = (size_t)M * (size_t)p->N * elem_size(p->dtype);
   if (overlaps(F, bytes, X, bytes)) return TDT_ERR_INVALID_ARG;
   return run(p, 0, F, X, nullptr, M, stream);
 }
 
 tdt_status_t tdt_solve_varlen(tdt_plan_t p, const void* F, void* X, hipStream_t stream) {
-  if (!p || !p->varlen || !F || !X) return TDT_ERR_INVALID_ARG;
+  if (!p || !p->varlen || p->strided || !F || !X) return TDT_ERR_INVALID_ARG;
   const size_t bytes = (size_t)p->total * elem_size(p->dtype);
   if (overlaps(F, bytes, X, bytes)) return TDT_ERR_INVALID_ARG;
   return run(p, 0, F, X, nullptr, 1, stream);
@@ -1369,7 +1512,7 @@ tdt_status_t tdt_solve_varlen(tdt_plan_t p, const void* F, void* X, hipStream_t 
 
 tdt_status_t tdt_solve_backward(tdt_plan_t p, const void* gX, const void* X, void* gF,
                                 double* d_gt, int64_t M, hipStream_t stream) {
-  if (!p || !gX || !X || !gF) return TDT_ERR_INVALID_ARG;
+  if (!p || p->strided || !gX || !X || !gF) return TDT_ERR_INVALID_ARG;
   if (p->varlen) M = 1;
   if (M < 1) return TDT_ERR_INVALID_ARG;
   const size_t bytes =
@@ -1407,6 +1550,11 @@ tdt_status_t tdt_last_info(tdt_plan_t p, int* n_refine_iters, double* last_rel_u
   if (dominance) *dominance = p->dominance;
   if (kappa2) *kappa2 = p->kappa;
   if (!n_refine_iters && !last_rel_update) return TDT_OK;
+  if (!p->iters) {   // no refinement in this kind of plan
+    if (n_refine_iters) *n_refine_iters = 0;
+    if (last_rel_update) *last_rel_update = 0.0;
+    return TDT_OK;
+  }
   int v[2] = {0, 0};
   if (hipDeviceSynchronize() != hipSuccess ||
       hipMemcpy(v, p->iters, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess ||
@@ -1424,7 +1572,7 @@ tdt_status_t tdt_last_info(tdt_plan_t p, int* n_refine_iters, double* last_rel_u
 }
 
 tdt_status_t tdt_plan_set_option(tdt_plan_t p, tdt_option_t opt, int64_t value) {
-  if (!p) return TDT_ERR_INVALID_ARG;
+  if (!p || p->strided) return TDT_ERR_INVALID_ARG;
   switch (opt) {
     case TDT_OPT_WHOLE_MAX_TILES: {
       if (!p->varlen || value < 0 || value > tdt::kSysMaxTiles) return TDT_ERR_INVALID_ARG;
@@ -1467,7 +1615,7 @@ tdt_status_t tdt_plan_get_option(tdt_plan_t p, tdt_option_t opt, int64_t* value)
 tdt_status_t tdt_plan_autotune(tdt_plan_t p, const void* F, void* X, int64_t M,
                                hipStream_t stream, int flags, double* best_ms) {
   if (best_ms) *best_ms = 0.0;
-  if (!p || !F || !X) return TDT_ERR_INVALID_ARG;
+  if (!p || p->strided || !F || !X) return TDT_ERR_INVALID_ARG;
   if (p->varlen) M = 1;
   if (M < 1) return TDT_ERR_INVALID_ARG;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;

@@ -131,6 +131,19 @@ def test_argument_validation_without_device():
     offq = np.array([0, 5, 8], dtype=np.int64)
     assert L.tdt_plan_varlen_quasi_create(2, p(offq), p(t3), p(t3), p(t3), None, p(t3), 0,
                                           ctypes.byref(h)) == _lib.TDT_ERR_INVALID_ARG
+    # strided plans: 1 <= N <= 1024, P >= 1, finite entries, f64 only; a zero
+    # block pivot is found on the host
+    tm, t0s, tp = -np.ones(3), np.full(3, 4.0), -np.ones(3)
+    for n, P_, dt in ((0, 3, 0), (1025, 3, 0), (10, 0, 0), (10, 3, 1), (10, 3, 2)):
+        assert L.tdt_plan_strided_create(n, P_, p(tm), p(t0s), p(tp), dt, ctypes.byref(h)) == \
+            _lib.TDT_ERR_INVALID_ARG, (n, P_, dt)
+    bad = np.array([4.0, float("nan"), 4.0])
+    assert L.tdt_plan_strided_create(10, 3, p(tm), p(bad), p(tp), 0, ctypes.byref(h)) == \
+        _lib.TDT_ERR_INVALID_ARG
+    sing = np.array([4.0, 0.0, 4.0])
+    assert L.tdt_plan_strided_create(10, 3, p(tm), p(sing), p(tp), 0, ctypes.byref(h)) == \
+        _lib.TDT_ERR_SINGULAR
+    assert L.tdt_solve_strided(None, None, None, 1, 1, 1, 0, None) == _lib.TDT_ERR_INVALID_ARG
     out = np.empty(4 * 3 + 4)
     assert L.tdt_block_constants(1.0, 0.0, 1.0, 3, p(out)) == _lib.TDT_ERR_SINGULAR
     assert L.tdt_block_constants(1.0, 2.0, 1.0, 65, p(out)) == _lib.TDT_ERR_INVALID_ARG
