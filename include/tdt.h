@@ -194,6 +194,49 @@ tdt_status_t tdt_poisson2d_solve(tdt_poisson_t p, const double *F, double *U,
 tdt_status_t tdt_poisson2d_line_plan(tdt_poisson_t p, tdt_plan_t *line);
 tdt_status_t tdt_poisson2d_destroy(tdt_poisson_t p);
 
+/* 3D Poisson solve of Sec. 3.5: the seven-point system
+ *     (2u - u_{i-1} - u_{i+1}) / hx^2 + (... along y) / hy^2 + (... along z) / hz^2 = f
+ * on Nx x Ny x Nz interior points, u = 0 on the boundary, F and U [Nz][Ny][Nx]
+ * doubles.  A sine transform along x (as in the 2D solve) leaves one 2D
+ * problem (A_y + A_z + mu_k) v_k = fhat_k per mode k, each solved by
+ * Peaceman-Rachford ADI (the shift split evenly between the two directions)
+ * whose half-steps are strided batches of Toeplitz line systems
+ * (tdt_solve_strided's kernel: lines along y, then along z, every plane's
+ * modes at once), then the inverse transform.  The ADI parameters of mode k
+ * are the optimal (Jordan, Wachspress) set w_j = b dn((2j-1) K / (2 J_k), m),
+ * m = 1 - (a/b)^2, for the interval [a, b] holding the spectra of both
+ * directions' operators; J_k is the smallest count whose error bound for a
+ * full cycle, d_J^2 with d_J = prod_j (w_j - a)/(w_j + a), is <= eps, so the
+ * 2-norm error of the result relative to the exact discrete solution is at
+ * most eps (plus rounding).  J_k falls as k grows.  1 <= Ny, Nz <= 1024,
+ * 640 Nx Ny < 2^31 (31-bit byte offsets of the z lines), 0 < eps < 1.  The handle
+ * owns the FFT plan, the per-iteration tables (~(36 + 4 ceil(N/16)) doubles
+ * per mode and iteration) and (2 Nx + 3) Ny Nz doubles of workspace
+ * (allocated here, blocking).  Errors: bad sizes, spacings or eps ->
+ * TDT_ERR_INVALID_ARG; allocation -> TDT_ERR_OOM; FFT plan -> TDT_ERR_HIP. */
+typedef struct tdt_poisson3d_s *tdt_poisson3d_t;
+tdt_status_t tdt_poisson3d_create(int64_t nx, int64_t ny, int64_t nz, double hx, double hy,
+                                  double hz, double eps, tdt_poisson3d_t *out);
+/* U = A^{-1} F (to the ADI bound); F, U: device, caller-owned, distinct.
+ * Enqueued on stream; one handle must not run two solves at once. */
+tdt_status_t tdt_poisson3d_solve(tdt_poisson3d_t p, const double *F, double *U,
+                                 hipStream_t stream);
+/* The ADI schedule: h_counts[k] = J_k (Nx ints, may be NULL), h_omega[k *
+ * jmax + j] = w_{k,j+1} for j < J_k, 0 after (omega_len >= Nx * jmax doubles,
+ * may be NULL), *jmax = J_1 (the largest count). */
+tdt_status_t tdt_poisson3d_schedule(tdt_poisson3d_t p, int *h_counts, double *h_omega,
+                                    int64_t omega_len, int *jmax);
+/* HIP events around the forward transform, the ADI iterations and the
+ * inverse transform of every later solve; _read returns their summed ms
+ * and the number of solves, and clears the record. */
+tdt_status_t tdt_poisson3d_profile(tdt_poisson3d_t p, int enable);
+tdt_status_t tdt_poisson3d_profile_read(tdt_poisson3d_t p, double *ms3, int64_t *nsolves);
+tdt_status_t tdt_poisson3d_destroy(tdt_poisson3d_t p);
+/* Host-only test hook: the J optimal ADI parameters for [a, b] (largest
+ * first; out: J doubles) and their bound d_J (may be NULL), as the 3D solve
+ * computes them.  0 < a <= b, 1 <= J <= 400, else TDT_ERR_INVALID_ARG. */
+tdt_status_t tdt_adi_parameters(double a, double b, int J, double *out, double *bound);
+
 /* Allocate the workspace for up to M_max right-hand sides now, so that later
  * solves allocate nothing and may be captured in a hipGraph.  Blocking. */
 tdt_status_t tdt_plan_reserve(tdt_plan_t plan, int64_t M_max);

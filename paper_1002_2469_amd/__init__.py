@@ -22,7 +22,7 @@ import numpy as np
 from . import _lib
 from ._lib import DTYPES, TDTError, build
 
-__all__ = ["Plan", "VarlenPlan", "GeneralPlan", "StridedPlan", "Poisson2D", "solve", "solve_varlen", "TridiagToeplitzSolve", "block_constants",
+__all__ = ["Plan", "VarlenPlan", "GeneralPlan", "StridedPlan", "Poisson2D", "Poisson3D", "solve", "solve_varlen", "TridiagToeplitzSolve", "block_constants",
            "green_rows", "segment_merge", "build_info", "build", "TDTError"]
 
 
@@ -449,6 +449,72 @@ class Poisson2D:
             pass
 
 
+class Poisson3D:
+    """3D Poisson solve of Sec. 3.5: the seven-point system on Nx x Ny x Nz
+    interior points with zero boundary values, F and U [Nz][Ny][Nx] float64
+    on the device.  Sine transform along x (hipFFT), Peaceman-Rachford ADI
+    on every mode's (y, z) plane with the optimal parameters (strided line
+    solves along y and z), inverse transform.  eps bounds the ADI error
+    relative to the exact discrete solution (2-norm)."""
+
+    def __init__(self, nx: int, ny: int, nz: int, hx: float, hy: float, hz: float,
+                 eps: float = 1e-13):
+        self._h = ctypes.c_void_p()
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.hx, self.hy, self.hz, self.eps = float(hx), float(hy), float(hz), float(eps)
+        _lib.check(_lib.lib().tdt_poisson3d_create(self.nx, self.ny, self.nz, self.hx, self.hy,
+                                                   self.hz, self.eps, ctypes.byref(self._h)),
+                   "tdt_poisson3d_create")
+
+    def solve(self, F, U=None, stream=None):
+        torch = _torch()
+        n = self.nx * self.ny * self.nz
+        _check_tensor(F, torch.float64, n, "F")
+        if U is None:
+            U = torch.empty_like(F)
+        _check_tensor(U, torch.float64, n, "U")
+        _lib.check(_lib.lib().tdt_poisson3d_solve(self._h, ctypes.c_void_p(F.data_ptr()),
+                                                  ctypes.c_void_p(U.data_ptr()),
+                                                  _stream_handle(stream)), "tdt_poisson3d_solve")
+        return U
+
+    def schedule(self):
+        """(counts J_k [Nx], parameters [Nx][jmax] with zeros past J_k)."""
+        jm = ctypes.c_int(0)
+        _lib.check(_lib.lib().tdt_poisson3d_schedule(self._h, None, None, 0, ctypes.byref(jm)),
+                   "tdt_poisson3d_schedule")
+        counts = np.zeros(self.nx, dtype=np.int32)
+        om = np.zeros((self.nx, jm.value))
+        _lib.check(_lib.lib().tdt_poisson3d_schedule(
+            self._h, counts.ctypes.data_as(ctypes.c_void_p), om.ctypes.data_as(ctypes.c_void_p),
+            om.size, ctypes.byref(jm)), "tdt_poisson3d_schedule")
+        return counts, om
+
+    def profile(self, enable: bool = True):
+        _lib.check(_lib.lib().tdt_poisson3d_profile(self._h, 1 if enable else 0),
+                   "tdt_poisson3d_profile")
+
+    def profile_read(self) -> dict:
+        ms = np.zeros(3)
+        n = ctypes.c_int64(0)
+        _lib.check(_lib.lib().tdt_poisson3d_profile_read(self._h,
+                                                         ms.ctypes.data_as(ctypes.c_void_p),
+                                                         ctypes.byref(n)),
+                   "tdt_poisson3d_profile_read")
+        return dict(forward_ms=ms[0], adi_ms=ms[1], inverse_ms=ms[2], solves=n.value)
+
+    def close(self):
+        if self._h:
+            _lib.lib().tdt_poisson3d_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 _plan_cache: dict = {}
 
 
@@ -554,6 +620,17 @@ def segment_merge(left, right) -> np.ndarray:
                                             out.ctypes.data_as(ctypes.c_void_p)),
                "tdt_segment_merge")
     return out
+
+
+def adi_parameters(a: float, b: float, J: int):
+    """Host hook: the 3D solve's J optimal ADI parameters for [a, b] and
+    their error bound d_J."""
+    out = np.zeros(int(J))
+    bound = ctypes.c_double(0.0)
+    _lib.check(_lib.lib().tdt_adi_parameters(float(a), float(b), int(J),
+                                             out.ctypes.data_as(ctypes.c_void_p),
+                                             ctypes.byref(bound)), "tdt_adi_parameters")
+    return out, bound.value
 
 
 def build_info() -> dict:

@@ -43,7 +43,9 @@ EXPORTS = [
     "tdt_plan_autotune", "tdt_plan_quasi_create", "tdt_plan_varlen_quasi_create",
     "tdt_plan_general_create", "tdt_poisson2d_create", "tdt_poisson2d_solve",
     "tdt_poisson2d_line_plan", "tdt_poisson2d_destroy", "tdt_plan_strided_create",
-    "tdt_solve_strided",
+    "tdt_solve_strided", "tdt_poisson3d_create", "tdt_poisson3d_solve", "tdt_poisson3d_schedule",
+    "tdt_poisson3d_profile", "tdt_poisson3d_profile_read", "tdt_poisson3d_destroy",
+    "tdt_adi_parameters",
 ]
 
 # tdt_option_t
@@ -99,6 +101,13 @@ def lib():
         "tdt_poisson2d_destroy": [p],
         "tdt_plan_strided_create": [i64, i64, p, p, p, i32, pp],
         "tdt_solve_strided": [p, p, p, i64, i64, i64, i64, p],
+        "tdt_poisson3d_create": [i64, i64, i64, d, d, d, d, pp],
+        "tdt_poisson3d_solve": [p, p, p, p],
+        "tdt_poisson3d_schedule": [p, p, p, i64, ctypes.POINTER(i32)],
+        "tdt_poisson3d_profile": [p, i32],
+        "tdt_poisson3d_profile_read": [p, p, ctypes.POINTER(i64)],
+        "tdt_poisson3d_destroy": [p],
+        "tdt_adi_parameters": [d, d, i32, p, p],
         "tdt_plan_reserve": [p, i64],
         "tdt_solve": [p, p, p, i64, p],
         "tdt_solve_varlen": [p, p, p, p],

@@ -23,11 +23,13 @@
 #include <hipfft/hipfft.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <cmath>
 #include <new>
 #include <vector>
 
 #include "tdt.h"
+#include "tdt_internal.h"
 
 struct tdt_poisson_s {
   int64_t nx = 0, ny = 0;
@@ -67,15 +69,16 @@ __global__ void k_fold_rows(const double* __restrict__ F, const double* __restri
 
 // In place on each spectrum row: Re Y_k -> S_{2k+1} (Re Y_0 / 2 plus the
 // inclusive prefix sum of Re Y_1..Re Y_k); Im Y_k (= -S_{2k}) is kept.  With
-// U non-null (the inverse transform) the row's coefficients S_1..S_Nx are
-// written to U's row instead, unscaled.  One workgroup per row walks it in
+// U non-null the row's coefficients S_1..S_Nx, times scale, are written to
+// U's row instead.  One workgroup per row walks it in
 // segments of 4 kScanNT entries: each thread takes 4 consecutive entries
 // (coalesced), the thread totals are scanned across the wavefront by
 // shuffles and across the wavefronts through LDS, and a carry runs from
 // segment to segment (a fixed summation order).
 __global__ __launch_bounds__(kScanNT) void k_scan_rows(double* __restrict__ spec,
                                                        int64_t nx, int64_t ny,
-                                                       double* __restrict__ U) {
+                                                       double* __restrict__ U,
+                                                       double scale) {
   constexpr int E = 4, NW = kScanNT / 64;
   __shared__ double wtot[NW];
   const int64_t K = (nx + 1) / 2 + 1;                  // complex entries per row
@@ -119,8 +122,8 @@ __global__ __launch_bounds__(kScanNT) void k_scan_rows(double* __restrict__ spec
         if (U) {
           // S_{2k+1} = acc, S_{2k} = -Im Y_k; U[m-1] = S_m for m = 1..Nx
           double* u = U + r * nx;
-          if (2 * k + 1 <= nx) u[2 * k] = acc;
-          if (k >= 1 && 2 * k <= nx) u[2 * k - 1] = -im[e];
+          if (2 * k + 1 <= nx) u[2 * k] = scale * acc;
+          if (k >= 1 && 2 * k <= nx) u[2 * k - 1] = -scale * im[e];
         } else {
           row[2 * k] = acc;
         }
@@ -282,7 +285,7 @@ tdt_status_t tdt_poisson2d_solve(tdt_poisson_t p, const double* F, double* U,
                      stream, F, p->sn, p->y, nx, ny);
   if (hipfftExecD2Z(p->fft, p->y, spec) != HIPFFT_SUCCESS) return TDT_ERR_HIP;
   hipLaunchKernelGGL(k_scan_rows, dim3(gy(ny)), dim3(kScanNT), 0, stream, p->spec, nx, ny,
-                     (double*)nullptr);
+                     (double*)nullptr, 1.0);
   const double s = p->hy * p->hy * 2.0 / (double)(nx + 1);
   hipLaunchKernelGGL(k_modes_from_rows, tiles, dim3(kTileP, 8), 0, stream, p->spec, p->T, nx,
                      ny, s);
@@ -293,7 +296,8 @@ tdt_status_t tdt_poisson2d_solve(tdt_poisson_t p, const double* F, double* U,
   hipLaunchKernelGGL(k_fold_modes, tiles, dim3(kTileP, 8), 0, stream, p->V, p->sn, p->y, nx,
                      ny);
   if (hipfftExecD2Z(p->fft, p->y, spec) != HIPFFT_SUCCESS) return TDT_ERR_HIP;
-  hipLaunchKernelGGL(k_scan_rows, dim3(gy(ny)), dim3(kScanNT), 0, stream, p->spec, nx, ny, U);
+  hipLaunchKernelGGL(k_scan_rows, dim3(gy(ny)), dim3(kScanNT), 0, stream, p->spec, nx, ny, U,
+                     1.0);
   return hipGetLastError() == hipSuccess ? TDT_OK : TDT_ERR_HIP;
 }
 
@@ -306,6 +310,395 @@ tdt_status_t tdt_poisson2d_line_plan(tdt_poisson_t p, tdt_plan_t* line) {
 tdt_status_t tdt_poisson2d_destroy(tdt_poisson_t p) {
   if (!p) return TDT_ERR_INVALID_ARG;
   destroy_poisson(p);
+  return TDT_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// 3D Poisson problem (Sec. 3.5): a sine transform along x leaves, for every
+// mode k, a 2D problem on the (y, z) plane,
+//     (A_y + A_z + mu_k) v_k = fhat_k,   A_y v = (2 v_j - v_{j-1} - v_{j+1}) / hy^2 (A_z alike),
+// solved by Peaceman-Rachford ADI with the shift split evenly, A1 = A_y + mu_k/2
+// and A2 = A_z + mu_k/2, from v = 0:
+//     (w_j + A1) v'  = (w_j - A2) v  + fhat,
+//     (w_j + A2) v'' = (w_j - A1) v' + fhat,       j = 1 .. J_k.
+// Each half-step is one strided batch of Toeplitz line systems (lines along
+// y, then along z, all modes of a plane at once; no transposes).  Its
+// right-hand side never needs the other direction's operator: with R1 the
+// first half-step's right-hand side, (w - A1) v' + fhat = 2 w v' - R1 + fhat,
+// and the next iteration's (w' - A2) v'' + fhat = (w' + w) v'' - R2 + fhat, so
+// each solve writes the next right-hand side directly (the fused epilogue),
+// and the last one of a mode writes v''.
+// Parameters: the optimal set of Jordan and Wachspress for the interval
+// [a_k, b_k] holding both spectra, w_j = b dn((2j - 1) K / (2J), m),
+// m = 1 - (a/b)^2; J_k is the smallest J whose error bound d_J^2 <= eps,
+// d_J = prod_j (w_j - a) / (w_j + a), the largest error factor of one
+// direction on [a, b] for this set.
+// ---------------------------------------------------------------------------
+struct tdt_poisson3d_s {
+  int64_t nx = 0, ny = 0, nz = 0;
+  double hx = 0.0, hy = 0.0, hz = 0.0, eps = 0.0;
+  hipfftHandle fft = 0;
+  bool fft_made = false;
+  double* sn = nullptr;     // sin(pi j / (Nx + 1)), j = 0 .. Nx
+  double* y = nullptr;      // [Ny Nz][Nx + 1] folded rows
+  double* spec = nullptr;   // [Ny Nz][(Nx + 1) / 2 + 1] complex spectra; the ADI work array
+  double* tabs = nullptr;   // per iteration and direction: iu | sc | pos | epi of its modes
+  std::vector<int> count;                  // J_k
+  std::vector<double> omega;               // [k][jmax]
+  int jmax = 0;
+  std::vector<int64_t> active;             // modes in iteration j (a prefix: J_k falls with k)
+  std::vector<int64_t> toff[2];            // table offset per iteration, y and z sweeps
+  bool profile = false;
+  std::vector<hipEvent_t> ev;              // 4 per recorded solve
+};
+
+namespace {
+
+const long double kPi = 3.141592653589793238462643383279502884L;
+
+// Complete elliptic integral of the first kind from the complementary
+// modulus kp = sqrt(1 - m): K = pi / (2 AGM(1, kp)) (Gauss).
+long double ellip_K(long double kp) {
+  long double a = 1.0L, b = kp;
+  for (int it = 0; it < 64 && std::fabs(a - b) > 1e-19L * a; ++it) {
+    const long double an = 0.5L * (a + b);
+    b = std::sqrt(a * b);
+    a = an;
+  }
+  return kPi / (2.0L * a);
+}
+
+// Jacobi dn(u | m), kp = sqrt(1 - m), by the arithmetic-geometric mean
+// scheme (Abramowitz and Stegun 16.4): a_0 = 1, b_0 = kp, c_0 = sqrt(m);
+// phi_N = 2^N a_N u, phi_{n-1} = (phi_n + asin(c_n sin(phi_n) / a_n)) / 2;
+// dn = cos(phi_0) / cos(phi_1 - phi_0).
+long double ellip_dn(long double u, long double kp) {
+  long double a[64], c[64];
+  a[0] = 1.0L;
+  c[0] = std::sqrt((1.0L - kp) * (1.0L + kp));
+  long double b = kp;
+  int n = 0;
+  while (n < 62 && std::fabs(c[n]) > 1e-19L * a[n]) {
+    a[n + 1] = 0.5L * (a[n] + b);
+    c[n + 1] = 0.5L * (a[n] - b);
+    b = std::sqrt(a[n] * b);
+    ++n;
+  }
+  if (n == 0) return 1.0L;   // m = 0
+  long double phi = std::ldexp(a[n] * u, n), prev = phi;
+  for (int i = n; i >= 1; --i) {
+    prev = phi;
+    phi = 0.5L * (phi + std::asin(c[i] * std::sin(phi) / a[i]));
+  }
+  return std::cos(phi) / std::cos(prev - phi);
+}
+
+// The J optimal parameters for [a, b] (largest first).  The half with
+// u <= K/2 comes from dn, where dn >= sqrt(a/b) keeps its relative accuracy;
+// the others from the pairing w_j w_{J+1-j} = a b (dn(K - u) = kp / dn(u)).
+void adi_parameters(long double a, long double b, int J, std::vector<long double>& w) {
+  w.assign((size_t)J, 0.0L);
+  const long double kp = a / b, K = ellip_K(kp);
+  for (int j = 1; 2 * j <= J + 1; ++j) {
+    w[(size_t)j - 1] = b * ellip_dn((2 * j - 1) * K / (2.0L * J), kp);
+    w[(size_t)(J - j)] = a * b / w[(size_t)j - 1];
+  }
+  if (J % 2 == 1) w[(size_t)(J / 2)] = std::sqrt(a * b);
+}
+
+long double adi_bound(long double a, long double b, int J) {
+  std::vector<long double> w;
+  adi_parameters(a, b, J, w);
+  long double d = 1.0L;
+  for (long double x : w) d *= std::fabs((x - a) / (x + a));
+  return d;
+}
+
+long double line_eig(int64_t n, double h, int64_t q) {
+  const long double s = std::sin(kPi * (long double)q / (2.0L * (long double)(n + 1)));
+  return 4.0L / ((long double)h * h) * s * s;
+}
+
+void destroy_poisson3d(tdt_poisson3d_s* p) {
+  if (!p) return;
+  (void)hipDeviceSynchronize();
+  if (p->fft_made) (void)hipfftDestroy(p->fft);
+  for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+  (void)hipFree(p->sn);
+  (void)hipFree(p->y);
+  (void)hipFree(p->spec);
+  (void)hipFree(p->tabs);
+  delete p;
+}
+
+constexpr int kAdiCap = 400;
+
+}  // namespace
+
+extern "C" {
+
+tdt_status_t tdt_poisson3d_create(int64_t nx, int64_t ny, int64_t nz, double hx, double hy,
+                                  double hz, double eps, tdt_poisson3d_t* out) {
+  if (!out) return TDT_ERR_INVALID_ARG;
+  *out = nullptr;
+  const int64_t lmax = (int64_t)tdt::kStrMaxChunks * tdt::kStrB;
+  if (nx < 1 || ny < 1 || nz < 1 || ny > lmax || nz > lmax || nx > (1 << 20) ||
+      nx * ny * nz > ((int64_t)1 << 34) || ny * nz > ((int64_t)1 << 31) ||
+      (int64_t)(5 * tdt::kStrB) * nx * ny * 8 + 512 >= ((int64_t)1 << 31) ||
+      !(hx > 0.0) || !(hy > 0.0) || !(hz > 0.0) || !std::isfinite(hx) || !std::isfinite(hy) ||
+      !std::isfinite(hz) || !(eps > 0.0) || !(eps < 1.0))
+    return TDT_ERR_INVALID_ARG;
+  tdt_poisson3d_s* p = new (std::nothrow) tdt_poisson3d_s();
+  if (!p) return TDT_ERR_OOM;
+  p->nx = nx;
+  p->ny = ny;
+  p->nz = nz;
+  p->hx = hx;
+  p->hy = hy;
+  p->hz = hz;
+  p->eps = eps;
+  // ADI schedule per mode (long double)
+  const long double ly0 = line_eig(ny, hy, 1), ly1 = line_eig(ny, hy, ny);
+  const long double lz0 = line_eig(nz, hz, 1), lz1 = line_eig(nz, hz, nz);
+  std::vector<long double> mu((size_t)nx);
+  std::vector<std::vector<long double>> w((size_t)nx);
+  p->count.assign((size_t)nx, 0);
+  int J = 1;
+  for (int64_t k = 0; k < nx; ++k) {
+    mu[(size_t)k] = line_eig(nx, hx, k + 1);
+    const long double a = 0.5L * mu[(size_t)k] + std::min(ly0, lz0);
+    const long double b = 0.5L * mu[(size_t)k] + std::max(ly1, lz1);
+    auto ok = [&](int j) {
+      const long double d = adi_bound(a, b, j);
+      return d * d <= (long double)eps;
+    };
+    // J_k falls with k (b/a does): start from the previous mode's count
+    while (J > 1 && ok(J - 1)) --J;
+    while (J < kAdiCap && !ok(J)) ++J;
+    if (!ok(J)) {
+      destroy_poisson3d(p);
+      return TDT_ERR_INVALID_ARG;   // eps out of reach within the cap
+    }
+    p->count[(size_t)k] = J;
+    adi_parameters(a, b, J, w[(size_t)k]);
+  }
+  // counts must not rise with k for the prefix structure of the iterations
+  for (int64_t k = nx - 1; k > 0; --k)
+    if (p->count[(size_t)k] > p->count[(size_t)k - 1]) {
+      destroy_poisson3d(p);
+      return TDT_ERR_SINGULAR;
+    }
+  p->jmax = p->count[0];
+  p->omega.assign((size_t)(nx * p->jmax), 0.0);
+  for (int64_t k = 0; k < nx; ++k)
+    for (int j = 0; j < p->count[(size_t)k]; ++j)
+      p->omega[(size_t)(k * p->jmax + j)] = (double)w[(size_t)k][(size_t)j];
+  p->active.assign((size_t)p->jmax, 0);
+  for (int j = 0; j < p->jmax; ++j) {
+    int64_t K = 0;
+    while (K < nx && p->count[(size_t)K] > j) ++K;
+    p->active[(size_t)j] = K;
+  }
+  // tables of every half-step: classes k < K_j with t_+-1 = -1,
+  // t_0 = 2 + h^2 (w_kj + mu_k / 2), and the epilogue of the step
+  std::vector<double> tab;
+  tdt_status_t st = TDT_OK;
+  for (int d = 0; d < 2 && st == TDT_OK; ++d) {
+    const int64_t N = d == 0 ? ny : nz;
+    const long double h2 = d == 0 ? (long double)hy * hy : (long double)hz * hz;
+    const int C = tdt::strided_chunks(N);
+    p->toff[d].assign((size_t)p->jmax, 0);
+    for (int j = 0; j < p->jmax && st == TDT_OK; ++j) {
+      const int64_t P = p->active[(size_t)j];
+      std::vector<double> tm1((size_t)P, -1.0), t0((size_t)P), t1((size_t)P, -1.0);
+      const size_t base = tab.size();
+      p->toff[d][(size_t)j] = (int64_t)base;
+      tab.resize(base + (size_t)((tdt::kStrB + tdt::kStrScalarN + 2 * C + tdt::kEpiN) * P));
+      double* epi = tab.data() + base + (tdt::kStrB + tdt::kStrScalarN + 2 * C) * P;
+      for (int64_t k = 0; k < P; ++k) {
+        const long double wk = w[(size_t)k][(size_t)j];
+        t0[(size_t)k] = (double)(2.0L + h2 * (wk + 0.5L * mu[(size_t)k]));
+        epi[tdt::kEpiScale * P + k] = (double)h2;
+        const bool fin = d == 1 && j + 1 == p->count[(size_t)k];
+        long double cx = d == 0 ? 2.0L * wk
+                                : (fin ? 1.0L : w[(size_t)k][(size_t)j + 1] + wk);
+        epi[tdt::kEpiCX * P + k] = (double)cx;
+        epi[tdt::kEpiCR * P + k] = fin ? 0.0 : -1.0;
+        epi[tdt::kEpiCG * P + k] = fin ? 0.0 : 1.0;
+      }
+      double dom = 0.0;
+      double* iu = tab.data() + base;
+      double* sc = iu + tdt::kStrB * P;
+      double* pos = sc + tdt::kStrScalarN * P;
+      const int r = tdt::strided_tables(N, P, tm1.data(), t0.data(), t1.data(), iu, sc, pos, &dom);
+      if (r < 0) st = (tdt_status_t)r;
+    }
+  }
+  const int64_t n = nx + 1, Kc = n / 2 + 1, rows = ny * nz;
+  if (st == TDT_OK &&
+      (hipMalloc(&p->sn, (size_t)n * sizeof(double)) != hipSuccess ||
+       hipMalloc(&p->y, (size_t)(rows * n) * sizeof(double)) != hipSuccess ||
+       hipMalloc(&p->spec, (size_t)(rows * Kc) * 2 * sizeof(double)) != hipSuccess ||
+       hipMalloc(&p->tabs, tab.size() * sizeof(double)) != hipSuccess))
+    st = TDT_ERR_OOM;
+  if (st == TDT_OK) {
+    std::vector<double> sn((size_t)n);
+    for (int64_t j = 0; j < n; ++j) sn[(size_t)j] = (double)std::sin(kPi * (long double)j / n);
+    if (hipMemcpy(p->sn, sn.data(), (size_t)n * sizeof(double), hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemcpy(p->tabs, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice) !=
+            hipSuccess)
+      st = TDT_ERR_HIP;
+  }
+  if (st == TDT_OK) {
+    int len[1] = {(int)n};
+    if (hipfftPlanMany(&p->fft, 1, len, nullptr, 1, (int)n, nullptr, 1, (int)Kc, HIPFFT_D2Z,
+                       (int)rows) != HIPFFT_SUCCESS)
+      st = TDT_ERR_HIP;
+    else
+      p->fft_made = true;
+  }
+  if (st < 0) {
+    destroy_poisson3d(p);
+    return st;
+  }
+  *out = p;
+  return TDT_OK;
+}
+
+tdt_status_t tdt_poisson3d_solve(tdt_poisson3d_t p, const double* F, double* U,
+                                 hipStream_t stream) {
+  if (!p || !F || !U) return TDT_ERR_INVALID_ARG;
+  const int64_t nx = p->nx, ny = p->ny, nz = p->nz, n = nx + 1, rows = ny * nz;
+  const size_t bytes = (size_t)(nx * rows) * sizeof(double);
+  if (F == U || (reinterpret_cast<const char*>(F) < reinterpret_cast<const char*>(U) + bytes &&
+                 reinterpret_cast<const char*>(U) < reinterpret_cast<const char*>(F) + bytes))
+    return TDT_ERR_INVALID_ARG;
+  if (hipfftSetStream(p->fft, stream) != HIPFFT_SUCCESS) return TDT_ERR_HIP;
+  hipEvent_t* ev = nullptr;
+  if (p->profile) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
+      const size_t k = p->ev.size();
+      p->ev.resize(k + 4);
+      for (size_t j = 0; j < 4; ++j)
+        if (hipEventCreate(&p->ev[k + j]) != hipSuccess) return TDT_ERR_HIP;
+      ev = p->ev.data() + k;
+    }
+  }
+  auto gy = [](int64_t v) { return (unsigned)(v < (int64_t)kMaxGridY ? v : kMaxGridY); };
+  auto* spec = reinterpret_cast<hipfftDoubleComplex*>(p->spec);
+  if (ev) (void)hipEventRecord(ev[0], stream);
+  // fhat (in U): the scaled sine transform of every row along x
+  hipLaunchKernelGGL(k_fold_rows, dim3((unsigned)((n + 255) / 256), gy(rows)), dim3(256), 0,
+                     stream, F, p->sn, p->y, nx, rows);
+  if (hipfftExecD2Z(p->fft, p->y, spec) != HIPFFT_SUCCESS) return TDT_ERR_HIP;
+  hipLaunchKernelGGL(k_scan_rows, dim3(gy(rows)), dim3(kScanNT), 0, stream, p->spec, nx, rows, U,
+                     2.0 / (double)(nx + 1));
+  if (ev) (void)hipEventRecord(ev[1], stream);
+  // ADI: W (in the spectrum buffer) holds each mode's current right-hand side
+  double* W = p->spec;
+  for (int j = 0; j < p->jmax; ++j) {
+    const int64_t P = p->active[(size_t)j];
+    for (int d = 0; d < 2; ++d) {
+      const int64_t N = d == 0 ? ny : nz;
+      const int C = tdt::strided_chunks(N);
+      tdt::StridedArgs a{};
+      a.R = (j == 0 && d == 0) ? U : W;
+      a.O = W;
+      a.G = U;
+      a.iu = p->tabs + p->toff[d][(size_t)j];
+      a.sc = a.iu + tdt::kStrB * P;
+      a.pos = a.sc + tdt::kStrScalarN * P;
+      a.epi = a.pos + 2 * C * P;
+      a.N = N;
+      a.P = P;
+      a.M = P;
+      a.C = C;
+      if (d == 0) {   // lines along y: rows nx apart, one batch per z plane
+        a.ld = nx;
+        a.nb = nz;
+        a.ldb = nx * ny;
+      } else {        // lines along z: rows nx ny apart, one batch per y row
+        a.ld = nx * ny;
+        a.nb = ny;
+        a.ldb = nx;
+      }
+      if (tdt::launch_strided(a, stream) != hipSuccess) return TDT_ERR_HIP;
+    }
+  }
+  if (ev) (void)hipEventRecord(ev[2], stream);
+  // U: the (unscaled) sine transform of the mode coefficients of every row
+  hipLaunchKernelGGL(k_fold_rows, dim3((unsigned)((n + 255) / 256), gy(rows)), dim3(256), 0,
+                     stream, W, p->sn, p->y, nx, rows);
+  if (hipfftExecD2Z(p->fft, p->y, spec) != HIPFFT_SUCCESS) return TDT_ERR_HIP;
+  hipLaunchKernelGGL(k_scan_rows, dim3(gy(rows)), dim3(kScanNT), 0, stream, p->spec, nx, rows, U,
+                     1.0);
+  if (ev) (void)hipEventRecord(ev[3], stream);
+  return hipGetLastError() == hipSuccess ? TDT_OK : TDT_ERR_HIP;
+}
+
+tdt_status_t tdt_poisson3d_schedule(tdt_poisson3d_t p, int* h_counts, double* h_omega,
+                                    int64_t omega_len, int* jmax) {
+  if (!p) return TDT_ERR_INVALID_ARG;
+  if (jmax) *jmax = p->jmax;
+  if (h_counts)
+    for (int64_t k = 0; k < p->nx; ++k) h_counts[k] = p->count[(size_t)k];
+  if (h_omega) {
+    if (omega_len < (int64_t)p->omega.size()) return TDT_ERR_INVALID_ARG;
+    for (size_t i = 0; i < p->omega.size(); ++i) h_omega[i] = p->omega[i];
+  }
+  return TDT_OK;
+}
+
+tdt_status_t tdt_poisson3d_profile(tdt_poisson3d_t p, int enable) {
+  if (!p) return TDT_ERR_INVALID_ARG;
+  if (!enable) {
+    (void)hipDeviceSynchronize();
+    for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+    p->ev.clear();
+  }
+  p->profile = enable != 0;
+  return TDT_OK;
+}
+
+tdt_status_t tdt_poisson3d_profile_read(tdt_poisson3d_t p, double* ms3, int64_t* nsolves) {
+  if (!p || !ms3) return TDT_ERR_INVALID_ARG;
+  if (hipDeviceSynchronize() != hipSuccess) return TDT_ERR_HIP;
+  ms3[0] = ms3[1] = ms3[2] = 0.0;
+  const size_t ns = p->ev.size() / 4;
+  for (size_t k = 0; k < ns; ++k)
+    for (int j = 0; j < 3; ++j) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, p->ev[4 * k + j], p->ev[4 * k + j + 1]) != hipSuccess)
+        return TDT_ERR_HIP;
+      ms3[j] += (double)ms;
+    }
+  if (nsolves) *nsolves = (int64_t)ns;
+  for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+  p->ev.clear();
+  return TDT_OK;
+}
+
+tdt_status_t tdt_adi_parameters(double a, double b, int J, double* out, double* bound) {
+  if (!(a > 0.0) || !(b >= a) || !std::isfinite(b) || J < 1 || J > kAdiCap || !out)
+    return TDT_ERR_INVALID_ARG;
+  std::vector<long double> w;
+  adi_parameters(a, b, J, w);
+  long double d = 1.0L;
+  for (int j = 0; j < J; ++j) {
+    out[j] = (double)w[(size_t)j];
+    d *= std::fabs((w[(size_t)j] - a) / (w[(size_t)j] + a));
+  }
+  if (bound) *bound = (double)d;
+  return TDT_OK;
+}
+
+tdt_status_t tdt_poisson3d_destroy(tdt_poisson3d_t p) {
+  if (!p) return TDT_ERR_INVALID_ARG;
+  destroy_poisson3d(p);
   return TDT_OK;
 }
 

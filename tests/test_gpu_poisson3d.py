@@ -1,0 +1,113 @@
+"""GPU parity of the 3D Poisson solve of Sec. 3.5 (sine transform along x,
+Peaceman-Rachford ADI on every mode's (y, z) plane through the strided line
+solves, inverse transform) against the CPU oracle, through the C ABI: the
+ADI schedule (iteration counts and parameters), the solution on grids up to
+63 x 64 x 65, and at the benchmark size (511^3, 2^9 intervals per side) the
+closed-form eigenmode results and the seven-point residual.
+
+Inputs: F ~ N(0, 1); spacings drawn in [0.005, 0.1] (unequal hx, hy, hz)."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import to_dev, to_host
+from oracle import poisson3d as P3
+
+pytestmark = pytest.mark.gpu
+
+
+def _tdt():
+    import paper_1002_2469_amd as tdt
+    return tdt
+
+
+def _rel2(x, y):
+    return float(np.linalg.norm(x - y) / np.linalg.norm(y))
+
+
+GRIDS = [(1, 1, 1), (3, 4, 5), (7, 9, 4), (16, 17, 15), (31, 20, 17), (12, 1, 40),
+         (20, 33, 1), (63, 64, 65)]
+
+
+@pytest.mark.parametrize("nx,ny,nz", GRIDS)
+def test_poisson3d_grids(nx, ny, nz):
+    tdt = _tdt()
+    rng = np.random.default_rng(nx * 10000 + ny * 100 + nz)
+    hx, hy, hz = rng.uniform(0.005, 0.1, 3)
+    eps = 1e-13
+    F = rng.standard_normal((nz, ny, nx))
+    print(f"[case] poisson3d {nx}x{ny}x{nz}", flush=True)
+    solver = tdt.Poisson3D(nx, ny, nz, hx, hy, hz, eps)
+    modes = P3.plan(nx, ny, nz, hx, hy, hz, eps)
+    counts, om = solver.schedule()
+    assert list(counts) == [m[3] for m in modes]
+    for k, m in enumerate(modes):
+        assert np.allclose(om[k, :m[3]], m[4], rtol=1e-13, atol=0)
+    U = to_host(solver.solve(to_dev(F)))
+    ref = P3.solve(F, hx, hy, hz, eps=eps, modes=modes)
+    err = _rel2(U, ref)
+    assert err < 1e-11, err
+
+
+def test_poisson3d_eps_levels():
+    """A loose eps: the result follows the oracle's ADI iterates (same
+    parameters), not the exact solution, and stays within eps of it."""
+    tdt = _tdt()
+    rng = np.random.default_rng(3)
+    nx, ny, nz, hx, hy, hz = 24, 30, 28, 0.04, 0.03, 0.035
+    F = rng.standard_normal((nz, ny, nx))
+    for eps in (1e-4, 1e-8):
+        print(f"[case] poisson3d eps={eps}", flush=True)
+        solver = tdt.Poisson3D(nx, ny, nz, hx, hy, hz, eps)
+        U = to_host(solver.solve(to_dev(F)))
+        ref = P3.solve(F, hx, hy, hz, eps=eps)
+        assert _rel2(U, ref) < 1e-11
+        exact = P3.solve(F, hx, hy, hz, eps=1e-15)
+        assert _rel2(U, exact) <= eps * 1.001 + 1e-12
+
+
+def test_poisson3d_eigenmodes_medium():
+    tdt = _tdt()
+    nx, ny, nz, hx, hy, hz = 127, 100, 90, 1 / 128, 0.9 / 101, 1.1 / 91
+    eps = 1e-6
+    solver = tdt.Poisson3D(nx, ny, nz, hx, hy, hz, eps)
+    for p, q, r in ((1, 1, 1), (64, 3, 80), (127, 100, 90), (5, 50, 2)):
+        print(f"[case] poisson3d eigen ({p},{q},{r})", flush=True)
+        F, Uex, Uadi = P3.eigen_case(nx, ny, nz, p, q, r, hx, hy, hz, eps=eps)
+        U = to_host(solver.solve(to_dev(F)))
+        assert _rel2(U, Uadi) < 1e-12, (p, q, r, _rel2(U, Uadi))
+
+
+def test_poisson3d_benchmark_size():
+    """511^3 (the benchmark): closed-form eigenmodes and the seven-point
+    residual of a random right-hand side (relative 2-norm)."""
+    tdt = _tdt()
+    n, h, eps = 511, 1.0 / 512, 1e-13
+    solver = tdt.Poisson3D(n, n, n, h, h, h, eps)
+    for p, q, r in ((1, 1, 1), (2, 300, 7), (511, 511, 511)):
+        print(f"[case] poisson3d 511^3 eigen ({p},{q},{r})", flush=True)
+        F, Uex, Uadi = P3.eigen_case(n, n, n, p, q, r, h, h, h, eps=eps)
+        U = to_host(solver.solve(to_dev(F)))
+        assert _rel2(U, Uadi) < 1e-11, (p, q, r, _rel2(U, Uadi))
+        del F, Uex, Uadi, U
+    print("[case] poisson3d 511^3 residual", flush=True)
+    F = np.random.default_rng(0).standard_normal((n, n, n))
+    U = to_host(solver.solve(to_dev(F)))
+    assert _rel2(P3.laplacian(U, h, h, h), F) < 1e-9
+
+
+def test_poisson3d_errors_and_repeatable():
+    tdt = _tdt()
+    from paper_1002_2469_amd import _lib
+    for args in ((0, 5, 5, 0.1, 0.1, 0.1, 1e-10), (5, 1025, 5, 0.1, 0.1, 0.1, 1e-10),
+                 (5, 5, 5, -0.1, 0.1, 0.1, 1e-10), (5, 5, 5, 0.1, 0.1, 0.1, 0.0),
+                 (5, 5, 5, 0.1, 0.1, 0.1, 1.0), (4000, 1000, 5, 0.1, 0.1, 0.1, 1e-10)):
+        with pytest.raises(_lib.TDTError):
+            tdt.Poisson3D(*args)
+    rng = np.random.default_rng(2)
+    F = to_dev(rng.standard_normal((20, 30, 40)))
+    print("[case] poisson3d repeatable", flush=True)
+    solver = tdt.Poisson3D(40, 30, 20, 0.01, 0.02, 0.015)
+    assert np.array_equal(to_host(solver.solve(F)), to_host(solver.solve(F)))
+    with pytest.raises(_lib.TDTError):
+        solver.solve(F, F)

@@ -181,3 +181,23 @@ def test_green_rows_match_dense_inverse(t, L):
     Ti = np.linalg.inv(dense_T(L, a, b, c))
     assert np.allclose(first, Ti[0], rtol=1e-13, atol=1e-15)
     assert np.allclose(last, Ti[-1], rtol=1e-13, atol=1e-15)
+
+
+def test_adi_parameters_match_the_oracle():
+    """The 3D solve's ADI parameters (long double AGM for K and dn, host
+    side) against the oracle's (mpmath elliptic functions), and their bound;
+    b/a up to 1e6 covers grids of up to 1024 points per side."""
+    import paper_1002_2469_amd as tdt
+    from oracle import poisson3d as P3
+    for a, b in ((1.0, 1.0), (1.0, 3.0), (2.5, 1e3), (14.8, 1.05e6)):
+        for J in (1, 2, 7, 16, 41):
+            om, d = tdt.adi_parameters(a, b, J)
+            ref = P3.adi_parameters(a, b, J)
+            assert np.allclose(om, ref, rtol=2e-14, atol=0), (a, b, J)
+            dref = abs(P3.adi_factor(ref, a))
+            assert abs(d - dref) <= 1e-13 * max(dref, 1e-300) or (a == b and d == 0.0)
+    L = _lib.lib()
+    out = np.zeros(4)
+    p = out.ctypes.data_as(ctypes.c_void_p)
+    for a, b, J in ((0.0, 1.0, 2), (2.0, 1.0, 2), (1.0, 2.0, 0), (1.0, 2.0, 401)):
+        assert L.tdt_adi_parameters(a, b, J, p, None) == _lib.TDT_ERR_INVALID_ARG
