@@ -19,7 +19,10 @@ adjoint backward pass) and `general` (64 right-hand sides of N = 2**20 sharing a
 general tridiagonal matrix with per-row entries; paths f64 and f32) and
 `poisson2d` (the 2D Poisson problem on 8191 x 8191 interior points, 2^13
 intervals per side, solved end to end by separation of variables: sine
-transforms, 8191 line systems of 8191, inverse transforms; path f64).
+transforms, 8191 line systems of 8191, inverse transforms; path f64) and
+`poisson3d` (the 3D problem of Sec. 3.5 on 511^3 interior points: sine
+transform along x, Peaceman-Rachford ADI on every mode's (y, z) plane with
+strided line solves, inverse transform; path f64).
 
 Prints one JSON line.  `roofline` is for the kernel with the longest average
 duration in the headline path, from HIP events recorded on the solve stream
@@ -47,7 +50,8 @@ if ROOT not in sys.path:
 
 METRIC = "unknowns/s + HBM GB/s (% peak): FP32+refine vs FP64 solve at rel err ≤1e-12"
 HBM_PEAK_GBS = 8000.0
-WORKLOADS = ("single_large", "series", "sov", "sov_neumann", "diff", "general", "poisson2d")
+WORKLOADS = ("single_large", "series", "sov", "sov_neumann", "diff", "general", "poisson2d",
+             "poisson3d")
 
 
 def kernel_source_hash() -> str:
@@ -122,6 +126,14 @@ def load_workload(name: str, args):
                       f"points of the unit square, zero boundary, F~N(0,1) seed 0, [Ny][Nx] "
                       f"double in/out; sine transforms (hipFFT) + one Toeplitz line system per "
                       f"mode + inverse transforms")
+    elif name == "poisson3d":
+        d = W.poisson3d(seed=0)
+        d.update(kind="poisson3d", units=d["nx"] * d["ny"] * d["nz"], eps=1e-13,
+                 desc=f"poisson3d: seven-point Poisson problem on {d['nx']}x{d['ny']}x{d['nz']} "
+                      f"interior points of the unit cube, zero boundary, F~N(0,1) seed 0, "
+                      f"[Nz][Ny][Nx] double in/out; sine transform along x (hipFFT), "
+                      f"Peaceman-Rachford ADI per mode plane (optimal parameters, eps 1e-13, "
+                      f"strided line solves along y and z), inverse transform")
     elif name == "diff":
         d = W.diff_batch(seed=0)
         d.update(kind="varlen", units=int(d["offsets"][-1]), adjoint=True,
@@ -260,6 +272,82 @@ def run_poisson(tdt, d, F, mode, steps, warmup, torch):
     return out
 
 
+def run_poisson3d(tdt, d, F, steps, warmup, torch):
+    """A step is one whole 3D solve (transforms and all ADI half-steps)."""
+    solver = tdt.Poisson3D(d["nx"], d["ny"], d["nz"], d["hx"], d["hy"], d["hz"], d["eps"])
+    U = torch.empty_like(F)
+    for _ in range(warmup):
+        solver.solve(F, U)
+    torch.cuda.synchronize()
+    solver.profile(True)
+    for _ in range(steps):
+        solver.solve(F, U)
+    torch.cuda.synchronize()
+    prof = solver.profile_read()
+    solver.profile(False)
+    n = max(prof["solves"], 1)
+    kern = {"forward_transform": prof["forward_ms"] / n, "adi": prof["adi_ms"] / n,
+            "inverse_transform": prof["inverse_ms"] / n}
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(steps):
+        solver.solve(F, U)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / steps
+    counts, _om = solver.schedule()
+    out = dict(ms=ms, kernels_ms=kern, refine_iters=0, X=U.cpu().numpy().reshape(-1), tuned=None,
+               counts=counts)
+    solver.close()
+    return out
+
+
+def adi_bytes(d, counts):
+    """Algorithmic HBM bytes of the ADI half-steps of one solve: per active
+    mode and line unknown, a y-sweep reads its right-hand side and fhat and
+    writes the next right-hand side (24 B; 16 B in the first iteration,
+    where both inputs are fhat), a z-sweep the same, but a mode's last one
+    does not read fhat (16 B)."""
+    import numpy as np
+    counts = np.asarray(counts)
+    plane = d["ny"] * d["nz"]
+    total = 0
+    for j in range(int(counts.max())):
+        P = int(np.sum(counts > j))
+        fin = int(np.sum(counts == j + 1))
+        total += (16 if j == 0 else 24) * P * plane          # y-sweep
+        total += (24 * P - 8 * fin) * plane                  # z-sweep
+    return float(total)
+
+
+def cpu_leg_poisson3d(d, budget_s=12.0, n_sample=127):
+    """The oracle (explicit sine transform, ADI per mode with Thomas per
+    line) on a smaller cube; the ADI parameters (mpmath) are computed once
+    outside the timed runs, as the GPU's are at plan creation."""
+    import numpy as np
+    import oracle
+    from oracle import poisson3d as P3
+    threads = oracle.threads(0)
+    h = 1.0 / (n_sample + 1)
+    modes = P3.plan(n_sample, n_sample, n_sample, h, h, h, d["eps"])
+    F = np.random.default_rng(1).standard_normal((n_sample, n_sample, n_sample))
+    times = []
+    t_budget = time.perf_counter()
+    while len(times) < 10 and (time.perf_counter() - t_budget < budget_s or len(times) < 2):
+        t0 = time.perf_counter()
+        P3.solve(F, h, h, h, eps=d["eps"], modes=modes)
+        times.append(time.perf_counter() - t0)
+    med = statistics.median(times)
+    return {"value": n_sample ** 3 / med, "unit": "unknowns/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"the same problem on a {n_sample}^3 grid (the oracle's explicit sine "
+                      f"transform costs O(N^4): the full grid would take many minutes), numpy + "
+                      f"the C Thomas oracle, {threads} thread(s), median of {len(times)} runs "
+                      f"of {med:.3f} s, ADI parameters computed once outside the runs"}
+
+
 def cpu_leg_poisson(d, budget_s=12.0, n_sample=2048):
     """The oracle (explicit sine transforms, Thomas per mode) on a smaller
     grid of the same problem: at the full size its O(N^3) transforms take
@@ -348,8 +436,8 @@ def main() -> int:
     X = torch.empty_like(F)
     torch.cuda.synchronize()
     if args.modes is None:
-        args.modes = {"general": "f64,f32", "poisson2d": "f64"}.get(args.workload,
-                                                                    "f32_refine,f64")
+        args.modes = {"general": "f64,f32", "poisson2d": "f64",
+                      "poisson3d": "f64"}.get(args.workload, "f32_refine,f64")
     modes = [m for m in args.modes.split(",") if m]
     res = {}
     for mode in modes:
@@ -357,6 +445,10 @@ def main() -> int:
         Xm = torch.empty_like(Fm) if mode == "f32" else X
         if d["kind"] == "poisson":
             res[mode] = run_poisson(tdt, d, F, mode, args.steps, args.warmup, torch)
+        elif d["kind"] == "poisson3d":
+            if mode != "f64":
+                raise SystemExit("poisson3d runs the f64 path only")
+            res[mode] = run_poisson3d(tdt, d, F, args.steps, args.warmup, torch)
         else:
             res[mode] = run_mode(tdt, d, Fm, Xm, mode, args.steps, args.warmup, torch,
                                  autotune=not args.no_autotune)
@@ -375,14 +467,16 @@ def main() -> int:
     head = modes[0]
     from paper_1002_2469_amd import _lib
     shape = (res[head]["tuned"] or {}).get("shape", 0)
-    if d["kind"] == "poisson":
+    if d["kind"] in ("poisson", "poisson3d"):
         n_first, n_final = 0, U
     else:
         n_first, n_final = tile_counts(d, _lib.SHAPES[shape][0] * _lib.SHAPES[shape][1])
     # algorithmic HBM bytes per launch of each kernel group (double data)
     per_launch = {"first_pass": 8.0 * n_first, "final_pass": 16.0 * n_final,
                   "bwd_first_pass": 8.0 * n_first, "bwd_final_pass": 24.0 * n_final,
-                  "line_first_pass": 0.0, "line_interface": 0.0, "line_final_pass": 16.0 * n_final}
+                  "line_first_pass": 0.0, "line_interface": 0.0, "line_final_pass": 16.0 * n_final,
+                  "forward_transform": 0.0, "inverse_transform": 0.0,
+                  "adi": adi_bytes(d, res[head]["counts"]) if d["kind"] == "poisson3d" else 0.0}
     names = {"first_pass": ("k_beta<double> (Green-row tile summaries, first pass)"
                             if d["kind"] == "series" else
                             "k_gtile<double, SUMMARY> (general matrix, tile summaries)"
@@ -394,6 +488,8 @@ def main() -> int:
                             if head == "f32_refine" else "k_tile<double, double, final> (solve and store)"),
              "line_final_pass": "k_sys<double, double> (the mode line systems, solved whole; "
                                 "the sine transforms around it are hipFFT's)",
+             "adi": "k_strided<double> with the ADI epilogue (all 2 J_1 half-steps of one "
+                    "solve: bytes and time summed over them)",
              "bwd_first_pass": "k_tile<double, *, SUMMARY> on T^T (adjoint first pass)",
              "bwd_final_pass": "k_tile<..., BWD> (adjoint solve, store gF, dL/dt partial sums)"}
 
@@ -406,6 +502,15 @@ def main() -> int:
             Um = res[mode]["X"].reshape(d["ny"], d["nx"])
             r = P2.laplacian(Um, d["hx"], d["hy"]) - d["F"]
             errs[mode] = {"residual": float(np.max(np.abs(r)) / np.max(np.abs(d["F"])))}
+    elif not args.no_cpu and d["kind"] == "poisson3d":
+        from oracle import poisson3d as P3
+        cpu = cpu_leg_poisson3d(d)
+        for mode in modes:
+            Um = res[mode]["X"].reshape(d["nz"], d["ny"], d["nx"])
+            r = P3.laplacian(Um, d["hx"], d["hy"], d["hz"]) - d["F"]
+            errs[mode] = {"residual": float(np.max(np.abs(r)) / np.max(np.abs(d["F"]))),
+                          "residual_2norm": float(np.linalg.norm(r) / np.linalg.norm(d["F"]))}
+            del r, Um
     elif not args.no_cpu:
         cpu, Xo, gFo, gto = cpu_leg(d)
         import oracle
@@ -464,6 +569,11 @@ def main() -> int:
     }
     if "f64" in res and head != "f64":
         line["speedup_vs_f64"] = res["f64"]["ms"] / res[head]["ms"]
+    if d["kind"] == "poisson3d":
+        c = np.asarray(res[head]["counts"])
+        line["adi_schedule"] = {"iterations_mode_1": int(c[0]), "iterations_last_mode": int(c[-1]),
+                                "mean_iterations": float(c.mean()),
+                                "half_step_launches": 2 * int(c.max())}
     line["kernel_source_sha"] = kernel_source_hash()
     print(json.dumps(line))
     return 0

@@ -1445,6 +1445,7 @@ tdt_status_t tdt_solve_strided(tdt_plan_t p, const double* F, double* X, int64_t
   a.N = N;
   a.P = p->sP;
   a.M = M;
+  a.Mg = M;
   a.ld = ld;
   a.nb = nb;
   a.ldb = ldb;

@@ -176,6 +176,7 @@ struct StridedArgs {
   const double* sc;         // [kStrScalarN][P]
   const double* pos;        // [2][C][P] per block position: beta_{c-1}, 1/(1 - phi_f beta_{c-1})
   int64_t N, P, M, ld, nb, ldb;
+  int64_t Mg;               // systems s < Mg read G (the others take g = 0)
   int C;                    // blocks per system, ceil(N / kStrB)
 };
 hipError_t launch_strided(const StridedArgs& a, hipStream_t st);

@@ -134,6 +134,53 @@ __global__ __launch_bounds__(kScanNT) void k_scan_rows(double* __restrict__ spec
   }
 }
 
+// The same for rows of at most 64 E spectrum entries (Nx < 128 E): one
+// wavefront per row, four rows per workgroup.  Entry k is taken by lane
+// k % 64 in round k / 64, so that every load and store of a round is
+// contiguous across the lanes; each round is a wavefront scan by shuffles
+// plus the carry of the rounds before it.  A lane writes the adjacent pair
+// (S_{2k}, S_{2k+1}) = (U[2k-1], U[2k]).
+template <int E>
+__global__ __launch_bounds__(256) void k_scan_rows_wave(double* __restrict__ spec, int64_t nx,
+                                                        int64_t ny, double* __restrict__ U,
+                                                        double scale) {
+  const int64_t K = (nx + 1) / 2 + 1;
+  const int lane = threadIdx.x & 63;
+  for (int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); r < ny;
+       r += (int64_t)gridDim.x * 4) {
+    double2* row = reinterpret_cast<double2*>(spec) + r * K;
+    double2 z[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int64_t k = (int64_t)64 * e + lane;
+      z[e] = k < K ? row[k] : make_double2(0.0, 0.0);
+    }
+    double carry = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int64_t k = (int64_t)64 * e + lane;
+      double x = k == 0 ? 0.5 * z[e].x : z[e].x;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const double y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+      }
+      const double acc = carry + x;
+      carry += __shfl(x, 63, 64);
+      if (k < K) {
+        if (U) {
+          double* u = U + r * nx;
+          // U[2k] = S_{2k+1} = acc, U[2k-1] = S_{2k} = -Im Y_k (m = 1 .. Nx)
+          if (k >= 1 && 2 * k <= nx) u[2 * k - 1] = -scale * z[e].y;
+          if (2 * k + 1 <= nx) u[2 * k] = scale * acc;
+        } else {
+          row[k].x = acc;
+        }
+      }
+    }
+  }
+}
+
 // T[m-1][j] = s * S_m of spectrum row j (S_m = Re' Y_{(m-1)/2} for odd m,
 // -Im Y_{m/2} for even m): the scaled coefficients transposed to mode-major
 // order through an LDS tile.
@@ -189,6 +236,25 @@ __global__ void k_fold_modes(const double* __restrict__ V, const double* __restr
         }
         y[j * n + m] = v;
       }
+    }
+  }
+}
+
+// The per-row prefix sums of a batch of spectra (see k_scan_rows).
+void launch_scan_rows(double* spec, int64_t nx, int64_t ny, double* U, double scale,
+                      hipStream_t st) {
+  const int64_t K = (nx + 1) / 2 + 1;
+  const int E = (int)((K + 63) / 64);
+  const unsigned gw = (unsigned)std::min<int64_t>((ny + 3) / 4, kMaxGridY);
+  switch (E) {
+#define TDT_SCAN_CASE(e) \
+  case e: hipLaunchKernelGGL(k_scan_rows_wave<e>, dim3(gw), dim3(256), 0, st, spec, nx, ny, U, scale); return;
+    TDT_SCAN_CASE(1) TDT_SCAN_CASE(2) TDT_SCAN_CASE(3) TDT_SCAN_CASE(4)
+    TDT_SCAN_CASE(5) TDT_SCAN_CASE(6) TDT_SCAN_CASE(7) TDT_SCAN_CASE(8)
+#undef TDT_SCAN_CASE
+    default: {
+      const unsigned g = (unsigned)std::min<int64_t>(ny, kMaxGridY);
+      hipLaunchKernelGGL(k_scan_rows, dim3(g), dim3(kScanNT), 0, st, spec, nx, ny, U, scale);
     }
   }
 }
@@ -284,8 +350,7 @@ tdt_status_t tdt_poisson2d_solve(tdt_poisson_t p, const double* F, double* U,
   hipLaunchKernelGGL(k_fold_rows, dim3((unsigned)((n + 255) / 256), gy(ny)), dim3(256), 0,
                      stream, F, p->sn, p->y, nx, ny);
   if (hipfftExecD2Z(p->fft, p->y, spec) != HIPFFT_SUCCESS) return TDT_ERR_HIP;
-  hipLaunchKernelGGL(k_scan_rows, dim3(gy(ny)), dim3(kScanNT), 0, stream, p->spec, nx, ny,
-                     (double*)nullptr, 1.0);
+  launch_scan_rows(p->spec, nx, ny, nullptr, 1.0, stream);
   const double s = p->hy * p->hy * 2.0 / (double)(nx + 1);
   hipLaunchKernelGGL(k_modes_from_rows, tiles, dim3(kTileP, 8), 0, stream, p->spec, p->T, nx,
                      ny, s);
@@ -296,8 +361,7 @@ tdt_status_t tdt_poisson2d_solve(tdt_poisson_t p, const double* F, double* U,
   hipLaunchKernelGGL(k_fold_modes, tiles, dim3(kTileP, 8), 0, stream, p->V, p->sn, p->y, nx,
                      ny);
   if (hipfftExecD2Z(p->fft, p->y, spec) != HIPFFT_SUCCESS) return TDT_ERR_HIP;
-  hipLaunchKernelGGL(k_scan_rows, dim3(gy(ny)), dim3(kScanNT), 0, stream, p->spec, nx, ny, U,
-                     1.0);
+  launch_scan_rows(p->spec, nx, ny, U, 1.0, stream);
   return hipGetLastError() == hipSuccess ? TDT_OK : TDT_ERR_HIP;
 }
 
@@ -595,8 +659,7 @@ tdt_status_t tdt_poisson3d_solve(tdt_poisson3d_t p, const double* F, double* U,
   hipLaunchKernelGGL(k_fold_rows, dim3((unsigned)((n + 255) / 256), gy(rows)), dim3(256), 0,
                      stream, F, p->sn, p->y, nx, rows);
   if (hipfftExecD2Z(p->fft, p->y, spec) != HIPFFT_SUCCESS) return TDT_ERR_HIP;
-  hipLaunchKernelGGL(k_scan_rows, dim3(gy(rows)), dim3(kScanNT), 0, stream, p->spec, nx, rows, U,
-                     2.0 / (double)(nx + 1));
+  launch_scan_rows(p->spec, nx, rows, U, 2.0 / (double)(nx + 1), stream);
   if (ev) (void)hipEventRecord(ev[1], stream);
   // ADI: W (in the spectrum buffer) holds each mode's current right-hand side
   double* W = p->spec;
@@ -616,6 +679,8 @@ tdt_status_t tdt_poisson3d_solve(tdt_poisson3d_t p, const double* F, double* U,
       a.N = N;
       a.P = P;
       a.M = P;
+      // the modes whose last half-step this is take no fhat
+      a.Mg = d == 0 ? P : (j + 1 < p->jmax ? p->active[(size_t)j + 1] : 0);
       a.C = C;
       if (d == 0) {   // lines along y: rows nx apart, one batch per z plane
         a.ld = nx;
@@ -634,8 +699,7 @@ tdt_status_t tdt_poisson3d_solve(tdt_poisson3d_t p, const double* F, double* U,
   hipLaunchKernelGGL(k_fold_rows, dim3((unsigned)((n + 255) / 256), gy(rows)), dim3(256), 0,
                      stream, W, p->sn, p->y, nx, rows);
   if (hipfftExecD2Z(p->fft, p->y, spec) != HIPFFT_SUCCESS) return TDT_ERR_HIP;
-  hipLaunchKernelGGL(k_scan_rows, dim3(gy(rows)), dim3(kScanNT), 0, stream, p->spec, nx, rows, U,
-                     1.0);
+  launch_scan_rows(p->spec, nx, rows, U, 1.0, stream);
   if (ev) (void)hipEventRecord(ev[3], stream);
   return hipGetLastError() == hipSuccess ? TDT_OK : TDT_ERR_HIP;
 }

@@ -53,82 +53,125 @@ __device__ __forceinline__ void st64(__amdgpu_buffer_rsrc_t r, uint32_t voff, ui
   using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, voff, soff, 0);
 }
-// Hides a value from the optimiser so that loads through it are issued where
-// they are written instead of being hoisted and kept live.
-__device__ __forceinline__ uint32_t opaque(uint32_t v) {
+// An LDS address hidden from the optimiser: reads through it are issued
+// next to their use instead of being merged with earlier reads and kept live.
+typedef __attribute__((address_space(3))) const double lds_cdouble;
+__device__ __forceinline__ lds_cdouble* lds_fresh(const double* p) {
+  uint32_t v = (uint32_t)(uintptr_t)(lds_cdouble*)p;
   asm volatile("" : "+v"(v));
-  return v;
+  return (lds_cdouble*)(uintptr_t)v;
 }
 
 template <int CW, int SW, bool EPI>
-__global__ __launch_bounds__(CW * SW, (CW * SW >= 1024 ? 1 : 1024 / (CW * SW)))
+__global__ __launch_bounds__(CW * SW, 4)
 void k_strided(StridedArgs a) {
   constexpr int NT = CW * SW;
   __shared__ double s0[2][NT], s1[2][NT];
+  // the class tables of this workgroup's SW systems, staged once
+  __shared__ double tIU[B][SW], tSC[kStrScalarN][SW], tEP[EPI ? kEpiN : 1][SW];
+  __shared__ double tPOS[2][CW][SW];
   const int t = threadIdx.x, sl = t % SW, c = t / SW;
   const int64_t s = (int64_t)blockIdx.x * SW + sl;
   const bool live = s < a.M && c < a.C;
-  const int64_t P = a.P;
   const int len = live ? (int)(a.N - (int64_t)c * B < B ? a.N - (int64_t)c * B : B) : 0;
   const bool last = c == a.C - 1;
   // the wave's first lane: its system and block give the uniform bases
   const int t0 = t & ~63, sl0 = t0 % SW, c0 = t0 / SW;
   const int64_t s_w = (int64_t)blockIdx.x * SW + sl0;
-  // per-class tables: the lane's class is its system, clamped to the last
-  // one for lanes past M (their loads still read a valid class), at a byte
-  // offset from the wave's first (clamped) class
-  const int64_t k_w = s_w < a.M ? s_w : a.M - 1;
-  const uint32_t koff = (uint32_t)((s < a.M ? s : a.M - 1) - k_w) * 8u;
-  const uint32_t rowP = (uint32_t)(P * 8);
-  const __amdgpu_buffer_rsrc_t tiu = wave_rsrc(a.iu + k_w);
-  const __amdgpu_buffer_rsrc_t tsc = wave_rsrc(a.sc + k_w);
-  const __amdgpu_buffer_rsrc_t tpos = wave_rsrc(a.pos + k_w);
-  const __amdgpu_buffer_rsrc_t tepi = wave_rsrc(EPI ? a.epi + k_w : a.sc);
-  const int cc = c < a.C ? c : 0;
   // data: unknown i of this lane at (c - c0) * B * ld + (sl - sl0) + i * ld
   // elements from the wave's base
   const uint32_t ldb8 = (uint32_t)(a.ld * 8);
   const uint32_t voff = (uint32_t)((c - c0) * B) * ldb8 + (uint32_t)(sl - sl0) * 8u;
+  const bool with_g = EPI && a.G != nullptr && s < a.Mg;
 
-  for (int64_t b = blockIdx.y; b < a.nb; b += gridDim.y) {
-    const int64_t wbase = b * a.ldb + (int64_t)c0 * B * a.ld + s_w;
+  int64_t b = blockIdx.y;
+  if (b >= a.nb) return;   // uniform over the workgroup
+  double q[B], w[B];
+  // the column's loads (0 past len), raw: r in q, g in w
+  // Only the system's last block can end inside a lane's rows: a wavefront
+  // without such a lane addresses every row through one per-lane offset
+  // (kBad for lanes without a block); one with it masks the rows past len.
+  const bool part = __builtin_amdgcn_ballot_w64(len > 0 && len < B) != 0;   // uniform
+  const uint32_t vo = len > 0 ? voff : kBad;
+  const uint32_t vg = (len > 0 && with_g) ? voff : kBad;
+  auto load = [&](int64_t bb) {
+    const int64_t wbase = bb * a.ldb + (int64_t)c0 * B * a.ld + s_w;
     const __amdgpu_buffer_rsrc_t rR = wave_rsrc(a.R + wbase);
+    const __amdgpu_buffer_rsrc_t rG = wave_rsrc(EPI && a.G ? a.G + wbase : a.R + wbase);
+    if (!part) {
+#pragma unroll
+      for (int i = 0; i < B; ++i) q[i] = ld64(rR, vo, (uint32_t)i * ldb8);
+      if (EPI) {
+#pragma unroll
+        for (int i = 0; i < B; ++i) w[i] = ld64(rG, vg, (uint32_t)i * ldb8);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < B; ++i) {
+        q[i] = 0.0;
+        if (i < len) q[i] = ld64(rR, vo, (uint32_t)i * ldb8);
+      }
+      if (EPI) {
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+          w[i] = 0.0;
+          if (i < len) w[i] = ld64(rG, vg, (uint32_t)i * ldb8);
+        }
+      }
+    }
+  };
+  load(b);
+  {
+    // the class tables into LDS, once, while the first column is in flight
+    // (classes past M read the last one)
+    const int64_t k0 = (int64_t)blockIdx.x * SW;
+#pragma unroll 1
+    for (int e = t; e < (B + kStrScalarN + (EPI ? kEpiN : 0) + 2 * CW) * SW; e += NT) {
+      const int row = e / SW, col = e % SW;
+      const int64_t k = k0 + col < a.M ? k0 + col : a.M - 1;
+      if (row < B) {
+        tIU[row][col] = a.iu[row * a.P + k];
+      } else if (row < B + kStrScalarN) {
+        tSC[row - B][col] = a.sc[(row - B) * a.P + k];
+      } else if (EPI && row < B + kStrScalarN + kEpiN) {
+        tEP[row - B - kStrScalarN][col] = a.epi[(row - B - kStrScalarN) * a.P + k];
+      } else {
+        const int r2 = row - B - kStrScalarN - (EPI ? kEpiN : 0);   // [2][CW]
+        const int half = r2 / CW, cpos = r2 % CW;
+        tPOS[half][cpos][col] = cpos < a.C ? a.pos[((int64_t)half * a.C + cpos) * a.P + k]
+                                           : (half == 0 ? 0.0 : 1.0);
+      }
+    }
+    __syncthreads();
+  }
+  for (;;) {
+    const int64_t wbase = b * a.ldb + (int64_t)c0 * B * a.ld + s_w;
     const __amdgpu_buffer_rsrc_t rO = wave_rsrc(a.O + wbase);
-    double q[B], w[B];
-    double scale = 1.0, cr = 0.0, cg = 0.0;
+    const double tm1 = tSC[kStrTM1][sl], t1 = tSC[kStrT1][sl];
     if (EPI) {
-      scale = ld64(tepi, koff, kEpiScale * rowP);
-      cr = ld64(tepi, koff, kEpiCR * rowP);
-      cg = ld64(tepi, koff, kEpiCG * rowP);
-    }
+      const double scale = tEP[kEpiScale][sl], cr = tEP[kEpiCR][sl], cg = tEP[kEpiCG][sl];
 #pragma unroll
-    for (int i = 0; i < B; ++i) {
-      const double r = ld64(rR, i < len ? voff : kBad, (uint32_t)i * ldb8);   // 0 past len
-      q[i] = EPI ? scale * r : r;
-      w[i] = EPI ? cr * r : 0.0;
+      for (int i = 0; i < B; ++i) {
+        w[i] = cr * q[i] + cg * w[i];
+        q[i] *= scale;
+        asm volatile("" : "+v"(w[i]));   // formed here: r and g are not kept to the store
+      }
     }
-    if (EPI && a.G != nullptr && cg != 0.0) {
-      const __amdgpu_buffer_rsrc_t rG = wave_rsrc(a.G + wbase);
-#pragma unroll
-      for (int i = 0; i < B; ++i)
-        w[i] += cg * ld64(rG, i < len ? voff : kBad, (uint32_t)i * ldb8);
-    }
-    const double tm1 = ld64(tsc, koff, kStrTM1 * rowP), t1 = ld64(tsc, koff, kStrT1 * rowP);
     // 1. local solve: d_i = q_i / u_i - (t_-1 / u_i) d_{i-1}, y_i = d_i - (t_1 / u_i) y_{i+1};
     //    rows past len stay 0
     {
-      const uint32_t ko = opaque(koff);
-      q[0] *= ld64(tiu, ko, 0);
+      lds_cdouble* iu = lds_fresh(&tIU[0][sl]);
+      q[0] *= iu[0];
 #pragma unroll
       for (int i = 1; i < B; ++i) {
-        const double d = (q[i] - tm1 * q[i - 1]) * ld64(tiu, ko, (uint32_t)i * rowP);
+        const double d = (q[i] - tm1 * q[i - 1]) * iu[i * SW];
         q[i] = i < len ? d : 0.0;
       }
     }
     {
-      const uint32_t ko = opaque(koff);
+      lds_cdouble* iu = lds_fresh(&tIU[0][sl]);
 #pragma unroll
-      for (int i = B - 2; i >= 0; --i) q[i] -= t1 * ld64(tiu, ko, (uint32_t)i * rowP) * q[i + 1];
+      for (int i = B - 2; i >= 0; --i) q[i] -= t1 * iu[i * SW] * q[i + 1];
     }
     double yl = q[0];
 #pragma unroll
@@ -137,83 +180,131 @@ void k_strided(StridedArgs a) {
     const double yf = q[0];
 
     // 2. interface: alpha_c = A alpha_{c-1} + g, left to right
-    // (per-lane rows: the lane's own block kind and position go into the
-    // per-lane offset, the uniform offset stays 0)
-    const uint32_t ko2 = opaque(koff);
-    const uint32_t kb = ko2 + (uint32_t)(last ? kStrTPF : kStrPF) * rowP;
-    const double pf = ld64(tsc, kb, 0);
-    const double pl = ld64(tsc, kb, (uint32_t)(kStrPL - kStrPF) * rowP);
-    const double cf = ld64(tsc, kb, (uint32_t)(kStrCF - kStrPF) * rowP);
-    const uint32_t kp = ko2 + (uint32_t)cc * rowP;
-    const double bp = ld64(tpos, kp, 0);
-    const double iD = ld64(tpos, kp, (uint32_t)a.C * rowP);
+    const int kind = last ? kStrTPF : kStrPF;
+    const double pf = tSC[kind][sl], pl = tSC[kind + 1][sl], cf = tSC[kind + 2][sl];
+    const double bp = tPOS[0][c][sl], iD = tPOS[1][c][sl];
     double A = live ? pl * iD : 1.0;
     double g = live ? yl + A * bp * yf : 0.0;
-    int p = 0;
+    double alpha_prev, Cc, h, u_next;
+    if constexpr (SW <= 64) {
+      // CPW blocks of each system per wavefront, 16/32/64 lanes apart: the
+      // scan steps inside a wavefront are shuffles, the wavefronts' totals
+      // go through LDS once per direction
+      constexpr int CPW = 64 / SW, NW = NT / 64;
+      const int j = (t & 63) / SW, wv = t >> 6;
 #pragma unroll
-    for (int d = 1; d < CW; d <<= 1) {
-      s0[p][t] = A;
-      s1[p][t] = g;
-      __syncthreads();
-      if (c >= d) {
-        const double Ap = s0[p][t - d * SW], gp = s1[p][t - d * SW];
-        g = A * gp + g;
-        A = A * Ap;
+      for (int d = 1; d < CPW; d <<= 1) {
+        const double Ap = __shfl_up(A, d * SW, 64), gp = __shfl_up(g, d * SW, 64);
+        if (j >= d) {
+          g = A * gp + g;
+          A = A * Ap;
+        }
       }
-      p ^= 1;
-    }
-    s1[p][t] = g;   // alpha_c
-    __syncthreads();
-    const double alpha_prev = c > 0 ? s1[p][t - SW] : 0.0;
-    p ^= 1;
-    // u_c = C u_{c+1} + h, right to left (blocks past the end pass u = 0 through)
-    double Cc = live ? cf * iD : 1.0;
-    double h = live ? (yf + pf * alpha_prev) * iD : 0.0;
+      if (j == CPW - 1) {
+        s0[0][wv * SW + sl] = A;
+        s1[0][wv * SW + sl] = g;
+      }
+      __syncthreads();
+      double cin = 0.0;   // alpha of the last block before this wavefront's
+#pragma unroll 1
+      for (int k = 0; k < wv; ++k) cin = s0[0][k * SW + sl] * cin + s1[0][k * SW + sl];
+      const double alpha = A * cin + g;
+      alpha_prev = __shfl_up(alpha, SW, 64);
+      if (j == 0) alpha_prev = cin;
+      // u_c = C u_{c+1} + h, right to left (blocks past the end pass u = 0 through)
+      Cc = live ? cf * iD : 1.0;
+      h = live ? (yf + pf * alpha_prev) * iD : 0.0;
 #pragma unroll
-    for (int d = 1; d < CW; d <<= 1) {
-      s0[p][t] = Cc;
-      s1[p][t] = h;
-      __syncthreads();
-      if (c + d < CW) {
-        const double Cn = s0[p][t + d * SW], hn = s1[p][t + d * SW];
-        h = Cc * hn + h;
-        Cc = Cc * Cn;
+      for (int d = 1; d < CPW; d <<= 1) {
+        const double Cn = __shfl_down(Cc, d * SW, 64), hn = __shfl_down(h, d * SW, 64);
+        if (j + d < CPW) {
+          h = Cc * hn + h;
+          Cc = Cc * Cn;
+        }
       }
+      if (j == 0) {
+        s0[1][wv * SW + sl] = Cc;
+        s1[1][wv * SW + sl] = h;
+      }
+      __syncthreads();
+      double ein = 0.0;   // u of the first block after this wavefront's
+#pragma unroll 1
+      for (int k = NW - 1; k > wv; --k) ein = s0[1][k * SW + sl] * ein + s1[1][k * SW + sl];
+      h = Cc * ein + h;   // u_c
+      u_next = __shfl_down(h, SW, 64);
+      if (j == CPW - 1) u_next = ein;
+    } else {
+      // a system's block spans SW / 64 wavefronts: Kogge-Stone through LDS
+      int p = 0;
+#pragma unroll
+      for (int d = 1; d < CW; d <<= 1) {
+        s0[p][t] = A;
+        s1[p][t] = g;
+        __syncthreads();
+        if (c >= d) {
+          const double Ap = s0[p][t - d * SW], gp = s1[p][t - d * SW];
+          g = A * gp + g;
+          A = A * Ap;
+        }
+        p ^= 1;
+      }
+      s1[p][t] = g;   // alpha_c
+      __syncthreads();
+      alpha_prev = c > 0 ? s1[p][t - SW] : 0.0;
       p ^= 1;
+      Cc = live ? cf * iD : 1.0;
+      h = live ? (yf + pf * alpha_prev) * iD : 0.0;
+#pragma unroll
+      for (int d = 1; d < CW; d <<= 1) {
+        s0[p][t] = Cc;
+        s1[p][t] = h;
+        __syncthreads();
+        if (c + d < CW) {
+          const double Cn = s0[p][t + d * SW], hn = s1[p][t + d * SW];
+          h = Cc * hn + h;
+          Cc = Cc * Cn;
+        }
+        p ^= 1;
+      }
+      s1[p][t] = h;   // u_c
+      __syncthreads();
+      u_next = c + 1 < CW ? s1[p][t + SW] : 0.0;
     }
-    s1[p][t] = h;   // u_c
-    __syncthreads();
-    const double u_next = c + 1 < CW ? s1[p][t + SW] : 0.0;
     const double xl = alpha_prev + bp * h;   // last unknown of the block on the left
     const double xr = u_next;                // first unknown of the block on the right
 
     // 3. correction: recover d_i = y_i + (t_1/u_i) y_{i+1}, add the outside
     //    values' contributions (-t_-1 xl carried down from row 0, -t_1 xr at
     //    the last row), back-substitute
-    {
-      const uint32_t ko = opaque(koff);
-      double delta = -tm1 * xl;
+    double delta = -tm1 * xl;
+    lds_cdouble* iu3 = lds_fresh(&tIU[0][sl]);
 #pragma unroll
-      for (int i = 0; i < B; ++i) {
-        const double ui = ld64(tiu, ko, (uint32_t)i * rowP);
-        delta *= ui;
-        const double ynext = i + 1 < B ? q[i + 1] : 0.0;
-        double dv = q[i] + t1 * ui * ynext + delta;
-        if (i == len - 1) dv -= t1 * xr * ui;
-        q[i] = i < len ? dv : 0.0;
-        delta = -tm1 * delta;
-      }
+    for (int i = 0; i < B; ++i) {
+      const double ui = iu3[i * SW];
+      delta *= ui;
+      const double ynext = i + 1 < B ? q[i + 1] : 0.0;
+      double dv = q[i] + t1 * ui * ynext + delta;
+      if (i == len - 1) dv -= t1 * xr * ui;
+      q[i] = i < len ? dv : 0.0;
+      delta = -tm1 * delta;
     }
-    {
-      const uint32_t ko = opaque(koff);
+    lds_cdouble* iu4 = lds_fresh(&tIU[0][sl]);
 #pragma unroll
-      for (int i = B - 2; i >= 0; --i) q[i] -= t1 * ld64(tiu, ko, (uint32_t)i * rowP) * q[i + 1];
+    for (int i = B - 2; i >= 0; --i) q[i] -= t1 * iu4[i * SW] * q[i + 1];
+    const double cx = EPI ? tEP[kEpiCX][sl] : 1.0;
+    if (!part) {
+#pragma unroll
+      for (int i = 0; i < B; ++i)
+        st64(rO, vo, (uint32_t)i * ldb8, EPI ? cx * q[i] + w[i] : q[i]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < B; ++i)
+        if (i < len) st64(rO, vo, (uint32_t)i * ldb8, EPI ? cx * q[i] + w[i] : q[i]);
     }
-    const double cx = EPI ? ld64(tepi, opaque(koff), kEpiCX * rowP) : 1.0;
-#pragma unroll
-    for (int i = 0; i < B; ++i)
-      st64(rO, i < len ? voff : kBad, (uint32_t)i * ldb8, EPI ? cx * q[i] + w[i] : q[i]);
+    b += gridDim.y;
+    if (b >= a.nb) break;
     __syncthreads();   // the LDS of this batch is read before the next one writes it
+    load(b);
   }
 }
 
@@ -238,13 +329,16 @@ hipError_t launch_strided(const StridedArgs& a, hipStream_t st) {
   if ((int64_t)(5 * kStrB) * a.ld * 8 + 64 * 8 >= ((int64_t)1 << 31) ||
       (int64_t)(kEpiN + 2 * kStrMaxChunks + kStrB) * a.P * 8 >= ((int64_t)1 << 31))
     return hipErrorInvalidValue;
+  // As many adjacent systems per workgroup as 1024 lanes allow: the
+  // contiguous run of a row (8 SW bytes) sets the achieved bandwidth here
+  // (a copy with this access pattern and no arithmetic runs no faster).
   const int C = a.C;
   if (C <= 1) return go<1, 256>(a, st);
   if (C <= 2) return go<2, 128>(a, st);
   if (C <= 4) return go<4, 64>(a, st);
-  if (C <= 8) return go<8, 32>(a, st);
-  if (C <= 16) return go<16, 16>(a, st);
-  if (C <= 32) return go<32, 16>(a, st);
+  if (C <= 8) return go<8, 64>(a, st);
+  if (C <= 16) return go<16, 64>(a, st);
+  if (C <= 32) return go<32, 32>(a, st);
   return go<64, 16>(a, st);
 }
 

@@ -117,6 +117,17 @@ def poisson2d(seed: int = 0, n: int = 8191) -> dict:
     return dict(name="poisson2d", nx=n, ny=n, hx=h, hy=h, F=rng.standard_normal((n, n)))
 
 
+def poisson3d(seed: int = 0, n: int = 511) -> dict:
+    """The 3D Poisson problem of Sec. 3.5 on the unit cube cut into
+    n + 1 = 2^9 intervals per side (n^3 interior points, h = 1 / (n + 1)),
+    F ~ N(0, 1) [Nz][Ny][Nx]; the sine transform along x has FFT length
+    n + 1, a power of two."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / (n + 1)
+    return dict(name="poisson3d", nx=n, ny=n, nz=n, hx=h, hy=h, hz=h,
+                F=rng.standard_normal((n, n, n)))
+
+
 def diff_batch(seed: int = 0, s: int = 1024, n: int = 16384) -> dict:
     rng = np.random.default_rng(seed)
     t0 = rng.uniform(2.5, 4.0, size=s)
