@@ -19,6 +19,7 @@
 
 #include "tdt.h"
 #include "tdt_internal.h"
+#include "tdt_strided.h"
 
 
 using tdt::SysDesc;

@@ -30,6 +30,7 @@
 
 #include "tdt.h"
 #include "tdt_internal.h"
+#include "tdt_strided.h"
 
 struct tdt_poisson_s {
   int64_t nx = 0, ny = 0;

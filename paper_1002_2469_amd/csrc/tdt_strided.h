@@ -1,0 +1,44 @@
+// tdt_strided.h -- the strided batch solve (systems along a slow axis of an
+// array) shared by the host plan code, the 3D Poisson driver and its kernel.
+#pragma once
+#include <stdint.h>
+#include <hip/hip_runtime.h>
+
+namespace tdt {
+
+// Strided batches: systems whose consecutive unknowns lie ld elements apart
+// and whose neighbouring systems are adjacent in memory (the lines along a
+// slow axis of a 2D or 3D array).  A workgroup holds the whole column of SW
+// adjacent systems, kStrB rows per lane in registers, and runs the three
+// steps of the method on it: the lanes of one system are its blocks.
+constexpr int kStrB = 16;             // rows per lane (one block)
+constexpr int kStrMaxChunks = 64;     // blocks per system: N <= 1024
+// Per-class scalars, [field][P]: t_-1, t_1, the end values
+// (phi_first, phi_last, chi_first) of a full block and of the last block.
+enum { kStrTM1, kStrT1, kStrPF, kStrPL, kStrCF, kStrTPF, kStrTPL, kStrTCF, kStrScalarN };
+// Per-class epilogue, [field][P]: the right-hand side read is scaled by
+// kEpiScale before the solve, and the output is c_x x + c_r r + c_g g (r the
+// unscaled right-hand side, g a second input).
+enum { kEpiScale, kEpiCX, kEpiCR, kEpiCG, kEpiN };
+struct StridedArgs {
+  const double* R;          // right-hand sides (read)
+  double* O;                // output (may be R itself)
+  const double* G;          // second input of the epilogue (or null)
+  const double* epi;        // [kEpiN][P] or null (plain solve: O = x)
+  const double* iu;         // [kStrB][P] 1/u_i of the block LU
+  const double* sc;         // [kStrScalarN][P]
+  const double* pos;        // [2][C][P] per block position: beta_{c-1}, 1/(1 - phi_f beta_{c-1})
+  int64_t N, P, M, ld, nb, ldb;
+  int64_t Mg;               // systems s < Mg read G (the others take g = 0)
+  int C;                    // blocks per system, ceil(N / kStrB)
+};
+hipError_t launch_strided(const StridedArgs& a, hipStream_t st);
+// Host tables of P classes (t_-1, t_0, t_1)[k] for systems of order N, in
+// long double: iu [kStrB][P], sc [kStrScalarN][P], pos [2][C][P].  Returns a
+// negative status on a singular class or bad arguments; *dominance is the
+// smallest |t_0| / (|t_-1| + |t_1|) over the classes.
+int strided_tables(int64_t N, int64_t P, const double* tm1, const double* t0, const double* t1,
+                   double* iu, double* sc, double* pos, double* dominance);
+inline int strided_chunks(int64_t N) { return (int)((N + kStrB - 1) / kStrB); }
+
+}  // namespace tdt

@@ -22,6 +22,7 @@
 #include <stdint.h>
 
 #include "tdt_internal.h"
+#include "tdt_strided.h"
 
 namespace tdt {
 namespace {
