@@ -306,19 +306,15 @@ def run_poisson3d(tdt, d, F, steps, warmup, torch):
 
 def adi_bytes(d, counts):
     """Algorithmic HBM bytes of the ADI half-steps of one solve: per active
-    mode and line unknown, a y-sweep reads its right-hand side and fhat and
-    writes the next right-hand side (24 B; 16 B in the first iteration,
-    where both inputs are fhat), a z-sweep the same, but a mode's last one
-    does not read fhat (16 B)."""
+    mode and line unknown, a y-sweep reads its right-hand side and writes
+    the next one (16 B), a z-sweep reads that and fhat and writes (24 B)."""
     import numpy as np
     counts = np.asarray(counts)
     plane = d["ny"] * d["nz"]
     total = 0
     for j in range(int(counts.max())):
         P = int(np.sum(counts > j))
-        fin = int(np.sum(counts == j + 1))
-        total += (16 if j == 0 else 24) * P * plane          # y-sweep
-        total += (24 * P - 8 * fin) * plane                  # z-sweep
+        total += (16 + 24) * P * plane
     return float(total)
 
 

@@ -392,9 +392,10 @@ tdt_status_t tdt_poisson2d_destroy(tdt_poisson_t p) {
 // y, then along z, all modes of a plane at once; no transposes).  Its
 // right-hand side never needs the other direction's operator: with R1 the
 // first half-step's right-hand side, (w - A1) v' + fhat = 2 w v' - R1 + fhat,
-// and the next iteration's (w' - A2) v'' + fhat = (w' + w) v'' - R2 + fhat, so
-// each solve writes the next right-hand side directly (the fused epilogue),
-// and the last one of a mode writes v''.
+// and the next iteration's (w' - A2) v'' + fhat = (w' + w) v'' - R2 + fhat.
+// So the first half-step writes P2 = 2 w v' - R1, the second solves with
+// P2 + fhat (R2) and writes R1' = (w' + w) v'' - P2, or v'' in a mode's last
+// iteration: fhat is read once per iteration, by the second half-step.
 // Parameters: the optimal set of Jordan and Wachspress for the interval
 // [a_k, b_k] holding both spectra, w_j = b dn((2j - 1) K / (2J), m),
 // m = 1 - (a/b)^2; J_k is the smallest J whose error bound d_J^2 <= eps,
@@ -587,11 +588,14 @@ tdt_status_t tdt_poisson3d_create(int64_t nx, int64_t ny, int64_t nz, double hx,
         t0[(size_t)k] = (double)(2.0L + h2 * (wk + 0.5L * mu[(size_t)k]));
         epi[tdt::kEpiScale * P + k] = (double)h2;
         const bool fin = d == 1 && j + 1 == p->count[(size_t)k];
+        // y: solve R1, write P2 = 2w v' - R1; z: solve P2 + fhat, write
+        // R1' = (w' + w) v'' - P2, or v'' at the mode's last iteration
         long double cx = d == 0 ? 2.0L * wk
                                 : (fin ? 1.0L : w[(size_t)k][(size_t)j + 1] + wk);
+        epi[tdt::kEpiCQ * P + k] = d == 0 ? 0.0 : 1.0;
         epi[tdt::kEpiCX * P + k] = (double)cx;
         epi[tdt::kEpiCR * P + k] = fin ? 0.0 : -1.0;
-        epi[tdt::kEpiCG * P + k] = fin ? 0.0 : 1.0;
+        epi[tdt::kEpiCG * P + k] = 0.0;
       }
       double dom = 0.0;
       double* iu = tab.data() + base;
@@ -680,8 +684,7 @@ tdt_status_t tdt_poisson3d_solve(tdt_poisson3d_t p, const double* F, double* U,
       a.N = N;
       a.P = P;
       a.M = P;
-      // the modes whose last half-step this is take no fhat
-      a.Mg = d == 0 ? P : (j + 1 < p->jmax ? p->active[(size_t)j + 1] : 0);
+      a.Mg = d == 0 ? 0 : P;   // fhat: read by the second half-step only
       a.C = C;
       if (d == 0) {   // lines along y: rows nx apart, one batch per z plane
         a.ld = nx;

@@ -16,10 +16,10 @@ constexpr int kStrMaxChunks = 64;     // blocks per system: N <= 1024
 // Per-class scalars, [field][P]: t_-1, t_1, the end values
 // (phi_first, phi_last, chi_first) of a full block and of the last block.
 enum { kStrTM1, kStrT1, kStrPF, kStrPL, kStrCF, kStrTPF, kStrTPL, kStrTCF, kStrScalarN };
-// Per-class epilogue, [field][P]: the right-hand side read is scaled by
-// kEpiScale before the solve, and the output is c_x x + c_r r + c_g g (r the
-// unscaled right-hand side, g a second input).
-enum { kEpiScale, kEpiCX, kEpiCR, kEpiCG, kEpiN };
+// Per-class epilogue, [field][P]: with r the array read and g a second
+// input, the system solved is T x = scale (r + c_q g), and the output is
+// c_x x + c_r r + c_g g.
+enum { kEpiScale, kEpiCQ, kEpiCX, kEpiCR, kEpiCG, kEpiN };
 struct StridedArgs {
   const double* R;          // right-hand sides (read)
   double* O;                // output (may be R itself)

@@ -14,10 +14,10 @@
 //      evaluated as Kogge-Stone scans across the blocks through LDS;
 //   3. every lane re-sweeps its block with its two outside values folded
 //      into the first and last right-hand side row.
-// Systems of at most kStrMaxChunks * kStrB = 1024 rows.  An optional
-// epilogue writes c_x x + c_r r + c_g g per class instead of x (r the
-// right-hand side as read, g a second array): the update of an ADI
-// half-step fused into its solve.
+// Systems of at most kStrMaxChunks * kStrB = 1024 rows.  Optionally the
+// right-hand side is scale (r + c_q g) and the output c_x x + c_r r + c_g g
+// per class (r the array read, g a second array): an ADI half-step's
+// right-hand side and update fused into its solve.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -150,11 +150,13 @@ void k_strided(StridedArgs a) {
     const __amdgpu_buffer_rsrc_t rO = wave_rsrc(a.O + wbase);
     const double tm1 = tSC[kStrTM1][sl], t1 = tSC[kStrT1][sl];
     if (EPI) {
-      const double scale = tEP[kEpiScale][sl], cr = tEP[kEpiCR][sl], cg = tEP[kEpiCG][sl];
+      const double scale = tEP[kEpiScale][sl], cq = tEP[kEpiCQ][sl];
+      const double cr = tEP[kEpiCR][sl], cg = tEP[kEpiCG][sl];
 #pragma unroll
       for (int i = 0; i < B; ++i) {
-        w[i] = cr * q[i] + cg * w[i];
-        q[i] *= scale;
+        const double r = q[i], gi = w[i];
+        w[i] = cr * r + cg * gi;
+        q[i] = scale * (r + cq * gi);
         asm volatile("" : "+v"(w[i]));   // formed here: r and g are not kept to the store
       }
     }
