@@ -43,6 +43,9 @@ struct tdt_poisson_s {
   double* spec = nullptr;        // [Ny][(Nx + 1) / 2 + 1] complex spectra
   double* T = nullptr;           // [Nx][Ny] mode-major right-hand sides
   double* V = nullptr;           // [Nx][Ny] mode-major solutions
+  bool fused = false;            // Nx + 1 = 2 N2 (N2 a power of two): k_dst_rows
+  double* tw = nullptr;          // its twiddle tables
+  double* pw = nullptr;
 };
 
 namespace {
@@ -260,6 +263,249 @@ void launch_scan_rows(double* spec, int64_t nx, int64_t ny, double* U, double sc
   }
 }
 
+// ---------------------------------------------------------------------------
+// Fused sine transform of rows, for n = Nx + 1 = 2 N2 with N2 a power of two
+// in [64, 4096]: out[m-1] = scale S_m, S_m = sum_{j=1}^{n-1} f_j sin(pi j m / n),
+// in one pass over HBM (read a row, write a row).  Per row, in LDS: the
+// folded sequence y (the same fold as k_fold_rows) packed as
+// z_k = y_2k + i y_2k+1, its complex FFT of length N2 by Stockham autosort
+// passes (radix 4, one radix-2 pass first when log2 N2 is odd; Govindaraju
+// et al., SC 2008), the split into the real FFT Y of length n,
+// Y_k = E_k + e^{-2 pi i k / n} O_k with E_k = (Z_k + conj Z_{N2-k}) / 2 and
+// O_k = -i (Z_k - conj Z_{N2-k}) / 2, then S_2k = -Im Y_k and the odd
+// coefficients as the prefix sum of Re Y_k (as in k_scan_rows).  Twiddles
+// come from tables made in long double on the host: tw[q] = e^{-2 pi i q/N2},
+// pw[k] = e^{-2 pi i k/n}.  N2/4 threads per row, 256/(N2/4) rows per
+// workgroup for N2 <= 1024.
+constexpr int kDstMinN2 = 64, kDstMaxN2 = 4096;
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+template <int N2>
+struct DstShape {
+  static constexpr int TR = N2 / 4;                      // threads per row
+  static constexpr int RW = TR >= 256 ? 1 : 256 / TR;    // rows per workgroup
+  static constexpr int NT = TR * RW;
+  static constexpr int NWR = TR >= 64 ? TR / 64 : 1;     // wavefronts per row
+};
+
+// Raw buffer accesses with a wave-uniform base and range (SGPRs), a per-lane
+// byte offset and a uniform byte offset: no 64-bit address per access.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void* base, uint32_t bytes) {
+  const uint64_t a = reinterpret_cast<uintptr_t>(base);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  const uint32_t nb = __builtin_amdgcn_readfirstlane(bytes);
+  void* ub = reinterpret_cast<void*>((uintptr_t)(((uint64_t)hi << 32) | lo));
+  return __builtin_amdgcn_make_buffer_rsrc(ub, (short)0, (int)nb, 0x00020000);
+}
+__device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0));
+}
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s, double x) {
+  using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, x), r, v, s, 0);
+}
+
+template <int N2>
+__global__ __launch_bounds__(DstShape<N2>::NT) void k_dst_rows(
+    const double* __restrict__ in, double* __restrict__ out, int64_t rows, double scale,
+    const double* __restrict__ sn, const double2* __restrict__ tw,
+    const double2* __restrict__ pw) {
+  using S = DstShape<N2>;
+  constexpr int TR = S::TR, RW = S::RW, n = 2 * N2, nx = n - 1;
+  __shared__ double2 buf[RW][2][N2];
+  __shared__ double wt[RW][S::NWR];
+  const int t = threadIdx.x, rr = t / TR, j = t % TR;
+  // the rows of a wavefront: its first row's base, the lane's row offset
+  const int rr0 = (t & ~63) / TR;
+  const uint32_t lrow = (uint32_t)((rr - rr0) * nx) * 8u;
+  const __amdgpu_buffer_rsrc_t tsn = row_rsrc(sn, (uint32_t)n * 8u);
+  for (int64_t r0 = (int64_t)blockIdx.x * RW; r0 < rows; r0 += (int64_t)gridDim.x * RW) {
+    const int64_t r = r0 + rr;
+    const bool live = r < rows;
+    // the row into LDS (f_m+1 at m), coalesced; rows past the end read 0
+    const int64_t rw0 = r0 + rr0;
+    const uint32_t avail = rw0 < rows ? (uint32_t)(((rows - rw0) * nx) * 8 < (int64_t)1 << 31
+                                                       ? (rows - rw0) * nx * 8 : 0x7fffffff)
+                                      : 0u;
+    const __amdgpu_buffer_rsrc_t rin = row_rsrc(in + (rw0 < rows ? rw0 : 0) * nx, avail);
+    double* fl = reinterpret_cast<double*>(buf[rr][1]);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int m = j + TR * i;
+      const double v = bload(rin, lrow + (uint32_t)j * 8u, (uint32_t)(TR * i) * 8u);
+      if (m < nx) fl[m] = v;
+    }
+    __syncthreads();
+    // fold, packed in pairs: z_k = y_2k + i y_2k+1
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int k = j + TR * e;
+      double y2[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int jj = 2 * k + h;
+        const double a = jj > 0 ? fl[jj - 1] : 0.0, b = jj > 0 ? fl[n - jj - 1] : 0.0;
+        const double sv = bload(tsn, (uint32_t)(2 * j) * 8u, (uint32_t)(2 * TR * e + h) * 8u);
+        y2[h] = jj > 0 ? sv * (a + b) + 0.5 * (a - b) : 0.0;
+      }
+      buf[rr][0][k] = make_double2(y2[0], y2[1]);
+    }
+    __syncthreads();
+    // complex FFT of length N2, Stockham autosort
+    int src = 0;
+    int Ns = 1;
+    if constexpr ((__builtin_ctz(N2) & 1) != 0) {   // one radix-2 pass
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int jb = j + TR * e;
+        const double2 a = buf[rr][0][jb], b = buf[rr][0][jb + N2 / 2];
+        buf[rr][1][2 * jb] = cadd(a, b);
+        buf[rr][1][2 * jb + 1] = csub(a, b);
+      }
+      src = 1;
+      Ns = 2;
+      __syncthreads();
+    }
+    // (not unrolled: the twiddle loads of later passes would be hoisted
+    // and held in registers)
+#pragma unroll 1
+    for (; Ns < N2; Ns *= 4) {
+      const int lg = __builtin_ctz(Ns);
+      const int k = j & (Ns - 1);
+      const int q = k << (__builtin_ctz(N2) - 2 - lg);
+      double2 v0 = buf[rr][src][j], v1 = buf[rr][src][j + TR];
+      double2 v2 = buf[rr][src][j + 2 * TR], v3 = buf[rr][src][j + 3 * TR];
+      v1 = cmul(v1, tw[q]);
+      v2 = cmul(v2, tw[2 * q]);
+      v3 = cmul(v3, tw[3 * q]);
+      const double2 s0 = cadd(v0, v2), d0 = csub(v0, v2), s1 = cadd(v1, v3), d1 = csub(v1, v3);
+      const int idx = ((j >> lg) << (lg + 2)) + k;
+      double2* o = buf[rr][src ^ 1];
+      o[idx] = cadd(s0, s1);
+      o[idx + Ns] = make_double2(d0.x + d1.y, d0.y - d1.x);       // d0 - i d1
+      o[idx + 2 * Ns] = csub(s0, s1);
+      o[idx + 3 * Ns] = make_double2(d0.x - d1.y, d0.y + d1.x);   // d0 + i d1
+      src ^= 1;
+      __syncthreads();
+    }
+    // the real transform Y_k for k = 4j .. 4j+3, and the prefix sum of Re Y
+    const double2* Z = buf[rr][src];
+    double v[4], im[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int k = 4 * j + e;
+      const double2 zk = Z[k], zm = Z[(N2 - k) & (N2 - 1)];
+      const double2 E = make_double2(0.5 * (zk.x + zm.x), 0.5 * (zk.y - zm.y));
+      const double2 O = make_double2(0.5 * (zk.y + zm.y), -0.5 * (zk.x - zm.x));
+      const double2 Y = cadd(E, cmul(pw[k], O));
+      v[e] = k == 0 ? 0.5 * Y.x : Y.x;
+      im[e] = Y.y;
+    }
+#pragma unroll
+    for (int e = 1; e < 4; ++e) v[e] += v[e - 1];
+    double x = v[3];
+    constexpr int W = TR < 64 ? TR : 64;
+    const int lw = t % W;
+#pragma unroll
+    for (int d = 1; d < W; d <<= 1) {
+      const double yv = __shfl_up(x, d, W);
+      if (lw >= d) x += yv;
+    }
+    double carry = 0.0;
+    if constexpr (TR > 64) {
+      const int wv = j / 64;
+      if (lw == 63) wt[rr][wv] = x;
+      __syncthreads();
+      for (int q2 = 0; q2 < wv; ++q2) carry += wt[rr][q2];
+    }
+    const double off = carry + x - v[3];
+    // S in natural order (m - 1) in the free buffer, then coalesced stores
+    double* ob = reinterpret_cast<double*>(buf[rr][src ^ 1]);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int k = 4 * j + e;
+      if (2 * k + 1 <= nx) ob[2 * k] = off + v[e];
+      if (k >= 1) ob[2 * k - 1] = -im[e];
+    }
+    __syncthreads();
+    const __amdgpu_buffer_rsrc_t rout = row_rsrc(out + (rw0 < rows ? rw0 : 0) * nx, avail);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int m = j + TR * i;
+      if (m < nx && live)
+        bstore(rout, lrow + (uint32_t)j * 8u, (uint32_t)(TR * i) * 8u, scale * ob[m]);
+    }
+    __syncthreads();   // the buffers are rewritten by the next rows
+  }
+}
+
+bool dst_supported(int64_t nx) {
+  const int64_t n2 = (nx + 1) / 2;
+  return (nx + 1) % 2 == 0 && n2 >= kDstMinN2 && n2 <= kDstMaxN2 && (n2 & (n2 - 1)) == 0;
+}
+
+// The twiddle tables of k_dst_rows (long double): tw [N2], pw [N2] complex.
+void dst_tables(int64_t nx, std::vector<double>& tw, std::vector<double>& pw) {
+  const int64_t n = nx + 1, n2 = n / 2;
+  const long double pi = 3.141592653589793238462643383279502884L;
+  tw.assign((size_t)(2 * n2), 0.0);
+  pw.assign((size_t)(2 * n2), 0.0);
+  for (int64_t q = 0; q < n2; ++q) {
+    const long double a = -2.0L * pi * (long double)q / (long double)n2;
+    tw[(size_t)(2 * q)] = (double)std::cos(a);
+    tw[(size_t)(2 * q + 1)] = (double)std::sin(a);
+    const long double b = -2.0L * pi * (long double)q / (long double)n;
+    pw[(size_t)(2 * q)] = (double)std::cos(b);
+    pw[(size_t)(2 * q + 1)] = (double)std::sin(b);
+  }
+}
+
+void launch_dst_rows(const double* in, double* out, int64_t nx, int64_t rows, double scale,
+                     const double* sn, const double* tw, const double* pw, hipStream_t st) {
+  const int n2 = (int)((nx + 1) / 2);
+  const auto* t2 = reinterpret_cast<const double2*>(tw);
+  const auto* p2 = reinterpret_cast<const double2*>(pw);
+  switch (n2) {
+#define TDT_DST_CASE(N)                                                                    \
+  case N: {                                                                                \
+    const int64_t g = (rows + DstShape<N>::RW - 1) / DstShape<N>::RW;                      \
+    hipLaunchKernelGGL(k_dst_rows<N>, dim3((unsigned)std::min<int64_t>(g, 1 << 20)),       \
+                       dim3(DstShape<N>::NT), 0, st, in, out, rows, scale, sn, t2, p2);    \
+    return;                                                                                \
+  }
+    TDT_DST_CASE(64) TDT_DST_CASE(128) TDT_DST_CASE(256) TDT_DST_CASE(512)
+    TDT_DST_CASE(1024) TDT_DST_CASE(2048) TDT_DST_CASE(4096)
+#undef TDT_DST_CASE
+    default: return;
+  }
+}
+
+// out[c][r] = s in[r][c] for an R x C row-major array, through 32 x 33 LDS tiles.
+__global__ void k_transpose_scale(const double* __restrict__ in, double* __restrict__ out,
+                                  int64_t R, int64_t C, double s) {
+  __shared__ double tile[kTileP][kTileP + 1];
+  const int64_t c0 = (int64_t)blockIdx.x * kTileP;
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  for (int64_t r0 = (int64_t)blockIdx.y * kTileP; r0 < R; r0 += (int64_t)gridDim.y * kTileP) {
+    __syncthreads();   // the previous tile is read
+    for (int q = ty; q < kTileP; q += blockDim.y) {
+      const int64_t r = r0 + q, c = c0 + tx;
+      if (r < R && c < C) tile[q][tx] = s * in[r * C + c];
+    }
+    __syncthreads();
+    for (int q = ty; q < kTileP; q += blockDim.y) {
+      const int64_t c = c0 + q, r = r0 + tx;
+      if (c < C && r < R) out[c * R + r] = tile[tx][q];
+    }
+  }
+}
+
 void destroy_poisson(tdt_poisson_s* p) {
   if (!p) return;
   (void)hipDeviceSynchronize();
@@ -270,6 +516,8 @@ void destroy_poisson(tdt_poisson_s* p) {
   (void)hipFree(p->spec);
   (void)hipFree(p->T);
   (void)hipFree(p->V);
+  (void)hipFree(p->tw);
+  (void)hipFree(p->pw);
   delete p;
 }
 
@@ -309,10 +557,12 @@ tdt_status_t tdt_poisson2d_create(int64_t nx, int64_t ny, double hx, double hy,
   }
   st = tdt_plan_reserve(p->line, 1);
   const int64_t n = nx + 1, K = n / 2 + 1;
+  p->fused = dst_supported(nx);
   if (st == TDT_OK &&
       (hipMalloc(&p->sn, (size_t)n * sizeof(double)) != hipSuccess ||
        hipMalloc(&p->y, (size_t)(ny * n) * sizeof(double)) != hipSuccess ||
-       hipMalloc(&p->spec, (size_t)(ny * K) * 2 * sizeof(double)) != hipSuccess ||
+       (!p->fused &&
+        hipMalloc(&p->spec, (size_t)(ny * K) * 2 * sizeof(double)) != hipSuccess) ||
        hipMalloc(&p->T, (size_t)(nx * ny) * sizeof(double)) != hipSuccess ||
        hipMalloc(&p->V, (size_t)(nx * ny) * sizeof(double)) != hipSuccess))
     st = TDT_ERR_OOM;
@@ -323,7 +573,19 @@ tdt_status_t tdt_poisson2d_create(int64_t nx, int64_t ny, double hx, double hy,
         hipSuccess)
       st = TDT_ERR_HIP;
   }
-  if (st == TDT_OK) {
+  if (st == TDT_OK && p->fused) {
+    std::vector<double> tw, pw;
+    dst_tables(nx, tw, pw);
+    if (hipMalloc(&p->tw, tw.size() * sizeof(double)) != hipSuccess ||
+        hipMalloc(&p->pw, pw.size() * sizeof(double)) != hipSuccess)
+      st = TDT_ERR_OOM;
+    else if (hipMemcpy(p->tw, tw.data(), tw.size() * sizeof(double), hipMemcpyHostToDevice) !=
+                 hipSuccess ||
+             hipMemcpy(p->pw, pw.data(), pw.size() * sizeof(double), hipMemcpyHostToDevice) !=
+                 hipSuccess)
+      st = TDT_ERR_HIP;
+  }
+  if (st == TDT_OK && !p->fused) {
     int len[1] = {(int)n};
     if (hipfftPlanMany(&p->fft, 1, len, nullptr, 1, (int)n, nullptr, 1, (int)K, HIPFFT_D2Z,
                        (int)ny) != HIPFFT_SUCCESS)
@@ -343,8 +605,23 @@ tdt_status_t tdt_poisson2d_solve(tdt_poisson_t p, const double* F, double* U,
                                  hipStream_t stream) {
   if (!p || !F || !U) return TDT_ERR_INVALID_ARG;
   const int64_t nx = p->nx, ny = p->ny, n = nx + 1;
-  if (hipfftSetStream(p->fft, stream) != HIPFFT_SUCCESS) return TDT_ERR_HIP;
   auto gy = [](int64_t v) { return (unsigned)(v < (int64_t)kMaxGridY ? v : kMaxGridY); };
+  if (p->fused) {
+    // rows' sine transforms in one pass each, transposes to and from
+    // mode-major order (the forward one scaled)
+    const dim3 trow((unsigned)((nx + kTileP - 1) / kTileP), gy((ny + kTileP - 1) / kTileP));
+    const dim3 tcol((unsigned)((ny + kTileP - 1) / kTileP), gy((nx + kTileP - 1) / kTileP));
+    launch_dst_rows(F, p->y, nx, ny, 1.0, p->sn, p->tw, p->pw, stream);
+    hipLaunchKernelGGL(k_transpose_scale, trow, dim3(kTileP, 8), 0, stream, p->y, p->T, ny, nx,
+                       p->hy * p->hy * 2.0 / (double)(nx + 1));
+    tdt_status_t st = tdt_solve_varlen(p->line, p->T, p->V, stream);
+    if (st < 0) return st;
+    hipLaunchKernelGGL(k_transpose_scale, tcol, dim3(kTileP, 8), 0, stream, p->V, p->y, nx, ny,
+                       1.0);
+    launch_dst_rows(p->y, U, nx, ny, 1.0, p->sn, p->tw, p->pw, stream);
+    return hipGetLastError() == hipSuccess ? TDT_OK : TDT_ERR_HIP;
+  }
+  if (hipfftSetStream(p->fft, stream) != HIPFFT_SUCCESS) return TDT_ERR_HIP;
   const dim3 tiles((unsigned)((nx + 1 + kTileP - 1) / kTileP), gy((ny + kTileP - 1) / kTileP));
   auto* spec = reinterpret_cast<hipfftDoubleComplex*>(p->spec);
   // sine transform of the rows, scaled and transposed to mode-major order
@@ -411,6 +688,10 @@ struct tdt_poisson3d_s {
   double* y = nullptr;      // [Ny Nz][Nx + 1] folded rows
   double* spec = nullptr;   // [Ny Nz][(Nx + 1) / 2 + 1] complex spectra; the ADI work array
   double* tabs = nullptr;   // per iteration and direction: iu | sc | pos | epi of its modes
+  bool fused = false;       // Nx + 1 = 2 N2 (N2 a power of two): k_dst_rows, no FFT buffers
+  double* tw = nullptr;     // its twiddle tables
+  double* pw = nullptr;
+  double* W = nullptr;      // the ADI work array (the spectrum buffer otherwise)
   std::vector<int> count;                  // J_k
   std::vector<double> omega;               // [k][jmax]
   int jmax = 0;
@@ -496,6 +777,9 @@ void destroy_poisson3d(tdt_poisson3d_s* p) {
   (void)hipFree(p->y);
   (void)hipFree(p->spec);
   (void)hipFree(p->tabs);
+  (void)hipFree(p->tw);
+  (void)hipFree(p->pw);
+  (void)hipFree(p->W);
   delete p;
 }
 
@@ -606,12 +890,27 @@ tdt_status_t tdt_poisson3d_create(int64_t nx, int64_t ny, int64_t nz, double hx,
     }
   }
   const int64_t n = nx + 1, Kc = n / 2 + 1, rows = ny * nz;
+  p->fused = dst_supported(nx);
   if (st == TDT_OK &&
       (hipMalloc(&p->sn, (size_t)n * sizeof(double)) != hipSuccess ||
-       hipMalloc(&p->y, (size_t)(rows * n) * sizeof(double)) != hipSuccess ||
-       hipMalloc(&p->spec, (size_t)(rows * Kc) * 2 * sizeof(double)) != hipSuccess ||
+       (p->fused && hipMalloc(&p->W, (size_t)(rows * nx) * sizeof(double)) != hipSuccess) ||
+       (!p->fused && hipMalloc(&p->y, (size_t)(rows * n) * sizeof(double)) != hipSuccess) ||
+       (!p->fused &&
+        hipMalloc(&p->spec, (size_t)(rows * Kc) * 2 * sizeof(double)) != hipSuccess) ||
        hipMalloc(&p->tabs, tab.size() * sizeof(double)) != hipSuccess))
     st = TDT_ERR_OOM;
+  if (st == TDT_OK && p->fused) {
+    std::vector<double> tw, pw;
+    dst_tables(nx, tw, pw);
+    if (hipMalloc(&p->tw, tw.size() * sizeof(double)) != hipSuccess ||
+        hipMalloc(&p->pw, pw.size() * sizeof(double)) != hipSuccess)
+      st = TDT_ERR_OOM;
+    else if (hipMemcpy(p->tw, tw.data(), tw.size() * sizeof(double), hipMemcpyHostToDevice) !=
+                 hipSuccess ||
+             hipMemcpy(p->pw, pw.data(), pw.size() * sizeof(double), hipMemcpyHostToDevice) !=
+                 hipSuccess)
+      st = TDT_ERR_HIP;
+  }
   if (st == TDT_OK) {
     std::vector<double> sn((size_t)n);
     for (int64_t j = 0; j < n; ++j) sn[(size_t)j] = (double)std::sin(kPi * (long double)j / n);
@@ -621,7 +920,7 @@ tdt_status_t tdt_poisson3d_create(int64_t nx, int64_t ny, int64_t nz, double hx,
             hipSuccess)
       st = TDT_ERR_HIP;
   }
-  if (st == TDT_OK) {
+  if (st == TDT_OK && !p->fused) {
     int len[1] = {(int)n};
     if (hipfftPlanMany(&p->fft, 1, len, nullptr, 1, (int)n, nullptr, 1, (int)Kc, HIPFFT_D2Z,
                        (int)rows) != HIPFFT_SUCCESS)
@@ -645,7 +944,7 @@ tdt_status_t tdt_poisson3d_solve(tdt_poisson3d_t p, const double* F, double* U,
   if (F == U || (reinterpret_cast<const char*>(F) < reinterpret_cast<const char*>(U) + bytes &&
                  reinterpret_cast<const char*>(U) < reinterpret_cast<const char*>(F) + bytes))
     return TDT_ERR_INVALID_ARG;
-  if (hipfftSetStream(p->fft, stream) != HIPFFT_SUCCESS) return TDT_ERR_HIP;
+  if (!p->fused && hipfftSetStream(p->fft, stream) != HIPFFT_SUCCESS) return TDT_ERR_HIP;
   hipEvent_t* ev = nullptr;
   if (p->profile) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -661,13 +960,18 @@ tdt_status_t tdt_poisson3d_solve(tdt_poisson3d_t p, const double* F, double* U,
   auto* spec = reinterpret_cast<hipfftDoubleComplex*>(p->spec);
   if (ev) (void)hipEventRecord(ev[0], stream);
   // fhat (in U): the scaled sine transform of every row along x
-  hipLaunchKernelGGL(k_fold_rows, dim3((unsigned)((n + 255) / 256), gy(rows)), dim3(256), 0,
-                     stream, F, p->sn, p->y, nx, rows);
-  if (hipfftExecD2Z(p->fft, p->y, spec) != HIPFFT_SUCCESS) return TDT_ERR_HIP;
-  launch_scan_rows(p->spec, nx, rows, U, 2.0 / (double)(nx + 1), stream);
+  if (p->fused) {
+    launch_dst_rows(F, U, nx, rows, 2.0 / (double)(nx + 1), p->sn, p->tw, p->pw, stream);
+  } else {
+    hipLaunchKernelGGL(k_fold_rows, dim3((unsigned)((n + 255) / 256), gy(rows)), dim3(256), 0,
+                       stream, F, p->sn, p->y, nx, rows);
+    if (hipfftExecD2Z(p->fft, p->y, spec) != HIPFFT_SUCCESS) return TDT_ERR_HIP;
+    launch_scan_rows(p->spec, nx, rows, U, 2.0 / (double)(nx + 1), stream);
+  }
   if (ev) (void)hipEventRecord(ev[1], stream);
-  // ADI: W (in the spectrum buffer) holds each mode's current right-hand side
-  double* W = p->spec;
+  // ADI: W (its own array, or the spectrum buffer) holds each mode's current
+  // right-hand side
+  double* W = p->fused ? p->W : p->spec;
   for (int j = 0; j < p->jmax; ++j) {
     const int64_t P = p->active[(size_t)j];
     for (int d = 0; d < 2; ++d) {
@@ -700,10 +1004,14 @@ tdt_status_t tdt_poisson3d_solve(tdt_poisson3d_t p, const double* F, double* U,
   }
   if (ev) (void)hipEventRecord(ev[2], stream);
   // U: the (unscaled) sine transform of the mode coefficients of every row
-  hipLaunchKernelGGL(k_fold_rows, dim3((unsigned)((n + 255) / 256), gy(rows)), dim3(256), 0,
-                     stream, W, p->sn, p->y, nx, rows);
-  if (hipfftExecD2Z(p->fft, p->y, spec) != HIPFFT_SUCCESS) return TDT_ERR_HIP;
-  launch_scan_rows(p->spec, nx, rows, U, 1.0, stream);
+  if (p->fused) {
+    launch_dst_rows(W, U, nx, rows, 1.0, p->sn, p->tw, p->pw, stream);
+  } else {
+    hipLaunchKernelGGL(k_fold_rows, dim3((unsigned)((n + 255) / 256), gy(rows)), dim3(256), 0,
+                       stream, W, p->sn, p->y, nx, rows);
+    if (hipfftExecD2Z(p->fft, p->y, spec) != HIPFFT_SUCCESS) return TDT_ERR_HIP;
+    launch_scan_rows(p->spec, nx, rows, U, 1.0, stream);
+  }
   if (ev) (void)hipEventRecord(ev[3], stream);
   return hipGetLastError() == hipSuccess ? TDT_OK : TDT_ERR_HIP;
 }

@@ -34,7 +34,10 @@ def tol(nx, ny, hx, hy):
     return max(1e-12, 8 * U64 * kappa(nx, ny, hx, hy))
 
 
-GRIDS = [(1, 1), (1, 9), (7, 1), (31, 17), (64, 64), (100, 257), (513, 700), (16, 20000)]
+# Nx + 1 = 2 N2 with N2 a power of two in [64, 4096] takes the fused row
+# transform (127 .. 8191), the other sizes hipFFT's
+GRIDS = [(1, 1), (1, 9), (7, 1), (31, 17), (64, 64), (100, 257), (513, 700), (16, 20000),
+         (127, 3), (255, 130), (1023, 41), (2047, 5), (4095, 19)]
 
 
 @pytest.mark.parametrize("nx,ny", GRIDS)

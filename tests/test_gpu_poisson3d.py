@@ -25,8 +25,9 @@ def _rel2(x, y):
     return float(np.linalg.norm(x - y) / np.linalg.norm(y))
 
 
+# Nx = 127, 255, 1023 take the fused row transform, the others hipFFT's
 GRIDS = [(1, 1, 1), (3, 4, 5), (7, 9, 4), (16, 17, 15), (31, 20, 17), (12, 1, 40),
-         (20, 33, 1), (63, 64, 65)]
+         (20, 33, 1), (63, 64, 65), (127, 20, 30), (255, 17, 9), (1023, 3, 4)]
 
 
 @pytest.mark.parametrize("nx,ny,nz", GRIDS)
