@@ -335,6 +335,22 @@ __global__ __launch_bounds__(DstShape<N2>::NT) void k_dst_rows(
                                       : 0u;
     const __amdgpu_buffer_rsrc_t rin = row_rsrc(in + (rw0 < rows ? rw0 : 0) * nx, avail);
     double* fl = reinterpret_cast<double*>(buf[rr][1]);
+    // one twiddle per pass (W^q; W^2q and W^3q follow from it), each loaded
+    // one pass ahead, the first and the real split's with the row
+    constexpr int L2 = __builtin_ctz(N2), NS0 = (L2 & 1) ? 2 : 1, NP = L2 / 2;
+    auto twq = [&](int ps) {
+      const int lg = __builtin_ctz(NS0) + 2 * ps;   // Ns = NS0 4^ps
+      return tw[(j & ((1 << lg) - 1)) << (L2 - 2 - lg)];
+    };
+    double2 wcur = twq(0);
+    const double2 pw0 = pw[4 * j];
+    // the fold's sines, with the row too
+    double sv[4][2];
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        sv[e][h] = bload(tsn, (uint32_t)(2 * j) * 8u, (uint32_t)(2 * TR * e + h) * 8u);
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int m = j + TR * i;
@@ -351,8 +367,7 @@ __global__ __launch_bounds__(DstShape<N2>::NT) void k_dst_rows(
       for (int h = 0; h < 2; ++h) {
         const int jj = 2 * k + h;
         const double a = jj > 0 ? fl[jj - 1] : 0.0, b = jj > 0 ? fl[n - jj - 1] : 0.0;
-        const double sv = bload(tsn, (uint32_t)(2 * j) * 8u, (uint32_t)(2 * TR * e + h) * 8u);
-        y2[h] = jj > 0 ? sv * (a + b) + 0.5 * (a - b) : 0.0;
+        y2[h] = jj > 0 ? sv[e][h] * (a + b) + 0.5 * (a - b) : 0.0;
       }
       buf[rr][0][k] = make_double2(y2[0], y2[1]);
     }
@@ -372,18 +387,18 @@ __global__ __launch_bounds__(DstShape<N2>::NT) void k_dst_rows(
       Ns = 2;
       __syncthreads();
     }
-    // (not unrolled: the twiddle loads of later passes would be hoisted
-    // and held in registers)
 #pragma unroll 1
-    for (; Ns < N2; Ns *= 4) {
-      const int lg = __builtin_ctz(Ns);
+    for (int ps = 0; ps < NP; ++ps, Ns *= 4) {
+      const int lg = __builtin_ctz(NS0) + 2 * ps;
       const int k = j & (Ns - 1);
-      const int q = k << (__builtin_ctz(N2) - 2 - lg);
+      const double2 wnext = twq(ps + 1 < NP ? ps + 1 : ps);
       double2 v0 = buf[rr][src][j], v1 = buf[rr][src][j + TR];
       double2 v2 = buf[rr][src][j + 2 * TR], v3 = buf[rr][src][j + 3 * TR];
-      v1 = cmul(v1, tw[q]);
-      v2 = cmul(v2, tw[2 * q]);
-      v3 = cmul(v3, tw[3 * q]);
+      const double2 w1 = wcur, w2 = cmul(w1, w1), w3 = cmul(w2, w1);
+      wcur = wnext;
+      v1 = cmul(v1, w1);
+      v2 = cmul(v2, w2);
+      v3 = cmul(v3, w3);
       const double2 s0 = cadd(v0, v2), d0 = csub(v0, v2), s1 = cadd(v1, v3), d1 = csub(v1, v3);
       const int idx = ((j >> lg) << (lg + 2)) + k;
       double2* o = buf[rr][src ^ 1];
@@ -397,15 +412,17 @@ __global__ __launch_bounds__(DstShape<N2>::NT) void k_dst_rows(
     // the real transform Y_k for k = 4j .. 4j+3, and the prefix sum of Re Y
     const double2* Z = buf[rr][src];
     double v[4], im[4];
+    double2 pwk = pw0;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int k = 4 * j + e;
       const double2 zk = Z[k], zm = Z[(N2 - k) & (N2 - 1)];
       const double2 E = make_double2(0.5 * (zk.x + zm.x), 0.5 * (zk.y - zm.y));
       const double2 O = make_double2(0.5 * (zk.y + zm.y), -0.5 * (zk.x - zm.x));
-      const double2 Y = cadd(E, cmul(pw[k], O));
+      const double2 Y = cadd(E, cmul(pwk, O));
       v[e] = k == 0 ? 0.5 * Y.x : Y.x;
       im[e] = Y.y;
+      pwk = cmul(pwk, pw[1]);   // e^{-2 pi i (k + 1) / n}
     }
 #pragma unroll
     for (int e = 1; e < 4; ++e) v[e] += v[e - 1];
