@@ -124,14 +124,14 @@ def load_workload(name: str, args):
         d.update(kind="poisson", units=d["nx"] * d["ny"],
                  desc=f"poisson2d: five-point Poisson problem on {d['nx']}x{d['ny']} interior "
                       f"points of the unit square, zero boundary, F~N(0,1) seed 0, [Ny][Nx] "
-                      f"double in/out; sine transforms (hipFFT) + one Toeplitz line system per "
-                      f"mode + inverse transforms")
+                      f"double in/out; sine transforms of the rows (fused: fold, FFT in LDS, "
+                      f"prefix sum) + one Toeplitz line system per mode + inverse transforms")
     elif name == "poisson3d":
         d = W.poisson3d(seed=0)
         d.update(kind="poisson3d", units=d["nx"] * d["ny"] * d["nz"], eps=1e-13,
                  desc=f"poisson3d: seven-point Poisson problem on {d['nx']}x{d['ny']}x{d['nz']} "
                       f"interior points of the unit cube, zero boundary, F~N(0,1) seed 0, "
-                      f"[Nz][Ny][Nx] double in/out; sine transform along x (hipFFT), "
+                      f"[Nz][Ny][Nx] double in/out; sine transform along x (fused row transform), "
                       f"Peaceman-Rachford ADI per mode plane (optimal parameters, eps 1e-13, "
                       f"strided line solves along y and z), inverse transform")
     elif name == "diff":
@@ -482,8 +482,9 @@ def main() -> int:
                             if d["kind"] == "general" else
                             "k_tile<double, float, REFINE, final> (solve, refine and store)"
                             if head == "f32_refine" else "k_tile<double, double, final> (solve and store)"),
-             "line_final_pass": "k_sys<double, double> (the mode line systems, solved whole; "
-                                "the sine transforms around it are hipFFT's)",
+             "line_final_pass": "k_sys<double, double> (the mode line systems, solved whole: "
+                                "the tridiagonal solve; the row transforms around it take "
+                                "longer, see the kernel profile)",
              "adi": "k_strided<double> with the ADI epilogue (all 2 J_1 half-steps of one "
                     "solve: bytes and time summed over them)",
              "bwd_first_pass": "k_tile<double, *, SUMMARY> on T^T (adjoint first pass)",
