@@ -170,14 +170,16 @@ tdt_status_t tdt_solve_strided(tdt_plan_t plan, const double *F, double *X, int6
  * and of the paper's timings): the five-point system
  *     (2u_ij - u_{i-1,j} - u_{i+1,j}) / hx^2 + (2u_ij - u_{i,j-1} - u_{i,j+1}) / hy^2 = f_ij
  * on Nx x Ny interior points with u = 0 on the boundary.  A sine transform
- * along x (a real FFT of length Nx+1 of each folded row, hipFFT, then a
- * prefix sum for the odd coefficients) leaves one tridiagonal Toeplitz
+ * along x (a real FFT of length Nx+1 of each folded row, then a prefix sum
+ * for the odd coefficients: in one kernel when Nx+1 is a power of two from
+ * 128 to 8192, through hipFFT otherwise) leaves one tridiagonal Toeplitz
  * system per mode k along y, t_+-1 = -1,
  * t_0 = 2 + hy^2 (4/hx^2) sin^2(pi k / (2 (Nx+1))), solved by a varlen plan of
  * this library (dtype TDT_F64 or TDT_F32_REFINE); the inverse transform
- * gives U.  The handle owns the line plan, the FFT plan and
- * 2 Nx Ny + Ny (Nx + 1) + 2 Ny (floor((Nx+1)/2) + 1) doubles of workspace
- * (allocated here, blocking).  Errors: sizes
+ * gives U.  The handle owns the line plan, the twiddle tables or the FFT
+ * plan, and 2 Nx Ny + Ny (Nx + 1) doubles of workspace, plus
+ * 2 Ny (floor((Nx+1)/2) + 1) on the hipFFT path (allocated here,
+ * blocking).  Errors: sizes
  * < 1 or Nx Ny > 2^31, non-positive or non-finite spacings, another dtype ->
  * TDT_ERR_INVALID_ARG; allocation -> TDT_ERR_OOM; an FFT plan failure ->
  * TDT_ERR_HIP. */
@@ -210,9 +212,10 @@ tdt_status_t tdt_poisson2d_destroy(tdt_poisson_t p);
  * 2-norm error of the result relative to the exact discrete solution is at
  * most eps (plus rounding).  J_k falls as k grows.  1 <= Ny, Nz <= 1024,
  * 640 Nx Ny < 2^31 (31-bit byte offsets of the z lines), 0 < eps < 1.  The handle
- * owns the FFT plan, the per-iteration tables (~(36 + 4 ceil(N/16)) doubles
- * per mode and iteration) and (2 Nx + 3) Ny Nz doubles of workspace
- * (allocated here, blocking).  Errors: bad sizes, spacings or eps ->
+ * owns the per-iteration tables (~(38 + 4 ceil(N/16)) doubles per mode and
+ * iteration) and Nx Ny Nz doubles of workspace when Nx+1 is a power of two
+ * from 128 to 8192 (the fused row transform), else the FFT plan and
+ * (2 Nx + 3) Ny Nz doubles (allocated here, blocking).  Errors: bad sizes, spacings or eps ->
  * TDT_ERR_INVALID_ARG; allocation -> TDT_ERR_OOM; FFT plan -> TDT_ERR_HIP. */
 typedef struct tdt_poisson3d_s *tdt_poisson3d_t;
 tdt_status_t tdt_poisson3d_create(int64_t nx, int64_t ny, int64_t nz, double hx, double hy,
