@@ -318,7 +318,13 @@ __global__ __launch_bounds__(DstShape<N2>::NT) void k_dst_rows(
     const double2* __restrict__ pw) {
   using S = DstShape<N2>;
   constexpr int TR = S::TR, RW = S::RW, n = 2 * N2, nx = n - 1;
-  __shared__ double2 buf[RW][2][N2];
+  // One buffer per row up to N2 = 2048: the row, then the transform, every
+  // pass reading its four values into registers before any thread writes
+  // (two barriers per pass), which halves the LDS of ping-pong buffers and
+  // fits more workgroups on a compute unit.  At N2 = 4096 (1024 threads per
+  // row) the barriers cost more than the second workgroup gains: ping-pong.
+  constexpr bool PP = N2 >= 4096;
+  __shared__ double2 buf[RW][PP ? 2 : 1][N2];
   __shared__ double wt[RW][S::NWR];
   const int t = threadIdx.x, rr = t / TR, j = t % TR;
   // the rows of a wavefront: its first row's base, the lane's row offset
@@ -334,10 +340,12 @@ __global__ __launch_bounds__(DstShape<N2>::NT) void k_dst_rows(
                                                        ? (rows - rw0) * nx * 8 : 0x7fffffff)
                                       : 0u;
     const __amdgpu_buffer_rsrc_t rin = row_rsrc(in + (rw0 < rows ? rw0 : 0) * nx, avail);
-    double* fl = reinterpret_cast<double*>(buf[rr][1]);
+    double* fl = reinterpret_cast<double*>(buf[rr][0]);
     // one twiddle per pass (W^q; W^2q and W^3q follow from it), each loaded
     // one pass ahead, the first and the real split's with the row
-    constexpr int L2 = __builtin_ctz(N2), NS0 = (L2 & 1) ? 2 : 1, NP = L2 / 2;
+    constexpr int L2 = __builtin_ctz(N2), ODD = L2 & 1, NP = L2 / 2;
+    constexpr int NS0 = ODD ? 2 : 4;   // Ns of the first pass taken from LDS
+    constexpr int NPL = NP - (ODD ? 0 : 1);
     auto twq = [&](int ps) {
       const int lg = __builtin_ctz(NS0) + 2 * ps;   // Ns = NS0 4^ps
       return tw[(j & ((1 << lg) - 1)) << (L2 - 2 - lg)];
@@ -358,7 +366,8 @@ __global__ __launch_bounds__(DstShape<N2>::NT) void k_dst_rows(
       if (m < nx) fl[m] = v;
     }
     __syncthreads();
-    // fold, packed in pairs: z_k = y_2k + i y_2k+1
+    // fold, packed in pairs: z_k = y_2k + i y_2k+1 for k = j + TR e
+    double2 z[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int k = j + TR * e;
@@ -369,29 +378,34 @@ __global__ __launch_bounds__(DstShape<N2>::NT) void k_dst_rows(
         const double a = jj > 0 ? fl[jj - 1] : 0.0, b = jj > 0 ? fl[n - jj - 1] : 0.0;
         y2[h] = jj > 0 ? sv[e][h] * (a + b) + 0.5 * (a - b) : 0.0;
       }
-      buf[rr][0][k] = make_double2(y2[0], y2[1]);
+      z[e] = make_double2(y2[0], y2[1]);
     }
-    __syncthreads();
-    // complex FFT of length N2, Stockham autosort
-    int src = 0;
-    int Ns = 1;
-    if constexpr ((__builtin_ctz(N2) & 1) != 0) {   // one radix-2 pass
+    __syncthreads();   // the row is read
+    // complex FFT of length N2, Stockham autosort; its first pass works on
+    // the thread's own z (the inputs of butterfly j are z_{j + r TR})
+    int src = PP ? 1 : 0;
+    if constexpr (ODD) {   // radix 2, Ns = 1: butterflies j and j + TR
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
         const int jb = j + TR * e;
-        const double2 a = buf[rr][0][jb], b = buf[rr][0][jb + N2 / 2];
-        buf[rr][1][2 * jb] = cadd(a, b);
-        buf[rr][1][2 * jb + 1] = csub(a, b);
+        buf[rr][src][2 * jb] = cadd(z[e], z[e + 2]);
+        buf[rr][src][2 * jb + 1] = csub(z[e], z[e + 2]);
       }
-      src = 1;
-      Ns = 2;
-      __syncthreads();
+    } else {               // radix 4, Ns = 1 (no twiddles)
+      const double2 s0 = cadd(z[0], z[2]), d0 = csub(z[0], z[2]);
+      const double2 s1 = cadd(z[1], z[3]), d1 = csub(z[1], z[3]);
+      buf[rr][src][4 * j] = cadd(s0, s1);
+      buf[rr][src][4 * j + 1] = make_double2(d0.x + d1.y, d0.y - d1.x);
+      buf[rr][src][4 * j + 2] = csub(s0, s1);
+      buf[rr][src][4 * j + 3] = make_double2(d0.x - d1.y, d0.y + d1.x);
     }
+    __syncthreads();
+    int Ns = NS0;
 #pragma unroll 1
-    for (int ps = 0; ps < NP; ++ps, Ns *= 4) {
+    for (int ps = 0; ps < NPL; ++ps, Ns *= 4) {
       const int lg = __builtin_ctz(NS0) + 2 * ps;
       const int k = j & (Ns - 1);
-      const double2 wnext = twq(ps + 1 < NP ? ps + 1 : ps);
+      const double2 wnext = twq(ps + 1 < NPL ? ps + 1 : ps);
       double2 v0 = buf[rr][src][j], v1 = buf[rr][src][j + TR];
       double2 v2 = buf[rr][src][j + 2 * TR], v3 = buf[rr][src][j + 3 * TR];
       const double2 w1 = wcur, w2 = cmul(w1, w1), w3 = cmul(w2, w1);
@@ -401,12 +415,13 @@ __global__ __launch_bounds__(DstShape<N2>::NT) void k_dst_rows(
       v3 = cmul(v3, w3);
       const double2 s0 = cadd(v0, v2), d0 = csub(v0, v2), s1 = cadd(v1, v3), d1 = csub(v1, v3);
       const int idx = ((j >> lg) << (lg + 2)) + k;
-      double2* o = buf[rr][src ^ 1];
+      if constexpr (!PP) __syncthreads();   // every thread has read the pass's inputs
+      if constexpr (PP) src ^= 1;
+      double2* o = buf[rr][src];
       o[idx] = cadd(s0, s1);
       o[idx + Ns] = make_double2(d0.x + d1.y, d0.y - d1.x);       // d0 - i d1
       o[idx + 2 * Ns] = csub(s0, s1);
       o[idx + 3 * Ns] = make_double2(d0.x - d1.y, d0.y + d1.x);   // d0 + i d1
-      src ^= 1;
       __syncthreads();
     }
     // the real transform Y_k for k = 4j .. 4j+3, and the prefix sum of Re Y
@@ -442,8 +457,9 @@ __global__ __launch_bounds__(DstShape<N2>::NT) void k_dst_rows(
       for (int q2 = 0; q2 < wv; ++q2) carry += wt[rr][q2];
     }
     const double off = carry + x - v[3];
-    // S in natural order (m - 1) in the free buffer, then coalesced stores
-    double* ob = reinterpret_cast<double*>(buf[rr][src ^ 1]);
+    __syncthreads();   // the spectrum is read
+    // S in natural order (m - 1), then coalesced stores
+    double* ob = reinterpret_cast<double*>(buf[rr][src]);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int k = 4 * j + e;
