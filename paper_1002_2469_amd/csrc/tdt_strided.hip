@@ -332,16 +332,18 @@ hipError_t launch_strided(const StridedArgs& a, hipStream_t st) {
   if ((int64_t)(5 * kStrB) * a.ld * 8 + 64 * 8 >= ((int64_t)1 << 31) ||
       (int64_t)(kEpiN + 2 * kStrMaxChunks + kStrB) * a.P * 8 >= ((int64_t)1 << 31))
     return hipErrorInvalidValue;
-  // As many adjacent systems per workgroup as 1024 lanes allow: the
-  // contiguous run of a row (8 SW bytes) sets the achieved bandwidth here
-  // (a copy with this access pattern and no arithmetic runs no faster).
+  // 16 adjacent systems (128 contiguous bytes of a row) per workgroup once
+  // the column needs 16 or more blocks: on rows that start on a cache line
+  // this measured faster than 32 or 64 (ADI of the 511^3 Poisson problem:
+  // 15.6 ms with 16, 16.9 ms with 32), while rows that do not start on one
+  // favour the wider runs (22.7 ms with 16, 20.6 ms with 32).
   const int C = a.C;
   if (C <= 1) return go<1, 256>(a, st);
   if (C <= 2) return go<2, 128>(a, st);
   if (C <= 4) return go<4, 64>(a, st);
-  if (C <= 8) return go<8, 64>(a, st);
-  if (C <= 16) return go<16, 64>(a, st);
-  if (C <= 32) return go<32, 32>(a, st);
+  if (C <= 8) return go<8, 32>(a, st);
+  if (C <= 16) return go<16, 16>(a, st);
+  if (C <= 32) return go<32, 16>(a, st);
   return go<64, 16>(a, st);
 }
 
