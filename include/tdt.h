@@ -213,9 +213,10 @@ tdt_status_t tdt_poisson2d_destroy(tdt_poisson_t p);
  * most eps (plus rounding).  J_k falls as k grows.  1 <= Ny, Nz <= 1024,
  * 640 Nx Ny < 2^31 (31-bit byte offsets of the z lines), 0 < eps < 1.  The handle
  * owns the per-iteration tables (~(38 + 4 ceil(N/16)) doubles per mode and
- * iteration) and Nx Ny Nz doubles of workspace when Nx+1 is a power of two
- * from 128 to 8192 (the fused row transform), else the FFT plan and
- * (2 Nx + 3) Ny Nz doubles (allocated here, blocking).  Errors: bad sizes, spacings or eps ->
+ * iteration) and 2 (16 ceil(Nx/16) + 16) Ny Nz doubles of workspace when
+ * Nx+1 is a power of two from 128 to 8192 (the fused row transform; rows
+ * padded to cache lines), else the FFT plan and (2 Nx + 3) Ny Nz doubles
+ * (allocated here, blocking).  Errors: bad sizes, spacings or eps ->
  * TDT_ERR_INVALID_ARG; allocation -> TDT_ERR_OOM; FFT plan -> TDT_ERR_HIP. */
 typedef struct tdt_poisson3d_s *tdt_poisson3d_t;
 tdt_status_t tdt_poisson3d_create(int64_t nx, int64_t ny, int64_t nz, double hx, double hy,
