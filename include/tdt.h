@@ -211,7 +211,8 @@ tdt_status_t tdt_poisson2d_destroy(tdt_poisson_t p);
  * full cycle, d_J^2 with d_J = prod_j (w_j - a)/(w_j + a), is <= eps, so the
  * 2-norm error of the result relative to the exact discrete solution is at
  * most eps (plus rounding).  J_k falls as k grows.  1 <= Ny, Nz <= 1024,
- * 640 Nx Ny < 2^31 (31-bit byte offsets of the z lines), 0 < eps < 1.  The handle
+ * 640 Nxp Ny < 2^31 with Nxp = 16 ceil(Nx/16) + 16 on the fused path, Nx otherwise
+ * (31-bit byte offsets of the z lines), 0 < eps < 1.  The handle
  * owns the per-iteration tables (~(38 + 4 ceil(N/16)) doubles per mode and
  * iteration) and 2 (16 ceil(Nx/16) + 16) Ny Nz doubles of workspace when
  * Nx+1 is a power of two from 128 to 8192 (the fused row transform; rows

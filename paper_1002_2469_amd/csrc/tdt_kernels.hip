@@ -2012,7 +2012,18 @@ __global__ __launch_bounds__(SH::NT, SH::WAVES) void k_gtile(GenArgs<Tio, Tc> A)
   const int tid = threadIdx.x;
   const SysDesc S = load_sys(A.sys, 0);
   const int nt = S.ntiles;
-  auto item_of = [&](int64_t k) { return A.reverse ? A.nitems - 1 - k : k; };
+  // Workgroup b runs on XCD b % 8 (the hardware deals workgroups out round
+  // robin), and an XCD's L2 serves only its own compute units: in every full
+  // round of gridDim.x items the workgroups of one XCD take a contiguous run
+  // of items, so that the groups of one tile, which share its constants,
+  // mostly meet in one L2 instead of fetching the constants once per XCD.
+  const int64_t cap = gridDim.x;
+  auto item_of = [&](int64_t k) {
+    const int64_t rd = k / cap, b = k - rd * cap;
+    int64_t l = k;
+    if ((cap & 7) == 0 && (rd + 1) * cap <= A.nitems) l = rd * cap + (b & 7) * (cap >> 3) + (b >> 3);
+    return A.reverse ? A.nitems - 1 - l : l;
+  };
   // item it: tile t, right-hand sides g R .. min(g R + R, M) - 1
   auto tile_of = [&](int64_t it) { return (int)(it / A.G); };
   auto first_of = [&](int64_t it) { return (it - (int64_t)tile_of(it) * A.G) * A.R; };
