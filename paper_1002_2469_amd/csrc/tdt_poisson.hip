@@ -287,7 +287,11 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 
 template <int N2>
 struct DstShape {
-  static constexpr int TR = N2 / 4;                      // threads per row
+  // complex values per thread: 4 (one radix-4 butterfly per pass), 8 for
+  // the 4096-point rows, whose 512 threads then fit two rows per compute
+  // unit in one LDS buffer each
+  static constexpr int E = N2 >= 4096 ? 8 : 4;
+  static constexpr int TR = N2 / E;                      // threads per row
   static constexpr int RW = TR >= 256 ? 1 : 256 / TR;    // rows per workgroup
   static constexpr int NT = TR * RW;
   static constexpr int NWR = TR >= 64 ? TR / 64 : 1;     // wavefronts per row
@@ -317,20 +321,22 @@ __global__ __launch_bounds__(DstShape<N2>::NT, N2 == 256 ? 5 : 4) void k_dst_row
     int64_t ldo, double scale, const double* __restrict__ sn, const double2* __restrict__ tw,
     const double2* __restrict__ pw) {
   using S = DstShape<N2>;
-  constexpr int TR = S::TR, RW = S::RW, n = 2 * N2, nx = n - 1;
-  // One buffer per row up to N2 = 2048: the row, then the transform, every
-  // pass reading its four values into registers before any thread writes
-  // (two barriers per pass), which halves the LDS of ping-pong buffers and
-  // fits more workgroups on a compute unit.  At N2 = 4096 (1024 threads per
-  // row) the barriers cost more than the second workgroup gains: ping-pong.
-  constexpr bool PP = N2 >= 4096;
-  __shared__ double2 buf[RW][PP ? 2 : 1][N2];
+  constexpr int E = S::E, TR = S::TR, RW = S::RW, n = 2 * N2, nx = n - 1;
+  constexpr int Q = E / 4;   // radix-4 butterflies per thread and pass
+  // One LDS buffer per row: the row, then the transform, every pass reading
+  // its inputs into registers before any thread writes (two barriers per
+  // pass) -- half the LDS of ping-pong buffers, so more rows per compute
+  // unit overlap their loads, arithmetic and stores.
+  __shared__ double2 buf[RW][N2];
   __shared__ double wt[RW][S::NWR];
-  const int t = threadIdx.x, rr = t / TR, j = t % TR;
+  const int t = threadIdx.x, rr = t / TR;
   // the rows of a wavefront: its first row's base, the lane's row offset
   const int rr0 = (t & ~63) / TR;
   const uint32_t lri = (uint32_t)((rr - rr0) * ldi) * 8u, lro = (uint32_t)((rr - rr0) * ldo) * 8u;
   const __amdgpu_buffer_rsrc_t tsn = row_rsrc(sn, (uint32_t)n * 8u);
+  constexpr int L2 = __builtin_ctz(N2), ODD = L2 & 1, NP = L2 / 2;
+  constexpr int NS0 = ODD ? 2 : 4;   // Ns of the first pass taken from LDS
+  constexpr int NPL = NP - (ODD ? 0 : 1);
   for (int64_t r0 = (int64_t)blockIdx.x * RW; r0 < rows; r0 += (int64_t)gridDim.x * RW) {
     const int64_t r = r0 + rr;
     const bool live = r < rows;
@@ -343,36 +349,42 @@ __global__ __launch_bounds__(DstShape<N2>::NT, N2 == 256 ? 5 : 4) void k_dst_row
       return b < ((int64_t)1 << 31) ? (uint32_t)b : 0x7fffffffu;
     };
     const __amdgpu_buffer_rsrc_t rin = row_rsrc(in + (rw0 < rows ? rw0 : 0) * ldi, avail(ldi));
-    double* fl = reinterpret_cast<double*>(buf[rr][0]);
-    // one twiddle per pass (W^q; W^2q and W^3q follow from it), each loaded
-    // one pass ahead, the first and the real split's with the row
-    constexpr int L2 = __builtin_ctz(N2), ODD = L2 & 1, NP = L2 / 2;
-    constexpr int NS0 = ODD ? 2 : 4;   // Ns of the first pass taken from LDS
-    constexpr int NPL = NP - (ODD ? 0 : 1);
-    auto twq = [&](int ps) {
+    double* fl = reinterpret_cast<double*>(buf[rr]);
+    // the lane's index, opaque to the compiler, for the table loads: their
+    // values repeat from row to row, and held across rows they would take
+    // more registers than reloading them (from cache) costs
+    int jt = t % TR;
+    asm volatile("" : "+v"(jt));
+    const int j = jt;
+    __builtin_assume(j >= 0 && j < TR);
+    // one twiddle per butterfly and pass (W^q; W^2q and W^3q follow from
+    // it), loaded one pass ahead, the first and the real split's with the row
+    auto twq = [&](int ps, int q) {
       const int lg = __builtin_ctz(NS0) + 2 * ps;   // Ns = NS0 4^ps
-      return tw[(j & ((1 << lg) - 1)) << (L2 - 2 - lg)];
+      return tw[((jt + TR * q) & ((1 << lg) - 1)) << (L2 - 2 - lg)];
     };
-    double2 wcur = twq(0);
-    const double2 pw0 = pw[4 * j];
-    // the fold's sines, with the row too
-    double sv[4][2];
+    double2 wcur[Q];
 #pragma unroll
-    for (int e = 0; e < 4; ++e)
+    for (int q = 0; q < Q; ++q) wcur[q] = twq(0, q);
+    const double2 pw0 = pw[E * jt];
+    // the fold's sines, with the row too
+    double sv[E][2];
+#pragma unroll
+    for (int e = 0; e < E; ++e)
 #pragma unroll
       for (int h = 0; h < 2; ++h)
-        sv[e][h] = bload(tsn, (uint32_t)(2 * j) * 8u, (uint32_t)(2 * TR * e + h) * 8u);
+        sv[e][h] = bload(tsn, (uint32_t)(2 * jt) * 8u, (uint32_t)(2 * TR * e + h) * 8u);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < 2 * E; ++i) {
       const int m = j + TR * i;
       const double v = bload(rin, lri + (uint32_t)j * 8u, (uint32_t)(TR * i) * 8u);
       if (m < nx) fl[m] = v;
     }
     __syncthreads();
     // fold, packed in pairs: z_k = y_2k + i y_2k+1 for k = j + TR e
-    double2 z[4];
+    double2 z[E];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < E; ++e) {
       const int k = j + TR * e;
       double y2[2];
 #pragma unroll
@@ -385,66 +397,86 @@ __global__ __launch_bounds__(DstShape<N2>::NT, N2 == 256 ? 5 : 4) void k_dst_row
     }
     __syncthreads();   // the row is read
     // complex FFT of length N2, Stockham autosort; its first pass works on
-    // the thread's own z (the inputs of butterfly j are z_{j + r TR})
-    int src = PP ? 1 : 0;
-    if constexpr (ODD) {   // radix 2, Ns = 1: butterflies j and j + TR
+    // the thread's own z (butterfly b = j + TR q takes z_{b + r N2/R})
+    if constexpr (ODD) {   // radix 2, Ns = 1
 #pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        const int jb = j + TR * e;
-        buf[rr][src][2 * jb] = cadd(z[e], z[e + 2]);
-        buf[rr][src][2 * jb + 1] = csub(z[e], z[e + 2]);
+      for (int q = 0; q < E / 2; ++q) {
+        const int b = j + TR * q;
+        buf[rr][2 * b] = cadd(z[q], z[q + E / 2]);
+        buf[rr][2 * b + 1] = csub(z[q], z[q + E / 2]);
       }
     } else {               // radix 4, Ns = 1 (no twiddles)
-      const double2 s0 = cadd(z[0], z[2]), d0 = csub(z[0], z[2]);
-      const double2 s1 = cadd(z[1], z[3]), d1 = csub(z[1], z[3]);
-      buf[rr][src][4 * j] = cadd(s0, s1);
-      buf[rr][src][4 * j + 1] = make_double2(d0.x + d1.y, d0.y - d1.x);
-      buf[rr][src][4 * j + 2] = csub(s0, s1);
-      buf[rr][src][4 * j + 3] = make_double2(d0.x - d1.y, d0.y + d1.x);
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int b = j + TR * q;
+        const double2 s0 = cadd(z[q], z[q + 2 * Q]), d0 = csub(z[q], z[q + 2 * Q]);
+        const double2 s1 = cadd(z[q + Q], z[q + 3 * Q]), d1 = csub(z[q + Q], z[q + 3 * Q]);
+        buf[rr][4 * b] = cadd(s0, s1);
+        buf[rr][4 * b + 1] = make_double2(d0.x + d1.y, d0.y - d1.x);
+        buf[rr][4 * b + 2] = csub(s0, s1);
+        buf[rr][4 * b + 3] = make_double2(d0.x - d1.y, d0.y + d1.x);
+      }
     }
     __syncthreads();
     int Ns = NS0;
 #pragma unroll 1
     for (int ps = 0; ps < NPL; ++ps, Ns *= 4) {
       const int lg = __builtin_ctz(NS0) + 2 * ps;
-      const int k = j & (Ns - 1);
-      const double2 wnext = twq(ps + 1 < NPL ? ps + 1 : ps);
-      double2 v0 = buf[rr][src][j], v1 = buf[rr][src][j + TR];
-      double2 v2 = buf[rr][src][j + 2 * TR], v3 = buf[rr][src][j + 3 * TR];
-      const double2 w1 = wcur, w2 = cmul(w1, w1), w3 = cmul(w2, w1);
-      wcur = wnext;
-      v1 = cmul(v1, w1);
-      v2 = cmul(v2, w2);
-      v3 = cmul(v3, w3);
-      const double2 s0 = cadd(v0, v2), d0 = csub(v0, v2), s1 = cadd(v1, v3), d1 = csub(v1, v3);
-      const int idx = ((j >> lg) << (lg + 2)) + k;
-      if constexpr (!PP) __syncthreads();   // every thread has read the pass's inputs
-      if constexpr (PP) src ^= 1;
-      double2* o = buf[rr][src];
-      o[idx] = cadd(s0, s1);
-      o[idx + Ns] = make_double2(d0.x + d1.y, d0.y - d1.x);       // d0 - i d1
-      o[idx + 2 * Ns] = csub(s0, s1);
-      o[idx + 3 * Ns] = make_double2(d0.x - d1.y, d0.y + d1.x);   // d0 + i d1
+      double2 X[Q][4];
+      int idx[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int b = j + TR * q;
+        const int k = b & (Ns - 1);
+        const double2 wnext = twq(ps + 1 < NPL ? ps + 1 : ps, q);
+        double2 v0 = buf[rr][b], v1 = buf[rr][b + N2 / 4];
+        double2 v2 = buf[rr][b + N2 / 2], v3 = buf[rr][b + 3 * (N2 / 4)];
+        const double2 w1 = wcur[q], w2 = cmul(w1, w1), w3 = cmul(w2, w1);
+        wcur[q] = wnext;
+        v1 = cmul(v1, w1);
+        v2 = cmul(v2, w2);
+        v3 = cmul(v3, w3);
+        const double2 s0 = cadd(v0, v2), d0 = csub(v0, v2), s1 = cadd(v1, v3), d1 = csub(v1, v3);
+        X[q][0] = cadd(s0, s1);
+        X[q][1] = make_double2(d0.x + d1.y, d0.y - d1.x);       // d0 - i d1
+        X[q][2] = csub(s0, s1);
+        X[q][3] = make_double2(d0.x - d1.y, d0.y + d1.x);       // d0 + i d1
+        idx[q] = ((b >> lg) << (lg + 2)) + k;
+      }
+      __syncthreads();   // every thread has read the pass's inputs
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int rj = 0; rj < 4; ++rj) buf[rr][idx[q] + rj * Ns] = X[q][rj];
       __syncthreads();
     }
-    // the real transform Y_k for k = 4j .. 4j+3, and the prefix sum of Re Y
-    const double2* Z = buf[rr][src];
-    double v[4], im[4];
+    // the real transform Y_k for k = E j .. E j + E - 1, and the prefix sum of Re Y
+    const double2* Z = buf[rr];
+    double v[E], im[E];
     double2 pwk = pw0;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int k = 4 * j + e;
+    for (int e = 0; e < E; ++e) {
+      const int k = E * j + e;
       const double2 zk = Z[k], zm = Z[(N2 - k) & (N2 - 1)];
-      const double2 E = make_double2(0.5 * (zk.x + zm.x), 0.5 * (zk.y - zm.y));
+      const double2 Ev = make_double2(0.5 * (zk.x + zm.x), 0.5 * (zk.y - zm.y));
       const double2 O = make_double2(0.5 * (zk.y + zm.y), -0.5 * (zk.x - zm.x));
-      const double2 Y = cadd(E, cmul(pwk, O));
+      const double2 Y = cadd(Ev, cmul(pwk, O));
       v[e] = k == 0 ? 0.5 * Y.x : Y.x;
       im[e] = Y.y;
       pwk = cmul(pwk, pw[1]);   // e^{-2 pi i (k + 1) / n}
     }
+    __syncthreads();   // the spectrum is read
+    // S in natural order (m - 1) in LDS: the odd terms now, the even ones
+    // after the scan, then coalesced stores
+    double* ob = reinterpret_cast<double*>(buf[rr]);
 #pragma unroll
-    for (int e = 1; e < 4; ++e) v[e] += v[e - 1];
-    double x = v[3];
+    for (int e = 0; e < E; ++e) {
+      const int k = E * j + e;
+      if (k >= 1) ob[2 * k - 1] = -im[e];
+    }
+#pragma unroll
+    for (int e = 1; e < E; ++e) v[e] += v[e - 1];
+    double x = v[E - 1];
     constexpr int W = TR < 64 ? TR : 64;
     const int lw = t % W;
 #pragma unroll
@@ -459,26 +491,22 @@ __global__ __launch_bounds__(DstShape<N2>::NT, N2 == 256 ? 5 : 4) void k_dst_row
       __syncthreads();
       for (int q2 = 0; q2 < wv; ++q2) carry += wt[rr][q2];
     }
-    const double off = carry + x - v[3];
-    __syncthreads();   // the spectrum is read
-    // S in natural order (m - 1), then coalesced stores
-    double* ob = reinterpret_cast<double*>(buf[rr][src]);
+    const double off = carry + x - v[E - 1];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int k = 4 * j + e;
+    for (int e = 0; e < E; ++e) {
+      const int k = E * j + e;
       if (2 * k + 1 <= nx) ob[2 * k] = off + v[e];
-      if (k >= 1) ob[2 * k - 1] = -im[e];
     }
     __syncthreads();
     const __amdgpu_buffer_rsrc_t rout =
         row_rsrc(out + (rw0 < rows ? rw0 : 0) * ldo, avail(ldo));
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < 2 * E; ++i) {
       const int m = j + TR * i;
       if (m < nx && live)
         bstore(rout, lro + (uint32_t)j * 8u, (uint32_t)(TR * i) * 8u, scale * ob[m]);
     }
-    __syncthreads();   // the buffers are rewritten by the next rows
+    __syncthreads();   // the buffer is rewritten by the next rows
   }
 }
 
