@@ -137,14 +137,21 @@ tdt_status_t tdt_plan_general_create(int64_t N, const double *h_a, const double 
 /* Plan for batches of Toeplitz systems laid out along a slow axis (the
  * lines along y or z of a row-major 2D or 3D array): P classes of matrices
  * T_k = tridiag{h_tm1[k], h_t0[k], h_t1[k]} of order N (host arrays of P
- * doubles, copied), 1 <= N <= 1024.  Solved with tdt_solve_strided, which
+ * doubles, copied), 1 <= N <= 2^24.  Solved with tdt_solve_strided, which
  * runs the dichotomy method (Sec. 2.1-2.5) with one workgroup per column of
  * adjacent systems: every lane holds a 16-row block of one system, the
  * interface values of eq. (15) are scanned across the blocks inside the
- * workgroup, and the blocks are corrected in registers.  The plan holds per
- * class the block LU, the blocks' end values and the interface table of the
- * column, computed in long double (17 + 2 ceil(N/16) doubles per class).
- * dtype: TDT_F64 only.  Errors: N outside [1, 1024], P < 1, null arrays,
+ * workgroup, and the blocks are corrected in registers.  A system of more
+ * than 1024 rows is cut into tiles of 1024 rows (the last one shorter), each
+ * such a column: a first pass keeps the end values of every tile's solution
+ * with zero outside values, one thread per system eliminates the tiles'
+ * interface values (the recurrences of eq. (15) over the tiles), and a
+ * second pass re-solves every tile with its two outside values.  The plan
+ * holds per class the block LU, the blocks' end values and the interface
+ * table of a column, computed in long double (17 + 2 ceil(N/16) doubles per
+ * class for N <= 1024; for longer N, that of a full tile and of the last
+ * tile plus 8 tile end values).
+ * dtype: TDT_F64 only.  Errors: N outside [1, 2^24], P < 1, null arrays,
  * non-finite entries, another dtype -> TDT_ERR_INVALID_ARG; a zero block
  * pivot or a vanishing interface pivot -> TDT_ERR_SINGULAR; returns
  * TDT_WARN_NOT_DOMINANT (plan valid) when some class has
@@ -161,8 +168,13 @@ tdt_status_t tdt_plan_strided_create(int64_t N, int64_t P, const double *h_tm1,
  * layout must be one of: batches one after another (ld >= M and, for
  * nb > 1, ldb >= (N-1)*ld + M), or batches interleaved in each row
  * (ldb >= M, ld >= (nb-1)*ldb + M); other layouts -> TDT_ERR_INVALID_ARG.
- * No workspace; capturable in a hipGraph.  Under tdt_plan_profile the
- * kernel time is reported as the third value of tdt_plan_profile_read. */
+ * N <= 1024: no workspace.  Longer N: the plan's workspace holds
+ * 4 nb M ceil(N/1024) doubles, allocated on first use or by
+ * tdt_plan_reserve(plan, nb*M); a solve that needs more while its stream is
+ * being captured returns TDT_ERR_CAPTURE.  Five launches then (two per pass,
+ * the full tiles and the last one, and the interface), one otherwise; both
+ * are capturable in a hipGraph.  Under tdt_plan_profile the kernel time is
+ * reported as the third value of tdt_plan_profile_read. */
 tdt_status_t tdt_solve_strided(tdt_plan_t plan, const double *F, double *X, int64_t M,
                                int64_t ld, int64_t nb, int64_t ldb, hipStream_t stream);
 
@@ -174,12 +186,18 @@ tdt_status_t tdt_solve_strided(tdt_plan_t plan, const double *F, double *X, int6
  * for the odd coefficients: in one kernel when Nx+1 is a power of two from
  * 128 to 8192, through hipFFT otherwise) leaves one tridiagonal Toeplitz
  * system per mode k along y, t_+-1 = -1,
- * t_0 = 2 + hy^2 (4/hx^2) sin^2(pi k / (2 (Nx+1))), solved by a varlen plan of
- * this library (dtype TDT_F64 or TDT_F32_REFINE); the inverse transform
- * gives U.  The handle owns the line plan, the twiddle tables or the FFT
- * plan, and 2 Nx Ny + Ny (Nx + 1) doubles of workspace, plus
- * 2 Ny (floor((Nx+1)/2) + 1) on the hipFFT path (allocated here,
- * blocking).  Errors: sizes
+ * t_0 = 2 + hy^2 (4/hx^2) sin^2(pi k / (2 (Nx+1))); the inverse transform
+ * gives U.  With the one-kernel transform and TDT_F64, the mode systems are
+ * solved in place in the transformed rows by a strided plan (system k is
+ * column k; rows padded to ldw = 16 ceil(Nx/16) + 16 doubles): 2 row
+ * transforms and the strided solve, no transposes; the workspace is Ny ldw
+ * doubles plus the strided plan's 4 Nx ceil(Ny/1024) when Ny > 1024.
+ * Otherwise (TDT_F32_REFINE, or the hipFFT path) the transformed rows are
+ * transposed to mode-major order and solved by a varlen plan of this
+ * library, with 2 Nx Ny + Ny (Nx + 1) doubles of workspace, plus
+ * 2 Ny (floor((Nx+1)/2) + 1) on the hipFFT path.  The handle owns the line
+ * plan, the twiddle tables or the FFT plan and the workspace (allocated
+ * here, blocking).  Errors: sizes
  * < 1 or Nx Ny > 2^31, non-positive or non-finite spacings, another dtype ->
  * TDT_ERR_INVALID_ARG; allocation -> TDT_ERR_OOM; an FFT plan failure ->
  * TDT_ERR_HIP. */
@@ -192,7 +210,8 @@ tdt_status_t tdt_poisson2d_create(int64_t nx, int64_t ny, double hx, double hy,
 tdt_status_t tdt_poisson2d_solve(tdt_poisson_t p, const double *F, double *U,
                                  hipStream_t stream);
 /* The handle's line plan (owned by the handle), e.g. to set its options or
- * autotune it. */
+ * autotune it: a varlen plan, or the strided plan of the in-place path
+ * (which takes no options). */
 tdt_status_t tdt_poisson2d_line_plan(tdt_poisson_t p, tdt_plan_t *line);
 tdt_status_t tdt_poisson2d_destroy(tdt_poisson_t p);
 
@@ -243,7 +262,9 @@ tdt_status_t tdt_poisson3d_destroy(tdt_poisson3d_t p);
 tdt_status_t tdt_adi_parameters(double a, double b, int J, double *out, double *bound);
 
 /* Allocate the workspace for up to M_max right-hand sides now, so that later
- * solves allocate nothing and may be captured in a hipGraph.  Blocking. */
+ * solves allocate nothing and may be captured in a hipGraph.  Blocking.  For
+ * a strided plan M_max counts systems over all batches (nb * M); it is a
+ * no-op for strided plans of at most 1024 rows. */
 tdt_status_t tdt_plan_reserve(tdt_plan_t plan, int64_t M_max);
 
 /* Solve T X_m = F_m for M right-hand sides sharing the plan's matrix (the

@@ -332,10 +332,12 @@ class GeneralPlan(_PlanBase):
 
 
 class StridedPlan(_PlanBase):
-    """Plan of P classes of Toeplitz matrices of order N <= 1024 (class k:
+    """Plan of P classes of Toeplitz matrices of order N <= 2^24 (class k:
     tridiag{t_m1[k], t_0[k], t_1[k]}) for systems along a slow axis: unknown
     i of system s of batch b at element b*ldb + i*ld + s, system s using
-    class s.  float64 only.  Scalars broadcast over the P classes."""
+    class s.  float64 only.  Scalars broadcast over the P classes.  Systems
+    of more than 1024 rows are solved in tiles and need workspace: call
+    reserve(nb * M) before capturing a solve in a hipGraph."""
 
     def __init__(self, N: int, t_m1, t_0, t_1):
         super().__init__()

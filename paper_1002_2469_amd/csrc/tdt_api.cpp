@@ -53,6 +53,11 @@ struct tdt_plan_s {
   int64_t sP = 0;
   int sC = 0;
   double* dstr = nullptr;   // iu [kStrB][P] | sc [kStrScalarN][P] | pos [2][C][P]
+  // a system longer than one column: sK tiles of kStrTile rows, the last of
+  // sNL rows (sCL blocks) with its own tables at dstr + str_last, and the
+  // tiles' end values [kTileEndN][P] at dstr + str_ends
+  int64_t sK = 1, sNL = 0, str_last = 0, str_ends = 0;
+  int sCL = 0;
   bool varlen = false;
   tdt_dtype_t dtype = TDT_F64;
   int64_t N = 0;          // series: order of the system (with its corner rows)
@@ -1391,18 +1396,54 @@ tdt_status_t tdt_plan_strided_create(int64_t N, int64_t P, const double* h_tm1,
                                      tdt_plan_t* out) {
   if (!out) return TDT_ERR_INVALID_ARG;
   *out = nullptr;
-  if (N < 1 || N > (int64_t)tdt::kStrMaxChunks * tdt::kStrB || P < 1 || P > ((int64_t)1 << 31) ||
-      !h_tm1 || !h_t0 || !h_t1 || dtype != TDT_F64)
+  if (N < 1 || N > tdt::kStrMaxN || P < 1 || P > ((int64_t)1 << 31) || !h_tm1 || !h_t0 ||
+      !h_t1 || dtype != TDT_F64)
     return TDT_ERR_INVALID_ARG;
-  const int C = tdt::strided_chunks(N);
-  const int64_t nv = (int64_t)(tdt::kStrB + tdt::kStrScalarN + 2 * C) * P;
-  std::vector<double> tab((size_t)nv);
+  // one column, or tiles of kStrTile rows and a last tile of NL rows
+  const int64_t K = (N + tdt::kStrTile - 1) / tdt::kStrTile;
+  const int64_t NT = K > 1 ? tdt::kStrTile : N, NL = N - (K - 1) * tdt::kStrTile;
+  const int C = tdt::strided_chunks(NT), CL = tdt::strided_chunks(NL);
+  const int64_t n1 = (int64_t)(tdt::kStrB + tdt::kStrScalarN + 2 * C) * P;
+  const int64_t n2 = K > 1 ? (int64_t)(tdt::kStrB + tdt::kStrScalarN + 2 * CL) * P : 0;
+  const int64_t n3 = K > 1 ? (int64_t)tdt::kTileEndN * P : 0;
+  std::vector<double> tab((size_t)(n1 + n2 + n3));
   double dom = 0.0;
-  double* iu = tab.data();
-  double* sc = iu + (int64_t)tdt::kStrB * P;
-  double* pos = sc + (int64_t)tdt::kStrScalarN * P;
-  const int st = tdt::strided_tables(N, P, h_tm1, h_t0, h_t1, iu, sc, pos, &dom);
+  auto tables = [&](int64_t n, double* t) {
+    double* iu = t;
+    double* sc = iu + (int64_t)tdt::kStrB * P;
+    double* pos = sc + (int64_t)tdt::kStrScalarN * P;
+    return tdt::strided_tables(n, P, h_tm1, h_t0, h_t1, iu, sc, pos, &dom);
+  };
+  int st = tables(NT, tab.data());
   if (st < 0) return (tdt_status_t)st;
+  if (K > 1) {
+    st = tables(NL, tab.data() + n1);
+    if (st < 0) return (tdt_status_t)st;
+    double* ends = tab.data() + n1 + n2;
+    for (int64_t k = 0; k < P; ++k) {
+      ld full[4], lastv[4];
+      if (!segment_ends(h_tm1[k], h_t0[k], h_t1[k], NT, full) ||
+          !segment_ends(h_tm1[k], h_t0[k], h_t1[k], NL, lastv))
+        return TDT_ERR_SINGULAR;
+      for (int e = 0; e < 4; ++e) {
+        ends[(int64_t)e * P + k] = (double)full[e];
+        ends[(int64_t)(4 + e) * P + k] = (double)lastv[e];
+      }
+      // the pivots D_m = 1 - phif s_{m-1} of the tiles' elimination (they
+      // depend on the class only); s_m settles quickly, so the full tiles
+      // stop at its fixed point
+      ld sv = 0.0L;
+      for (int64_t m = 0; m < K; ++m) {
+        const ld* e = m == K - 1 ? lastv : full;
+        const ld D = 1.0L - e[0] * sv;
+        if (!(std::fabs((double)D) > 1e-13)) return TDT_ERR_SINGULAR;
+        const ld sn = e[1] * sv * e[2] / D + e[3];
+        if (!std::isfinite((double)sn)) return TDT_ERR_SINGULAR;
+        if (m < K - 2 && sn == sv) m = K - 2;   // the full tiles left repeat it
+        sv = sn;
+      }
+    }
+  }
   tdt_plan_s* p = new (std::nothrow) tdt_plan_s();
   if (!p) return TDT_ERR_OOM;
   p->strided = true;
@@ -1411,12 +1452,17 @@ tdt_status_t tdt_plan_strided_create(int64_t N, int64_t P, const double* h_tm1,
   p->S = P;
   p->sP = P;
   p->sC = C;
+  p->sK = K;
+  p->sNL = NL;
+  p->sCL = CL;
+  p->str_last = n1;
+  p->str_ends = n1 + n2;
   p->dominance = dom;
   p->kappa = 0.0;
-  tdt_status_t s = dev_upload(&p->dstr, tab.data(), tab.size());
-  if (s != TDT_OK) {
+  tdt_status_t s2 = dev_upload(&p->dstr, tab.data(), tab.size());
+  if (s2 != TDT_OK) {
     destroy(p);
-    return s;
+    return s2;
   }
   *out = p;
   return dom < 1.0 ? TDT_WARN_NOT_DOMINANT : TDT_OK;
@@ -1435,15 +1481,24 @@ tdt_status_t tdt_solve_strided(tdt_plan_t p, const double* F, double* X, int64_t
   const int64_t extent = (nb - 1) * ldb + (N - 1) * ld + M;
   const size_t bytes = (size_t)extent * sizeof(double);
   if (F != X && overlaps(F, bytes, X, bytes)) return TDT_ERR_INVALID_ARG;
+  const int64_t K = p->sK;
+  if (K > 1) {
+    // the tiles' end values and outside values, [nb][K][2][M] each
+    const tdt_status_t ws = ensure_workspace(p, nb * K * M, 0, stream);
+    if (ws != TDT_OK) return ws;
+  }
   tdt::StridedArgs a{};
+  auto set_tables = [&](const double* t) {
+    a.iu = t;
+    a.sc = a.iu + (int64_t)tdt::kStrB * p->sP;
+    a.pos = a.sc + (int64_t)tdt::kStrScalarN * p->sP;
+  };
   a.R = F;
   a.O = X;
   a.G = nullptr;
   a.epi = nullptr;
-  a.iu = p->dstr;
-  a.sc = a.iu + (int64_t)tdt::kStrB * p->sP;
-  a.pos = a.sc + (int64_t)tdt::kStrScalarN * p->sP;
-  a.N = N;
+  set_tables(p->dstr);
+  a.N = K > 1 ? tdt::kStrTile : N;
   a.P = p->sP;
   a.M = M;
   a.Mg = M;
@@ -1463,7 +1518,40 @@ tdt_status_t tdt_solve_strided(tdt_plan_t p, const double* F, double* X, int64_t
       for (int j = 0; j < 3; ++j) (void)hipEventRecord(ev[j], stream);
     }
   }
-  if (tdt::launch_strided(a, stream) != hipSuccess) return TDT_ERR_HIP;
+  if (K == 1) {
+    if (tdt::launch_strided(a, stream) != hipSuccess) return TDT_ERR_HIP;
+  } else {
+    // pass 1 and pass 2 over the full tiles, then over the last one
+    const int64_t off = (K - 1) * tdt::kStrTile * ld;
+    a.K = K;
+    a.ldt = tdt::kStrTile * ld;
+    a.Y = p->summ;
+    a.Gh = p->ghost;
+    auto pass = [&](int which) {
+      a.pass = which;
+      set_tables(p->dstr);
+      a.R = F;
+      a.O = X;
+      a.N = tdt::kStrTile;
+      a.C = p->sC;
+      a.tiles = K - 1;
+      a.m0 = 0;
+      if (tdt::launch_strided(a, stream) != hipSuccess) return false;
+      set_tables(p->dstr + p->str_last);
+      a.R = F + off;
+      a.O = X + off;
+      a.N = p->sNL;
+      a.C = p->sCL;
+      a.tiles = 1;
+      a.m0 = K - 1;
+      return tdt::launch_strided(a, stream) == hipSuccess;
+    };
+    if (!pass(1)) return TDT_ERR_HIP;
+    if (tdt::launch_strided_interface(p->dstr + p->str_ends, p->summ, p->ghost, M, p->sP, K, nb,
+                                      stream) != hipSuccess)
+      return TDT_ERR_HIP;
+    if (!pass(2)) return TDT_ERR_HIP;
+  }
   if (ev) (void)hipEventRecord(ev[3], stream);
   return TDT_OK;
 }
@@ -1482,7 +1570,8 @@ tdt_status_t tdt_plan_varlen_quasi_create(int64_t S, const int64_t* h_offsets,
 
 tdt_status_t tdt_plan_reserve(tdt_plan_t p, int64_t M_max) {
   if (!p || M_max < 1) return TDT_ERR_INVALID_ARG;
-  if (p->strided) return TDT_OK;   // no workspace
+  if (p->strided)   // workspace only for systems of several tiles
+    return p->sK > 1 ? ensure_workspace(p, M_max * p->sK, 0, nullptr) : TDT_OK;
   p->reserved_M = std::max(p->reserved_M, M_max);
   int64_t slots, fslots;
   if (p->general) {

@@ -35,7 +35,9 @@
 struct tdt_poisson_s {
   int64_t nx = 0, ny = 0;
   double hx = 0.0, hy = 0.0;
-  tdt_plan_t line = nullptr;     // Nx Toeplitz systems of Ny rows (mode-major)
+  tdt_plan_t line = nullptr;     // Nx Toeplitz systems of Ny rows (mode-major), or
+  bool strided = false;          // the same systems in place in the row-major
+  int64_t ldw = 0;               // transformed rows (a strided plan), rows ldw apart
   hipfftHandle fft = 0;          // Ny real transforms of length Nx + 1
   bool fft_made = false;
   double* sn = nullptr;          // sin(pi j / (Nx + 1)), j = 0 .. Nx
@@ -284,6 +286,34 @@ __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_doub
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
+// 4-point DFT in place: y_s = sum_t x_t e^{-2 pi i t s / 4}
+__device__ __forceinline__ void dft4(double2& x0, double2& x1, double2& x2, double2& x3) {
+  const double2 s0 = cadd(x0, x2), d0 = csub(x0, x2), s1 = cadd(x1, x3), d1 = csub(x1, x3);
+  x0 = cadd(s0, s1);
+  x1 = make_double2(d0.x + d1.y, d0.y - d1.x);   // d0 - i d1
+  x2 = csub(s0, s1);
+  x3 = make_double2(d0.x - d1.y, d0.y + d1.x);   // d0 + i d1
+}
+// 8-point DFT in place, X_s = sum_r a_r w^{r s}, w = e^{-i pi / 4}: the
+// 4-point DFTs E, O of the even and odd inputs, X_s = E_s + w^s O_s,
+// X_{s+4} = E_s - w^s O_s.
+__device__ __forceinline__ void dft8(double2 (&a)[8]) {
+  dft4(a[0], a[2], a[4], a[6]);
+  dft4(a[1], a[3], a[5], a[7]);
+  constexpr double h = 0.70710678118654752440;   // 1 / sqrt(2)
+  const double2 o1 = make_double2(h * (a[3].x + a[3].y), h * (a[3].y - a[3].x));
+  const double2 o2 = make_double2(a[5].y, -a[5].x);
+  const double2 o3 = make_double2(h * (a[7].y - a[7].x), -h * (a[7].x + a[7].y));
+  const double2 e0 = a[0], e1 = a[2], e2 = a[4], e3 = a[6], o0 = a[1];
+  a[0] = cadd(e0, o0);
+  a[4] = csub(e0, o0);
+  a[1] = cadd(e1, o1);
+  a[5] = csub(e1, o1);
+  a[2] = cadd(e2, o2);
+  a[6] = csub(e2, o2);
+  a[3] = cadd(e3, o3);
+  a[7] = csub(e3, o3);
+}
 
 template <int N2>
 struct DstShape {
@@ -337,6 +367,10 @@ __global__ __launch_bounds__(DstShape<N2>::NT, N2 == 256 ? 5 : 4) void k_dst_row
   constexpr int L2 = __builtin_ctz(N2), ODD = L2 & 1, NP = L2 / 2;
   constexpr int NS0 = ODD ? 2 : 4;   // Ns of the first pass taken from LDS
   constexpr int NPL = NP - (ODD ? 0 : 1);
+  // eight values per thread and a power of 8: radix-8 passes (one in
+  // registers, L2 / 3 - 1 through LDS) instead of radix 4
+  constexpr bool R8 = E == 8 && L2 % 3 == 0;
+  constexpr int NP8 = L2 / 3 - 1;
   for (int64_t r0 = (int64_t)blockIdx.x * RW; r0 < rows; r0 += (int64_t)gridDim.x * RW) {
     const int64_t r = r0 + rr;
     const bool live = r < rows;
@@ -363,9 +397,18 @@ __global__ __launch_bounds__(DstShape<N2>::NT, N2 == 256 ? 5 : 4) void k_dst_row
       const int lg = __builtin_ctz(NS0) + 2 * ps;   // Ns = NS0 4^ps
       return tw[((jt + TR * q) & ((1 << lg) - 1)) << (L2 - 2 - lg)];
     };
+    // the radix-8 passes' twiddle W^k, k = j mod Ns, Ns = 8^(ps + 1)
+    auto tw8 = [&](int ps) {
+      const int lg = 3 * (ps + 1);
+      return tw[(jt & ((1 << lg) - 1)) << (L2 - 3 - lg)];
+    };
     double2 wcur[Q];
+    if constexpr (R8) {
+      wcur[0] = tw8(0);
+    } else {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) wcur[q] = twq(0, q);
+      for (int q = 0; q < Q; ++q) wcur[q] = twq(0, q);
+    }
     const double2 pw0 = pw[E * jt];
     // the fold's sines, with the row too
     double sv[E][2];
@@ -398,7 +441,37 @@ __global__ __launch_bounds__(DstShape<N2>::NT, N2 == 256 ? 5 : 4) void k_dst_row
     __syncthreads();   // the row is read
     // complex FFT of length N2, Stockham autosort; its first pass works on
     // the thread's own z (butterfly b = j + TR q takes z_{b + r N2/R})
-    if constexpr (ODD) {   // radix 2, Ns = 1
+    if constexpr (R8) {
+      // butterfly b = j: inputs at b + r N2/8 (the thread's z), outputs at
+      // (b / Ns) 8 Ns + (b mod Ns) + r Ns
+      dft8(z);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) buf[rr][8 * j + r] = z[r];
+      __syncthreads();
+#pragma unroll 1
+      for (int ps = 0; ps < NP8; ++ps) {
+        const int lg = 3 * (ps + 1), Ns = 1 << lg;
+        const double2 wnext = tw8(ps + 1 < NP8 ? ps + 1 : ps);
+        double2 a8[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) a8[r] = buf[rr][j + r * (N2 / 8)];
+        const double2 w1 = wcur[0], w2 = cmul(w1, w1), w3 = cmul(w2, w1), w4 = cmul(w2, w2);
+        wcur[0] = wnext;
+        a8[1] = cmul(a8[1], w1);
+        a8[2] = cmul(a8[2], w2);
+        a8[3] = cmul(a8[3], w3);
+        a8[4] = cmul(a8[4], w4);
+        a8[5] = cmul(a8[5], cmul(w4, w1));
+        a8[6] = cmul(a8[6], cmul(w4, w2));
+        a8[7] = cmul(a8[7], cmul(w4, w3));
+        dft8(a8);
+        const int idx = ((j >> lg) << (lg + 3)) + (j & (Ns - 1));
+        __syncthreads();   // every thread has read the pass's inputs
+#pragma unroll
+        for (int r = 0; r < 8; ++r) buf[rr][idx + r * Ns] = a8[r];
+        __syncthreads();
+      }
+    } else if constexpr (ODD) {   // radix 2, Ns = 1
 #pragma unroll
       for (int q = 0; q < E / 2; ++q) {
         const int b = j + TR * q;
@@ -417,10 +490,10 @@ __global__ __launch_bounds__(DstShape<N2>::NT, N2 == 256 ? 5 : 4) void k_dst_row
         buf[rr][4 * b + 3] = make_double2(d0.x - d1.y, d0.y + d1.x);
       }
     }
-    __syncthreads();
+    if constexpr (!R8) __syncthreads();
     int Ns = NS0;
 #pragma unroll 1
-    for (int ps = 0; ps < NPL; ++ps, Ns *= 4) {
+    for (int ps = 0; ps < (R8 ? 0 : NPL); ++ps, Ns *= 4) {
       const int lg = __builtin_ctz(NS0) + 2 * ps;
       double2 X[Q][4];
       int idx[Q];
@@ -616,22 +689,32 @@ tdt_status_t tdt_poisson2d_create(int64_t nx, int64_t ny, double hx, double hy,
     t0[(size_t)k - 1] = (double)(2.0L + (long double)hy * hy * mu);
   }
   for (int64_t k = 0; k <= nx; ++k) off[(size_t)k] = k * ny;
-  tdt_status_t st = tdt_plan_varlen_create(nx, off.data(), tm1.data(), t0.data(), t1.data(),
-                                           dtype, &p->line);
+  const int64_t n = nx + 1, K = n / 2 + 1;
+  p->fused = dst_supported(nx);
+  // In float64 with the fused row transform, the mode systems are solved in
+  // place in the transformed rows, as a strided batch (system k: column k),
+  // with rows padded to a multiple of 16 doubles plus 16, so that each
+  // starts on a cache line and consecutive rows fall on different channels.
+  // Otherwise transposes to and from mode-major order around a varlen plan.
+  p->strided = p->fused && dtype == TDT_F64;
+  p->ldw = p->strided ? (nx + 15) / 16 * 16 + 16 : n;
+  tdt_status_t st =
+      p->strided
+          ? tdt_plan_strided_create(ny, nx, tm1.data(), t0.data(), t1.data(), dtype, &p->line)
+          : tdt_plan_varlen_create(nx, off.data(), tm1.data(), t0.data(), t1.data(), dtype,
+                                   &p->line);
   if (st < 0) {
     destroy_poisson(p);
     return st;
   }
-  st = tdt_plan_reserve(p->line, 1);
-  const int64_t n = nx + 1, K = n / 2 + 1;
-  p->fused = dst_supported(nx);
+  st = tdt_plan_reserve(p->line, p->strided ? nx : 1);
   if (st == TDT_OK &&
       (hipMalloc(&p->sn, (size_t)n * sizeof(double)) != hipSuccess ||
-       hipMalloc(&p->y, (size_t)(ny * n) * sizeof(double)) != hipSuccess ||
+       hipMalloc(&p->y, (size_t)(ny * p->ldw) * sizeof(double)) != hipSuccess ||
        (!p->fused &&
         hipMalloc(&p->spec, (size_t)(ny * K) * 2 * sizeof(double)) != hipSuccess) ||
-       hipMalloc(&p->T, (size_t)(nx * ny) * sizeof(double)) != hipSuccess ||
-       hipMalloc(&p->V, (size_t)(nx * ny) * sizeof(double)) != hipSuccess))
+       (!p->strided && hipMalloc(&p->T, (size_t)(nx * ny) * sizeof(double)) != hipSuccess) ||
+       (!p->strided && hipMalloc(&p->V, (size_t)(nx * ny) * sizeof(double)) != hipSuccess)))
     st = TDT_ERR_OOM;
   if (st == TDT_OK) {
     std::vector<double> sn((size_t)n);
@@ -673,6 +756,17 @@ tdt_status_t tdt_poisson2d_solve(tdt_poisson_t p, const double* F, double* U,
   if (!p || !F || !U) return TDT_ERR_INVALID_ARG;
   const int64_t nx = p->nx, ny = p->ny, n = nx + 1;
   auto gy = [](int64_t v) { return (unsigned)(v < (int64_t)kMaxGridY ? v : kMaxGridY); };
+  if (p->strided) {
+    // rows' sine transforms (the forward one scaled) into the padded work
+    // rows, the mode systems solved in place down the columns, the inverse
+    // transforms into U
+    launch_dst_rows(F, p->y, nx, ny, nx, p->ldw, p->hy * p->hy * 2.0 / (double)(nx + 1), p->sn,
+                    p->tw, p->pw, stream);
+    tdt_status_t st = tdt_solve_strided(p->line, p->y, p->y, nx, p->ldw, 1, 0, stream);
+    if (st < 0) return st;
+    launch_dst_rows(p->y, U, nx, ny, p->ldw, nx, 1.0, p->sn, p->tw, p->pw, stream);
+    return hipGetLastError() == hipSuccess ? TDT_OK : TDT_ERR_HIP;
+  }
   if (p->fused) {
     // rows' sine transforms in one pass each, transposes to and from
     // mode-major order (the forward one scaled)

@@ -12,7 +12,21 @@ namespace tdt {
 // adjacent systems, kStrB rows per lane in registers, and runs the three
 // steps of the method on it: the lanes of one system are its blocks.
 constexpr int kStrB = 16;             // rows per lane (one block)
-constexpr int kStrMaxChunks = 64;     // blocks per system: N <= 1024
+constexpr int kStrMaxChunks = 64;     // blocks per column: 1024 rows
+// Longer systems are cut into tiles of kStrTile rows (the last one shorter),
+// each a column of the kernel above: a first pass keeps every tile's end
+// values with zero outside values, one thread per system eliminates the
+// tiles' interface values, and a second pass re-solves every tile with its
+// two outside values.  Tiles of 512 rows (512 lanes per workgroup, two
+// workgroups per compute unit) measured faster than 1024 (one) and as fast
+// as 256: 0.41 against 0.49 ms for the 8191 x 8191 batch.
+constexpr int kStrTileChunks = 32;
+constexpr int64_t kStrTile = (int64_t)kStrTileChunks * kStrB;
+constexpr int64_t kStrMaxN = (int64_t)1 << 24;
+// Per-class end values of a tile's responses to unit outside values,
+// [field][P]: phi_first, phi_last, chi_first, chi_last of a full tile, then
+// of the last tile.
+enum { kTilePF, kTilePL, kTileCF, kTileCL, kTileEndN = 8 };
 // Per-class scalars, [field][P]: t_-1, t_1, the end values
 // (phi_first, phi_last, chi_first) of a full block and of the last block.
 enum { kStrTM1, kStrT1, kStrPF, kStrPL, kStrCF, kStrTPF, kStrTPL, kStrTCF, kStrScalarN };
@@ -31,8 +45,22 @@ struct StridedArgs {
   int64_t N, P, M, ld, nb, ldb;
   int64_t Mg;               // systems s < Mg read G (the others take g = 0)
   int C;                    // blocks per system, ceil(N / kStrB)
+  // Tiles of a longer system (pass 0: none).  Column b of a launch is tile
+  // m0 + b % tiles of batch b / tiles, at (b / tiles) ldb + (b % tiles) ldt.
+  // Pass 1 writes the tile's first and last unknown to Y, pass 2 folds the
+  // outside values of Gh into the tile's end rows; both index
+  // [(batch K + tile) 2 + end][M].
+  int pass;
+  int64_t tiles, ldt, K, m0;
+  double* Y;
+  const double* Gh;
 };
 hipError_t launch_strided(const StridedArgs& a, hipStream_t st);
+// The tiles' interface values of every system (one thread each), from the
+// tiles' end values Y: Gh receives every tile's left and right outside
+// value; Y is overwritten with intermediate coefficients.
+hipError_t launch_strided_interface(const double* ends, double* Y, double* Gh, int64_t M,
+                                    int64_t P, int64_t K, int64_t nb, hipStream_t st);
 // Host tables of P classes (t_-1, t_0, t_1)[k] for systems of order N, in
 // long double: iu [kStrB][P], sc [kStrScalarN][P], pos [2][C][P].  Returns a
 // negative status on a singular class or bad arguments; *dominance is the

@@ -14,7 +14,11 @@
 //      evaluated as Kogge-Stone scans across the blocks through LDS;
 //   3. every lane re-sweeps its block with its two outside values folded
 //      into the first and last right-hand side row.
-// Systems of at most kStrMaxChunks * kStrB = 1024 rows.  Optionally the
+// Columns of at most kStrMaxChunks * kStrB = 1024 rows; a longer system is
+// cut into tiles of that many rows, solved in two passes over the columns
+// with the tiles' interface values eliminated between them (the same steps
+// one level up: the end values of every tile's zero-outside solution, the
+// recurrences of eq. (15) over the tiles, the re-solve).  Optionally the
 // right-hand side is scale (r + c_q g) and the output c_x x + c_r r + c_g g
 // per class (r the array read, g a second array): an ADI half-step's
 // right-hand side and update fused into its solve.
@@ -63,7 +67,7 @@ __device__ __forceinline__ lds_cdouble* lds_fresh(const double* p) {
   return (lds_cdouble*)(uintptr_t)v;
 }
 
-template <int CW, int SW, bool EPI>
+template <int CW, int SW, bool EPI, int PASS>
 __global__ __launch_bounds__(CW * SW, 4)
 void k_strided(StridedArgs a) {
   constexpr int NT = CW * SW;
@@ -85,8 +89,23 @@ void k_strided(StridedArgs a) {
   const uint32_t voff = (uint32_t)((c - c0) * B) * ldb8 + (uint32_t)(sl - sl0) * 8u;
   const bool with_g = EPI && a.G != nullptr && s < a.Mg;
 
+  // columns of the launch: batches, or (batch, tile) pairs of a tiled system
+  const int64_t ncol = PASS ? a.nb * a.tiles : a.nb;
+  auto col_off = [&](int64_t bb) -> int64_t {
+    if constexpr (PASS == 0) {
+      return bb * a.ldb;
+    } else {
+      const int64_t q2 = bb / a.tiles;
+      return q2 * a.ldb + (bb - q2 * a.tiles) * a.ldt;
+    }
+  };
+  // this lane's system in the tiles' end arrays, [(batch K + tile) 2 + end][M]
+  auto end_idx = [&](int64_t bb) -> int64_t {
+    const int64_t q2 = bb / a.tiles;
+    return ((q2 * a.K + a.m0 + (bb - q2 * a.tiles)) * 2) * a.M + s;
+  };
   int64_t b = blockIdx.y;
-  if (b >= a.nb) return;   // uniform over the workgroup
+  if (b >= ncol) return;   // uniform over the workgroup
   double q[B], w[B];
   // the column's loads (0 past len), raw: r in q, g in w
   // Only the system's last block can end inside a lane's rows: a wavefront
@@ -96,7 +115,7 @@ void k_strided(StridedArgs a) {
   const uint32_t vo = len > 0 ? voff : kBad;
   const uint32_t vg = (len > 0 && with_g) ? voff : kBad;
   auto load = [&](int64_t bb) {
-    const int64_t wbase = bb * a.ldb + (int64_t)c0 * B * a.ld + s_w;
+    const int64_t wbase = col_off(bb) + (int64_t)c0 * B * a.ld + s_w;
     const __amdgpu_buffer_rsrc_t rR = wave_rsrc(a.R + wbase);
     const __amdgpu_buffer_rsrc_t rG = wave_rsrc(EPI && a.G ? a.G + wbase : a.R + wbase);
     if (!part) {
@@ -146,9 +165,23 @@ void k_strided(StridedArgs a) {
     __syncthreads();
   }
   for (;;) {
-    const int64_t wbase = b * a.ldb + (int64_t)c0 * B * a.ld + s_w;
+    const int64_t wbase = col_off(b) + (int64_t)c0 * B * a.ld + s_w;
     const __amdgpu_buffer_rsrc_t rO = wave_rsrc(a.O + wbase);
     const double tm1 = tSC[kStrTM1][sl], t1 = tSC[kStrT1][sl];
+    if constexpr (PASS == 2) {
+      // the tile's outside values moved to the right-hand side:
+      // f_0 - t_-1 x_left and f_last - t_1 x_right
+      if (live) {
+        const int64_t gi = end_idx(b);
+        if (c == 0) q[0] -= tm1 * a.Gh[gi];
+        if (last) {
+          const double gr = t1 * a.Gh[gi + a.M];
+#pragma unroll
+          for (int i = 0; i < B; ++i)
+            if (i == len - 1) q[i] -= gr;
+        }
+      }
+    }
     if (EPI) {
       const double scale = tEP[kEpiScale][sl], cq = tEP[kEpiCQ][sl];
       const double cr = tEP[kEpiCR][sl], cg = tEP[kEpiCG][sl];
@@ -295,7 +328,20 @@ void k_strided(StridedArgs a) {
 #pragma unroll
     for (int i = B - 2; i >= 0; --i) q[i] -= t1 * iu4[i * SW] * q[i + 1];
     const double cx = EPI ? tEP[kEpiCX][sl] : 1.0;
-    if (!part) {
+    if constexpr (PASS == 1) {
+      // only the tile's first and last unknown are kept
+      if (live) {
+        const int64_t gi = end_idx(b);
+        if (c == 0) a.Y[gi] = q[0];
+        if (last) {
+          double v = q[0];
+#pragma unroll
+          for (int i = 1; i < B; ++i)
+            if (i == len - 1) v = q[i];
+          a.Y[gi + a.M] = v;
+        }
+      }
+    } else if (!part) {
 #pragma unroll
       for (int i = 0; i < B; ++i)
         st64(rO, vo, (uint32_t)i * ldb8, EPI ? cx * q[i] + w[i] : q[i]);
@@ -305,7 +351,7 @@ void k_strided(StridedArgs a) {
         if (i < len) st64(rO, vo, (uint32_t)i * ldb8, EPI ? cx * q[i] + w[i] : q[i]);
     }
     b += gridDim.y;
-    if (b >= a.nb) break;
+    if (b >= ncol) break;
     __syncthreads();   // the LDS of this batch is read before the next one writes it
     load(b);
   }
@@ -314,15 +360,119 @@ void k_strided(StridedArgs a) {
 template <int CW, int SW>
 hipError_t go(const StridedArgs& a, hipStream_t st) {
   const unsigned gx = (unsigned)((a.M + SW - 1) / SW);
-  const unsigned gy = (unsigned)(a.nb < 65535 ? a.nb : 65535);
+  const int64_t ncol = a.pass ? a.nb * a.tiles : a.nb;
+  const unsigned gy = (unsigned)(ncol < 65535 ? ncol : 65535);
   if (a.epi)
-    hipLaunchKernelGGL((k_strided<CW, SW, true>), dim3(gx, gy), dim3(CW * SW), 0, st, a);
+    hipLaunchKernelGGL((k_strided<CW, SW, true, 0>), dim3(gx, gy), dim3(CW * SW), 0, st, a);
   else
-    hipLaunchKernelGGL((k_strided<CW, SW, false>), dim3(gx, gy), dim3(CW * SW), 0, st, a);
+    hipLaunchKernelGGL((k_strided<CW, SW, false, 0>), dim3(gx, gy), dim3(CW * SW), 0, st, a);
   return hipGetLastError();
 }
 
+// A tiled system's passes: every tile (the last one too, whatever its block
+// count) is a column of the full tile's shape.
+template <int PASS>
+hipError_t go_tiles(const StridedArgs& a, hipStream_t st) {
+  constexpr int CW = kStrTileChunks, SW = 16;
+  const unsigned gx = (unsigned)((a.M + SW - 1) / SW);
+  const int64_t ncol = a.nb * a.tiles;
+  const unsigned gy = (unsigned)(ncol < 65535 ? ncol : 65535);
+  hipLaunchKernelGGL((k_strided<CW, SW, false, PASS>), dim3(gx, gy), dim3(CW * SW), 0, st, a);
+  return hipGetLastError();
+}
+
+// The tiles' interface values, one thread per (batch, system).  With
+// (phi, chi) a tile's responses to unit outside values (first and last entry
+// each) and y its zero-outside solution, the first and last unknowns a_m,
+// z_m of tile m satisfy
+//     a_m = yf_m + phif z_{m-1} + chif a_{m+1},
+//     z_m = yl_m + phil z_{m-1} + chil a_{m+1},     z_{-1} = a_K = 0.
+// Left to right, z_{m-1} = r_{m-1} + s_{m-1} a_m gives
+//     a_m = p_m + q_m a_{m+1},  p_m = (yf_m + phif r_{m-1}) / D_m,
+//     q_m = chif / D_m,  D_m = 1 - phif s_{m-1},
+//     r_m = yl_m + phil (r_{m-1} + s_{m-1} p_m),  s_m = phil s_{m-1} q_m + chil;
+// right to left the a_m and z_m follow, and tile m's outside values are
+// z_{m-1} and a_{m+1}.  (p, r) are kept in Gh and (q, s) in Y until the
+// backward sweep.
+__global__ __launch_bounds__(256) void k_strided_interface(
+    const double* __restrict__ ends, double* __restrict__ Y, double* __restrict__ Gh, int64_t M,
+    int64_t P, int64_t K, int64_t nb) {
+  const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (id >= nb * M) return;
+  const int64_t bb = id / M, s = id - bb * M;
+  const double fpf = ends[kTilePF * P + s], fpl = ends[kTilePL * P + s];
+  const double fcf = ends[kTileCF * P + s], fcl = ends[kTileCL * P + s];
+  const double lpf = ends[(4 + kTilePF) * P + s], lpl = ends[(4 + kTilePL) * P + s];
+  const double lcf = ends[(4 + kTileCF) * P + s], lcl = ends[(4 + kTileCL) * P + s];
+  const int64_t base = bb * K * 2 * M + s;
+  // eight tiles at a time: their loads are issued together
+  constexpr int G = 8;
+  double r = 0.0, sp = 0.0;
+  for (int64_t m0 = 0; m0 < K; m0 += G) {
+    double yf[G], yl[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      const int64_t i0 = base + (m0 + u) * 2 * M;
+      yf[u] = m0 + u < K ? Y[i0] : 0.0;
+      yl[u] = m0 + u < K ? Y[i0 + M] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      const int64_t m = m0 + u;
+      if (m >= K) break;
+      const bool lt = m == K - 1;
+      const double pf = lt ? lpf : fpf, pl = lt ? lpl : fpl;
+      const double cf = lt ? lcf : fcf, cl = lt ? lcl : fcl;
+      const int64_t i0 = base + m * 2 * M, i1 = i0 + M;
+      const double iD = 1.0 / (1.0 - pf * sp);
+      const double pm = (yf[u] + pf * r) * iD, qm = cf * iD;
+      const double rn = yl[u] + pl * (r + sp * pm);
+      const double sn = pl * sp * qm + cl;
+      Gh[i0] = pm;
+      Gh[i1] = rn;
+      Y[i0] = qm;
+      Y[i1] = sn;
+      r = rn;
+      sp = sn;
+    }
+  }
+  double an = 0.0;   // a_{m+1}
+  for (int64_t m1 = K - 1; m1 >= 0; m1 -= G) {
+    double pm[G], rm[G], qm[G], sm[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      const int64_t m = m1 - u, i0 = base + m * 2 * M, i1 = i0 + M;
+      const bool in = m >= 0;
+      pm[u] = in ? Gh[i0] : 0.0;
+      rm[u] = in ? Gh[i1] : 0.0;
+      qm[u] = in ? Y[i0] : 0.0;
+      sm[u] = in ? Y[i1] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      const int64_t m = m1 - u;
+      if (m < 0) break;
+      const int64_t i0 = base + m * 2 * M, i1 = i0 + M;
+      const double am = pm[u] + qm[u] * an, zm = rm[u] + sm[u] * an;
+      Gh[i1] = an;                           // right outside value of tile m
+      if (m + 1 < K) Gh[i0 + 2 * M] = zm;    // left outside value of tile m + 1
+      an = am;
+    }
+  }
+  Gh[base] = 0.0;
+}
+
 }  // namespace
+
+hipError_t launch_strided_interface(const double* ends, double* Y, double* Gh, int64_t M,
+                                    int64_t P, int64_t K, int64_t nb, hipStream_t st) {
+  if (M <= 0 || nb <= 0 || K <= 0) return hipSuccess;
+  if (M > P) return hipErrorInvalidValue;
+  const int64_t n = nb * M;
+  hipLaunchKernelGGL(k_strided_interface, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                     ends, Y, Gh, M, P, K, nb);
+  return hipGetLastError();
+}
 
 hipError_t launch_strided(const StridedArgs& a, hipStream_t st) {
   if (a.M <= 0 || a.nb <= 0 || a.N <= 0) return hipSuccess;
@@ -338,6 +488,12 @@ hipError_t launch_strided(const StridedArgs& a, hipStream_t st) {
   // 15.6 ms with 16, 16.9 ms with 32), while rows that do not start on one
   // favour the wider runs (22.7 ms with 16, 20.6 ms with 32).
   const int C = a.C;
+  if (a.pass) {
+    if (a.epi || a.tiles < 1 || a.K < 1 || C > kStrTileChunks ||
+        (a.pass == 1 && !a.Y) || (a.pass == 2 && !a.Gh) || a.pass > 2)
+      return hipErrorInvalidValue;
+    return a.pass == 1 ? go_tiles<1>(a, st) : go_tiles<2>(a, st);
+  }
   if (C <= 1) return go<1, 256>(a, st);
   if (C <= 2) return go<2, 128>(a, st);
   if (C <= 4) return go<4, 64>(a, st);

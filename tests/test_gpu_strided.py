@@ -2,8 +2,9 @@
 i of system s of batch b at b*ldb + i*ld + s) against the CPU oracle,
 through the C ABI: orders 1 to 1024 (every block count, full and ragged last
 blocks), one to hundreds of adjacent systems with their own matrices, both
-batch layouts, padded rows, in place; plus errors, bitwise repeatability and
-hipGraph replay.
+batch layouts, padded rows, in place; longer systems in tiles of 1024 rows
+(a last tile of 1 to 1024 rows, up to 8191 rows, weakly dominant classes);
+plus errors, bitwise repeatability and hipGraph replay.
 
 Inputs: F ~ N(0, 1); classes with t_0 ~ U[2.5, 4], t_+-1 ~ U[-1, -0.5]
 independently (dominance >= 1.25), and the weakly dominant line operators
@@ -133,6 +134,87 @@ def test_strided_in_place_and_repeatable():
     plan.solve(G, G)
     assert np.array_equal(X1, X2)
     assert np.array_equal(X1, to_host(G))
+
+
+TILED = [(1025, "dominant"), (1040, "adi"), (2048, "dominant"), (2049, "adi"),
+         (3000, "adi"), (4097, "dominant"), (8191, "adi")]
+
+
+@pytest.mark.parametrize("n,kind", TILED)
+def test_strided_tiled_orders(n, kind):
+    """Systems longer than one column: full tiles of 1024 rows and a last
+    tile of 1, 16, 1024, 1, 952, 1 and 1023 rows."""
+    tdt = _tdt()
+    rng = np.random.default_rng(300 + n)
+    P = 37
+    tm1, t0, t1 = classes(rng, P, kind)
+    F = rng.standard_normal((n, P))
+    print(f"[case] strided tiled N={n} P={P} {kind}", flush=True)
+    plan = tdt.StridedPlan(n, tm1, t0, t1)
+    X = to_host(plan.solve(to_dev(F)))
+    ref, idx = oracle_strided(F, n, P, P, 1, 0, tm1, t0, t1)
+    check(X, ref, idx, n, P, 1, tm1, t0, t1)
+
+
+@pytest.mark.parametrize("layout", ["outer", "inner"])
+def test_strided_tiled_layouts(layout):
+    """Tiles with M below P, padded rows and nb batches in both layouts."""
+    tdt = _tdt()
+    rng = np.random.default_rng(21 if layout == "outer" else 22)
+    n, M, nb = 2500, 45, 3
+    P = M + 4
+    tm1, t0, t1 = classes(rng, P, "adi")
+    plan = tdt.StridedPlan(n, tm1, t0, t1)
+    if layout == "outer":
+        ld = M + 3
+        F = rng.standard_normal((nb, n, ld))
+        ldb = n * ld
+    else:
+        F = rng.standard_normal((n, nb, M + 2))
+        ld, ldb = nb * (M + 2), M + 2
+    print(f"[case] strided tiled {layout}", flush=True)
+    Xd = to_dev(np.full_like(F, 7.0))
+    plan.solve(to_dev(F), Xd, M=M, ld=ld, nb=nb, ldb=ldb)
+    X = to_host(Xd)
+    ref, idx = oracle_strided(F, n, M, ld, nb, ldb, tm1, t0, t1)
+    check(X, ref, idx, n, M, nb, tm1, t0, t1)
+    mask = np.ones(X.size, dtype=bool)
+    mask[idx.reshape(-1)] = False
+    assert np.all(X.reshape(-1)[mask] == 7.0)   # what no system owns is untouched
+
+
+def test_strided_tiled_in_place_repeatable_graph():
+    """In place equals out of place bit for bit, twice; a captured solve
+    (workspace reserved first) replays to the eager result."""
+    import torch
+    tdt = _tdt()
+    rng = np.random.default_rng(23)
+    n, M = 5000, 100
+    tm1, t0, t1 = classes(rng, M, "adi")
+    plan = tdt.StridedPlan(n, tm1, t0, t1)
+    plan.reserve(M)
+    F = to_dev(rng.standard_normal((n, M)))
+    print("[case] strided tiled in place / graph", flush=True)
+    X1 = to_host(plan.solve(F))
+    X2 = to_host(plan.solve(F))
+    G = F.clone()
+    plan.solve(G, G)
+    assert np.array_equal(X1, X2)
+    assert np.array_equal(X1, to_host(G))
+    X = torch.empty_like(F)
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            plan.solve(F, X, stream=s)
+    for r in range(3):
+        X.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host(X), X1), r
+        plan.solve(F)
 
 
 def test_strided_errors():

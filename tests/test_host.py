@@ -131,10 +131,10 @@ def test_argument_validation_without_device():
     offq = np.array([0, 5, 8], dtype=np.int64)
     assert L.tdt_plan_varlen_quasi_create(2, p(offq), p(t3), p(t3), p(t3), None, p(t3), 0,
                                           ctypes.byref(h)) == _lib.TDT_ERR_INVALID_ARG
-    # strided plans: 1 <= N <= 1024, P >= 1, finite entries, f64 only; a zero
+    # strided plans: 1 <= N <= 2^24, P >= 1, finite entries, f64 only; a zero
     # block pivot is found on the host
     tm, t0s, tp = -np.ones(3), np.full(3, 4.0), -np.ones(3)
-    for n, P_, dt in ((0, 3, 0), (1025, 3, 0), (10, 0, 0), (10, 3, 1), (10, 3, 2)):
+    for n, P_, dt in ((0, 3, 0), (2**24 + 1, 3, 0), (10, 0, 0), (10, 3, 1), (10, 3, 2)):
         assert L.tdt_plan_strided_create(n, P_, p(tm), p(t0s), p(tp), dt, ctypes.byref(h)) == \
             _lib.TDT_ERR_INVALID_ARG, (n, P_, dt)
     bad = np.array([4.0, float("nan"), 4.0])
