@@ -19,7 +19,8 @@ adjoint backward pass) and `general` (64 right-hand sides of N = 2**20 sharing a
 general tridiagonal matrix with per-row entries; paths f64 and f32) and
 `poisson2d` (the 2D Poisson problem on 8191 x 8191 interior points, 2^13
 intervals per side, solved end to end by separation of variables: sine
-transforms, 8191 line systems of 8191, inverse transforms; path f64) and
+transforms, 8191 line systems of 8191 solved in place as a strided batch,
+inverse transforms; path f64) and
 `poisson3d` (the 3D problem of Sec. 3.5 on 511^3 interior points: sine
 transform along x, Peaceman-Rachford ADI on every mode's (y, z) plane with
 strided line solves, inverse transform; path f64).
@@ -125,7 +126,8 @@ def load_workload(name: str, args):
                  desc=f"poisson2d: five-point Poisson problem on {d['nx']}x{d['ny']} interior "
                       f"points of the unit square, zero boundary, F~N(0,1) seed 0, [Ny][Nx] "
                       f"double in/out; sine transforms of the rows (fused: fold, FFT in LDS, "
-                      f"prefix sum) + one Toeplitz line system per mode + inverse transforms")
+                      f"prefix sum) + one Toeplitz line system per mode, solved in place down "
+                      f"the columns of the transformed rows + inverse transforms")
     elif name == "poisson3d":
         d = W.poisson3d(seed=0)
         d.update(kind="poisson3d", units=d["nx"] * d["ny"] * d["nz"], eps=1e-13,
@@ -249,15 +251,15 @@ def run_poisson(tdt, d, F, mode, steps, warmup, torch):
     for _ in range(warmup):
         solver.solve(F, U)
     torch.cuda.synchronize()
-    solver.line_profile(True)
+    solver.profile(True)
     for _ in range(steps):
         solver.solve(F, U)
     torch.cuda.synchronize()
-    prof = solver.line_profile_read()
-    solver.line_profile(False)
+    prof = solver.profile_read()
+    solver.profile(False)
     n = max(prof["solves"], 1)
-    kern = {"line_first_pass": prof["first_pass_ms"] / n, "line_interface": prof["interface_ms"] / n,
-            "line_final_pass": prof["final_ms"] / n}
+    kern = {"forward_transform": prof["forward_ms"] / n, "line_solve": prof["line_ms"] / n,
+            "inverse_transform": prof["inverse_ms"] / n}
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -467,11 +469,16 @@ def main() -> int:
         n_first, n_final = 0, U
     else:
         n_first, n_final = tile_counts(d, _lib.SHAPES[shape][0] * _lib.SHAPES[shape][1])
-    # algorithmic HBM bytes per launch of each kernel group (double data)
+    # algorithmic HBM bytes per launch of each kernel group (double data);
+    # the transforms read and write every unknown once (16 B), the 2D line
+    # solve in tiles (columns of more than 1024 rows) reads them twice and
+    # writes them once (24 B), in one column 16 B
+    line_bytes = (24.0 if d.get("ny", 0) > 1024 else 16.0) * U
     per_launch = {"first_pass": 8.0 * n_first, "final_pass": 16.0 * n_final,
                   "bwd_first_pass": 8.0 * n_first, "bwd_final_pass": 24.0 * n_final,
-                  "line_first_pass": 0.0, "line_interface": 0.0, "line_final_pass": 16.0 * n_final,
-                  "forward_transform": 0.0, "inverse_transform": 0.0,
+                  "line_solve": line_bytes if d["kind"] == "poisson" else 0.0,
+                  "forward_transform": 16.0 * U if d["kind"] in ("poisson", "poisson3d") else 0.0,
+                  "inverse_transform": 16.0 * U if d["kind"] in ("poisson", "poisson3d") else 0.0,
                   "adi": adi_bytes(d, res[head]["counts"]) if d["kind"] == "poisson3d" else 0.0}
     names = {"first_pass": ("k_beta<double> (Green-row tile summaries, first pass)"
                             if d["kind"] == "series" else
@@ -482,9 +489,11 @@ def main() -> int:
                             if d["kind"] == "general" else
                             "k_tile<double, float, REFINE, final> (solve, refine and store)"
                             if head == "f32_refine" else "k_tile<double, double, final> (solve and store)"),
-             "line_final_pass": "k_sys<double, double> (the mode line systems, solved whole: "
-                                "the tridiagonal solve; the row transforms around it take "
-                                "longer, see the kernel profile)",
+             "forward_transform": "k_dst_rows<N2> (the sine transform of every row: fold, "
+                                  "complex FFT in LDS, real split, prefix sum)",
+             "inverse_transform": "k_dst_rows<N2> (the inverse sine transform of every row)",
+             "line_solve": "k_strided in tiles (the mode line systems in place down the "
+                           "columns: end-value pass, interface, re-solve; summed)",
              "adi": "k_strided<double> with the ADI epilogue (all 2 J_1 half-steps of one "
                     "solve: bytes and time summed over them)",
              "bwd_first_pass": "k_tile<double, *, SUMMARY> on T^T (adjoint first pass)",

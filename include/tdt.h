@@ -213,6 +213,14 @@ tdt_status_t tdt_poisson2d_solve(tdt_poisson_t p, const double *F, double *U,
  * autotune it: a varlen plan, or the strided plan of the in-place path
  * (which takes no options). */
 tdt_status_t tdt_poisson2d_line_plan(tdt_poisson_t p, tdt_plan_t *line);
+/* HIP events around the forward transform (with the transpose to mode-major
+ * order on that path), the line solve and the inverse transform of every
+ * later solve (solves on a capturing stream are not recorded); _read
+ * synchronises the device and returns their summed ms in ms3[0..2] and the
+ * number of solves, and clears the record.  Errors: null handle or ms3 ->
+ * TDT_ERR_INVALID_ARG; an event failure -> TDT_ERR_HIP. */
+tdt_status_t tdt_poisson2d_profile(tdt_poisson_t p, int enable);
+tdt_status_t tdt_poisson2d_profile_read(tdt_poisson_t p, double *ms3, int64_t *nsolves);
 tdt_status_t tdt_poisson2d_destroy(tdt_poisson_t p);
 
 /* 3D Poisson solve of Sec. 3.5: the seven-point system

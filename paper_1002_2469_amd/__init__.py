@@ -391,9 +391,12 @@ class StridedPlan(_PlanBase):
 class Poisson2D:
     """2D Poisson solve by separation of variables (Sec. 3.2): the five-point
     system on Nx x Ny interior points with zero boundary values, F and U
-    [Ny][Nx] float64 on the device.  Sine transforms along x (hipFFT), one
-    Toeplitz line system per mode along y (a varlen plan of dtype 'f64' or
-    'f32_refine'), inverse transform."""
+    [Ny][Nx] float64 on the device.  Sine transforms along x (one fused
+    kernel when Nx + 1 is a power of two from 128 to 8192, hipFFT
+    otherwise), one Toeplitz line system per mode along y (in float64 with
+    the fused transform, a strided plan solving the modes in place in the
+    transformed rows; otherwise a varlen plan of dtype 'f64' or
+    'f32_refine' after a transpose), inverse transform."""
 
     def __init__(self, nx: int, ny: int, hx: float, hy: float, dtype: str = "f64"):
         if dtype not in ("f64", "f32_refine"):
@@ -414,6 +417,20 @@ class Poisson2D:
                                                   ctypes.c_void_p(U.data_ptr()),
                                                   _stream_handle(stream)), "tdt_poisson2d_solve")
         return U
+
+    def profile(self, enable: bool = True):
+        """Record HIP events around the forward transform, the line solve
+        and the inverse transform of every later solve."""
+        _lib.check(_lib.lib().tdt_poisson2d_profile(self._h, 1 if enable else 0),
+                   "tdt_poisson2d_profile")
+
+    def profile_read(self) -> dict:
+        ms = np.zeros(3)
+        n = ctypes.c_int64(0)
+        _lib.check(_lib.lib().tdt_poisson2d_profile_read(self._h, ms.ctypes.data_as(ctypes.c_void_p),
+                                                         ctypes.byref(n)),
+                   "tdt_poisson2d_profile_read")
+        return dict(forward_ms=ms[0], line_ms=ms[1], inverse_ms=ms[2], solves=n.value)
 
     def _line(self):
         line = ctypes.c_void_p()

@@ -42,7 +42,8 @@ EXPORTS = [
     "tdt_plan_profile_read", "tdt_build_info", "tdt_plan_set_option", "tdt_plan_get_option",
     "tdt_plan_autotune", "tdt_plan_quasi_create", "tdt_plan_varlen_quasi_create",
     "tdt_plan_general_create", "tdt_poisson2d_create", "tdt_poisson2d_solve",
-    "tdt_poisson2d_line_plan", "tdt_poisson2d_destroy", "tdt_plan_strided_create",
+    "tdt_poisson2d_line_plan", "tdt_poisson2d_destroy", "tdt_poisson2d_profile",
+    "tdt_poisson2d_profile_read", "tdt_plan_strided_create",
     "tdt_solve_strided", "tdt_poisson3d_create", "tdt_poisson3d_solve", "tdt_poisson3d_schedule",
     "tdt_poisson3d_profile", "tdt_poisson3d_profile_read", "tdt_poisson3d_destroy",
     "tdt_adi_parameters",
@@ -99,6 +100,8 @@ def lib():
         "tdt_poisson2d_solve": [p, p, p, p],
         "tdt_poisson2d_line_plan": [p, pp],
         "tdt_poisson2d_destroy": [p],
+        "tdt_poisson2d_profile": [p, i32],
+        "tdt_poisson2d_profile_read": [p, p, ctypes.POINTER(i64)],
         "tdt_plan_strided_create": [i64, i64, p, p, p, i32, pp],
         "tdt_solve_strided": [p, p, p, i64, i64, i64, i64, p],
         "tdt_poisson3d_create": [i64, i64, i64, d, d, d, d, pp],

@@ -48,6 +48,8 @@ struct tdt_poisson_s {
   bool fused = false;            // Nx + 1 = 2 N2 (N2 a power of two): k_dst_rows
   double* tw = nullptr;          // its twiddle tables
   double* pw = nullptr;
+  bool profile = false;
+  std::vector<hipEvent_t> ev;    // 4 per recorded solve
 };
 
 namespace {
@@ -651,6 +653,7 @@ void destroy_poisson(tdt_poisson_s* p) {
   (void)hipDeviceSynchronize();
   if (p->line) (void)tdt_plan_destroy(p->line);
   if (p->fft_made) (void)hipfftDestroy(p->fft);
+  for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
   (void)hipFree(p->sn);
   (void)hipFree(p->y);
   (void)hipFree(p->spec);
@@ -756,15 +759,33 @@ tdt_status_t tdt_poisson2d_solve(tdt_poisson_t p, const double* F, double* U,
   if (!p || !F || !U) return TDT_ERR_INVALID_ARG;
   const int64_t nx = p->nx, ny = p->ny, n = nx + 1;
   auto gy = [](int64_t v) { return (unsigned)(v < (int64_t)kMaxGridY ? v : kMaxGridY); };
+  hipEvent_t* ev = nullptr;
+  if (p->profile) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
+      const size_t k = p->ev.size();
+      p->ev.resize(k + 4);
+      for (size_t j = 0; j < 4; ++j)
+        if (hipEventCreate(&p->ev[k + j]) != hipSuccess) return TDT_ERR_HIP;
+      ev = p->ev.data() + k;
+    }
+  }
+  auto mark = [&](int j) {
+    if (ev) (void)hipEventRecord(ev[j], stream);
+  };
+  const double s = p->hy * p->hy * 2.0 / (double)(nx + 1);
   if (p->strided) {
     // rows' sine transforms (the forward one scaled) into the padded work
     // rows, the mode systems solved in place down the columns, the inverse
     // transforms into U
-    launch_dst_rows(F, p->y, nx, ny, nx, p->ldw, p->hy * p->hy * 2.0 / (double)(nx + 1), p->sn,
-                    p->tw, p->pw, stream);
+    mark(0);
+    launch_dst_rows(F, p->y, nx, ny, nx, p->ldw, s, p->sn, p->tw, p->pw, stream);
+    mark(1);
     tdt_status_t st = tdt_solve_strided(p->line, p->y, p->y, nx, p->ldw, 1, 0, stream);
     if (st < 0) return st;
+    mark(2);
     launch_dst_rows(p->y, U, nx, ny, p->ldw, nx, 1.0, p->sn, p->tw, p->pw, stream);
+    mark(3);
     return hipGetLastError() == hipSuccess ? TDT_OK : TDT_ERR_HIP;
   }
   if (p->fused) {
@@ -772,36 +793,72 @@ tdt_status_t tdt_poisson2d_solve(tdt_poisson_t p, const double* F, double* U,
     // mode-major order (the forward one scaled)
     const dim3 trow((unsigned)((nx + kTileP - 1) / kTileP), gy((ny + kTileP - 1) / kTileP));
     const dim3 tcol((unsigned)((ny + kTileP - 1) / kTileP), gy((nx + kTileP - 1) / kTileP));
+    mark(0);
     launch_dst_rows(F, p->y, nx, ny, nx, nx, 1.0, p->sn, p->tw, p->pw, stream);
     hipLaunchKernelGGL(k_transpose_scale, trow, dim3(kTileP, 8), 0, stream, p->y, p->T, ny, nx,
-                       p->hy * p->hy * 2.0 / (double)(nx + 1));
+                       s);
+    mark(1);
     tdt_status_t st = tdt_solve_varlen(p->line, p->T, p->V, stream);
     if (st < 0) return st;
+    mark(2);
     hipLaunchKernelGGL(k_transpose_scale, tcol, dim3(kTileP, 8), 0, stream, p->V, p->y, nx, ny,
                        1.0);
     launch_dst_rows(p->y, U, nx, ny, nx, nx, 1.0, p->sn, p->tw, p->pw, stream);
+    mark(3);
     return hipGetLastError() == hipSuccess ? TDT_OK : TDT_ERR_HIP;
   }
   if (hipfftSetStream(p->fft, stream) != HIPFFT_SUCCESS) return TDT_ERR_HIP;
   const dim3 tiles((unsigned)((nx + 1 + kTileP - 1) / kTileP), gy((ny + kTileP - 1) / kTileP));
   auto* spec = reinterpret_cast<hipfftDoubleComplex*>(p->spec);
   // sine transform of the rows, scaled and transposed to mode-major order
+  mark(0);
   hipLaunchKernelGGL(k_fold_rows, dim3((unsigned)((n + 255) / 256), gy(ny)), dim3(256), 0,
                      stream, F, p->sn, p->y, nx, ny);
   if (hipfftExecD2Z(p->fft, p->y, spec) != HIPFFT_SUCCESS) return TDT_ERR_HIP;
   launch_scan_rows(p->spec, nx, ny, nullptr, 1.0, stream);
-  const double s = p->hy * p->hy * 2.0 / (double)(nx + 1);
   hipLaunchKernelGGL(k_modes_from_rows, tiles, dim3(kTileP, 8), 0, stream, p->spec, p->T, nx,
                      ny, s);
+  mark(1);
   // one Toeplitz system per mode
   tdt_status_t st = tdt_solve_varlen(p->line, p->T, p->V, stream);
   if (st < 0) return st;
+  mark(2);
   // inverse transform: the same sine transform of the mode coefficients
   hipLaunchKernelGGL(k_fold_modes, tiles, dim3(kTileP, 8), 0, stream, p->V, p->sn, p->y, nx,
                      ny);
   if (hipfftExecD2Z(p->fft, p->y, spec) != HIPFFT_SUCCESS) return TDT_ERR_HIP;
   launch_scan_rows(p->spec, nx, ny, U, 1.0, stream);
+  mark(3);
   return hipGetLastError() == hipSuccess ? TDT_OK : TDT_ERR_HIP;
+}
+
+tdt_status_t tdt_poisson2d_profile(tdt_poisson_t p, int enable) {
+  if (!p) return TDT_ERR_INVALID_ARG;
+  if (!enable) {
+    (void)hipDeviceSynchronize();
+    for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+    p->ev.clear();
+  }
+  p->profile = enable != 0;
+  return TDT_OK;
+}
+
+tdt_status_t tdt_poisson2d_profile_read(tdt_poisson_t p, double* ms3, int64_t* nsolves) {
+  if (!p || !ms3) return TDT_ERR_INVALID_ARG;
+  if (hipDeviceSynchronize() != hipSuccess) return TDT_ERR_HIP;
+  ms3[0] = ms3[1] = ms3[2] = 0.0;
+  const size_t ns = p->ev.size() / 4;
+  for (size_t k = 0; k < ns; ++k)
+    for (int j = 0; j < 3; ++j) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, p->ev[4 * k + j], p->ev[4 * k + j + 1]) != hipSuccess)
+        return TDT_ERR_HIP;
+      ms3[j] += (double)ms;
+    }
+  if (nsolves) *nsolves = (int64_t)ns;
+  for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+  p->ev.clear();
+  return TDT_OK;
 }
 
 tdt_status_t tdt_poisson2d_line_plan(tdt_poisson_t p, tdt_plan_t* line) {

@@ -106,3 +106,28 @@ def test_poisson_errors_and_repeatable():
     print("[case] poisson repeatable", flush=True)
     solver = tdt.Poisson2D(200, 300, 0.01, 0.02)
     assert np.array_equal(to_host(solver.solve(F)), to_host(solver.solve(F)))
+
+
+@pytest.mark.parametrize("nx,ny,dtype", [(255, 2000, "f64"), (255, 40, "f32_refine"),
+                                         (100, 30, "f64")])
+def test_poisson_profile(nx, ny, dtype):
+    """The handle's events: three positive durations per recorded solve (the
+    in-place strided path, the transposing path, the hipFFT path), cleared
+    by the read; the solve is unchanged by recording."""
+    tdt = _tdt()
+    rng = np.random.default_rng(nx + ny)
+    F = to_dev(rng.standard_normal((ny, nx)))
+    print(f"[case] poisson profile nx={nx} ny={ny} {dtype}", flush=True)
+    solver = tdt.Poisson2D(nx, ny, 0.01, 0.02, dtype)
+    ref = to_host(solver.solve(F))
+    solver.profile(True)
+    U1 = to_host(solver.solve(F))
+    solver.solve(F)
+    prof = solver.profile_read()
+    assert prof["solves"] == 2
+    assert prof["forward_ms"] > 0 and prof["line_ms"] > 0 and prof["inverse_ms"] > 0
+    assert solver.profile_read()["solves"] == 0
+    solver.profile(False)
+    solver.solve(F)
+    assert solver.profile_read()["solves"] == 0
+    assert np.array_equal(U1, ref)
