@@ -316,6 +316,15 @@ __device__ __forceinline__ void dft8(double2 (&a)[8]) {
   a[3] = cadd(e3, o3);
   a[7] = csub(e3, o3);
 }
+// LDS positions that spread strided accesses over the banks.  A wavefront's
+// 16-byte accesses are served eight lanes (128 bytes) at a time, 8-byte ones
+// sixteen at a time; lanes k = 8j + e (fixed e) of the real split, and the
+// first radix-8 pass's outputs 8j + r, would all fall on one bank group.
+// Element k of the complex buffer sits at k ^ ((k >> 3) & 7) and double d
+// of the output staging at d ^ ((d >> 4) & 15): each keeps its aligned group
+// of 8 (16) slots, so consecutive indices stay conflict-free too.
+__device__ __forceinline__ int swz16(int k) { return k ^ ((k >> 3) & 7); }
+__device__ __forceinline__ int swz8(int d) { return d ^ ((d >> 4) & 15); }
 
 template <int N2>
 struct DstShape {
@@ -373,6 +382,9 @@ __global__ __launch_bounds__(DstShape<N2>::NT, N2 == 256 ? 5 : 4) void k_dst_row
   // registers, L2 / 3 - 1 through LDS) instead of radix 4
   constexpr bool R8 = E == 8 && L2 % 3 == 0;
   constexpr int NP8 = L2 / 3 - 1;
+  // the radix-8 layout's swizzled positions (identity on the radix-4 path)
+  auto pz = [](int k) { return R8 ? swz16(k) : k; };
+  auto pd = [](int d) { return R8 ? swz8(d) : d; };
   for (int64_t r0 = (int64_t)blockIdx.x * RW; r0 < rows; r0 += (int64_t)gridDim.x * RW) {
     const int64_t r = r0 + rr;
     const bool live = r < rows;
@@ -448,7 +460,7 @@ __global__ __launch_bounds__(DstShape<N2>::NT, N2 == 256 ? 5 : 4) void k_dst_row
       // (b / Ns) 8 Ns + (b mod Ns) + r Ns
       dft8(z);
 #pragma unroll
-      for (int r = 0; r < 8; ++r) buf[rr][8 * j + r] = z[r];
+      for (int r = 0; r < 8; ++r) buf[rr][pz(8 * j + r)] = z[r];
       __syncthreads();
 #pragma unroll 1
       for (int ps = 0; ps < NP8; ++ps) {
@@ -456,7 +468,7 @@ __global__ __launch_bounds__(DstShape<N2>::NT, N2 == 256 ? 5 : 4) void k_dst_row
         const double2 wnext = tw8(ps + 1 < NP8 ? ps + 1 : ps);
         double2 a8[8];
 #pragma unroll
-        for (int r = 0; r < 8; ++r) a8[r] = buf[rr][j + r * (N2 / 8)];
+        for (int r = 0; r < 8; ++r) a8[r] = buf[rr][pz(j + r * (N2 / 8))];
         const double2 w1 = wcur[0], w2 = cmul(w1, w1), w3 = cmul(w2, w1), w4 = cmul(w2, w2);
         wcur[0] = wnext;
         a8[1] = cmul(a8[1], w1);
@@ -470,7 +482,7 @@ __global__ __launch_bounds__(DstShape<N2>::NT, N2 == 256 ? 5 : 4) void k_dst_row
         const int idx = ((j >> lg) << (lg + 3)) + (j & (Ns - 1));
         __syncthreads();   // every thread has read the pass's inputs
 #pragma unroll
-        for (int r = 0; r < 8; ++r) buf[rr][idx + r * Ns] = a8[r];
+        for (int r = 0; r < 8; ++r) buf[rr][pz(idx + r * Ns)] = a8[r];
         __syncthreads();
       }
     } else if constexpr (ODD) {   // radix 2, Ns = 1
@@ -532,7 +544,7 @@ __global__ __launch_bounds__(DstShape<N2>::NT, N2 == 256 ? 5 : 4) void k_dst_row
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int k = E * j + e;
-      const double2 zk = Z[k], zm = Z[(N2 - k) & (N2 - 1)];
+      const double2 zk = Z[pz(k)], zm = Z[pz((N2 - k) & (N2 - 1))];
       const double2 Ev = make_double2(0.5 * (zk.x + zm.x), 0.5 * (zk.y - zm.y));
       const double2 O = make_double2(0.5 * (zk.y + zm.y), -0.5 * (zk.x - zm.x));
       const double2 Y = cadd(Ev, cmul(pwk, O));
@@ -547,7 +559,7 @@ __global__ __launch_bounds__(DstShape<N2>::NT, N2 == 256 ? 5 : 4) void k_dst_row
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int k = E * j + e;
-      if (k >= 1) ob[2 * k - 1] = -im[e];
+      if (k >= 1) ob[pd(2 * k - 1)] = -im[e];
     }
 #pragma unroll
     for (int e = 1; e < E; ++e) v[e] += v[e - 1];
@@ -570,7 +582,7 @@ __global__ __launch_bounds__(DstShape<N2>::NT, N2 == 256 ? 5 : 4) void k_dst_row
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int k = E * j + e;
-      if (2 * k + 1 <= nx) ob[2 * k] = off + v[e];
+      if (2 * k + 1 <= nx) ob[pd(2 * k)] = off + v[e];
     }
     __syncthreads();
     const __amdgpu_buffer_rsrc_t rout =
@@ -579,7 +591,7 @@ __global__ __launch_bounds__(DstShape<N2>::NT, N2 == 256 ? 5 : 4) void k_dst_row
     for (int i = 0; i < 2 * E; ++i) {
       const int m = j + TR * i;
       if (m < nx && live)
-        bstore(rout, lro + (uint32_t)j * 8u, (uint32_t)(TR * i) * 8u, scale * ob[m]);
+        bstore(rout, lro + (uint32_t)j * 8u, (uint32_t)(TR * i) * 8u, scale * ob[pd(m)]);
     }
     __syncthreads();   // the buffer is rewritten by the next rows
   }
