@@ -318,13 +318,19 @@ __device__ __forceinline__ void dft8(double2 (&a)[8]) {
 }
 // LDS positions that spread strided accesses over the banks.  A wavefront's
 // 16-byte accesses are served eight lanes (128 bytes) at a time, 8-byte ones
-// sixteen at a time; lanes k = 8j + e (fixed e) of the real split, and the
-// first radix-8 pass's outputs 8j + r, would all fall on one bank group.
-// Element k of the complex buffer sits at k ^ ((k >> 3) & 7) and double d
-// of the output staging at d ^ ((d >> 4) & 15): each keeps its aligned group
-// of 8 (16) slots, so consecutive indices stay conflict-free too.
-__device__ __forceinline__ int swz16(int k) { return k ^ ((k >> 3) & 7); }
-__device__ __forceinline__ int swz8(int d) { return d ^ ((d >> 4) & 15); }
+// sixteen at a time; the lanes k = E j + e (fixed e) of the real split, and
+// the first pass's outputs E j + r, would fall on one bank group (E = 8) or
+// four (E = 4).  Element k of the complex buffer sits at
+// k ^ ((k >> S) & 7) and double d of the output staging at
+// d ^ ((d >> (S + 1)) & 15): a bijection that keeps each aligned group of 8
+// (16) slots, so consecutive indices stay conflict-free too.  S = 3 for the
+// radix-8 passes and for log2 N2 odd, S = 2 for the even radix-4 sizes,
+// whose passes then have no conflicts at all (one 2-way pass remains for
+// the odd sizes).
+template <int S>
+__device__ __forceinline__ int swz16(int k) { return k ^ ((k >> S) & 7); }
+template <int S>
+__device__ __forceinline__ int swz8(int d) { return d ^ ((d >> (S + 1)) & 15); }
 
 template <int N2>
 struct DstShape {
@@ -382,9 +388,10 @@ __global__ __launch_bounds__(DstShape<N2>::NT, N2 == 256 ? 5 : 4) void k_dst_row
   // registers, L2 / 3 - 1 through LDS) instead of radix 4
   constexpr bool R8 = E == 8 && L2 % 3 == 0;
   constexpr int NP8 = L2 / 3 - 1;
-  // the radix-8 layout's swizzled positions (identity on the radix-4 path)
-  auto pz = [](int k) { return R8 ? swz16(k) : k; };
-  auto pd = [](int d) { return R8 ? swz8(d) : d; };
+  // swizzled positions of the complex buffer and of the output staging
+  constexpr int SZ = (R8 || ODD) ? 3 : 2;
+  auto pz = [](int k) { return swz16<SZ>(k); };
+  auto pd = [](int d) { return swz8<SZ>(d); };
   for (int64_t r0 = (int64_t)blockIdx.x * RW; r0 < rows; r0 += (int64_t)gridDim.x * RW) {
     const int64_t r = r0 + rr;
     const bool live = r < rows;
@@ -489,8 +496,8 @@ __global__ __launch_bounds__(DstShape<N2>::NT, N2 == 256 ? 5 : 4) void k_dst_row
 #pragma unroll
       for (int q = 0; q < E / 2; ++q) {
         const int b = j + TR * q;
-        buf[rr][2 * b] = cadd(z[q], z[q + E / 2]);
-        buf[rr][2 * b + 1] = csub(z[q], z[q + E / 2]);
+        buf[rr][pz(2 * b)] = cadd(z[q], z[q + E / 2]);
+        buf[rr][pz(2 * b + 1)] = csub(z[q], z[q + E / 2]);
       }
     } else {               // radix 4, Ns = 1 (no twiddles)
 #pragma unroll
@@ -498,10 +505,10 @@ __global__ __launch_bounds__(DstShape<N2>::NT, N2 == 256 ? 5 : 4) void k_dst_row
         const int b = j + TR * q;
         const double2 s0 = cadd(z[q], z[q + 2 * Q]), d0 = csub(z[q], z[q + 2 * Q]);
         const double2 s1 = cadd(z[q + Q], z[q + 3 * Q]), d1 = csub(z[q + Q], z[q + 3 * Q]);
-        buf[rr][4 * b] = cadd(s0, s1);
-        buf[rr][4 * b + 1] = make_double2(d0.x + d1.y, d0.y - d1.x);
-        buf[rr][4 * b + 2] = csub(s0, s1);
-        buf[rr][4 * b + 3] = make_double2(d0.x - d1.y, d0.y + d1.x);
+        buf[rr][pz(4 * b)] = cadd(s0, s1);
+        buf[rr][pz(4 * b + 1)] = make_double2(d0.x + d1.y, d0.y - d1.x);
+        buf[rr][pz(4 * b + 2)] = csub(s0, s1);
+        buf[rr][pz(4 * b + 3)] = make_double2(d0.x - d1.y, d0.y + d1.x);
       }
     }
     if constexpr (!R8) __syncthreads();
@@ -516,8 +523,8 @@ __global__ __launch_bounds__(DstShape<N2>::NT, N2 == 256 ? 5 : 4) void k_dst_row
         const int b = j + TR * q;
         const int k = b & (Ns - 1);
         const double2 wnext = twq(ps + 1 < NPL ? ps + 1 : ps, q);
-        double2 v0 = buf[rr][b], v1 = buf[rr][b + N2 / 4];
-        double2 v2 = buf[rr][b + N2 / 2], v3 = buf[rr][b + 3 * (N2 / 4)];
+        double2 v0 = buf[rr][pz(b)], v1 = buf[rr][pz(b + N2 / 4)];
+        double2 v2 = buf[rr][pz(b + N2 / 2)], v3 = buf[rr][pz(b + 3 * (N2 / 4))];
         const double2 w1 = wcur[q], w2 = cmul(w1, w1), w3 = cmul(w2, w1);
         wcur[q] = wnext;
         v1 = cmul(v1, w1);
@@ -534,7 +541,7 @@ __global__ __launch_bounds__(DstShape<N2>::NT, N2 == 256 ? 5 : 4) void k_dst_row
 #pragma unroll
       for (int q = 0; q < Q; ++q)
 #pragma unroll
-        for (int rj = 0; rj < 4; ++rj) buf[rr][idx[q] + rj * Ns] = X[q][rj];
+        for (int rj = 0; rj < 4; ++rj) buf[rr][pz(idx[q] + rj * Ns)] = X[q][rj];
       __syncthreads();
     }
     // the real transform Y_k for k = E j .. E j + E - 1, and the prefix sum of Re Y
