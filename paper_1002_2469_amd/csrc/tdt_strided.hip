@@ -309,46 +309,47 @@ void k_strided(StridedArgs a) {
     const double xl = alpha_prev + bp * h;   // last unknown of the block on the left
     const double xr = u_next;                // first unknown of the block on the right
 
-    // 3. correction: recover d_i = y_i + (t_1/u_i) y_{i+1}, add the outside
-    //    values' contributions (-t_-1 xl carried down from row 0, -t_1 xr at
-    //    the last row), back-substitute
-    double delta = -tm1 * xl;
-    lds_cdouble* iu3 = lds_fresh(&tIU[0][sl]);
-#pragma unroll
-    for (int i = 0; i < B; ++i) {
-      const double ui = iu3[i * SW];
-      delta *= ui;
-      const double ynext = i + 1 < B ? q[i + 1] : 0.0;
-      double dv = q[i] + t1 * ui * ynext + delta;
-      if (i == len - 1) dv -= t1 * xr * ui;
-      q[i] = i < len ? dv : 0.0;
-      delta = -tm1 * delta;
-    }
-    lds_cdouble* iu4 = lds_fresh(&tIU[0][sl]);
-#pragma unroll
-    for (int i = B - 2; i >= 0; --i) q[i] -= t1 * iu4[i * SW] * q[i + 1];
-    const double cx = EPI ? tEP[kEpiCX][sl] : 1.0;
     if constexpr (PASS == 1) {
-      // only the tile's first and last unknown are kept
+      // only the tile's first and last unknown are kept, and they need no
+      // re-sweep: x_0 = y_0 + phi_f xl + chi_f xr and
+      // x_last = y_last + phi_l xl + chi_l xr, with xl = 0 in the first
+      // block and xr = 0 in the last (the tile's outside values are zero)
       if (live) {
         const int64_t gi = end_idx(b);
-        if (c == 0) a.Y[gi] = q[0];
-        if (last) {
-          double v = q[0];
-#pragma unroll
-          for (int i = 1; i < B; ++i)
-            if (i == len - 1) v = q[i];
-          a.Y[gi + a.M] = v;
-        }
+        if (c == 0)
+          a.Y[gi] = yf + tSC[last ? kStrTCF : kStrCF][sl] * xr +
+                    tSC[last ? kStrTPF : kStrPF][sl] * xl;
+        if (last) a.Y[gi + a.M] = yl + tSC[kStrTPL][sl] * xl;
       }
-    } else if (!part) {
-#pragma unroll
-      for (int i = 0; i < B; ++i)
-        st64(rO, vo, (uint32_t)i * ldb8, EPI ? cx * q[i] + w[i] : q[i]);
     } else {
+      // 3. correction: recover d_i = y_i + (t_1/u_i) y_{i+1}, add the outside
+      //    values' contributions (-t_-1 xl carried down from row 0, -t_1 xr at
+      //    the last row), back-substitute
+      double delta = -tm1 * xl;
+      lds_cdouble* iu3 = lds_fresh(&tIU[0][sl]);
 #pragma unroll
-      for (int i = 0; i < B; ++i)
-        if (i < len) st64(rO, vo, (uint32_t)i * ldb8, EPI ? cx * q[i] + w[i] : q[i]);
+      for (int i = 0; i < B; ++i) {
+        const double ui = iu3[i * SW];
+        delta *= ui;
+        const double ynext = i + 1 < B ? q[i + 1] : 0.0;
+        double dv = q[i] + t1 * ui * ynext + delta;
+        if (i == len - 1) dv -= t1 * xr * ui;
+        q[i] = i < len ? dv : 0.0;
+        delta = -tm1 * delta;
+      }
+      lds_cdouble* iu4 = lds_fresh(&tIU[0][sl]);
+#pragma unroll
+      for (int i = B - 2; i >= 0; --i) q[i] -= t1 * iu4[i * SW] * q[i + 1];
+      const double cx = EPI ? tEP[kEpiCX][sl] : 1.0;
+      if (!part) {
+#pragma unroll
+        for (int i = 0; i < B; ++i)
+          st64(rO, vo, (uint32_t)i * ldb8, EPI ? cx * q[i] + w[i] : q[i]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < B; ++i)
+          if (i < len) st64(rO, vo, (uint32_t)i * ldb8, EPI ? cx * q[i] + w[i] : q[i]);
+      }
     }
     b += gridDim.y;
     if (b >= ncol) break;
