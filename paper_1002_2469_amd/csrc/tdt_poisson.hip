@@ -392,10 +392,28 @@ __global__ __launch_bounds__(DstShape<N2>::NT, N2 == 256 ? 5 : 4) void k_dst_row
   constexpr int SZ = (R8 || ODD) ? 3 : 2;
   auto pz = [](int k) { return swz16<SZ>(k); };
   auto pd = [](int d) { return swz8<SZ>(d); };
-  for (int64_t r0 = (int64_t)blockIdx.x * RW; r0 < rows; r0 += (int64_t)gridDim.x * RW) {
+  const int64_t rstep = (int64_t)gridDim.x * RW;
+  // a row block's input, coalesced, into registers (rows past the end read
+  // 0): the next block's is requested while this one's spectrum is written
+  // out, so its latency is hidden behind the scan and the stores
+  const uint32_t lrj = lri + (uint32_t)(t % TR) * 8u;
+  auto load_rows = [&](int64_t rb, double (&nv)[2 * E]) {
+    const int64_t w0 = rb + rr0;
+    uint32_t nb = 0u;
+    if (w0 < rows) {
+      const int64_t b = ((rows - w0 - 1) * ldi + nx) * 8;
+      nb = b < ((int64_t)1 << 31) ? (uint32_t)b : 0x7fffffffu;
+    }
+    const __amdgpu_buffer_rsrc_t rin = row_rsrc(in + (w0 < rows ? w0 : 0) * ldi, nb);
+#pragma unroll
+    for (int i = 0; i < 2 * E; ++i) nv[i] = bload(rin, lrj, (uint32_t)(TR * i) * 8u);
+  };
+  double nv[2 * E];
+  load_rows((int64_t)blockIdx.x * RW, nv);
+  for (int64_t r0 = (int64_t)blockIdx.x * RW; r0 < rows; r0 += rstep) {
     const int64_t r = r0 + rr;
     const bool live = r < rows;
-    // the row into LDS (f_m+1 at m), coalesced; rows past the end read 0
+    // the row into LDS (f_m+1 at m)
     const int64_t rw0 = r0 + rr0;
     // the bytes from the wavefront's first row to the end of the array
     auto avail = [&](int64_t ld) {
@@ -403,7 +421,6 @@ __global__ __launch_bounds__(DstShape<N2>::NT, N2 == 256 ? 5 : 4) void k_dst_row
       const int64_t b = ((rows - rw0 - 1) * ld + nx) * 8;
       return b < ((int64_t)1 << 31) ? (uint32_t)b : 0x7fffffffu;
     };
-    const __amdgpu_buffer_rsrc_t rin = row_rsrc(in + (rw0 < rows ? rw0 : 0) * ldi, avail(ldi));
     double* fl = reinterpret_cast<double*>(buf[rr]);
     // the lane's index, opaque to the compiler, for the table loads: their
     // values repeat from row to row, and held across rows they would take
@@ -441,8 +458,7 @@ __global__ __launch_bounds__(DstShape<N2>::NT, N2 == 256 ? 5 : 4) void k_dst_row
 #pragma unroll
     for (int i = 0; i < 2 * E; ++i) {
       const int m = j + TR * i;
-      const double v = bload(rin, lri + (uint32_t)j * 8u, (uint32_t)(TR * i) * 8u);
-      if (m < nx) fl[m] = v;
+      if (m < nx) fl[m] = nv[i];
     }
     __syncthreads();
     // fold, packed in pairs: z_k = y_2k + i y_2k+1 for k = j + TR e
@@ -560,6 +576,7 @@ __global__ __launch_bounds__(DstShape<N2>::NT, N2 == 256 ? 5 : 4) void k_dst_row
       pwk = cmul(pwk, pw[1]);   // e^{-2 pi i (k + 1) / n}
     }
     __syncthreads();   // the spectrum is read
+    if (r0 + rstep < rows) load_rows(r0 + rstep, nv);
     // S in natural order (m - 1) in LDS: the odd terms now, the even ones
     // after the scan, then coalesced stores
     double* ob = reinterpret_cast<double*>(buf[rr]);
