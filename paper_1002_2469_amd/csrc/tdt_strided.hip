@@ -67,7 +67,9 @@ __device__ __forceinline__ lds_cdouble* lds_fresh(const double* p) {
   return (lds_cdouble*)(uintptr_t)v;
 }
 
-template <int CW, int SW, bool EPI, int PASS>
+// EPI: 0 plain solve, 1 epilogue without the second input (g = 0, not
+// read), 2 epilogue with it
+template <int CW, int SW, int EPI, int PASS>
 __global__ __launch_bounds__(CW * SW, 4)
 void k_strided(StridedArgs a) {
   constexpr int NT = CW * SW;
@@ -87,7 +89,7 @@ void k_strided(StridedArgs a) {
   // elements from the wave's base
   const uint32_t ldb8 = (uint32_t)(a.ld * 8);
   const uint32_t voff = (uint32_t)((c - c0) * B) * ldb8 + (uint32_t)(sl - sl0) * 8u;
-  const bool with_g = EPI && a.G != nullptr && s < a.Mg;
+  const bool with_g = EPI == 2 && a.G != nullptr && s < a.Mg;
 
   // columns of the launch: batches, or (batch, tile) pairs of a tiled system
   const int64_t ncol = PASS ? a.nb * a.tiles : a.nb;
@@ -117,11 +119,11 @@ void k_strided(StridedArgs a) {
   auto load = [&](int64_t bb) {
     const int64_t wbase = col_off(bb) + (int64_t)c0 * B * a.ld + s_w;
     const __amdgpu_buffer_rsrc_t rR = wave_rsrc(a.R + wbase);
-    const __amdgpu_buffer_rsrc_t rG = wave_rsrc(EPI && a.G ? a.G + wbase : a.R + wbase);
+    const __amdgpu_buffer_rsrc_t rG = wave_rsrc(EPI == 2 && a.G ? a.G + wbase : a.R + wbase);
     if (!part) {
 #pragma unroll
       for (int i = 0; i < B; ++i) q[i] = ld64(rR, vo, (uint32_t)i * ldb8);
-      if (EPI) {
+      if (EPI == 2) {
 #pragma unroll
         for (int i = 0; i < B; ++i) w[i] = ld64(rG, vg, (uint32_t)i * ldb8);
       }
@@ -131,7 +133,7 @@ void k_strided(StridedArgs a) {
         q[i] = 0.0;
         if (i < len) q[i] = ld64(rR, vo, (uint32_t)i * ldb8);
       }
-      if (EPI) {
+      if (EPI == 2) {
 #pragma unroll
         for (int i = 0; i < B; ++i) {
           w[i] = 0.0;
@@ -187,7 +189,7 @@ void k_strided(StridedArgs a) {
       const double cr = tEP[kEpiCR][sl], cg = tEP[kEpiCG][sl];
 #pragma unroll
       for (int i = 0; i < B; ++i) {
-        const double r = q[i], gi = w[i];
+        const double r = q[i], gi = EPI == 2 ? w[i] : 0.0;
         w[i] = cr * r + cg * gi;
         q[i] = scale * (r + cq * gi);
         asm volatile("" : "+v"(w[i]));   // formed here: r and g are not kept to the store
@@ -363,10 +365,12 @@ hipError_t go(const StridedArgs& a, hipStream_t st) {
   const unsigned gx = (unsigned)((a.M + SW - 1) / SW);
   const int64_t ncol = a.pass ? a.nb * a.tiles : a.nb;
   const unsigned gy = (unsigned)(ncol < 65535 ? ncol : 65535);
-  if (a.epi)
-    hipLaunchKernelGGL((k_strided<CW, SW, true, 0>), dim3(gx, gy), dim3(CW * SW), 0, st, a);
+  if (a.epi && a.G && a.Mg > 0)
+    hipLaunchKernelGGL((k_strided<CW, SW, 2, 0>), dim3(gx, gy), dim3(CW * SW), 0, st, a);
+  else if (a.epi)
+    hipLaunchKernelGGL((k_strided<CW, SW, 1, 0>), dim3(gx, gy), dim3(CW * SW), 0, st, a);
   else
-    hipLaunchKernelGGL((k_strided<CW, SW, false, 0>), dim3(gx, gy), dim3(CW * SW), 0, st, a);
+    hipLaunchKernelGGL((k_strided<CW, SW, 0, 0>), dim3(gx, gy), dim3(CW * SW), 0, st, a);
   return hipGetLastError();
 }
 
@@ -378,7 +382,7 @@ hipError_t go_tiles(const StridedArgs& a, hipStream_t st) {
   const unsigned gx = (unsigned)((a.M + SW - 1) / SW);
   const int64_t ncol = a.nb * a.tiles;
   const unsigned gy = (unsigned)(ncol < 65535 ? ncol : 65535);
-  hipLaunchKernelGGL((k_strided<CW, SW, false, PASS>), dim3(gx, gy), dim3(CW * SW), 0, st, a);
+  hipLaunchKernelGGL((k_strided<CW, SW, 0, PASS>), dim3(gx, gy), dim3(CW * SW), 0, st, a);
   return hipGetLastError();
 }
 
