@@ -36,8 +36,11 @@ def tol(nx, ny, hx, hy):
 
 # Nx + 1 = 2 N2 with N2 a power of two in [64, 4096] takes the fused row
 # transform (127 .. 8191), the other sizes hipFFT's
+# (in f64 these solve the mode systems in place as a strided batch: one
+# column per system up to Ny = 1024, tiles of 512 rows above, e.g. 255 x 3001
+# with a last tile of 441 rows and 511 x 1537 with one of 1 row)
 GRIDS = [(1, 1), (1, 9), (7, 1), (31, 17), (64, 64), (100, 257), (513, 700), (16, 20000),
-         (127, 3), (255, 130), (1023, 41), (2047, 5), (4095, 19)]
+         (127, 3), (255, 130), (1023, 41), (2047, 5), (4095, 19), (255, 3001), (511, 1537)]
 
 
 @pytest.mark.parametrize("nx,ny", GRIDS)
