@@ -142,7 +142,7 @@ tdt_status_t tdt_plan_general_create(int64_t N, const double *h_a, const double 
  * adjacent systems: every lane holds a 16-row block of one system, the
  * interface values of eq. (15) are scanned across the blocks inside the
  * workgroup, and the blocks are corrected in registers.  A system of more
- * than 1024 rows is cut into tiles of 1024 rows (the last one shorter), each
+ * than 1024 rows is cut into tiles of 512 rows (the last one shorter), each
  * such a column: a first pass keeps the end values of every tile's solution
  * with zero outside values, one thread per system eliminates the tiles'
  * interface values (the recurrences of eq. (15) over the tiles), and a
@@ -169,7 +169,7 @@ tdt_status_t tdt_plan_strided_create(int64_t N, int64_t P, const double *h_tm1,
  * nb > 1, ldb >= (N-1)*ld + M), or batches interleaved in each row
  * (ldb >= M, ld >= (nb-1)*ldb + M); other layouts -> TDT_ERR_INVALID_ARG.
  * N <= 1024: no workspace.  Longer N: the plan's workspace holds
- * 4 nb M ceil(N/1024) doubles, allocated on first use or by
+ * 4 nb M ceil(N/512) doubles, allocated on first use or by
  * tdt_plan_reserve(plan, nb*M); a solve that needs more while its stream is
  * being captured returns TDT_ERR_CAPTURE.  Five launches then (two per pass,
  * the full tiles and the last one, and the interface), one otherwise; both
@@ -191,7 +191,7 @@ tdt_status_t tdt_solve_strided(tdt_plan_t plan, const double *F, double *X, int6
  * solved in place in the transformed rows by a strided plan (system k is
  * column k; rows padded to ldw = 16 ceil(Nx/16) + 16 doubles): 2 row
  * transforms and the strided solve, no transposes; the workspace is Ny ldw
- * doubles plus the strided plan's 4 Nx ceil(Ny/1024) when Ny > 1024.
+ * doubles plus the strided plan's 4 Nx ceil(Ny/512) when Ny > 1024.
  * Otherwise (TDT_F32_REFINE, or the hipFFT path) the transformed rows are
  * transposed to mode-major order and solved by a varlen plan of this
  * library, with 2 Nx Ny + Ny (Nx + 1) doubles of workspace, plus

@@ -15,7 +15,7 @@
 //   3. every lane re-sweeps its block with its two outside values folded
 //      into the first and last right-hand side row.
 // Columns of at most kStrMaxChunks * kStrB = 1024 rows; a longer system is
-// cut into tiles of that many rows, solved in two passes over the columns
+// cut into tiles of kStrTile rows, solved in two passes over the columns
 // with the tiles' interface values eliminated between them (the same steps
 // one level up: the end values of every tile's zero-outside solution, the
 // recurrences of eq. (15) over the tiles, the re-solve).  Optionally the
