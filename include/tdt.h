@@ -153,7 +153,8 @@ tdt_status_t tdt_plan_general_create(int64_t N, const double *h_a, const double 
  * tile plus 8 tile end values).
  * dtype: TDT_F64 only.  Errors: N outside [1, 2^24], P < 1, null arrays,
  * non-finite entries, another dtype -> TDT_ERR_INVALID_ARG; a zero block
- * pivot or a vanishing interface pivot -> TDT_ERR_SINGULAR; returns
+ * pivot or a vanishing interface pivot (of the blocks or of the tiles) ->
+ * TDT_ERR_SINGULAR; host or device allocation -> TDT_ERR_OOM; returns
  * TDT_WARN_NOT_DOMINANT (plan valid) when some class has
  * |t_0| < |t_-1| + |t_1|.  tdt_solve, tdt_solve_varlen, tdt_solve_backward,
  * options and autotuning refuse such a plan (TDT_ERR_INVALID_ARG). */

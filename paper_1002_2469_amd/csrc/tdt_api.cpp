@@ -15,6 +15,7 @@
 #include <new>
 #include <numeric>
 #include <queue>
+#include <exception>
 #include <vector>
 
 #include "tdt.h"
@@ -1406,7 +1407,12 @@ tdt_status_t tdt_plan_strided_create(int64_t N, int64_t P, const double* h_tm1,
   const int64_t n1 = (int64_t)(tdt::kStrB + tdt::kStrScalarN + 2 * C) * P;
   const int64_t n2 = K > 1 ? (int64_t)(tdt::kStrB + tdt::kStrScalarN + 2 * CL) * P : 0;
   const int64_t n3 = K > 1 ? (int64_t)tdt::kTileEndN * P : 0;
-  std::vector<double> tab((size_t)(n1 + n2 + n3));
+  std::vector<double> tab;
+  try {
+    tab.resize((size_t)(n1 + n2 + n3));
+  } catch (const std::exception&) {   // P too large for the host tables
+    return TDT_ERR_OOM;
+  }
   double dom = 0.0;
   auto tables = [&](int64_t n, double* t) {
     double* iu = t;
