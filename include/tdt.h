@@ -238,11 +238,15 @@ tdt_status_t tdt_poisson2d_destroy(tdt_poisson_t p);
  * directions' operators; J_k is the smallest count whose error bound for a
  * full cycle, d_J^2 with d_J = prod_j (w_j - a)/(w_j + a), is <= eps, so the
  * 2-norm error of the result relative to the exact discrete solution is at
- * most eps (plus rounding).  J_k falls as k grows.  1 <= Ny, Nz <= 1024,
- * 640 Nxp Ny < 2^31 with Nxp = 16 ceil(Nx/16) + 16 on the fused path, Nx otherwise
- * (31-bit byte offsets of the z lines), 0 < eps < 1.  The handle
- * owns the per-iteration tables (~(38 + 4 ceil(N/16)) doubles per mode and
- * iteration) and 2 (16 ceil(Nx/16) + 16) Ny Nz doubles of workspace when
+ * most eps (plus rounding).  J_k falls as k grows.  1 <= Ny, Nz <= 2^24
+ * (lines of more than 1024 points are solved in tiles of 512, as by
+ * tdt_solve_strided), 640 Nxp Ny < 2^31 with Nxp = 16 ceil(Nx/16) + 16 on
+ * the fused path, Nx otherwise (31-bit byte offsets of the z lines),
+ * 0 < eps < 1; a count above 400 for some mode -> TDT_ERR_INVALID_ARG.  The
+ * handle owns the per-iteration tables (~(38 + 4 ceil(N/16)) doubles per
+ * mode and iteration, about twice that for tiled lines), for tiled lines
+ * 4 Nx max(Nz ceil(Ny/512), Ny ceil(Nz/512)) doubles, and
+ * 2 (16 ceil(Nx/16) + 16) Ny Nz doubles of workspace when
  * Nx+1 is a power of two from 128 to 8192 (the fused row transform; rows
  * padded to cache lines), else the FFT plan and (2 Nx + 3) Ny Nz doubles
  * (allocated here, blocking).  Errors: bad sizes, spacings or eps ->

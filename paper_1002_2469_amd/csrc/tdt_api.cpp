@@ -54,11 +54,10 @@ struct tdt_plan_s {
   int64_t sP = 0;
   int sC = 0;
   double* dstr = nullptr;   // iu [kStrB][P] | sc [kStrScalarN][P] | pos [2][C][P]
-  // a system longer than one column: sK tiles of kStrTile rows, the last of
-  // sNL rows (sCL blocks) with its own tables at dstr + str_last, and the
-  // tiles' end values [kTileEndN][P] at dstr + str_ends
-  int64_t sK = 1, sNL = 0, str_last = 0, str_ends = 0;
-  int sCL = 0;
+  // a system longer than one column: sK tiles (tdt::strided_tiles), the
+  // full tile's tables, the last tile's and the end values one after
+  // another at dstr
+  int64_t sK = 1;
   bool varlen = false;
   tdt_dtype_t dtype = TDT_F64;
   int64_t N = 0;          // series: order of the system (with its corner rows)
@@ -1114,6 +1113,61 @@ int strided_tables(int64_t N, int64_t P, const double* tm1, const double* t0, co
   if (dominance) *dominance = dom;
   return TDT_OK;
 }
+
+StridedTiles strided_tiles(int64_t N, int64_t P) {
+  StridedTiles g{};
+  g.K = (N + kStrTile - 1) / kStrTile;
+  g.NL = N - (g.K - 1) * kStrTile;
+  g.C = strided_chunks(g.K > 1 ? kStrTile : N);
+  g.CL = strided_chunks(g.NL);
+  g.n_full = (int64_t)(kStrB + kStrScalarN + 2 * g.C) * P;
+  g.n_last = (int64_t)(kStrB + kStrScalarN + 2 * g.CL) * P;
+  g.n_ends = (int64_t)kTileEndN * P;
+  return g;
+}
+
+// Tables of a system in tiles: a full tile's and the last tile's column
+// tables, and per class the end values (phi_f, phi_l, chi_f, chi_l) of both
+// tile lengths.  The pivots D_m = 1 - phi_f s_{m-1} of the tiles'
+// elimination depend on the class only and are checked here; s_m settles
+// quickly, so the full tiles stop at its fixed point.
+int strided_tiled_tables(int64_t N, int64_t P, const double* tm1, const double* t0,
+                         const double* t1, double* out, double* dominance) {
+  const StridedTiles g = strided_tiles(N, P);
+  if (g.K < 2) return TDT_ERR_INVALID_ARG;
+  auto tables = [&](int64_t n, double* t) {
+    double* iu = t;
+    double* sc = iu + (int64_t)kStrB * P;
+    double* pos = sc + (int64_t)kStrScalarN * P;
+    return strided_tables(n, P, tm1, t0, t1, iu, sc, pos, dominance);
+  };
+  int st = tables(kStrTile, out);
+  if (st < 0) return st;
+  st = tables(g.NL, out + g.n_full);
+  if (st < 0) return st;
+  double* ends = out + g.n_full + g.n_last;
+  for (int64_t k = 0; k < P; ++k) {
+    ld full[4], lastv[4];
+    if (!segment_ends(tm1[k], t0[k], t1[k], kStrTile, full) ||
+        !segment_ends(tm1[k], t0[k], t1[k], g.NL, lastv))
+      return TDT_ERR_SINGULAR;
+    for (int e = 0; e < 4; ++e) {
+      ends[(int64_t)e * P + k] = (double)full[e];
+      ends[(int64_t)(4 + e) * P + k] = (double)lastv[e];
+    }
+    ld sv = 0.0L;
+    for (int64_t m = 0; m < g.K; ++m) {
+      const ld* e = m == g.K - 1 ? lastv : full;
+      const ld D = 1.0L - e[0] * sv;
+      if (!(std::fabs((double)D) > 1e-13)) return TDT_ERR_SINGULAR;
+      const ld sn = e[1] * sv * e[2] / D + e[3];
+      if (!std::isfinite((double)sn)) return TDT_ERR_SINGULAR;
+      if (m < g.K - 2 && sn == sv) m = g.K - 2;   // the full tiles left repeat it
+      sv = sn;
+    }
+  }
+  return TDT_OK;
+}
 }  // namespace tdt
 
 // ---------------------------------------------------------------------------
@@ -1400,13 +1454,11 @@ tdt_status_t tdt_plan_strided_create(int64_t N, int64_t P, const double* h_tm1,
   if (N < 1 || N > tdt::kStrMaxN || P < 1 || P > ((int64_t)1 << 31) || !h_tm1 || !h_t0 ||
       !h_t1 || dtype != TDT_F64)
     return TDT_ERR_INVALID_ARG;
-  // one column, or tiles of kStrTile rows and a last tile of NL rows
-  const int64_t K = (N + tdt::kStrTile - 1) / tdt::kStrTile;
-  const int64_t NT = K > 1 ? tdt::kStrTile : N, NL = N - (K - 1) * tdt::kStrTile;
-  const int C = tdt::strided_chunks(NT), CL = tdt::strided_chunks(NL);
-  const int64_t n1 = (int64_t)(tdt::kStrB + tdt::kStrScalarN + 2 * C) * P;
-  const int64_t n2 = K > 1 ? (int64_t)(tdt::kStrB + tdt::kStrScalarN + 2 * CL) * P : 0;
-  const int64_t n3 = K > 1 ? (int64_t)tdt::kTileEndN * P : 0;
+  // one column, or tiles of kStrTile rows and a shorter last tile
+  const tdt::StridedTiles g = tdt::strided_tiles(N, P);
+  const int64_t K = g.K;
+  const int C = g.C;
+  const int64_t n1 = g.n_full, n2 = K > 1 ? g.n_last : 0, n3 = K > 1 ? g.n_ends : 0;
   std::vector<double> tab;
   try {
     tab.resize((size_t)(n1 + n2 + n3));
@@ -1414,42 +1466,12 @@ tdt_status_t tdt_plan_strided_create(int64_t N, int64_t P, const double* h_tm1,
     return TDT_ERR_OOM;
   }
   double dom = 0.0;
-  auto tables = [&](int64_t n, double* t) {
-    double* iu = t;
-    double* sc = iu + (int64_t)tdt::kStrB * P;
-    double* pos = sc + (int64_t)tdt::kStrScalarN * P;
-    return tdt::strided_tables(n, P, h_tm1, h_t0, h_t1, iu, sc, pos, &dom);
-  };
-  int st = tables(NT, tab.data());
+  const int st =
+      K > 1 ? tdt::strided_tiled_tables(N, P, h_tm1, h_t0, h_t1, tab.data(), &dom)
+            : tdt::strided_tables(N, P, h_tm1, h_t0, h_t1, tab.data(),
+                                  tab.data() + (int64_t)tdt::kStrB * P,
+                                  tab.data() + (int64_t)(tdt::kStrB + tdt::kStrScalarN) * P, &dom);
   if (st < 0) return (tdt_status_t)st;
-  if (K > 1) {
-    st = tables(NL, tab.data() + n1);
-    if (st < 0) return (tdt_status_t)st;
-    double* ends = tab.data() + n1 + n2;
-    for (int64_t k = 0; k < P; ++k) {
-      ld full[4], lastv[4];
-      if (!segment_ends(h_tm1[k], h_t0[k], h_t1[k], NT, full) ||
-          !segment_ends(h_tm1[k], h_t0[k], h_t1[k], NL, lastv))
-        return TDT_ERR_SINGULAR;
-      for (int e = 0; e < 4; ++e) {
-        ends[(int64_t)e * P + k] = (double)full[e];
-        ends[(int64_t)(4 + e) * P + k] = (double)lastv[e];
-      }
-      // the pivots D_m = 1 - phif s_{m-1} of the tiles' elimination (they
-      // depend on the class only); s_m settles quickly, so the full tiles
-      // stop at its fixed point
-      ld sv = 0.0L;
-      for (int64_t m = 0; m < K; ++m) {
-        const ld* e = m == K - 1 ? lastv : full;
-        const ld D = 1.0L - e[0] * sv;
-        if (!(std::fabs((double)D) > 1e-13)) return TDT_ERR_SINGULAR;
-        const ld sn = e[1] * sv * e[2] / D + e[3];
-        if (!std::isfinite((double)sn)) return TDT_ERR_SINGULAR;
-        if (m < K - 2 && sn == sv) m = K - 2;   // the full tiles left repeat it
-        sv = sn;
-      }
-    }
-  }
   tdt_plan_s* p = new (std::nothrow) tdt_plan_s();
   if (!p) return TDT_ERR_OOM;
   p->strided = true;
@@ -1459,10 +1481,6 @@ tdt_status_t tdt_plan_strided_create(int64_t N, int64_t P, const double* h_tm1,
   p->sP = P;
   p->sC = C;
   p->sK = K;
-  p->sNL = NL;
-  p->sCL = CL;
-  p->str_last = n1;
-  p->str_ends = n1 + n2;
   p->dominance = dom;
   p->kappa = 0.0;
   tdt_status_t s2 = dev_upload(&p->dstr, tab.data(), tab.size());
@@ -1528,35 +1546,9 @@ tdt_status_t tdt_solve_strided(tdt_plan_t p, const double* F, double* X, int64_t
     if (tdt::launch_strided(a, stream) != hipSuccess) return TDT_ERR_HIP;
   } else {
     // pass 1 and pass 2 over the full tiles, then over the last one
-    const int64_t off = (K - 1) * tdt::kStrTile * ld;
-    a.K = K;
-    a.ldt = tdt::kStrTile * ld;
-    a.Y = p->summ;
-    a.Gh = p->ghost;
-    auto pass = [&](int which) {
-      a.pass = which;
-      set_tables(p->dstr);
-      a.R = F;
-      a.O = X;
-      a.N = tdt::kStrTile;
-      a.C = p->sC;
-      a.tiles = K - 1;
-      a.m0 = 0;
-      if (tdt::launch_strided(a, stream) != hipSuccess) return false;
-      set_tables(p->dstr + p->str_last);
-      a.R = F + off;
-      a.O = X + off;
-      a.N = p->sNL;
-      a.C = p->sCL;
-      a.tiles = 1;
-      a.m0 = K - 1;
-      return tdt::launch_strided(a, stream) == hipSuccess;
-    };
-    if (!pass(1)) return TDT_ERR_HIP;
-    if (tdt::launch_strided_interface(p->dstr + p->str_ends, p->summ, p->ghost, M, p->sP, K, nb,
-                                      stream) != hipSuccess)
+    if (tdt::launch_strided_tiled(a, tdt::strided_tiles(N, p->sP), p->dstr, p->summ, p->ghost,
+                                  stream) != hipSuccess)
       return TDT_ERR_HIP;
-    if (!pass(2)) return TDT_ERR_HIP;
   }
   if (ev) (void)hipEventRecord(ev[3], stream);
   return TDT_OK;

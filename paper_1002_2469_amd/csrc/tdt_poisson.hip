@@ -946,6 +946,8 @@ struct tdt_poisson3d_s {
   double* tw = nullptr;     // its twiddle tables
   double* pw = nullptr;
   double* W = nullptr;      // the ADI work array (the spectrum buffer otherwise)
+  double* Yt = nullptr;     // lines of more than 1024 rows: the tiles' end values
+  double* Gt = nullptr;     // and outside values, [nb][K][2][modes] each
   double* fh = nullptr;     // fhat (U otherwise)
   int64_t ldx = 0;          // row stride of W and fhat: Nx rounded up to 16 (128-byte rows)
   std::vector<int> count;                  // J_k
@@ -1037,6 +1039,8 @@ void destroy_poisson3d(tdt_poisson3d_s* p) {
   (void)hipFree(p->pw);
   (void)hipFree(p->W);
   (void)hipFree(p->fh);
+  (void)hipFree(p->Yt);
+  (void)hipFree(p->Gt);
   delete p;
 }
 
@@ -1050,7 +1054,7 @@ tdt_status_t tdt_poisson3d_create(int64_t nx, int64_t ny, int64_t nz, double hx,
                                   double hz, double eps, tdt_poisson3d_t* out) {
   if (!out) return TDT_ERR_INVALID_ARG;
   *out = nullptr;
-  const int64_t lmax = (int64_t)tdt::kStrMaxChunks * tdt::kStrB;
+  const int64_t lmax = tdt::kStrMaxN;
   if (nx < 1 || ny < 1 || nz < 1 || ny > lmax || nz > lmax || nx > (1 << 20) ||
       nx * ny * nz > ((int64_t)1 << 34) || ny * nz > ((int64_t)1 << 31) ||
       (int64_t)(5 * tdt::kStrB) * nx * ny * 8 + 512 >= ((int64_t)1 << 31) ||
@@ -1122,8 +1126,12 @@ tdt_status_t tdt_poisson3d_create(int64_t nx, int64_t ny, int64_t nz, double hx,
       std::vector<double> tm1((size_t)P, -1.0), t0((size_t)P), t1((size_t)P, -1.0);
       const size_t base = tab.size();
       p->toff[d][(size_t)j] = (int64_t)base;
-      tab.resize(base + (size_t)((tdt::kStrB + tdt::kStrScalarN + 2 * C + tdt::kEpiN) * P));
-      double* epi = tab.data() + base + (tdt::kStrB + tdt::kStrScalarN + 2 * C) * P;
+      // one column: iu | sc | pos | epi; tiles: full | last | ends | epi
+      const tdt::StridedTiles g = tdt::strided_tiles(N, P);
+      const int64_t ncol = g.K > 1 ? g.n_full + g.n_last + g.n_ends
+                                   : (int64_t)(tdt::kStrB + tdt::kStrScalarN + 2 * C) * P;
+      tab.resize(base + (size_t)(ncol + tdt::kEpiN * P));
+      double* epi = tab.data() + base + ncol;
       for (int64_t k = 0; k < P; ++k) {
         const long double wk = w[(size_t)k][(size_t)j];
         t0[(size_t)k] = (double)(2.0L + h2 * (wk + 0.5L * mu[(size_t)k]));
@@ -1142,7 +1150,9 @@ tdt_status_t tdt_poisson3d_create(int64_t nx, int64_t ny, int64_t nz, double hx,
       double* iu = tab.data() + base;
       double* sc = iu + tdt::kStrB * P;
       double* pos = sc + tdt::kStrScalarN * P;
-      const int r = tdt::strided_tables(N, P, tm1.data(), t0.data(), t1.data(), iu, sc, pos, &dom);
+      const int r =
+          g.K > 1 ? tdt::strided_tiled_tables(N, P, tm1.data(), t0.data(), t1.data(), iu, &dom)
+                  : tdt::strided_tables(N, P, tm1.data(), t0.data(), t1.data(), iu, sc, pos, &dom);
       if (r < 0) st = (tdt_status_t)r;
     }
   }
@@ -1167,6 +1177,16 @@ tdt_status_t tdt_poisson3d_create(int64_t nx, int64_t ny, int64_t nz, double hx,
         hipMalloc(&p->spec, (size_t)(rows * Kc) * 2 * sizeof(double)) != hipSuccess) ||
        hipMalloc(&p->tabs, tab.size() * sizeof(double)) != hipSuccess))
     st = TDT_ERR_OOM;
+  // lines of more than 1024 rows run in tiles, with the tiles' end and
+  // outside values of every (batch, mode) in two work arrays
+  {
+    const int64_t ky = tdt::strided_tiles(ny, 1).K, kz = tdt::strided_tiles(nz, 1).K;
+    const int64_t slots = std::max(ky > 1 ? nz * ky : 0, kz > 1 ? ny * kz : 0) * nx * 2;
+    if (st == TDT_OK && slots > 0 &&
+        (hipMalloc(&p->Yt, (size_t)slots * sizeof(double)) != hipSuccess ||
+         hipMalloc(&p->Gt, (size_t)slots * sizeof(double)) != hipSuccess))
+      st = TDT_ERR_OOM;
+  }
   if (st == TDT_OK && p->fused) {
     std::vector<double> tw, pw;
     dst_tables(nx, tw, pw);
@@ -1249,14 +1269,16 @@ tdt_status_t tdt_poisson3d_solve(tdt_poisson3d_t p, const double* F, double* U,
     for (int d = 0; d < 2; ++d) {
       const int64_t N = d == 0 ? ny : nz;
       const int C = tdt::strided_chunks(N);
+      const tdt::StridedTiles g = tdt::strided_tiles(N, P);
+      const double* tb = p->tabs + p->toff[d][(size_t)j];
       tdt::StridedArgs a{};
       a.R = (j == 0 && d == 0) ? fh : W;
       a.O = W;
       a.G = fh;
-      a.iu = p->tabs + p->toff[d][(size_t)j];
+      a.iu = tb;
       a.sc = a.iu + tdt::kStrB * P;
       a.pos = a.sc + tdt::kStrScalarN * P;
-      a.epi = a.pos + 2 * C * P;
+      a.epi = g.K > 1 ? tb + g.n_full + g.n_last + g.n_ends : a.pos + 2 * C * P;
       a.N = N;
       a.P = P;
       a.M = P;
@@ -1271,7 +1293,12 @@ tdt_status_t tdt_poisson3d_solve(tdt_poisson3d_t p, const double* F, double* U,
         a.nb = ny;
         a.ldb = lx;
       }
-      if (tdt::launch_strided(a, stream) != hipSuccess) return TDT_ERR_HIP;
+      if (g.K > 1) {
+        if (tdt::launch_strided_tiled(a, g, tb, p->Yt, p->Gt, stream) != hipSuccess)
+          return TDT_ERR_HIP;
+      } else if (tdt::launch_strided(a, stream) != hipSuccess) {
+        return TDT_ERR_HIP;
+      }
     }
   }
   if (ev) (void)hipEventRecord(ev[2], stream);

@@ -61,6 +61,24 @@ hipError_t launch_strided(const StridedArgs& a, hipStream_t st);
 // value; Y is overwritten with intermediate coefficients.
 hipError_t launch_strided_interface(const double* ends, double* Y, double* Gh, int64_t M,
                                     int64_t P, int64_t K, int64_t nb, hipStream_t st);
+// A system of N > 1024 rows in tiles: K tiles, the last of NL rows; C (CL)
+// blocks per full (last) tile; the sizes of the full tile's tables
+// [iu|sc|pos], the last tile's, and the end values [kTileEndN][P], which lie
+// one after another in that order.
+struct StridedTiles {
+  int64_t K, NL;
+  int C, CL;
+  int64_t n_full, n_last, n_ends;
+};
+StridedTiles strided_tiles(int64_t N, int64_t P);
+// The tables of a tiled system (host, long double; n_full + n_last + n_ends
+// doubles at out), with the tiles' interface pivots checked per class.
+int strided_tiled_tables(int64_t N, int64_t P, const double* tm1, const double* t0,
+                         const double* t1, double* out, double* dominance);
+// The passes of a tiled system: a carries R, O, G, epi, P, M, Mg, ld, nb,
+// ldb; tabs the tables above; Y and Gh hold nb K M 2 doubles each.
+hipError_t launch_strided_tiled(StridedArgs a, const StridedTiles& g, const double* tabs,
+                                double* Y, double* Gh, hipStream_t st);
 // Host tables of P classes (t_-1, t_0, t_1)[k] for systems of order N, in
 // long double: iu [kStrB][P], sc [kStrScalarN][P], pos [2][C][P].  Returns a
 // negative status on a singular class or bad arguments; *dominance is the

@@ -170,20 +170,6 @@ void k_strided(StridedArgs a) {
     const int64_t wbase = col_off(b) + (int64_t)c0 * B * a.ld + s_w;
     const __amdgpu_buffer_rsrc_t rO = wave_rsrc(a.O + wbase);
     const double tm1 = tSC[kStrTM1][sl], t1 = tSC[kStrT1][sl];
-    if constexpr (PASS == 2) {
-      // the tile's outside values moved to the right-hand side:
-      // f_0 - t_-1 x_left and f_last - t_1 x_right
-      if (live) {
-        const int64_t gi = end_idx(b);
-        if (c == 0) q[0] -= tm1 * a.Gh[gi];
-        if (last) {
-          const double gr = t1 * a.Gh[gi + a.M];
-#pragma unroll
-          for (int i = 0; i < B; ++i)
-            if (i == len - 1) q[i] -= gr;
-        }
-      }
-    }
     if (EPI) {
       const double scale = tEP[kEpiScale][sl], cq = tEP[kEpiCQ][sl];
       const double cr = tEP[kEpiCR][sl], cg = tEP[kEpiCG][sl];
@@ -193,6 +179,20 @@ void k_strided(StridedArgs a) {
         w[i] = cr * r + cg * gi;
         q[i] = scale * (r + cq * gi);
         asm volatile("" : "+v"(w[i]));   // formed here: r and g are not kept to the store
+      }
+    }
+    if constexpr (PASS == 2) {
+      // the tile's outside values moved to the right-hand side (after the
+      // epilogue formed it): f_0 - t_-1 x_left and f_last - t_1 x_right
+      if (live) {
+        const int64_t gi = end_idx(b);
+        if (c == 0) q[0] -= tm1 * a.Gh[gi];
+        if (last) {
+          const double gr = t1 * a.Gh[gi + a.M];
+#pragma unroll
+          for (int i = 0; i < B; ++i)
+            if (i == len - 1) q[i] -= gr;
+        }
       }
     }
     // 1. local solve: d_i = q_i / u_i - (t_-1 / u_i) d_{i-1}, y_i = d_i - (t_1 / u_i) y_{i+1};
@@ -382,7 +382,12 @@ hipError_t go_tiles(const StridedArgs& a, hipStream_t st) {
   const unsigned gx = (unsigned)((a.M + SW - 1) / SW);
   const int64_t ncol = a.nb * a.tiles;
   const unsigned gy = (unsigned)(ncol < 65535 ? ncol : 65535);
-  hipLaunchKernelGGL((k_strided<CW, SW, 0, PASS>), dim3(gx, gy), dim3(CW * SW), 0, st, a);
+  if (a.epi && a.G && a.Mg > 0)
+    hipLaunchKernelGGL((k_strided<CW, SW, 2, PASS>), dim3(gx, gy), dim3(CW * SW), 0, st, a);
+  else if (a.epi)
+    hipLaunchKernelGGL((k_strided<CW, SW, 1, PASS>), dim3(gx, gy), dim3(CW * SW), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_strided<CW, SW, 0, PASS>), dim3(gx, gy), dim3(CW * SW), 0, st, a);
   return hipGetLastError();
 }
 
@@ -479,6 +484,51 @@ hipError_t launch_strided_interface(const double* ends, double* Y, double* Gh, i
   return hipGetLastError();
 }
 
+hipError_t launch_strided_tiled(StridedArgs a, const StridedTiles& g, const double* tabs,
+                                double* Y, double* Gh, hipStream_t st) {
+  if (a.M <= 0 || a.nb <= 0) return hipSuccess;
+  const double* R = a.R;
+  double* O = a.O;
+  const double* G = a.G;
+  const int64_t off = (g.K - 1) * kStrTile * a.ld;   // the last tile's first row
+  a.K = g.K;
+  a.ldt = kStrTile * a.ld;
+  a.Y = Y;
+  a.Gh = Gh;
+  auto tables = [&](const double* t) {
+    a.iu = t;
+    a.sc = t + (int64_t)kStrB * a.P;
+    a.pos = a.sc + (int64_t)kStrScalarN * a.P;
+  };
+  auto pass = [&](int which) {
+    a.pass = which;
+    tables(tabs);
+    a.R = R;
+    a.O = O;
+    a.G = G;
+    a.N = kStrTile;
+    a.C = g.C;
+    a.tiles = g.K - 1;
+    a.m0 = 0;
+    hipError_t e = launch_strided(a, st);
+    if (e != hipSuccess) return e;
+    tables(tabs + g.n_full);
+    a.R = R + off;
+    a.O = O + off;
+    a.G = G ? G + off : nullptr;
+    a.N = g.NL;
+    a.C = g.CL;
+    a.tiles = 1;
+    a.m0 = g.K - 1;
+    return launch_strided(a, st);
+  };
+  hipError_t e = pass(1);
+  if (e != hipSuccess) return e;
+  e = launch_strided_interface(tabs + g.n_full + g.n_last, Y, Gh, a.M, a.P, g.K, a.nb, st);
+  if (e != hipSuccess) return e;
+  return pass(2);
+}
+
 hipError_t launch_strided(const StridedArgs& a, hipStream_t st) {
   if (a.M <= 0 || a.nb <= 0 || a.N <= 0) return hipSuccess;
   // buffer offsets below 2^31: a lane reaches at most (4 + 1) * kStrB rows
@@ -494,7 +544,7 @@ hipError_t launch_strided(const StridedArgs& a, hipStream_t st) {
   // favour the wider runs (22.7 ms with 16, 20.6 ms with 32).
   const int C = a.C;
   if (a.pass) {
-    if (a.epi || a.tiles < 1 || a.K < 1 || C > kStrTileChunks ||
+    if (a.tiles < 1 || a.K < 1 || C > kStrTileChunks ||
         (a.pass == 1 && !a.Y) || (a.pass == 2 && !a.Gh) || a.pass > 2)
       return hipErrorInvalidValue;
     return a.pass == 1 ? go_tiles<1>(a, st) : go_tiles<2>(a, st);

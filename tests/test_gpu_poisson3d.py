@@ -2,7 +2,8 @@
 Peaceman-Rachford ADI on every mode's (y, z) plane through the strided line
 solves, inverse transform) against the CPU oracle, through the C ABI: the
 ADI schedule (iteration counts and parameters), the solution on grids up to
-63 x 64 x 65, and at the benchmark size (511^3, 2^9 intervals per side) the
+63 x 64 x 65 and on grids whose lines along y or z are longer than 1024 (the
+tiled line solves), and at the benchmark size (511^3, 2^9 intervals per side) the
 closed-form eigenmode results and the seven-point residual.
 
 Inputs: F ~ N(0, 1); spacings drawn in [0.005, 0.1] (unequal hx, hy, hz)."""
@@ -25,9 +26,11 @@ def _rel2(x, y):
     return float(np.linalg.norm(x - y) / np.linalg.norm(y))
 
 
-# Nx = 127, 255, 1023 take the fused row transform, the others hipFFT's
+# Nx = 127, 255, 1023 take the fused row transform, the others hipFFT's;
+# lines of more than 1024 points run in tiles of 512 (along y, along z, both)
 GRIDS = [(1, 1, 1), (3, 4, 5), (7, 9, 4), (16, 17, 15), (31, 20, 17), (12, 1, 40),
-         (20, 33, 1), (63, 64, 65), (127, 20, 30), (255, 17, 9), (1023, 3, 4)]
+         (20, 33, 1), (63, 64, 65), (127, 20, 30), (255, 17, 9), (1023, 3, 4),
+         (5, 1100, 20), (127, 1030, 3), (7, 20, 1300), (2, 1030, 1029)]
 
 
 @pytest.mark.parametrize("nx,ny,nz", GRIDS)
@@ -100,7 +103,7 @@ def test_poisson3d_benchmark_size():
 def test_poisson3d_errors_and_repeatable():
     tdt = _tdt()
     from paper_1002_2469_amd import _lib
-    for args in ((0, 5, 5, 0.1, 0.1, 0.1, 1e-10), (5, 1025, 5, 0.1, 0.1, 0.1, 1e-10),
+    for args in ((0, 5, 5, 0.1, 0.1, 0.1, 1e-10), (5, 2**24 + 1, 5, 0.1, 0.1, 0.1, 1e-10),
                  (5, 5, 5, -0.1, 0.1, 0.1, 1e-10), (5, 5, 5, 0.1, 0.1, 0.1, 0.0),
                  (5, 5, 5, 0.1, 0.1, 0.1, 1.0), (4000, 1000, 5, 0.1, 0.1, 0.1, 1e-10)):
         with pytest.raises(_lib.TDTError):
