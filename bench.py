@@ -55,11 +55,18 @@ WORKLOADS = ("single_large", "series", "sov", "sov_neumann", "diff", "general", 
              "poisson3d")
 
 
-def kernel_source_hash() -> str:
-    """Hash of the device code (comments and blank lines removed, so that a
-    comment edit does not invalidate the committed counter summary)."""
+# the device sources of each workload's kernels
+SOURCES_TILES = ("paper_1002_2469_amd/csrc/tdt_kernels.hip", "paper_1002_2469_amd/csrc/tdt_internal.h")
+SOURCES_POISSON = ("paper_1002_2469_amd/csrc/tdt_poisson.hip", "paper_1002_2469_amd/csrc/tdt_strided.hip",
+                   "paper_1002_2469_amd/csrc/tdt_strided.h", "paper_1002_2469_amd/csrc/tdt_internal.h")
+
+
+def kernel_source_hash(workload: str = "") -> str:
+    """Hash of the device code of a workload's kernels (comments and blank
+    lines removed, so that a comment edit does not invalidate the committed
+    counter summary)."""
     h = hashlib.sha256()
-    for rel in ("paper_1002_2469_amd/csrc/tdt_kernels.hip", "paper_1002_2469_amd/csrc/tdt_internal.h"):
+    for rel in (SOURCES_POISSON if workload.startswith("poisson") else SOURCES_TILES):
         with open(os.path.join(ROOT, rel)) as f:
             src = f.read()
         src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
@@ -78,7 +85,7 @@ def committed_traffic(workload: str, kernel_key: str, mode: str):
     try:
         with open(path) as f:
             rec = json.load(f)
-        if rec.get("kernel_source_sha") != kernel_source_hash():
+        if rec.get("kernel_source_sha") != kernel_source_hash(workload):
             return None
         return rec["modes"][mode][kernel_key]["hbm_bytes_per_launch"]
     except Exception:
@@ -580,7 +587,7 @@ def main() -> int:
         line["adi_schedule"] = {"iterations_mode_1": int(c[0]), "iterations_last_mode": int(c[-1]),
                                 "mean_iterations": float(c.mean()),
                                 "half_step_launches": 2 * int(c.max())}
-    line["kernel_source_sha"] = kernel_source_hash()
+    line["kernel_source_sha"] = kernel_source_hash(args.workload)
     print(json.dumps(line))
     return 0
 
