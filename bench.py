@@ -9,7 +9,8 @@ interface pass, final pass).  The headline path is float sweeps with double
 residual refinement ('f32_refine', data in and out in double); the all-double
 path ('f64') is timed the same way beside it.
 
-Other workloads (`--workload`): `series` (8192 right-hand sides of N = 8192
+Other workloads (`--workload`): `single_small` (one system of N = 65536,
+T = tridiag{-1, 4, -1}: launch-bound), `series` (8192 right-hand sides of N = 8192
 sharing T = tridiag{-1, 3, -1}), `sov` (2048 separation-of-variables systems,
 N_k log-uniform in [256, 65536], each with its own t_0; one step is a replay
 of the solve captured in a hipGraph), `sov_neumann` (the same batch with
@@ -24,6 +25,12 @@ inverse transforms; path f64) and
 `poisson3d` (the 3D problem of Sec. 3.5 on 511^3 interior points: sine
 transform along x, Peaceman-Rachford ADI on every mode's (y, z) plane with
 strided line solves, inverse transform; path f64).
+
+Launch options: the library's autotuner picks them on the data, unless
+`--shape`, `--whole` or `--wg` fix them (then nothing else is tried, so a
+profiler trace of the run holds one configuration per kernel).  The plan
+creation (the paper's Stage 1, the preliminary step) is timed beside the
+solve (Stage 2).
 
 Prints one JSON line.  `roofline` is for the kernel with the longest average
 duration in the headline path, from HIP events recorded on the solve stream
@@ -51,14 +58,17 @@ if ROOT not in sys.path:
 
 METRIC = "unknowns/s + HBM GB/s (% peak): FP32+refine vs FP64 solve at rel err ≤1e-12"
 HBM_PEAK_GBS = 8000.0
-WORKLOADS = ("single_large", "series", "sov", "sov_neumann", "diff", "general", "poisson2d",
-             "poisson3d")
+WORKLOADS = ("single_large", "single_small", "series", "sov", "sov_neumann", "diff", "general",
+             "poisson2d", "poisson3d")
 
 
 # the device sources of each workload's kernels
-SOURCES_TILES = ("paper_1002_2469_amd/csrc/tdt_kernels.hip", "paper_1002_2469_amd/csrc/tdt_internal.h")
+# (with the host code that decides the launches: tiling, work lists, shapes)
+SOURCES_TILES = ("paper_1002_2469_amd/csrc/tdt_kernels.hip", "paper_1002_2469_amd/csrc/tdt_internal.h",
+                 "paper_1002_2469_amd/csrc/tdt_api.cpp")
 SOURCES_POISSON = ("paper_1002_2469_amd/csrc/tdt_poisson.hip", "paper_1002_2469_amd/csrc/tdt_strided.hip",
-                   "paper_1002_2469_amd/csrc/tdt_strided.h", "paper_1002_2469_amd/csrc/tdt_internal.h")
+                   "paper_1002_2469_amd/csrc/tdt_strided.h", "paper_1002_2469_amd/csrc/tdt_internal.h",
+                   "paper_1002_2469_amd/csrc/tdt_api.cpp")
 
 
 def kernel_source_hash(workload: str = "") -> str:
@@ -103,6 +113,11 @@ def load_workload(name: str, args):
         d.update(kind="series", units=d["N"],
                  desc=f"single_large: one Toeplitz tridiagonal system, N={d['N']}, "
                       f"t=(-0.9, 2.5, -1.1), F~N(0,1) seed 0, double in/out")
+    elif name == "single_small":
+        d = W.single_small(seed=0)
+        d.update(kind="series", units=d["N"],
+                 desc=f"single_small: one Toeplitz tridiagonal system, N={d['N']}, "
+                      f"t=(-1, 4, -1), F~U[-1,1] seed 0, double in/out (launch-bound)")
     elif name == "series":
         d = W.series(seed=0)
         d.update(kind="series", units=d["N"] * d["M"],
@@ -173,12 +188,36 @@ def tile_counts(d, tile):
     return int(sizes[inner > tile].sum()), int(sizes.sum())
 
 
-def run_mode(tdt, d, F, X, mode, steps, warmup, torch, autotune=True):
+def plan_create_ms(tdt, d, mode, reps=3):
+    """The preliminary step (the paper's Stage 1): plan creation on the host
+    in long double plus the blocking upload, median of `reps` creations."""
+    times = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        p = make_plan(tdt, d, mode)
+        times.append((time.perf_counter() - t0) * 1e3)
+        p.close()
+    return statistics.median(times)
+
+
+def run_mode(tdt, d, F, X, mode, steps, warmup, torch, opts=None):
+    """opts None: the library's autotuner picks the work shape and launch
+    options on this data (timed afresh, not from a cache file); otherwise
+    the given options are set and nothing else is tried (one launch
+    configuration, e.g. for a profiler trace)."""
+    stage1_ms = plan_create_ms(tdt, d, mode)
     plan = make_plan(tdt, d, mode)
-    plan.reserve(d.get("M", 1))
-    # the library's autotuner picks the work shape and launch options on
-    # this data (timed afresh, not from a cache file)
-    tuned = plan.autotune(F, X, cache=False) if autotune else None
+    if opts is None:
+        plan.reserve(d.get("M", 1))
+        tuned = plan.autotune(F, X, cache=False)
+    else:
+        for k, v in opts.items():
+            if k != "whole_max_tiles" or d["kind"] == "varlen":
+                plan.set_option(k, v)
+        plan.reserve(d.get("M", 1))
+        tuned = {k: plan.get_option(k) for k in ("shape", "whole_max_tiles", "wg_per_cu")}
+        tuned["fixed"] = True
+    support = plan.green_support()["forward"] if d["kind"] == "series" else (0, 0)
     adj = d.get("adjoint", False)
     gX = gF = gt = None
     if adj:
@@ -242,7 +281,8 @@ def run_mode(tdt, d, F, X, mode, steps, warmup, torch, autotune=True):
     torch.cuda.synchronize()
     ms = start.elapsed_time(stop) / steps
     out = dict(ms=ms, kernels_ms=kern, refine_iters=info["refine_iters"],
-               X=X.cpu().numpy().reshape(-1), tuned=tuned)
+               X=X.cpu().numpy().reshape(-1), tuned=tuned, stage1_ms=stage1_ms,
+               green_support=support)
     if adj:
         out["gF"] = gF.cpu().numpy().reshape(-1)
         out["gt"] = gt.cpu().numpy()
@@ -253,7 +293,9 @@ def run_mode(tdt, d, F, X, mode, steps, warmup, torch, autotune=True):
 
 def run_poisson(tdt, d, F, mode, steps, warmup, torch):
     """A step is one whole 2D solve (transforms and line solves)."""
+    t0 = time.perf_counter()
     solver = tdt.Poisson2D(d["nx"], d["ny"], d["hx"], d["hy"], mode)
+    stage1_ms = (time.perf_counter() - t0) * 1e3
     U = torch.empty_like(F)
     for _ in range(warmup):
         solver.solve(F, U)
@@ -276,14 +318,17 @@ def run_poisson(tdt, d, F, mode, steps, warmup, torch):
     stop.record()
     torch.cuda.synchronize()
     ms = start.elapsed_time(stop) / steps
-    out = dict(ms=ms, kernels_ms=kern, refine_iters=0, X=U.cpu().numpy().reshape(-1), tuned=None)
+    out = dict(ms=ms, kernels_ms=kern, refine_iters=0, X=U.cpu().numpy().reshape(-1), tuned=None,
+               stage1_ms=stage1_ms)
     solver.close()
     return out
 
 
 def run_poisson3d(tdt, d, F, steps, warmup, torch):
     """A step is one whole 3D solve (transforms and all ADI half-steps)."""
+    t0 = time.perf_counter()
     solver = tdt.Poisson3D(d["nx"], d["ny"], d["nz"], d["hx"], d["hy"], d["hz"], d["eps"])
+    stage1_ms = (time.perf_counter() - t0) * 1e3
     U = torch.empty_like(F)
     for _ in range(warmup):
         solver.solve(F, U)
@@ -308,7 +353,7 @@ def run_poisson3d(tdt, d, F, steps, warmup, torch):
     ms = start.elapsed_time(stop) / steps
     counts, _om = solver.schedule()
     out = dict(ms=ms, kernels_ms=kern, refine_iters=0, X=U.cpu().numpy().reshape(-1), tuned=None,
-               counts=counts)
+               counts=counts, stage1_ms=stage1_ms)
     solver.close()
     return out
 
@@ -423,7 +468,13 @@ def main() -> int:
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain device copy of F (counter calibration)")
     ap.add_argument("--no-autotune", action="store_true",
-                    help="time the default work shape instead of the autotuner's choice")
+                    help="time the default launch options instead of the autotuner's choice")
+    ap.add_argument("--shape", type=int, default=None,
+                    help="fixed work shape (no autotuning; with --whole and --wg)")
+    ap.add_argument("--whole", type=int, default=None,
+                    help="fixed whole-system threshold of varlen plans (no autotuning)")
+    ap.add_argument("--wg", type=int, default=None,
+                    help="fixed cap of workgroups per CU (no autotuning)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -455,8 +506,10 @@ def main() -> int:
                 raise SystemExit("poisson3d runs the f64 path only")
             res[mode] = run_poisson3d(tdt, d, F, args.steps, args.warmup, torch)
         else:
-            res[mode] = run_mode(tdt, d, Fm, Xm, mode, args.steps, args.warmup, torch,
-                                 autotune=not args.no_autotune)
+            fixed = {k: v for k, v in (("shape", args.shape), ("whole_max_tiles", args.whole),
+                                       ("wg_per_cu", args.wg)) if v is not None}
+            opts = fixed if (fixed or args.no_autotune) else None
+            res[mode] = run_mode(tdt, d, Fm, Xm, mode, args.steps, args.warmup, torch, opts=opts)
         print(f"[bench] {args.workload} {mode}: {res[mode]['ms']:.4f} ms/step  kernels(ms) "
               f"{json.dumps({k: round(v, 5) for k, v in res[mode]['kernels_ms'].items()})}",
               file=sys.stderr, flush=True)
@@ -481,13 +534,21 @@ def main() -> int:
     # solve in tiles (columns of more than 1024 rows) reads them twice and
     # writes them once (24 B), in one column 16 B
     line_bytes = (24.0 if d.get("ny", 0) > 1024 else 16.0) * U
+    # a series plan whose Green rows decay reads only their supports per tile
+    # in the first pass (tdt_plan_green_support)
+    kf, kl = res[head].get("green_support", (0, 0))
+    if kf + kl > 0 and n_first > 0:
+        tile = _lib.SHAPES[shape][0] * _lib.SHAPES[shape][1]
+        n_first = (n_first // tile) * (kf + kl)
     per_launch = {"first_pass": 8.0 * n_first, "final_pass": 16.0 * n_final,
                   "bwd_first_pass": 8.0 * n_first, "bwd_final_pass": 24.0 * n_final,
                   "line_solve": line_bytes if d["kind"] == "poisson" else 0.0,
                   "forward_transform": 16.0 * U if d["kind"] in ("poisson", "poisson3d") else 0.0,
                   "inverse_transform": 16.0 * U if d["kind"] in ("poisson", "poisson3d") else 0.0,
                   "adi": adi_bytes(d, res[head]["counts"]) if d["kind"] == "poisson3d" else 0.0}
-    names = {"first_pass": ("k_beta<double> (Green-row tile summaries, first pass)"
+    names = {"first_pass": (f"k_beta_ends<double> (tile summaries from the Green rows' "
+                            f"supports, {kf} + {kl} rows per tile)" if kf + kl > 0 else
+                            "k_beta<double> (Green-row tile summaries, first pass)"
                             if d["kind"] == "series" else
                             "k_gtile<double, SUMMARY> (general matrix, tile summaries)"
                             if d["kind"] == "general" else
@@ -549,6 +610,7 @@ def main() -> int:
     def path_record(mode):
         r = res[mode]
         return {"value": U / (r["ms"] * 1e-3), "unit": "unknowns/s", "ms_per_step": r["ms"],
+                "stage1_ms": r.get("stage1_ms"),
                 "kernels_ms": {k: round(v, 6) for k, v in r["kernels_ms"].items()},
                 "rel_err_vs_oracle": err_of(mode), "refine_iters": r["refine_iters"],
                 "tuned": r["tuned"]}
@@ -580,6 +642,11 @@ def main() -> int:
         "paths": {m: path_record(m) for m in modes},
         "cpu_baseline": cpu,
     }
+    if cpu is not None:
+        cpu["host_cores"] = len(os.sched_getaffinity(0))
+    # the paper's Stage 1 (preliminary step) beside Stage 2 (the solve)
+    line["stage1_ms"] = res[head].get("stage1_ms")
+    line["first_pass_bytes_per_launch"] = per_launch["first_pass"]
     if "f64" in res and head != "f64":
         line["speedup_vs_f64"] = res["f64"]["ms"] / res[head]["ms"]
     if d["kind"] == "poisson3d":

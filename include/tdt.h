@@ -201,7 +201,11 @@ tdt_status_t tdt_solve_strided(tdt_plan_t plan, const double *F, double *X, int6
  * here, blocking).  Errors: sizes
  * < 1 or Nx Ny > 2^31, non-positive or non-finite spacings, another dtype ->
  * TDT_ERR_INVALID_ARG; allocation -> TDT_ERR_OOM; an FFT plan failure ->
- * TDT_ERR_HIP. */
+ * TDT_ERR_HIP; TDT_F32_REFINE when a mode system's condition number (closed
+ * form, largest for the lowest mode: about 0.2 (Ny+1)^2 on a square grid)
+ * exceeds 8e6, where float sweeps contract the refinement too slowly to
+ * reach double accuracy (eq. (34)'s error growth bounds what a float solve
+ * contributes) -> TDT_ERR_NOT_CONVERGED, before anything is allocated. */
 typedef struct tdt_poisson_s *tdt_poisson_t;
 tdt_status_t tdt_poisson2d_create(int64_t nx, int64_t ny, double hx, double hy,
                                   tdt_dtype_t dtype, tdt_poisson_t *out);
@@ -289,9 +293,11 @@ tdt_status_t tdt_plan_reserve(tdt_plan_t plan, int64_t M_max);
 tdt_status_t tdt_solve(tdt_plan_t plan, const void *F, void *X, int64_t M,
                        hipStream_t stream);
 
-/* Solve every system of a varlen plan: F, X device, packed by the plan's
- * offsets, element type of the plan's dtype.  One launch sequence for all
- * systems; systems are processed largest first.  Errors as tdt_solve. */
+/* Solve every system of a varlen plan (the series of Sec. 3.2: one system
+ * per Fourier mode after separating variables, each mode with its own t_0
+ * and, here, its own size): F, X device, packed by the plan's offsets,
+ * element type of the plan's dtype.  One launch sequence for all systems;
+ * systems are processed largest first.  Errors as tdt_solve. */
 tdt_status_t tdt_solve_varlen(tdt_plan_t plan, const void *F, void *X,
                               hipStream_t stream);
 
@@ -317,7 +323,10 @@ tdt_status_t tdt_plan_destroy(tdt_plan_t plan);
 /* Static string for a status code. */
 const char *tdt_status_string(tdt_status_t status);
 
-/* Facts about a plan (any pointer may be NULL).  For TDT_F32_REFINE solves
+/* Facts about a plan (any pointer may be NULL): the dominance ratio of
+ * Sec. 3.4 (eqs. (32)-(33), the condition under which the method's rounding
+ * errors stay bounded), the condition number, and the refinement record.
+ * For TDT_F32_REFINE solves
  * since the previous call that asked for them (read back from the device, so
  * asking synchronises the device; the record is then cleared):
  * *n_refine_iters = the most float solves any tile needed (0 when no such
@@ -354,6 +363,29 @@ tdt_status_t tdt_block_constants(double t_m1, double t_0, double t_1, int B,
  * series plan uses them for its tiles (L = the tile length). */
 tdt_status_t tdt_green_rows(double t_m1, double t_0, double t_1, int64_t L,
                             double *first, double *last);
+
+/* Host-only: where those two rows carry their mass.  Under diagonal
+ * dominance the entries of T_L^{-1} fall off geometrically away from the
+ * diagonal (Sec. 3.4, eqs. (32)-(33)), so the first pass of a series plan,
+ * whose tile summaries are the dot products of eq. (13) of a tile's right-hand
+ * side with these rows, reads only the rows of the tile that matter:
+ * *kf = the fewest leading entries of the first row and *kl = the fewest
+ * trailing entries of the last row such that the dropped entries' 1-norm is
+ * at most 2^-60 of the row's (computed in long double).  The dropped part of
+ * a summary is then at most 2^-60 |row|_1 |F|_inf, below the rounding of the
+ * dot product.  Errors: L outside [1, 2^26], non-finite t's, null outputs ->
+ * TDT_ERR_INVALID_ARG; a zero pivot -> TDT_ERR_SINGULAR. */
+tdt_status_t tdt_green_support(double t_m1, double t_0, double t_1, int64_t L, int64_t *kf,
+                               int64_t *kl);
+
+/* What the first pass of a plan reads per full tile: rows4[0], rows4[1] =
+ * the leading and trailing rows of each tile the forward solve's summaries
+ * read (tdt_green_support rounded up to multiples of 64), rows4[2], rows4[3]
+ * the same for the adjoint (the rows of T^T); 0, 0 when the pass reads whole
+ * tiles (the supports would cover a quarter of the tile or more: weak
+ * dominance) or the plan has no such pass (one tile, varlen, general or
+ * strided plans).  Errors: null arguments -> TDT_ERR_INVALID_ARG. */
+tdt_status_t tdt_plan_green_support(tdt_plan_t plan, int64_t *rows4);
 
 /* Host-only: the interface merge of two adjacent segments, in double, as the
  * kernels compute it.  seg = (y_first, y_last, phi_first, phi_last,

@@ -23,7 +23,7 @@ from . import _lib
 from ._lib import DTYPES, TDTError, build
 
 __all__ = ["Plan", "VarlenPlan", "GeneralPlan", "StridedPlan", "Poisson2D", "Poisson3D", "solve", "solve_varlen", "TridiagToeplitzSolve", "block_constants",
-           "green_rows", "segment_merge", "build_info", "build", "TDTError"]
+           "green_rows", "green_support", "segment_merge", "build_info", "build", "TDTError"]
 
 
 def _torch():
@@ -87,6 +87,15 @@ class _PlanBase:
         _lib.check(_lib.lib().tdt_plan_profile_read(self._h, ms.ctypes.data_as(ctypes.c_void_p),
                                                     ctypes.byref(n)), "tdt_plan_profile_read")
         return dict(first_pass_ms=ms[0], interface_ms=ms[1], final_ms=ms[2], solves=n.value)
+
+    def green_support(self) -> dict:
+        """Rows per full tile the first pass reads from the head and the tail
+        of each tile ((0, 0): whole tiles, or no such pass), for the forward
+        solve and the adjoint."""
+        rows = np.zeros(4, dtype=np.int64)
+        _lib.check(_lib.lib().tdt_plan_green_support(self._h, rows.ctypes.data_as(ctypes.c_void_p)),
+                   "tdt_plan_green_support")
+        return dict(forward=(int(rows[0]), int(rows[1])), adjoint=(int(rows[2]), int(rows[3])))
 
     def set_option(self, name: str, value: int):
         """Option of tdt_option_t: 'whole_max_tiles', 'wg_per_cu',
@@ -627,6 +636,17 @@ def green_rows(t_m1: float, t_0: float, t_1: float, L: int):
                                          last.ctypes.data_as(ctypes.c_void_p)),
                "tdt_green_rows")
     return first, last
+
+
+def green_support(t_m1: float, t_0: float, t_1: float, L: int):
+    """Host-only: (kf, kl), the fewest leading entries of the first Green row
+    and trailing entries of the last that hold all but 2^-60 of each row's
+    1-norm (the supports the first pass reads)."""
+    kf, kl = ctypes.c_int64(0), ctypes.c_int64(0)
+    _lib.check(_lib.lib().tdt_green_support(float(t_m1), float(t_0), float(t_1), int(L),
+                                            ctypes.byref(kf), ctypes.byref(kl)),
+               "tdt_green_support")
+    return kf.value, kl.value
 
 
 def segment_merge(left, right) -> np.ndarray:

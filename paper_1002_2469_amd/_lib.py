@@ -14,10 +14,6 @@ import subprocess
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _ROOT = os.path.dirname(_HERE)
 LIB_PATH = os.path.join(_HERE, "libtdt.so")
-# An alternative build of the same sources may be loaded instead (tuning
-# experiments); the tests and the bench use the in-tree library.
-if os.environ.get("TDT_LIB_PATH"):
-    LIB_PATH = os.environ["TDT_LIB_PATH"]
 SOURCES = [os.path.join(_HERE, "csrc", "tdt_kernels.hip"), os.path.join(_HERE, "csrc", "tdt_api.cpp"),
            os.path.join(_HERE, "csrc", "tdt_poisson.hip"), os.path.join(_HERE, "csrc", "tdt_strided.hip")]
 HEADER = os.path.join(_ROOT, "include", "tdt.h")
@@ -46,7 +42,7 @@ EXPORTS = [
     "tdt_poisson2d_profile_read", "tdt_plan_strided_create",
     "tdt_solve_strided", "tdt_poisson3d_create", "tdt_poisson3d_solve", "tdt_poisson3d_schedule",
     "tdt_poisson3d_profile", "tdt_poisson3d_profile_read", "tdt_poisson3d_destroy",
-    "tdt_adi_parameters",
+    "tdt_adi_parameters", "tdt_green_support", "tdt_plan_green_support",
 ]
 
 # tdt_option_t
@@ -57,17 +53,28 @@ TUNE_NO_CACHE = 1
 TUNE_FORCE = 2
 
 
-def build_command(out: str = LIB_PATH) -> list:
-    return ["hipcc", "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
+def _flags() -> list:
+    return ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            "-I", os.path.join(_ROOT, "include"), "-I", os.path.join(_HERE, "csrc"),
-            *SOURCES, "-o", out, "-L/opt/rocm/lib", "-lhipfft"]
+            "-I", os.path.join(_ROOT, "include"), "-I", os.path.join(_HERE, "csrc")]
 
 
 def build() -> str:
-    """Compile libtdt.so for gfx950 in-tree (always recompiles)."""
-    tmp = LIB_PATH + ".tmp"
-    subprocess.check_call(build_command(tmp))
+    """Compile libtdt.so for gfx950 in-tree (always recompiles): each source
+    to an object file in parallel, then one link."""
+    import tempfile
+    with tempfile.TemporaryDirectory(prefix="tdt_build_") as tmpd:
+        objs, procs = [], []
+        for src in SOURCES:
+            obj = os.path.join(tmpd, os.path.basename(src) + ".o")
+            objs.append(obj)
+            procs.append(subprocess.Popen(["hipcc", *_flags(), "-c", src, "-o", obj]))
+        rcs = [q.wait() for q in procs]
+        if any(rcs):
+            raise subprocess.CalledProcessError(max(rcs, key=abs), "hipcc -c")
+        tmp = LIB_PATH + ".tmp"
+        subprocess.check_call(["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", *objs,
+                               "-o", tmp, "-L/opt/rocm/lib", "-lhipfft"])
     os.replace(tmp, LIB_PATH)
     return LIB_PATH
 
@@ -121,6 +128,8 @@ def lib():
         "tdt_block_constants": [d, d, d, i32, p],
         "tdt_segment_merge": [p, p, p],
         "tdt_green_rows": [d, d, d, i64, p, p],
+        "tdt_green_support": [d, d, d, i64, ctypes.POINTER(i64), ctypes.POINTER(i64)],
+        "tdt_plan_green_support": [p, p],
         "tdt_plan_profile": [p, i32],
         "tdt_plan_profile_read": [p, p, ctypes.POINTER(i64)],
         "tdt_build_info": [ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),

@@ -70,6 +70,8 @@ struct tdt_plan_s {
   double* dtab64[2] = {nullptr, nullptr};
   float* dtab32[2] = {nullptr, nullptr};
   double* dgreen[2] = {nullptr, nullptr};   // series with several tiles: [2][L]
+  // rows of a tile the first pass reads from the head and the tail (0: all)
+  int green_kf[2] = {0, 0}, green_kl[2] = {0, 0};
   double* dttab[2] = {nullptr, nullptr};    // per tile position table [2][ttab_n]
   int64_t ttab_n = 0;
   // varlen launch lists
@@ -158,8 +160,10 @@ bool segment_ends(ld a, ld b, ld c, int64_t L, ld out[4]) {
 
 // First and last row of T_L^{-1} (T = tridiag{a, b, c} of order L): the rows
 // r solve T^T r = e_0 and T^T r = e_{L-1}, T^T = tridiag{c, b, a}.
-bool green_rows(ld a, ld b, ld c, int64_t L, double* first, double* last) {
-  std::vector<ld> cpv((size_t)L), r1((size_t)L), r2((size_t)L);
+bool green_rows_ld(ld a, ld b, ld c, int64_t L, std::vector<ld>& r1, std::vector<ld>& r2) {
+  std::vector<ld> cpv((size_t)L);
+  r1.assign((size_t)L, 0.0L);
+  r2.assign((size_t)L, 0.0L);
   ld u = b;
   if (u == 0.0L) return false;
   cpv[0] = a / u;                 // super-diagonal of T^T is a
@@ -176,12 +180,52 @@ bool green_rows(ld a, ld b, ld c, int64_t L, double* first, double* last) {
     r1[i] -= cpv[i] * r1[i + 1];
     r2[i] -= cpv[i] * r2[i + 1];
   }
+  return true;
+}
+
+bool green_rows(ld a, ld b, ld c, int64_t L, double* first, double* last) {
+  std::vector<ld> r1, r2;
+  if (!green_rows_ld(a, b, c, L, r1, r2)) return false;
   for (int64_t i = 0; i < L; ++i) {
     first[i] = (double)r1[i];
     last[i] = (double)r2[i];
     if (!std::isfinite(first[i]) || !std::isfinite(last[i])) return false;
   }
   return true;
+}
+
+// Where the two Green rows carry their mass (the decay of the inverse's
+// entries away from the diagonal under dominance, Sec. 3.4): kf = the
+// fewest leading entries of the first row, kl = the fewest trailing entries
+// of the last row, such that the rest of the row has 1-norm at most
+// kGreenDrop times the row's.  Sums in long double from the small end.
+constexpr long double kGreenDrop = 0x1p-60L;
+void green_support(const std::vector<ld>& r1, const std::vector<ld>& r2, int64_t& kf,
+                   int64_t& kl) {
+  const int64_t L = (int64_t)r1.size();
+  ld n1 = 0.0L, n2 = 0.0L;
+  for (int64_t i = L - 1; i >= 0; --i) n1 += std::fabs(r1[i]);
+  for (int64_t i = 0; i < L; ++i) n2 += std::fabs(r2[i]);
+  // first row: grow the dropped tail from the far end while it stays small
+  ld drop = 0.0L;
+  kf = L;
+  while (kf > 1 && drop + std::fabs(r1[kf - 1]) <= kGreenDrop * n1) drop += std::fabs(r1[--kf]);
+  drop = 0.0L;
+  kl = L;
+  while (kl > 1 && drop + std::fabs(r2[L - kl]) <= kGreenDrop * n2) drop += std::fabs(r2[L - kl--]);
+}
+
+// The supports the first pass of a series plan uses: kf, kl rounded up to
+// the kernel's 64-row runs, or 0 (read whole tiles) when they would cover a
+// quarter of the tile or more.
+void green_support_rounded(int64_t L, int64_t kf, int64_t kl, int& rkf, int& rkl) {
+  const int64_t f = (kf + 63) / 64 * 64, l = (kl + 63) / 64 * 64;
+  if (4 * (f + l) > L) {
+    rkf = rkl = 0;
+  } else {
+    rkf = (int)f;
+    rkl = (int)l;
+  }
 }
 
 struct SegLD {
@@ -593,10 +637,21 @@ tdt_status_t finish_plan(tdt_plan_s* p, const std::vector<double>& tm1,
       fs += p->hsys[dir][s].ntiles + (p->quasi ? 2 : 0);
     }
     p->vfslots = fs;
+    p->green_kf[dir] = p->green_kl[dir] = 0;
     if (!p->varlen && needs_interface(p->hsys[dir][0])) {
       std::vector<double> g(2 * (size_t)kTile);
       const double a = dir == 0 ? tm1[0] : t1[0], c = dir == 0 ? t1[0] : tm1[0];
-      if (!green_rows(a, t0[0], c, kTile, g.data(), g.data() + kTile)) return TDT_ERR_SINGULAR;
+      std::vector<ld> r1, r2;
+      if (!green_rows_ld(a, t0[0], c, kTile, r1, r2)) return TDT_ERR_SINGULAR;
+      for (int64_t i = 0; i < kTile; ++i) {
+        g[(size_t)i] = (double)r1[(size_t)i];
+        g[(size_t)(kTile + i)] = (double)r2[(size_t)i];
+        if (!std::isfinite(g[(size_t)i]) || !std::isfinite(g[(size_t)(kTile + i)]))
+          return TDT_ERR_SINGULAR;
+      }
+      int64_t kf = 0, kl = 0;
+      green_support(r1, r2, kf, kl);
+      green_support_rounded(kTile, kf, kl, p->green_kf[dir], p->green_kl[dir]);
       tdt_status_t sg = dev_upload(&p->dgreen[dir], g.data(), g.size());
       if (sg != TDT_OK) return sg;
     }
@@ -972,6 +1027,7 @@ tdt_status_t run(tdt_plan_s* p, int dir, const void* F, void* X, const void* Xfw
     const SysDesc& D0 = p->hsys[0][0];
     const int64_t nt = D0.ntiles;
     L.green = nullptr;
+    L.green_kf = L.green_kl = 0;
     L.gen_green = p->dggreen[dir];
     L.p1_items = L.fin_items = nullptr;
     L.grid_items = L.sys_items = L.sys_bins = nullptr;
@@ -997,6 +1053,7 @@ tdt_status_t run(tdt_plan_s* p, int dir, const void* F, void* X, const void* Xfw
     fslots = 0;
   } else if (p->varlen) {
     L.green = nullptr;
+    L.green_kf = L.green_kl = 0;
     L.n_beta = L.n_last = 0;
     L.nfull = 0;
     L.p1_items = p->dp1;
@@ -1024,6 +1081,8 @@ tdt_status_t run(tdt_plan_s* p, int dir, const void* F, void* X, const void* Xfw
     L.n_bins = 0;
     L.n_sys = 0;
     L.green = p->dgreen[dir];
+    L.green_kf = p->green_kf[dir];
+    L.green_kl = p->green_kl[dir];
     L.nfull = (int)(D0.n % p->L == 0 ? nt : nt - 1);
     L.n_beta = itf ? M * L.nfull : 0;
     L.n_last = (itf && D0.n % p->L != 0) ? M : 0;
@@ -1116,7 +1175,8 @@ int strided_tables(int64_t N, int64_t P, const double* tm1, const double* t0, co
 
 StridedTiles strided_tiles(int64_t N, int64_t P) {
   StridedTiles g{};
-  g.K = (N + kStrTile - 1) / kStrTile;
+  // one column up to kStrMaxChunks blocks, tiles of kStrTile rows beyond
+  g.K = N > (int64_t)kStrMaxChunks * kStrB ? (N + kStrTile - 1) / kStrTile : 1;
   g.NL = N - (g.K - 1) * kStrTile;
   g.C = strided_chunks(g.K > 1 ? kStrTile : N);
   g.CL = strided_chunks(g.NL);
@@ -1788,6 +1848,25 @@ tdt_status_t tdt_green_rows(double t_m1, double t_0, double t_1, int64_t L, doub
   if (!first || !last || L < 1 || L > ((int64_t)1 << 26) || !finite3(t_m1, t_0, t_1))
     return TDT_ERR_INVALID_ARG;
   return green_rows(t_m1, t_0, t_1, L, first, last) ? TDT_OK : TDT_ERR_SINGULAR;
+}
+
+tdt_status_t tdt_green_support(double t_m1, double t_0, double t_1, int64_t L, int64_t* kf,
+                               int64_t* kl) {
+  if (!kf || !kl || L < 1 || L > ((int64_t)1 << 26) || !finite3(t_m1, t_0, t_1))
+    return TDT_ERR_INVALID_ARG;
+  std::vector<ld> r1, r2;
+  if (!green_rows_ld(t_m1, t_0, t_1, L, r1, r2)) return TDT_ERR_SINGULAR;
+  green_support(r1, r2, *kf, *kl);
+  return TDT_OK;
+}
+
+tdt_status_t tdt_plan_green_support(tdt_plan_t p, int64_t* rows4) {
+  if (!p || !rows4) return TDT_ERR_INVALID_ARG;
+  for (int dir = 0; dir < 2; ++dir) {
+    rows4[2 * dir] = p->green_kf[dir];
+    rows4[2 * dir + 1] = p->green_kl[dir];
+  }
+  return TDT_OK;
 }
 
 tdt_status_t tdt_segment_merge(const double* l, const double* r, double* out) {

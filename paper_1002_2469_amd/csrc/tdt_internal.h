@@ -106,6 +106,7 @@ struct LaunchSet {
   // sweep-based pass over the partial last tile of each right-hand side
   // (n_last items); varlen plans use the sweep-based pass over p1_items
   const double* green;     // [2][L] or null
+  int green_kf, green_kl;  // supports of the Green rows (multiples of 64), or 0: whole tile
   int64_t n_beta, n_last;
   int nfull;
   int max_ntiles;          // most tiles of any system (selects the interface kernel)

@@ -1331,6 +1331,73 @@ __global__ __launch_bounds__(kBetaNT) void k_beta(BetaArgs<Tio> A) {
   }
 }
 
+// The same first pass when the two Green rows decay fast (a diagonally
+// dominant T, Sec. 3.4: the entries fall geometrically away from the row's
+// own end): the plan has found the head of the first row (kf entries) and
+// the tail of the last row (kl entries) outside which a row's mass is below
+// 2^-60 of its 1-norm, so each summary reads only those rows of its tile.
+// What is dropped is at most 2^-60 |row|_1 |F|_inf, below the rounding of
+// the dot product itself.  One wavefront per tile; lanes stride the head and
+// the tail 64 rows at a time (kf, kl are multiples of 64), and the two
+// lane sums are added by a fixed butterfly, so results are repeatable.
+constexpr int kEndsNT = 256;
+constexpr int kEndsNW = kEndsNT / 64;
+template <typename Tio>
+struct BetaEndsArgs {
+  const Tio* __restrict__ F;
+  const SysDesc* __restrict__ sys;
+  const double* __restrict__ green;   // [2][kTile]: first row, last row
+  int64_t nitems;                     // right-hand sides x full tiles per right-hand side
+  int nfull;                          // full tiles per right-hand side
+  int kf, kl;                         // head of the first row, tail of the last row
+  double* __restrict__ summ;          // [slot][2]
+};
+
+template <class SH, typename Tio>
+__global__ __launch_bounds__(kEndsNT) void k_beta_ends(BetaEndsArgs<Tio> A) {
+  TDT_SHAPE(SH)
+  constexpr int U = 4;   // loads in flight per lane and row run
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const SysDesc S0 = load_sys(A.sys, 0);
+  const int nf = A.kf / 64, nl = A.kl / 64;
+  const double* gf = A.green + lane;
+  const double* gl = A.green + 2 * kTile - A.kl + lane;
+  for (int64_t it = (int64_t)blockIdx.x * kEndsNW + w; it < A.nitems;
+       it += (int64_t)gridDim.x * kEndsNW) {
+    const int64_t m = it / A.nfull;
+    const int t = (int)(it - m * A.nfull);
+    const Tio* head = A.F + S0.off + m * S0.stride + (int64_t)t * kTile + lane;
+    const Tio* tail = head + kTile - A.kl;
+    double s1 = 0.0, s2 = 0.0;
+    for (int j0 = 0; j0 < nf; j0 += U) {
+      double v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = j0 + u < nf ? (double)head[(j0 + u) * 64] : 0.0;
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (j0 + u < nf) s1 += v[u] * gf[(j0 + u) * 64];
+    }
+    for (int j0 = 0; j0 < nl; j0 += U) {
+      double v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = j0 + u < nl ? (double)tail[(j0 + u) * 64] : 0.0;
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (j0 + u < nl) s2 += v[u] * gl[(j0 + u) * 64];
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+      s1 += __shfl_xor(s1, d, 64);
+      s2 += __shfl_xor(s2, d, 64);
+    }
+    if (lane == 0) {
+      const int64_t sl = tile_slot(S0, m, t, false);
+      A.summ[2 * sl] = s1;
+      A.summ[2 * sl + 1] = s2;
+    }
+  }
+}
 
 // First pass of a general double series plan: the same Green-row dot
 // products as k_beta, with the rows of each tile's own inverse
@@ -2200,6 +2267,20 @@ static void launch_beta(const LaunchSet& L, const Tio* F, hipStream_t st) {
   hipLaunchKernelGGL(kern, dim3(grid), dim3(kBetaNT), 0, st, B);
 }
 
+// The first pass over the Green rows' supports only (the plan found them
+// short enough): one wavefront per tile, as many workgroups as the tiles
+// need up to the resident count.
+template <class SH, typename Tio>
+static void launch_beta_ends(const LaunchSet& L, const Tio* F, hipStream_t st) {
+  auto kern = k_beta_ends<SH, Tio>;
+  static int per_cu = resident_per_cu(kern, kEndsNT);
+  const int64_t cap = grid_cap(per_cu, L.wg_per_cu);
+  BetaEndsArgs<Tio> B{F, L.sys, L.green, L.n_beta, L.nfull, L.green_kf, L.green_kl, L.summ};
+  const int64_t want = (L.n_beta + kEndsNW - 1) / kEndsNW;
+  const unsigned grid = (unsigned)(want < cap ? want : cap);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kEndsNT), 0, st, B);
+}
+
 // Interface pass across tiles: the affine variant sized for the most tiled
 // system (up to 16384 tiles), beyond that the segment-merge kernel.  The
 // plan lays out its workspace slots for the same choice (interface_run).
@@ -2246,7 +2327,12 @@ static hipError_t run_solve(const LaunchSet& L, const void* F, void* X, const vo
   using Ts = typename std::conditional<REFINE, double, Tc>::type;
   if (L.n_p1 > 0) {
     if (L.green) {
-      if (L.n_beta > 0) launch_beta<SH, Tio>(L, static_cast<const Tio*>(F), st);
+      if (L.n_beta > 0) {
+        if (L.green_kf > 0)
+          launch_beta_ends<SH, Tio>(L, static_cast<const Tio*>(F), st);
+        else
+          launch_beta<SH, Tio>(L, static_cast<const Tio*>(F), st);
+      }
       if (L.n_last > 0) {
         A.items = nullptr;
         launch_tile<SH, Tio, Ts, false, true, false, QUASI>(A, L.n_last, 0, 1, L.wg_per_cu, st);

@@ -704,6 +704,9 @@ void destroy_poisson(tdt_poisson_s* p) {
 
 extern "C" {
 
+// Largest condition number of a mode system a TDT_F32_REFINE handle accepts.
+constexpr double kRefineKappaMax = 8.0e6;
+
 tdt_status_t tdt_poisson2d_create(int64_t nx, int64_t ny, double hx, double hy,
                                   tdt_dtype_t dtype, tdt_poisson_t* out) {
   if (!out) return TDT_ERR_INVALID_ARG;
@@ -728,6 +731,23 @@ tdt_status_t tdt_poisson2d_create(int64_t nx, int64_t ny, double hx, double hy,
     t0[(size_t)k - 1] = (double)(2.0L + (long double)hy * hy * mu);
   }
   for (int64_t k = 0; k <= nx; ++k) off[(size_t)k] = k * ny;
+  // Float sweeps contract a refinement by about c kappa_2 2^-24 per step.
+  // The mode systems' condition numbers are known in closed form (spectrum
+  // t_0 - 2 cos(j pi / (Ny+1))); the lowest mode's is the largest.  Above
+  // kRefineKappaMax the contraction is too slow to reach the double tier
+  // (measured: systems up to kappa_2 = 6.8e6 reach it, the lowest modes of
+  // the 8191 x 8191 grid, kappa_2 = 1.4e7, do not), so such a plan is refused.
+  if (dtype == TDT_F32_REFINE) {
+    const long double cs = std::cos(pi / (long double)(ny + 1));
+    for (int64_t k = 0; k < nx; ++k) {
+      const long double lo = (long double)t0[(size_t)k] - 2.0L * cs;
+      const long double hi = (long double)t0[(size_t)k] + 2.0L * cs;
+      if (!(lo > 0.0L) || (double)(hi / lo) > kRefineKappaMax) {
+        delete p;
+        return TDT_ERR_NOT_CONVERGED;
+      }
+    }
+  }
   const int64_t n = nx + 1, K = n / 2 + 1;
   p->fused = dst_supported(nx);
   // In float64 with the fused row transform, the mode systems are solved in

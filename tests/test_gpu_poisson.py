@@ -95,6 +95,21 @@ def test_poisson_benchmark_size(n, dtype):
     assert oracle.rel_err(P2.laplacian(U, h, h), F) <= t
 
 
+def test_poisson_refinement_refused_where_it_cannot_converge():
+    """At 8191 x 8191 the lowest mode's line system has cond_2 = 1.4e7, above
+    the limit where float sweeps still contract a refinement to double
+    accuracy: the f32_refine handle is refused with TDT_ERR_NOT_CONVERGED
+    (the f64 one is made); at 2047 x 2047 (cond_2 = 8.5e5) it is made."""
+    tdt = _tdt()
+    from paper_1002_2469_amd import _lib
+    h = 1.0 / 8192
+    with pytest.raises(_lib.TDTError) as e:
+        tdt.Poisson2D(8191, 8191, h, h, "f32_refine")
+    assert e.value.status == _lib.TDT_ERR_NOT_CONVERGED
+    tdt.Poisson2D(8191, 8191, h, h, "f64").close()
+    tdt.Poisson2D(2047, 2047, 1.0 / 2048, 1.0 / 2048, "f32_refine").close()
+
+
 def test_poisson_errors_and_repeatable():
     tdt = _tdt()
     from paper_1002_2469_amd import _lib

@@ -2,9 +2,11 @@
 i of system s of batch b at b*ldb + i*ld + s) against the CPU oracle,
 through the C ABI: orders 1 to 1024 (every block count, full and ragged last
 blocks), one to hundreds of adjacent systems with their own matrices, both
-batch layouts, padded rows, in place; longer systems in tiles of 1024 rows
-(a last tile of 1 to 1024 rows, up to 8191 rows, weakly dominant classes);
-plus errors, bitwise repeatability and hipGraph replay.
+batch layouts, padded rows, in place (orders up to 1024 are one column per
+workgroup, 33 to 64 blocks in the widest kernel); longer systems in tiles
+of 512 rows (a last tile of 1 to 512 rows, up to 8191 rows, weakly dominant
+classes); plus errors, bitwise repeatability and hipGraph replay, with and
+without a reservation.
 
 Inputs: F ~ N(0, 1); classes with t_0 ~ U[2.5, 4], t_+-1 ~ U[-1, -0.5]
 independently (dominance >= 1.25), and the weakly dominant line operators
@@ -142,8 +144,8 @@ TILED = [(1025, "dominant"), (1040, "adi"), (2048, "dominant"), (2049, "adi"),
 
 @pytest.mark.parametrize("n,kind", TILED)
 def test_strided_tiled_orders(n, kind):
-    """Systems longer than one column: full tiles of 1024 rows and a last
-    tile of 1, 16, 1024, 1, 952, 1 and 1023 rows."""
+    """Systems longer than one column: full tiles of 512 rows and a last
+    tile of 1, 16, 512, 1, 440, 1 and 511 rows."""
     tdt = _tdt()
     rng = np.random.default_rng(300 + n)
     P = 37
@@ -276,3 +278,35 @@ def test_strided_graph_replay():
         torch.cuda.synchronize()
         assert np.array_equal(to_host(X), ref), r
         plan.solve(F)
+
+
+@pytest.mark.parametrize("n", [1000, 1024])
+def test_strided_one_column_captures_without_reserve(n):
+    """Orders up to 1024 run as one column per workgroup with no workspace, so
+    a hipGraph capture needs no tdt_plan_reserve; replays equal the eager
+    solve bit for bit, and the result matches the oracle."""
+    import torch
+    tdt = _tdt()
+    rng = np.random.default_rng(40 + n)
+    M = 40
+    tm1, t0, t1 = classes(rng, M, "adi")
+    plan = tdt.StridedPlan(n, tm1, t0, t1)
+    Fh = rng.standard_normal((n, M))
+    F = to_dev(Fh)
+    X = torch.empty_like(F)
+    print(f"[case] strided capture without reserve N={n}", flush=True)
+    ref = to_host(plan.solve(F))
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            plan.solve(F, X, stream=s)
+    for r in range(3):
+        X.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host(X), ref), r
+    o, idx = oracle_strided(Fh, n, M, M, 1, 0, tm1, t0, t1)
+    check(ref, o, idx, n, M, 1, tm1, t0, t1)

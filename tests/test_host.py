@@ -201,3 +201,50 @@ def test_adi_parameters_match_the_oracle():
     p = out.ctypes.data_as(ctypes.c_void_p)
     for a, b, J in ((0.0, 1.0, 2), (2.0, 1.0, 2), (1.0, 2.0, 0), (1.0, 2.0, 401)):
         assert L.tdt_adi_parameters(a, b, J, p, None) == _lib.TDT_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("t", [(-0.9, 2.5, -1.1), (-1.1, 2.5, -0.9), (-1.0, 4.0, -1.0),
+                               (-1.0, 2.01, -1.0), (0.3, -1.0, 0.45), (1.0, -2.0000006, 1.0)])
+@pytest.mark.parametrize("L", [8192, 4096, 1000, 3])
+def test_green_support_against_oracle_rows(t, L):
+    """The supports of the first and last Green rows (Sec. 3.4's decay of the
+    inverse's entries): the dropped entries' 1-norm is at most 2^-60 of the
+    row's, and one entry fewer would drop more.  The rows come from the
+    oracle's long double solves of T^T r = e_0 and T^T r = e_{L-1}."""
+    import oracle
+    a, b, c = t
+    kf, kl = tdt.green_support(a, b, c, L)
+    assert 1 <= kf <= L and 1 <= kl <= L
+    E = np.zeros((2, L))
+    E[0, 0] = 1.0
+    E[1, -1] = 1.0
+    R = np.abs(oracle.solve(E, c, b, a, precision="ld"))   # T^T = tridiag{c, b, a}
+    r1, r2 = R[0], R[1][::-1]          # both now decay away from index 0
+    drop = 2.0 ** -60
+    for k, r in ((kf, r1), (kl, r2)):
+        tail = np.concatenate([np.cumsum(r[::-1])[::-1], [0.0]])   # tail[j] = sum_{i >= j}
+        n1 = tail[0]
+        assert tail[k] <= drop * n1 * (1 + 1e-6), (k, tail[k] / n1)
+        if k > 1:
+            assert tail[k - 1] > drop * n1 * (1 - 1e-6), (k, tail[k - 1] / n1)
+
+
+def test_green_support_headline_matrix():
+    """For the matrix of the single-system workload the first Green row falls
+    by 0.548 per entry and the last by 0.448 (1/q_1 and q_2 for the roots
+    q_1 = 1.824, q_2 = 0.448 of t_1 q^2 + t_0 q + t_-1 = 0): 2^-60 of the
+    mass is left after 70 and 52 entries."""
+    assert tdt.green_support(-0.9, 2.5, -1.1, 8192) == (70, 52)
+    assert tdt.green_support(-1.1, 2.5, -0.9, 8192) == (52, 70)
+    assert tdt.green_support(1.0, -2.0, 1.0, 8192) == (8192, 8192)   # singular in the limit
+
+
+def test_poisson2d_refinement_refused_before_any_device_call():
+    """The 2D Poisson handle refuses float sweeps with refinement where the
+    lowest mode's cond_2 (closed form, 1.4e7 at 8191 x 8191) is above the
+    contraction limit; the check runs on the host before any allocation."""
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    st = L.tdt_poisson2d_create(8191, 8191, 1.0 / 8192, 1.0 / 8192, _lib.DTYPES["f32_refine"],
+                                ctypes.byref(h))
+    assert st == _lib.TDT_ERR_NOT_CONVERGED and not h.value
