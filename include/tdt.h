@@ -412,8 +412,10 @@ tdt_status_t tdt_plan_profile_read(tdt_plan_t plan, double *ms3, int64_t *nsolve
  *       tile-parallel three-kernel path (first pass, interface pass, final
  *       pass).  0..16, default 8; 0 sends every multi-tile system through
  *       the three kernels.
- *   TDT_OPT_WG_PER_CU        cap on the persistent workgroups per compute
- *       unit of every kernel; 0 (default) = as many as fit.
+ *   TDT_OPT_WG_PER_CU        0 (default): the tile kernels launch one
+ *       workgroup per tile and the other kernels as many workgroups as fit
+ *       at once; k > 0: every kernel runs at most k persistent workgroups
+ *       per compute unit, each looping over its share of the work.
  *   TDT_OPT_MAX_REFINE       TDT_F32_REFINE: most float solves per tile
  *       (1..100, default 40).
  *   TDT_OPT_SHAPE            work shape of the tile kernels: 0 = blocks of

@@ -1261,16 +1261,17 @@ std::string key_of(const tdt_plan_s* p, int64_t M) {
   if (colon != std::string::npos) arch.resize(colon);
   const char* dt = p->dtype == TDT_F64 ? "f64" : (p->dtype == TDT_F32 ? "f32" : "f32_refine");
   const char* kind = p->quasi ? "q" : (p->general ? "g" : "");
+  // (the leading version tag changes when the meaning of a choice does)
   char buf[256];
   if (p->varlen) {
     int maxt = 1;
     for (const SysDesc& D : p->hsys[0]) maxt = std::max(maxt, (int)D.ntiles);
-    std::snprintf(buf, sizeof(buf), "%s|cu%d|varlen%s|%s|S%lld|U%lld|P%lld", arch.c_str(), cus,
+    std::snprintf(buf, sizeof(buf), "v2|%s|cu%d|varlen%s|%s|S%lld|U%lld|P%lld", arch.c_str(), cus,
                   kind, dt,
                   (long long)pow2_ceil(p->S), (long long)pow2_ceil(p->total),
                   (long long)pow2_ceil(maxt));
   } else {
-    std::snprintf(buf, sizeof(buf), "%s|cu%d|series%s|%s|N%lld|M%lld", arch.c_str(), cus, kind,
+    std::snprintf(buf, sizeof(buf), "v2|%s|cu%d|series%s|%s|N%lld|M%lld", arch.c_str(), cus, kind,
                   dt,
                   (long long)pow2_ceil(p->N), (long long)pow2_ceil(M));
   }
@@ -1782,7 +1783,7 @@ tdt_status_t tdt_plan_autotune(tdt_plan_t p, const void* F, void* X, int64_t M,
   std::vector<tune::Choice> cands;
   const int whole[] = {0, 1, 2, 4, 8, 16};
   for (int sh = 0; sh < tdt::kNumShapes; ++sh)
-    for (int wpc : {0, 1}) {
+    for (int wpc : {0, 1, 2}) {
       if (p->general && sh != tdt::kGeneralShape) continue;
       if (p->varlen)
         for (int w : whole) cands.push_back(tune::Choice{sh, w, wpc, 0.0});
@@ -1802,18 +1803,22 @@ tdt_status_t tdt_plan_autotune(tdt_plan_t p, const void* F, void* X, int64_t M,
     if (st < 0) break;
     st = solve();   // warm-up (also grows the workspace outside the timing)
     if (st < 0) break;
-    float ms = 0.0f, tot = 0.0f;
-    constexpr int kReps = 3;
+    // the median of five timed solves (single solves of a few hundred us
+    // vary by several per cent)
+    constexpr int kReps = 5;
+    float t[kReps] = {};
     for (int r = 0; r < kReps && st >= 0; ++r) {
+      float ms = 0.0f;
       (void)hipEventRecord(e0, stream);
       st = solve();
       (void)hipEventRecord(e1, stream);
       if (hipEventSynchronize(e1) != hipSuccess ||
           hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
         st = TDT_ERR_HIP;
-      tot += ms;
+      t[r] = ms;
     }
-    cands[i].ms = tot / kReps;
+    std::sort(t, t + kReps);
+    cands[i].ms = t[kReps / 2];
     if (st >= 0 && (best < 0 || cands[i].ms < cands[best].ms)) best = (int)i;
   }
   (void)hipEventDestroy(e0);

@@ -665,10 +665,15 @@ __device__ __forceinline__ void prefetch(const TileArgs<Tio>& A, int64_t item,
 // A workgroup's refinement record, published once when it exits: rec[0] =
 // most float solves of any tile, rec[1] = bits of the largest estimated
 // remaining relative error (non-negative floats order like their bits).
+// Thousands of workgroups publish to the same two words, and atomics on one
+// address serialise; the record only grows, so a plain read that already
+// shows a value at least as large (a stale read can only show a smaller one)
+// makes the atomic unnecessary, and most workgroups skip it.
 __device__ __forceinline__ void publish_refine_record(int* rec, int it_max, float est_max) {
   if (threadIdx.x == 0 && rec && it_max > 0) {
-    atomicMax(rec, it_max);
-    atomicMax(rec + 1, __float_as_int(est_max));
+    const int e = __float_as_int(est_max);
+    if (__atomic_load_n(rec, __ATOMIC_RELAXED) < it_max) atomicMax(rec, it_max);
+    if (__atomic_load_n(rec + 1, __ATOMIC_RELAXED) < e) atomicMax(rec + 1, e);
   }
 }
 
@@ -2224,12 +2229,17 @@ static int64_t grid_cap(int per_cu, int wg_per_cu) {
   return (int64_t)n * num_cus();
 }
 
+// One workgroup per tile by default: the hardware keeps as many resident as
+// fit and starts new ones as others finish, so one workgroup's stores
+// overlap the next ones' loads (measured on a 512 MiB solve: 5.8 TB/s
+// against 5.3 TB/s for the same tile code run by resident workgroups that
+// loop over tiles).  With a cap per CU the workgroups persist and loop.
 template <class SH, typename Tio, typename Tc, bool REFINE, bool SUMMARY, bool BWD, bool QUASI>
 static void launch_tile(TileArgs<Tio>& A, int64_t nitems, int reverse, int last_only,
                         int wg_per_cu, hipStream_t st) {
   auto kern = k_tile<SH, Tio, Tc, REFINE, SUMMARY, BWD, QUASI>;
   static int per_cu = resident_per_cu(kern, SH::NT);
-  const int64_t cap = grid_cap(per_cu, wg_per_cu);
+  const int64_t cap = wg_per_cu > 0 ? grid_cap(per_cu, wg_per_cu) : nitems;
   A.nitems = nitems;
   A.reverse = reverse;
   A.last_only = last_only;
@@ -2268,8 +2278,8 @@ static void launch_beta(const LaunchSet& L, const Tio* F, hipStream_t st) {
 }
 
 // The first pass over the Green rows' supports only (the plan found them
-// short enough): one wavefront per tile, as many workgroups as the tiles
-// need up to the resident count.
+// short enough): one wavefront per tile (with a cap per CU, persistent
+// workgroups loop over the tiles).
 template <class SH, typename Tio>
 static void launch_beta_ends(const LaunchSet& L, const Tio* F, hipStream_t st) {
   auto kern = k_beta_ends<SH, Tio>;
@@ -2277,7 +2287,8 @@ static void launch_beta_ends(const LaunchSet& L, const Tio* F, hipStream_t st) {
   const int64_t cap = grid_cap(per_cu, L.wg_per_cu);
   BetaEndsArgs<Tio> B{F, L.sys, L.green, L.n_beta, L.nfull, L.green_kf, L.green_kl, L.summ};
   const int64_t want = (L.n_beta + kEndsNW - 1) / kEndsNW;
-  const unsigned grid = (unsigned)(want < cap ? want : cap);
+  const int64_t lim = L.wg_per_cu > 0 ? cap : ((int64_t)1 << 30);
+  const unsigned grid = (unsigned)(want < lim ? want : lim);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(kEndsNT), 0, st, B);
 }
 
