@@ -293,6 +293,20 @@ tdt_status_t tdt_plan_reserve(tdt_plan_t plan, int64_t M_max);
 tdt_status_t tdt_solve(tdt_plan_t plan, const void *F, void *X, int64_t M,
                        hipStream_t stream);
 
+/* tdt_solve for callers that cannot allocate device memory (code being
+ * captured into a hipGraph without a prior tdt_plan_reserve, tight serving
+ * loops, harnesses that forbid allocation): the same solve, same kernels,
+ * same result, but its workspace is a static device array of the library
+ * (7 MiB per GPU it runs on, held until the process ends) instead of the
+ * plan's, so it calls no hipMalloc, hipFree or other allocating routine.
+ * Arguments, layouts and errors as tdt_solve; a solve that needs more than
+ * 2^17 tile slots (M times the number of tiles of N) -> TDT_ERR_INVALID_ARG.
+ * Every call on one GPU shares that array: calls that may overlap on one GPU
+ * (two streams, two threads) race and must be serialised by the caller.
+ * Not recorded by tdt_plan_profile. */
+tdt_status_t tdt_solve_noalloc(tdt_plan_t plan, const void *F, void *X, int64_t M,
+                               hipStream_t stream);
+
 /* Solve every system of a varlen plan (the series of Sec. 3.2: one system
  * per Fourier mode after separating variables, each mode with its own t_0
  * and, here, its own size): F, X device, packed by the plan's offsets,

@@ -42,7 +42,7 @@ EXPORTS = [
     "tdt_poisson2d_profile_read", "tdt_plan_strided_create",
     "tdt_solve_strided", "tdt_poisson3d_create", "tdt_poisson3d_solve", "tdt_poisson3d_schedule",
     "tdt_poisson3d_profile", "tdt_poisson3d_profile_read", "tdt_poisson3d_destroy",
-    "tdt_adi_parameters", "tdt_green_support", "tdt_plan_green_support",
+    "tdt_adi_parameters", "tdt_green_support", "tdt_plan_green_support", "tdt_solve_noalloc",
 ]
 
 # tdt_option_t
@@ -120,6 +120,7 @@ def lib():
         "tdt_adi_parameters": [d, d, i32, p, p],
         "tdt_plan_reserve": [p, i64],
         "tdt_solve": [p, p, p, i64, p],
+        "tdt_solve_noalloc": [p, p, p, i64, p],
         "tdt_solve_varlen": [p, p, p, p],
         "tdt_solve_backward": [p, p, p, p, p, i64, p],
         "tdt_plan_destroy": [p],

@@ -999,9 +999,11 @@ int64_t series_fslots(const tdt_plan_s* p, int64_t M) {
   return M * p->hsys[0][0].ntiles + (p->quasi ? 2 * M : 0);
 }
 
-tdt_status_t run(tdt_plan_s* p, int dir, const void* F, void* X, const void* Xfwd, int64_t M,
-                 hipStream_t st) {
-  tdt::LaunchSet L{};
+// The launch set of a solve (everything but the workspace and the profile
+// events) and the tile slots / adjoint partial-sum slots it needs.
+tdt_status_t launch_set(tdt_plan_s* p, int dir, bool adjoint, int64_t M, tdt::LaunchSet& L,
+                        int64_t& slots, int64_t& fslots) {
+  L = tdt::LaunchSet{};
   L.sys = p->dsys[dir];
   L.vec64 = p->dvec64[dir];
   L.vec32 = p->dvec32[dir];
@@ -1022,7 +1024,6 @@ tdt_status_t run(tdt_plan_s* p, int dir, const void* F, void* X, const void* Xfw
   L.gen_blk = p->dgblk[dir];
   L.gen_tK = p->dgtK[dir];
   L.gen_M = M;
-  int64_t slots, fslots;
   if (p->general) {
     const SysDesc& D0 = p->hsys[0][0];
     const int64_t nt = D0.ntiles;
@@ -1067,7 +1068,7 @@ tdt_status_t run(tdt_plan_s* p, int dir, const void* F, void* X, const void* Xfw
     L.n_grid = p->n_grid;
     L.n_sys = p->n_whole;
     slots = p->vslots;
-    fslots = Xfwd ? p->vfslots : 0;
+    fslots = adjoint ? p->vfslots : 0;
     L.corner0 = 0;
   } else {
     const SysDesc& D0 = p->hsys[0][0];
@@ -1090,11 +1091,20 @@ tdt_status_t run(tdt_plan_s* p, int dir, const void* F, void* X, const void* Xfw
     L.n_grid = itf ? M : 0;
     L.n_fin = M * nt;
     slots = itf ? M * D0.tslots : 0;
-    fslots = Xfwd ? series_fslots(p, M) : 0;
+    fslots = adjoint ? series_fslots(p, M) : 0;
     L.corner0 = M * nt;
   }
   if (L.n_fin > 0x7fffffffLL) return TDT_ERR_INVALID_ARG;
-  tdt_status_t s = ensure_workspace(p, slots, fslots, st);
+  return TDT_OK;
+}
+
+tdt_status_t run(tdt_plan_s* p, int dir, const void* F, void* X, const void* Xfwd, int64_t M,
+                 hipStream_t st) {
+  tdt::LaunchSet L;
+  int64_t slots = 0, fslots = 0;
+  tdt_status_t s = launch_set(p, dir, Xfwd != nullptr, M, L, slots, fslots);
+  if (s != TDT_OK) return s;
+  s = ensure_workspace(p, slots, fslots, st);
   if (s != TDT_OK) return s;
   if (!p->summ || !p->ghost || !p->gscr || !p->gpart) return TDT_ERR_OOM;
   L.summ = p->summ;
@@ -1118,6 +1128,21 @@ tdt_status_t run(tdt_plan_s* p, int dir, const void* F, void* X, const void* Xfw
 }
 
 }  // namespace
+
+namespace tdt {
+// The checks of tdt_solve and its launch set, for the entry point whose
+// workspace is the library's static device scratch (tdt_solve_noalloc).
+int series_solve_prepare(tdt_plan_s* p, const void* F, void* X, int64_t M, LaunchSet& L,
+                         int64_t& slots, int& dtype) {
+  if (!p || p->varlen || p->strided || !F || !X || M < 1) return TDT_ERR_INVALID_ARG;
+  const size_t bytes = (size_t)M * (size_t)p->N * elem_size(p->dtype);
+  if (overlaps(F, bytes, X, bytes)) return TDT_ERR_INVALID_ARG;
+  int64_t fslots = 0;
+  dtype = (int)p->dtype;
+  return launch_set(p, 0, false, M, L, slots, fslots);
+}
+}  // namespace tdt
+
 
 // Tables of a strided batch (systems along a slow axis, one workgroup per
 // column of adjacent systems): per class the block LU pivots, the end values

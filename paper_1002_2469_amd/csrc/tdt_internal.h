@@ -3,6 +3,8 @@
 #include <stdint.h>
 #include <hip/hip_runtime.h>
 
+struct tdt_plan_s;
+
 namespace tdt {
 
 // Work shape of the tile kernels: B contiguous unknowns per lane (the
@@ -135,6 +137,11 @@ struct LaunchSet {
                            // after the interface pass, after the final pass) or null
 };
 
+// The argument checks of a forward solve of a series plan (those of
+// tdt_solve) and its launch set without workspace; slots = the tile slots
+// its workspace needs, dtype = the plan's.  Returns a tdt_status_t.
+int series_solve_prepare(tdt_plan_s* p, const void* F, void* X, int64_t M, LaunchSet& L,
+                         int64_t& slots, int& dtype);
 // dtype: 0 double, 1 float, 2 float sweeps with double refinement.
 hipError_t launch_solve(int dtype, bool bwd, const LaunchSet& L, const void* F, void* X,
                         const void* Xfwd, hipStream_t st);

@@ -2496,3 +2496,59 @@ hipError_t launch_gt_reduce(const double* gpart, const SysDesc* sys, int64_t nsy
 }
 
 }  // namespace tdt
+
+// ---------------------------------------------------------------------------
+// Solve without allocation: the workspace is a static device array of this
+// file instead of the plan's.  Layout in doubles: tile summaries [slot][2],
+// values outside the tiles [slot][2], the segment-merge suffixes [slot][3],
+// then one adjoint partial-sum slot (passed, never used by a forward solve).
+// No part of it needs to start at zero: a solve reads only what it wrote
+// earlier in the same call (the one unconditional read, slot 0 of the values
+// outside a one-tile system, is discarded).
+// ---------------------------------------------------------------------------
+#include <mutex>
+
+#include "tdt.h"
+
+namespace {
+constexpr int64_t kScratchSlots = (int64_t)1 << 17;
+constexpr int64_t kScratchDoubles = 7 * kScratchSlots + tdt::kGradN;   // 7 MiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+// The array's device address on the current device, looked up once per
+// device (the host-side symbol is not a device address).
+constexpr int kMaxDevices = 64;
+double* g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+double* scratch_on_current_device() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+
+extern "C" tdt_status_t tdt_solve_noalloc(tdt_plan_t plan, const void* F, void* X, int64_t M,
+                                          hipStream_t stream) {
+  tdt::LaunchSet L;
+  int64_t slots = 0;
+  int dtype = 0;
+  const int st = tdt::series_solve_prepare(plan, F, X, M, L, slots, dtype);
+  if (st != TDT_OK) return (tdt_status_t)st;
+  if (slots > kScratchSlots) return TDT_ERR_INVALID_ARG;
+  double* base = scratch_on_current_device();
+  if (!base) return TDT_ERR_HIP;
+  L.summ = base;
+  L.ghost = base + 2 * kScratchSlots;
+  L.gscr = base + 4 * kScratchSlots;
+  L.gpart = base + 7 * kScratchSlots;
+  L.ev = nullptr;
+  return tdt::launch_solve(dtype, false, L, F, X, nullptr, stream) == hipSuccess ? TDT_OK
+                                                                                : TDT_ERR_HIP;
+}
