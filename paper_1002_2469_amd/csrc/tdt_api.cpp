@@ -132,19 +132,21 @@ bool block_vectors(ld a, ld b, ld c, int B, ld* iu, ld* cp, ld* phi, ld* chi) {
 
 // End values (phi_first, phi_last, chi_first, chi_last) of a run of L rows,
 // by an O(L) long double elimination.  Returns false on a zero pivot.
-bool segment_ends(ld a, ld b, ld c, int64_t L, ld out[4]) {
+bool segment_ends_sweep(ld a, ld b, ld c, int64_t L, ld out[4]) {
   std::vector<ld> cpv((size_t)L), d1((size_t)L), d2((size_t)L);
   ld u = b;
   if (u == 0.0L) return false;
-  cpv[0] = c / u;
-  d1[0] = -a / u;
-  d2[0] = L == 1 ? -c / u : 0.0L;
+  ld iu = 1.0L / u;
+  cpv[0] = c * iu;
+  d1[0] = -a * iu;
+  d2[0] = L == 1 ? -c * iu : 0.0L;
   for (int64_t i = 1; i < L; ++i) {
     u = b - a * cpv[i - 1];
     if (u == 0.0L) return false;
-    cpv[i] = c / u;
-    d1[i] = (0.0L - a * d1[i - 1]) / u;
-    d2[i] = ((i == L - 1 ? -c : 0.0L) - a * d2[i - 1]) / u;
+    iu = 1.0L / u;
+    cpv[i] = c * iu;
+    d1[i] = (0.0L - a * d1[i - 1]) * iu;
+    d2[i] = ((i == L - 1 ? -c : 0.0L) - a * d2[i - 1]) * iu;
   }
   for (int64_t i = L - 2; i >= 0; --i) {
     d1[i] -= cpv[i] * d1[i + 1];
@@ -156,6 +158,49 @@ bool segment_ends(ld a, ld b, ld c, int64_t L, ld out[4]) {
   out[3] = d2[L - 1];
   return std::isfinite((double)out[0]) && std::isfinite((double)out[1]) &&
          std::isfinite((double)out[2]) && std::isfinite((double)out[3]);
+}
+
+struct SegLD {
+  ld yf, yl, pf, pl, cf, cl;
+};
+bool merge_ld(const SegLD& L, const SegLD& R, SegLD& M);
+
+// The same end values by the merge of the dichotomy step (eqs. (6)-(8)):
+// the run of one row is (phi, chi) = (-t_-1/t_0, -t_1/t_0) at both ends, and
+// runs of 2k rows are two runs of k merged, so L rows take O(log L) merges
+// instead of L elimination steps.  Every merge divides by 1 - chi_last phi_first
+// of its two halves; under diagonal dominance both factors are below 1 in
+// magnitude (a maximum principle), so the divisor loses at most a few of the
+// 64 bits of long double.  Used at dominance ratio >= 1.001; below that (and
+// if a merge is refused) the elimination above gives the values.
+bool segment_ends(ld a, ld b, ld c, int64_t L, ld out[4]) {
+  const ld off = std::fabs(a) + std::fabs(c);
+  if (L >= 32 && std::fabs(b) >= 1.001L * off && b != 0.0L) {
+    SegLD acc{0, 0, 0, 1, 1, 0};   // the run of no rows: merging with it changes nothing
+    SegLD pw{0, 0, -a / b, -a / b, -c / b, -c / b};
+    bool ok = true;
+    for (int64_t k = L; k > 0 && ok; k >>= 1) {
+      SegLD t;
+      if (k & 1) {
+        ok = merge_ld(acc, pw, t);
+        acc = t;
+      }
+      if (ok && k > 1) {
+        ok = merge_ld(pw, pw, t);
+        pw = t;
+      }
+    }
+    if (ok) {
+      out[0] = acc.pf;
+      out[1] = acc.pl;
+      out[2] = acc.cf;
+      out[3] = acc.cl;
+      if (std::isfinite((double)out[0]) && std::isfinite((double)out[1]) &&
+          std::isfinite((double)out[2]) && std::isfinite((double)out[3]))
+        return true;
+    }
+  }
+  return segment_ends_sweep(a, b, c, L, out);
 }
 
 // First and last row of T_L^{-1} (T = tridiag{a, b, c} of order L): the rows
@@ -228,10 +273,6 @@ void green_support_rounded(int64_t L, int64_t kf, int64_t kl, int& rkf, int& rkl
   }
 }
 
-struct SegLD {
-  ld yf, yl, pf, pl, cf, cl;
-};
-
 bool merge_ld(const SegLD& L, const SegLD& R, SegLD& M) {
   const ld D = 1.0L - L.cl * R.pf;
   if (!(std::fabs((double)D) > 1e-13)) return false;
@@ -251,7 +292,11 @@ bool merge_ld(const SegLD& L, const SegLD& R, SegLD& M) {
 // The interface merges the kernels perform divide by 1 - chi_last(L) phi_first(R)
 // for runs of full blocks of every length up to a wavefront and beyond; check
 // them for runs of up to 64 + 64 blocks.  Under diagonal dominance they are
-// bounded away from zero; otherwise a sub-block may be (nearly) singular.
+// bounded away from zero (|chi_last|, |phi_first| < 1 by the maximum
+// principle, and the divisor of two runs of m and n rows of tridiag{-1,2,-1},
+// the weakest dominant case, is (m+n+1)/((m+1)(n+1)) >= 1/1025 here), so the
+// check runs only without dominance, where a sub-block may be (nearly)
+// singular.
 bool merges_ok(const ld blk4[4]) {
   std::vector<SegLD> run(65);
   run[1] = SegLD{0, 0, blk4[0], blk4[1], blk4[2], blk4[3]};
@@ -346,21 +391,31 @@ tdt_status_t build_system(double a, double b, double c, int64_t n, bool quasi, i
   D.ntiles = (int32_t)((n + kTile - 1) / kTile);
   const ld blk[4] = {phi[0], phi[kB - 1], chi[0], chi[kB - 1]};
   for (int k = 0; k < 4; ++k) D.blk[k] = (double)blk[k];
-  if (!merges_ok(blk)) return TDT_ERR_SINGULAR;
+  if (std::fabs(b) < std::fabs(a) + std::fabs(c) && !merges_ok(blk)) return TDT_ERR_SINGULAR;
   // per-position table of the left-to-right interface elimination over the
   // NT blocks of a tile: beta_{m-1} and 1/(1 - phi_first beta_{m-1})
+  // (beta_m contracts to a fixed point, under dominance within a few
+  // blocks; once it repeats exactly, so does every later entry)
   {
     ld beta = 0.0L;
+    bool fixed = false;
+    ld iD = 1.0L;
     for (int m = 0; m < kNT; ++m) {
-      const ld D = 1.0L - blk[0] * beta;
-      if (!(std::fabs((double)D) > 1e-13)) return TDT_ERR_SINGULAR;
-      const ld iD = 1.0L / D;
+      if (!fixed) {
+        const ld D = 1.0L - blk[0] * beta;
+        if (!(std::fabs((double)D) > 1e-13)) return TDT_ERR_SINGULAR;
+        iD = 1.0L / D;
+      }
       t64[tdt::kTabBeta * kNT + m] = (double)beta;
       t64[tdt::kTabInvD * kNT + m] = (double)iD;
       t32[tdt::kTabBeta * kNT + m] = (float)beta;
       t32[tdt::kTabInvD * kNT + m] = (float)iD;
-      beta = blk[3] + blk[1] * beta * blk[2] * iD;
-      if (!std::isfinite((double)beta)) return TDT_ERR_SINGULAR;
+      if (!fixed) {
+        const ld next = blk[3] + blk[1] * beta * blk[2] * iD;
+        if (!std::isfinite((double)next)) return TDT_ERR_SINGULAR;
+        fixed = next == beta;
+        beta = next;
+      }
     }
   }
   // last block of the system
@@ -535,12 +590,18 @@ tdt_status_t build_varlen_lists(tdt_plan_s* p) {
   p1.erase(std::remove_if(p1.begin(), p1.end(), alone), p1.end());
   fin.assign(p1.rbegin(), p1.rend());
   fin.insert(fin.end(), single.begin(), single.end());
-  // Whole systems over the resident workgroups, longest processing time
-  // first: each system (largest first) goes to the least loaded list.  A
-  // system of nt tiles costs about 2 nt tile steps (summaries, then the
-  // solve), a one-tile system one.
+  // Whole systems: by default one workgroup each, largest first, so that
+  // the hardware starts the next system wherever a workgroup finishes (the
+  // longest-processing-time order, scheduled dynamically).  With a cap of
+  // persistent workgroups per CU, the systems go to that many lists instead,
+  // each system (largest first) to the least loaded list; a system of nt
+  // tiles costs about 2 nt tile steps (summaries, then the solve), a
+  // one-tile system one.
   std::vector<int> whole, bins;
-  if (!whole_sys.empty()) {
+  if (!whole_sys.empty() && p->wg_per_cu == 0) {
+    whole = whole_sys;
+    for (size_t b = 0; b <= whole.size(); ++b) bins.push_back((int)b);
+  } else if (!whole_sys.empty()) {
     const int64_t G = std::min<int64_t>(
         (int64_t)whole_sys.size(),
         std::max(1, tdt::sys_wg_capacity(p->shape, (int)p->dtype, p->wg_per_cu,
