@@ -387,10 +387,13 @@ tdt_status_t tdt_green_rows(double t_m1, double t_0, double t_1, int64_t L,
  * trailing entries of the last row such that the dropped entries' 1-norm is
  * at most 2^-60 of the row's (computed in long double).  The dropped part of
  * a summary is then at most 2^-60 |row|_1 |F|_inf, below the rounding of the
- * dot product.  Errors: L outside [1, 2^26], non-finite t's, null outputs ->
- * TDT_ERR_INVALID_ARG; a zero pivot -> TDT_ERR_SINGULAR. */
+ * dot product.  bound2 (may be NULL): the supports a varlen plan uses for
+ * its systems, found without forming the rows, from the decay of the ratios
+ * of the elimination's pivots (at least *kf and *kl; 0, 0 when that bound
+ * finds no truncation).  Errors: L outside [1, 2^26], non-finite t's, null
+ * kf or kl -> TDT_ERR_INVALID_ARG; a zero pivot -> TDT_ERR_SINGULAR. */
 tdt_status_t tdt_green_support(double t_m1, double t_0, double t_1, int64_t L, int64_t *kf,
-                               int64_t *kl);
+                               int64_t *kl, int64_t *bound2);
 
 /* What the first pass of a plan reads per full tile: rows4[0], rows4[1] =
  * the leading and trailing rows of each tile the forward solve's summaries

@@ -638,14 +638,20 @@ def green_rows(t_m1: float, t_0: float, t_1: float, L: int):
     return first, last
 
 
-def green_support(t_m1: float, t_0: float, t_1: float, L: int):
+def green_support(t_m1: float, t_0: float, t_1: float, L: int, bound: bool = False):
     """Host-only: (kf, kl), the fewest leading entries of the first Green row
     and trailing entries of the last that hold all but 2^-60 of each row's
-    1-norm (the supports the first pass reads)."""
+    1-norm (the supports a series plan's first pass reads); with bound=True
+    also the supports a varlen plan derives from the pivots' decay (0, 0:
+    no truncation), as ((kf, kl), (bkf, bkl))."""
     kf, kl = ctypes.c_int64(0), ctypes.c_int64(0)
+    b2 = np.zeros(2, dtype=np.int64)
     _lib.check(_lib.lib().tdt_green_support(float(t_m1), float(t_0), float(t_1), int(L),
-                                            ctypes.byref(kf), ctypes.byref(kl)),
+                                            ctypes.byref(kf), ctypes.byref(kl),
+                                            b2.ctypes.data_as(ctypes.c_void_p)),
                "tdt_green_support")
+    if bound:
+        return (kf.value, kl.value), (int(b2[0]), int(b2[1]))
     return kf.value, kl.value
 
 

@@ -129,7 +129,7 @@ def lib():
         "tdt_block_constants": [d, d, d, i32, p],
         "tdt_segment_merge": [p, p, p],
         "tdt_green_rows": [d, d, d, i64, p, p],
-        "tdt_green_support": [d, d, d, i64, ctypes.POINTER(i64), ctypes.POINTER(i64)],
+        "tdt_green_support": [d, d, d, i64, ctypes.POINTER(i64), ctypes.POINTER(i64), p],
         "tdt_plan_green_support": [p, p],
         "tdt_plan_profile": [p, i32],
         "tdt_plan_profile_read": [p, p, ctypes.POINTER(i64)],

@@ -72,6 +72,11 @@ struct tdt_plan_s {
   double* dgreen[2] = {nullptr, nullptr};   // series with several tiles: [2][L]
   // rows of a tile the first pass reads from the head and the tail (0: all)
   int green_kf[2] = {0, 0}, green_kl[2] = {0, 0};
+  // varlen: the systems' Green row supports, packed (SysDesc goff, gkf, gkl),
+  // and the full tiles whose summaries use them
+  double* dgpack[2] = {nullptr, nullptr};
+  int2* dends = nullptr;
+  int64_t n_ends = 0;
   double* dttab[2] = {nullptr, nullptr};    // per tile position table [2][ttab_n]
   int64_t ttab_n = 0;
   // varlen launch lists
@@ -271,6 +276,80 @@ void green_support_rounded(int64_t L, int64_t kf, int64_t kl, int& rkf, int& rkl
     rkf = (int)f;
     rkl = (int)l;
   }
+}
+
+// The same supports without forming the rows (for the many matrices of a
+// varlen plan), with their entries.  The rows are ratios of leading minors:
+//   (T_L^{-1})_{0,j}         = (-t_1)^j  / (u_{L-1-j} ... u_{L-1}),
+//   (T_L^{-1})_{L-1,L-1-m}   = (-t_-1)^m / (u_{L-1-m} ... u_{L-1}),
+// u_i the pivots of the elimination (u_0 = t_0, u_i = t_0 - t_-1 t_1 / u_{i-1}).
+// Under dominance the pivots settle at u* (the larger root of
+// u^2 - t_0 u + t_-1 t_1 = 0); once two agree to long double rounding (at C),
+// the entries within L-1-C of the row's own end are geometric,
+// (-t_1)^j / u*^(j+1), and every entry is at most |t_1|^j / umin^(j+1),
+// umin the smallest |u_i|.  So the mass beyond entry k is at most
+// s^k / (umin (1 - s)), s = |t_1| / umin, against a total of at least the
+// first entry, 1 / |u*|: kf is the least k with s^k |u*| / (umin (1 - s))
+// <= kGreenDrop (the same with t_-1 for kl), a support at least as long as
+// the minimal one of green_support.  head: kf entries of the first row from
+// its start, tail: kl entries of the last row up to its end, in row order.
+// Returns false (no truncation) unless the pivots settle, s < 1 for both
+// rows and both supports lie where they have settled.
+bool green_support_bound(ld a, ld b, ld c, int64_t L, int64_t& kf, int64_t& kl, ld* ustar,
+                         int64_t* settled_at) {
+  if (b == 0.0L || L < 2) return false;
+  ld u = b, umin = std::fabs(b);
+  int64_t C = -1;
+  for (int64_t i = 1; i < L; ++i) {
+    const ld un = b - a * c / u;
+    if (un == 0.0L || !std::isfinite((double)un)) return false;
+    umin = std::min(umin, std::fabs(un));
+    const bool settled = std::fabs(un - u) <= 0x1p-62L * std::fabs(un);
+    u = un;
+    if (settled) {
+      C = i;
+      break;
+    }
+  }
+  if (C < 0) return false;
+  auto support = [&](ld t, int64_t& k) {
+    const ld sr = std::fabs(t) / umin;
+    if (!(sr < 1.0L)) return false;
+    if (sr == 0.0L) {
+      k = 1;
+      return true;
+    }
+    const ld factor = std::fabs(u) / (umin * (1.0L - sr));
+    const ld kk = std::ceil((std::log(kGreenDrop) - std::log(factor)) / std::log(sr));
+    k = std::max<int64_t>(1, (int64_t)kk);
+    return k <= L - C;
+  };
+  if (!support(c, kf) || !support(a, kl)) return false;
+  if (ustar) *ustar = u;
+  if (settled_at) *settled_at = C;
+  return true;
+}
+
+// The supports a varlen plan's first pass uses for a full tile of L rows
+// (green_support_bound rounded up to 64-row runs; false when they would
+// cover a quarter of the tile, or reach past where the pivots settled) and
+// their entries: head = the first rf entries of the first row, tail = the
+// last rl entries of the last row, (-t_1)^j / u*^(j+1) and
+// (-t_-1)^m / u*^(m+1) at distance j, m from the row's own end.
+bool green_ends(ld a, ld b, ld c, int64_t L, int& rf, int& rl, std::vector<ld>& head,
+                std::vector<ld>& tail) {
+  int64_t kf = 0, kl = 0, C = 0;
+  ld us = 0.0L;
+  if (!green_support_bound(a, b, c, L, kf, kl, &us, &C)) return false;
+  green_support_rounded(L, kf, kl, rf, rl);
+  if (rf == 0 || rf > L - C || rl > L - C) return false;
+  head.assign((size_t)rf, 0.0L);
+  tail.assign((size_t)rl, 0.0L);
+  ld e = 1.0L / us;
+  for (int j = 0; j < rf; ++j, e *= -c / us) head[(size_t)j] = e;
+  e = 1.0L / us;
+  for (int m = 0; m < rl; ++m, e *= -a / us) tail[(size_t)(rl - 1 - m)] = e;
+  return true;
 }
 
 bool merge_ld(const SegLD& L, const SegLD& R, SegLD& M) {
@@ -554,6 +633,8 @@ void destroy(tdt_plan_s* p) {
     (void)hipFree(p->dggreen[k]);
   }
   (void)hipFree(p->dstr);
+  for (int k = 0; k < 2; ++k) (void)hipFree(p->dgpack[k]);
+  (void)hipFree(p->dends);
   (void)hipFree(p->dp1);
   (void)hipFree(p->dfin);
   (void)hipFree(p->dgrid);
@@ -590,6 +671,16 @@ tdt_status_t build_varlen_lists(tdt_plan_s* p) {
   p1.erase(std::remove_if(p1.begin(), p1.end(), alone), p1.end());
   fin.assign(p1.rbegin(), p1.rend());
   fin.insert(fin.end(), single.begin(), single.end());
+  // full tiles of systems whose Green rows decay (in both directions): their
+  // summaries are dot products with the rows' supports, not sweeps
+  std::vector<int2> ends;
+  auto by_ends = [&](const int2& it) {
+    const SysDesc& D0 = p->hsys[0][it.x];
+    return D0.gkf > 0 && p->hsys[1][it.x].gkf > 0 && (int64_t)(it.y + 1) * p->L <= D0.n;
+  };
+  for (const int2& it : p1)
+    if (by_ends(it)) ends.push_back(it);
+  p1.erase(std::remove_if(p1.begin(), p1.end(), by_ends), p1.end());
   // Whole systems: by default one workgroup each, largest first, so that
   // the hardware starts the next system wherever a workgroup finishes (the
   // longest-processing-time order, scheduled dynamically).  With a cap of
@@ -624,6 +715,9 @@ tdt_status_t build_varlen_lists(tdt_plan_s* p) {
       bins.push_back((int)whole.size());
     }
   }
+  (void)hipFree(p->dends);
+  p->dends = nullptr;
+  p->n_ends = (int64_t)ends.size();
   (void)hipFree(p->dp1);
   (void)hipFree(p->dfin);
   (void)hipFree(p->dgrid);
@@ -637,6 +731,7 @@ tdt_status_t build_varlen_lists(tdt_plan_s* p) {
   p->n_whole = (int64_t)whole.size();
   p->n_bins = bins.empty() ? 0 : (int64_t)bins.size() - 1;
   tdt_status_t st = dev_upload(&p->dp1, p1.data(), p1.size());
+  if (st == TDT_OK) st = dev_upload(&p->dends, ends.data(), ends.size());
   if (st == TDT_OK) st = dev_upload(&p->dfin, fin.data(), fin.size());
   if (st == TDT_OK) st = dev_upload(&p->dgrid, grid.data(), grid.size());
   if (st == TDT_OK) st = dev_upload(&p->dwhole, whole.data(), whole.size());
@@ -698,6 +793,31 @@ tdt_status_t finish_plan(tdt_plan_s* p, const std::vector<double>& tm1,
       fs += p->hsys[dir][s].ntiles + (p->quasi ? 2 : 0);
     }
     p->vfslots = fs;
+    // varlen: Green row supports of each multi-tile system's full tiles
+    if (p->varlen) {
+      std::vector<double> pack;
+      std::vector<ld> head, tail;
+      for (int64_t s = 0; s < S; ++s) {
+        SysDesc& D = p->hsys[dir][s];
+        D.goff = 0;
+        D.gkf = D.gkl = 0;
+        if (!needs_interface(D) || D.n < kTile) continue;
+        const double a = dir == 0 ? tm1[s] : t1[s], c = dir == 0 ? t1[s] : tm1[s];
+        int rf = 0, rl = 0;
+        if (!green_ends(a, t0[s], c, kTile, rf, rl, head, tail)) continue;
+        D.goff = (int64_t)pack.size();
+        D.gkf = (int32_t)rf;
+        D.gkl = (int32_t)rl;
+        for (ld v : head) pack.push_back((double)v);
+        for (ld v : tail) pack.push_back((double)v);
+      }
+      (void)hipFree(p->dgpack[dir]);
+      p->dgpack[dir] = nullptr;
+      if (!pack.empty()) {
+        tdt_status_t sg = dev_upload(&p->dgpack[dir], pack.data(), pack.size());
+        if (sg != TDT_OK) return sg;
+      }
+    }
     p->green_kf[dir] = p->green_kl[dir] = 0;
     if (!p->varlen && needs_interface(p->hsys[dir][0])) {
       std::vector<double> g(2 * (size_t)kTile);
@@ -1065,6 +1185,9 @@ int64_t series_fslots(const tdt_plan_s* p, int64_t M) {
 tdt_status_t launch_set(tdt_plan_s* p, int dir, bool adjoint, int64_t M, tdt::LaunchSet& L,
                         int64_t& slots, int64_t& fslots) {
   L = tdt::LaunchSet{};
+  L.ends_items = nullptr;
+  L.n_ends = 0;
+  L.gpack = nullptr;
   L.sys = p->dsys[dir];
   L.vec64 = p->dvec64[dir];
   L.vec32 = p->dvec32[dir];
@@ -1128,6 +1251,9 @@ tdt_status_t launch_set(tdt_plan_s* p, int dir, bool adjoint, int64_t M, tdt::La
     L.n_fin = p->n_fin;
     L.n_grid = p->n_grid;
     L.n_sys = p->n_whole;
+    L.ends_items = p->n_ends > 0 ? p->dends : nullptr;
+    L.n_ends = p->n_ends;
+    L.gpack = p->dgpack[dir];
     slots = p->vslots;
     fslots = adjoint ? p->vfslots : 0;
     L.corner0 = 0;
@@ -1942,12 +2068,18 @@ tdt_status_t tdt_green_rows(double t_m1, double t_0, double t_1, int64_t L, doub
 }
 
 tdt_status_t tdt_green_support(double t_m1, double t_0, double t_1, int64_t L, int64_t* kf,
-                               int64_t* kl) {
+                               int64_t* kl, int64_t* bound2) {
   if (!kf || !kl || L < 1 || L > ((int64_t)1 << 26) || !finite3(t_m1, t_0, t_1))
     return TDT_ERR_INVALID_ARG;
   std::vector<ld> r1, r2;
   if (!green_rows_ld(t_m1, t_0, t_1, L, r1, r2)) return TDT_ERR_SINGULAR;
   green_support(r1, r2, *kf, *kl);
+  if (bound2) {
+    int64_t bf = 0, bl = 0;
+    if (!green_support_bound(t_m1, t_0, t_1, L, bf, bl, nullptr, nullptr)) bf = bl = 0;
+    bound2[0] = bf;
+    bound2[1] = bl;
+  }
   return TDT_OK;
 }
 

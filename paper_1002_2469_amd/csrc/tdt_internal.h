@@ -62,6 +62,11 @@ struct SysDesc {
   // [3] -t_-1/(t0+chi), the last corner's response to a unit value left of
   // it; [4] beta of the last inner tile; [5] 1/(1 - [3] [4])
   double qc[6];
+  // varlen plans: the supports of a full tile's two Green rows (gkf leading
+  // entries of the first row, then gkl trailing entries of the last, at
+  // goff of the plan's packed array), or gkf = gkl = 0 (summaries by sweeps)
+  int64_t goff;
+  int32_t gkf, gkl;
 };
 
 // Slot of tile t of a system: a varlen plan adds the system's slot0; a
@@ -110,6 +115,11 @@ struct LaunchSet {
   const double* green;     // [2][L] or null
   int green_kf, green_kl;  // supports of the Green rows (multiples of 64), or 0: whole tile
   int64_t n_beta, n_last;
+  // varlen plans: full tiles whose summaries come from their system's Green
+  // row supports (packed entries at gpack + goff of the system)
+  const int2* ends_items;
+  int64_t n_ends;
+  const double* gpack;
   int nfull;
   int max_ntiles;          // most tiles of any system (selects the interface kernel)
   const double* ttab;      // per tile position: beta_{t-1}, 1/(1 - Pf beta_{t-1}) ([2][ttab_n])

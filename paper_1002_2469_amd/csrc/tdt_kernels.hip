@@ -1036,6 +1036,42 @@ __global__ __launch_bounds__(SH::NT, REFINE ? TDT_REFINE_WAVES : SH::WAVES) void
   publish_refine_record(A.iters, it_max, est_max);
 }
 
+// One wavefront's summary of one tile from the Green rows' supports: s1 =
+// first row head (kf entries at gf) . the tile's first kf rows, s2 = last row
+// tail (kl entries at gl) . its last kl rows (kf, kl multiples of 64; the
+// pointers already offset by the lane).  The lane sums are added by a fixed
+// butterfly, so the result is repeatable and the same in every lane.
+template <typename Tio>
+__device__ __forceinline__ void ends_dot(const Tio* head, const Tio* tail, const double* gf,
+                                         const double* gl, int kf, int kl, double& s1,
+                                         double& s2) {
+  constexpr int U = 4;   // loads in flight per lane and row run
+  const int nf = kf / 64, nl = kl / 64;
+  s1 = 0.0;
+  s2 = 0.0;
+  for (int j0 = 0; j0 < nf; j0 += U) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = j0 + u < nf ? (double)head[(j0 + u) * 64] : 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (j0 + u < nf) s1 += v[u] * gf[(j0 + u) * 64];
+  }
+  for (int j0 = 0; j0 < nl; j0 += U) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = j0 + u < nl ? (double)tail[(j0 + u) * 64] : 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (j0 + u < nl) s2 += v[u] * gl[(j0 + u) * 64];
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    s1 += __shfl_xor(s1, d, 64);
+    s2 += __shfl_xor(s2, d, 64);
+  }
+}
+
 template <typename Tio>
 struct SysArgs {
   const Tio* __restrict__ F;
@@ -1054,6 +1090,7 @@ struct SysArgs {
   int* __restrict__ iters;
   int max_iter;
   double refine_tol;
+  const double* __restrict__ gpack;   // Green row supports of the systems (SysDesc goff)
 };
 
 // Coalesced load of rows [base, base + tl) into the LDS tile (rows past tl
@@ -1140,16 +1177,19 @@ __global__ __launch_bounds__(SH::NT, REFINE ? TDT_REFINE_WAVES : SH::WAVES) void
     const SysDesc S = load_sys(A.sys, s);
     const int nt = S.ntiles;
     if (nt > kSysMaxTiles) continue;   // never listed here (the host checks it)
+    // the last tile is still in LDS after the summaries unless they came
+    // from the Green rows' supports
+    bool last_in_lds = true;
     if (nt > 1 || QUASI) {
       const Consts<Ts> KS = make_consts<SH, Ts>(S, A.vec64, A.vec32);
       Ts sbp, siD;
       lane_table<SH, Ts>(S, A.tab64, A.tab32, sbp, siD);
-      for (int t = 0; t < nt; ++t) {
+      auto sweep_summary = [&](int t, bool pf) {
         const int tl = tile_len(S, t);
         __syncthreads();   // LDS free
-        if (!PF || t == 0) load_tile<SH>(sh, A.F, S.off + (int64_t)t * kTile, tl);
+        if (!pf || t == 0) load_tile<SH>(sh, A.F, S.off + (int64_t)t * kTile, tl);
         else commit();
-        if (PF && t + 1 < nt) issue(S.off + (int64_t)(t + 1) * kTile, tile_len(S, t + 1));
+        if (pf && t + 1 < nt) issue(S.off + (int64_t)(t + 1) * kTile, tile_len(S, t + 1));
         __syncthreads();
         Ts q[kB];
         const Tio* myrow = sh.lds + tid * TileShared<SH, Tio, Tc>::RP;
@@ -1157,6 +1197,27 @@ __global__ __launch_bounds__(SH::NT, REFINE ? TDT_REFINE_WAVES : SH::WAVES) void
         for (int i = 0; i < kB; ++i) q[i] = (Ts)myrow[i];
         tile_solve<SH, Ts, false, QUASI>(q, block_len<SH>(tl), Ts(0), Ts(0), KS, sbp, siD, sfw,
                                         sbw, &tsum[t][0], &tsum[t][1]);
+      };
+      if (S.gkf > 0) {
+        // full tiles: one wavefront per tile reads only the rows under the
+        // supports; a shorter last tile is swept (and stays in LDS)
+        const int nfull = (int)(S.n / kTile);
+        if (nfull < nt) sweep_summary(nt - 1, false);
+        else last_in_lds = false;
+        const int lane = tid & 63, w = tid >> 6;
+        const double* gf = A.gpack + S.goff + lane;
+        const double* gl = gf + S.gkf;
+        for (int t = w; t < nfull; t += kNW) {
+          const Tio* hd = A.F + S.off + (int64_t)t * kTile + lane;
+          double s1, s2;
+          ends_dot<Tio>(hd, hd + kTile - S.gkl, gf, gl, S.gkf, S.gkl, s1, s2);
+          if (lane == 0) {
+            tsum[t][0] = s1;
+            tsum[t][1] = s2;
+          }
+        }
+      } else {
+        for (int t = 0; t < nt; ++t) sweep_summary(t, PF);
       }
       __syncthreads();
       if (tid == 0) {
@@ -1202,8 +1263,8 @@ __global__ __launch_bounds__(SH::NT, REFINE ? TDT_REFINE_WAVES : SH::WAVES) void
       const int tl = tile_len(S, t);
       const double XLt = nt > 1 || QUASI ? tgh[t][0] : 0.0;
       const double XRt = nt > 1 || QUASI ? tgh[t][1] : 0.0;
-      // the last tile summarised is still in LDS
-      if ((!QUASI && nt == 1) || t < nt - 1) {
+      // the last tile summarised may still be in LDS
+      if ((!QUASI && nt == 1) || t < nt - 1 || !last_in_lds) {
         __syncthreads();   // LDS free
         if (PF && t < nt - 1) commit();
         else load_tile<SH>(sh, A.F, S.off + t0, tl);
@@ -1351,53 +1412,51 @@ template <typename Tio>
 struct BetaEndsArgs {
   const Tio* __restrict__ F;
   const SysDesc* __restrict__ sys;
-  const double* __restrict__ green;   // [2][kTile]: first row, last row
-  int64_t nitems;                     // right-hand sides x full tiles per right-hand side
-  int nfull;                          // full tiles per right-hand side
-  int kf, kl;                         // head of the first row, tail of the last row
+  const double* __restrict__ green;   // series: [2][kTile]: first row, last row
+  int64_t nitems;                     // series: right-hand sides x full tiles per right-hand side
+  int nfull;                          // series: full tiles per right-hand side
+  int kf, kl;                         // series: head of the first row, tail of the last row
   double* __restrict__ summ;          // [slot][2]
+  const int2* __restrict__ items;     // varlen: (system, full tile) per item, else null
+  const double* __restrict__ gpack;   // varlen: each system's head and tail entries
 };
 
 template <class SH, typename Tio>
 __global__ __launch_bounds__(kEndsNT) void k_beta_ends(BetaEndsArgs<Tio> A) {
   TDT_SHAPE(SH)
-  constexpr int U = 4;   // loads in flight per lane and row run
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const SysDesc S0 = load_sys(A.sys, 0);
-  const int nf = A.kf / 64, nl = A.kl / 64;
-  const double* gf = A.green + lane;
-  const double* gl = A.green + 2 * kTile - A.kl + lane;
   for (int64_t it = (int64_t)blockIdx.x * kEndsNW + w; it < A.nitems;
        it += (int64_t)gridDim.x * kEndsNW) {
-    const int64_t m = it / A.nfull;
-    const int t = (int)(it - m * A.nfull);
-    const Tio* head = A.F + S0.off + m * S0.stride + (int64_t)t * kTile + lane;
-    const Tio* tail = head + kTile - A.kl;
-    double s1 = 0.0, s2 = 0.0;
-    for (int j0 = 0; j0 < nf; j0 += U) {
-      double v[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) v[u] = j0 + u < nf ? (double)head[(j0 + u) * 64] : 0.0;
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (j0 + u < nf) s1 += v[u] * gf[(j0 + u) * 64];
+    // this item's tile, the supports and their entries
+    const Tio* head;
+    const double *gf, *gl;
+    int kf, kl;
+    int64_t sl;
+    if (A.items) {
+      const cptr<int> iv = as_const(reinterpret_cast<const int*>(A.items)) + 2 * it;
+      const int s = iv[0], t = iv[1];
+      const SysDesc S = load_sys(A.sys, s);
+      kf = S.gkf;
+      kl = S.gkl;
+      gf = A.gpack + S.goff;
+      gl = gf + kf;
+      head = A.F + S.off + (int64_t)t * kTile;
+      sl = tile_slot(S, 0, t, true);
+    } else {
+      const SysDesc S = load_sys(A.sys, 0);
+      const int64_t m = it / A.nfull;
+      const int t = (int)(it - m * A.nfull);
+      kf = A.kf;
+      kl = A.kl;
+      gf = A.green;
+      gl = A.green + 2 * kTile - kl;
+      head = A.F + S.off + m * S.stride + (int64_t)t * kTile;
+      sl = tile_slot(S, m, t, false);
     }
-    for (int j0 = 0; j0 < nl; j0 += U) {
-      double v[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) v[u] = j0 + u < nl ? (double)tail[(j0 + u) * 64] : 0.0;
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (j0 + u < nl) s2 += v[u] * gl[(j0 + u) * 64];
-    }
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-      s1 += __shfl_xor(s1, d, 64);
-      s2 += __shfl_xor(s2, d, 64);
-    }
+    double s1, s2;
+    ends_dot<Tio>(head + lane, head + kTile - kl + lane, gf + lane, gl + lane, kf, kl, s1, s2);
     if (lane == 0) {
-      const int64_t sl = tile_slot(S0, m, t, false);
       A.summ[2 * sl] = s1;
       A.summ[2 * sl + 1] = s2;
     }
@@ -2251,7 +2310,7 @@ template <class SH, typename Tio, typename Tc, bool REFINE, bool BWD, bool QUASI
 static void launch_sys(const LaunchSet& L, const TileArgs<Tio>& T, hipStream_t st) {
   SysArgs<Tio> A{T.F,         T.X,         T.sys,      T.vec64,  T.vec32,   T.tab64,
                  T.tab32,     L.sys_items, L.sys_bins, L.ttab,   L.ttab_n,  T.Xfwd,
-                 T.gpart,     T.iters,     T.max_iter, T.refine_tol};
+                 T.gpart,     T.iters,     T.max_iter, T.refine_tol, L.gpack};
   hipLaunchKernelGGL((k_sys<SH, Tio, Tc, REFINE, BWD, QUASI>), dim3((unsigned)L.n_bins), dim3(SH::NT),
                      0, st, A);
 }
@@ -2285,8 +2344,11 @@ static void launch_beta_ends(const LaunchSet& L, const Tio* F, hipStream_t st) {
   auto kern = k_beta_ends<SH, Tio>;
   static int per_cu = resident_per_cu(kern, kEndsNT);
   const int64_t cap = grid_cap(per_cu, L.wg_per_cu);
-  BetaEndsArgs<Tio> B{F, L.sys, L.green, L.n_beta, L.nfull, L.green_kf, L.green_kl, L.summ};
-  const int64_t want = (L.n_beta + kEndsNW - 1) / kEndsNW;
+  const bool varlen = L.ends_items != nullptr;
+  const int64_t n = varlen ? L.n_ends : L.n_beta;
+  BetaEndsArgs<Tio> B{F,       L.sys,  L.green, n,      L.nfull, L.green_kf, L.green_kl,
+                      L.summ,  varlen ? L.ends_items : nullptr, L.gpack};
+  const int64_t want = (n + kEndsNW - 1) / kEndsNW;
   const int64_t lim = L.wg_per_cu > 0 ? cap : ((int64_t)1 << 30);
   const unsigned grid = (unsigned)(want < lim ? want : lim);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(kEndsNT), 0, st, B);
@@ -2336,7 +2398,7 @@ static hipError_t run_solve(const LaunchSet& L, const void* F, void* X, const vo
   // double sweep costs less than a float solve plus refinement, and the
   // values outside each tile then come out exact in double).
   using Ts = typename std::conditional<REFINE, double, Tc>::type;
-  if (L.n_p1 > 0) {
+  if (L.n_grid > 0) {
     if (L.green) {
       if (L.n_beta > 0) {
         if (L.green_kf > 0)
@@ -2349,8 +2411,10 @@ static hipError_t run_solve(const LaunchSet& L, const void* F, void* X, const vo
         launch_tile<SH, Tio, Ts, false, true, false, QUASI>(A, L.n_last, 0, 1, L.wg_per_cu, st);
       }
     } else {
+      if (L.n_ends > 0) launch_beta_ends<SH, Tio>(L, static_cast<const Tio*>(F), st);
       A.items = L.p1_items;
-      launch_tile<SH, Tio, Ts, false, true, false, QUASI>(A, L.n_p1, 0, 0, L.wg_per_cu, st);
+      if (L.n_p1 > 0)
+        launch_tile<SH, Tio, Ts, false, true, false, QUASI>(A, L.n_p1, 0, 0, L.wg_per_cu, st);
     }
     if (L.ev) (void)hipEventRecord(L.ev[1], st);
     launch_grid<QUASI>(L, F, X, Xfwd, sizeof(Tio) == 4 ? 1 : 0, st);

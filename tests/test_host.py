@@ -248,3 +248,26 @@ def test_poisson2d_refinement_refused_before_any_device_call():
     st = L.tdt_poisson2d_create(8191, 8191, 1.0 / 8192, 1.0 / 8192, _lib.DTYPES["f32_refine"],
                                 ctypes.byref(h))
     assert st == _lib.TDT_ERR_NOT_CONVERGED and not h.value
+
+
+@pytest.mark.parametrize("t", [(-0.9, 2.5, -1.1), (-1.0, 2.01, -1.0), (0.3, -1.0, 0.45),
+                               (-0.5, -3.2, 0.7), (1.0, -18.0, 1.0), (1.0, -2.0000006, 1.0)])
+@pytest.mark.parametrize("L", [8192, 4096])
+def test_green_support_bound_against_oracle_rows(t, L):
+    """The supports a varlen plan derives from the pivots' decay, without
+    forming the rows: at least the minimal ones, dropping at most 2^-60 of
+    each row's 1-norm (rows from the oracle's long double solves); none for
+    the nearly singular matrix, whose rows do not decay within the tile."""
+    import oracle
+    a, b, c = t
+    (kf, kl), (bf, bl) = tdt.green_support(a, b, c, L, bound=True)
+    if b == -2.0000006:
+        assert (bf, bl) == (0, 0)
+        return
+    assert bf >= kf and bl >= kl
+    E = np.zeros((2, L))
+    E[0, 0] = 1.0
+    E[1, -1] = 1.0
+    R = np.abs(oracle.solve(E, c, b, a, precision="ld"))
+    for k, r in ((bf, R[0]), (bl, R[1][::-1])):
+        assert r[k:].sum() <= 2.0 ** -60 * r.sum() * (1 + 1e-6), (k, r[k:].sum() / r.sum())
