@@ -209,7 +209,7 @@ def run_mode(tdt, d, F, X, mode, steps, warmup, torch, opts=None):
     plan = make_plan(tdt, d, mode)
     if opts is None:
         plan.reserve(d.get("M", 1))
-        tuned = plan.autotune(F, X, cache=False)
+        tuned = plan.autotune(F, X, cache=False, adjoint=d.get("adjoint", False))
     else:
         for k, v in opts.items():
             if k != "whole_max_tiles" or d["kind"] == "varlen":

@@ -467,11 +467,15 @@ tdt_status_t tdt_plan_get_option(tdt_plan_t plan, tdt_option_t opt, int64_t *val
  * rounded up to powers of two): the file named by the environment variable
  * TDT_TUNE_CACHE, else $HOME/.cache/tdt/autotune.json.  A cached choice is
  * applied without timing.  flags: TDT_TUNE_NO_CACHE neither reads nor
- * writes the file; TDT_TUNE_FORCE times again and replaces the entry.
+ * writes the file; TDT_TUNE_FORCE times again and replaces the entry;
+ * TDT_TUNE_ADJOINT times each trial as a solve followed by
+ * tdt_solve_backward (gX = F, into buffers the tuner allocates and frees),
+ * for plans used in training loops (its own cache entry).
  * *best_ms (may be NULL): the chosen shape's time per solve (0 when taken
  * from the cache). */
 #define TDT_TUNE_NO_CACHE 1
 #define TDT_TUNE_FORCE 2
+#define TDT_TUNE_ADJOINT 4
 tdt_status_t tdt_plan_autotune(tdt_plan_t plan, const void *F, void *X, int64_t M,
                                hipStream_t stream, int flags, double *best_ms);
 

@@ -109,8 +109,9 @@ class _PlanBase:
                    "tdt_plan_get_option")
         return v.value
 
-    def _autotune(self, F, X, M, cache=True, force=False, stream=None) -> dict:
-        flags = (0 if cache else _lib.TUNE_NO_CACHE) | (_lib.TUNE_FORCE if force else 0)
+    def _autotune(self, F, X, M, cache=True, force=False, stream=None, adjoint=False) -> dict:
+        flags = ((0 if cache else _lib.TUNE_NO_CACHE) | (_lib.TUNE_FORCE if force else 0) |
+                 (_lib.TUNE_ADJOINT if adjoint else 0))
         ms = ctypes.c_double(0.0)
         _lib.check(_lib.lib().tdt_plan_autotune(self._h, ctypes.c_void_p(F.data_ptr()),
                                                 ctypes.c_void_p(X.data_ptr()), int(M),
@@ -180,16 +181,18 @@ class Plan(_PlanBase):
                                         _stream_handle(stream)), "tdt_solve")
         return X
 
-    def autotune(self, F, X=None, cache=True, force=False, stream=None) -> dict:
+    def autotune(self, F, X=None, cache=True, force=False, stream=None,
+                 adjoint=False) -> dict:
         """Time the launch shapes on F (X is overwritten with the solution)
-        and keep the fastest; cached per device and problem size."""
+        and keep the fastest; cached per device and problem size.  adjoint:
+        time each trial as a solve plus its adjoint."""
         torch = _torch()
         M = F.numel() // self.N
         if X is None:
             X = torch.empty_like(F)
         _check_tensor(F, _data_dtype(self.dtype), M * self.N, "F")
         _check_tensor(X, _data_dtype(self.dtype), M * self.N, "X")
-        return self._autotune(F, X, M, cache, force, stream)
+        return self._autotune(F, X, M, cache, force, stream, adjoint)
 
     def backward(self, gX, X, gF=None, gt=None, stream=None):
         """gF = T^{-T} gX and gt = (dL/dt_-1, dL/dt_0, dL/dt_1[, dL/dpsi,
@@ -262,15 +265,17 @@ class VarlenPlan(_PlanBase):
                                                _stream_handle(stream)), "tdt_solve_varlen")
         return X
 
-    def autotune(self, F, X=None, cache=True, force=False, stream=None) -> dict:
+    def autotune(self, F, X=None, cache=True, force=False, stream=None,
+                 adjoint=False) -> dict:
         """Time the launch shapes (whole-system threshold, workgroups per CU)
-        on F (X is overwritten with the solution) and keep the fastest."""
+        on F (X is overwritten with the solution) and keep the fastest;
+        adjoint: time each trial as a solve plus its adjoint."""
         torch = _torch()
         if X is None:
             X = torch.empty_like(F)
         _check_tensor(F, _data_dtype(self.dtype), self.total, "F")
         _check_tensor(X, _data_dtype(self.dtype), self.total, "X")
-        return self._autotune(F, X, 1, cache, force, stream)
+        return self._autotune(F, X, 1, cache, force, stream, adjoint)
 
     def backward(self, gX, X, gF=None, gt=None, stream=None):
         """gF = T_s^{-T} gX per system and gt[s] = (dL/dt_-1, dL/dt_0,
@@ -316,8 +321,9 @@ class GeneralPlan(_PlanBase):
     def solve(self, F, X=None, stream=None):
         return Plan.solve(self, F, X, stream)
 
-    def autotune(self, F, X=None, cache=True, force=False, stream=None) -> dict:
-        return Plan.autotune(self, F, X, cache, force, stream)
+    def autotune(self, F, X=None, cache=True, force=False, stream=None,
+                 adjoint=False) -> dict:
+        return Plan.autotune(self, F, X, cache, force, stream, adjoint)
 
     def backward(self, gX, X, gF=None, g=None, stream=None):
         """gF = A^{-T} gX and g = [3][N]: (dL/da, dL/db, dL/dc) summed over

@@ -51,6 +51,7 @@ OPTIONS = {"whole_max_tiles": 0, "wg_per_cu": 1, "max_refine": 2, "shape": 3}
 SHAPES = [(16, 512), (8, 512), (16, 256)]
 TUNE_NO_CACHE = 1
 TUNE_FORCE = 2
+TUNE_ADJOINT = 4
 
 
 def _flags() -> list:

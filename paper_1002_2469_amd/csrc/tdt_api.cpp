@@ -72,22 +72,25 @@ struct tdt_plan_s {
   double* dgreen[2] = {nullptr, nullptr};   // series with several tiles: [2][L]
   // rows of a tile the first pass reads from the head and the tail (0: all)
   int green_kf[2] = {0, 0}, green_kl[2] = {0, 0};
-  // varlen: the systems' Green row supports, packed (SysDesc goff, gkf, gkl),
-  // and the full tiles whose summaries use them
+  // varlen: the systems' Green row supports, packed (SysDesc goff, gkf, gkl)
   double* dgpack[2] = {nullptr, nullptr};
-  int2* dends = nullptr;
-  int64_t n_ends = 0;
   double* dttab[2] = {nullptr, nullptr};    // per tile position table [2][ttab_n]
   int64_t ttab_n = 0;
-  // varlen launch lists
+  // varlen launch lists: [0] forward solves, [1] the adjoint, which solves
+  // only one-tile systems whole (its whole-system kernel holds no prefetched
+  // tile: the register budget goes to the gradient sums, so it streams
+  // multi-tile systems slower than the tile kernels)
   std::vector<int64_t> order;   // systems, largest first
   int sys_max_tiles = tdt::kSysMaxTilesDefault;
-  int2* dp1 = nullptr;
-  int2* dfin = nullptr;
-  int* dgrid = nullptr;
-  int* dwhole = nullptr;
-  int* dbins = nullptr;
-  int64_t n_p1 = 0, n_fin = 0, n_grid = 0, n_whole = 0, n_bins = 0;
+  struct Lists {
+    int2* p1 = nullptr;     // first pass by sweeps: (system, tile)
+    int2* ends = nullptr;   // first pass from the Green rows' supports: (system, full tile)
+    int2* fin = nullptr;    // final pass: (system, tile)
+    int* grid = nullptr;    // systems with an interface pass across tiles
+    int* whole = nullptr;   // systems solved whole by one workgroup each, by bins
+    int* bins = nullptr;
+    int64_t n_p1 = 0, n_ends = 0, n_fin = 0, n_grid = 0, n_whole = 0, n_bins = 0;
+  } lists[2];
   int64_t vslots = 0, vfslots = 0;
   // workspace
   int64_t ws_slots = 0, ws_fslots = 0;
@@ -633,13 +636,16 @@ void destroy(tdt_plan_s* p) {
     (void)hipFree(p->dggreen[k]);
   }
   (void)hipFree(p->dstr);
-  for (int k = 0; k < 2; ++k) (void)hipFree(p->dgpack[k]);
-  (void)hipFree(p->dends);
-  (void)hipFree(p->dp1);
-  (void)hipFree(p->dfin);
-  (void)hipFree(p->dgrid);
-  (void)hipFree(p->dwhole);
-  (void)hipFree(p->dbins);
+  for (int k = 0; k < 2; ++k) {
+    (void)hipFree(p->dgpack[k]);
+    tdt_plan_s::Lists& q = p->lists[k];
+    (void)hipFree(q.p1);
+    (void)hipFree(q.ends);
+    (void)hipFree(q.fin);
+    (void)hipFree(q.grid);
+    (void)hipFree(q.whole);
+    (void)hipFree(q.bins);
+  }
   (void)hipFree(p->iters);
   free_workspace(p);
   delete p;
@@ -650,12 +656,13 @@ void destroy(tdt_plan_s* p) {
 // the three kernels: first pass over their tiles, interface pass, final pass
 // over their tiles in the reverse of the first pass's order (the most
 // recently read, still cached, tiles first).
-tdt_status_t build_varlen_lists(tdt_plan_s* p) {
+tdt_status_t build_lists(tdt_plan_s* p, int dir, int max_tiles) {
+  tdt_plan_s::Lists& q = p->lists[dir];
   std::vector<int2> p1, fin;
   std::vector<int> grid, whole_sys;
   for (int64_t s : p->order) {
     const int nt = p->hsys[0][s].ntiles;
-    if (nt <= p->sys_max_tiles) {
+    if (nt <= max_tiles) {
       whole_sys.push_back((int)s);
     } else {
       for (int t = 0; t < nt; ++t) p1.push_back(make_int2((int)s, t));
@@ -715,28 +722,31 @@ tdt_status_t build_varlen_lists(tdt_plan_s* p) {
       bins.push_back((int)whole.size());
     }
   }
-  (void)hipFree(p->dends);
-  p->dends = nullptr;
-  p->n_ends = (int64_t)ends.size();
-  (void)hipFree(p->dp1);
-  (void)hipFree(p->dfin);
-  (void)hipFree(p->dgrid);
-  (void)hipFree(p->dwhole);
-  (void)hipFree(p->dbins);
-  p->dp1 = p->dfin = nullptr;
-  p->dgrid = p->dwhole = p->dbins = nullptr;
-  p->n_p1 = (int64_t)p1.size();
-  p->n_fin = (int64_t)fin.size();
-  p->n_grid = (int64_t)grid.size();
-  p->n_whole = (int64_t)whole.size();
-  p->n_bins = bins.empty() ? 0 : (int64_t)bins.size() - 1;
-  tdt_status_t st = dev_upload(&p->dp1, p1.data(), p1.size());
-  if (st == TDT_OK) st = dev_upload(&p->dends, ends.data(), ends.size());
-  if (st == TDT_OK) st = dev_upload(&p->dfin, fin.data(), fin.size());
-  if (st == TDT_OK) st = dev_upload(&p->dgrid, grid.data(), grid.size());
-  if (st == TDT_OK) st = dev_upload(&p->dwhole, whole.data(), whole.size());
-  if (st == TDT_OK) st = dev_upload(&p->dbins, bins.data(), bins.size());
+  (void)hipFree(q.p1);
+  (void)hipFree(q.ends);
+  (void)hipFree(q.fin);
+  (void)hipFree(q.grid);
+  (void)hipFree(q.whole);
+  (void)hipFree(q.bins);
+  q = tdt_plan_s::Lists{};
+  q.n_p1 = (int64_t)p1.size();
+  q.n_ends = (int64_t)ends.size();
+  q.n_fin = (int64_t)fin.size();
+  q.n_grid = (int64_t)grid.size();
+  q.n_whole = (int64_t)whole.size();
+  q.n_bins = bins.empty() ? 0 : (int64_t)bins.size() - 1;
+  tdt_status_t st = dev_upload(&q.p1, p1.data(), p1.size());
+  if (st == TDT_OK) st = dev_upload(&q.ends, ends.data(), ends.size());
+  if (st == TDT_OK) st = dev_upload(&q.fin, fin.data(), fin.size());
+  if (st == TDT_OK) st = dev_upload(&q.grid, grid.data(), grid.size());
+  if (st == TDT_OK) st = dev_upload(&q.whole, whole.data(), whole.size());
+  if (st == TDT_OK) st = dev_upload(&q.bins, bins.data(), bins.size());
   return st;
+}
+
+tdt_status_t build_varlen_lists(tdt_plan_s* p) {
+  const tdt_status_t st = build_lists(p, 0, p->sys_max_tiles);
+  return st == TDT_OK ? build_lists(p, 1, std::min(p->sys_max_tiles, 1)) : st;
 }
 
 // Build both descriptor sets (T and T^T) and upload everything.  sizes and
@@ -1241,18 +1251,19 @@ tdt_status_t launch_set(tdt_plan_s* p, int dir, bool adjoint, int64_t M, tdt::La
     L.green_kf = L.green_kl = 0;
     L.n_beta = L.n_last = 0;
     L.nfull = 0;
-    L.p1_items = p->dp1;
-    L.fin_items = p->dfin;
-    L.grid_items = p->dgrid;
-    L.sys_items = p->dwhole;
-    L.sys_bins = p->dbins;
-    L.n_bins = p->n_bins;
-    L.n_p1 = p->n_p1;
-    L.n_fin = p->n_fin;
-    L.n_grid = p->n_grid;
-    L.n_sys = p->n_whole;
-    L.ends_items = p->n_ends > 0 ? p->dends : nullptr;
-    L.n_ends = p->n_ends;
+    const tdt_plan_s::Lists& q = p->lists[dir];
+    L.p1_items = q.p1;
+    L.fin_items = q.fin;
+    L.grid_items = q.grid;
+    L.sys_items = q.whole;
+    L.sys_bins = q.bins;
+    L.n_bins = q.n_bins;
+    L.n_p1 = q.n_p1;
+    L.n_fin = q.n_fin;
+    L.n_grid = q.n_grid;
+    L.n_sys = q.n_whole;
+    L.ends_items = q.n_ends > 0 ? q.ends : nullptr;
+    L.n_ends = q.n_ends;
     L.gpack = p->dgpack[dir];
     slots = p->vslots;
     fslots = adjoint ? p->vfslots : 0;
@@ -1983,14 +1994,41 @@ tdt_status_t tdt_plan_autotune(tdt_plan_t p, const void* F, void* X, int64_t M,
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
     return TDT_ERR_CAPTURE;
-  const std::string key = tune::key_of(p, M);
+  const bool adjoint = (flags & TDT_TUNE_ADJOINT) != 0;
+  const std::string key = tune::key_of(p, M) + (adjoint ? "|adj" : "");
   const bool use_cache = !(flags & TDT_TUNE_NO_CACHE);
   if (use_cache && !(flags & TDT_TUNE_FORCE)) {
     tune::Choice c;
     if (tune::lookup(key, c)) return tune::apply(p, c);
   }
+  // with the adjoint, each trial also runs tdt_solve_backward (gX = F, the
+  // forward solution X) into buffers of the tuner's own
+  void* gF = nullptr;
+  double* gt = nullptr;
+  if (adjoint) {
+    const size_t n = (size_t)(p->varlen ? p->total : M * p->N);
+    if (hipMalloc(&gF, n * elem_size(p->dtype)) != hipSuccess) return TDT_ERR_OOM;
+    if (hipMalloc(reinterpret_cast<void**>(&gt), (size_t)p->S * tdt::kGradN * sizeof(double) +
+                                                     (p->general ? 3 * (size_t)p->N * 8 : 0)) !=
+        hipSuccess) {
+      (void)hipFree(gF);
+      return TDT_ERR_OOM;
+    }
+  }
+  struct Free {
+    void* a;
+    void* b;
+    ~Free() {
+      if (a || b) (void)hipDeviceSynchronize();
+      (void)hipFree(a);
+      (void)hipFree(b);
+    }
+  } free_bufs{gF, gt};
   auto solve = [&]() {
-    return p->varlen ? tdt_solve_varlen(p, F, X, stream) : tdt_solve(p, F, X, M, stream);
+    tdt_status_t st =
+        p->varlen ? tdt_solve_varlen(p, F, X, stream) : tdt_solve(p, F, X, M, stream);
+    if (st >= 0 && adjoint) st = tdt_solve_backward(p, F, X, gF, gt, M, stream);
+    return st;
   };
   std::vector<tune::Choice> cands;
   const int whole[] = {0, 1, 2, 4, 8, 16};
@@ -2040,7 +2078,8 @@ tdt_status_t tdt_plan_autotune(tdt_plan_t p, const void* F, void* X, int64_t M,
   if (st < 0) return st;
   if (best_ms) *best_ms = cands[best].ms;
   if (use_cache) tune::store(key, cands[best]);
-  return solve();   // leave X holding the solution under the chosen shape
+  // leave X holding the solution under the chosen shape
+  return p->varlen ? tdt_solve_varlen(p, F, X, stream) : tdt_solve(p, F, X, M, stream);
 }
 
 tdt_status_t tdt_block_constants(double t_m1, double t_0, double t_1, int B, double* out) {

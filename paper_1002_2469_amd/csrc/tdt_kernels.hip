@@ -858,10 +858,12 @@ __device__ __forceinline__ void solve_tile_lds(TileShared<SH, Tio, Tc>& sh, int 
 
 // Stores the solved tile from LDS (coalesced).  BWD: also forms this tile's
 // t-gradient partial sums against the forward solution Xfwd and writes their
-// negatives to gpart[0..2] (one barrier pair inside).  QUASI (quasi-Toeplitz
-// plans, whose partials have 5 components): 0 to the corner components
-// gpart[3..4], and the rows next to the corner rows read those rows' forward
-// solution; the corner rows themselves are stored by the interface pass.
+// negatives to gpart[0..2].  Each lane loads the forward solution at its own
+// elements; the neighbours x_{e-1}, x_{e+1} come from the adjacent lanes by
+// shuffles, and only the first and last lane of a wavefront load theirs.  QUASI (quasi-Toeplitz plans, whose partials have 5
+// components): 0 to the corner components gpart[3..4], and the rows next to
+// the corner rows read those rows' forward solution; the corner rows
+// themselves are stored by the interface pass.  One barrier inside (BWD).
 template <class SH, typename Tio, typename Tc, bool BWD, bool QUASI>
 __device__ __forceinline__ void store_tile(TileShared<SH, Tio, Tc>& sh, Tio* X, const Tio* Xfwd,
                                            int64_t base, int64_t t0, int tl, int64_t n,
@@ -869,7 +871,6 @@ __device__ __forceinline__ void store_tile(TileShared<SH, Tio, Tc>& sh, Tio* X, 
   TDT_SHAPE(SH)
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   constexpr int lstride = lds_stride<SH, Tio>();
-  double s0 = 0.0, s1 = 0.0, sm1 = 0.0;
   const __amdgpu_buffer_rsrc_t dst = make_rsrc(X + base, (int64_t)tl * sizeof(Tio));
   // adjoint: the forward solution over this tile and one row on each side
   // that lies inside the system (rows outside read as 0)
@@ -879,29 +880,31 @@ __device__ __forceinline__ void store_tile(TileShared<SH, Tio, Tc>& sh, Tio* X, 
   const Tio* lr = sh.lds + opaque(lds_base<SH, Tio>());
   const int vs = opaque(tid * (int)sizeof(Tio));
 #pragma unroll
-  for (int j = 0; j < kB; ++j) {
-    const int e = j * kNT + tid;
-    const Tio gval = lr[j * lstride];
-    buf_store<Tio, TDT_STORE_AUX>(dst, vs + j * kNT * (int)sizeof(Tio), gval);
-    if constexpr (BWD) {
-      const int xo = vs + (j * kNT + lo) * (int)sizeof(Tio);
-      const double xe = (double)buf_load<Tio>(xf, xo);
-      const double xn = (double)buf_load<Tio>(xf, xo + (int)sizeof(Tio));
-      const double xq = (double)buf_load<Tio>(xf, xo - (int)sizeof(Tio));
-      const double gv = e < tl ? (double)gval : 0.0;
-      s0 += gv * xe;
-      s1 += gv * xn;
-      sm1 += gv * xq;
-    }
-  }
+  for (int j = 0; j < kB; ++j)
+    buf_store<Tio, TDT_STORE_AUX>(dst, vs + j * kNT * (int)sizeof(Tio), lr[j * lstride]);
   if constexpr (BWD) {
+    // four rows at a time: all of them at once would hold too many loads in
+    // registers (spills)
+    double s0 = 0.0, s1 = 0.0, sm1 = 0.0;
+#pragma unroll 4
+    for (int j = 0; j < kB; ++j) {
+      const int xo = vs + (j * kNT + lo) * (int)sizeof(Tio);
+      const Tio xt = buf_load<Tio>(xf, xo);
+      Tio xn = __shfl_down(xt, 1, 64);   // element e + 1
+      Tio xq = __shfl_up(xt, 1, 64);     // element e - 1
+      if (lane == 63) xn = buf_load<Tio>(xf, xo + (int)sizeof(Tio));
+      if (lane == 0) xq = buf_load<Tio>(xf, xo - (int)sizeof(Tio));
+      const double gv = j * kNT + tid < tl ? (double)lr[j * lstride] : 0.0;
+      s0 += gv * (double)xt;
+      s1 += gv * (double)xn;
+      sm1 += gv * (double)xq;
+    }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
       s0 += __shfl_xor(s0, d, 64);
       s1 += __shfl_xor(s1, d, 64);
       sm1 += __shfl_xor(sm1, d, 64);
     }
-    __syncthreads();
     if (lane == 0) { sh.red[w][0] = sm1; sh.red[w][1] = s0; sh.red[w][2] = s1; }
     __syncthreads();
     if (tid == 0) {
@@ -986,7 +989,7 @@ __global__ __launch_bounds__(SH::NT, REFINE ? TDT_REFINE_WAVES : SH::WAVES) void
   const int lbase = lds_base<SH, Tio>();
   constexpr int lstride = lds_stride<SH, Tio>();
   auto item_of = [&](int64_t k) { return A.reverse ? A.nitems - 1 - k : k; };
-  constexpr bool PF = !REFINE || TDT_REFINE_PREFETCH;
+  constexpr bool PF = !REFINE && !BWD;
   int it_max = 0;        // refinement record of this workgroup
   float est_max = 0.0f;
   int64_t k = blockIdx.x;
@@ -1151,7 +1154,7 @@ __global__ __launch_bounds__(SH::NT, REFINE ? TDT_REFINE_WAVES : SH::WAVES) void
   constexpr int lstride = lds_stride<SH, Tio>();
   // The next tile of the system is loaded into registers while the current
   // one is solved, unless the refinement solve needs those registers.
-  constexpr bool PF = !REFINE;
+  constexpr bool PF = !REFINE && !BWD;
   Tio pv[kB];
   auto issue = [&](int64_t base, int tl) {
     const __amdgpu_buffer_rsrc_t src = make_rsrc(A.F + base, (int64_t)tl * sizeof(Tio));

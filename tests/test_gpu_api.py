@@ -212,3 +212,31 @@ def test_autotune_choice_cache_and_result(tmp_path, monkeypatch):
     r3 = sp.autotune(Fs, force=True)
     assert r3["ms"] > 0
     assert len(json.loads(cache.read_text())["entries"]) == 2
+
+
+def test_autotune_with_adjoint(tmp_path, monkeypatch):
+    """TDT_TUNE_ADJOINT times each trial as a solve plus its adjoint, keeps
+    its own cache entry, and leaves the plan at parity in both directions."""
+    import json
+    tdt = _tdt()
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("TDT_TUNE_CACHE", str(cache))
+    rng = np.random.default_rng(6)
+    sizes = np.array([16384, 16384, 700, 40000])
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    tm1, t0, t1 = rng.uniform(-1, -0.5, 4), rng.uniform(2.5, 4.0, 4), rng.uniform(-1, -0.5, 4)
+    F = rng.standard_normal(int(off[-1]))
+    G = rng.standard_normal(int(off[-1]))
+    plan = tdt.VarlenPlan(off, tm1, t0, t1, "f64")
+    Fd = to_dev(F)
+    res = plan.autotune(Fd, adjoint=True)
+    assert res["ms"] > 0
+    (key, _), = json.loads(cache.read_text())["entries"].items()
+    assert key.endswith("|adj")
+    X = plan.solve(Fd)
+    gF, gt = plan.backward(to_dev(G), X)
+    Xr = oracle.solve_varlen(F, off, tm1, t0, t1)
+    gFr, gtr = oracle.adjoint_varlen(G, Xr, off, tm1, t0, t1)
+    assert oracle.rel_err_rows(to_host(X), Xr, off).max() <= 1e-12
+    assert oracle.rel_err_rows(to_host(gF), gFr, off).max() <= 1e-12
+    assert np.max(np.abs(to_host(gt) - gtr) / np.maximum(1.0, np.abs(gtr))) <= 1e-11
