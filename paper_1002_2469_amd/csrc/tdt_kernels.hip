@@ -135,9 +135,7 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, int off, T v
 // The solution is stored non-temporal: it is not read again by this solve,
 // and lines that do not linger dirty in the caches leave the next read of the
 // right-hand side (the first pass of the next solve) at full speed.
-#ifndef TDT_STORE_AUX
-#define TDT_STORE_AUX 2
-#endif
+constexpr int kStoreAux = 2;
 
 // The segment of no rows: its "first row" is the value right of it and its
 // "last row" the value left of it, so that merging it on either side of a
@@ -655,12 +653,11 @@ __device__ __forceinline__ void prefetch(const TileArgs<Tio>& A, int64_t item,
   }
 }
 
-#ifndef TDT_REFINE_WAVES
-#define TDT_REFINE_WAVES kMinWavesPerSimd
-#endif
-#ifndef TDT_REFINE_PREFETCH
-#define TDT_REFINE_PREFETCH 0
-#endif
+// Occupancy target of the refinement kernels.  They hold no prefetched next
+// tile: the register budget goes to the double iterate, and a build that
+// prefetched (16 more doubles per lane) spilled and ran the 2^26-row final
+// pass at 330-370 us against 213-228 us without.
+constexpr int kRefineWaves = kMinWavesPerSimd;
 
 // A workgroup's refinement record, published once when it exits: rec[0] =
 // most float solves of any tile, rec[1] = bits of the largest estimated
@@ -881,7 +878,7 @@ __device__ __forceinline__ void store_tile(TileShared<SH, Tio, Tc>& sh, Tio* X, 
   const int vs = opaque(tid * (int)sizeof(Tio));
 #pragma unroll
   for (int j = 0; j < kB; ++j)
-    buf_store<Tio, TDT_STORE_AUX>(dst, vs + j * kNT * (int)sizeof(Tio), lr[j * lstride]);
+    buf_store<Tio, kStoreAux>(dst, vs + j * kNT * (int)sizeof(Tio), lr[j * lstride]);
   if constexpr (BWD) {
     // four rows at a time: all of them at once would hold too many loads in
     // registers (spills)
@@ -981,7 +978,7 @@ __device__ __forceinline__ void store_corner(Tio* X, const Tio* Xfwd, double* cg
 //   BWD            : also accumulates the t-gradient partial sums against the
 //                    forward solution Xfwd (the tile solves T^T gF = gX).
 template <class SH, typename Tio, typename Tc, bool REFINE, bool SUMMARY, bool BWD, bool QUASI>
-__global__ __launch_bounds__(SH::NT, REFINE ? TDT_REFINE_WAVES : SH::WAVES) void k_tile(
+__global__ __launch_bounds__(SH::NT, REFINE ? kRefineWaves : SH::WAVES) void k_tile(
     TileArgs<Tio> A) {
   TDT_SHAPE(SH)
   __shared__ TileShared<SH, Tio, Tc> sh;
@@ -1141,7 +1138,7 @@ __device__ __forceinline__ void lane_table(const SysDesc& S, const double* tab64
 // Summaries are computed in double for the refinement path (as in the
 // multi-kernel path), in the data precision otherwise.
 template <class SH, typename Tio, typename Tc, bool REFINE, bool BWD, bool QUASI>
-__global__ __launch_bounds__(SH::NT, REFINE ? TDT_REFINE_WAVES : SH::WAVES) void k_sys(
+__global__ __launch_bounds__(SH::NT, REFINE ? kRefineWaves : SH::WAVES) void k_sys(
     SysArgs<Tio> A) {
   TDT_SHAPE(SH)
   using Ts = typename std::conditional<REFINE, double, Tc>::type;
