@@ -965,10 +965,12 @@ __device__ __forceinline__ void store_corner(Tio* X, const Tio* Xfwd, double* cg
   }
 }
 
-// Persistent workgroups over tiles; each workgroup prefetches its next tile
-// into registers while it solves the current one (the refinement kernel
-// loads each tile at the top of its iteration instead, trading latency
-// hiding for registers).
+// Workgroups over tiles: by default one tile each (latency hidden by the
+// other resident workgroups, whose loads overlap this one's solve and
+// stores), or a grid capped per CU whose workgroups loop over tiles.  Each
+// iteration loads its tile at the top; a copy that held the next tile in
+// registers ran no faster with one tile per workgroup and spilled in the
+// refinement and adjoint variants.
 //   SUMMARY = true : first pass over a tile of a multi-tile system: writes the
 //                    tile's (y_first, y_last) of its zero-boundary problem.
 //   SUMMARY = false: solves the tile given the values just outside it (zero
@@ -986,7 +988,7 @@ __global__ __launch_bounds__(SH::NT, REFINE ? kRefineWaves : SH::WAVES) void k_t
   const int lbase = lds_base<SH, Tio>();
   constexpr int lstride = lds_stride<SH, Tio>();
   auto item_of = [&](int64_t k) { return A.reverse ? A.nitems - 1 - k : k; };
-  constexpr bool PF = !REFINE && !BWD;
+  constexpr bool PF = false;   // one tile per workgroup: nothing to fetch ahead
   int it_max = 0;        // refinement record of this workgroup
   float est_max = 0.0f;
   int64_t k = blockIdx.x;
@@ -2378,7 +2380,7 @@ static void launch_grid(const LaunchSet& L, const void* F, void* X, const void* 
 template <class SH, typename Tio, typename Tc, bool REFINE, bool BWD, bool QUASI>
 static hipError_t run_solve(const LaunchSet& L, const void* F, void* X, const void* Xfwd,
                             hipStream_t st) {
-  TileArgs<Tio> A;
+  TileArgs<Tio> A{};
   A.F = static_cast<const Tio*>(F);
   A.X = static_cast<Tio*>(X);
   A.sys = L.sys;
