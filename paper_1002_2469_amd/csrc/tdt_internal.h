@@ -67,7 +67,13 @@ struct SysDesc {
   // goff of the plan's packed array), or gkf = gkl = 0 (summaries by sweeps)
   int64_t goff;
   int32_t gkf, gkl;
+  // series plans of 8193 to 16384 tiles: the interface pass runs over pairs
+  // of adjacent tiles, with the end values of a full pair and of the last one
+  double pairK[4], lpairK[4];
 };
+// The pair interface pass: threads, and pairs per thread (2 kPairR tiles)
+constexpr int kPairNT = 512;
+constexpr int kPairR = 16;
 
 // Slot of tile t of a system: a varlen plan adds the system's slot0; a
 // series plan uses tslots slots per right-hand side m.
@@ -122,6 +128,7 @@ struct LaunchSet {
   const double* gpack;
   int nfull;
   int max_ntiles;          // most tiles of any system (selects the interface kernel)
+  int pairs;               // series of 8193..16384 tiles: interface pass over tile pairs
   const double* ttab;      // per tile position: beta_{t-1}, 1/(1 - Pf beta_{t-1}) ([2][ttab_n])
   int64_t ttab_n;
   double* summ;

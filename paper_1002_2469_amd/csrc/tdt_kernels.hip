@@ -1903,6 +1903,128 @@ __global__ __launch_bounds__(NTG) void k_grid_affine(GridArgs A) {
   }
 }
 
+// The interface pass of a series of 8193 to 16384 tiles (a 2^26-row system
+// in 4096-row tiles): over pairs of adjacent tiles, each of 512 threads
+// taking 16 pairs, as the kernel above takes 16 tiles.  A pair's summary is
+// its two tiles' merged (the 2x2 elimination at their junction with zero
+// outside values); the summaries wait in LDS (8192 pairs: 128 KiB), so that
+// the registers hold only the scans' per-pair values.  Once the scans have
+// given each pair its two outside values, the same 2x2 system gives the two
+// unknowns at the junction, the inner outside values of the two tiles (the
+// dichotomy step one level down).  Tile t = 2q + k of pair q sits at slot
+// (t % 2R) tq + t / 2R; the plan's table runs over pair positions
+// (q % R) tq + q / R.
+template <int NTG, int R>
+__global__ __launch_bounds__(NTG) void k_grid_pairs(GridArgs A) {
+  __shared__ GridShared<NTG> sh;
+  __shared__ double ys[2][R * NTG];   // pair summaries, pair qa + r at r NTG + tid
+  const int tid = threadIdx.x;
+  const int64_t slot0 = (int64_t)blockIdx.x * *as_const(&A.sys[0].tslots);
+  const SysDesc S = load_sys(A.sys, 0);
+  const int P = S.ntiles, P2 = (P + 1) / 2;
+  const int tq = S.tq;
+  const double* summ = A.summ + 2 * slot0;
+  double* ghost = A.ghost + 2 * slot0;
+  const int qa = tid * R;   // this thread's pairs qa .. qa+R-1
+  auto tpos = [&](int r, int k) { return (2 * r + k) * tq + tid; };
+  auto tK = [&](int t) { return t == P - 1 ? S.ltileK : S.tileK; };
+  // 1. pair summaries (pairs past the end: empty, passing values through;
+  //    eight pairs' loads in flight: all sixteen spill)
+#pragma unroll 8
+  for (int r = 0; r < R; ++r) {
+    const int a = 2 * (qa + r), b = a + 1;
+    const double ufa = summ[2 * tpos(r, 0)], ula = summ[2 * tpos(r, 0) + 1];
+    const double ufb = summ[2 * tpos(r, 1)], ulb = summ[2 * tpos(r, 1) + 1];
+    const double* Ka = tK(a);
+    const double* Kb = tK(b);
+    const double iDj = 1.0 / (1.0 - Ka[3] * Kb[0]);
+    const double xa = (ula + Ka[3] * ufb) * iDj;   // last row of a, zero outside the pair
+    const double xb = ufb + Kb[0] * xa;            // first row of b
+    ys[0][r * NTG + tid] = b < P ? ufa + xb * Ka[2] : (a < P ? ufa : 0.0);
+    ys[1][r * NTG + tid] = b < P ? ulb + xa * Kb[1] : (a < P ? ula : 0.0);
+  }
+  auto kofs = [&](int q, double& pf, double& pl, double& cf, double& cl) {
+    const bool real = q < P2, last = q == P2 - 1;
+    const double* K = last ? S.lpairK : S.pairK;
+    pf = real ? K[0] : 0.0;
+    pl = real ? K[1] : 1.0;
+    cf = real ? K[2] : 1.0;
+    cl = real ? K[3] : 0.0;
+  };
+  auto yf = [&](int r) { return ys[0][r * NTG + tid]; };
+  auto yl = [&](int r) { return ys[1][r * NTG + tid]; };
+  double bp[R], iD[R];
+  double Af = 1.0, gf = 0.0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int q = qa + r;
+    const int pc = q < P2 ? r * tq + tid : 0;
+    const double b0 = A.ttab[pc], i0 = A.ttab[A.ttab_n + pc];
+    bp[r] = q < P2 ? b0 : 0.0;
+    iD[r] = q < P2 ? i0 : 1.0;
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    double pf, pl, cf, cl;
+    kofs(qa + r, pf, pl, cf, cl);
+    const double At = pl * iD[r];
+    const double gt = yl(r) + At * bp[r] * yf(r);
+    gf = At * gf + gt;
+    Af = At * Af;
+  }
+  // 2. alpha (left to right)
+  double alpha = scan_affine_fwd<NTG>(Af, gf, 0.0, sh.f);
+  double ap[R], h[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    double pf, pl, cf, cl;
+    kofs(qa + r, pf, pl, cf, cl);
+    ap[r] = alpha;
+    h[r] = (yf(r) + pf * alpha) * iD[r];
+    alpha = pl * iD[r] * alpha + (yl(r) + pl * iD[r] * bp[r] * yf(r));
+  }
+  // 3. u (right to left)
+  double Cb = 1.0, hb = 0.0;
+#pragma unroll
+  for (int r = R - 1; r >= 0; --r) {
+    double pf, pl, cf, cl;
+    kofs(qa + r, pf, pl, cf, cl);
+    const double Cr = cf * iD[r];
+    hb = Cr * hb + h[r];
+    Cb = Cr * Cb;
+  }
+  double u = scan_affine_bwd<NTG>(Cb, hb, 0.0, sh.b);
+  // 4. the pair's outside values, then its tiles': the junction unknowns
+  //    v (last row of a) and w (first row of b) from
+  //      v = yl_a + XL pl_a + w cl_a,   w = yf_b + v pf_b + XR cf_b
+#pragma unroll
+  for (int r = R - 1; r >= 0; --r) {
+    const int q = qa + r;
+    double pf, pl, cf, cl;
+    kofs(q, pf, pl, cf, cl);
+    const double un = u;                 // right outside value of pair q
+    u = cf * iD[r] * u + h[r];           // first unknown of pair q
+    if (q < P2) {
+      const double XL = ap[r] + bp[r] * u, XR = un;
+      const int a = 2 * q, b = a + 1;
+      if (b < P) {
+        const double ula = summ[2 * tpos(r, 0) + 1], ufb = summ[2 * tpos(r, 1)];
+        const double* Ka = tK(a);
+        const double* Kb = tK(b);
+        const double v = (ula + XL * Ka[1] + Ka[3] * (ufb + XR * Kb[2])) / (1.0 - Ka[3] * Kb[0]);
+        const double w = ufb + v * Kb[0] + XR * Kb[2];
+        ghost[2 * tpos(r, 0)] = XL;
+        ghost[2 * tpos(r, 0) + 1] = w;
+        ghost[2 * tpos(r, 1)] = v;
+        ghost[2 * tpos(r, 1) + 1] = XR;
+      } else {
+        ghost[2 * tpos(r, 0)] = XL;
+        ghost[2 * tpos(r, 0) + 1] = XR;
+      }
+    }
+  }
+}
+
 // The same pass for the widest workgroup (1024 threads, whose register
 // budget cannot hold a run's inputs): each pass re-reads a tile's inputs from
 // L2, and alpha_{t-1} and h_t wait in the tile's ghost slot between passes.
@@ -2365,7 +2487,9 @@ static void launch_grid(const LaunchSet& L, const void* F, void* X, const void* 
   GridArgs G{F,     X,          Xfwd,   L.gpart,  L.corner0, f32,    L.gen_tK, L.sys,
              L.grid_items, L.ttab, L.ttab_n, L.summ,   L.ghost, L.gscr};
   const dim3 gg((unsigned)L.n_grid);
-  if (L.max_ntiles <= 256)
+  if (!QUASI && !GEN && L.pairs)
+    hipLaunchKernelGGL((k_grid_pairs<kPairNT, kPairR>), gg, dim3(kPairNT), 0, st, G);
+  else if (L.max_ntiles <= 256)
     hipLaunchKernelGGL((k_grid_affine<256, 1, QUASI, GEN>), gg, dim3(256), 0, st, G);
   else if (L.max_ntiles <= 2048)
     hipLaunchKernelGGL((k_grid_affine<256, 8, QUASI, GEN>), gg, dim3(256), 0, st, G);
