@@ -397,11 +397,13 @@ tdt_status_t tdt_green_support(double t_m1, double t_0, double t_1, int64_t L, i
 
 /* What the first pass of a plan reads per full tile: rows4[0], rows4[1] =
  * the leading and trailing rows of each tile the forward solve's summaries
- * read (tdt_green_support rounded up to multiples of 64), rows4[2], rows4[3]
- * the same for the adjoint (the rows of T^T); 0, 0 when the pass reads whole
- * tiles (the supports would cover a quarter of the tile or more: weak
- * dominance) or the plan has no such pass (one tile, varlen, general or
- * strided plans).  Errors: null arguments -> TDT_ERR_INVALID_ARG. */
+ * read (tdt_green_support rounded up to multiples of 64; for a general
+ * plan whose size is a multiple of the tile, the widest supports of the
+ * tiles' own inverses), rows4[2], rows4[3] the same for the adjoint (the
+ * rows of T^T); 0, 0 when the pass reads whole tiles (the supports would
+ * cover a quarter of the tile or more: weak dominance) or the plan has no
+ * such pass (one tile, varlen or strided plans, or a general plan with a
+ * ragged last tile).  Errors: null arguments -> TDT_ERR_INVALID_ARG. */
 tdt_status_t tdt_plan_green_support(tdt_plan_t plan, int64_t *rows4);
 
 /* Host-only: the interface merge of two adjacent segments, in double, as the

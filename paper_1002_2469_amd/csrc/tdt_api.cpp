@@ -48,7 +48,12 @@ struct tdt_plan_s {
   void* dgrow[2] = {nullptr, nullptr};
   void* dgblk[2] = {nullptr, nullptr};
   double* dgtK[2] = {nullptr, nullptr};
-  void* dggreen[2] = {nullptr, nullptr};   // first and last row of each tile's inverse
+  // first and last row of each tile's inverse, in double: with supports
+  // (gen_kf > 0, the widest over all tiles) only their entries,
+  // [tile][gen_kf + gen_kl]; without, double plans keep whole rows,
+  // [tile][2][L], and float plans none
+  void* dggreen[2] = {nullptr, nullptr};
+  int gen_kf[2] = {0, 0}, gen_kl[2] = {0, 0};
   int64_t reserved_M = 0;
   // strided batch plan (systems along a slow axis): P classes of order N
   bool strided = false;
@@ -1083,19 +1088,39 @@ tdt_status_t build_general_dir(tdt_plan_s* p, int dir, double& dom, double& kap)
   }
   std::vector<Tc> row((size_t)P * tdt::kGenRowN * L), blk((size_t)P * tdt::kGenBlkN * NT);
   std::vector<double> tK((size_t)P * 4);
-  // the tiles' Green rows (first pass of a double plan with several tiles)
-  std::vector<Tc> green(P > 1 && sizeof(Tc) == 8 ? (size_t)P * 2 * L : 0);
-  {
-    std::vector<double> g1((size_t)L), g2((size_t)L);
-    for (int64_t t = 0; !green.empty() && t < P; ++t) {
-      if (!green_rows_general(a.data() + t * L, b.data() + t * L, c.data() + t * L, L,
-                              g1.data(), g2.data()))
-        return TDT_ERR_SINGULAR;
-      for (int64_t i = 0; i < L; ++i) {
-        green[(size_t)t * 2 * L + i] = (Tc)g1[i];
-        green[(size_t)t * 2 * L + L + i] = (Tc)g2[i];
-      }
+  // the tiles' Green rows (the first pass's summaries are their dot
+  // products with the tile's F) and their supports: with several tiles,
+  // all of them full (no tail to mask), the first pass reads the widest
+  // supports over the tiles
+  std::vector<double> green(P > 1 ? (size_t)P * 2 * L : 0);
+  int64_t kfmax = 0, klmax = 0;
+  for (int64_t t = 0; !green.empty() && t < P; ++t) {
+    double* g1 = green.data() + (size_t)t * 2 * L;
+    if (!green_rows_general(a.data() + t * L, b.data() + t * L, c.data() + t * L, L, g1,
+                            g1 + L))
+      return TDT_ERR_SINGULAR;
+    std::vector<ld> r1(g1, g1 + L), r2(g1 + L, g1 + 2 * L);
+    int64_t kf = 0, kl = 0;
+    green_support(r1, r2, kf, kl);
+    kfmax = std::max(kfmax, kf);
+    klmax = std::max(klmax, kl);
+  }
+  int gkf = 0, gkl = 0;
+  if (!green.empty() && N % L == 0) green_support_rounded(L, kfmax, klmax, gkf, gkl);
+  p->gen_kf[dir] = gkf;
+  p->gen_kl[dir] = gkl;
+  if (gkf > 0) {
+    // only the supports' entries: the head of the first row, the tail of the last
+    std::vector<double> packed((size_t)P * (gkf + gkl));
+    for (int64_t t = 0; t < P; ++t) {
+      const double* g1 = green.data() + (size_t)t * 2 * L;
+      double* o = packed.data() + (size_t)t * (gkf + gkl);
+      std::copy(g1, g1 + gkf, o);
+      std::copy(g1 + 2 * L - gkl, g1 + 2 * L, o + gkf);
     }
+    green.swap(packed);
+  } else if (sizeof(Tc) == 4) {
+    green.clear();   // float plans sweep whole tiles: the rows would weigh as much as F
   }
   std::vector<ld> iu(B), aiu(B), cp(B), ph(B), ch(B);
   for (int64_t t = 0; t < P; ++t) {
@@ -1187,7 +1212,7 @@ tdt_status_t build_general_dir(tdt_plan_s* p, int dir, double& dom, double& kap)
   if (st == TDT_OK) st = dev_upload(reinterpret_cast<Tc**>(&p->dgblk[dir]), blk.data(), blk.size());
   if (st == TDT_OK) st = dev_upload(&p->dgtK[dir], tK.data(), tK.size());
   if (st == TDT_OK)
-    st = dev_upload(reinterpret_cast<Tc**>(&p->dggreen[dir]), green.data(), green.size());
+    st = dev_upload(reinterpret_cast<double**>(&p->dggreen[dir]), green.data(), green.size());
   if (st == TDT_OK) st = dev_upload(&p->dttab[dir], tt.data(), tt.size());
   if (st == TDT_OK) st = dev_upload(&p->dsys[dir], p->hsys[dir].data(), 1);
   return st;
@@ -1260,6 +1285,8 @@ tdt_status_t launch_set(tdt_plan_s* p, int dir, bool adjoint, int64_t M, tdt::La
     L.green = nullptr;
     L.green_kf = L.green_kl = 0;
     L.gen_green = p->dggreen[dir];
+    L.gen_kf = p->gen_kf[dir];
+    L.gen_kl = p->gen_kl[dir];
     L.p1_items = L.fin_items = nullptr;
     L.grid_items = L.sys_items = L.sys_bins = nullptr;
     L.n_bins = L.n_sys = 0;
@@ -2161,8 +2188,8 @@ tdt_status_t tdt_green_support(double t_m1, double t_0, double t_1, int64_t L, i
 tdt_status_t tdt_plan_green_support(tdt_plan_t p, int64_t* rows4) {
   if (!p || !rows4) return TDT_ERR_INVALID_ARG;
   for (int dir = 0; dir < 2; ++dir) {
-    rows4[2 * dir] = p->green_kf[dir];
-    rows4[2 * dir + 1] = p->green_kl[dir];
+    rows4[2 * dir] = p->general ? p->gen_kf[dir] : p->green_kf[dir];
+    rows4[2 * dir + 1] = p->general ? p->gen_kl[dir] : p->green_kl[dir];
   }
   return TDT_OK;
 }

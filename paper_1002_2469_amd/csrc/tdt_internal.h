@@ -143,7 +143,8 @@ struct LaunchSet {
   const void* gen_row;
   const void* gen_blk;
   const double* gen_tK;
-  const void* gen_green;   // [tile][2][L] Green rows, data precision
+  const void* gen_green;   // Green rows of the tiles, double (the plan's dggreen)
+  int gen_kf, gen_kl;      // double plans: the rows' supports over all tiles, or 0
   int64_t gen_M;
   int gen_R;               // right-hand sides per item (the item counts below are per item)
   int* iters;

@@ -843,8 +843,8 @@ __device__ __forceinline__ void solve_tile_lds(TileShared<SH, Tio, Tc>& sh, int 
                                                int max_iter, double refine_tol) {
   TDT_SHAPE(SH)
   Tio* myrow = sh.lds + threadIdx.x * TileShared<SH, Tio, Tc>::RP;
-  // a separate full-tile copy of the solve pays where registers are free:
-  // in the refinement kernel, which holds no prefetched tile
+  // a separate full-tile copy of the solve (no tail masking) pays in the
+  // refinement kernel; in the double ones it measured the same time
   if (REFINE && tl == kTile)
     solve_in_lds<SH, Tio, Tc, REFINE, SUMMARY, true, TAILV>(sh, myrow, kB, tl, XLt, XRt, S, K, bp, iDf, yfo, ylo,
                                         it_max, est_max, max_iter, refine_tol);
@@ -1419,6 +1419,9 @@ struct BetaEndsArgs {
   int nfull;                          // series: full tiles per right-hand side
   int kf, kl;                         // series: head of the first row, tail of the last row
   double* __restrict__ summ;          // [slot][2]
+  int64_t gstride;                    // series: 0, one matrix, green = [2][kTile]; else a
+                                      // general matrix, [tile][kf + kl] (the supports'
+                                      // entries of each tile's own rows)
   const int2* __restrict__ items;     // varlen: (system, full tile) per item, else null
   const double* __restrict__ gpack;   // varlen: each system's head and tail entries
 };
@@ -1451,8 +1454,8 @@ __global__ __launch_bounds__(kEndsNT) void k_beta_ends(BetaEndsArgs<Tio> A) {
       const int t = (int)(it - m * A.nfull);
       kf = A.kf;
       kl = A.kl;
-      gf = A.green;
-      gl = A.green + 2 * kTile - kl;
+      gf = A.green + t * A.gstride;
+      gl = A.gstride ? gf + kf : gf + 2 * kTile - kl;
       head = A.F + S.off + m * S.stride + (int64_t)t * kTile;
       sl = tile_slot(S, m, t, false);
     }
@@ -2471,7 +2474,7 @@ static void launch_beta_ends(const LaunchSet& L, const Tio* F, hipStream_t st) {
   const bool varlen = L.ends_items != nullptr;
   const int64_t n = varlen ? L.n_ends : L.n_beta;
   BetaEndsArgs<Tio> B{F,       L.sys,  L.green, n,      L.nfull, L.green_kf, L.green_kl,
-                      L.summ,  varlen ? L.ends_items : nullptr, L.gpack};
+                      L.summ,  0,      varlen ? L.ends_items : nullptr, L.gpack};
   const int64_t want = (n + kEndsNW - 1) / kEndsNW;
   const int64_t lim = L.wg_per_cu > 0 ? cap : ((int64_t)1 << 30);
   const unsigned grid = (unsigned)(want < lim ? want : lim);
@@ -2614,8 +2617,31 @@ static hipError_t run_general(const LaunchSet& L, const void* F, void* X, hipStr
                      L.summ, L.ghost};
   if (L.ev) (void)hipEventRecord(L.ev[0], st);
   if (L.n_p1 > 0) {
-    if constexpr (sizeof(Tio) == 8) {
-      // tile summaries as Green-row dot products (double plans)
+    if (L.gen_kf > 0) {
+      // the rows' supports are short (dominance, Sec. 3.4): one wavefront
+      // per tile and right-hand side reads the two ends only
+      auto kern = k_beta_ends<SH, Tio>;
+      const int64_t nt = L.n_p1 / A.G, n = L.gen_M * nt;
+      BetaEndsArgs<Tio> B{static_cast<const Tio*>(F),
+                          L.sys,
+                          static_cast<const double*>(L.gen_green),
+                          n,
+                          (int)nt,
+                          L.gen_kf,
+                          L.gen_kl,
+                          L.summ,
+                          (int64_t)L.gen_kf + L.gen_kl,
+                          nullptr,
+                          nullptr};
+      int64_t grid = (n + kEndsNW - 1) / kEndsNW;
+      if (L.wg_per_cu > 0) {
+        static int per_cu = resident_per_cu(kern, kEndsNT);
+        const int64_t cap = grid_cap(per_cu, L.wg_per_cu);
+        grid = grid < cap ? grid : cap;
+      }
+      hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kEndsNT), 0, st, B);
+    } else if constexpr (sizeof(Tio) == 8) {
+      // tile summaries as Green-row dot products over whole tiles
       auto kern = k_gbeta<SH, Tio>;
       static int per_cu = resident_per_cu(kern, kBetaNT);
       const int64_t cap = grid_cap(per_cu, L.wg_per_cu);
@@ -2624,7 +2650,7 @@ static hipError_t run_general(const LaunchSet& L, const void* F, void* X, hipStr
       hipLaunchKernelGGL(kern, dim3((unsigned)(L.n_p1 < cap ? L.n_p1 : cap)), dim3(kBetaNT), 0,
                          st, B);
     } else {
-      // by sweeps (float plans: there the Green rows would be as large as F)
+      // by sweeps (float plans: whole Green rows would weigh as much as F)
       launch_gtile<SH, Tio, Tc, true>(A, L.n_p1, 0, L.wg_per_cu, st);
     }
     if (L.ev) (void)hipEventRecord(L.ev[1], st);

@@ -62,6 +62,46 @@ def test_general_many_tiles(tiles, extra):
     assert oracle.rel_err(X, oracle.solve_general(F, a, b, c)) <= 1e-12
 
 
+@pytest.mark.parametrize("M", [1, 5])
+def test_general_truncated_first_pass(M):
+    """Whole tiles of dominant rows: the first pass reads only the supports
+    of the tiles' own Green rows (multiples of 64 rows from each end,
+    together under a quarter of the tile), forward and adjoint; the solve and
+    the adjoint against the oracle, and a float plan's solve.  Rows of weak dominance
+    (ratio 1.0002: the rows decay over thousands of entries) keep whole
+    tiles, and so does a size with a ragged last tile."""
+    tdt = _tdt()
+    rng = np.random.default_rng(77 + M)
+    n = 6 * L
+    a, b, c = random_rows(rng, n, 1.2, 3.0)
+    F = rng.standard_normal((M, n))
+    G = rng.standard_normal((M, n))
+    print(f"[case] general truncated first pass M={M}", flush=True)
+    plan = tdt.GeneralPlan(a, b, c, "f64")
+    sup = plan.green_support()
+    for kf, kl in (sup["forward"], sup["adjoint"]):
+        assert kf > 0 and kl > 0 and kf % 64 == 0 and kl % 64 == 0 and 4 * (kf + kl) <= L, sup
+    X = plan.solve(to_dev(F))
+    Xr = oracle.solve_general(F, a, b, c)
+    assert oracle.rel_err_rows(to_host(X), Xr).max() <= 1e-12
+    gF, g = plan.backward(to_dev(G), X)
+    gFr, (ga, gb, gc) = oracle.adjoint_general(G, Xr, a, b, c)
+    assert oracle.rel_err_rows(to_host(gF), gFr).max() <= 1e-12
+    ref = np.stack([ga, gb, gc])
+    assert np.max(np.abs(to_host(g) - ref)) <= 1e-11 * np.max(np.abs(ref))
+    plan.close()
+    # a float plan reads the same supports (its rows are computed in double)
+    plan = tdt.GeneralPlan(a, b, c, "f32")
+    assert plan.green_support() == sup
+    X = to_host(plan.solve(to_dev(F, "f32")))
+    assert oracle.rel_err_rows(X, oracle.solve_general(_f32_round(F, "f32"), a, b, c)).max() <= TOL["f32"]
+    plan.close()
+    assert tdt.GeneralPlan(a[:n - 5], b[:n - 5], c[:n - 5], "f64").green_support() == \
+        dict(forward=(0, 0), adjoint=(0, 0))
+    a, b, c = W.general_rows(rng, n, 1.0002, 1.0002)
+    assert tdt.GeneralPlan(a, b, c, "f64").green_support() == dict(forward=(0, 0), adjoint=(0, 0))
+
+
 @pytest.mark.slow
 def test_general_segment_merge_interface():
     """More than 16384 tiles: the segment-merge interface pass."""
