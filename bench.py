@@ -217,7 +217,7 @@ def run_mode(tdt, d, F, X, mode, steps, warmup, torch, opts=None):
         plan.reserve(d.get("M", 1))
         tuned = {k: plan.get_option(k) for k in ("shape", "whole_max_tiles", "wg_per_cu")}
         tuned["fixed"] = True
-    support = plan.green_support()["forward"] if d["kind"] == "series" else (0, 0)
+    support = plan.green_support()["forward"] if d["kind"] in ("series", "general") else (0, 0)
     adj = d.get("adjoint", False)
     gX = gF = gt = None
     if adj:
@@ -280,9 +280,11 @@ def run_mode(tdt, d, F, X, mode, steps, warmup, torch, opts=None):
     stop.record()
     torch.cuda.synchronize()
     ms = start.elapsed_time(stop) / steps
+    # steps run on this plan after tuning (warm-up, event loop, graph warm-up, timed)
+    solves = warmup + 2 * steps + (1 + warmup if d.get("graph") else 0)
     out = dict(ms=ms, kernels_ms=kern, refine_iters=info["refine_iters"],
                X=X.cpu().numpy().reshape(-1), tuned=tuned, stage1_ms=stage1_ms,
-               green_support=support)
+               green_support=support, solves=solves)
     if adj:
         out["gF"] = gF.cpu().numpy().reshape(-1)
         out["gt"] = gt.cpu().numpy()
@@ -319,7 +321,7 @@ def run_poisson(tdt, d, F, mode, steps, warmup, torch):
     torch.cuda.synchronize()
     ms = start.elapsed_time(stop) / steps
     out = dict(ms=ms, kernels_ms=kern, refine_iters=0, X=U.cpu().numpy().reshape(-1), tuned=None,
-               stage1_ms=stage1_ms)
+               stage1_ms=stage1_ms, solves=warmup + 2 * steps)
     solver.close()
     return out
 
@@ -353,7 +355,7 @@ def run_poisson3d(tdt, d, F, steps, warmup, torch):
     ms = start.elapsed_time(stop) / steps
     counts, _om = solver.schedule()
     out = dict(ms=ms, kernels_ms=kern, refine_iters=0, X=U.cpu().numpy().reshape(-1), tuned=None,
-               counts=counts, stage1_ms=stage1_ms)
+               counts=counts, stage1_ms=stage1_ms, solves=warmup + 2 * steps)
     solver.close()
     return out
 
@@ -475,6 +477,9 @@ def main() -> int:
                     help="fixed whole-system threshold of varlen plans (no autotuning)")
     ap.add_argument("--wg", type=int, default=None,
                     help="fixed cap of workgroups per CU (no autotuning)")
+    ap.add_argument("--fixed", action="append", default=[], metavar="MODE:SHAPE,WHOLE,WG",
+                    help="fixed launch options of one path (no autotuning for it), e.g. "
+                         "f32_refine:2,0,0; repeatable, overrides --shape/--whole/--wg")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -508,6 +513,11 @@ def main() -> int:
         else:
             fixed = {k: v for k, v in (("shape", args.shape), ("whole_max_tiles", args.whole),
                                        ("wg_per_cu", args.wg)) if v is not None}
+            for spec in args.fixed:
+                m, _, vals = spec.partition(":")
+                if m == mode:
+                    fixed = dict(zip(("shape", "whole_max_tiles", "wg_per_cu"),
+                                     (int(v) for v in vals.split(","))))
             opts = fixed if (fixed or args.no_autotune) else None
             res[mode] = run_mode(tdt, d, Fm, Xm, mode, args.steps, args.warmup, torch, opts=opts)
         print(f"[bench] {args.workload} {mode}: {res[mode]['ms']:.4f} ms/step  kernels(ms) "
@@ -613,7 +623,7 @@ def main() -> int:
                 "stage1_ms": r.get("stage1_ms"),
                 "kernels_ms": {k: round(v, 6) for k, v in r["kernels_ms"].items()},
                 "rel_err_vs_oracle": err_of(mode), "refine_iters": r["refine_iters"],
-                "tuned": r["tuned"]}
+                "tuned": r["tuned"], "steps_run": r["solves"]}
 
     hk = res[head]["kernels_ms"]
     dom = max((k for k in per_launch if hk.get(k, 0) > 0 and per_launch[k] > 0),

@@ -344,14 +344,18 @@ bool green_support_bound(ld a, ld b, ld c, int64_t L, int64_t& kf, int64_t& kl, 
 // cover a quarter of the tile, or reach past where the pivots settled) and
 // their entries: head = the first rf entries of the first row, tail = the
 // last rl entries of the last row, (-t_1)^j / u*^(j+1) and
-// (-t_-1)^m / u*^(m+1) at distance j, m from the row's own end.
+// (-t_-1)^m / u*^(m+1) at distance j, m from the row's own end.  These are
+// the entries of every order n >= max(rf, rl) + C (C = *settled, where the
+// pivots settle): the entries within them involve only the pivots
+// u_{n-1-j} .. u_{n-1}, all past C.
 bool green_ends(ld a, ld b, ld c, int64_t L, int& rf, int& rl, std::vector<ld>& head,
-                std::vector<ld>& tail) {
+                std::vector<ld>& tail, int64_t* settled) {
   int64_t kf = 0, kl = 0, C = 0;
   ld us = 0.0L;
   if (!green_support_bound(a, b, c, L, kf, kl, &us, &C)) return false;
   green_support_rounded(L, kf, kl, rf, rl);
   if (rf == 0 || rf > L - C || rl > L - C) return false;
+  *settled = C;
   head.assign((size_t)rf, 0.0L);
   tail.assign((size_t)rl, 0.0L);
   ld e = 1.0L / us;
@@ -684,12 +688,15 @@ tdt_status_t build_lists(tdt_plan_s* p, int dir, int max_tiles) {
   p1.erase(std::remove_if(p1.begin(), p1.end(), alone), p1.end());
   fin.assign(p1.rbegin(), p1.rend());
   fin.insert(fin.end(), single.begin(), single.end());
-  // full tiles of systems whose Green rows decay (in both directions): their
-  // summaries are dot products with the rows' supports, not sweeps
+  // full tiles of systems whose Green rows decay (in both directions), and
+  // their last tiles where long enough: their summaries are dot products
+  // with the rows' supports, not sweeps
   std::vector<int2> ends;
   auto by_ends = [&](const int2& it) {
     const SysDesc& D0 = p->hsys[0][it.x];
-    return D0.gkf > 0 && p->hsys[1][it.x].gkf > 0 && (int64_t)(it.y + 1) * p->L <= D0.n;
+    const SysDesc& D1 = p->hsys[1][it.x];
+    const bool full = (int64_t)(it.y + 1) * p->L <= D0.n;
+    return D0.gkf > 0 && D1.gkf > 0 && (full || (D0.glast && D1.glast));
   };
   for (const int2& it : p1)
     if (by_ends(it)) ends.push_back(it);
@@ -816,11 +823,17 @@ tdt_status_t finish_plan(tdt_plan_s* p, const std::vector<double>& tm1,
       for (int64_t s = 0; s < S; ++s) {
         SysDesc& D = p->hsys[dir][s];
         D.goff = 0;
-        D.gkf = D.gkl = 0;
-        if (!needs_interface(D) || D.n < kTile) continue;
+        D.gkf = D.gkl = D.glast = 0;
+        if (!needs_interface(D)) continue;
         const double a = dir == 0 ? tm1[s] : t1[s], c = dir == 0 ? t1[s] : tm1[s];
         int rf = 0, rl = 0;
-        if (!green_ends(a, t0[s], c, kTile, rf, rl, head, tail)) continue;
+        int64_t C = 0;
+        if (!green_ends(a, t0[s], c, kTile, rf, rl, head, tail, &C)) continue;
+        const int64_t tl = D.n - (int64_t)(D.ntiles - 1) * kTile;
+        D.glast = tl < kTile && tl >= std::max(rf, rl) + C ? 1 : 0;
+        // a quasi-Toeplitz system of one shorter tile: only if that tile is
+        // long enough for the entries
+        if (D.n < kTile && !D.glast) continue;
         D.goff = (int64_t)pack.size();
         D.gkf = (int32_t)rf;
         D.gkl = (int32_t)rl;

@@ -64,9 +64,12 @@ struct SysDesc {
   double qc[6];
   // varlen plans: the supports of a full tile's two Green rows (gkf leading
   // entries of the first row, then gkl trailing entries of the last, at
-  // goff of the plan's packed array), or gkf = gkl = 0 (summaries by sweeps)
+  // goff of the plan's packed array), or gkf = gkl = 0 (summaries by sweeps);
+  // glast = 1: a shorter last tile has the same entries (its rows under the
+  // supports meet only settled pivots) and is summarised from them too
   int64_t goff;
   int32_t gkf, gkl;
+  int32_t glast, gpad;
   // series plans of 8193 to 16384 tiles: the interface pass runs over pairs
   // of adjacent tiles, with the end values of a full pair and of the last one
   double pairK[4], lpairK[4];

@@ -1201,18 +1201,20 @@ __global__ __launch_bounds__(SH::NT, REFINE ? kRefineWaves : SH::WAVES) void k_s
                                         sbw, &tsum[t][0], &tsum[t][1]);
       };
       if (S.gkf > 0) {
-        // full tiles: one wavefront per tile reads only the rows under the
-        // supports; a shorter last tile is swept (and stays in LDS)
+        // full tiles, and a shorter last tile with the same entries
+        // (glast): one wavefront per tile reads only the rows under the
+        // supports; another shorter last tile is swept (and stays in LDS)
         const int nfull = (int)(S.n / kTile);
-        if (nfull < nt) sweep_summary(nt - 1, false);
+        const int nends = nfull < nt && S.glast ? nt : nfull;
+        if (nends < nt) sweep_summary(nt - 1, false);
         else last_in_lds = false;
         const int lane = tid & 63, w = tid >> 6;
         const double* gf = A.gpack + S.goff + lane;
         const double* gl = gf + S.gkf;
-        for (int t = w; t < nfull; t += kNW) {
+        for (int t = w; t < nends; t += kNW) {
           const Tio* hd = A.F + S.off + (int64_t)t * kTile + lane;
           double s1, s2;
-          ends_dot<Tio>(hd, hd + kTile - S.gkl, gf, gl, S.gkf, S.gkl, s1, s2);
+          ends_dot<Tio>(hd, hd + tile_len(S, t) - S.gkl, gf, gl, S.gkf, S.gkl, s1, s2);
           if (lane == 0) {
             tsum[t][0] = s1;
             tsum[t][1] = s2;
@@ -1438,6 +1440,7 @@ __global__ __launch_bounds__(kEndsNT) void k_beta_ends(BetaEndsArgs<Tio> A) {
     const double *gf, *gl;
     int kf, kl;
     int64_t sl;
+    int tl = kTile;
     if (A.items) {
       const cptr<int> iv = as_const(reinterpret_cast<const int*>(A.items)) + 2 * it;
       const int s = iv[0], t = iv[1];
@@ -1448,6 +1451,8 @@ __global__ __launch_bounds__(kEndsNT) void k_beta_ends(BetaEndsArgs<Tio> A) {
       gl = gf + kf;
       head = A.F + S.off + (int64_t)t * kTile;
       sl = tile_slot(S, 0, t, true);
+      const int64_t rest = S.n - (int64_t)t * kTile;   // a shorter last tile (glast)
+      tl = rest < kTile ? (int)rest : kTile;
     } else {
       const SysDesc S = load_sys(A.sys, 0);
       const int64_t m = it / A.nfull;
@@ -1460,7 +1465,7 @@ __global__ __launch_bounds__(kEndsNT) void k_beta_ends(BetaEndsArgs<Tio> A) {
       sl = tile_slot(S, m, t, false);
     }
     double s1, s2;
-    ends_dot<Tio>(head + lane, head + kTile - kl + lane, gf + lane, gl + lane, kf, kl, s1, s2);
+    ends_dot<Tio>(head + lane, head + tl - kl + lane, gf + lane, gl + lane, kf, kl, s1, s2);
     if (lane == 0) {
       A.summ[2 * sl] = s1;
       A.summ[2 * sl + 1] = s2;

@@ -85,3 +85,73 @@ def test_headline_first_pass_support_and_parity():
         X = to_host(plan.solve(Fd))
         assert oracle.rel_err(X, ref) <= 1e-12
         plan.close()
+
+
+# last-tile lengths on both sides of where the shorter tile can take the
+# full tile's support entries (supports of 64 to 448 rows, pivots settling
+# within tens to a few hundred rows), and full tiles
+TAILS = [0, 1, 17, 63, 64, 65, 100, 129, 200, 257, 450, 511, 700, 1000, 3000, 8191]
+
+
+@pytest.mark.parametrize("quasi", [False, True])
+@pytest.mark.parametrize("whole", [0, 16])
+@pytest.mark.parametrize("dtype", ["f64", "f32_refine"])
+def test_varlen_first_pass_last_tiles(whole, dtype, quasi):
+    """Varlen plans: each multi-tile system's full tiles are summarised from
+    its supports, and so is its shorter last tile where that tile is long
+    enough, otherwise swept; through the tile kernels (whole 0) and the
+    whole-system kernel (whole 16).  Quasi-Toeplitz plans (corner terms
+    psi, chi) also summarise a system of one shorter tile that way.  Solve
+    and adjoint against the oracle, system by system, for strongly,
+    moderately and weakly dominant matrices of both signs."""
+    tdt = _tdt()
+    mats = [(-0.9, 2.5, -1.1), (-1.0, 2.01, -1.0), (0.3, -1.0, 0.45), (1.0, -2.3, 1.0),
+            (-1.0, 2.0001, -1.0)]
+    sizes, tm1, t0, t1 = [], [], [], []
+    for i, r in enumerate(TAILS):
+        for k in ((0, 1, 2, 3) if quasi else (1, 2, 3)):
+            if k == 0 and r == 0:
+                continue
+            a, b, c = mats[(i + k) % len(mats)]
+            sizes.append(k * 8192 + r + (2 if quasi else 0))   # quasi: tiles over the inner rows
+            tm1.append(a)
+            t0.append(b)
+            t1.append(c)
+    sizes += [5, 8192]            # one-tile systems in the same plan
+    tm1 += [-1.0, -1.0]
+    t0 += [3.0, 3.0]
+    t1 += [-1.0, -1.0]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    tm1, t0, t1 = np.array(tm1), np.array(t0), np.array(t1)
+    # corner terms that keep the corner rows dominant
+    psi = 0.25 * np.sign(t0) if quasi else None
+    chi = 0.15 * np.sign(t0) if quasi else None
+    rng = np.random.default_rng(4242 + whole)
+    F = rng.standard_normal(int(off[-1]))
+    G = rng.standard_normal(int(off[-1]))
+    print(f"[case] varlen first pass last tiles whole={whole} dtype={dtype} quasi={quasi} "
+          f"S={len(sizes)} sum N={int(off[-1])}", flush=True)
+    plan = tdt.VarlenPlan(off, tm1, t0, t1, dtype, psi=psi, chi=chi)
+    plan.set_option("shape", 0)
+    plan.set_option("whole_max_tiles", whole)
+    Xd = plan.solve(to_dev(F))
+    ref = oracle.solve_varlen(F, off, tm1, t0, t1, psi=psi, chi=chi)
+    tols = np.array([tol_f64(tm1[s], t0[s], t1[s], sizes[s]) for s in range(len(sizes))])
+    errs = oracle.rel_err_rows(to_host(Xd), ref, off)
+    bad = np.nonzero(errs > tols)[0]
+    assert bad.size == 0, [(int(s), sizes[s], errs[s], tols[s]) for s in bad[:5]]
+    if dtype == "f64":
+        gF, gt = plan.backward(to_dev(G), Xd)
+        gFr, gtr = oracle.adjoint_varlen(G, ref, off, tm1, t0, t1, psi=psi, chi=chi,
+                                         corners=quasi)
+        tolT = np.array([tol_f64(t1[s], t0[s], tm1[s], sizes[s]) for s in range(len(sizes))])
+        errs = oracle.rel_err_rows(to_host(gF), gFr, off)
+        bad = np.nonzero(errs > tolT)[0]
+        assert bad.size == 0, [(int(s), sizes[s], errs[s], tolT[s]) for s in bad[:5]]
+        gt = to_host(gt)
+        assert gt.shape == gtr.shape
+        scale = np.maximum(1.0, np.max(np.abs(gtr), axis=1))
+        rel = np.max(np.abs(gt - gtr), axis=1) / scale
+        lim = np.maximum(1e-11, 4 * tols)
+        assert np.all(rel <= lim), [(int(s), rel[s], lim[s]) for s in np.nonzero(rel > lim)[0][:5]]
+    plan.close()

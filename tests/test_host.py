@@ -276,3 +276,32 @@ def test_green_support_bound_against_oracle_rows(t, L):
     R = np.abs(oracle.solve(E, c, b, a, precision="ld"))
     for k, r in ((bf, R[0]), (bl, R[1][::-1])):
         assert r[k:].sum() <= 2.0 ** -60 * r.sum() * (1 + 1e-6), (k, r[k:].sum() / r.sum())
+
+
+@pytest.mark.parametrize("t", [(-0.9, 2.5, -1.1), (-1.0, 2.01, -1.0), (0.3, -1.0, 0.45),
+                               (-0.5, -3.2, 0.7)])
+def test_green_support_entries_of_shorter_tiles(t):
+    """A varlen plan's last tile, shorter than a tile, is summarised with the
+    full tile's support entries when it is long enough that the entries
+    under the supports involve only settled pivots: the first rows of T_n
+    and T_L (and the last rows) agree there once n exceeds the supports by
+    the pivots' settling length (a few hundred rows at most for these
+    matrices).  Rows from the oracle's long double solves."""
+    import oracle
+    a, b, c = t
+    L = 8192
+    _, (bf, bl) = tdt.green_support(a, b, c, L, bound=True)
+    rf, rl = -(-bf // 64) * 64, -(-bl // 64) * 64
+
+    def rows(n):
+        E = np.zeros((2, n))
+        E[0, 0] = 1.0
+        E[1, -1] = 1.0
+        R = oracle.solve(E, c, b, a, precision="ld")   # T^T = tridiag{c, b, a}
+        return R[0], R[1]
+
+    f_L, l_L = rows(L)
+    for n in (max(rf, rl) + 300, 2500, L - 1):
+        f, l = rows(n)
+        assert np.max(np.abs(f[:rf] - f_L[:rf])) <= 1e-15 * np.max(np.abs(f_L)), (t, n)
+        assert np.max(np.abs(l[-rl:] - l_L[-rl:])) <= 1e-15 * np.max(np.abs(l_L)), (t, n)
