@@ -699,7 +699,16 @@ tdt_status_t build_lists(tdt_plan_s* p, int dir, int max_tiles) {
     return D0.gkf > 0 && D1.gkf > 0 && (full || (D0.glast && D1.glast));
   };
   for (const int2& it : p1)
-    if (by_ends(it)) ends.push_back(it);
+    if (by_ends(it)) {
+      // long supports: a wavefront per tile end
+      const SysDesc& D = p->hsys[dir][it.x];
+      if (D.gkf + D.gkl > tdt::kEndsSplitRows) {
+        ends.push_back(make_int2(it.x, it.y | (1 << tdt::kEndsPartShift)));
+        ends.push_back(make_int2(it.x, it.y | (2 << tdt::kEndsPartShift)));
+      } else {
+        ends.push_back(it);
+      }
+    }
   p1.erase(std::remove_if(p1.begin(), p1.end(), by_ends), p1.end());
   // Whole systems: by default one workgroup each, largest first, so that
   // the hardware starts the next system wherever a workgroup finishes (the

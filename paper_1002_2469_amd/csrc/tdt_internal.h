@@ -77,6 +77,12 @@ struct SysDesc {
 // The pair interface pass: threads, and pairs per thread (2 kPairR tiles)
 constexpr int kPairNT = 512;
 constexpr int kPairR = 16;
+// First pass from the Green rows' supports: supports longer than this many
+// rows (head and tail together) take a wavefront per tile end, shorter ones
+// a wavefront per tile.  Varlen items carry the part of the tile in the bits
+// of the tile index from kEndsPartShift up: 0 both ends, 1 head, 2 tail.
+constexpr int kEndsSplitRows = 256;
+constexpr int kEndsPartShift = 24;
 
 // Slot of tile t of a system: a varlen plan adds the system's slot0; a
 // series plan uses tslots slots per right-hand side m.

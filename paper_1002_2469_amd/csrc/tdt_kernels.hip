@@ -1038,40 +1038,59 @@ __global__ __launch_bounds__(SH::NT, REFINE ? kRefineWaves : SH::WAVES) void k_t
   publish_refine_record(A.iters, it_max, est_max);
 }
 
-// One wavefront's summary of one tile from the Green rows' supports: s1 =
-// first row head (kf entries at gf) . the tile's first kf rows, s2 = last row
-// tail (kl entries at gl) . its last kl rows (kf, kl multiples of 64; the
-// pointers already offset by the lane).  The lane sums are added by a fixed
+// One wavefront's dot product of k rows of a tile with k entries of a Green
+// row's support (k a multiple of 64; both pointers already offset by the
+// lane), U rows in flight per lane.  The lane sums are added by a fixed
 // butterfly, so the result is repeatable and the same in every lane.
-template <typename Tio>
-__device__ __forceinline__ void ends_dot(const Tio* head, const Tio* tail, const double* gf,
-                                         const double* gl, int kf, int kl, double& s1,
-                                         double& s2) {
-  constexpr int U = 4;   // loads in flight per lane and row run
+// Both ends of a tile in one wavefront: H rows of the head and H of the tail
+// in flight together per lane (for short supports, where a wavefront per end
+// would cost more to launch than it saves in waiting).
+template <typename Tio, int H>
+__device__ __forceinline__ void support_dot2(const Tio* head, const double* gf, int kf,
+                                             const Tio* tail, const double* gl, int kl,
+                                             double& s1, double& s2) {
   const int nf = kf / 64, nl = kl / 64;
   s1 = 0.0;
   s2 = 0.0;
-  for (int j0 = 0; j0 < nf; j0 += U) {
-    double v[U];
+  for (int j0 = 0; j0 < nf || j0 < nl; j0 += H) {
+    double v[H], w[H], x[H], y[H];
 #pragma unroll
-    for (int u = 0; u < U; ++u) v[u] = j0 + u < nf ? (double)head[(j0 + u) * 64] : 0.0;
+    for (int u = 0; u < H; ++u) {
+      v[u] = j0 + u < nf ? (double)head[(j0 + u) * 64] : 0.0;
+      w[u] = j0 + u < nf ? gf[(j0 + u) * 64] : 0.0;
+      x[u] = j0 + u < nl ? (double)tail[(j0 + u) * 64] : 0.0;
+      y[u] = j0 + u < nl ? gl[(j0 + u) * 64] : 0.0;
+    }
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (j0 + u < nf) s1 += v[u] * gf[(j0 + u) * 64];
-  }
-  for (int j0 = 0; j0 < nl; j0 += U) {
-    double v[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) v[u] = j0 + u < nl ? (double)tail[(j0 + u) * 64] : 0.0;
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (j0 + u < nl) s2 += v[u] * gl[(j0 + u) * 64];
+    for (int u = 0; u < H; ++u) {
+      s1 += v[u] * w[u];
+      s2 += x[u] * y[u];
+    }
   }
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) {
     s1 += __shfl_xor(s1, d, 64);
     s2 += __shfl_xor(s2, d, 64);
   }
+}
+
+template <typename Tio, int U>
+__device__ __forceinline__ double support_dot(const Tio* rows, const double* g, int k) {
+  const int nr = k / 64;
+  double s = 0.0;
+  for (int j0 = 0; j0 < nr; j0 += U) {
+    double v[U], w[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      v[u] = j0 + u < nr ? (double)rows[(j0 + u) * 64] : 0.0;
+      w[u] = j0 + u < nr ? g[(j0 + u) * 64] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) s += v[u] * w[u];
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
+  return s;
 }
 
 template <typename Tio>
@@ -1202,7 +1221,7 @@ __global__ __launch_bounds__(SH::NT, REFINE ? kRefineWaves : SH::WAVES) void k_s
       };
       if (S.gkf > 0) {
         // full tiles, and a shorter last tile with the same entries
-        // (glast): one wavefront per tile reads only the rows under the
+        // (glast): one wavefront per tile end reads only the rows under the
         // supports; another shorter last tile is swept (and stays in LDS)
         const int nfull = (int)(S.n / kTile);
         const int nends = nfull < nt && S.glast ? nt : nfull;
@@ -1211,14 +1230,13 @@ __global__ __launch_bounds__(SH::NT, REFINE ? kRefineWaves : SH::WAVES) void k_s
         const int lane = tid & 63, w = tid >> 6;
         const double* gf = A.gpack + S.goff + lane;
         const double* gl = gf + S.gkf;
-        for (int t = w; t < nends; t += kNW) {
+        for (int iw = w; iw < 2 * nends; iw += kNW) {
+          const int t = iw >> 1;
           const Tio* hd = A.F + S.off + (int64_t)t * kTile + lane;
-          double s1, s2;
-          ends_dot<Tio>(hd, hd + tile_len(S, t) - S.gkl, gf, gl, S.gkf, S.gkl, s1, s2);
-          if (lane == 0) {
-            tsum[t][0] = s1;
-            tsum[t][1] = s2;
-          }
+          const double sv = (iw & 1) == 0
+                                ? support_dot<Tio, 4>(hd, gf, S.gkf)
+                                : support_dot<Tio, 4>(hd + tile_len(S, t) - S.gkl, gl, S.gkl);
+          if (lane == 0) tsum[t][iw & 1] = sv;
         }
       } else {
         for (int t = 0; t < nt; ++t) sweep_summary(t, PF);
@@ -1407,9 +1425,12 @@ __global__ __launch_bounds__(kBetaNT) void k_beta(BetaArgs<Tio> A) {
 // the tail of the last row (kl entries) outside which a row's mass is below
 // 2^-60 of its 1-norm, so each summary reads only those rows of its tile.
 // What is dropped is at most 2^-60 |row|_1 |F|_inf, below the rounding of
-// the dot product itself.  One wavefront per tile; lanes stride the head and
-// the tail 64 rows at a time (kf, kl are multiples of 64), and the two
-// lane sums are added by a fixed butterfly, so results are repeatable.
+// the dot product itself.  A wavefront takes a tile, or for long supports
+// one end of a tile (the head's dot product and the tail's are independent,
+// so two wavefronts halve the chain of loads each waits on); lanes stride
+// the rows 64 at a time (kf, kl are multiples of 64), and the lane sums are
+// added by a fixed butterfly, so results are repeatable.
+// (kEndsSplitRows, kEndsPartShift: tdt_internal.h)
 constexpr int kEndsNT = 256;
 constexpr int kEndsNW = kEndsNT / 64;
 template <typename Tio>
@@ -1418,13 +1439,16 @@ struct BetaEndsArgs {
   const SysDesc* __restrict__ sys;
   const double* __restrict__ green;   // series: [2][kTile]: first row, last row
   int64_t nitems;                     // series: right-hand sides x full tiles per right-hand side
+                                      // (varlen: items)
+  int split;                          // series: a wavefront per tile end (else per tile)
   int nfull;                          // series: full tiles per right-hand side
   int kf, kl;                         // series: head of the first row, tail of the last row
   double* __restrict__ summ;          // [slot][2]
   int64_t gstride;                    // series: 0, one matrix, green = [2][kTile]; else a
                                       // general matrix, [tile][kf + kl] (the supports'
                                       // entries of each tile's own rows)
-  const int2* __restrict__ items;     // varlen: (system, full tile) per item, else null
+  const int2* __restrict__ items;     // varlen: (system, tile | part << kEndsPartShift) per
+                                      // item, else null
   const double* __restrict__ gpack;   // varlen: each system's head and tail entries
 };
 
@@ -1433,8 +1457,11 @@ __global__ __launch_bounds__(kEndsNT) void k_beta_ends(BetaEndsArgs<Tio> A) {
   TDT_SHAPE(SH)
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  for (int64_t it = (int64_t)blockIdx.x * kEndsNW + w; it < A.nitems;
-       it += (int64_t)gridDim.x * kEndsNW) {
+  const int64_t nw = A.items || !A.split ? A.nitems : 2 * A.nitems;   // wavefront items
+  for (int64_t iw = (int64_t)blockIdx.x * kEndsNW + w; iw < nw;
+       iw += (int64_t)gridDim.x * kEndsNW) {
+    const int64_t it = A.items || !A.split ? iw : iw >> 1;
+    int part = A.items || !A.split ? 0 : 1 + (int)(iw & 1);
     // this item's tile, the supports and their entries
     const Tio* head;
     const double *gf, *gl;
@@ -1443,7 +1470,8 @@ __global__ __launch_bounds__(kEndsNT) void k_beta_ends(BetaEndsArgs<Tio> A) {
     int tl = kTile;
     if (A.items) {
       const cptr<int> iv = as_const(reinterpret_cast<const int*>(A.items)) + 2 * it;
-      const int s = iv[0], t = iv[1];
+      const int s = iv[0], t = iv[1] & ((1 << kEndsPartShift) - 1);
+      part = iv[1] >> kEndsPartShift;
       const SysDesc S = load_sys(A.sys, s);
       kf = S.gkf;
       kl = S.gkl;
@@ -1464,11 +1492,20 @@ __global__ __launch_bounds__(kEndsNT) void k_beta_ends(BetaEndsArgs<Tio> A) {
       head = A.F + S.off + m * S.stride + (int64_t)t * kTile;
       sl = tile_slot(S, m, t, false);
     }
-    double s1, s2;
-    ends_dot<Tio>(head + lane, head + tl - kl + lane, gf + lane, gl + lane, kf, kl, s1, s2);
-    if (lane == 0) {
-      A.summ[2 * sl] = s1;
-      A.summ[2 * sl + 1] = s2;
+    // the first row's head against the tile's first rows, the last row's
+    // tail against its last rows
+    if (part == 0) {
+      double s1, s2;
+      support_dot2<Tio, 4>(head + lane, gf + lane, kf, head + tl - kl + lane, gl + lane, kl, s1,
+                           s2);
+      if (lane == 0) {
+        A.summ[2 * sl] = s1;
+        A.summ[2 * sl + 1] = s2;
+      }
+    } else {
+      const double s = part == 1 ? support_dot<Tio, 8>(head + lane, gf + lane, kf)
+                                 : support_dot<Tio, 8>(head + tl - kl + lane, gl + lane, kl);
+      if (lane == 0) A.summ[2 * sl + part - 1] = s;
     }
   }
 }
@@ -2478,9 +2515,11 @@ static void launch_beta_ends(const LaunchSet& L, const Tio* F, hipStream_t st) {
   const int64_t cap = grid_cap(per_cu, L.wg_per_cu);
   const bool varlen = L.ends_items != nullptr;
   const int64_t n = varlen ? L.n_ends : L.n_beta;
-  BetaEndsArgs<Tio> B{F,       L.sys,  L.green, n,      L.nfull, L.green_kf, L.green_kl,
-                      L.summ,  0,      varlen ? L.ends_items : nullptr, L.gpack};
-  const int64_t want = (n + kEndsNW - 1) / kEndsNW;
+  const int split = !varlen && L.green_kf + L.green_kl > kEndsSplitRows ? 1 : 0;
+  BetaEndsArgs<Tio> B{F,      L.sys,  L.green, n,     split, L.nfull,
+                      L.green_kf, L.green_kl, L.summ, 0,     varlen ? L.ends_items : nullptr,
+                      L.gpack};
+  const int64_t want = ((split ? 2 : 1) * n + kEndsNW - 1) / kEndsNW;
   const int64_t lim = L.wg_per_cu > 0 ? cap : ((int64_t)1 << 30);
   const unsigned grid = (unsigned)(want < lim ? want : lim);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(kEndsNT), 0, st, B);
@@ -2627,10 +2666,12 @@ static hipError_t run_general(const LaunchSet& L, const void* F, void* X, hipStr
       // per tile and right-hand side reads the two ends only
       auto kern = k_beta_ends<SH, Tio>;
       const int64_t nt = L.n_p1 / A.G, n = L.gen_M * nt;
+      const int split = L.gen_kf + L.gen_kl > kEndsSplitRows ? 1 : 0;
       BetaEndsArgs<Tio> B{static_cast<const Tio*>(F),
                           L.sys,
                           static_cast<const double*>(L.gen_green),
                           n,
+                          split,
                           (int)nt,
                           L.gen_kf,
                           L.gen_kl,
@@ -2638,7 +2679,7 @@ static hipError_t run_general(const LaunchSet& L, const void* F, void* X, hipStr
                           (int64_t)L.gen_kf + L.gen_kl,
                           nullptr,
                           nullptr};
-      int64_t grid = (n + kEndsNW - 1) / kEndsNW;
+      int64_t grid = ((split ? 2 : 1) * n + kEndsNW - 1) / kEndsNW;
       if (L.wg_per_cu > 0) {
         static int per_cu = resident_per_cu(kern, kEndsNT);
         const int64_t cap = grid_cap(per_cu, L.wg_per_cu);
