@@ -488,6 +488,7 @@ tdt_status_t build_system(double a, double b, double c, int64_t n, bool quasi, i
   // NT blocks of a tile: beta_{m-1} and 1/(1 - phi_first beta_{m-1})
   // (beta_m contracts to a fixed point, under dominance within a few
   // blocks; once it repeats exactly, so does every later entry)
+  D.tfix = 0;
   {
     ld beta = 0.0L;
     bool fixed = false;
@@ -506,6 +507,7 @@ tdt_status_t build_system(double a, double b, double c, int64_t n, bool quasi, i
         const ld next = blk[3] + blk[1] * beta * blk[2] * iD;
         if (!std::isfinite((double)next)) return TDT_ERR_SINGULAR;
         fixed = next == beta;
+        if (fixed) D.tfix = m;   // entries m, m + 1, ... are equal
         beta = next;
       }
     }

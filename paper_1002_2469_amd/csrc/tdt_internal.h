@@ -69,7 +69,12 @@ struct SysDesc {
   // supports meet only settled pivots) and is summarised from them too
   int64_t goff;
   int32_t gkf, gkl;
-  int32_t glast, gpad;
+  int32_t glast;
+  // the per-position table's entries repeat from position tfix on (its
+  // recurrence reached its fixed point): lanes past it read entry tfix, so
+  // a workgroup's table loads touch a few cache lines (0: every lane reads
+  // its own entry)
+  int32_t tfix;
   // series plans of 8193 to 16384 tiles: the interface pass runs over pairs
   // of adjacent tiles, with the end values of a full pair and of the last one
   double pairK[4], lpairK[4];

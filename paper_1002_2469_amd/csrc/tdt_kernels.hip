@@ -630,14 +630,15 @@ __device__ __forceinline__ void prefetch(const TileArgs<Tio>& A, int64_t item,
   const int vb = opaque(tid * (int)sizeof(Tio));
 #pragma unroll
   for (int j = 0; j < kB; ++j) P.v[j] = buf_load<Tio>(src, vb + j * kNT * (int)sizeof(Tio));
+  const int ti = S.tfix > 0 && tid > S.tfix ? S.tfix : tid;   // repeated entries: one address
   if constexpr (sizeof(Tc) == 8) {
     const double* tb = A.tab64 + (int64_t)S.cidx * kTabN * kNT;
-    P.bp = tb[kTabBeta * kNT + tid];
-    P.iD = tb[kTabInvD * kNT + tid];
+    P.bp = tb[kTabBeta * kNT + ti];
+    P.iD = tb[kTabInvD * kNT + ti];
   } else {
     const float* tb = A.tab32 + (int64_t)S.cidx * kTabN * kNT;
-    P.bp = tb[kTabBeta * kNT + tid];
-    P.iD = tb[kTabInvD * kNT + tid];
+    P.bp = tb[kTabBeta * kNT + ti];
+    P.iD = tb[kTabInvD * kNT + ti];
   }
   if (!SUMMARY) {
     // a one-tile system has no interface pass (zero outside values) unless
@@ -1136,14 +1137,15 @@ __device__ __forceinline__ void lane_table(const SysDesc& S, const double* tab64
                                            const float* tab32, T& bp, T& iD) {
   TDT_SHAPE(SH)
   const int tid = threadIdx.x;
+  const int ti = S.tfix > 0 && tid > S.tfix ? S.tfix : tid;   // repeated entries: one address
   if constexpr (sizeof(T) == 8) {
     const double* tb = tab64 + (int64_t)S.cidx * kTabN * kNT;
-    bp = tb[kTabBeta * kNT + tid];
-    iD = tb[kTabInvD * kNT + tid];
+    bp = tb[kTabBeta * kNT + ti];
+    iD = tb[kTabInvD * kNT + ti];
   } else {
     const float* tb = tab32 + (int64_t)S.cidx * kTabN * kNT;
-    bp = tb[kTabBeta * kNT + tid];
-    iD = tb[kTabInvD * kNT + tid];
+    bp = tb[kTabBeta * kNT + ti];
+    iD = tb[kTabInvD * kNT + ti];
   }
 }
 
