@@ -212,7 +212,9 @@ def run_mode(tdt, d, F, X, mode, steps, warmup, torch, opts=None):
         tuned = plan.autotune(F, X, cache=False, adjoint=d.get("adjoint", False))
     else:
         for k, v in opts.items():
-            if k != "whole_max_tiles" or d["kind"] == "varlen":
+            # whole-system threshold: varlen plans only; a general plan has one work shape
+            if (k != "whole_max_tiles" or d["kind"] == "varlen") and \
+                    (k != "shape" or d["kind"] != "general"):
                 plan.set_option(k, v)
         plan.reserve(d.get("M", 1))
         tuned = {k: plan.get_option(k) for k in ("shape", "whole_max_tiles", "wg_per_cu")}
