@@ -532,6 +532,12 @@ struct TileArgs {
   int* __restrict__ iters;            // refinement: max iterations used (atomicMax)
   int max_iter;
   double refine_tol;
+  // summary launch of a varlen plan: workgroups past the nitems tiles take
+  // the first pass's support items (k_beta_ends' varlen items), a wavefront
+  // each, so that the two halves of the first pass share one launch
+  const int2* __restrict__ ends_items;
+  int64_t n_ends;
+  const double* __restrict__ gpack;
 };
 
 // Copy of a system descriptor read with scalar loads (wave-uniform index).
@@ -996,79 +1002,6 @@ __device__ __forceinline__ void store_corner(Tio* X, const Tio* Xfwd, double* cg
   }
 }
 
-// Workgroups over tiles: by default one tile each (latency hidden by the
-// other resident workgroups, whose loads overlap this one's solve and
-// stores), or a grid capped per CU whose workgroups loop over tiles.  Each
-// iteration loads its tile at the top; a copy that held the next tile in
-// registers ran no faster with one tile per workgroup and spilled in the
-// refinement and adjoint variants.
-//   SUMMARY = true : first pass over a tile of a multi-tile system: writes the
-//                    tile's (y_first, y_last) of its zero-boundary problem.
-//   SUMMARY = false: solves the tile given the values just outside it (zero
-//                    for a one-tile system) and stores X.
-//   REFINE         : Tio = double data, Tc = float sweeps; residual and update
-//                    in double, repeated until converged.
-//   BWD            : also accumulates the t-gradient partial sums against the
-//                    forward solution Xfwd (the tile solves T^T gF = gX).
-template <class SH, typename Tio, typename Tc, bool REFINE, bool SUMMARY, bool BWD, bool QUASI>
-__global__ __launch_bounds__(SH::NT, REFINE ? kRefineWaves : SH::WAVES) void k_tile(
-    TileArgs<Tio> A) {
-  TDT_SHAPE(SH)
-  __shared__ TileShared<SH, Tio, Tc> sh;
-  const int tid = threadIdx.x;
-  const int lbase = lds_base<SH, Tio>();
-  constexpr int lstride = lds_stride<SH, Tio>();
-  auto item_of = [&](int64_t k) { return A.reverse ? A.nitems - 1 - k : k; };
-  constexpr bool PF = false;   // one tile per workgroup: nothing to fetch ahead
-  int it_max = 0;        // refinement record of this workgroup
-  float est_max = 0.0f;
-  int64_t k = blockIdx.x;
-  Prefetch<SH, Tio, Tc> P;
-  if (PF && k < A.nitems) prefetch<SH, Tio, Tc, SUMMARY, QUASI>(A, item_of(k), P);
-
-  while (k < A.nitems) {
-    if (!PF) prefetch<SH, Tio, Tc, SUMMARY, QUASI>(A, item_of(k), P);
-    const int64_t item = item_of(k);
-    const TileGeom G = tile_geom<SH>(A.items, A.sys, item, A.last_only);
-    const SysDesc S = load_sys(A.sys, G.I.s);
-    const int64_t slot = tile_slot(S, G.I.m, G.I.t, A.items != nullptr);
-    const double XLt = P.XL, XRt = P.XR;
-    const Tc bp = P.bp, iDf = P.iD;
-    const Consts<Tc> K = make_consts<SH, Tc>(S, A.vec64, A.vec32);
-    const int tl = G.tl;
-
-    __syncthreads();   // the previous tile is done with LDS
-    {
-      Tio* lw = sh.lds + opaque(lbase);
-#pragma unroll
-      for (int j = 0; j < kB; ++j) lw[j * lstride] = P.v[j];
-    }
-    const int64_t kn = k + gridDim.x;
-    if (PF && kn < A.nitems) prefetch<SH, Tio, Tc, SUMMARY, QUASI>(A, item_of(kn), P);
-    __syncthreads();
-    const bool fold = QUASI && !SUMMARY && tl < kTile;
-    if (fold) {
-      fold_right<SH>(sh, tl, S.c, XRt);
-      __syncthreads();
-    }
-
-    if constexpr (SUMMARY) {
-      solve_tile_lds<SH, Tio, Tc, REFINE, true, QUASI>(sh, tl, 0.0, 0.0, S, K, bp, iDf, A.summ + 2 * slot,
-                                      A.summ + 2 * slot + 1, it_max, est_max, A.max_iter, A.refine_tol);
-    } else {
-      solve_tile_lds<SH, Tio, Tc, REFINE, false>(sh, tl, XLt, fold ? 0.0 : XRt, S, K, bp, iDf,
-                                                 (double*)nullptr, (double*)nullptr, it_max,
-                                                 est_max, A.max_iter, A.refine_tol);
-      __syncthreads();
-      const int64_t fs = A.items ? (int64_t)S.fslot0 + G.I.t : G.I.m * S.ntiles + G.I.t;
-      store_tile<SH, Tio, Tc, BWD, QUASI>(sh, A.X, A.Xfwd, G.base, G.t0, tl, S.n,
-                                          A.gpart + (QUASI ? kGradN : 3) * fs);
-    }
-    k = kn;
-  }
-  publish_refine_record(A.iters, it_max, est_max);
-}
-
 // One wavefront's dot product of k rows of a tile with k entries of a Green
 // row's support (k a multiple of 64; both pointers already offset by the
 // lane), U rows in flight per lane.  The lane sums are added by a fixed
@@ -1122,6 +1055,184 @@ __device__ __forceinline__ double support_dot(const Tio* rows, const double* g, 
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
   return s;
+}
+
+// The same first pass when the two Green rows decay fast (a diagonally
+// dominant T, Sec. 3.4: the entries fall geometrically away from the row's
+// own end): the plan has found the head of the first row (kf entries) and
+// the tail of the last row (kl entries) outside which a row's mass is below
+// 2^-60 of its 1-norm, so each summary reads only those rows of its tile.
+// What is dropped is at most 2^-60 |row|_1 |F|_inf, below the rounding of
+// the dot product itself.  A wavefront takes a tile, or for long supports
+// one end of a tile (the head's dot product and the tail's are independent,
+// so two wavefronts halve the chain of loads each waits on); lanes stride
+// the rows 64 at a time (kf, kl are multiples of 64), and the lane sums are
+// added by a fixed butterfly, so results are repeatable.
+// (kEndsSplitRows, kEndsPartShift: tdt_internal.h)
+constexpr int kEndsNT = 256;
+constexpr int kEndsNW = kEndsNT / 64;
+template <typename Tio>
+struct BetaEndsArgs {
+  const Tio* __restrict__ F;
+  const SysDesc* __restrict__ sys;
+  const double* __restrict__ green;   // series: [2][kTile]: first row, last row
+  int64_t nitems;                     // series: right-hand sides x full tiles per right-hand side
+                                      // (varlen: items)
+  int split;                          // series: a wavefront per tile end (else per tile)
+  int nfull;                          // series: full tiles per right-hand side
+  int kf, kl;                         // series: head of the first row, tail of the last row
+  double* __restrict__ summ;          // [slot][2]
+  int64_t gstride;                    // series: 0, one matrix, green = [2][kTile]; else a
+                                      // general matrix, [tile][kf + kl] (the supports'
+                                      // entries of each tile's own rows)
+  const int2* __restrict__ items;     // varlen: (system, tile | part << kEndsPartShift) per
+                                      // item, else null
+  const double* __restrict__ gpack;   // varlen: each system's head and tail entries
+};
+
+// One wavefront's share of the first pass from the supports: wavefront
+// item iw (a tile, or one end of a tile).  Used by k_beta_ends and by the
+// summary launch of the tile kernel, whose extra workgroups take these items
+// next to the tiles it sweeps.
+template <class SH, typename Tio>
+__device__ __forceinline__ void beta_ends_item(const BetaEndsArgs<Tio>& A, int64_t iw, int lane) {
+  TDT_SHAPE(SH)
+  const int64_t it = A.items || !A.split ? iw : iw >> 1;
+  int part = A.items || !A.split ? 0 : 1 + (int)(iw & 1);
+  // this item's tile, the supports and their entries
+  const Tio* head;
+  const double *gf, *gl;
+  int kf, kl;
+  int64_t sl;
+  int tl = kTile;
+  if (A.items) {
+    const cptr<int> iv = as_const(reinterpret_cast<const int*>(A.items)) + 2 * it;
+    const int s = iv[0], t = iv[1] & ((1 << kEndsPartShift) - 1);
+    part = iv[1] >> kEndsPartShift;
+    const SysDesc S = load_sys(A.sys, s);
+    kf = S.gkf;
+    kl = S.gkl;
+    gf = A.gpack + S.goff;
+    gl = gf + kf;
+    head = A.F + S.off + (int64_t)t * kTile;
+    sl = tile_slot(S, 0, t, true);
+    const int64_t rest = S.n - (int64_t)t * kTile;   // a shorter last tile (glast)
+    tl = rest < kTile ? (int)rest : kTile;
+  } else {
+    const SysDesc S = load_sys(A.sys, 0);
+    const int64_t m = it / A.nfull;
+    const int t = (int)(it - m * A.nfull);
+    kf = A.kf;
+    kl = A.kl;
+    gf = A.green + t * A.gstride;
+    gl = A.gstride ? gf + kf : gf + 2 * kTile - kl;
+    head = A.F + S.off + m * S.stride + (int64_t)t * kTile;
+    sl = tile_slot(S, m, t, false);
+  }
+  // the first row's head against the tile's first rows, the last row's
+  // tail against its last rows
+  if (part == 0) {
+    double s1, s2;
+    support_dot2<Tio, 4>(head + lane, gf + lane, kf, head + tl - kl + lane, gl + lane, kl, s1,
+                         s2);
+    if (lane == 0) {
+      A.summ[2 * sl] = s1;
+      A.summ[2 * sl + 1] = s2;
+    }
+  } else {
+    const double s = part == 1 ? support_dot<Tio, 8>(head + lane, gf + lane, kf)
+                               : support_dot<Tio, 8>(head + tl - kl + lane, gl + lane, kl);
+    if (lane == 0) A.summ[2 * sl + part - 1] = s;
+  }
+}
+
+// Workgroups over tiles: by default one tile each (latency hidden by the
+// other resident workgroups, whose loads overlap this one's solve and
+// stores), or a grid capped per CU whose workgroups loop over tiles.  Each
+// iteration loads its tile at the top; a copy that held the next tile in
+// registers ran no faster with one tile per workgroup and spilled in the
+// refinement and adjoint variants.
+//   SUMMARY = true : first pass over a tile of a multi-tile system: writes the
+//                    tile's (y_first, y_last) of its zero-boundary problem.
+//   SUMMARY = false: solves the tile given the values just outside it (zero
+//                    for a one-tile system) and stores X.
+//   REFINE         : Tio = double data, Tc = float sweeps; residual and update
+//                    in double, repeated until converged.
+//   BWD            : also accumulates the t-gradient partial sums against the
+//                    forward solution Xfwd (the tile solves T^T gF = gX).
+template <class SH, typename Tio, typename Tc, bool REFINE, bool SUMMARY, bool BWD, bool QUASI>
+__global__ __launch_bounds__(SH::NT, REFINE ? kRefineWaves : SH::WAVES) void k_tile(
+    TileArgs<Tio> A) {
+  TDT_SHAPE(SH)
+  __shared__ TileShared<SH, Tio, Tc> sh;
+  const int tid = threadIdx.x;
+  if constexpr (SUMMARY) {
+    if (A.n_ends > 0 && (int64_t)blockIdx.x >= A.nitems) {
+      // a workgroup of support items (the launch has one tile per workgroup)
+      BetaEndsArgs<Tio> B{};
+      B.F = A.F;
+      B.sys = A.sys;
+      B.nitems = A.n_ends;
+      B.summ = A.summ;
+      B.items = A.ends_items;
+      B.gpack = A.gpack;
+      const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+      const int64_t iw = ((int64_t)blockIdx.x - A.nitems) * kNW + w;
+      if (iw < A.n_ends) beta_ends_item<SH, Tio>(B, iw, tid & 63);
+      return;
+    }
+  }
+  const int lbase = lds_base<SH, Tio>();
+  constexpr int lstride = lds_stride<SH, Tio>();
+  auto item_of = [&](int64_t k) { return A.reverse ? A.nitems - 1 - k : k; };
+  constexpr bool PF = false;   // one tile per workgroup: nothing to fetch ahead
+  int it_max = 0;        // refinement record of this workgroup
+  float est_max = 0.0f;
+  int64_t k = blockIdx.x;
+  Prefetch<SH, Tio, Tc> P;
+  if (PF && k < A.nitems) prefetch<SH, Tio, Tc, SUMMARY, QUASI>(A, item_of(k), P);
+
+  while (k < A.nitems) {
+    if (!PF) prefetch<SH, Tio, Tc, SUMMARY, QUASI>(A, item_of(k), P);
+    const int64_t item = item_of(k);
+    const TileGeom G = tile_geom<SH>(A.items, A.sys, item, A.last_only);
+    const SysDesc S = load_sys(A.sys, G.I.s);
+    const int64_t slot = tile_slot(S, G.I.m, G.I.t, A.items != nullptr);
+    const double XLt = P.XL, XRt = P.XR;
+    const Tc bp = P.bp, iDf = P.iD;
+    const Consts<Tc> K = make_consts<SH, Tc>(S, A.vec64, A.vec32);
+    const int tl = G.tl;
+
+    __syncthreads();   // the previous tile is done with LDS
+    {
+      Tio* lw = sh.lds + opaque(lbase);
+#pragma unroll
+      for (int j = 0; j < kB; ++j) lw[j * lstride] = P.v[j];
+    }
+    const int64_t kn = k + gridDim.x;
+    if (PF && kn < A.nitems) prefetch<SH, Tio, Tc, SUMMARY, QUASI>(A, item_of(kn), P);
+    __syncthreads();
+    const bool fold = QUASI && !SUMMARY && tl < kTile;
+    if (fold) {
+      fold_right<SH>(sh, tl, S.c, XRt);
+      __syncthreads();
+    }
+
+    if constexpr (SUMMARY) {
+      solve_tile_lds<SH, Tio, Tc, REFINE, true, QUASI>(sh, tl, 0.0, 0.0, S, K, bp, iDf, A.summ + 2 * slot,
+                                      A.summ + 2 * slot + 1, it_max, est_max, A.max_iter, A.refine_tol);
+    } else {
+      solve_tile_lds<SH, Tio, Tc, REFINE, false>(sh, tl, XLt, fold ? 0.0 : XRt, S, K, bp, iDf,
+                                                 (double*)nullptr, (double*)nullptr, it_max,
+                                                 est_max, A.max_iter, A.refine_tol);
+      __syncthreads();
+      const int64_t fs = A.items ? (int64_t)S.fslot0 + G.I.t : G.I.m * S.ntiles + G.I.t;
+      store_tile<SH, Tio, Tc, BWD, QUASI>(sh, A.X, A.Xfwd, G.base, G.t0, tl, S.n,
+                                          A.gpart + (QUASI ? kGradN : 3) * fs);
+    }
+    k = kn;
+  }
+  publish_refine_record(A.iters, it_max, est_max);
 }
 
 template <typename Tio>
@@ -1451,95 +1562,14 @@ __global__ __launch_bounds__(kBetaNT) void k_beta(BetaArgs<Tio> A) {
   }
 }
 
-// The same first pass when the two Green rows decay fast (a diagonally
-// dominant T, Sec. 3.4: the entries fall geometrically away from the row's
-// own end): the plan has found the head of the first row (kf entries) and
-// the tail of the last row (kl entries) outside which a row's mass is below
-// 2^-60 of its 1-norm, so each summary reads only those rows of its tile.
-// What is dropped is at most 2^-60 |row|_1 |F|_inf, below the rounding of
-// the dot product itself.  A wavefront takes a tile, or for long supports
-// one end of a tile (the head's dot product and the tail's are independent,
-// so two wavefronts halve the chain of loads each waits on); lanes stride
-// the rows 64 at a time (kf, kl are multiples of 64), and the lane sums are
-// added by a fixed butterfly, so results are repeatable.
-// (kEndsSplitRows, kEndsPartShift: tdt_internal.h)
-constexpr int kEndsNT = 256;
-constexpr int kEndsNW = kEndsNT / 64;
-template <typename Tio>
-struct BetaEndsArgs {
-  const Tio* __restrict__ F;
-  const SysDesc* __restrict__ sys;
-  const double* __restrict__ green;   // series: [2][kTile]: first row, last row
-  int64_t nitems;                     // series: right-hand sides x full tiles per right-hand side
-                                      // (varlen: items)
-  int split;                          // series: a wavefront per tile end (else per tile)
-  int nfull;                          // series: full tiles per right-hand side
-  int kf, kl;                         // series: head of the first row, tail of the last row
-  double* __restrict__ summ;          // [slot][2]
-  int64_t gstride;                    // series: 0, one matrix, green = [2][kTile]; else a
-                                      // general matrix, [tile][kf + kl] (the supports'
-                                      // entries of each tile's own rows)
-  const int2* __restrict__ items;     // varlen: (system, tile | part << kEndsPartShift) per
-                                      // item, else null
-  const double* __restrict__ gpack;   // varlen: each system's head and tail entries
-};
-
 template <class SH, typename Tio>
 __global__ __launch_bounds__(kEndsNT) void k_beta_ends(BetaEndsArgs<Tio> A) {
-  TDT_SHAPE(SH)
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int64_t nw = A.items || !A.split ? A.nitems : 2 * A.nitems;   // wavefront items
   for (int64_t iw = (int64_t)blockIdx.x * kEndsNW + w; iw < nw;
-       iw += (int64_t)gridDim.x * kEndsNW) {
-    const int64_t it = A.items || !A.split ? iw : iw >> 1;
-    int part = A.items || !A.split ? 0 : 1 + (int)(iw & 1);
-    // this item's tile, the supports and their entries
-    const Tio* head;
-    const double *gf, *gl;
-    int kf, kl;
-    int64_t sl;
-    int tl = kTile;
-    if (A.items) {
-      const cptr<int> iv = as_const(reinterpret_cast<const int*>(A.items)) + 2 * it;
-      const int s = iv[0], t = iv[1] & ((1 << kEndsPartShift) - 1);
-      part = iv[1] >> kEndsPartShift;
-      const SysDesc S = load_sys(A.sys, s);
-      kf = S.gkf;
-      kl = S.gkl;
-      gf = A.gpack + S.goff;
-      gl = gf + kf;
-      head = A.F + S.off + (int64_t)t * kTile;
-      sl = tile_slot(S, 0, t, true);
-      const int64_t rest = S.n - (int64_t)t * kTile;   // a shorter last tile (glast)
-      tl = rest < kTile ? (int)rest : kTile;
-    } else {
-      const SysDesc S = load_sys(A.sys, 0);
-      const int64_t m = it / A.nfull;
-      const int t = (int)(it - m * A.nfull);
-      kf = A.kf;
-      kl = A.kl;
-      gf = A.green + t * A.gstride;
-      gl = A.gstride ? gf + kf : gf + 2 * kTile - kl;
-      head = A.F + S.off + m * S.stride + (int64_t)t * kTile;
-      sl = tile_slot(S, m, t, false);
-    }
-    // the first row's head against the tile's first rows, the last row's
-    // tail against its last rows
-    if (part == 0) {
-      double s1, s2;
-      support_dot2<Tio, 4>(head + lane, gf + lane, kf, head + tl - kl + lane, gl + lane, kl, s1,
-                           s2);
-      if (lane == 0) {
-        A.summ[2 * sl] = s1;
-        A.summ[2 * sl + 1] = s2;
-      }
-    } else {
-      const double s = part == 1 ? support_dot<Tio, 8>(head + lane, gf + lane, kf)
-                                 : support_dot<Tio, 8>(head + tl - kl + lane, gl + lane, kl);
-      if (lane == 0) A.summ[2 * sl + part - 1] = s;
-    }
-  }
+       iw += (int64_t)gridDim.x * kEndsNW)
+    beta_ends_item<SH, Tio>(A, iw, lane);
 }
 
 // First pass of a general double series plan: the same Green-row dot
@@ -2496,14 +2526,16 @@ static int64_t grid_cap(int per_cu, int wg_per_cu) {
 // loop over tiles).  With a cap per CU the workgroups persist and loop.
 template <class SH, typename Tio, typename Tc, bool REFINE, bool SUMMARY, bool BWD, bool QUASI>
 static void launch_tile(TileArgs<Tio>& A, int64_t nitems, int reverse, int last_only,
-                        int wg_per_cu, hipStream_t st) {
+                        int wg_per_cu, hipStream_t st, int64_t extra_wg = 0) {
   auto kern = k_tile<SH, Tio, Tc, REFINE, SUMMARY, BWD, QUASI>;
   static int per_cu = resident_per_cu(kern, SH::NT);
   const int64_t cap = wg_per_cu > 0 ? grid_cap(per_cu, wg_per_cu) : nitems;
   A.nitems = nitems;
   A.reverse = reverse;
   A.last_only = last_only;
-  const unsigned grid = (unsigned)(nitems < cap ? nitems : cap);
+  // extra_wg: workgroups past the tiles (support items of the summary
+  // launch; only with one tile per workgroup)
+  const unsigned grid = (unsigned)((nitems < cap ? nitems : cap) + extra_wg);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(SH::NT), 0, st, A);
 }
 
@@ -2616,10 +2648,21 @@ static hipError_t run_solve(const LaunchSet& L, const void* F, void* X, const vo
         launch_tile<SH, Tio, Ts, false, true, false, QUASI>(A, L.n_last, 0, 1, L.wg_per_cu, st);
       }
     } else {
-      if (L.n_ends > 0) launch_beta_ends<SH, Tio>(L, static_cast<const Tio*>(F), st);
+      // support items and swept tiles in one launch (one tile per
+      // workgroup), else the support items first
+      const bool fuse = L.n_ends > 0 && L.n_p1 > 0 && L.wg_per_cu == 0;
+      if (L.n_ends > 0 && !fuse) launch_beta_ends<SH, Tio>(L, static_cast<const Tio*>(F), st);
       A.items = L.p1_items;
-      if (L.n_p1 > 0)
-        launch_tile<SH, Tio, Ts, false, true, false, QUASI>(A, L.n_p1, 0, 0, L.wg_per_cu, st);
+      if (L.n_p1 > 0) {
+        if (fuse) {
+          A.ends_items = L.ends_items;
+          A.n_ends = L.n_ends;
+          A.gpack = L.gpack;
+        }
+        launch_tile<SH, Tio, Ts, false, true, false, QUASI>(
+            A, L.n_p1, 0, 0, L.wg_per_cu, st, fuse ? (L.n_ends + SH::NW - 1) / SH::NW : 0);
+        A.n_ends = 0;
+      }
     }
     if (L.ev) (void)hipEventRecord(L.ev[1], st);
     launch_grid<QUASI>(L, F, X, Xfwd, sizeof(Tio) == 4 ? 1 : 0, st);
