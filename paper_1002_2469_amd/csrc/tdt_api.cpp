@@ -40,7 +40,7 @@ struct tdt_plan_s {
   std::vector<double> in_psi, in_chi;   // quasi-Toeplitz corner terms (quasi plans)
   std::vector<int64_t> in_sizes, in_offs;
   bool quasi = false;     // every system is quasi-Toeplitz (eq. (21))
-  bool pairs = false;     // series of 8193..16384 tiles: interface pass over tile pairs
+  bool chunks = false;    // series of 2049..16384 tiles: interface pass in chunks of 64 tiles
   // general (per-row) matrix of a series plan: its rows, and per direction the
   // per-row LU and per-block constants (compute precision), per-tile end values
   bool general = false;
@@ -889,12 +889,12 @@ tdt_status_t finish_plan(tdt_plan_s* p, const std::vector<double>& tm1,
   {
     int maxp = 1;
     for (const SysDesc& D : p->hsys[0]) maxp = std::max(maxp, (int)D.ntiles);
-    // (the same thresholds as launch_grid: <256,1>, <256,8>, <512,16>,
-    // <1024,16>, then the segment-merge kernel; a series Toeplitz plan of
-    // 8193..16384 tiles takes the pair kernel, kPairR pairs per thread)
-    p->pairs = !p->varlen && !p->quasi && maxp > 8192 && maxp <= 16384;
-    const int tr = p->pairs ? 2 * tdt::kPairR
-                            : (maxp <= 256 ? 1 : (maxp <= 2048 ? 8 : (maxp <= 16384 ? 16 : 1)));
+    // (the same thresholds as launch_grid: <64,1>, <256,1>, <256,8>,
+    // <512,16>, <1024,16>, then the segment-merge kernel; a series Toeplitz
+    // plan of 2049..16384 tiles takes the chunked pass, one tile per slot)
+    p->chunks = !p->varlen && !p->quasi && maxp > 2048 && maxp <= 16384;
+    const int tr = p->chunks ? 1
+                             : (maxp <= 256 ? 1 : (maxp <= 2048 ? 8 : (maxp <= 16384 ? 16 : 1)));
     for (int dir = 0; dir < 2; ++dir)
       for (SysDesc& D : p->hsys[dir]) {
         D.tr = tr;
@@ -933,37 +933,6 @@ tdt_status_t finish_plan(tdt_plan_s* p, const std::vector<double>& tm1,
       if (!needs_interface(D)) continue;
       const int64_t base = p->varlen ? D.slot0 : 0;
       ld beta = D.quasi ? (ld)D.qc[1] : 0.0L;
-      if (p->pairs) {
-        // pairs of tiles: the end values of a pair are its two tiles' merged
-        // (the last pair is the last two tiles, or the last tile alone), and
-        // the table runs over pair positions q, at (q % kPairR) tq + q / kPairR
-        auto seg = [](const double* K) { return SegLD{0, 0, K[0], K[1], K[2], K[3]}; };
-        SegLD full, last;
-        if (!merge_ld(seg(D.tileK), seg(D.tileK), full)) return TDT_ERR_SINGULAR;
-        if (D.ntiles % 2 == 0) {
-          if (!merge_ld(seg(D.tileK), seg(D.ltileK), last)) return TDT_ERR_SINGULAR;
-        } else {
-          last = seg(D.ltileK);
-        }
-        const ld fk[4] = {full.pf, full.pl, full.cf, full.cl};
-        const ld lk[4] = {last.pf, last.pl, last.cf, last.cl};
-        for (int k = 0; k < 4; ++k) {
-          D.pairK[k] = (double)fk[k];
-          D.lpairK[k] = (double)lk[k];
-        }
-        const int np = (D.ntiles + 1) / 2;
-        for (int q = 0; q < np; ++q) {
-          const ld* K = q + 1 < np ? fk : lk;
-          const ld den = 1.0L - K[0] * beta;
-          if (!(std::fabs((double)den) > 1e-13)) return TDT_ERR_SINGULAR;
-          const ld iD = 1.0L / den;
-          const int64_t pos = (int64_t)(q % tdt::kPairR) * D.tq + q / tdt::kPairR;
-          tt[base + pos] = (double)beta;
-          tt[p->ttab_n + base + pos] = (double)iD;
-          beta = K[3] + K[1] * beta * K[2] * iD;
-        }
-        continue;
-      }
       for (int t = 0; t < D.ntiles; ++t) {
         const double* K = t + 1 < D.ntiles ? D.tileK : D.ltileK;
         const ld den = 1.0L - (ld)K[0] * beta;
@@ -1297,7 +1266,7 @@ tdt_status_t launch_set(tdt_plan_s* p, int dir, bool adjoint, int64_t M, tdt::La
   L.ttab_n = p->ttab_n;
   L.max_ntiles = 1;
   for (const SysDesc& D : p->hsys[0]) L.max_ntiles = std::max(L.max_ntiles, (int)D.ntiles);
-  L.pairs = p->pairs ? 1 : 0;
+  L.chunks = p->chunks ? 1 : 0;
   L.general = p->general ? 1 : 0;
   L.gen_row = p->dgrow[dir];
   L.gen_blk = p->dgblk[dir];

@@ -75,13 +75,7 @@ struct SysDesc {
   // a workgroup's table loads touch a few cache lines (0: every lane reads
   // its own entry)
   int32_t tfix;
-  // series plans of 8193 to 16384 tiles: the interface pass runs over pairs
-  // of adjacent tiles, with the end values of a full pair and of the last one
-  double pairK[4], lpairK[4];
 };
-// The pair interface pass: threads, and pairs per thread (2 kPairR tiles)
-constexpr int kPairNT = 512;
-constexpr int kPairR = 16;
 // First pass from the Green rows' supports: supports longer than this many
 // rows (head and tail together) take a wavefront per tile end, shorter ones
 // a wavefront per tile.  Varlen items carry the part of the tile in the bits
@@ -142,7 +136,7 @@ struct LaunchSet {
   const double* gpack;
   int nfull;
   int max_ntiles;          // most tiles of any system (selects the interface kernel)
-  int pairs;               // series of 8193..16384 tiles: interface pass over tile pairs
+  int chunks;              // series of 2049..16384 tiles: interface pass in chunks of 64 tiles
   const double* ttab;      // per tile position: beta_{t-1}, 1/(1 - Pf beta_{t-1}) ([2][ttab_n])
   int64_t ttab_n;
   double* summ;

@@ -2010,128 +2010,6 @@ __global__ __launch_bounds__(NTG) void k_grid_affine(GridArgs A) {
   }
 }
 
-// The interface pass of a series of 8193 to 16384 tiles (a 2^26-row system
-// in 4096-row tiles): over pairs of adjacent tiles, each of 512 threads
-// taking 16 pairs, as the kernel above takes 16 tiles.  A pair's summary is
-// its two tiles' merged (the 2x2 elimination at their junction with zero
-// outside values); the summaries wait in LDS (8192 pairs: 128 KiB), so that
-// the registers hold only the scans' per-pair values.  Once the scans have
-// given each pair its two outside values, the same 2x2 system gives the two
-// unknowns at the junction, the inner outside values of the two tiles (the
-// dichotomy step one level down).  Tile t = 2q + k of pair q sits at slot
-// (t % 2R) tq + t / 2R; the plan's table runs over pair positions
-// (q % R) tq + q / R.
-template <int NTG, int R>
-__global__ __launch_bounds__(NTG) void k_grid_pairs(GridArgs A) {
-  __shared__ GridShared<NTG> sh;
-  __shared__ double ys[2][R * NTG];   // pair summaries, pair qa + r at r NTG + tid
-  const int tid = threadIdx.x;
-  const int64_t slot0 = (int64_t)blockIdx.x * *as_const(&A.sys[0].tslots);
-  const SysDesc S = load_sys(A.sys, 0);
-  const int P = S.ntiles, P2 = (P + 1) / 2;
-  const int tq = S.tq;
-  const double* summ = A.summ + 2 * slot0;
-  double* ghost = A.ghost + 2 * slot0;
-  const int qa = tid * R;   // this thread's pairs qa .. qa+R-1
-  auto tpos = [&](int r, int k) { return (2 * r + k) * tq + tid; };
-  auto tK = [&](int t) { return t == P - 1 ? S.ltileK : S.tileK; };
-  // 1. pair summaries (pairs past the end: empty, passing values through;
-  //    eight pairs' loads in flight: all sixteen spill)
-#pragma unroll 8
-  for (int r = 0; r < R; ++r) {
-    const int a = 2 * (qa + r), b = a + 1;
-    const double ufa = summ[2 * tpos(r, 0)], ula = summ[2 * tpos(r, 0) + 1];
-    const double ufb = summ[2 * tpos(r, 1)], ulb = summ[2 * tpos(r, 1) + 1];
-    const double* Ka = tK(a);
-    const double* Kb = tK(b);
-    const double iDj = 1.0 / (1.0 - Ka[3] * Kb[0]);
-    const double xa = (ula + Ka[3] * ufb) * iDj;   // last row of a, zero outside the pair
-    const double xb = ufb + Kb[0] * xa;            // first row of b
-    ys[0][r * NTG + tid] = b < P ? ufa + xb * Ka[2] : (a < P ? ufa : 0.0);
-    ys[1][r * NTG + tid] = b < P ? ulb + xa * Kb[1] : (a < P ? ula : 0.0);
-  }
-  auto kofs = [&](int q, double& pf, double& pl, double& cf, double& cl) {
-    const bool real = q < P2, last = q == P2 - 1;
-    const double* K = last ? S.lpairK : S.pairK;
-    pf = real ? K[0] : 0.0;
-    pl = real ? K[1] : 1.0;
-    cf = real ? K[2] : 1.0;
-    cl = real ? K[3] : 0.0;
-  };
-  auto yf = [&](int r) { return ys[0][r * NTG + tid]; };
-  auto yl = [&](int r) { return ys[1][r * NTG + tid]; };
-  double bp[R], iD[R];
-  double Af = 1.0, gf = 0.0;
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int q = qa + r;
-    const int pc = q < P2 ? r * tq + tid : 0;
-    const double b0 = A.ttab[pc], i0 = A.ttab[A.ttab_n + pc];
-    bp[r] = q < P2 ? b0 : 0.0;
-    iD[r] = q < P2 ? i0 : 1.0;
-  }
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    double pf, pl, cf, cl;
-    kofs(qa + r, pf, pl, cf, cl);
-    const double At = pl * iD[r];
-    const double gt = yl(r) + At * bp[r] * yf(r);
-    gf = At * gf + gt;
-    Af = At * Af;
-  }
-  // 2. alpha (left to right)
-  double alpha = scan_affine_fwd<NTG>(Af, gf, 0.0, sh.f);
-  double ap[R], h[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    double pf, pl, cf, cl;
-    kofs(qa + r, pf, pl, cf, cl);
-    ap[r] = alpha;
-    h[r] = (yf(r) + pf * alpha) * iD[r];
-    alpha = pl * iD[r] * alpha + (yl(r) + pl * iD[r] * bp[r] * yf(r));
-  }
-  // 3. u (right to left)
-  double Cb = 1.0, hb = 0.0;
-#pragma unroll
-  for (int r = R - 1; r >= 0; --r) {
-    double pf, pl, cf, cl;
-    kofs(qa + r, pf, pl, cf, cl);
-    const double Cr = cf * iD[r];
-    hb = Cr * hb + h[r];
-    Cb = Cr * Cb;
-  }
-  double u = scan_affine_bwd<NTG>(Cb, hb, 0.0, sh.b);
-  // 4. the pair's outside values, then its tiles': the junction unknowns
-  //    v (last row of a) and w (first row of b) from
-  //      v = yl_a + XL pl_a + w cl_a,   w = yf_b + v pf_b + XR cf_b
-#pragma unroll
-  for (int r = R - 1; r >= 0; --r) {
-    const int q = qa + r;
-    double pf, pl, cf, cl;
-    kofs(q, pf, pl, cf, cl);
-    const double un = u;                 // right outside value of pair q
-    u = cf * iD[r] * u + h[r];           // first unknown of pair q
-    if (q < P2) {
-      const double XL = ap[r] + bp[r] * u, XR = un;
-      const int a = 2 * q, b = a + 1;
-      if (b < P) {
-        const double ula = summ[2 * tpos(r, 0) + 1], ufb = summ[2 * tpos(r, 1)];
-        const double* Ka = tK(a);
-        const double* Kb = tK(b);
-        const double v = (ula + XL * Ka[1] + Ka[3] * (ufb + XR * Kb[2])) / (1.0 - Ka[3] * Kb[0]);
-        const double w = ufb + v * Kb[0] + XR * Kb[2];
-        ghost[2 * tpos(r, 0)] = XL;
-        ghost[2 * tpos(r, 0) + 1] = w;
-        ghost[2 * tpos(r, 1)] = v;
-        ghost[2 * tpos(r, 1) + 1] = XR;
-      } else {
-        ghost[2 * tpos(r, 0)] = XL;
-        ghost[2 * tpos(r, 0) + 1] = XR;
-      }
-    }
-  }
-}
-
 // The same pass for the widest workgroup (1024 threads, whose register
 // budget cannot hold a run's inputs): each pass re-reads a tile's inputs from
 // L2, and alpha_{t-1} and h_t wait in the tile's ghost slot between passes.
@@ -2589,6 +2467,163 @@ static void launch_beta_ends(const LaunchSet& L, const Tio* F, hipStream_t st) {
   hipLaunchKernelGGL(kern, dim3(grid), dim3(kEndsNT), 0, st, B);
 }
 
+// Interface pass of a series Toeplitz plan of 2049 to 16384 tiles, in two
+// launches over chunks of 64 tiles, one wavefront per chunk and right-hand
+// side, instead of one workgroup per system (whose single compute unit the
+// 16384-tile pass left waiting on its loads and stores).  With the tiles'
+// maps of eq. (15) written as in the affine variants,
+//   alpha_t = A_t alpha_{t-1} + g_t,   u_t = C_t u_{t+1} + h_t,
+//   h_t = (y_f + Pf alpha_{t-1}) iD_t,
+// a chunk's alpha_{t-1} is affine in the alpha entering the chunk, so its
+// h_t are too, and the chunk composes to alpha_out = Ac alpha_in + gc and
+//   u_first = Cc u_right + Hq + Hp alpha_in.
+// The first launch writes these five numbers per chunk; the second scans
+// them over the chunks (every wavefront redundantly: at most 256 chunks, in
+// L2), then its own chunk's tiles, and writes their outside values.  No
+// atomics and no waiting between workgroups.  Slots are plain (a run of one
+// tile per thread), so a chunk's summaries are contiguous.
+constexpr int kChunkNT = 256;
+constexpr int kChunkRC = 4;   // chunks per lane in the chunk scan (up to 64 x 4 chunks)
+
+// Tile t's summaries, table entries and end values (identity maps past the
+// last tile).
+__device__ __forceinline__ void chunk_tile(const GridArgs& A, const SysDesc& S, int64_t slot0,
+                                           int t, double& yf, double& yl, double& bp,
+                                           double& iD, double& pf, double& pl, double& cf) {
+  const int P = S.ntiles;
+  const bool real = t < P;
+  const int tc = real ? t : 0;
+  const double* K = t == P - 1 ? S.ltileK : S.tileK;
+  const double u = A.summ[2 * (slot0 + tc)], v = A.summ[2 * (slot0 + tc) + 1];
+  const double b0 = A.ttab[tc], i0 = A.ttab[A.ttab_n + tc];
+  yf = real ? u : 0.0;
+  yl = real ? v : 0.0;
+  bp = real ? b0 : 0.0;
+  iD = real ? i0 : 1.0;
+  pf = real ? K[0] : 0.0;
+  pl = real ? K[1] : 1.0;
+  cf = real ? K[2] : 1.0;
+}
+
+__global__ __launch_bounds__(kChunkNT) void k_grid_chunk_reduce(GridArgs A, int64_t M) {
+  const int lane = threadIdx.x & 63;
+  const int64_t gw = (int64_t)blockIdx.x * (kChunkNT / 64) +
+                     __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const SysDesc S = load_sys(A.sys, 0);
+  const int NC = (S.ntiles + 63) / 64;
+  const int64_t m = gw / NC;
+  const int c = (int)(gw - m * NC);
+  if (m >= M) return;
+  double yf, yl, bp, iD, pf, pl, cf;
+  chunk_tile(A, S, m * S.tslots, c * 64 + lane, yf, yl, bp, iD, pf, pl, cf);
+  double Ai = pl * iD, gi = yl + pl * iD * bp * yf;
+  wave_scan_affine_fwd(Ai, gi);   // alpha_t = Ai alpha_in + gi
+  double Pe = __shfl_up(Ai, 1, 64), Qe = __shfl_up(gi, 1, 64);   // alpha_{t-1}
+  if (lane == 0) {
+    Pe = 1.0;
+    Qe = 0.0;
+  }
+  double C1 = cf * iD, C2 = C1;
+  double hq = (yf + pf * Qe) * iD, hp = pf * Pe * iD;
+  wave_scan_affine_bwd(C1, hq);
+  wave_scan_affine_bwd(C2, hp);
+  const double Ac = readlane(Ai, 63), gc = readlane(gi, 63);
+  if (lane == 0) {
+    double* o = A.gscr + 5 * (m * NC + c);
+    o[0] = Ac;
+    o[1] = gc;
+    o[2] = C1;
+    o[3] = hq;
+    o[4] = hp;
+  }
+}
+
+__global__ __launch_bounds__(kChunkNT) void k_grid_chunk_apply(GridArgs A, int64_t M) {
+  const int lane = threadIdx.x & 63;
+  const int64_t gw = (int64_t)blockIdx.x * (kChunkNT / 64) +
+                     __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const SysDesc S = load_sys(A.sys, 0);
+  const int NC = (S.ntiles + 63) / 64;
+  const int64_t m = gw / NC;
+  const int c = (int)(gw - m * NC);
+  if (m >= M) return;
+  // 1. the chunks: lane k holds chunks k RC .. k RC + RC - 1
+  const double* ch = A.gscr + 5 * m * NC;
+  double Ac[kChunkRC], gc[kChunkRC], Cc[kChunkRC], Hq[kChunkRC], Hp[kChunkRC];
+#pragma unroll
+  for (int r = 0; r < kChunkRC; ++r) {
+    const int q = lane * kChunkRC + r;
+    const bool real = q < NC;
+    const double* e = ch + 5 * (real ? q : 0);
+    const double e0 = e[0], e1 = e[1], e2 = e[2], e3 = e[3], e4 = e[4];
+    Ac[r] = real ? e0 : 1.0;
+    gc[r] = real ? e1 : 0.0;
+    Cc[r] = real ? e2 : 1.0;
+    Hq[r] = real ? e3 : 0.0;
+    Hp[r] = real ? e4 : 0.0;
+  }
+  double Ar = 1.0, gr = 0.0;
+#pragma unroll
+  for (int r = 0; r < kChunkRC; ++r) {
+    gr = Ac[r] * gr + gc[r];
+    Ar = Ac[r] * Ar;
+  }
+  wave_scan_affine_fwd(Ar, gr);
+  double a = __shfl_up(gr, 1, 64);   // alpha entering the lane's chunks (alpha_{-1} = 0)
+  if (lane == 0) a = 0.0;
+  double ain[kChunkRC], hb[kChunkRC];
+#pragma unroll
+  for (int r = 0; r < kChunkRC; ++r) {
+    ain[r] = a;
+    hb[r] = Hq[r] + Hp[r] * a;
+    a = Ac[r] * a + gc[r];
+  }
+  double Cr = 1.0, hr = 0.0;
+#pragma unroll
+  for (int r = kChunkRC - 1; r >= 0; --r) {
+    hr = Cc[r] * hr + hb[r];
+    Cr = Cc[r] * Cr;
+  }
+  wave_scan_affine_bwd(Cr, hr);
+  double u = __shfl_down(hr, 1, 64);   // u entering the lane's chunks from the right (u_P = 0)
+  if (lane == 63) u = 0.0;
+  double ur[kChunkRC];
+#pragma unroll
+  for (int r = kChunkRC - 1; r >= 0; --r) {
+    ur[r] = u;
+    u = Cc[r] * u + hb[r];
+  }
+  // this wavefront's chunk c: held by lane c / RC as its entry c % RC
+  const int rc = c % kChunkRC;
+  double ai = ain[0], uo = ur[0];
+#pragma unroll
+  for (int r = 1; r < kChunkRC; ++r) {
+    ai = rc == r ? ain[r] : ai;
+    uo = rc == r ? ur[r] : uo;
+  }
+  const double alpha_in = __shfl(ai, c / kChunkRC, 64);
+  const double u_right = __shfl(uo, c / kChunkRC, 64);
+  // 2. the chunk's tiles
+  const int64_t slot0 = m * S.tslots;
+  const int t = c * 64 + lane;
+  double yf, yl, bp, iD, pf, pl, cf;
+  chunk_tile(A, S, slot0, t, yf, yl, bp, iD, pf, pl, cf);
+  double Ai = pl * iD, gi = yl + pl * iD * bp * yf;
+  wave_scan_affine_fwd(Ai, gi);
+  const double ainc = Ai * alpha_in + gi;                    // alpha_t
+  double am = __shfl_up(ainc, 1, 64);                        // alpha_{t-1}
+  if (lane == 0) am = alpha_in;
+  double Ct = cf * iD, ht = (yf + pf * am) * iD;
+  wave_scan_affine_bwd(Ct, ht);
+  const double ut = Ct * u_right + ht;                       // u_t
+  double un = __shfl_down(ut, 1, 64);                        // u_{t+1}
+  if (lane == 63) un = u_right;
+  if (t < S.ntiles) {
+    A.ghost[2 * (slot0 + t)] = am + bp * ut;
+    A.ghost[2 * (slot0 + t) + 1] = un;
+  }
+}
+
 // Interface pass across tiles: the affine variant sized for the most tiled
 // system (up to 16384 tiles), beyond that the segment-merge kernel.  The
 // plan lays out its workspace slots for the same choice (interface_run).
@@ -2598,8 +2633,13 @@ static void launch_grid(const LaunchSet& L, const void* F, void* X, const void* 
   GridArgs G{F,     X,          Xfwd,   L.gpart,  L.corner0, f32,    L.gen_tK, L.sys,
              L.grid_items, L.ttab, L.ttab_n, L.summ,   L.ghost, L.gscr};
   const dim3 gg((unsigned)L.n_grid);
-  if (!QUASI && !GEN && L.pairs)
-    hipLaunchKernelGGL((k_grid_pairs<kPairNT, kPairR>), gg, dim3(kPairNT), 0, st, G);
+  if (!QUASI && !GEN && L.chunks) {
+    const int64_t nw = L.n_grid * ((L.max_ntiles + 63) / 64);   // chunks of all right-hand sides
+    const dim3 cg((unsigned)((nw + kChunkNT / 64 - 1) / (kChunkNT / 64)));
+    hipLaunchKernelGGL(k_grid_chunk_reduce, cg, dim3(kChunkNT), 0, st, G, (int64_t)L.n_grid);
+    hipLaunchKernelGGL(k_grid_chunk_apply, cg, dim3(kChunkNT), 0, st, G, (int64_t)L.n_grid);
+  } else if (L.max_ntiles <= 64)   // one wavefront per system: no idle waves, no LDS level
+    hipLaunchKernelGGL((k_grid_affine<64, 1, QUASI, GEN>), gg, dim3(64), 0, st, G);
   else if (L.max_ntiles <= 256)
     hipLaunchKernelGGL((k_grid_affine<256, 1, QUASI, GEN>), gg, dim3(256), 0, st, G);
   else if (L.max_ntiles <= 2048)

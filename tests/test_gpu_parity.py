@@ -160,11 +160,13 @@ def test_repeatable_bitwise():
         assert np.array_equal(X1, X2), whole
 
 
-@pytest.mark.parametrize("tiles,extra", [(257, 0), (2048, 17), (2049, 3), (8193, 100)])
+@pytest.mark.parametrize("tiles,extra", [(64, 0), (64, 5), (65, 0), (257, 0), (2048, 17),
+                                         (2049, 3), (8193, 100)])
 @pytest.mark.parametrize("dtype", ["f64", "f32_refine"])
 def test_many_tiles(tiles, extra, dtype):
-    """Every variant of the interface pass across tiles: up to 256 tiles, up to
-    2048, up to 8192 (the single-system workload) and the general one beyond."""
+    """Every variant of the interface pass across tiles: up to 64 tiles (one
+    wavefront), up to 256, up to 2048, up to 8192 (the single-system
+    workload) and the general one beyond."""
     tdt = _tdt()
     n = (tiles - 1) * 8192 + (extra if extra else 8192)   # last tile partial if extra
     rng = np.random.default_rng(tiles)
