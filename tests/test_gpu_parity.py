@@ -177,3 +177,30 @@ def test_many_tiles(tiles, extra, dtype):
     X = to_host(plan.solve(to_dev(F)))
     ref = oracle.solve(F, a, b, c)
     assert oracle.rel_err(X, ref) <= tol_f64(a, b, c, n)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32_refine"])
+def test_chunked_interface_series(dtype):
+    """Series of 2049 to 16384 tiles take the interface pass in chunks of 64
+    tiles (chunk composites, then every chunk's tiles): several right-hand
+    sides (the chunks of all of them in one launch), a ragged last chunk and
+    tile, forward and adjoint against the oracle."""
+    tdt = _tdt()
+    n = 2100 * 8192 + 5          # 2101 tiles: 33 chunks, the last one of 53 tiles
+    M = 3
+    rng = np.random.default_rng(2101)
+    a, b, c = W.random_system(rng, 1.05, 2.0)
+    F = rng.standard_normal((M, n))
+    print(f"[case] chunked interface n={n} M={M} dtype={dtype}", flush=True)
+    plan = tdt.Plan(a, b, c, n, dtype)
+    Xd = plan.solve(to_dev(F))
+    ref = oracle.solve(F, a, b, c)
+    assert oracle.rel_err_rows(to_host(Xd), ref).max() <= tol_f64(a, b, c, n)
+    if dtype == "f64":
+        G = rng.standard_normal((M, n))
+        gF, gt = plan.backward(to_dev(G), Xd)
+        gFr, gtr = oracle.adjoint(G, ref, a, b, c)
+        assert oracle.rel_err_rows(to_host(gF), gFr).max() <= tol_f64(c, b, a, n)
+        gt = to_host(gt)
+        assert np.max(np.abs(gt - gtr)) <= 1e-11 * max(1.0, np.max(np.abs(gtr)))
+    plan.close()
