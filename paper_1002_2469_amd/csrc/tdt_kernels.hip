@@ -1313,22 +1313,10 @@ __global__ __launch_bounds__(SH::NT, REFINE ? kRefineWaves : SH::WAVES) void k_s
   __shared__ double tgh[kSysMaxTiles][2];
   __shared__ double tap[kSysMaxTiles], th[kSysMaxTiles], tbp[kSysMaxTiles], tiD[kSysMaxTiles];
   const int tid = threadIdx.x;
-  constexpr int lstride = lds_stride<SH, Tio>();
-  // The next tile of the system is loaded into registers while the current
-  // one is solved, unless the refinement solve needs those registers.
-  constexpr bool PF = !REFINE && !BWD;
-  Tio pv[kB];
-  auto issue = [&](int64_t base, int tl) {
-    const __amdgpu_buffer_rsrc_t src = make_rsrc(A.F + base, (int64_t)tl * sizeof(Tio));
-    const int vb = opaque(tid * (int)sizeof(Tio));
-#pragma unroll
-    for (int j = 0; j < kB; ++j) pv[j] = buf_load<Tio>(src, vb + j * kNT * (int)sizeof(Tio));
-  };
-  auto commit = [&]() {
-    Tio* lw = sh.lds + opaque(lds_base<SH, Tio>());
-#pragma unroll
-    for (int j = 0; j < kB; ++j) lw[j * lstride] = pv[j];
-  };
+  // Each tile is loaded when its turn comes: holding the next one in
+  // registers spilled the double kernel (120-148 B per lane) and made it
+  // slower than without (differentiable batch forward, 4 tiles per system:
+  // 54.6 -> 47.1 us).
   auto tile_len = [](const SysDesc& S, int t) {
     const int64_t t0 = (int64_t)t * kTile;
     return (int)(S.n - t0 < kTile ? S.n - t0 : kTile);
@@ -1349,12 +1337,10 @@ __global__ __launch_bounds__(SH::NT, REFINE ? kRefineWaves : SH::WAVES) void k_s
       const Consts<Ts> KS = make_consts<SH, Ts>(S, A.vec64, A.vec32);
       Ts sbp, siD;
       lane_table<SH, Ts>(S, A.tab64, A.tab32, sbp, siD);
-      auto sweep_summary = [&](int t, bool pf) {
+      auto sweep_summary = [&](int t) {
         const int tl = tile_len(S, t);
         __syncthreads();   // LDS free
-        if (!pf || t == 0) load_tile<SH>(sh, A.F, S.off + (int64_t)t * kTile, tl);
-        else commit();
-        if (pf && t + 1 < nt) issue(S.off + (int64_t)(t + 1) * kTile, tile_len(S, t + 1));
+        load_tile<SH>(sh, A.F, S.off + (int64_t)t * kTile, tl);
         __syncthreads();
         Ts q[kB];
         const Tio* myrow = sh.lds + tid * TileShared<SH, Tio, Tc>::RP;
@@ -1369,7 +1355,7 @@ __global__ __launch_bounds__(SH::NT, REFINE ? kRefineWaves : SH::WAVES) void k_s
         // supports; another shorter last tile is swept (and stays in LDS)
         const int nfull = (int)(S.n / kTile);
         const int nends = nfull < nt && S.glast ? nt : nfull;
-        if (nends < nt) sweep_summary(nt - 1, false);
+        if (nends < nt) sweep_summary(nt - 1);
         else last_in_lds = false;
         const int lane = tid & 63, w = tid >> 6;
         const double* gf = A.gpack + S.goff + lane;
@@ -1383,7 +1369,7 @@ __global__ __launch_bounds__(SH::NT, REFINE ? kRefineWaves : SH::WAVES) void k_s
           if (lane == 0) tsum[t][iw & 1] = sv;
         }
       } else {
-        for (int t = 0; t < nt; ++t) sweep_summary(t, PF);
+        for (int t = 0; t < nt; ++t) sweep_summary(t);
       }
       __syncthreads();
       if (tid == 0) {
@@ -1432,8 +1418,7 @@ __global__ __launch_bounds__(SH::NT, REFINE ? kRefineWaves : SH::WAVES) void k_s
       // the last tile summarised may still be in LDS
       if ((!QUASI && nt == 1) || t < nt - 1 || !last_in_lds) {
         __syncthreads();   // LDS free
-        if (PF && t < nt - 1) commit();
-        else load_tile<SH>(sh, A.F, S.off + t0, tl);
+        load_tile<SH>(sh, A.F, S.off + t0, tl);
         __syncthreads();
       }
       const bool fold = QUASI && tl < kTile;   // only the last tile can be short
@@ -1441,7 +1426,6 @@ __global__ __launch_bounds__(SH::NT, REFINE ? kRefineWaves : SH::WAVES) void k_s
         fold_right<SH>(sh, tl, S.c, XRt);
         __syncthreads();
       }
-      if (PF && t > 0) issue(S.off + t0 - kTile, kTile);
       solve_tile_lds<SH, Tio, Tc, REFINE, false>(sh, tl, XLt, fold ? 0.0 : XRt, S, K, bp, iD,
                                                  (double*)nullptr, (double*)nullptr, it_max,
                                                  est_max, A.max_iter, A.refine_tol);
