@@ -612,22 +612,21 @@ __device__ __forceinline__ TileGeom tile_geom(const int2* items, const SysDesc* 
   return G;
 }
 
-// Everything a workgroup needs from global memory for one tile, fetched one
-// tile ahead: the tile's rows (coalesced, element j*kNT + tid), this lane's
-// table entries, one block-vector entry per thread (tid < kVecN*kB), and the
-// values just outside the tile.  Every load is unconditional (rows past the
-// tile read as 0 through the buffer range check) so that all of them are in
-// flight together and nothing waits for them before the next tile starts.
+// Everything a workgroup needs from global memory for one tile, issued
+// together at the top of its iteration: the tile's rows (coalesced, element
+// j*kNT + tid), this lane's table entries and the values just outside the
+// tile.  Every load is unconditional (rows past the tile read as 0 through
+// the buffer range check) so that all of them are in flight together.
 template <class SH, typename Tio, typename Tc>
-struct Prefetch {
+struct TileLoad {
   Tio v[SH::B];
   Tc bp, iD;
   double XL, XR;
 };
 
 template <class SH, typename Tio, typename Tc, bool SUMMARY, bool QUASI>
-__device__ __forceinline__ void prefetch(const TileArgs<Tio>& A, int64_t item,
-                                         Prefetch<SH, Tio, Tc>& P) {
+__device__ __forceinline__ void load_tile_item(const TileArgs<Tio>& A, int64_t item,
+                                               TileLoad<SH, Tio, Tc>& P) {
   TDT_SHAPE(SH)
   const int tid = threadIdx.x;
   const TileGeom G = tile_geom<SH>(A.items, A.sys, item, A.last_only);
@@ -1186,15 +1185,13 @@ __global__ __launch_bounds__(SH::NT, REFINE ? kRefineWaves : SH::WAVES) void k_t
   const int lbase = lds_base<SH, Tio>();
   constexpr int lstride = lds_stride<SH, Tio>();
   auto item_of = [&](int64_t k) { return A.reverse ? A.nitems - 1 - k : k; };
-  constexpr bool PF = false;   // one tile per workgroup: nothing to fetch ahead
   int it_max = 0;        // refinement record of this workgroup
   float est_max = 0.0f;
   int64_t k = blockIdx.x;
-  Prefetch<SH, Tio, Tc> P;
-  if (PF && k < A.nitems) prefetch<SH, Tio, Tc, SUMMARY, QUASI>(A, item_of(k), P);
+  TileLoad<SH, Tio, Tc> P;
 
   while (k < A.nitems) {
-    if (!PF) prefetch<SH, Tio, Tc, SUMMARY, QUASI>(A, item_of(k), P);
+    load_tile_item<SH, Tio, Tc, SUMMARY, QUASI>(A, item_of(k), P);
     const int64_t item = item_of(k);
     const TileGeom G = tile_geom<SH>(A.items, A.sys, item, A.last_only);
     const SysDesc S = load_sys(A.sys, G.I.s);
@@ -1211,7 +1208,6 @@ __global__ __launch_bounds__(SH::NT, REFINE ? kRefineWaves : SH::WAVES) void k_t
       for (int j = 0; j < kB; ++j) lw[j * lstride] = P.v[j];
     }
     const int64_t kn = k + gridDim.x;
-    if (PF && kn < A.nitems) prefetch<SH, Tio, Tc, SUMMARY, QUASI>(A, item_of(kn), P);
     __syncthreads();
     const bool fold = QUASI && !SUMMARY && tl < kTile;
     if (fold) {
