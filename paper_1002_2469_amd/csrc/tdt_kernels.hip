@@ -2625,9 +2625,12 @@ static void launch_grid(const LaunchSet& L, const void* F, void* X, const void* 
     hipLaunchKernelGGL((k_grid_affine<256, 1, QUASI, GEN>), gg, dim3(256), 0, st, G);
   else if (L.max_ntiles <= 2048)
     hipLaunchKernelGGL((k_grid_affine<256, 8, QUASI, GEN>), gg, dim3(256), 0, st, G);
-  else if (L.max_ntiles <= 8192)
-    hipLaunchKernelGGL((k_grid_affine<512, 16, QUASI, GEN>), gg, dim3(512), 0, st, G);
-  else if (L.max_ntiles <= 16384)
+  else if (!GEN && L.max_ntiles <= 8192) {
+    // (a general matrix's end values per tile, 16 tiles per thread, would
+    // not fit 512 threads' registers: it takes the lean kernel from here on)
+    if constexpr (!GEN)
+      hipLaunchKernelGGL((k_grid_affine<512, 16, QUASI, false>), gg, dim3(512), 0, st, G);
+  } else if (L.max_ntiles <= 16384)
     hipLaunchKernelGGL((k_grid_affine_lean<1024, 16, QUASI, GEN>), gg, dim3(1024), 0, st, G);
   else
     hipLaunchKernelGGL((k_grid<QUASI, GEN>), gg, dim3(kGridNT), 0, st, G);
