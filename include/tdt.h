@@ -33,10 +33,12 @@ typedef struct tdt_plan_s *tdt_plan_t;
  * TDT_F32_REFINE, float for TDT_F32.
  *   TDT_F64        every step in double;
  *   TDT_F32        every step in float (accuracy ~ cond(T) * 2^-24);
- *   TDT_F32_REFINE sweeps, interface pass and correction in float; the
- *                  residual r = F - T X and the update X += d in double,
- *                  repeated until the update stops shrinking (iterative
- *                  refinement), so the result matches the double solve. */
+ *   TDT_F32_REFINE each tile's sweeps, its in-tile interface and the
+ *                  correction in float; the tile summaries, the interface
+ *                  pass across tiles, the residual r = F - T X and the
+ *                  update X += d in double, repeated until the update stops
+ *                  shrinking (iterative refinement), so the result matches
+ *                  the double solve. */
 typedef enum { TDT_F64 = 0, TDT_F32 = 1, TDT_F32_REFINE = 2 } tdt_dtype_t;
 
 typedef enum {
@@ -119,7 +121,9 @@ tdt_status_t tdt_plan_varlen_quasi_create(int64_t S, const int64_t *h_offsets,
  * plan computes, in long double, the LU of every B-row block, every block's
  * responses to unit outside values and the end values of every tile, for A
  * and for A^T; the device holds 3 values per row and 5 per block in the
- * compute precision, plus 4 per tile.  dtype: TDT_F64 or TDT_F32
+ * compute precision, plus 4 per tile and, for the first pass, the tiles'
+ * first and last inverse rows in double (only the entries under their
+ * supports when the plan finds them short: tdt_plan_green_support).  dtype: TDT_F64 or TDT_F32
  * (TDT_F32_REFINE -> TDT_ERR_INVALID_ARG).  Solve with tdt_solve (F, X:
  * [M][N]).  tdt_solve_backward solves A^T gF = gX and, if d_gt is not NULL,
  * writes 3*N doubles: d_gt[i] = dL/da_i, d_gt[N+i] = dL/db_i, d_gt[2N+i] =
