@@ -78,8 +78,8 @@ def test_shape_varlen(shape, dtype, whole):
 
 @pytest.mark.parametrize("shape", [1, 2])
 def test_shape_single_large(shape):
-    """N = 2^26 with tiles of 4096 rows: 16384 tiles, the largest affine
-    interface-pass variant."""
+    """N = 2^26 with tiles of 4096 rows: 16384 tiles, the largest the
+    chunked interface pass of a series plan takes (256 chunks of 64 tiles)."""
     tdt = _tdt()
     d = W.single_large(0)
     print(f"[case] shape={shape} single_large", flush=True)
