@@ -2486,6 +2486,31 @@ __device__ __forceinline__ void chunk_tile(const GridArgs& A, const SysDesc& S, 
   cf = real ? K[2] : 1.0;
 }
 
+// The tiles of chunk c (64 tiles, one per lane) given the alpha entering the
+// chunk and the u right of it: the scans of eq. (15) over the chunk, and
+// every tile's values just outside it.
+__device__ __forceinline__ void chunk_tiles_apply(const GridArgs& A, const SysDesc& S,
+                                                  int64_t slot0, int c, double alpha_in,
+                                                  double u_right, int lane) {
+  const int t = c * 64 + lane;
+  double yf, yl, bp, iD, pf, pl, cf;
+  chunk_tile(A, S, slot0, t, yf, yl, bp, iD, pf, pl, cf);
+  double Ai = pl * iD, gi = yl + pl * iD * bp * yf;
+  wave_scan_affine_fwd(Ai, gi);
+  const double ainc = Ai * alpha_in + gi;                    // alpha_t
+  double am = __shfl_up(ainc, 1, 64);                        // alpha_{t-1}
+  if (lane == 0) am = alpha_in;
+  double Ct = cf * iD, ht = (yf + pf * am) * iD;
+  wave_scan_affine_bwd(Ct, ht);
+  const double ut = Ct * u_right + ht;                       // u_t
+  double un = __shfl_down(ut, 1, 64);                        // u_{t+1}
+  if (lane == 63) un = u_right;
+  if (t < S.ntiles) {
+    A.ghost[2 * (slot0 + t)] = am + bp * ut;
+    A.ghost[2 * (slot0 + t) + 1] = un;
+  }
+}
+
 __global__ __launch_bounds__(kChunkNT) void k_grid_chunk_reduce(GridArgs A, int64_t M) {
   const int lane = threadIdx.x & 63;
   const int64_t gw = (int64_t)blockIdx.x * (kChunkNT / 64) +
@@ -2585,24 +2610,55 @@ __global__ __launch_bounds__(kChunkNT) void k_grid_chunk_apply(GridArgs A, int64
   const double alpha_in = __shfl(ai, c / kChunkRC, 64);
   const double u_right = __shfl(uo, c / kChunkRC, 64);
   // 2. the chunk's tiles
-  const int64_t slot0 = m * S.tslots;
-  const int t = c * 64 + lane;
-  double yf, yl, bp, iD, pf, pl, cf;
-  chunk_tile(A, S, slot0, t, yf, yl, bp, iD, pf, pl, cf);
-  double Ai = pl * iD, gi = yl + pl * iD * bp * yf;
-  wave_scan_affine_fwd(Ai, gi);
-  const double ainc = Ai * alpha_in + gi;                    // alpha_t
-  double am = __shfl_up(ainc, 1, 64);                        // alpha_{t-1}
-  if (lane == 0) am = alpha_in;
-  double Ct = cf * iD, ht = (yf + pf * am) * iD;
-  wave_scan_affine_bwd(Ct, ht);
-  const double ut = Ct * u_right + ht;                       // u_t
-  double un = __shfl_down(ut, 1, 64);                        // u_{t+1}
-  if (lane == 63) un = u_right;
-  if (t < S.ntiles) {
-    A.ghost[2 * (slot0 + t)] = am + bp * ut;
-    A.ghost[2 * (slot0 + t) + 1] = un;
+  chunk_tiles_apply(A, S, m * S.tslots, c, alpha_in, u_right, lane);
+}
+
+// The first pass from the supports of a series plan of at most 64 whole
+// tiles per right-hand side, with its interface pass: every wavefront,
+// having written its summary, counts itself in on its right-hand side's
+// counter; the one that completes the count runs the interface pass of
+// that right-hand side (one wavefront: the tiles of one chunk) and clears
+// the counter for the next solve.  No wavefront waits for another, and the
+// launch the interface pass took is saved.  Each count costs an L2
+// write-back, so the launch takes this path for a few wavefronts only
+// (kItfFuseWaves).
+template <class SH, typename Tio>
+__global__ __launch_bounds__(kEndsNT) void k_beta_ends_itf(BetaEndsArgs<Tio> A, GridArgs G,
+                                                           int* __restrict__ cnt) {
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int64_t nw = A.split ? 2 * A.nitems : A.nitems;
+  const int expect = (A.split ? 2 : 1) * A.nfull;   // wavefronts per right-hand side
+  for (int64_t iw = (int64_t)blockIdx.x * kEndsNW + w; iw < nw;
+       iw += (int64_t)gridDim.x * kEndsNW) {
+    beta_ends_item<SH, Tio>(A, iw, lane);
+    const int64_t m = (A.split ? iw >> 1 : iw) / A.nfull;
+    // release: this wavefront's summary reaches the device before it counts
+    // (an L2 write-back, no invalidation); acquire, in the wavefront that
+    // completes the count: every summary of the right-hand side is seen
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    int old = 0;
+    if (lane == 0) old = atomicAdd(cnt + m, 1);
+    old = __shfl(old, 0, 64);
+    if (old == expect - 1) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      const SysDesc S = load_sys(G.sys, 0);
+      chunk_tiles_apply(G, S, m * S.tslots, 0, 0.0, 0.0, lane);
+      if (lane == 0) cnt[m] = 0;
+    }
   }
+}
+
+template <class SH, typename Tio>
+static void launch_beta_ends_itf(const LaunchSet& L, const Tio* F, const GridArgs& G,
+                                 hipStream_t st) {
+  const int64_t n = L.n_beta;
+  const int split = L.green_kf + L.green_kl > kEndsSplitRows ? 1 : 0;
+  BetaEndsArgs<Tio> B{F,      L.sys,  L.green, n,      split, L.nfull,
+                      L.green_kf, L.green_kl, L.summ, 0,     nullptr, nullptr};
+  const int64_t nw = split ? 2 * n : n;
+  hipLaunchKernelGGL((k_beta_ends_itf<SH, Tio>), dim3((unsigned)((nw + kEndsNW - 1) / kEndsNW)),
+                     dim3(kEndsNT), 0, st, B, G, L.itf_cnt);
 }
 
 // Interface pass across tiles: the affine variant sized for the most tiled
@@ -2659,13 +2715,25 @@ static hipError_t run_solve(const LaunchSet& L, const void* F, void* X, const vo
   // double sweep costs less than a float solve plus refinement, and the
   // values outside each tile then come out exact in double).
   using Ts = typename std::conditional<REFINE, double, Tc>::type;
+  // a series of at most 64 whole tiles per right-hand side, short supports
+  // and few first-pass wavefronts: the last of them per right-hand side runs
+  // its interface pass
+  const int64_t itf_waves = L.n_beta * (L.green_kf + L.green_kl > kEndsSplitRows ? 2 : 1);
+  const bool fused = !QUASI && L.green && L.itf_cnt && L.green_kf > 0 && L.n_last == 0 &&
+                     L.n_beta > 0 && L.max_ntiles <= 64 &&
+                     itf_waves <= kItfFuseWaves;
   if (L.n_grid > 0) {
     if (L.green) {
       if (L.n_beta > 0) {
-        if (L.green_kf > 0)
+        if (fused) {
+          GridArgs G{F,       X,        Xfwd,    L.gpart, L.corner0, 0,       L.gen_tK,
+                     L.sys,   nullptr,  L.ttab,  L.ttab_n, L.summ,   L.ghost, L.gscr};
+          launch_beta_ends_itf<SH, Tio>(L, static_cast<const Tio*>(F), G, st);
+        } else if (L.green_kf > 0) {
           launch_beta_ends<SH, Tio>(L, static_cast<const Tio*>(F), st);
-        else
+        } else {
           launch_beta<SH, Tio>(L, static_cast<const Tio*>(F), st);
+        }
       }
       if (L.n_last > 0) {
         A.items = nullptr;
@@ -2689,7 +2757,7 @@ static hipError_t run_solve(const LaunchSet& L, const void* F, void* X, const vo
       }
     }
     if (L.ev) (void)hipEventRecord(L.ev[1], st);
-    launch_grid<QUASI>(L, F, X, Xfwd, sizeof(Tio) == 4 ? 1 : 0, st);
+    if (!fused) launch_grid<QUASI>(L, F, X, Xfwd, sizeof(Tio) == 4 ? 1 : 0, st);
     if (L.ev) (void)hipEventRecord(L.ev[2], st);
   } else if (L.ev) {
     (void)hipEventRecord(L.ev[1], st);
@@ -2908,6 +2976,7 @@ extern "C" tdt_status_t tdt_solve_noalloc(tdt_plan_t plan, const void* F, void* 
   L.summ = base;
   L.ghost = base + 2 * kScratchSlots;
   L.gscr = base + 4 * kScratchSlots;
+  L.itf_cnt = nullptr;   // nothing of the array may be assumed zero: interface pass alone
   L.gpart = base + 7 * kScratchSlots;
   L.ev = nullptr;
   return tdt::launch_solve(dtype, false, L, F, X, nullptr, stream) == hipSuccess ? TDT_OK

@@ -179,6 +179,39 @@ def test_many_tiles(tiles, extra, dtype):
     assert oracle.rel_err(X, ref) <= tol_f64(a, b, c, n)
 
 
+@pytest.mark.parametrize("tiles,M,dom,sym", [(2, 1, 2.0, False), (64, 2, 2.0, False),
+                                             (64, 3, 2.0, False), (17, 2, 1.02, True)])
+@pytest.mark.parametrize("dtype", ["f64", "f32_refine"])
+def test_first_pass_with_interface(tiles, M, dom, sym, dtype):
+    """A series of at most 64 whole tiles per right-hand side whose first
+    pass has at most 128 wavefronts runs the interface pass in the last of
+    them per right-hand side (a counter per right-hand side, cleared by that
+    wavefront); 64 tiles times 3 right-hand sides is beyond that and takes
+    the interface launch.  Two solves in a row with other data, the adjoint
+    after them, and a weakly dominant matrix whose supports are long enough
+    to split every tile end into its own wavefront."""
+    tdt = _tdt()
+    n = tiles * 8192
+    rng = np.random.default_rng(tiles * 10 + M)
+    a, b, c = W.random_system(rng, dom, dom, symmetric=sym)
+    print(f"[case] first pass with interface n={n} M={M} dtype={dtype}", flush=True)
+    plan = tdt.Plan(a, b, c, n, dtype)
+    plan.set_option("shape", 0)
+    assert plan.green_support()["forward"][0] > 0
+    for rep in range(2):
+        F = rng.standard_normal((M, n))
+        Xd = plan.solve(to_dev(F))
+        ref = oracle.solve(F, a, b, c)
+        assert oracle.rel_err_rows(to_host(Xd), ref).max() <= tol_f64(a, b, c, n), rep
+    G = rng.standard_normal((M, n))
+    gF, gt = plan.backward(to_dev(G), Xd)
+    gFr, gtr = oracle.adjoint(G, ref, a, b, c)
+    assert oracle.rel_err_rows(to_host(gF), gFr).max() <= tol_f64(c, b, a, n)
+    gt = to_host(gt)
+    assert np.max(np.abs(gt - gtr)) <= 1e-10 * max(1.0, np.max(np.abs(gtr)))
+    plan.close()
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32_refine"])
 def test_chunked_interface_series(dtype):
     """Series of 2049 to 16384 tiles take the interface pass in chunks of 64
