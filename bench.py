@@ -558,7 +558,18 @@ def main() -> int:
                   "forward_transform": 16.0 * U if d["kind"] in ("poisson", "poisson3d") else 0.0,
                   "inverse_transform": 16.0 * U if d["kind"] in ("poisson", "poisson3d") else 0.0,
                   "adi": adi_bytes(d, res[head]["counts"]) if d["kind"] == "poisson3d" else 0.0}
-    names = {"first_pass": (f"k_beta_ends<double> (tile summaries from the Green rows' "
+    # a series of at most 64 whole tiles per right-hand side whose first pass
+    # has at most 128 wavefronts runs the interface pass in that launch
+    fused = False
+    if d["kind"] == "series" and kf + kl > 0:
+        tile = _lib.SHAPES[shape][0] * _lib.SHAPES[shape][1]
+        tiles = d["N"] // tile
+        fused = (d["N"] % tile == 0 and 2 <= tiles <= 64
+                 and d["M"] * tiles * (2 if kf + kl > 256 else 1) <= 128)
+    names = {"first_pass": (f"k_beta_ends_itf<double> (tile summaries from the Green rows' "
+                            f"supports, {kf} + {kl} rows per tile, then the interface pass in "
+                            f"the last wavefront)" if fused else
+                            f"k_beta_ends<double> (tile summaries from the Green rows' "
                             f"supports, {kf} + {kl} rows per tile)" if kf + kl > 0 else
                             "k_beta<double> (Green-row tile summaries, first pass)"
                             if d["kind"] == "series" else
