@@ -2115,19 +2115,25 @@ tdt_status_t tdt_plan_autotune(tdt_plan_t p, const void* F, void* X, int64_t M,
     if (st < 0) break;
     st = solve();   // warm-up (also grows the workspace outside the timing)
     if (st < 0) break;
-    // the median of five timed solves (single solves of a few hundred us
-    // vary by several per cent)
+    // the median of five timed samples (single solves of a few hundred us
+    // vary by several per cent); a sample is one solve, or back-to-back
+    // solves filling about 0.2 ms where one solve is shorter (a solve of
+    // 10-20 us timed alone is mostly the events' own overhead and jitter)
     constexpr int kReps = 5;
     float t[kReps] = {};
-    for (int r = 0; r < kReps && st >= 0; ++r) {
+    int per = 1;
+    for (int r = -1; r < kReps && st >= 0; ++r) {   // r = -1: sizes the samples
       float ms = 0.0f;
       (void)hipEventRecord(e0, stream);
-      st = solve();
+      for (int k = 0; k < per && st >= 0; ++k) st = solve();
       (void)hipEventRecord(e1, stream);
       if (hipEventSynchronize(e1) != hipSuccess ||
           hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
         st = TDT_ERR_HIP;
-      t[r] = ms;
+      if (r < 0)
+        per = ms > 0.0f ? std::min(64, std::max(1, (int)std::ceil(0.2f / ms))) : 64;
+      else
+        t[r] = ms / (float)per;
     }
     std::sort(t, t + kReps);
     cands[i].ms = t[kReps / 2];
