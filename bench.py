@@ -558,18 +558,16 @@ def main() -> int:
                   "forward_transform": 16.0 * U if d["kind"] in ("poisson", "poisson3d") else 0.0,
                   "inverse_transform": 16.0 * U if d["kind"] in ("poisson", "poisson3d") else 0.0,
                   "adi": adi_bytes(d, res[head]["counts"]) if d["kind"] == "poisson3d" else 0.0}
-    # a series of at most 64 whole tiles per right-hand side whose first pass
-    # has at most 128 wavefronts runs the interface pass in that launch
-    fused = False
-    if d["kind"] == "series" and kf + kl > 0:
+    # plans whose multi-tile systems have at most 64 tiles and no corner rows
+    # run the interface pass inside the final pass (no launch of its own)
+    inline_itf = False
+    if d["kind"] in ("series", "varlen") and "psi" not in d:
         tile = _lib.SHAPES[shape][0] * _lib.SHAPES[shape][1]
-        tiles = d["N"] // tile
-        fused = (d["N"] % tile == 0 and 2 <= tiles <= 64
-                 and d["M"] * tiles * (2 if kf + kl > 256 else 1) <= 128)
-    names = {"first_pass": (f"k_beta_ends_itf<double> (tile summaries from the Green rows' "
-                            f"supports, {kf} + {kl} rows per tile, then the interface pass in "
-                            f"the last wavefront)" if fused else
-                            f"k_beta_ends<double> (tile summaries from the Green rows' "
+        o = [int(x) for x in d["offsets"]] if d["kind"] == "varlen" else []
+        nmax = d["N"] if d["kind"] == "series" else max(b - a for a, b in zip(o, o[1:]))
+        inline_itf = tile < nmax <= 64 * tile
+    itf = ", interface pass inline" if inline_itf else ""
+    names = {"first_pass": (f"k_beta_ends<double> (tile summaries from the Green rows' "
                             f"supports, {kf} + {kl} rows per tile)" if kf + kl > 0 else
                             "k_beta<double> (Green-row tile summaries, first pass)"
                             if d["kind"] == "series" else
@@ -578,8 +576,9 @@ def main() -> int:
                             "k_tile<double, *, SUMMARY> (tile summaries, first pass)"),
              "final_pass": ("k_gtile<double, final> (general matrix: solve and store)"
                             if d["kind"] == "general" else
-                            "k_tile<double, float, REFINE, final> (solve, refine and store)"
-                            if head == "f32_refine" else "k_tile<double, double, final> (solve and store)"),
+                            f"k_tile<double, float, REFINE, final> (solve, refine and store{itf})"
+                            if head == "f32_refine" else
+                            f"k_tile<double, double, final> (solve and store{itf})"),
              "forward_transform": "k_dst_rows<N2> (the sine transform of every row: fold, "
                                   "complex FFT in LDS, real split, prefix sum)",
              "inverse_transform": "k_dst_rows<N2> (the inverse sine transform of every row)",
@@ -588,7 +587,7 @@ def main() -> int:
              "adi": "k_strided<double> with the ADI epilogue (all 2 J_1 half-steps of one "
                     "solve: bytes and time summed over them)",
              "bwd_first_pass": "k_tile<double, *, SUMMARY> on T^T (adjoint first pass)",
-             "bwd_final_pass": "k_tile<..., BWD> (adjoint solve, store gF, dL/dt partial sums)"}
+             "bwd_final_pass": f"k_tile<..., BWD> (adjoint solve, store gF, dL/dt partial sums{itf})"}
 
     cpu = None
     errs = {}

@@ -103,7 +103,6 @@ struct tdt_plan_s {
   double* summ = nullptr;
   double* ghost = nullptr;
   double* gscr = nullptr;
-  int* icnt = nullptr;   // per right-hand side: first-pass wavefronts done (zero between solves)
   double* gpart = nullptr;
   int* iters = nullptr;
   double dominance = 0.0, kappa = 0.0;
@@ -592,9 +591,7 @@ void free_workspace(tdt_plan_s* p) {
   (void)hipFree(p->ghost);
   (void)hipFree(p->gscr);
   (void)hipFree(p->gpart);
-  (void)hipFree(p->icnt);
   p->summ = p->ghost = p->gscr = p->gpart = nullptr;
-  p->icnt = nullptr;
   p->ws_slots = p->ws_fslots = 0;
 }
 
@@ -615,13 +612,11 @@ tdt_status_t ensure_workspace(tdt_plan_s* p, int64_t slots, int64_t fslots, hipS
   if (hipMalloc(&p->summ, (size_t)ns * 2 * sizeof(double)) != hipSuccess ||
       hipMalloc(&p->ghost, (size_t)ns * 2 * sizeof(double)) != hipSuccess ||
       hipMalloc(&p->gscr, (size_t)ns * 3 * sizeof(double)) != hipSuccess ||
-      hipMalloc(&p->gpart, (size_t)nf * tdt::kGradN * sizeof(double)) != hipSuccess ||
-      hipMalloc(&p->icnt, (size_t)ns * sizeof(int)) != hipSuccess) {
+      hipMalloc(&p->gpart, (size_t)nf * tdt::kGradN * sizeof(double)) != hipSuccess) {
     free_workspace(p);
     return TDT_ERR_OOM;
   }
-  if (hipMemset(p->ghost, 0, (size_t)ns * 2 * sizeof(double)) != hipSuccess ||
-      hipMemset(p->icnt, 0, (size_t)ns * sizeof(int)) != hipSuccess) {
+  if (hipMemset(p->ghost, 0, (size_t)ns * 2 * sizeof(double)) != hipSuccess) {
     free_workspace(p);
     return TDT_ERR_HIP;
   }
@@ -1369,7 +1364,6 @@ tdt_status_t run(tdt_plan_s* p, int dir, const void* F, void* X, const void* Xfw
   L.summ = p->summ;
   L.ghost = p->ghost;
   L.gscr = p->gscr;
-  L.itf_cnt = p->icnt;
   L.gpart = p->gpart;
   L.ev = nullptr;
   if (p->profile) {

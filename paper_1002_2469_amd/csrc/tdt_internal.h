@@ -82,10 +82,6 @@ struct SysDesc {
 // of the tile index from kEndsPartShift up: 0 both ends, 1 head, 2 tail.
 constexpr int kEndsSplitRows = 256;
 constexpr int kEndsPartShift = 24;
-// First passes of at most this many wavefronts run a series' interface pass
-// in their last wavefront per right-hand side (each wavefront's count costs
-// an L2 write-back: 4096 of them added about 38 us, one launch is about 3 us).
-constexpr int kItfFuseWaves = 128;
 
 // Slot of tile t of a system: a varlen plan adds the system's slot0; a
 // series plan uses tslots slots per right-hand side m.
@@ -146,8 +142,6 @@ struct LaunchSet {
   double* summ;
   double* ghost;
   double* gscr;
-  int* itf_cnt;            // series: per right-hand side, first-pass wavefronts done
-                           // (zero between solves; null: the interface pass runs alone)
   double* gpart;
   int64_t corner0;        // series, quasi-Toeplitz: first corner t-gradient slot
   int quasi;              // the plan's systems are quasi-Toeplitz

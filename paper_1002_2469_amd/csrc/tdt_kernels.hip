@@ -538,6 +538,12 @@ struct TileArgs {
   const int2* __restrict__ ends_items;
   int64_t n_ends;
   const double* __restrict__ gpack;
+  // final pass of a plan whose multi-tile systems have at most 64 tiles and
+  // no corner rows: each wavefront runs its system's interface pass itself
+  // (lane t takes tile t) instead of reading the ghosts of a separate launch
+  int itf_inline;
+  const double* __restrict__ ttab;    // as the interface pass's table ([2][ttab_n])
+  int64_t ttab_n;
 };
 
 // Copy of a system descriptor read with scalar loads (wave-uniform index).
@@ -624,6 +630,32 @@ struct TileLoad {
   double XL, XR;
 };
 
+// The values just outside tile t of a system of at most 64 tiles without
+// corner rows, by the system's interface pass (the scans of eq. (15), one
+// tile per lane, zero outside the system) from the tile summaries and table
+// entries this lane loaded for tile `lane`.
+__device__ __forceinline__ void inline_ghosts(const SysDesc& S, int t, double u, double v,
+                                              double b0, double i0, double& XL, double& XR) {
+  const int lane = threadIdx.x & 63;
+  const int P = S.ntiles;
+  const bool real = lane < P, last = lane == P - 1;
+  const double yf = real ? u : 0.0, yl = real ? v : 0.0;
+  const double bp = real ? b0 : 0.0, iD = real ? i0 : 1.0;
+  const double pf = real ? (last ? S.ltileK[0] : S.tileK[0]) : 0.0;
+  const double pl = real ? (last ? S.ltileK[1] : S.tileK[1]) : 1.0;
+  const double cf = real ? (last ? S.ltileK[2] : S.tileK[2]) : 1.0;
+  double Ai = pl * iD, gi = yl + pl * iD * bp * yf;
+  wave_scan_affine_fwd(Ai, gi);                   // gi = alpha_lane
+  double am = __shfl_up(gi, 1, 64);               // alpha_{lane-1}
+  if (lane == 0) am = 0.0;
+  double Ct = cf * iD, ht = (yf + pf * am) * iD;
+  wave_scan_affine_bwd(Ct, ht);                   // ht = u_lane
+  double un = __shfl_down(ht, 1, 64);             // u_{lane+1}
+  if (lane == 63) un = 0.0;
+  XL = __shfl(am + bp * ht, t, 64);
+  XR = __shfl(un, t, 64);
+}
+
 template <class SH, typename Tio, typename Tc, bool SUMMARY, bool QUASI>
 __device__ __forceinline__ void load_tile_item(const TileArgs<Tio>& A, int64_t item,
                                                TileLoad<SH, Tio, Tc>& P) {
@@ -631,6 +663,21 @@ __device__ __forceinline__ void load_tile_item(const TileArgs<Tio>& A, int64_t i
   const int tid = threadIdx.x;
   const TileGeom G = tile_geom<SH>(A.items, A.sys, item, A.last_only);
   const SysDesc S = load_sys(A.sys, G.I.s);
+  // the inline interface pass: its loads first, so that its scans can run
+  // while the tile's rows are still on their way
+  const bool inl = !SUMMARY && !QUASI && A.itf_inline && S.ntiles > 1;
+  double iu = 0.0, iv = 0.0, ib = 0.0, ii = 1.0;
+  if (inl) {
+    const int lane = tid & 63;
+    const int tc = lane < S.ntiles ? lane : 0;
+    const bool varlen = A.items != nullptr;
+    const int64_t sl = tile_slot(S, G.I.m, tc, varlen);
+    const int64_t tb = varlen ? sl : tile_slot(S, 0, tc, false);
+    iu = A.summ[2 * sl];
+    iv = A.summ[2 * sl + 1];
+    ib = A.ttab[tb];
+    ii = A.ttab[A.ttab_n + tb];
+  }
   const __amdgpu_buffer_rsrc_t src = make_rsrc(A.F + G.base, (int64_t)G.tl * sizeof(Tio));
   const int vb = opaque(tid * (int)sizeof(Tio));
 #pragma unroll
@@ -645,7 +692,9 @@ __device__ __forceinline__ void load_tile_item(const TileArgs<Tio>& A, int64_t i
     P.bp = tb[kTabBeta * kNT + ti];
     P.iD = tb[kTabInvD * kNT + ti];
   }
-  if (!SUMMARY) {
+  if (inl) {
+    inline_ghosts(S, G.I.t, iu, iv, ib, ii, P.XL, P.XR);
+  } else if (!SUMMARY) {
     // a one-tile system has no interface pass (zero outside values) unless
     // it has corner rows
     const bool has_ghosts = S.ntiles > 1 || QUASI;
@@ -2613,54 +2662,6 @@ __global__ __launch_bounds__(kChunkNT) void k_grid_chunk_apply(GridArgs A, int64
   chunk_tiles_apply(A, S, m * S.tslots, c, alpha_in, u_right, lane);
 }
 
-// The first pass from the supports of a series plan of at most 64 whole
-// tiles per right-hand side, with its interface pass: every wavefront,
-// having written its summary, counts itself in on its right-hand side's
-// counter; the one that completes the count runs the interface pass of
-// that right-hand side (one wavefront: the tiles of one chunk) and clears
-// the counter for the next solve.  No wavefront waits for another, and the
-// launch the interface pass took is saved.  Each count costs an L2
-// write-back, so the launch takes this path for a few wavefronts only
-// (kItfFuseWaves).
-template <class SH, typename Tio>
-__global__ __launch_bounds__(kEndsNT) void k_beta_ends_itf(BetaEndsArgs<Tio> A, GridArgs G,
-                                                           int* __restrict__ cnt) {
-  const int lane = threadIdx.x & 63;
-  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int64_t nw = A.split ? 2 * A.nitems : A.nitems;
-  const int expect = (A.split ? 2 : 1) * A.nfull;   // wavefronts per right-hand side
-  for (int64_t iw = (int64_t)blockIdx.x * kEndsNW + w; iw < nw;
-       iw += (int64_t)gridDim.x * kEndsNW) {
-    beta_ends_item<SH, Tio>(A, iw, lane);
-    const int64_t m = (A.split ? iw >> 1 : iw) / A.nfull;
-    // release: this wavefront's summary reaches the device before it counts
-    // (an L2 write-back, no invalidation); acquire, in the wavefront that
-    // completes the count: every summary of the right-hand side is seen
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    int old = 0;
-    if (lane == 0) old = atomicAdd(cnt + m, 1);
-    old = __shfl(old, 0, 64);
-    if (old == expect - 1) {
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      const SysDesc S = load_sys(G.sys, 0);
-      chunk_tiles_apply(G, S, m * S.tslots, 0, 0.0, 0.0, lane);
-      if (lane == 0) cnt[m] = 0;
-    }
-  }
-}
-
-template <class SH, typename Tio>
-static void launch_beta_ends_itf(const LaunchSet& L, const Tio* F, const GridArgs& G,
-                                 hipStream_t st) {
-  const int64_t n = L.n_beta;
-  const int split = L.green_kf + L.green_kl > kEndsSplitRows ? 1 : 0;
-  BetaEndsArgs<Tio> B{F,      L.sys,  L.green, n,      split, L.nfull,
-                      L.green_kf, L.green_kl, L.summ, 0,     nullptr, nullptr};
-  const int64_t nw = split ? 2 * n : n;
-  hipLaunchKernelGGL((k_beta_ends_itf<SH, Tio>), dim3((unsigned)((nw + kEndsNW - 1) / kEndsNW)),
-                     dim3(kEndsNT), 0, st, B, G, L.itf_cnt);
-}
-
 // Interface pass across tiles: the affine variant sized for the most tiled
 // system (up to 16384 tiles), beyond that the segment-merge kernel.  The
 // plan lays out its workspace slots for the same choice (interface_run).
@@ -2710,30 +2711,23 @@ static hipError_t run_solve(const LaunchSet& L, const void* F, void* X, const vo
   A.iters = L.iters;
   A.max_iter = L.max_iter;
   A.refine_tol = L.refine_tol;
+  A.ttab = L.ttab;
+  A.ttab_n = L.ttab_n;
   if (L.ev) (void)hipEventRecord(L.ev[0], st);
   // Tile summaries of the refinement path are computed in double (one
   // double sweep costs less than a float solve plus refinement, and the
   // values outside each tile then come out exact in double).
   using Ts = typename std::conditional<REFINE, double, Tc>::type;
-  // a series of at most 64 whole tiles per right-hand side, short supports
-  // and few first-pass wavefronts: the last of them per right-hand side runs
-  // its interface pass
-  const int64_t itf_waves = L.n_beta * (L.green_kf + L.green_kl > kEndsSplitRows ? 2 : 1);
-  const bool fused = !QUASI && L.green && L.itf_cnt && L.green_kf > 0 && L.n_last == 0 &&
-                     L.n_beta > 0 && L.max_ntiles <= 64 &&
-                     itf_waves <= kItfFuseWaves;
+  // every multi-tile system of at most 64 tiles, no corner rows: the final
+  // pass runs the interface pass itself, and there is no interface launch
+  const bool inl = !QUASI && L.n_grid > 0 && L.max_ntiles <= 64;
   if (L.n_grid > 0) {
     if (L.green) {
       if (L.n_beta > 0) {
-        if (fused) {
-          GridArgs G{F,       X,        Xfwd,    L.gpart, L.corner0, 0,       L.gen_tK,
-                     L.sys,   nullptr,  L.ttab,  L.ttab_n, L.summ,   L.ghost, L.gscr};
-          launch_beta_ends_itf<SH, Tio>(L, static_cast<const Tio*>(F), G, st);
-        } else if (L.green_kf > 0) {
+        if (L.green_kf > 0)
           launch_beta_ends<SH, Tio>(L, static_cast<const Tio*>(F), st);
-        } else {
+        else
           launch_beta<SH, Tio>(L, static_cast<const Tio*>(F), st);
-        }
       }
       if (L.n_last > 0) {
         A.items = nullptr;
@@ -2757,7 +2751,7 @@ static hipError_t run_solve(const LaunchSet& L, const void* F, void* X, const vo
       }
     }
     if (L.ev) (void)hipEventRecord(L.ev[1], st);
-    if (!fused) launch_grid<QUASI>(L, F, X, Xfwd, sizeof(Tio) == 4 ? 1 : 0, st);
+    if (!inl) launch_grid<QUASI>(L, F, X, Xfwd, sizeof(Tio) == 4 ? 1 : 0, st);
     if (L.ev) (void)hipEventRecord(L.ev[2], st);
   } else if (L.ev) {
     (void)hipEventRecord(L.ev[1], st);
@@ -2766,6 +2760,7 @@ static hipError_t run_solve(const LaunchSet& L, const void* F, void* X, const vo
   // systems solved whole by one workgroup each (varlen plans)
   if (L.n_sys > 0) launch_sys<SH, Tio, Tc, REFINE, BWD, QUASI>(L, A, st);
   A.items = L.fin_items;
+  A.itf_inline = inl ? 1 : 0;
   // after a first pass the final pass re-reads the tiles the first pass read
   // last while they are still cached: a series runs last-tile-first, a varlen
   // plan's list already starts with the first pass's tiles in reverse
@@ -2976,7 +2971,6 @@ extern "C" tdt_status_t tdt_solve_noalloc(tdt_plan_t plan, const void* F, void* 
   L.summ = base;
   L.ghost = base + 2 * kScratchSlots;
   L.gscr = base + 4 * kScratchSlots;
-  L.itf_cnt = nullptr;   // nothing of the array may be assumed zero: interface pass alone
   L.gpart = base + 7 * kScratchSlots;
   L.ev = nullptr;
   return tdt::launch_solve(dtype, false, L, F, X, nullptr, stream) == hipSuccess ? TDT_OK

@@ -182,14 +182,13 @@ def test_many_tiles(tiles, extra, dtype):
 @pytest.mark.parametrize("tiles,M,dom,sym", [(2, 1, 2.0, False), (64, 2, 2.0, False),
                                              (64, 3, 2.0, False), (17, 2, 1.02, True)])
 @pytest.mark.parametrize("dtype", ["f64", "f32_refine"])
-def test_first_pass_with_interface(tiles, M, dom, sym, dtype):
-    """A series of at most 64 whole tiles per right-hand side whose first
-    pass has at most 128 wavefronts runs the interface pass in the last of
-    them per right-hand side (a counter per right-hand side, cleared by that
-    wavefront); 64 tiles times 3 right-hand sides is beyond that and takes
-    the interface launch.  Two solves in a row with other data, the adjoint
-    after them, and a weakly dominant matrix whose supports are long enough
-    to split every tile end into its own wavefront."""
+def test_interface_inside_final_pass(tiles, M, dom, sym, dtype):
+    """A series of at most 64 tiles per right-hand side runs the interface
+    pass inside the final pass (every wavefront scans its system's tiles, one
+    per lane) instead of in a launch of its own: two solves in a row with
+    other data, the adjoint after them, and a weakly dominant matrix whose
+    supports are long enough to split every tile end into its own
+    first-pass wavefront."""
     tdt = _tdt()
     n = tiles * 8192
     rng = np.random.default_rng(tiles * 10 + M)
