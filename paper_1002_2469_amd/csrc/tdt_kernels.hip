@@ -538,12 +538,15 @@ struct TileArgs {
   const int2* __restrict__ ends_items;
   int64_t n_ends;
   const double* __restrict__ gpack;
-  // final pass of a plan whose multi-tile systems have at most 64 tiles and
-  // no corner rows: each wavefront runs its system's interface pass itself
-  // (lane t takes tile t) instead of reading the ghosts of a separate launch
+  // final pass of a plan whose multi-tile systems have at most 64 tiles:
+  // each wavefront runs its system's interface pass itself (lane t takes
+  // tile t) instead of reading the ghosts of a separate launch, and the
+  // workgroups of a quasi-Toeplitz system's end tiles store its corner rows
   int itf_inline;
   const double* __restrict__ ttab;    // as the interface pass's table ([2][ttab_n])
   int64_t ttab_n;
+  int64_t corner0;                    // series, quasi-Toeplitz: first corner slot (2 per
+                                      // right-hand side) of the adjoint partials
 };
 
 // Copy of a system descriptor read with scalar loads (wave-uniform index).
@@ -630,12 +633,47 @@ struct TileLoad {
   double XL, XR;
 };
 
-// The values just outside tile t of a system of at most 64 tiles without
-// corner rows, by the system's interface pass (the scans of eq. (15), one
-// tile per lane, zero outside the system) from the tile summaries and table
-// entries this lane loaded for tile `lane`.
+// A corner row of a quasi-Toeplitz system once the interface pass has its
+// value v: which = 0 is row 0 (stored at X[base - 1], base = the first inner
+// row), which = 1 row N-1 (at X[base + n]).  With Xfwd (adjoint, v = gF of
+// that row) the row's own t-gradient terms go to the corner slot cg[0..4]:
+// row 0 holds t_0 + psi and t_1, row N-1 holds t_-1 and t_0 + chi.
+template <typename Tio>
+__device__ __forceinline__ void store_corner(Tio* X, const Tio* Xfwd, double* cg, int64_t base,
+                                             int64_t n, int which, double v) {
+  if (which == 0) {
+    X[base - 1] = (Tio)v;
+    if (Xfwd) {
+      const double x0 = (double)Xfwd[base - 1], x1 = (double)Xfwd[base];
+      cg[0] = 0.0;
+      cg[1] = -v * x0;
+      cg[2] = -v * x1;
+      cg[3] = -v * x0;
+      cg[4] = 0.0;
+    }
+  } else {
+    X[base + n] = (Tio)v;
+    if (Xfwd) {
+      const double xn = (double)Xfwd[base + n], xp = (double)Xfwd[base + n - 1];
+      cg[0] = -v * xp;
+      cg[1] = -v * xn;
+      cg[2] = 0.0;
+      cg[3] = 0.0;
+      cg[4] = -v * xn;
+    }
+  }
+}
+
+// The values just outside tile t of a system of at most 64 tiles, by the
+// system's interface pass (the scans of eq. (15), one tile per lane) from
+// the tile summaries and table entries this lane loaded for tile `lane`.
+// Outside the chain of tiles: zero, or for a quasi-Toeplitz system the two
+// corner rows, whose equations close the chain at both ends (fl, fr: their
+// right-hand sides).
+template <bool QUASI>
 __device__ __forceinline__ void inline_ghosts(const SysDesc& S, int t, double u, double v,
-                                              double b0, double i0, double& XL, double& XR) {
+                                              double b0, double i0, double fl, double fr,
+                                              double& XL, double& XR) {
   const int lane = threadIdx.x & 63;
   const int P = S.ntiles;
   const bool real = lane < P, last = lane == P - 1;
@@ -644,19 +682,25 @@ __device__ __forceinline__ void inline_ghosts(const SysDesc& S, int t, double u,
   const double pf = real ? (last ? S.ltileK[0] : S.tileK[0]) : 0.0;
   const double pl = real ? (last ? S.ltileK[1] : S.tileK[1]) : 1.0;
   const double cf = real ? (last ? S.ltileK[2] : S.tileK[2]) : 1.0;
+  const double alpha_in = QUASI ? fl * S.qc[0] : 0.0;   // alpha_{-1}
   double Ai = pl * iD, gi = yl + pl * iD * bp * yf;
-  wave_scan_affine_fwd(Ai, gi);                   // gi = alpha_lane
-  double am = __shfl_up(gi, 1, 64);               // alpha_{lane-1}
-  if (lane == 0) am = 0.0;
+  wave_scan_affine_fwd(Ai, gi);
+  const double at = Ai * alpha_in + gi;           // alpha_lane
+  double am = __shfl_up(at, 1, 64);               // alpha_{lane-1}
+  if (lane == 0) am = alpha_in;
+  const double u_right =                          // u_P
+      QUASI ? (fr * S.qc[2] + S.qc[3] * __shfl(at, P - 1, 64)) * S.qc[5] : 0.0;
   double Ct = cf * iD, ht = (yf + pf * am) * iD;
-  wave_scan_affine_bwd(Ct, ht);                   // ht = u_lane
-  double un = __shfl_down(ht, 1, 64);             // u_{lane+1}
-  if (lane == 63) un = 0.0;
-  XL = __shfl(am + bp * ht, t, 64);
+  wave_scan_affine_bwd(Ct, ht);
+  const double ut = Ct * u_right + ht;            // u_lane
+  double un = __shfl_down(ut, 1, 64);             // u_{lane+1}
+  if (lane == 63) un = u_right;
+  XL = __shfl(am + bp * ut, t, 64);
   XR = __shfl(un, t, 64);
 }
 
-template <class SH, typename Tio, typename Tc, bool SUMMARY, bool QUASI>
+//   INLINE: the kernel can run the interface pass inline (when A.itf_inline)
+template <class SH, typename Tio, typename Tc, bool SUMMARY, bool QUASI, bool INLINE>
 __device__ __forceinline__ void load_tile_item(const TileArgs<Tio>& A, int64_t item,
                                                TileLoad<SH, Tio, Tc>& P) {
   TDT_SHAPE(SH)
@@ -665,8 +709,9 @@ __device__ __forceinline__ void load_tile_item(const TileArgs<Tio>& A, int64_t i
   const SysDesc S = load_sys(A.sys, G.I.s);
   // the inline interface pass: its loads first, so that its scans can run
   // while the tile's rows are still on their way
-  const bool inl = !SUMMARY && !QUASI && A.itf_inline && S.ntiles > 1;
-  double iu = 0.0, iv = 0.0, ib = 0.0, ii = 1.0;
+  const bool inl = INLINE && !SUMMARY && A.itf_inline && (S.ntiles > 1 || QUASI);
+  const int64_t sbase = G.base - G.t0;   // the system's first row (inside the corners)
+  double iu = 0.0, iv = 0.0, ib = 0.0, ii = 1.0, fl = 0.0, fr = 0.0;
   if (inl) {
     const int lane = tid & 63;
     const int tc = lane < S.ntiles ? lane : 0;
@@ -677,6 +722,10 @@ __device__ __forceinline__ void load_tile_item(const TileArgs<Tio>& A, int64_t i
     iv = A.summ[2 * sl + 1];
     ib = A.ttab[tb];
     ii = A.ttab[A.ttab_n + tb];
+    if (QUASI) {
+      fl = (double)A.F[sbase - 1];
+      fr = (double)A.F[sbase + S.n];
+    }
   }
   const __amdgpu_buffer_rsrc_t src = make_rsrc(A.F + G.base, (int64_t)G.tl * sizeof(Tio));
   const int vb = opaque(tid * (int)sizeof(Tio));
@@ -693,7 +742,15 @@ __device__ __forceinline__ void load_tile_item(const TileArgs<Tio>& A, int64_t i
     P.iD = tb[kTabInvD * kNT + ti];
   }
   if (inl) {
-    inline_ghosts(S, G.I.t, iu, iv, ib, ii, P.XL, P.XR);
+    inline_ghosts<QUASI>(S, G.I.t, iu, iv, ib, ii, fl, fr, P.XL, P.XR);
+    if (QUASI && tid == 0 && (G.I.t == 0 || G.I.t == S.ntiles - 1)) {
+      // the corner rows (and, in the adjoint, their t-gradient partials)
+      const int64_t cs0 = A.items ? (int64_t)S.fslot0 + S.ntiles : A.corner0 + 2 * G.I.m;
+      if (G.I.t == 0)
+        store_corner<Tio>(A.X, A.Xfwd, A.gpart + kGradN * cs0, sbase, S.n, 0, P.XL);
+      if (G.I.t == S.ntiles - 1)
+        store_corner<Tio>(A.X, A.Xfwd, A.gpart + kGradN * (cs0 + 1), sbase, S.n, 1, P.XR);
+    }
   } else if (!SUMMARY) {
     // a one-tile system has no interface pass (zero outside values) unless
     // it has corner rows
@@ -1020,37 +1077,6 @@ __device__ __forceinline__ void fold_right(TileShared<SH, Tio, Tc>& sh, int tl, 
   }
 }
 
-// A corner row of a quasi-Toeplitz system once the interface pass has its
-// value v: which = 0 is row 0 (stored at X[base - 1], base = the first inner
-// row), which = 1 row N-1 (at X[base + n]).  With Xfwd (adjoint, v = gF of
-// that row) the row's own t-gradient terms go to the corner slot cg[0..4]:
-// row 0 holds t_0 + psi and t_1, row N-1 holds t_-1 and t_0 + chi.
-template <typename Tio>
-__device__ __forceinline__ void store_corner(Tio* X, const Tio* Xfwd, double* cg, int64_t base,
-                                             int64_t n, int which, double v) {
-  if (which == 0) {
-    X[base - 1] = (Tio)v;
-    if (Xfwd) {
-      const double x0 = (double)Xfwd[base - 1], x1 = (double)Xfwd[base];
-      cg[0] = 0.0;
-      cg[1] = -v * x0;
-      cg[2] = -v * x1;
-      cg[3] = -v * x0;
-      cg[4] = 0.0;
-    }
-  } else {
-    X[base + n] = (Tio)v;
-    if (Xfwd) {
-      const double xn = (double)Xfwd[base + n], xp = (double)Xfwd[base + n - 1];
-      cg[0] = -v * xp;
-      cg[1] = -v * xn;
-      cg[2] = 0.0;
-      cg[3] = 0.0;
-      cg[4] = -v * xn;
-    }
-  }
-}
-
 // One wavefront's dot product of k rows of a tile with k entries of a Green
 // row's support (k a multiple of 64; both pointers already offset by the
 // lane), U rows in flight per lane.  The lane sums are added by a fixed
@@ -1240,7 +1266,7 @@ __global__ __launch_bounds__(SH::NT, REFINE ? kRefineWaves : SH::WAVES) void k_t
   TileLoad<SH, Tio, Tc> P;
 
   while (k < A.nitems) {
-    load_tile_item<SH, Tio, Tc, SUMMARY, QUASI>(A, item_of(k), P);
+    load_tile_item<SH, Tio, Tc, SUMMARY, QUASI, !(REFINE && QUASI)>(A, item_of(k), P);
     const int64_t item = item_of(k);
     const TileGeom G = tile_geom<SH>(A.items, A.sys, item, A.last_only);
     const SysDesc S = load_sys(A.sys, G.I.s);
@@ -2713,14 +2739,17 @@ static hipError_t run_solve(const LaunchSet& L, const void* F, void* X, const vo
   A.refine_tol = L.refine_tol;
   A.ttab = L.ttab;
   A.ttab_n = L.ttab_n;
+  A.corner0 = L.corner0;
   if (L.ev) (void)hipEventRecord(L.ev[0], st);
   // Tile summaries of the refinement path are computed in double (one
   // double sweep costs less than a float solve plus refinement, and the
   // values outside each tile then come out exact in double).
   using Ts = typename std::conditional<REFINE, double, Tc>::type;
-  // every multi-tile system of at most 64 tiles, no corner rows: the final
-  // pass runs the interface pass itself, and there is no interface launch
-  const bool inl = !QUASI && L.n_grid > 0 && L.max_ntiles <= 64;
+  // every multi-tile system of at most 64 tiles: the final pass runs the
+  // interface pass itself, and there is no interface launch (except in the
+  // refinement of quasi-Toeplitz systems, whose final pass lost more to it
+  // than the launch costs)
+  const bool inl = L.n_grid > 0 && L.max_ntiles <= 64 && !(REFINE && QUASI);
   if (L.n_grid > 0) {
     if (L.green) {
       if (L.n_beta > 0) {
