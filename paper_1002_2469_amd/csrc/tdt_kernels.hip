@@ -973,7 +973,9 @@ __device__ __forceinline__ void solve_tile_lds(TileShared<SH, Tio, Tc>& sh, int 
 // components): 0 to the corner components gpart[3..4], and the rows next to
 // the corner rows read those rows' forward solution; the corner rows
 // themselves are stored by the interface pass.  One barrier inside (BWD).
-template <class SH, typename Tio, typename Tc, bool BWD, bool QUASI>
+//   PRE (adjoint): the forward solution's first rows are requested before
+//   the stores, so that their latency overlaps them (costs registers)
+template <class SH, typename Tio, typename Tc, bool BWD, bool QUASI, bool PRE = false>
 __device__ __forceinline__ void store_tile(TileShared<SH, Tio, Tc>& sh, Tio* X, const Tio* Xfwd,
                                            int64_t base, int64_t t0, int tl, int64_t n,
                                            double* gpart) {
@@ -993,6 +995,13 @@ __device__ __forceinline__ void store_tile(TileShared<SH, Tio, Tc>& sh, Tio* X, 
   constexpr int kLine = 128 / (int)sizeof(Tio);
   const int mis = __builtin_amdgcn_readfirstlane(
       (int)((reinterpret_cast<uintptr_t>(X + base) / sizeof(Tio)) & (kLine - 1)));
+  constexpr int kPre = BWD && PRE ? 8 : 0;
+  Tio xpre[kPre > 0 ? kPre : 1];
+  if constexpr (kPre > 0) {
+#pragma unroll
+    for (int j = 0; j < kPre; ++j)
+      xpre[j] = buf_load<Tio>(xf, vs + (j * kNT + lo) * (int)sizeof(Tio));
+  }
   if (mis == 0) {
 #pragma unroll
     for (int j = 0; j < kB; ++j)
@@ -1029,7 +1038,7 @@ __device__ __forceinline__ void store_tile(TileShared<SH, Tio, Tc>& sh, Tio* X, 
 #pragma unroll 8
     for (int j = 0; j < kB; ++j) {
       const int xo = vs + (j * kNT + lo) * (int)sizeof(Tio);
-      const Tio xt = buf_load<Tio>(xf, xo);
+      const Tio xt = j < kPre ? xpre[j < kPre ? j : 0] : buf_load<Tio>(xf, xo);
       Tio xn = __shfl_down(xt, 1, 64);   // element e + 1
       Tio xq = __shfl_up(xt, 1, 64);     // element e - 1
       if (lane == 63) xn = buf_load<Tio>(xf, xo + (int)sizeof(Tio));
@@ -1299,7 +1308,7 @@ __global__ __launch_bounds__(SH::NT, REFINE ? kRefineWaves : SH::WAVES) void k_t
                                                  est_max, A.max_iter, A.refine_tol);
       __syncthreads();
       const int64_t fs = A.items ? (int64_t)S.fslot0 + G.I.t : G.I.m * S.ntiles + G.I.t;
-      store_tile<SH, Tio, Tc, BWD, QUASI>(sh, A.X, A.Xfwd, G.base, G.t0, tl, S.n,
+      store_tile<SH, Tio, Tc, BWD, QUASI, true>(sh, A.X, A.Xfwd, G.base, G.t0, tl, S.n,
                                           A.gpart + (QUASI ? kGradN : 3) * fs);
     }
     k = kn;
