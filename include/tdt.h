@@ -419,7 +419,10 @@ tdt_status_t tdt_segment_merge(const double *l, const double *r, double *out);
 /* Measurement support.  While enabled (enable != 0), every solve of the plan
  * that is not being captured records HIP events on its stream around its
  * three kernel groups: the first pass over tiles (tile summaries), the
- * interface pass across tiles, and the final pass (solve and store).
+ * interface pass across tiles, and the final pass (solve and store).  Where
+ * every multi-tile system has at most 64 tiles the final pass runs the
+ * interface pass itself, and the interface group is empty (two events with
+ * nothing between them).
  * tdt_plan_profile_read synchronises the device, returns in ms3[0..2] the
  * summed milliseconds of the three groups over the recorded solves and in
  * *nsolves their number, and clears the record.  Disabling clears it too. */
@@ -432,9 +435,10 @@ tdt_status_t tdt_plan_profile_read(tdt_plan_t plan, double *ms3, int64_t *nsolve
  *       (8192 rows each) are solved whole by one workgroup each, so that a
  *       batch of such systems takes a single launch whose second read of
  *       every tile comes from cache; larger systems go through the
- *       tile-parallel three-kernel path (first pass, interface pass, final
- *       pass).  0..16, default 8; 0 sends every multi-tile system through
- *       the three kernels.
+ *       tile-parallel path (first pass, interface pass, final pass; the
+ *       final pass runs the interface pass itself when every such system
+ *       has at most 64 tiles).  0..16, default 8; 0 sends every multi-tile
+ *       system through the tile-parallel path.
  *   TDT_OPT_WG_PER_CU        0 (default): the tile kernels launch one
  *       workgroup per tile and the other kernels as many workgroups as fit
  *       at once; k > 0: every kernel runs at most k persistent workgroups
