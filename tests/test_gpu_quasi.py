@@ -107,8 +107,9 @@ def _ragged_quasi(rng, sizes, lo=1.2):
 @pytest.mark.parametrize("dtype", ["f64", "f32_refine", "f32"])
 def test_quasi_varlen_ragged(dtype, whole):
     """Quasi-Toeplitz systems of 3 rows to 13 tiles, solved whole by one
-    workgroup each up to `whole` tiles (of inner rows) and by the three-kernel
-    path beyond."""
+    workgroup each up to `whole` tiles (of inner rows) and tile-parallel
+    beyond (f64 and f32: the final pass closes the chain of tiles with the
+    corner rows itself and stores them; f32_refine: the interface launch)."""
     tdt = _tdt()
     rng = np.random.default_rng(77)
     sizes = np.array([3, 4, 35, 8194, 8195, 67, 20000, 7, 16386, 33, 66, 100002])
