@@ -211,20 +211,25 @@ def test_interface_inside_final_pass(tiles, M, dom, sym, dtype):
     plan.close()
 
 
+@pytest.mark.parametrize("extra,dom,sym", [(5, (1.05, 2.0), False), (0, (1.05, 2.0), False),
+                                           (0, (1.02, 1.02), True)])
 @pytest.mark.parametrize("dtype", ["f64", "f32_refine"])
-def test_chunked_interface_series(dtype):
+def test_chunked_interface_series(dtype, extra, dom, sym):
     """Series of 2049 to 16384 tiles take the interface pass in chunks of 64
     tiles (chunk composites, then every chunk's tiles): several right-hand
-    sides (the chunks of all of them in one launch), a ragged last chunk and
-    tile, forward and adjoint against the oracle."""
+    sides (the chunks of all of them in one launch), a ragged last chunk,
+    a partial or a whole last tile, and long supports of a weakly dominant
+    matrix (every tile end a first-pass wavefront of its own); forward and
+    adjoint against the oracle."""
     tdt = _tdt()
-    n = 2100 * 8192 + 5          # 2101 tiles: 33 chunks, the last one of 53 tiles
+    n = 2100 * 8192 + extra      # 2100 or 2101 tiles: 33 chunks, the last one of 52 or 53
     M = 3
     rng = np.random.default_rng(2101)
-    a, b, c = W.random_system(rng, 1.05, 2.0)
+    a, b, c = W.random_system(rng, dom[0], dom[1], symmetric=sym, signs=not sym)
     F = rng.standard_normal((M, n))
-    print(f"[case] chunked interface n={n} M={M} dtype={dtype}", flush=True)
+    print(f"[case] chunked interface n={n} M={M} dtype={dtype} sym={sym}", flush=True)
     plan = tdt.Plan(a, b, c, n, dtype)
+    plan.set_option("shape", 0)
     Xd = plan.solve(to_dev(F))
     ref = oracle.solve(F, a, b, c)
     assert oracle.rel_err_rows(to_host(Xd), ref).max() <= tol_f64(a, b, c, n)
