@@ -547,6 +547,12 @@ struct TileArgs {
   int64_t ttab_n;
   int64_t corner0;                    // series, quasi-Toeplitz: first corner slot (2 per
                                       // right-hand side) of the adjoint partials
+  // final pass of a small series whose Green rows have short supports (the
+  // P1 kernels): each workgroup also computes its system's tile summaries
+  // (no first-pass launch); the supports' entries as the first pass's
+  // ([2][tile length])
+  const double* __restrict__ green;
+  int gkf, gkl;
 };
 
 // Copy of a system descriptor read with scalar loads (wave-uniform index).
@@ -700,9 +706,10 @@ __device__ __forceinline__ void inline_ghosts(const SysDesc& S, int t, double u,
 }
 
 //   INLINE: the kernel can run the interface pass inline (when A.itf_inline)
-template <class SH, typename Tio, typename Tc, bool SUMMARY, bool QUASI, bool INLINE>
+//   P1: the system's tile summaries are in LDS (ps), computed by the workgroup
+template <class SH, typename Tio, typename Tc, bool SUMMARY, bool QUASI, bool INLINE, bool P1>
 __device__ __forceinline__ void load_tile_item(const TileArgs<Tio>& A, int64_t item,
-                                               TileLoad<SH, Tio, Tc>& P) {
+                                               TileLoad<SH, Tio, Tc>& P, const double* ps) {
   TDT_SHAPE(SH)
   const int tid = threadIdx.x;
   const TileGeom G = tile_geom<SH>(A.items, A.sys, item, A.last_only);
@@ -718,8 +725,8 @@ __device__ __forceinline__ void load_tile_item(const TileArgs<Tio>& A, int64_t i
     const bool varlen = A.items != nullptr;
     const int64_t sl = tile_slot(S, G.I.m, tc, varlen);
     const int64_t tb = varlen ? sl : tile_slot(S, 0, tc, false);
-    iu = A.summ[2 * sl];
-    iv = A.summ[2 * sl + 1];
+    iu = P1 ? ps[2 * tc] : A.summ[2 * sl];
+    iv = P1 ? ps[2 * tc + 1] : A.summ[2 * sl + 1];
     ib = A.ttab[tb];
     ii = A.ttab[A.ttab_n + tb];
     if (QUASI) {
@@ -794,7 +801,55 @@ struct TileShared {
   Tc fw[SH::NW][2], bw[SH::NW][2];
   double red[SH::NW][4];
   double edge[SH::NW][2];
+  double ps[64][2];   // a small series system's tile summaries (final pass)
 };
+
+// The tile summaries of one system of a small series from the Green rows'
+// supports (the dot products of the first pass, eq. (13)), computed by the
+// final pass's workgroup itself: wavefront w takes tiles w, w + NW, ...,
+// four at a time with all their loads in flight; lanes stride the support
+// rows and the lane sums are added by the same butterfly as in the first
+// pass.  Results to ps (LDS); the caller's barrier publishes them.
+template <class SH, typename Tio>
+__device__ __forceinline__ void system_summaries(const TileArgs<Tio>& A, const SysDesc& S,
+                                                 int64_t sbase, double (*ps)[2]) {
+  TDT_SHAPE(SH)
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int nf = A.gkf / 64, nl = A.gkl / 64;
+  const double* gf = A.green + lane;
+  const double* gl = A.green + 2 * kTile - A.gkl + lane;
+  for (int t0 = w; t0 < S.ntiles; t0 += 4 * kNW) {
+    double s1[4], s2[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s1[q] = s2[q] = 0.0;
+    for (int j = 0; j < nf || j < nl; ++j) {
+      const double g1 = j < nf ? gf[j * 64] : 0.0, g2 = j < nl ? gl[j * 64] : 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int t = t0 + q * kNW;
+        const Tio* head = A.F + sbase + (int64_t)(t < S.ntiles ? t : 0) * kTile + lane;
+        const double h = j < nf ? (double)head[j * 64] : 0.0;
+        const double l = j < nl ? (double)head[kTile - A.gkl + j * 64] : 0.0;
+        s1[q] += h * g1;
+        s2[q] += l * g2;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+      for (int d = 32; d >= 1; d >>= 1) {
+        s1[q] += __shfl_xor(s1[q], d, 64);
+        s2[q] += __shfl_xor(s2[q], d, 64);
+      }
+      const int t = t0 + q * kNW;
+      if (lane == 0 && t < S.ntiles) {
+        ps[t][0] = s1[q];
+        ps[t][1] = s2[q];
+      }
+    }
+  }
+}
 
 // Element j*kNT + tid of a tile lives in LDS row j*(kNT/kB) + tid/kB, column
 // tid%kB: after the coalesced loads each lane owns kB consecutive rows.
@@ -1244,7 +1299,10 @@ __device__ __forceinline__ void beta_ends_item(const BetaEndsArgs<Tio>& A, int64
 //                    in double, repeated until converged.
 //   BWD            : also accumulates the t-gradient partial sums against the
 //                    forward solution Xfwd (the tile solves T^T gF = gX).
-template <class SH, typename Tio, typename Tc, bool REFINE, bool SUMMARY, bool BWD, bool QUASI>
+//   P1             : final pass of a small series that computes its
+//                    system's tile summaries itself (no first pass)
+template <class SH, typename Tio, typename Tc, bool REFINE, bool SUMMARY, bool BWD, bool QUASI,
+          bool P1 = false>
 __global__ __launch_bounds__(SH::NT, REFINE ? kRefineWaves : SH::WAVES) void k_tile(
     TileArgs<Tio> A) {
   TDT_SHAPE(SH)
@@ -1275,7 +1333,14 @@ __global__ __launch_bounds__(SH::NT, REFINE ? kRefineWaves : SH::WAVES) void k_t
   TileLoad<SH, Tio, Tc> P;
 
   while (k < A.nitems) {
-    load_tile_item<SH, Tio, Tc, SUMMARY, QUASI, !(REFINE && QUASI)>(A, item_of(k), P);
+    if constexpr (P1) {
+      const TileGeom G0 = tile_geom<SH>(A.items, A.sys, item_of(k), A.last_only);
+      const SysDesc S0 = load_sys(A.sys, G0.I.s);
+      system_summaries<SH, Tio>(A, S0, G0.base - G0.t0, sh.ps);
+      __syncthreads();
+    }
+    load_tile_item<SH, Tio, Tc, SUMMARY, QUASI, !(REFINE && QUASI), P1>(A, item_of(k), P,
+                                                                        &sh.ps[0][0]);
     const int64_t item = item_of(k);
     const TileGeom G = tile_geom<SH>(A.items, A.sys, item, A.last_only);
     const SysDesc S = load_sys(A.sys, G.I.s);
@@ -2467,10 +2532,11 @@ static int64_t grid_cap(int per_cu, int wg_per_cu) {
 // overlap the next ones' loads (measured on a 512 MiB solve: 5.8 TB/s
 // against 5.3 TB/s for the same tile code run by resident workgroups that
 // loop over tiles).  With a cap per CU the workgroups persist and loop.
-template <class SH, typename Tio, typename Tc, bool REFINE, bool SUMMARY, bool BWD, bool QUASI>
+template <class SH, typename Tio, typename Tc, bool REFINE, bool SUMMARY, bool BWD, bool QUASI,
+          bool P1 = false>
 static void launch_tile(TileArgs<Tio>& A, int64_t nitems, int reverse, int last_only,
                         int wg_per_cu, hipStream_t st, int64_t extra_wg = 0) {
-  auto kern = k_tile<SH, Tio, Tc, REFINE, SUMMARY, BWD, QUASI>;
+  auto kern = k_tile<SH, Tio, Tc, REFINE, SUMMARY, BWD, QUASI, P1>;
   static int per_cu = resident_per_cu(kern, SH::NT);
   const int64_t cap = wg_per_cu > 0 ? grid_cap(per_cu, wg_per_cu) : nitems;
   A.nitems = nitems;
@@ -2759,9 +2825,15 @@ static hipError_t run_solve(const LaunchSet& L, const void* F, void* X, const vo
   // refinement of quasi-Toeplitz systems, whose final pass lost more to it
   // than the launch costs)
   const bool inl = L.n_grid > 0 && L.max_ntiles <= 64 && !(REFINE && QUASI);
+  // a small series (few tiles in all, at most four per wavefront of a
+  // workgroup) of whole tiles with short supports: the final pass computes
+  // the summaries too, and the solve is one launch
+  const bool p1i = inl && !QUASI && !BWD && L.green && L.green_kf > 0 && L.n_last == 0 &&
+                   L.n_beta > 0 && L.n_beta <= 256 && L.max_ntiles <= 4 * SH::NW &&
+                   L.green_kf + L.green_kl <= kEndsSplitRows;
   if (L.n_grid > 0) {
     if (L.green) {
-      if (L.n_beta > 0) {
+      if (L.n_beta > 0 && !p1i) {
         if (L.green_kf > 0)
           launch_beta_ends<SH, Tio>(L, static_cast<const Tio*>(F), st);
         else
@@ -2799,12 +2871,24 @@ static hipError_t run_solve(const LaunchSet& L, const void* F, void* X, const vo
   if (L.n_sys > 0) launch_sys<SH, Tio, Tc, REFINE, BWD, QUASI>(L, A, st);
   A.items = L.fin_items;
   A.itf_inline = inl ? 1 : 0;
+  A.green = L.green;
+  A.gkf = L.green_kf;
+  A.gkl = L.green_kl;
   // after a first pass the final pass re-reads the tiles the first pass read
   // last while they are still cached: a series runs last-tile-first, a varlen
   // plan's list already starts with the first pass's tiles in reverse
-  if (L.n_fin > 0)
+  if (L.n_fin > 0) {
+    if constexpr (!BWD && !QUASI) {
+      if (p1i) {
+        launch_tile<SH, Tio, Tc, REFINE, false, false, false, true>(A, L.n_fin, 0, 0,
+                                                                   L.wg_per_cu, st);
+        if (L.ev) (void)hipEventRecord(L.ev[3], st);
+        return hipGetLastError();
+      }
+    }
     launch_tile<SH, Tio, Tc, REFINE, false, BWD, QUASI>(
         A, L.n_fin, (L.n_p1 > 0 && !L.fin_items) ? 1 : 0, 0, L.wg_per_cu, st);
+  }
   if (L.ev) (void)hipEventRecord(L.ev[3], st);
   return hipGetLastError();
 }

@@ -211,6 +211,33 @@ def test_interface_inside_final_pass(tiles, M, dom, sym, dtype):
     plan.close()
 
 
+@pytest.mark.parametrize("shape,M", [(2, 1), (2, 3), (0, 2), (1, 5)])
+@pytest.mark.parametrize("dtype", ["f64", "f32_refine", "f32"])
+def test_small_series_in_one_launch(shape, M, dtype):
+    """A small series of whole tiles with short supports (at most 256 tiles
+    in all, at most four per wavefront of a workgroup) is solved by the
+    final pass alone: each workgroup computes its system's tile summaries
+    from the supports, runs the interface pass and solves its tile.  The
+    65536-row system at every work shape, several right-hand sides, two
+    solves in a row with other data."""
+    tdt = _tdt()
+    n = 65536
+    rng = np.random.default_rng(31 + shape + M)
+    a, b, c = -1.0, 4.0, -1.0
+    print(f"[case] small series in one launch shape={shape} M={M} dtype={dtype}", flush=True)
+    plan = tdt.Plan(a, b, c, n, dtype)
+    plan.set_option("shape", shape)
+    assert plan.green_support()["forward"][0] > 0
+    for rep in range(2):
+        F = rng.uniform(-1.0, 1.0, (M, n))
+        X = to_host(plan.solve(to_dev(F, dtype)))
+        Fr = F.astype(np.float32).astype(np.float64) if dtype == "f32" else F
+        ref = oracle.solve(Fr, a, b, c)
+        tol = tol_f32(a, b, c, n) if dtype == "f32" else tol_f64(a, b, c, n)
+        assert oracle.rel_err_rows(X, ref).max() <= tol, (rep, dtype)
+    plan.close()
+
+
 @pytest.mark.parametrize("extra,dom,sym", [(5, (1.05, 2.0), False), (0, (1.05, 2.0), False),
                                            (0, (1.02, 1.02), True)])
 @pytest.mark.parametrize("dtype", ["f64", "f32_refine"])
