@@ -567,6 +567,17 @@ def main() -> int:
         nmax = d["N"] if d["kind"] == "series" else max(b - a for a, b in zip(o, o[1:]))
         inline_itf = tile < nmax <= 64 * tile
     itf = ", interface pass inline" if inline_itf else ""
+    # a small series of whole tiles with short supports is solved by the
+    # final pass alone (at most 256 tiles in all and four per wavefront of a
+    # workgroup): the summaries' rows are read there
+    if d["kind"] == "series" and 0 < kf + kl <= 256 and n_first > 0:
+        tile = _lib.SHAPES[shape][0] * _lib.SHAPES[shape][1]
+        tiles = d["N"] // tile
+        if (d["N"] % tile == 0 and tiles <= 4 * (_lib.SHAPES[shape][1] // 64)
+                and d["M"] * tiles <= 256):
+            per_launch["final_pass"] += per_launch["first_pass"]
+            per_launch["first_pass"] = 0.0
+            itf = ", tile summaries and interface pass inline: one launch"
     names = {"first_pass": (f"k_beta_ends<double> (tile summaries from the Green rows' "
                             f"supports, {kf} + {kl} rows per tile)" if kf + kl > 0 else
                             "k_beta<double> (Green-row tile summaries, first pass)"
