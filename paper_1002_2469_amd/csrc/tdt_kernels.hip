@@ -1027,7 +1027,8 @@ __device__ __forceinline__ void solve_tile_lds(TileShared<SH, Tio, Tc>& sh, int 
 // shuffles, and only the first and last lane of a wavefront load theirs.  QUASI (quasi-Toeplitz plans, whose partials have 5
 // components): 0 to the corner components gpart[3..4], and the rows next to
 // the corner rows read those rows' forward solution; the corner rows
-// themselves are stored by the interface pass.  One barrier inside (BWD).
+// themselves are stored by the interface pass (inline: by the workgroups of
+// the system's end tiles).  One barrier inside (BWD).
 //   PRE (adjoint): the forward solution's first rows are requested before
 //   the stores, so that their latency overlaps them (costs registers)
 template <class SH, typename Tio, typename Tc, bool BWD, bool QUASI, bool PRE = false>
