@@ -422,7 +422,8 @@ tdt_status_t tdt_segment_merge(const double *l, const double *r, double *out);
  * interface pass across tiles, and the final pass (solve and store).  Where
  * every multi-tile system has at most 64 tiles the final pass runs the
  * interface pass itself, and the interface group is empty (two events with
- * nothing between them).
+ * nothing between them); a small series of whole tiles (at most 256 in all)
+ * is solved by the final pass alone, and the first-pass group is empty too.
  * tdt_plan_profile_read synchronises the device, returns in ms3[0..2] the
  * summed milliseconds of the three groups over the recorded solves and in
  * *nsolves their number, and clears the record.  Disabling clears it too. */
