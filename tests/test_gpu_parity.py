@@ -219,7 +219,8 @@ def test_small_series_in_one_launch(shape, M, dtype):
     final pass alone: each workgroup computes its system's tile summaries
     from the supports, runs the interface pass and solves its tile.  The
     65536-row system at every work shape, several right-hand sides, two
-    solves in a row with other data."""
+    solves in a row with other data (the second with persistent workgroups
+    that loop over tiles and recompute the summaries per tile)."""
     tdt = _tdt()
     n = 65536
     rng = np.random.default_rng(31 + shape + M)
@@ -229,6 +230,7 @@ def test_small_series_in_one_launch(shape, M, dtype):
     plan.set_option("shape", shape)
     assert plan.green_support()["forward"][0] > 0
     for rep in range(2):
+        plan.set_option("wg_per_cu", 0 if rep == 0 else 1)
         F = rng.uniform(-1.0, 1.0, (M, n))
         X = to_host(plan.solve(to_dev(F, dtype)))
         Fr = F.astype(np.float32).astype(np.float64) if dtype == "f32" else F
